@@ -1,0 +1,253 @@
+"""Independent statement of the subdomain numbering and the jump maps B_s.
+
+Oracle module (test infrastructure only).  The HIP path's host code builds
+the same objects from its own implementation; the tests compare the two
+bit for bit.
+
+The paper tears the domain into the two physics regions and glues the
+displacement on the interface with a Lagrange multiplier (Section 3.1,
+eq. (linalg-system-reformulated)); the multiplier space is represented here
+by nodal multipliers, so each multiplier row of the jump operator has one +1
+and one -1.  For more than two subdomains every C0 field is glued at every
+shared node: u everywhere, eta / xi_P / p between poroelastic subdomains and
+xi_E between elastic ones.  A node shared by m subdomains carries m-1
+multipliers, chaining the subdomains in increasing id order.
+
+Numbering
+---------
+* Subdomain s = b*nsub_x + a covers cells [cx[a], cx[a+1]) x [cy[b], cy[b+1])
+  with cx[a] = floor(a * ncell / nsub_x) (same for y).  Every subdomain lies in
+  one physics region.
+* DOF kinds: 0 ux, 1 uy, 2 eta, 3 xi_P, 4 p, 5 xi_E.  A DOF is identified by
+  code = 8 * lattice_node + kind (displacement lattice for kinds 0, 1, the P1
+  lattice otherwise).  Dirichlet DOFs are not unknowns.
+* A local DOF is an interface DOF (set b) when another subdomain has the same
+  code; otherwise interior (set I).  Categories: 0 interior U (u, eta),
+  1 interior P (xi, p), 2 interface U, 3 interface P, 4 fixed.
+* A subdomain whose closure holds no Dirichlet displacement node is floating.
+  Its fixed DOFs are ux, uy at the lower-left closure corner and ux at the
+  upper-right corner; they are interface DOFs kept out of the local
+  elimination.
+* Local order: sort by (category, field order, node, component) with field
+  order u 0, eta 1, xi 2, p 3 and component 0/1 for ux/uy.
+* Multiplier rows: for each shared code, with S the sorted subdomains having
+  it, one row per consecutive pair (S[k], S[k+1]) with sign +1 on S[k] and -1
+  on S[k+1], except that a poroelastic/elastic pair puts +1 on the poroelastic
+  side (the sign of H_P in eq. (linalg-system)).  Rows are sorted by
+  (kind, node, k).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List
+
+import numpy as np
+
+from workloads import Workload, XSPLIT, YSPLIT, CORE
+
+KIND_FIELD_ORDER = {0: 0, 1: 0, 2: 1, 3: 2, 4: 3, 5: 2}
+U_KINDS = (0, 1, 2)
+
+
+def _region_poro(layout, xc, yc):
+    if layout == XSPLIT:
+        return xc < 0.5
+    if layout == YSPLIT:
+        return yc < 0.5
+    if layout == CORE:
+        return (xc > 0.25) & (xc < 0.75) & (yc > 0.25) & (yc < 0.75)
+    raise ValueError(layout)
+
+
+def _sides(i, j, nmax, mask):
+    out = False
+    if mask & 1 and i == 0:
+        out = True
+    if mask & 2 and i == nmax:
+        out = True
+    if mask & 4 and j == 0:
+        out = True
+    if mask & 8 and j == nmax:
+        out = True
+    return out
+
+
+@dataclass
+class Sub:
+    sid: int
+    poro: bool
+    i0: int
+    i1: int
+    j0: int
+    j1: int
+    codes: List[int]        # local order
+    cats: List[int]
+    floating: bool
+
+
+@dataclass
+class IndexSpec:
+    subs: List[Sub]
+    rows: np.ndarray        # (N_lambda, 2, 3): (sub, local index, sign) for the two entries
+    row_code: np.ndarray    # (N_lambda,) code of the glued DOF
+    mult: np.ndarray        # (N_lambda,) number of subdomains sharing the DOF
+
+    @property
+    def n_lambda(self):
+        return len(self.rows)
+
+
+def build(w: Workload) -> IndexSpec:
+    n = w.ncell
+    k = w.order_u
+    ratio = 1 if k == 1 else 2
+    nu = ratio * n              # max displacement lattice index
+    mu = nu + 1
+    cx = [(a * n) // w.nsub_x for a in range(w.nsub_x + 1)]
+    cy = [(b * n) // w.nsub_y for b in range(w.nsub_y + 1)]
+    subs = []
+    owners = {}   # code -> list of subdomain ids
+    local_sets = []
+    for b in range(w.nsub_y):
+        for a in range(w.nsub_x):
+            sid = b * w.nsub_x + a
+            i0, i1, j0, j1 = cx[a], cx[a + 1], cy[b], cy[b + 1]
+            xs = (np.arange(i0, i1) + 0.5) / n
+            ys = (np.arange(j0, j1) + 0.5) / n
+            XC, YC = np.meshgrid(xs, ys)
+            reg = _region_poro(w.layout, XC, YC)
+            if not (reg.all() or (~reg).all()):
+                raise ValueError(f"subdomain {sid} straddles the interface")
+            poro = bool(reg.all())
+            codes = []
+            has_dir = False
+            for J in range(ratio * j0, ratio * j1 + 1):
+                for I in range(ratio * i0, ratio * i1 + 1):
+                    if _sides(I, J, nu, w.dirichlet_u):
+                        has_dir = True
+                        continue
+                    node = J * mu + I
+                    codes += [8 * node + 0, 8 * node + 1]
+            for j in range(j0, j1 + 1):
+                for i in range(i0, i1 + 1):
+                    node = j * (n + 1) + i
+                    if poro:
+                        codes += [8 * node + 2, 8 * node + 3]
+                        if not _sides(i, j, n, w.dirichlet_p):
+                            codes.append(8 * node + 4)
+                    else:
+                        codes.append(8 * node + 5)
+            for c in codes:
+                owners.setdefault(c, []).append(sid)
+            local_sets.append((sid, poro, i0, i1, j0, j1, codes, not has_dir))
+    for sid, poro, i0, i1, j0, j1, codes, floating in local_sets:
+        fixed = set()
+        if floating:
+            A = (ratio * j0) * mu + ratio * i0
+            C = (ratio * j1) * mu + ratio * i1
+            fixed = {8 * A + 0, 8 * A + 1, 8 * C + 0}
+        keyed = []
+        for c in codes:
+            node, kind = c // 8, c % 8
+            shared = len(owners[c]) > 1
+            if c in fixed:
+                cat = 4
+            elif kind in U_KINDS:
+                cat = 2 if shared else 0
+            else:
+                cat = 3 if shared else 1
+            comp = 1 if kind == 1 else 0
+            keyed.append(((cat, KIND_FIELD_ORDER[kind], node, comp), c, cat))
+        keyed.sort()
+        subs.append(Sub(sid, poro, i0, i1, j0, j1, [c for _, c, _ in keyed],
+                        [ct for _, _, ct in keyed], floating))
+    pos = [dict((c, i) for i, c in enumerate(s.codes)) for s in subs]
+    rows = []
+    for c in sorted(owners, key=lambda c: (c % 8, c // 8)):
+        S = sorted(owners[c])
+        if len(S) < 2:
+            continue
+        for kk in range(len(S) - 1):
+            s1, s2 = S[kk], S[kk + 1]
+            sg1, sg2 = 1, -1
+            if subs[s1].poro != subs[s2].poro and not subs[s1].poro:
+                sg1, sg2 = -1, 1
+            rows.append(((c % 8, c // 8, kk), c, len(S),
+                         ((s1, pos[s1][c], sg1), (s2, pos[s2][c], sg2))))
+    rows.sort(key=lambda r: r[0])
+    R = np.array([r[3] for r in rows], dtype=np.int64).reshape(-1, 2, 3)
+    return IndexSpec(subs, R, np.array([r[1] for r in rows], dtype=np.int64),
+                     np.array([r[2] for r in rows], dtype=np.int64))
+
+
+def closed_form_n_lambda(w: Workload) -> int:
+    """Number of multipliers counted directly from the lattice geometry.
+
+    Each glued code shared by m subdomains gives m - 1 rows.  Counted here
+    from node multiplicities on the cut lines (no subdomain lists needed).
+    """
+    n, r = w.ncell, (1 if w.order_u == 1 else 2)
+    cx = [(a * n) // w.nsub_x for a in range(w.nsub_x + 1)]
+    cy = [(b * n) // w.nsub_y for b in range(w.nsub_y + 1)]
+    cutx = set(cx[1:-1])
+    cuty = set(cy[1:-1])
+
+    def reg_of_cell(i, j):
+        return bool(_region_poro(w.layout, (i + 0.5) / n, (j + 0.5) / n))
+
+    def sub_of_cell(i, j):
+        a = max(q for q in range(w.nsub_x) if cx[q] <= i)
+        b = max(q for q in range(w.nsub_y) if cy[q] <= j)
+        return b * w.nsub_x + a
+
+    total = 0
+    for J in range(r * n + 1):
+        for I in range(r * n + 1):
+            on_x = (I % r == 0) and (I // r) in cutx
+            on_y = (J % r == 0) and (J // r) in cuty
+            if not (on_x or on_y):
+                continue
+            # cells whose closure holds lattice node (I, J)
+            ilo = (I - 1) // r if I > 0 else 0
+            ihi = min(I // r, n - 1)
+            jlo = (J - 1) // r if J > 0 else 0
+            jhi = min(J // r, n - 1)
+            cells = {(ci, cj) for ci in range(max(ilo, 0), ihi + 1)
+                     for cj in range(max(jlo, 0), jhi + 1)
+                     if ci * r <= I <= (ci + 1) * r and cj * r <= J <= (cj + 1) * r}
+            subs = {sub_of_cell(ci, cj) for ci, cj in cells}
+            if len(subs) < 2:
+                continue
+            if not _sides(I, J, r * n, w.dirichlet_u):
+                total += 2 * (len(subs) - 1)
+            if I % r == 0 and J % r == 0:
+                i, j = I // r, J // r
+                psubs = {sub_of_cell(ci, cj) for ci, cj in cells if reg_of_cell(ci, cj)}
+                esubs = subs - psubs
+                if len(psubs) >= 2:
+                    total += 2 * (len(psubs) - 1)          # eta, xi_P
+                    if not _sides(i, j, n, w.dirichlet_p):
+                        total += len(psubs) - 1            # p
+                if len(esubs) >= 2:
+                    total += len(esubs) - 1                # xi_E
+    return total
+
+
+def rigid_modes(w: Workload, sub: Sub) -> np.ndarray:
+    """Rigid-body modes (n_s, 3) of a subdomain: translations and the rotation
+    about the subdomain centre, on the displacement DOFs, zero elsewhere."""
+    r = 1 if w.order_u == 1 else 2
+    mu = r * w.ncell + 1
+    s = 1.0 / (r * w.ncell)
+    xc = 0.5 * (sub.i0 + sub.i1) / w.ncell
+    yc = 0.5 * (sub.j0 + sub.j1) / w.ncell
+    R = np.zeros((len(sub.codes), 3))
+    for i, c in enumerate(sub.codes):
+        node, kind = c // 8, c % 8
+        if kind > 1:
+            continue
+        x = (node % mu) * s
+        y = (node // mu) * s
+        R[i, kind] = 1.0
+        R[i, 2] = -(y - yc) if kind == 0 else (x - xc)
+    return R
