@@ -1,0 +1,167 @@
+"""Benchmark of the FETI time step on one MI355X.
+
+Workload: the 64-subdomain nearly incompressible problem (unit square,
+poroelastic x < 1/2, elastic x > 1/2, 8x8 subdomains, P2-P1-P1-P1 / P2-P1
+elements, h = 1/128, E = 1e4, nu = 0.49999, alpha = 1, c0 = 1e-3, K = 1e-6,
+dt = 1e-3) with the smooth manufactured load, synthetic and seeded-free.
+
+A bench step is one backward-Euler time step of the hot path: right-hand
+side, d = B K^+ f, admissible start, projected PCG to a per-field relative
+residual of 1e-10, recovery of every field.  The one-off setup (element
+assembly, batched elimination, coarse matrix) is timed separately and
+reported, together with the amortised rate over the workload's 50 steps.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+FP32_PEAK_TFS = 157.3
+
+
+def cpu_baseline(w, nsteps=3):
+    """The FP64 oracle on the host, single-threaded, on a bounded sample of the workload."""
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    from oracle.monolithic import MonolithicSystem
+    t0 = time.perf_counter()
+    S = MonolithicSystem(w)
+    S.factor()
+    t_setup = time.perf_counter() - t0
+    eta = S.initial_eta()
+    b = S.blocks
+    ts = []
+    for k in range(1, nsteps + 1):
+        t1 = time.perf_counter()
+        x = S.solve_step(k * w.tau, eta)
+        ts.append(time.perf_counter() - t1)
+        eta = x[b.offsets['eta']:b.offsets['eta'] + b.sizes['eta']].copy()
+    step = sum(ts) / len(ts)
+    amort = w.nsteps / (t_setup + w.nsteps * step)
+    return {"value": 1.0 / step, "unit": "time steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{w.name}: assembly + SuperLU factorisation + {nsteps} steps "
+                      f"(setup {t_setup:.1f} s, {step:.2f} s/step); value is the steady-state "
+                      f"rate, amortised over {w.nsteps} steps {amort:.3f} steps/s",
+            "amortised": amort}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--variant", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check-every", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the solver here runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not an implemented path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2509_06673_amd import _binding as B
+    from paper_2509_06673_amd.workload import load, opts, mesh_args, material
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    w = W.nearly_incompressible_large()
+    stream = torch.cuda.current_stream()
+    f = B.Feti(stream)
+    f.setup_mesh(**mesh_args(w))
+    sizes = f.get_sizes()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.assemble(material(w.mat_p), material(w.mat_e), w.tau)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    f.factor_subdomains(B.FP64, B.PRECOND_DIRICHLET)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f.init_state(load(w, 0.0))
+    o = opts(tol=w.tol, max_it=2000, start=B.START_PREVIOUS, check_every=args.check_every)
+    n = 0
+    iters = []
+    for _ in range(args.warmup):
+        n += 1
+        f.step(load(w, n * w.tau), o)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    ta = time.perf_counter()
+    for _ in range(args.steps):
+        n += 1
+        st = f.step(load(w, n * w.tau), o)
+        iters.append(st["iters"])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    elapsed = tb - ta
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = args.steps / elapsed
+    setup_s = (t1 - t0) + (t2 - t1)
+    amortised = w.nsteps / (setup_s + w.nsteps * elapsed / args.steps)
+
+    # roofline of the per-step kernels (HIP events on the context stream)
+    ls_ms, ls_bytes = f.time_kernel(B.KERNEL_LOCAL_SOLVE, 20)
+    if_ms, if_bytes = f.time_kernel(B.KERNEL_IFACE_GEMV, 50)
+    pc_ms, pc_bytes = f.time_kernel(B.KERNEL_PRECOND_GEMV, 50)
+    el_ms, el_flops = f.time_kernel(B.KERNEL_ELIMINATION, 1)
+    it_mean = sum(iters) / len(iters)
+    share = {"local_solve": 2 * ls_ms, "iface_gemv": (it_mean + 1) * if_ms,
+             "precond_gemv": (it_mean + 1) * pc_ms}
+    dom = max(share, key=share.get)
+    dms, dbytes = {"local_solve": (ls_ms, ls_bytes), "iface_gemv": (if_ms, if_bytes),
+                   "precond_gemv": (pc_ms, pc_bytes)}[dom]
+    achieved = dbytes / (dms * 1e-3) / 1e9
+    kernels = {
+        "local_solve_sgemv": {"avg_ms": ls_ms, "GB/s": ls_bytes / (ls_ms * 1e-3) / 1e9},
+        "iface_sgemv": {"avg_ms": if_ms, "GB/s": if_bytes / (if_ms * 1e-3) / 1e9},
+        "precond_sgemv": {"avg_ms": pc_ms, "GB/s": pc_bytes / (pc_ms * 1e-3) / 1e9},
+        "elimination": {"ms": el_ms, "TFLOP/s": el_flops / (el_ms * 1e-3) / 1e12,
+                        "frac_fp64_peak": el_flops / (el_ms * 1e-3) / 1e12 / FP64_PEAK_TFS},
+    }
+    out = {
+        "metric": "time steps/s and PCG iters at rel. residual 1e-10",
+        "value": value,
+        "unit": "time steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "variant": args.variant, "n_sub": sizes["n_sub"],
+                   "n_lambda": sizes["n_lambda"], "sum_ns": sizes["sum_ns"],
+                   "max_ns": sizes["max_ns"], "max_nb": sizes["max_nb"], "tol": w.tol},
+        "pcg_iters_mean": it_mean,
+        "pcg_iters": iters,
+        "setup_s": {"assemble": t1 - t0, "factor": t2 - t1},
+        "amortised_steps_per_s": amortised,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    f.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,231 @@
+/*
+ * feti.h -- C ABI of the MI355X FETI solver for the coupled poroelasticity /
+ * elasticity model (Ge & Wang, arXiv 2509.06673).
+ *
+ * The library computes, for every backward-Euler step, the discrete solution
+ * of the block system of eq. (linalg-system) (Section 2.5): the poroelastic
+ * region carries (u, xi_P, eta, p) on P_k-P1-P1-P1 elements, the elastic region
+ * (u, xi_E) on P_k-P1 elements, and a Lagrange multiplier glues the two
+ * (Section 2.3, Problem 2).  The system is torn into subdomains and solved by
+ * the FETI method of Section 3: the interface problem F lambda = d (eq.
+ * (feti-system) / (sim-feti)) is solved by projected preconditioned CG with
+ * the Dirichlet preconditioner of eq. (feti_dirichlet_preconditioner), after
+ * which the subdomain fields are recovered (proof of Theorem 3.1).
+ *
+ * Conventions
+ *  - Every function returns FETI_OK (0) or a negative FETI_E* code; the text of
+ *    the last error of a context is returned by feti_last_error().
+ *  - Pointers named *_dev are device pointers (HIP global memory, for example
+ *    the data_ptr() of a torch tensor on cuda:0).  Pointers named *_host are
+ *    host pointers.  Every pointer argument is owned by the caller; no call
+ *    retains or frees caller memory.  Device buffers written by the library
+ *    are written on the context's stream (stream-ordered): synchronise that
+ *    stream before reading them on the host.
+ *  - Calls follow create -> setup_mesh -> assemble -> factor_subdomains ->
+ *    {step | solve}* -> destroy; a call out of this order returns FETI_ESTATE.
+ *  - One context is used by one host thread at a time.
+ *  - DOF numbering.  A DOF is identified by code = 8 * node + kind with kind
+ *    0 ux, 1 uy (node on the displacement lattice of spacing h/k), 2 eta,
+ *    3 xi_P, 4 p, 5 xi_E (node on the P1 lattice of spacing h); lattices are
+ *    row-major with x fastest.  Each subdomain lists its DOFs in the order
+ *    [interior U | interior P | interface U | interface P | fixed] (U = u, eta;
+ *    P = xi, p), each block sorted by (field u, eta, xi, p; node; component).
+ *    "Torn" vectors concatenate the subdomain vectors in subdomain order.
+ */
+#ifndef FETI_H
+#define FETI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct feti_ctx_s* feti_ctx;
+
+enum {
+    FETI_OK = 0,
+    FETI_EINVAL = -1,       /* bad argument or unsupported configuration */
+    FETI_ESTATE = -2,       /* call out of order */
+    FETI_ENOMEM = -3,       /* device or host allocation failed */
+    FETI_EHIP = -4,         /* a HIP runtime call failed */
+    FETI_ESINGULAR = -5,    /* zero or non-finite pivot in the local elimination */
+    FETI_ENOTCONV = -6,     /* PCG hit max_it; the best iterate is still written */
+    FETI_EBREAKDOWN = -7,   /* PCG denominator vanished; the iterate is still written */
+    FETI_ENAN = -8          /* non-finite value in a load or in the iteration */
+};
+
+/* layouts of the poroelastic region in the unit square */
+enum { FETI_XSPLIT = 0, FETI_YSPLIT = 1, FETI_CORE = 2 };
+/* load kinds of feti_load */
+enum { FETI_LOAD_MANUFACTURED = 0, FETI_LOAD_PERIODIC = 1, FETI_LOAD_POINT_SOURCE = 2,
+       FETI_LOAD_PATCH = 3 };
+/* precision of the subdomain factors */
+enum { FETI_FP64 = 0, FETI_FP32_IR = 1 };
+/* preconditioner (Section 3.1 Dirichlet; Section 3.2 lumped) */
+enum { FETI_PRECOND_DIRICHLET = 0, FETI_PRECOND_LUMPED = 1, FETI_PRECOND_NONE = 2 };
+/* start vector of the interface iteration */
+enum { FETI_START_PREVIOUS = 0, FETI_START_ZERO = 1, FETI_START_EXTRAPOLATE = 2,
+       FETI_START_GIVEN = 3 };
+
+/* Mesh and decomposition (Section 2.4 spaces on a structured right-triangle
+ * mesh of the unit square; subdomains are an nsub_x x nsub_y grid of cell
+ * blocks with cuts at floor(a * ncell / nsub_x)). */
+typedef struct {
+    int32_t ncell;        /* cells per side, h = 1/ncell */
+    int32_t order_u;      /* k of P_k for the displacement: 1 or 2 */
+    int32_t layout;       /* FETI_XSPLIT | FETI_YSPLIT | FETI_CORE */
+    int32_t nsub_x, nsub_y;
+    uint32_t dirichlet_u; /* bit 0: x=0, 1: x=1, 2: y=0, 3: y=1 -- sides with u Dirichlet */
+    uint32_t dirichlet_p; /* sides with p Dirichlet (where the poroelastic region touches them) */
+} feti_mesh_desc;
+
+/* Parameters of Table 2 for one region; lame_mode 0: mu = E/(2(1+nu)),
+ * 1: mu = E/(1+nu) as printed in Table 3. */
+typedef struct {
+    double E, nu, alpha, c0, K, mu_f;
+    int32_t lame_mode;
+} feti_material;
+
+/* Loads.  MANUFACTURED: the smooth solution of Section 4.1 (rotated to the
+ * layout); PATCH: the polynomial solution (coefficients in params[0..13]:
+ * ux(1,x,y,x^2,xy,y^2), uy(...), p(1,y)); PERIODIC: body force
+ * amp sin(omega t + phase) (sin(pi x) sin(pi y), cos(pi x) sin(pi y)) and
+ * source amp sin(omega t + phase) sin(pi x) sin(pi y), params = {amp, omega,
+ * phase}; POINT_SOURCE: source sin(t) * Gaussian(centre, sigma) of unit
+ * integral, params = {cx, cy, sigma}.  t is the time of the step. */
+typedef struct {
+    int32_t kind;
+    double t;
+    double params[16];
+} feti_load;
+
+typedef struct {
+    double tol;           /* interface tolerance of a solve, e.g. 1e-10, on w = P (d - F lambda):
+                             |w_k| <= tol max(|P d|_k, |w^(0)|_k) for every constrained field
+                             kind k (u, eta, xi_P, p, xi_E jumps) that carries load data, and
+                             the dual-energy norm (sum_j |M_jj| w_j^2)^(1/2), M the Dirichlet
+                             preconditioner, <= tol times its reference */
+    double tol_corr;      /* interface tolerance of each refinement correction (e.g. 1e-2) */
+    double ir_tol;        /* refinement stops once max_k |du_k|_inf / |u_k|_inf <= ir_tol */
+    int32_t max_it;       /* PCG iteration cap per solve */
+    int32_t start;        /* FETI_START_* */
+    int32_t check_every;  /* iterations between host convergence checks (>= 1) */
+    int32_t ir_max;       /* refinement corrections on a step with previous multipliers */
+    int32_t ir_cold;      /* refinement corrections on a step without them */
+} feti_solve_opts;
+
+typedef struct {
+    int32_t iters;        /* PCG iterations (summed over refinement corrections) */
+    int32_t ir_steps;     /* refinement corrections performed */
+    int32_t status;       /* FETI_OK or the failure code */
+    int32_t start_used;   /* FETI_START_* actually used */
+    double res0, res;     /* max over kinds of the relative interface residual, start / end */
+    double rho;           /* size of the last refinement correction, max_k |du_k|/|u_k| (0 if none) */
+    double t_ms[8];       /* phase times (ms): rhs, d + start, pcg, recovery, refinement, total */
+} feti_stats;
+
+/* ---- lifetime ---------------------------------------------------------- */
+
+/* Create a context bound to hip_stream (a hipStream_t, NULL = default stream).
+ * No device memory is touched until feti_assemble. */
+int feti_create(feti_ctx* out, void* hip_stream);
+int feti_destroy(feti_ctx ctx);
+const char* feti_last_error(feti_ctx ctx);
+
+/* ---- setup (Sections 2.4 and 3.1) ------------------------------------------ */
+
+/* Build the lattice, the subdomains, their local DOF orders, the signed Boolean
+ * jump rows and the rigid modes of floating subdomains (host only). */
+int feti_setup_mesh(feti_ctx ctx, const feti_mesh_desc* mesh);
+
+/* sizes: [0] n_sub, [1] sum n_s, [2] N_lambda, [3] n_c (coarse size),
+ * [4] max n_s, [5] max n_b, [6] sum n_b, [7] P1 lattice size, [8] u lattice size,
+ * [9] n_floating */
+int feti_get_sizes(feti_ctx ctx, int64_t* sizes_host);
+
+/* Bit-exact export of the numbering (host buffers):
+ * local_code[sum n_s]: DOF code of each local DOF, torn order;
+ * sub_offset[n_sub+1]: start of each subdomain in torn order;
+ * sub_nb[n_sub]: interface (b) size; the b DOFs are the trailing ones;
+ * brow_sub/brow_local/brow_sign[2*N_lambda]: the two entries of each jump row. */
+int feti_export_indexing(feti_ctx ctx, int32_t* local_code_host, int32_t* sub_offset_host,
+                         int32_t* sub_nb_host, int32_t* brow_sub_host,
+                         int32_t* brow_local_host, int8_t* brow_sign_host);
+
+/* Element-parallel assembly of every dense local matrix K_s (rows 1-4 or 5-6
+ * of eq. (linalg-system) restricted to the subdomain's elements, Dirichlet
+ * DOFs removed).  tau is the time step. */
+int feti_assemble(feti_ctx ctx, const feti_material* mat_p, const feti_material* mat_e,
+                  double tau);
+
+/* Batched local elimination: pivot-free symmetric Gauss-Jordan sweeps of each
+ * K_s in its [I | b] order (the LDL^T pivots of Theorem 3.1's reduction), which
+ * snapshots the interface Schur complement S_bb of eq. (reduced-system) after
+ * the interior pivots and ends with the generalised inverse K_s^+ (fixed DOFs
+ * of floating subdomains zeroed).  Also builds the coarse matrix G^T G.
+ * precision: FETI_FP64 | FETI_FP32_IR; precond: FETI_PRECOND_*. */
+int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond);
+
+/* ---- time stepping ----------------------------------------------------------- */
+
+/* Set eta^0 (the initial fluid content) from a load's initial data: nodal
+ * interpolation of c0 p0 + alpha div u0 (eq. (mreform)), and reset the step
+ * counter and the multiplier history. */
+int feti_init_state(feti_ctx ctx, const feti_load* load);
+
+/* One backward-Euler step at time load->t: right-hand side (eq.
+ * (linalg-system) rows 1 and 4 with eta^{n-1}), interface PCG, recovery of all
+ * fields, eta^n kept for the next step.  stats may be NULL. */
+int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* opts,
+              feti_stats* stats);
+
+/* Solve the torn system K_s u_s + B_s^T lam = f_s, sum_s B_s u_s = 0 for a
+ * caller-given torn right-hand side (device, sum n_s doubles).  lambda_dev
+ * (N_lambda doubles) is the start on input when opts->start is
+ * FETI_START_GIVEN and the solution on output; u_dev receives the torn primal
+ * solution. */
+int feti_solve(feti_ctx ctx, const double* f_dev, double* lambda_dev, double* u_dev,
+               const feti_solve_opts* opts, feti_stats* stats);
+
+/* Copy the torn primal solution of the last step (sum n_s doubles) and the
+ * multipliers (N_lambda doubles) to device buffers; either may be NULL. */
+int feti_get_solution(feti_ctx ctx, double* u_dev, double* lambda_dev);
+
+/* Set the multiplier start of the next step (used with FETI_START_GIVEN). */
+int feti_set_start(feti_ctx ctx, const double* lambda_dev);
+
+/* ---- inspection (unit parity of each stage) ------------------------------- */
+
+/* Dense local matrix K_s, its S_bb snapshot and K_s^+ of subdomain sub, row
+ * major into a device buffer of n_s*n_s (K, K^+) or n_b*n_b (S_bb) doubles. */
+int feti_export_local(feti_ctx ctx, int32_t sub, int32_t which, double* out_dev);
+enum { FETI_EXPORT_K = 0, FETI_EXPORT_SBB = 1, FETI_EXPORT_KPLUS = 2 };
+
+/* y = F x (F = sum_s B_s K_s^+ B_s^T) and y = M^{-1} x (Dirichlet
+ * preconditioner) on device vectors of N_lambda doubles. */
+int feti_apply_F(feti_ctx ctx, const double* x_dev, double* y_dev);
+int feti_apply_precond(feti_ctx ctx, const double* x_dev, double* y_dev);
+
+/* Torn right-hand side of the last prepared step (sum n_s doubles). */
+int feti_get_rhs(feti_ctx ctx, double* f_dev);
+
+/* ---- measurement ------------------------------------------------------------ */
+
+/* Launch one stage reps times back to back on the context stream between two
+ * HIP events and report its average duration in ms and its algorithmic work
+ * per launch: bytes for the GEMV stages (matrix entries read once plus the
+ * vector traffic), flops for the elimination (sum_s n_s^3, the count of a
+ * symmetric inversion).  The stage's outputs are the same as in a step, so a
+ * context stays valid.  Requires a factored context. */
+enum { FETI_KERNEL_LOCAL_SOLVE = 0,    /* y_s = K_s^+ f_s, every subdomain */
+       FETI_KERNEL_IFACE_GEMV = 1,     /* y_b = (K_s^+)_bb B_s^T x: the F application */
+       FETI_KERNEL_PRECOND_GEMV = 2,   /* y_b = S_bb (B^T D x)_s: the preconditioner */
+       FETI_KERNEL_ELIMINATION = 3 };  /* the whole batched elimination (reps forced to 1) */
+int feti_time_kernel(feti_ctx ctx, int32_t which, int32_t reps, double* avg_ms_host,
+                     double* work_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FETI_H */

@@ -1,0 +1,236 @@
+"""ctypes binding of libfeti.so (the C ABI declared in include/feti.h).
+
+Argument marshalling only: every numerical step runs in the HIP library.
+Device buffers are passed as torch tensors on the GPU (their data_ptr()), and
+the context is bound to a torch stream.  The library must be built first
+(``python -m paper_2509_06673_amd.build``); importing this module without it
+raises an error rather than falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfeti.so")
+
+# status codes
+OK, EINVAL, ESTATE, ENOMEM, EHIP, ESINGULAR, ENOTCONV, EBREAKDOWN, ENAN = 0, -1, -2, -3, -4, -5, -6, -7, -8
+XSPLIT, YSPLIT, CORE = 0, 1, 2
+LOAD_MANUFACTURED, LOAD_PERIODIC, LOAD_POINT_SOURCE, LOAD_PATCH = 0, 1, 2, 3
+FP64, FP32_IR = 0, 1
+PRECOND_DIRICHLET, PRECOND_LUMPED, PRECOND_NONE = 0, 1, 2
+START_PREVIOUS, START_ZERO, START_EXTRAPOLATE, START_GIVEN = 0, 1, 2, 3
+EXPORT_K, EXPORT_SBB, EXPORT_KPLUS = 0, 1, 2
+KERNEL_LOCAL_SOLVE, KERNEL_IFACE_GEMV, KERNEL_PRECOND_GEMV, KERNEL_ELIMINATION = 0, 1, 2, 3
+
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM", EHIP: "EHIP",
+                ESINGULAR: "ESINGULAR", ENOTCONV: "ENOTCONV", EBREAKDOWN: "EBREAKDOWN",
+                ENAN: "ENAN"}
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("ncell", C.c_int32), ("order_u", C.c_int32), ("layout", C.c_int32),
+                ("nsub_x", C.c_int32), ("nsub_y", C.c_int32), ("dirichlet_u", C.c_uint32),
+                ("dirichlet_p", C.c_uint32)]
+
+
+class Material(C.Structure):
+    _fields_ = [("E", C.c_double), ("nu", C.c_double), ("alpha", C.c_double), ("c0", C.c_double),
+                ("K", C.c_double), ("mu_f", C.c_double), ("lame_mode", C.c_int32)]
+
+
+class Load(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("t", C.c_double), ("params", C.c_double * 16)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("tol_corr", C.c_double), ("ir_tol", C.c_double),
+                ("max_it", C.c_int32), ("start", C.c_int32), ("check_every", C.c_int32),
+                ("ir_max", C.c_int32), ("ir_cold", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("ir_steps", C.c_int32), ("status", C.c_int32),
+                ("start_used", C.c_int32), ("res0", C.c_double), ("res", C.c_double),
+                ("rho", C.c_double), ("t_ms", C.c_double * 8)]
+
+    def as_dict(self) -> Dict:
+        return {"iters": self.iters, "ir_steps": self.ir_steps, "status": self.status,
+                "start_used": self.start_used, "res0": self.res0, "res": self.res,
+                "rho": self.rho, "t_ms": list(self.t_ms)}
+
+
+class FetiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib: Optional[C.CDLL] = None
+
+_SIGS = {
+    "feti_create": [C.POINTER(C.c_void_p), C.c_void_p],
+    "feti_destroy": [C.c_void_p],
+    "feti_setup_mesh": [C.c_void_p, C.POINTER(MeshDesc)],
+    "feti_get_sizes": [C.c_void_p, C.POINTER(C.c_int64)],
+    "feti_export_indexing": [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                             C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                             C.POINTER(C.c_int8)],
+    "feti_assemble": [C.c_void_p, C.POINTER(Material), C.POINTER(Material), C.c_double],
+    "feti_factor_subdomains": [C.c_void_p, C.c_int32, C.c_int32],
+    "feti_init_state": [C.c_void_p, C.POINTER(Load)],
+    "feti_step": [C.c_void_p, C.POINTER(Load), C.POINTER(SolveOpts), C.POINTER(Stats)],
+    "feti_solve": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts),
+                   C.POINTER(Stats)],
+    "feti_get_solution": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "feti_set_start": [C.c_void_p, C.c_void_p],
+    "feti_export_local": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p],
+    "feti_apply_F": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "feti_apply_precond": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "feti_get_rhs": [C.c_void_p, C.c_void_p],
+    "feti_time_kernel": [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                         C.POINTER(C.c_double)],
+}
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2509_06673_amd.build`")
+    lib = C.CDLL(path)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.feti_last_error.argtypes = [C.c_void_p]
+    lib.feti_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> int:
+    """Device (or host) address of a torch tensor, or 0 for None."""
+    if t is None:
+        return 0
+    return t.data_ptr()
+
+
+class Feti:
+    """One solver context bound to a torch stream on the current GPU."""
+
+    def __init__(self, stream=None):
+        self.lib = load_library()
+        self.ctx = C.c_void_p()
+        sp = None
+        if stream is not None:
+            sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        self._check(self.lib.feti_create(C.byref(self.ctx), sp), "feti_create")
+
+    # -- errors -------------------------------------------------------------
+    def last_error(self) -> str:
+        return self.lib.feti_last_error(self.ctx).decode()
+
+    def _check(self, rc: int, what: str, allow=()):
+        if rc != OK and rc not in allow:
+            raise FetiError(rc, f"{what}: {self.last_error() if self.ctx else ''}")
+        return rc
+
+    def close(self):
+        if self.ctx:
+            self.lib.feti_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setup ----------------------------------------------------------------
+    def setup_mesh(self, ncell, order_u, layout, nsub_x, nsub_y, dirichlet_u=0xF, dirichlet_p=0xF):
+        d = MeshDesc(ncell, order_u, layout, nsub_x, nsub_y, dirichlet_u, dirichlet_p)
+        return self._check(self.lib.feti_setup_mesh(self.ctx, C.byref(d)), "feti_setup_mesh")
+
+    def get_sizes(self) -> Dict[str, int]:
+        a = (C.c_int64 * 10)()
+        self._check(self.lib.feti_get_sizes(self.ctx, a), "feti_get_sizes")
+        keys = ["n_sub", "sum_ns", "n_lambda", "n_c", "max_ns", "max_nb", "sum_nb", "n_p1",
+                "n_u", "n_float"]
+        return dict(zip(keys, list(a)))
+
+    def export_indexing(self):
+        import numpy as np
+        sz = self.get_sizes()
+        code = np.zeros(sz["sum_ns"], np.int32)
+        off = np.zeros(sz["n_sub"] + 1, np.int32)
+        nb = np.zeros(sz["n_sub"], np.int32)
+        bs = np.zeros(2 * sz["n_lambda"], np.int32)
+        bl = np.zeros(2 * sz["n_lambda"], np.int32)
+        sg = np.zeros(2 * sz["n_lambda"], np.int8)
+        P = lambda a, t: a.ctypes.data_as(C.POINTER(t))
+        self._check(self.lib.feti_export_indexing(self.ctx, P(code, C.c_int32), P(off, C.c_int32),
+                                                  P(nb, C.c_int32), P(bs, C.c_int32),
+                                                  P(bl, C.c_int32), P(sg, C.c_int8)),
+                    "feti_export_indexing")
+        return dict(code=code, sub_offset=off, sub_nb=nb, brow_sub=bs, brow_local=bl, brow_sign=sg)
+
+    def assemble(self, mat_p: Material, mat_e: Material, tau: float):
+        return self._check(self.lib.feti_assemble(self.ctx, C.byref(mat_p), C.byref(mat_e), tau),
+                           "feti_assemble")
+
+    def factor_subdomains(self, precision=FP64, precond=PRECOND_DIRICHLET):
+        return self._check(self.lib.feti_factor_subdomains(self.ctx, precision, precond),
+                           "feti_factor_subdomains")
+
+    # -- stepping ---------------------------------------------------------------
+    def init_state(self, load: Load):
+        return self._check(self.lib.feti_init_state(self.ctx, C.byref(load)), "feti_init_state")
+
+    def step(self, load: Load, opts: SolveOpts, allow=()) -> Dict:
+        st = Stats()
+        rc = self.lib.feti_step(self.ctx, C.byref(load), C.byref(opts), C.byref(st))
+        self._check(rc, "feti_step", allow)
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
+    def solve(self, f, lam, u, opts: SolveOpts, allow=()) -> Dict:
+        st = Stats()
+        rc = self.lib.feti_solve(self.ctx, _ptr(f), _ptr(lam), _ptr(u), C.byref(opts), C.byref(st))
+        self._check(rc, "feti_solve", allow)
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
+    def get_solution(self, u=None, lam=None):
+        return self._check(self.lib.feti_get_solution(self.ctx, _ptr(u), _ptr(lam)),
+                           "feti_get_solution")
+
+    def set_start(self, lam):
+        return self._check(self.lib.feti_set_start(self.ctx, _ptr(lam)), "feti_set_start")
+
+    # -- inspection ---------------------------------------------------------------
+    def export_local(self, sub: int, which: int, out):
+        return self._check(self.lib.feti_export_local(self.ctx, sub, which, _ptr(out)),
+                           "feti_export_local")
+
+    def apply_F(self, x, y):
+        return self._check(self.lib.feti_apply_F(self.ctx, _ptr(x), _ptr(y)), "feti_apply_F")
+
+    def apply_precond(self, x, y):
+        return self._check(self.lib.feti_apply_precond(self.ctx, _ptr(x), _ptr(y)),
+                           "feti_apply_precond")
+
+    def get_rhs(self, f):
+        return self._check(self.lib.feti_get_rhs(self.ctx, _ptr(f)), "feti_get_rhs")
+
+    # -- measurement --------------------------------------------------------------
+    def time_kernel(self, which: int, reps: int = 20):
+        ms, work = C.c_double(), C.c_double()
+        self._check(self.lib.feti_time_kernel(self.ctx, which, reps, C.byref(ms), C.byref(work)),
+                    "feti_time_kernel")
+        return ms.value, work.value

@@ -1,0 +1,899 @@
+// C ABI of the FETI library and the host orchestration of one time step.
+//
+// A step (Section 2.5 backward Euler, Section 3 FETI):
+//   f_s        per-subdomain right-hand side (rows 1 and 4 of eq. (linalg-system))
+//   d          = sum_s B_s K_s^+ f_s,  e_s = R_s^T f_s            (eq. (feti-system))
+//   lambda_0   start: previous multipliers (Algorithm 1/2 warm start), made
+//              admissible (G^T lambda = e) by one coarse solve
+//   PCG        projected preconditioned CG on F lambda = d with the Dirichlet
+//              preconditioner of eq. (feti_dirichlet_preconditioner)
+//   recovery   u_s = K_s^+ (f_s - B_s^T lambda) + R_s alpha  (proof of Theorem 3.1)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "feti_internal.h"
+#include "iface.h"
+#include "kernels.h"
+
+using namespace feti;
+
+struct feti_ctx_s {
+  hipStream_t stream = nullptr;
+  std::string err;
+  int state = 0;  // 0 created, 1 mesh, 2 assembled, 3 factored
+  int device = -1;
+  MeshHost mh;
+  DevMesh dm;
+  std::vector<void*> allocs;
+  std::vector<void*> mat_allocs;
+  // materials
+  feti_material matP{}, matE{};
+  MatParams mpP{}, mpE{};
+  double lamP = 0, muP = 0, lamE = 0, muE = 0, tau = 0;
+  int precision = FETI_FP64, precond = FETI_PRECOND_DIRICHLET;
+  // dense blocks
+  int64_t k_total = 0, s_total = 0;
+  double* K = nullptr;      // assembled local matrices
+  double* Kinv = nullptr;   // K_s^+
+  double* Sbb = nullptr;    // S_bb snapshots
+  double* Splus = nullptr;  // (K_s^+)_bb
+  double* Kbb = nullptr;    // K_bb (lumped preconditioner)
+  double* Cinv = nullptr;   // (G^T G)^{-1}
+  int nc = 0;
+  // vectors
+  double *f = nullptr, *u = nullptr, *ytmp = nullptr, *yb = nullptr, *zb = nullptr;
+  double *rf = nullptr, *du = nullptr, *dlam = nullptr, *cj = nullptr, *kpart = nullptr;
+  double* mdiag = nullptr;  // diagonal of the preconditioner (weights of the dual-energy norm)
+  double* h_kpart = nullptr;
+  double *lam = nullptr, *lam_prev = nullptr, *lam_prev2 = nullptr, *d = nullptr, *r = nullptr,
+         *w = nullptr, *z = nullptr, *y = nullptr, *p = nullptr, *q = nullptr, *qraw = nullptr,
+         *tl = nullptr;
+  double *g = nullptr, *ac = nullptr;
+  double *part = nullptr, *sc = nullptr;
+  int32_t* ist = nullptr;
+  int32_t* h_ist = nullptr;
+  double* h_sc = nullptr;
+  int64_t nstep = 0;
+  bool have_prev = false, have_prev2 = false;
+  hipEvent_t ev[8] = {};
+};
+
+namespace {
+
+int fail(feti_ctx c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return fail(ctx, FETI_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));     \
+  } while (0)
+
+template <class T>
+int dalloc(feti_ctx ctx, T** p, size_t count, std::vector<void*>& list) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) return fail(ctx, FETI_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  list.push_back(*p);
+  return FETI_OK;
+}
+
+template <class T>
+int upload(feti_ctx ctx, T** p, const std::vector<T>& v) {
+  int rc = dalloc(ctx, p, v.size(), ctx->allocs);
+  if (rc) return rc;
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  return FETI_OK;
+}
+
+#define RC(expr)              \
+  do {                        \
+    int _rc = (expr);         \
+    if (_rc) return _rc;      \
+  } while (0)
+
+void lame(const feti_material& m, double& lam, double& mu) {
+  lam = m.E * m.nu / ((1.0 + m.nu) * (1.0 - 2.0 * m.nu));
+  mu = m.lame_mode == 1 ? m.E / (1.0 + m.nu) : m.E / (2.0 * (1.0 + m.nu));
+}
+
+int64_t round8(int64_t n) { return (n + 7) / 8 * 8; }
+
+constexpr int KMAX_NBLK = 128;  // blocks of the per-kind max-abs reduction
+
+int upload_mesh(feti_ctx ctx) {
+  const MeshHost& h = ctx->mh;
+  DevMesh& m = ctx->dm;
+  const int nsub = (int)h.subs.size();
+  m.nsub = nsub;
+  m.order = h.desc.order_u;
+  m.ncell = h.desc.ncell;
+  m.edof = h.edof;
+  m.nelem = (int)h.el_sub.size();
+  m.sum_ns = h.sum_ns;
+  m.sum_nb = h.sum_nb;
+  m.n_lambda = h.n_lambda;
+  m.n_float = h.n_float;
+  m.max_ns = h.max_ns;
+  m.max_nb = h.max_nb;
+  std::vector<int32_t> ns(nsub), nI(nsub), nb(nsub), nfix(nsub), ld(nsub), ldb(nsub), sfl(nsub);
+  std::vector<int64_t> soff(nsub), boff(nsub), kofs(nsub), sofs(nsub);
+  std::vector<uint8_t> poro(nsub);
+  int64_t ko = 0, so = 0;
+  for (int s = 0; s < nsub; ++s) {
+    const SubHost& sh = h.subs[s];
+    ns[s] = sh.ns; nI[s] = sh.nI; nb[s] = sh.nb; nfix[s] = sh.nfix;
+    soff[s] = sh.off; boff[s] = sh.boff;
+    ld[s] = (int32_t)round8(sh.ns);
+    kofs[s] = ko;
+    ko += (int64_t)sh.ns * ld[s];
+    ldb[s] = (int32_t)round8(sh.nb);
+    sofs[s] = so;
+    so += (int64_t)sh.nb * ldb[s];
+    poro[s] = sh.poro ? 1 : 0;
+    sfl[s] = h.sub_float[s];
+  }
+  ctx->k_total = ko;
+  ctx->s_total = so;
+  std::vector<int32_t> code(h.sum_ns), b_sub(h.sum_nb), b_torn(h.sum_nb);
+  for (const SubHost& sh : h.subs) {
+    for (int i = 0; i < sh.ns; ++i) code[sh.off + i] = sh.codes[i];
+    for (int i = 0; i < sh.nb; ++i) {
+      b_sub[sh.boff + i] = sh.sid;
+      b_torn[sh.boff + i] = (int32_t)(sh.off + sh.nI + i);
+    }
+  }
+  std::vector<int32_t> row_kind(h.n_lambda);
+  for (int64_t j = 0; j < h.n_lambda; ++j) row_kind[j] = h.rows[j].kind;
+  RC(upload(ctx, &m.ns, ns));
+  RC(upload(ctx, &m.nI, nI));
+  RC(upload(ctx, &m.nb, nb));
+  RC(upload(ctx, &m.nfix, nfix));
+  RC(upload(ctx, &m.soff, soff));
+  RC(upload(ctx, &m.boff, boff));
+  RC(upload(ctx, &m.kofs, kofs));
+  RC(upload(ctx, &m.ld, ld));
+  RC(upload(ctx, &m.sofs, sofs));
+  RC(upload(ctx, &m.ldb, ldb));
+  RC(upload(ctx, &m.sub_poro, poro));
+  RC(upload(ctx, &m.sub_float, sfl));
+  RC(upload(ctx, &m.code, code));
+  RC(upload(ctx, &m.rfull, h.rfull));
+  RC(upload(ctx, &m.el_sub, h.el_sub));
+  RC(upload(ctx, &m.el_cell, h.el_cell));
+  RC(upload(ctx, &m.el_type, h.el_type));
+  RC(upload(ctx, &m.el_ldof, h.el_ldof));
+  RC(upload(ctx, &m.el_code, h.el_code));
+  RC(upload(ctx, &m.bg_row, h.bg_row));
+  RC(upload(ctx, &m.bg_sign, h.bg_sign));
+  RC(upload(ctx, &m.bd_row, h.bd_row));
+  RC(upload(ctx, &m.bd_wt, h.bd_wt));
+  RC(upload(ctx, &m.rb, h.rb));
+  RC(upload(ctx, &m.b_sub, b_sub));
+  RC(upload(ctx, &m.b_torn, b_torn));
+  std::vector<int32_t> jr_b(h.jr_b.begin(), h.jr_b.end());
+  RC(upload(ctx, &m.jr_b, jr_b));
+  RC(upload(ctx, &m.jr_sign, h.jr_sign));
+  RC(upload(ctx, &m.grp_start, h.grp_start));
+  RC(upload(ctx, &m.grp_size, h.grp_size));
+  RC(upload(ctx, &m.dwt, h.dwt));
+  RC(upload(ctx, &m.row_kind, row_kind));
+  RC(upload(ctx, &m.float_sub, h.float_sub));
+  // vectors
+  const int64_t nl = h.n_lambda;
+  RC(dalloc(ctx, &ctx->f, h.sum_ns, ctx->allocs));
+  RC(dalloc(ctx, &ctx->u, h.sum_ns, ctx->allocs));
+  RC(dalloc(ctx, &ctx->ytmp, h.sum_ns, ctx->allocs));
+  RC(dalloc(ctx, &ctx->yb, h.sum_nb, ctx->allocs));
+  RC(dalloc(ctx, &ctx->zb, h.sum_nb, ctx->allocs));
+  RC(dalloc(ctx, &ctx->rf, h.sum_ns, ctx->allocs));
+  RC(dalloc(ctx, &ctx->du, h.sum_ns, ctx->allocs));
+  RC(dalloc(ctx, &ctx->dlam, h.n_lambda, ctx->allocs));
+  RC(dalloc(ctx, &ctx->cj, h.n_lambda, ctx->allocs));
+  RC(dalloc(ctx, &ctx->mdiag, h.n_lambda, ctx->allocs));
+  RC(dalloc(ctx, &ctx->kpart, (size_t)KMAX_NBLK * 12, ctx->allocs));
+  double** lv[] = {&ctx->lam, &ctx->lam_prev, &ctx->lam_prev2, &ctx->d, &ctx->r, &ctx->w,
+                   &ctx->z, &ctx->y, &ctx->p, &ctx->q, &ctx->qraw, &ctx->tl};
+  for (double** pp : lv) RC(dalloc(ctx, pp, nl, ctx->allocs));
+  ctx->nc = 3 * h.n_float;
+  RC(dalloc(ctx, &ctx->g, std::max(ctx->nc, 1), ctx->allocs));
+  RC(dalloc(ctx, &ctx->ac, std::max(ctx->nc, 1), ctx->allocs));
+  RC(dalloc(ctx, &ctx->part, (size_t)RED_NBLK * NPART, ctx->allocs));
+  RC(dalloc(ctx, &ctx->sc, SC_COUNT, ctx->allocs));
+  RC(dalloc(ctx, &ctx->ist, IS_COUNT, ctx->allocs));
+  HIPCHK(hipMemsetAsync(ctx->u, 0, h.sum_ns * sizeof(double), ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->lam_prev, 0, nl * sizeof(double), ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->lam_prev2, 0, nl * sizeof(double), ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->ist, 0, IS_COUNT * sizeof(int32_t), ctx->stream));
+  if (!ctx->h_ist) {
+    HIPCHK(hipHostMalloc((void**)&ctx->h_ist, IS_COUNT * sizeof(int32_t), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&ctx->h_sc, SC_COUNT * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&ctx->h_kpart, KMAX_NBLK * 12 * sizeof(double), hipHostMallocDefault));
+  }
+  for (auto& e : ctx->ev)
+    if (!e) HIPCHK(hipEventCreate(&e));
+  return FETI_OK;
+}
+
+void free_all(feti_ctx ctx) {
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  for (void* p : ctx->mat_allocs) (void)hipFree(p);
+  ctx->allocs.clear();
+  ctx->mat_allocs.clear();
+  ctx->dm = DevMesh();
+  ctx->K = ctx->Kinv = ctx->Sbb = ctx->Splus = ctx->Kbb = ctx->Cinv = nullptr;
+}
+
+LoadDev make_load(feti_ctx ctx, const feti_load* L) {
+  LoadDev d{};
+  d.kind = L->kind;
+  d.layout = ctx->mh.desc.layout;
+  d.t = L->t;
+  for (int i = 0; i < 16; ++i) d.prm[i] = L->params[i];
+  d.lamP = ctx->lamP; d.muP = ctx->muP; d.lamE = ctx->lamE; d.muE = ctx->muE;
+  d.alpha = ctx->matP.alpha; d.c0 = ctx->matP.c0;
+  d.kf = ctx->matP.K / ctx->matP.mu_f;
+  return d;
+}
+
+// ---- interface operators ----------------------------------------------------
+
+void op_project(feti_ctx ctx, const double* in, double* out, const int32_t* skip) {
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  if (ctx->nc == 0) {
+    if (out != in) launch_axpby(m.n_lambda, 1.0, in, 0.0, nullptr, out, st);
+    return;
+  }
+  launch_coarse_g(m, in, nullptr, 1.0, ctx->g, skip, st);
+  launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, 1.0, skip, st);
+  launch_coarse_correct(m, ctx->ac, -1.0, in, out, skip, st);
+}
+
+void op_F(feti_ctx ctx, const double* x, double* y, const int32_t* skip) {
+  DevMesh& m = ctx->dm;
+  GemvArgs a;
+  a.A = ctx->Splus; a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
+  a.v = x; a.gmode = G_SIGNED; a.gcoef = 1.0; a.y = ctx->yb; a.skip = skip;
+  launch_sgemv(m, a, ctx->stream);
+  launch_jump(m, ctx->yb, 0, y, 0, skip, ctx->stream);
+}
+
+void op_M(feti_ctx ctx, const double* x, double* y, const int32_t* skip) {
+  DevMesh& m = ctx->dm;
+  if (ctx->precond == FETI_PRECOND_NONE) {
+    launch_axpby(m.n_lambda, 1.0, x, 0.0, nullptr, y, ctx->stream);
+    return;
+  }
+  GemvArgs a;
+  a.A = ctx->precond == FETI_PRECOND_LUMPED ? ctx->Kbb : ctx->Sbb;
+  a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
+  a.v = x; a.gmode = G_SCALED; a.gcoef = 1.0; a.y = ctx->zb; a.skip = skip;
+  launch_sgemv(m, a, ctx->stream);
+  launch_jump(m, ctx->zb, 0, y, 1, skip, ctx->stream);
+}
+
+// Projected PCG on F lambda = d with d = sum_s B_s K_s^+ f_s - c (c: prescribed jump
+// of the primal solution, nullptr = 0).  lam holds the start guess on entry (any
+// vector) and the solution on exit; u receives the recovered torn primal solution.
+// iters_out accumulates the PCG iterations.
+int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double* f, const double* cj,
+               double* lam, double* u, feti_stats* stats, int* iters_out, double* res0,
+               double* res) {
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  const int64_t nl = m.n_lambda;
+  HIPCHK(hipEventRecord(ctx->ev[1], st));
+  // d = sum_s B_s K_s^+ f_s - c
+  {
+    GemvArgs a;
+    a.A = ctx->Kinv; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
+    a.xbase = f; a.y = ctx->ytmp;
+    launch_sgemv(m, a, st);
+    launch_jump(m, ctx->ytmp, 1, ctx->d, 0, nullptr, st);
+    if (cj) launch_axpby(nl, 1.0, ctx->d, -1.0, cj, ctx->d, st);
+  }
+  // admissible start: lambda += G (G^T G)^{-1} (e - G^T lambda)
+  if (ctx->nc > 0) {
+    launch_coarse_g(m, lam, f, -1.0, ctx->g, nullptr, st);
+    launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, 1.0, nullptr, st);
+    launch_coarse_correct(m, ctx->ac, 1.0, lam, lam, nullptr, st);
+  }
+  // tolerance reference: per-kind norms of P d
+  double hsc[SC_COUNT] = {0};
+  hsc[SC_TOL] = tol;
+  HIPCHK(hipMemcpyAsync(ctx->sc, hsc, sizeof(hsc), hipMemcpyHostToDevice, st));
+  int32_t hist[IS_COUNT] = {0, 0, 0, std::max(o->max_it, 0)};
+  HIPCHK(hipMemcpyAsync(ctx->ist, hist, sizeof(hist), hipMemcpyHostToDevice, st));
+  op_project(ctx, ctx->d, ctx->tl, nullptr);
+  launch_partials(m, nullptr, nullptr, ctx->tl, ctx->mdiag, ctx->part, RED_NBLK, nullptr, st);
+  launch_scalar(ctx->part, RED_NBLK, ctx->sc, ctx->ist, PH_REFNORM, st);
+  // r = d - F lambda; w = P r; y = P M^{-1} w; p = y
+  op_F(ctx, lam, ctx->q, nullptr);
+  launch_axpby(nl, 1.0, ctx->d, -1.0, ctx->q, ctx->r, st);
+  op_project(ctx, ctx->r, ctx->w, nullptr);
+  op_M(ctx, ctx->w, ctx->z, nullptr);
+  op_project(ctx, ctx->z, ctx->y, nullptr);
+  launch_axpby(nl, 1.0, ctx->y, 0.0, nullptr, ctx->p, st);
+  launch_partials(m, ctx->w, ctx->y, ctx->w, ctx->mdiag, ctx->part, RED_NBLK, nullptr, st);
+  launch_scalar(ctx->part, RED_NBLK, ctx->sc, ctx->ist, PH_INIT, st);
+  HIPCHK(hipEventRecord(ctx->ev[2], st));
+  const int32_t* done = ctx->ist + IS_DONE;
+  const int chunk = std::max(1, o->check_every);
+  static const bool trace = std::getenv("FETI_TRACE") != nullptr;
+  for (;;) {
+    HIPCHK(hipMemcpyAsync(ctx->h_ist, ctx->ist, IS_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (trace)
+      HIPCHK(hipMemcpyAsync(ctx->h_sc, ctx->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (trace)
+      std::fprintf(stderr, "[feti] it %d res %.3e rho %.3e status %d\n", ctx->h_ist[IS_ITERS],
+                   ctx->h_sc[SC_RES], ctx->h_sc[SC_RHO], ctx->h_ist[IS_STATUS]);
+    if (ctx->h_ist[IS_DONE] || ctx->h_ist[IS_ITERS] >= o->max_it) break;
+    for (int it = 0; it < chunk; ++it) {
+      op_F(ctx, ctx->p, ctx->qraw, done);
+      op_project(ctx, ctx->qraw, ctx->q, done);
+      launch_partials(m, ctx->p, ctx->q, nullptr, nullptr, ctx->part, RED_NBLK, done, st);
+      launch_scalar(ctx->part, RED_NBLK, ctx->sc, ctx->ist, PH_ALPHA, st);
+      launch_cg_lam(nl, ctx->sc, ctx->ist, ctx->p, ctx->qraw, ctx->q, lam, ctx->r, ctx->w, st);
+      launch_partials(m, nullptr, nullptr, ctx->w, ctx->mdiag, ctx->part, RED_NBLK, done, st);
+      launch_scalar(ctx->part, RED_NBLK, ctx->sc, ctx->ist, PH_CONV, st);
+      op_M(ctx, ctx->w, ctx->z, done);
+      op_project(ctx, ctx->z, ctx->y, done);
+      launch_partials(m, ctx->w, ctx->y, nullptr, nullptr, ctx->part, RED_NBLK, done, st);
+      launch_scalar(ctx->part, RED_NBLK, ctx->sc, ctx->ist, PH_BETA, st);
+      launch_cg_p(nl, ctx->sc, ctx->ist, ctx->y, ctx->p, st);
+    }
+  }
+  HIPCHK(hipEventRecord(ctx->ev[3], st));
+  // recovery: alpha_c = -(G^T G)^{-1} G^T r,  u = K^+ (f - B^T lambda) + R alpha_c
+  if (ctx->nc > 0) {
+    launch_coarse_g(m, ctx->r, nullptr, 1.0, ctx->g, nullptr, st);
+    launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, -1.0, nullptr, st);
+  }
+  {
+    GemvArgs a;
+    a.A = ctx->Kinv; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
+    a.xbase = f; a.v = lam; a.gmode = G_SIGNED; a.gcoef = -1.0;
+    a.y = u; a.alpha_c = ctx->nc > 0 ? ctx->ac : nullptr;
+    launch_sgemv(m, a, st);
+  }
+  HIPCHK(hipEventRecord(ctx->ev[4], st));
+  HIPCHK(hipMemcpyAsync(ctx->h_ist, ctx->ist, IS_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ctx->h_sc, ctx->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const int status = ctx->h_ist[IS_STATUS];
+  if (iters_out) *iters_out += ctx->h_ist[IS_ITERS];
+  if (res0) *res0 = ctx->h_sc[SC_RES0];
+  if (res) *res = ctx->h_sc[SC_RES];
+  if (stats) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]);
+    stats->t_ms[1] += ms;
+    hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]);
+    stats->t_ms[2] += ms;
+    hipEventElapsedTime(&ms, ctx->ev[3], ctx->ev[4]);
+    stats->t_ms[3] += ms;
+  }
+  if (status == FETI_ENOTCONV) return fail(ctx, status, "PCG did not converge within max_it");
+  if (status == FETI_EBREAKDOWN) return fail(ctx, status, "PCG breakdown");
+  if (status == FETI_ENAN) return fail(ctx, status, "non-finite value in the interface iteration");
+  return FETI_OK;
+}
+
+// Torn-system residual of (u, lam) for right-hand side f: rf = f - K u - B^T lam,
+// cj = -sum_s B_s u_s (the jump a correction must add).
+void torn_residual(feti_ctx ctx, const double* f, const double* u, const double* lam) {
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  (void)hipMemsetAsync(ctx->ytmp, 0, m.sum_ns * sizeof(double), st);
+  launch_elem_matvec(m, u, ctx->ytmp, ctx->mpP, ctx->mpE, st);
+  launch_axpby(m.sum_ns, 1.0, f, -1.0, ctx->ytmp, ctx->rf, st);
+  launch_sub_gather(m, lam, ctx->rf, st);
+  launch_jump(m, u, 1, ctx->cj, 0, nullptr, st);
+  launch_axpby(m.n_lambda, -1.0, ctx->cj, 0.0, nullptr, ctx->cj, st);
+}
+
+// One FETI solve followed by up to nref FP64 refinement corrections.
+int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* stats) {
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  int iters = 0;
+  double res0 = 0, res = 0, r0c = 0, rc_ = 0;
+  int rc = solve_torn(ctx, o, o->tol, ctx->f, nullptr, ctx->lam, ctx->u, stats, &iters, &res0, &res);
+  int done_ir = 0;
+  double corr = 0.0;
+  HIPCHK(hipEventRecord(ctx->ev[6], st));
+  for (int k = 0; k < nref && (rc == FETI_OK || rc == FETI_ENOTCONV); ++k) {
+    torn_residual(ctx, ctx->f, ctx->u, ctx->lam);
+    HIPCHK(hipMemsetAsync(ctx->dlam, 0, m.n_lambda * sizeof(double), st));
+    rc = solve_torn(ctx, o, o->tol_corr, ctx->rf, ctx->cj, ctx->dlam, ctx->du, stats, &iters, &r0c,
+                    &rc_);
+    launch_axpby(m.sum_ns, 1.0, ctx->u, 1.0, ctx->du, ctx->u, st);
+    launch_axpby(m.n_lambda, 1.0, ctx->lam, 1.0, ctx->dlam, ctx->lam, st);
+    // size of the correction per DOF kind
+    launch_kind_maxabs(m, ctx->du, ctx->u, ctx->kpart, KMAX_NBLK, st);
+    HIPCHK(hipMemcpyAsync(ctx->h_kpart, ctx->kpart, KMAX_NBLK * 12 * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double mx[12] = {0};
+    for (int b = 0; b < KMAX_NBLK; ++b)
+      for (int c = 0; c < 12; ++c) mx[c] = std::max(mx[c], ctx->h_kpart[b * 12 + c]);
+    corr = 0.0;
+    for (int kk = 0; kk < 6; ++kk)
+      if (mx[6 + kk] > 0.0) corr = std::max(corr, mx[kk] / mx[6 + kk]);
+    ++done_ir;
+    if (corr <= o->ir_tol) break;
+  }
+  HIPCHK(hipEventRecord(ctx->ev[7], st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (stats) {
+    stats->iters = iters;
+    stats->ir_steps = done_ir;
+    stats->res0 = res0;
+    stats->res = res;
+    stats->rho = corr;
+    stats->status = rc;
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]);
+    stats->t_ms[4] = ms;
+  }
+  return rc;
+}
+
+int build_gj_plan(feti_ctx ctx, GJPlan& P, std::vector<int32_t>& host_flag, int nmat,
+                  const std::vector<int>& n, const std::vector<int>& nI, const std::vector<int>& nsw,
+                  const std::vector<int64_t>& aofs, const std::vector<int32_t>& lda,
+                  const std::vector<int64_t>& snap_ofs, const std::vector<int32_t>& snap_ld,
+                  int nb, std::vector<void*>& list) {
+  P = GJPlan();
+  P.nmat = nmat;
+  P.nb = nb;
+  std::vector<std::vector<std::pair<int, int>>> panels(nmat);
+  std::vector<int> snap_step(nmat, -1);
+  for (int mI = 0; mI < nmat; ++mI) {
+    P.max_n = std::max(P.max_n, n[mI]);
+    for (int k = 0; k < nI[mI]; k += nb) panels[mI].push_back({k, std::min(nb, nI[mI] - k)});
+    if (snap_ofs[mI] >= 0) snap_step[mI] = (int)panels[mI].size() - 1;
+    for (int k = nI[mI]; k < nsw[mI]; k += nb) panels[mI].push_back({k, std::min(nb, nsw[mI] - k)});
+    P.nsteps = std::max(P.nsteps, (int)panels[mI].size());
+  }
+  std::vector<int32_t> ps((size_t)P.nsteps * nmat, 0), pw((size_t)P.nsteps * nmat, 0),
+      pf((size_t)P.nsteps * nmat, 0);
+  for (int mI = 0; mI < nmat; ++mI)
+    for (int s = 0; s < (int)panels[mI].size(); ++s) {
+      ps[(size_t)s * nmat + mI] = panels[mI][s].first;
+      pw[(size_t)s * nmat + mI] = panels[mI][s].second;
+      if (s == snap_step[mI]) pf[(size_t)s * nmat + mI] = 1;
+    }
+  host_flag.assign(P.nsteps, 0);
+  for (int s = 0; s < P.nsteps; ++s)
+    for (int mI = 0; mI < nmat; ++mI) host_flag[s] |= pf[(size_t)s * nmat + mI];
+  std::vector<int32_t> nn(n.begin(), n.end()), snap_at(nI.begin(), nI.end());
+  auto up = [&](auto** p, const auto& v) {
+    int rc = dalloc(ctx, p, v.size(), list);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(*p, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice, ctx->stream);
+    return e == hipSuccess ? FETI_OK : fail(ctx, FETI_EHIP, hipGetErrorString(e));
+  };
+  RC(up(&P.pstart, ps));
+  RC(up(&P.pwidth, pw));
+  RC(up(&P.pflag, pf));
+  RC(up(&P.aofs, aofs));
+  RC(up(&P.lda, lda));
+  RC(up(&P.n, nn));
+  RC(up(&P.snap_ofs, snap_ofs));
+  RC(up(&P.snap_at, snap_at));
+  RC(up(&P.snap_ld, snap_ld));
+  RC(dalloc(ctx, &P.pinv, (size_t)nmat * nb * nb, list));
+  RC(dalloc(ctx, &P.wrow, (size_t)nmat * nb * P.max_n, list));
+  RC(dalloc(ctx, &P.status, nmat, list));
+  HIPCHK(hipMemsetAsync(P.status, 0, nmat * sizeof(int32_t), ctx->stream));
+  return FETI_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+int feti_create(feti_ctx* out, void* hip_stream) {
+  if (!out) return FETI_EINVAL;
+  feti_ctx ctx = new (std::nothrow) feti_ctx_s();
+  if (!ctx) return FETI_ENOMEM;
+  ctx->stream = (hipStream_t)hip_stream;
+  *out = ctx;
+  return FETI_OK;
+}
+
+int feti_destroy(feti_ctx ctx) {
+  if (!ctx) return FETI_EINVAL;
+  if (ctx->state >= 2) {
+    (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    for (auto& e : ctx->ev)
+      if (e) (void)hipEventDestroy(e);
+    if (ctx->h_ist) (void)hipHostFree(ctx->h_ist);
+    if (ctx->h_sc) (void)hipHostFree(ctx->h_sc);
+    if (ctx->h_kpart) (void)hipHostFree(ctx->h_kpart);
+  }
+  delete ctx;
+  return FETI_OK;
+}
+
+const char* feti_last_error(feti_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int feti_setup_mesh(feti_ctx ctx, const feti_mesh_desc* mesh) {
+  if (!ctx || !mesh) return FETI_EINVAL;
+  if (ctx->state != 0) return fail(ctx, FETI_ESTATE, "setup_mesh must be the first call");
+  std::string e = build_mesh(*mesh, ctx->mh);
+  if (!e.empty()) return fail(ctx, FETI_EINVAL, e);
+  ctx->state = 1;
+  return FETI_OK;
+}
+
+int feti_get_sizes(feti_ctx ctx, int64_t* s) {
+  if (!ctx || !s) return FETI_EINVAL;
+  if (ctx->state < 1) return fail(ctx, FETI_ESTATE, "no mesh");
+  const MeshHost& h = ctx->mh;
+  s[0] = (int64_t)h.subs.size();
+  s[1] = h.sum_ns;
+  s[2] = h.n_lambda;
+  s[3] = 3 * h.n_float;
+  s[4] = h.max_ns;
+  s[5] = h.max_nb;
+  s[6] = h.sum_nb;
+  s[7] = (int64_t)h.n1 * h.n1;
+  s[8] = (int64_t)h.mu * h.mu;
+  s[9] = h.n_float;
+  return FETI_OK;
+}
+
+int feti_export_indexing(feti_ctx ctx, int32_t* code, int32_t* sub_off, int32_t* sub_nb,
+                         int32_t* brow_sub, int32_t* brow_local, int8_t* brow_sign) {
+  if (!ctx) return FETI_EINVAL;
+  if (ctx->state < 1) return fail(ctx, FETI_ESTATE, "no mesh");
+  const MeshHost& h = ctx->mh;
+  for (size_t s = 0; s < h.subs.size(); ++s) {
+    const SubHost& sh = h.subs[s];
+    if (code) std::memcpy(code + sh.off, sh.codes.data(), sh.ns * sizeof(int32_t));
+    if (sub_off) sub_off[s] = (int32_t)sh.off;
+    if (sub_nb) sub_nb[s] = sh.nb;
+  }
+  if (sub_off) sub_off[h.subs.size()] = (int32_t)h.sum_ns;
+  for (int64_t j = 0; j < h.n_lambda; ++j)
+    for (int e = 0; e < 2; ++e) {
+      if (brow_sub) brow_sub[2 * j + e] = h.rows[j].sub[e];
+      if (brow_local) brow_local[2 * j + e] = h.rows[j].loc[e];
+      if (brow_sign) brow_sign[2 * j + e] = h.rows[j].sign[e];
+    }
+  return FETI_OK;
+}
+
+int feti_assemble(feti_ctx ctx, const feti_material* P, const feti_material* E, double tau) {
+  if (!ctx || !P || !E) return FETI_EINVAL;
+  if (ctx->state < 1) return fail(ctx, FETI_ESTATE, "assemble before setup_mesh");
+  if (!(tau > 0.0) || !(P->nu < 0.5) || !(E->nu < 0.5) || !(P->E > 0) || !(E->E > 0) ||
+      !(P->c0 > 0) || !(P->K > 0) || !(P->mu_f > 0))
+    return fail(ctx, FETI_EINVAL, "material parameters out of range (need E>0, nu<1/2, c0>0, K>0, tau>0)");
+  if (ctx->state >= 2) {
+    (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  ctx->device = dev;
+  ctx->matP = *P;
+  ctx->matE = *E;
+  ctx->tau = tau;
+  lame(*P, ctx->lamP, ctx->muP);
+  lame(*E, ctx->lamE, ctx->muE);
+  const double den = P->alpha * P->alpha + P->c0 * ctx->lamP;
+  ctx->mpP.mu = ctx->muP;
+  ctx->mpP.kap1 = P->alpha / den;
+  ctx->mpP.kap2 = ctx->lamP / den;
+  ctx->mpP.kap3 = P->c0 / den;
+  ctx->mpP.kf = P->K / P->mu_f;
+  ctx->mpP.tau = tau;
+  ctx->mpE.mu = ctx->muE;
+  ctx->mpE.lam_inv = 1.0 / ctx->lamE;
+  ctx->mpE.tau = tau;
+  RC(upload_mesh(ctx));
+  RC(dalloc(ctx, &ctx->K, ctx->k_total, ctx->mat_allocs));
+  HIPCHK(hipMemsetAsync(ctx->K, 0, ctx->k_total * sizeof(double), ctx->stream));
+  launch_assemble(ctx->dm, ctx->K, ctx->mpP, ctx->mpE, ctx->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->state = 2;
+  ctx->nstep = 0;
+  ctx->have_prev = ctx->have_prev2 = false;
+  return FETI_OK;
+}
+
+int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
+  if (!ctx) return FETI_EINVAL;
+  if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "factor before assemble");
+  if (precision != FETI_FP64) return fail(ctx, FETI_EINVAL, "precision not supported");
+  if (precond < 0 || precond > 2) return fail(ctx, FETI_EINVAL, "bad preconditioner");
+  ctx->precision = precision;
+  ctx->precond = precond;
+  hipStream_t st = ctx->stream;
+  const MeshHost& h = ctx->mh;
+  DevMesh& m = ctx->dm;
+  const int nsub = m.nsub;
+  if (!ctx->Kinv) {
+    RC(dalloc(ctx, &ctx->Kinv, ctx->k_total, ctx->mat_allocs));
+    RC(dalloc(ctx, &ctx->Sbb, ctx->s_total, ctx->mat_allocs));
+    RC(dalloc(ctx, &ctx->Splus, ctx->s_total, ctx->mat_allocs));
+    RC(dalloc(ctx, &ctx->Kbb, ctx->s_total, ctx->mat_allocs));
+  }
+  HIPCHK(hipMemcpyAsync(ctx->Kinv, ctx->K, ctx->k_total * sizeof(double), hipMemcpyDeviceToDevice, st));
+  // host copies of the per-subdomain geometry of the dense blocks
+  std::vector<int> n(nsub), nI(nsub), nsw(nsub);
+  std::vector<int64_t> aofs(nsub), sofs(nsub);
+  std::vector<int32_t> lda(nsub), ldb(nsub), nbv(nsub), nIv(nsub);
+  int64_t ko = 0, so = 0;
+  for (int s = 0; s < nsub; ++s) {
+    const SubHost& sh = h.subs[s];
+    n[s] = sh.ns; nI[s] = sh.nI; nsw[s] = sh.ns - sh.nfix;
+    lda[s] = (int32_t)round8(sh.ns); aofs[s] = ko; ko += (int64_t)sh.ns * lda[s];
+    ldb[s] = (int32_t)round8(sh.nb); sofs[s] = so; so += (int64_t)sh.nb * ldb[s];
+    nbv[s] = sh.nb; nIv[s] = sh.nI;
+  }
+  // lumped preconditioner block K_bb (Section 3.2) from the assembled matrix
+  launch_copy_block(nsub, m.max_nb, m.kofs, m.ld, m.nI, m.sofs, m.ldb, m.nb, ctx->K, ctx->Kbb, st);
+  std::vector<void*> tmp;
+  GJPlan P;
+  std::vector<int32_t> hflag;
+  int rc = build_gj_plan(ctx, P, hflag, nsub, n, nI, nsw, aofs, lda, sofs, ldb, 32, tmp);
+  if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
+  for (int s = 0; s < P.nsteps; ++s) launch_gj_step(P, ctx->Kinv, ctx->Sbb, s, hflag[s] != 0, st);
+  std::vector<int32_t> stat(nsub, 0);
+  std::vector<int32_t> nswv(nsw.begin(), nsw.end());
+  int32_t* d_nsw = nullptr;
+  rc = upload(ctx, &d_nsw, nswv);
+  if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
+  launch_gj_finalize(P, ctx->Kinv, d_nsw, st);
+  // weights of the dual-energy residual norm: |diag| of the Dirichlet preconditioner
+  launch_precond_diag(m, ctx->Sbb, ctx->mdiag, st);
+  // (K^+)_bb into the compact interface blocks
+  launch_copy_block(nsub, m.max_nb, m.kofs, m.ld, m.nI, m.sofs, m.ldb, m.nb, ctx->Kinv, ctx->Splus, st);
+  HIPCHK(hipMemcpyAsync(stat.data(), P.status, nsub * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (void* p : tmp) (void)hipFree(p);
+  for (int s = 0; s < nsub; ++s)
+    if (stat[s]) return fail(ctx, FETI_ESINGULAR, "zero or non-finite pivot in subdomain " + std::to_string(s));
+  // coarse matrix G^T G and its inverse
+  const int nc = ctx->nc;
+  if (nc > 0) {
+    if (!ctx->Cinv) RC(dalloc(ctx, &ctx->Cinv, (size_t)nc * nc, ctx->mat_allocs));
+    launch_gtg(m, ctx->Cinv, nc, st);
+    GJPlan C;
+    std::vector<int32_t> cflag;
+    std::vector<void*> ctmp;
+    rc = build_gj_plan(ctx, C, cflag, 1, {nc}, {0}, {nc}, {0}, {nc}, {-1}, {nc}, 32, ctmp);
+    if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
+    for (int s = 0; s < C.nsteps; ++s) launch_gj_step(C, ctx->Cinv, nullptr, s, false, st);
+    int32_t* d_nc = nullptr;
+    std::vector<int32_t> ncv{nc};
+    rc = upload(ctx, &d_nc, ncv);
+    if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
+    launch_gj_finalize(C, ctx->Cinv, d_nc, st);
+    int32_t cs = 0;
+    HIPCHK(hipMemcpyAsync(&cs, C.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (void* p : ctmp) (void)hipFree(p);
+    if (cs) return fail(ctx, FETI_ESINGULAR, "singular coarse matrix G^T G");
+  }
+  HIPCHK(hipGetLastError());
+  ctx->state = 3;
+  return FETI_OK;
+}
+
+int feti_init_state(feti_ctx ctx, const feti_load* load) {
+  if (!ctx || !load) return FETI_EINVAL;
+  if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "init_state before assemble");
+  DevMesh& m = ctx->dm;
+  HIPCHK(hipMemsetAsync(ctx->u, 0, m.sum_ns * sizeof(double), ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->lam_prev, 0, m.n_lambda * sizeof(double), ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->lam_prev2, 0, m.n_lambda * sizeof(double), ctx->stream));
+  LoadDev L = make_load(ctx, load);
+  launch_init_eta(m, ctx->u, L, ctx->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->nstep = 0;
+  ctx->have_prev = ctx->have_prev2 = false;
+  return FETI_OK;
+}
+
+int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, feti_stats* stats) {
+  if (!ctx || !load || !o) return FETI_EINVAL;
+  if (ctx->state < 3) return fail(ctx, FETI_ESTATE, "step before factor_subdomains");
+  if (!(o->tol > 0.0) || o->max_it < 1) return fail(ctx, FETI_EINVAL, "bad solve options");
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  HIPCHK(hipEventRecord(ctx->ev[0], st));
+  HIPCHK(hipMemsetAsync(ctx->f, 0, m.sum_ns * sizeof(double), st));
+  LoadDev L = make_load(ctx, load);
+  launch_rhs(m, ctx->u, ctx->f, ctx->mpP, ctx->mpE, L, st);
+  // start vector
+  int used = o->start;
+  if (o->start == FETI_START_ZERO || (o->start != FETI_START_GIVEN && !ctx->have_prev)) {
+    HIPCHK(hipMemsetAsync(ctx->lam, 0, m.n_lambda * sizeof(double), st));
+    used = FETI_START_ZERO;
+  }
+  if (o->start == FETI_START_PREVIOUS && ctx->have_prev) {
+    launch_axpby(m.n_lambda, 1.0, ctx->lam_prev, 0.0, nullptr, ctx->lam, st);
+  } else if (o->start == FETI_START_EXTRAPOLATE && ctx->have_prev) {
+    if (ctx->have_prev2) launch_axpby(m.n_lambda, 2.0, ctx->lam_prev, -1.0, ctx->lam_prev2, ctx->lam, st);
+    else { launch_axpby(m.n_lambda, 1.0, ctx->lam_prev, 0.0, nullptr, ctx->lam, st); used = FETI_START_PREVIOUS; }
+  }
+  // FETI_START_GIVEN: ctx->lam was set by feti_set_start
+  HIPCHK(hipGetLastError());
+  const bool cold = !ctx->have_prev && o->start != FETI_START_GIVEN;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  int rc = solve_refined(ctx, o, cold ? std::max(o->ir_cold, o->ir_max) : o->ir_max, stats);
+  // keep the multiplier history
+  std::swap(ctx->lam_prev2, ctx->lam_prev);
+  launch_axpby(m.n_lambda, 1.0, ctx->lam, 0.0, nullptr, ctx->lam_prev, st);
+  ctx->have_prev2 = ctx->have_prev;
+  ctx->have_prev = true;
+  ctx->nstep += 1;
+  HIPCHK(hipEventRecord(ctx->ev[5], st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (stats) {
+    stats->start_used = used;
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]);
+    stats->t_ms[0] = ms;
+    hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[5]);
+    stats->t_ms[5] = ms;
+  }
+  return rc;
+}
+
+int feti_solve(feti_ctx ctx, const double* f_dev, double* lambda_dev, double* u_dev,
+               const feti_solve_opts* o, feti_stats* stats) {
+  if (!ctx || !f_dev || !o) return FETI_EINVAL;
+  if (ctx->state < 3) return fail(ctx, FETI_ESTATE, "solve before factor_subdomains");
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  HIPCHK(hipEventRecord(ctx->ev[0], st));
+  HIPCHK(hipMemcpyAsync(ctx->f, f_dev, m.sum_ns * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (o->start == FETI_START_GIVEN && lambda_dev)
+    HIPCHK(hipMemcpyAsync(ctx->lam, lambda_dev, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else
+    HIPCHK(hipMemsetAsync(ctx->lam, 0, m.n_lambda * sizeof(double), st));
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  int rc = solve_refined(ctx, o, o->ir_max, stats);
+  if (lambda_dev)
+    HIPCHK(hipMemcpyAsync(lambda_dev, ctx->lam, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (u_dev) HIPCHK(hipMemcpyAsync(u_dev, ctx->u, m.sum_ns * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return rc;
+}
+
+int feti_get_solution(feti_ctx ctx, double* u_dev, double* lambda_dev) {
+  if (!ctx) return FETI_EINVAL;
+  if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "no solution");
+  DevMesh& m = ctx->dm;
+  if (u_dev) HIPCHK(hipMemcpyAsync(u_dev, ctx->u, m.sum_ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  if (lambda_dev)
+    HIPCHK(hipMemcpyAsync(lambda_dev, ctx->lam_prev, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FETI_OK;
+}
+
+int feti_set_start(feti_ctx ctx, const double* lambda_dev) {
+  if (!ctx || !lambda_dev) return FETI_EINVAL;
+  if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "set_start before assemble");
+  HIPCHK(hipMemcpyAsync(ctx->lam, lambda_dev, ctx->dm.n_lambda * sizeof(double), hipMemcpyDeviceToDevice,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FETI_OK;
+}
+
+int feti_export_local(feti_ctx ctx, int32_t sub, int32_t which, double* out) {
+  if (!ctx || !out) return FETI_EINVAL;
+  if (ctx->state < 2 || (which != FETI_EXPORT_K && ctx->state < 3))
+    return fail(ctx, FETI_ESTATE, "export before the stage that produces it");
+  if (sub < 0 || sub >= (int)ctx->mh.subs.size()) return fail(ctx, FETI_EINVAL, "bad subdomain");
+  const MeshHost& h = ctx->mh;
+  int64_t ko = 0, so = 0;
+  for (int s = 0; s < sub; ++s) {
+    ko += (int64_t)h.subs[s].ns * round8(h.subs[s].ns);
+    so += (int64_t)h.subs[s].nb * round8(h.subs[s].nb);
+  }
+  const SubHost& sh = h.subs[sub];
+  if (which == FETI_EXPORT_SBB) {
+    HIPCHK(hipMemcpy2DAsync(out, sh.nb * sizeof(double), ctx->Sbb + so, round8(sh.nb) * sizeof(double),
+                            sh.nb * sizeof(double), sh.nb, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    const double* src = which == FETI_EXPORT_K ? ctx->K : ctx->Kinv;
+    HIPCHK(hipMemcpy2DAsync(out, sh.ns * sizeof(double), src + ko, round8(sh.ns) * sizeof(double),
+                            sh.ns * sizeof(double), sh.ns, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FETI_OK;
+}
+
+int feti_apply_F(feti_ctx ctx, const double* x, double* y) {
+  if (!ctx || !x || !y) return FETI_EINVAL;
+  if (ctx->state < 3) return fail(ctx, FETI_ESTATE, "apply_F before factor_subdomains");
+  op_F(ctx, x, y, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FETI_OK;
+}
+
+int feti_apply_precond(feti_ctx ctx, const double* x, double* y) {
+  if (!ctx || !x || !y) return FETI_EINVAL;
+  if (ctx->state < 3) return fail(ctx, FETI_ESTATE, "apply_precond before factor_subdomains");
+  op_M(ctx, x, y, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FETI_OK;
+}
+
+int feti_get_rhs(feti_ctx ctx, double* f_dev) {
+  if (!ctx || !f_dev) return FETI_EINVAL;
+  if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "no right-hand side");
+  HIPCHK(hipMemcpyAsync(f_dev, ctx->f, ctx->dm.sum_ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FETI_OK;
+}
+
+int feti_time_kernel(feti_ctx ctx, int32_t which, int32_t reps, double* avg_ms, double* work) {
+  if (!ctx || !avg_ms || !work) return FETI_EINVAL;
+  if (ctx->state < 3) return fail(ctx, FETI_ESTATE, "time_kernel before factor_subdomains");
+  if (which < 0 || which > 3 || reps < 1) return fail(ctx, FETI_EINVAL, "bad kernel id");
+  DevMesh& m = ctx->dm;
+  const MeshHost& h = ctx->mh;
+  hipStream_t st = ctx->stream;
+  double w = 0.0;
+  if (which == FETI_KERNEL_ELIMINATION) {
+    HIPCHK(hipEventRecord(ctx->ev[6], st));
+    RC(feti_factor_subdomains(ctx, ctx->precision, ctx->precond));
+    HIPCHK(hipEventRecord(ctx->ev[7], st));
+    HIPCHK(hipEventSynchronize(ctx->ev[7]));
+    for (const SubHost& sh : h.subs) w += (double)sh.ns * sh.ns * sh.ns;
+    reps = 1;
+  } else {
+    GemvArgs a;
+    if (which == FETI_KERNEL_LOCAL_SOLVE) {
+      a.A = ctx->Kinv; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0; a.xbase = ctx->f; a.y = ctx->ytmp;
+      for (const SubHost& sh : h.subs) w += 8.0 * ((double)sh.ns * sh.ns + 2.0 * sh.ns);
+    } else {
+      a.A = which == FETI_KERNEL_IFACE_GEMV ? ctx->Splus : ctx->Sbb;
+      a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1; a.v = ctx->p;
+      a.gmode = which == FETI_KERNEL_IFACE_GEMV ? G_SIGNED : G_SCALED; a.gcoef = 1.0;
+      a.y = ctx->yb;
+      for (const SubHost& sh : h.subs) w += 8.0 * ((double)sh.nb * sh.nb + 2.0 * sh.nb);
+    }
+    launch_sgemv(m, a, st);  // warm-up launch
+    HIPCHK(hipEventRecord(ctx->ev[6], st));
+    for (int i = 0; i < reps; ++i) launch_sgemv(m, a, st);
+    HIPCHK(hipEventRecord(ctx->ev[7], st));
+    HIPCHK(hipEventSynchronize(ctx->ev[7]));
+  }
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]));
+  *avg_ms = (double)ms / reps;
+  *work = w;
+  return FETI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,333 @@
+// Host-side mesh, decomposition and numbering (runs once per problem).
+//
+// Builds the structured right-triangle mesh of the unit square (Section 4.1
+// uses uniform triangulations), the nsub_x x nsub_y subdomain grid, the local
+// DOF order of every subdomain, the signed Boolean jump rows that glue the
+// torn fields (Section 3.1: H_P, H_E of eq. (linalg-system) become the signed
+// entries of one row per glued DOF pair), the weights of D = (B B^T)^{-1} for
+// the preconditioner, the element DOF tables for the assembly kernels and the
+// rigid modes of floating subdomains for the coarse space.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <tuple>
+#include <unordered_map>
+
+#include "feti_internal.h"
+
+namespace feti {
+
+namespace {
+
+bool on_sides(int i, int j, int nmax, uint32_t mask) {
+  return ((mask & 1u) && i == 0) || ((mask & 2u) && i == nmax) || ((mask & 4u) && j == 0) ||
+         ((mask & 8u) && j == nmax);
+}
+
+bool cell_poro(int layout, int i, int j, int n) {
+  const double xc = (i + 0.5) / n, yc = (j + 0.5) / n;
+  switch (layout) {
+    case FETI_XSPLIT: return xc < 0.5;
+    case FETI_YSPLIT: return yc < 0.5;
+    default: return xc > 0.25 && xc < 0.75 && yc > 0.25 && yc < 0.75;
+  }
+}
+
+int field_order(int kind) {
+  switch (kind) {
+    case K_UX: case K_UY: return 0;
+    case K_ETA: return 1;
+    case K_XIP: case K_XIE: return 2;
+    default: return 3;
+  }
+}
+
+// inverse of a small symmetric positive definite matrix (size <= 3) by Gauss-Jordan
+void small_inverse(int n, double* a) {
+  double b[9];
+  for (int i = 0; i < n * n; ++i) b[i] = 0.0;
+  for (int i = 0; i < n; ++i) b[i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    const double piv = a[k * n + k];
+    for (int j = 0; j < n; ++j) { a[k * n + j] /= piv; b[k * n + j] /= piv; }
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = a[i * n + k];
+      for (int j = 0; j < n; ++j) { a[i * n + j] -= f * a[k * n + j]; b[i * n + j] -= f * b[k * n + j]; }
+    }
+  }
+  for (int i = 0; i < n * n; ++i) a[i] = b[i];
+}
+
+}  // namespace
+
+std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
+  const int n = d.ncell;
+  if (n < 1 || (d.order_u != 1 && d.order_u != 2) || d.nsub_x < 1 || d.nsub_y < 1 ||
+      d.nsub_x > n || d.nsub_y > n || d.layout < 0 || d.layout > 2)
+    return "invalid mesh description";
+  m = MeshHost();
+  m.desc = d;
+  m.ratio = d.order_u == 2 ? 2 : 1;
+  const int r = m.ratio;
+  const int nu = r * n;  // last displacement lattice index
+  m.mu = nu + 1;
+  m.n1 = n + 1;
+  std::vector<int> cx(d.nsub_x + 1), cy(d.nsub_y + 1);
+  for (int a = 0; a <= d.nsub_x; ++a) cx[a] = (int)((int64_t)a * n / d.nsub_x);
+  for (int b = 0; b <= d.nsub_y; ++b) cy[b] = (int)((int64_t)b * n / d.nsub_y);
+  const int nsub = d.nsub_x * d.nsub_y;
+  m.subs.resize(nsub);
+  // owners of every DOF code
+  std::unordered_map<int32_t, std::vector<int32_t>> owners;
+  owners.reserve((size_t)nsub * 64);
+  std::vector<bool> has_dir(nsub, false);
+  for (int b = 0; b < d.nsub_y; ++b) {
+    for (int a = 0; a < d.nsub_x; ++a) {
+      const int sid = b * d.nsub_x + a;
+      SubHost& s = m.subs[sid];
+      s.sid = sid;
+      s.i0 = cx[a]; s.i1 = cx[a + 1]; s.j0 = cy[b]; s.j1 = cy[b + 1];
+      if (s.i1 <= s.i0 || s.j1 <= s.j0) return "empty subdomain";
+      const bool p0 = cell_poro(d.layout, s.i0, s.j0, n);
+      for (int j = s.j0; j < s.j1; ++j)
+        for (int i = s.i0; i < s.i1; ++i)
+          if (cell_poro(d.layout, i, j, n) != p0) return "a subdomain straddles the interface";
+      s.poro = p0;
+      for (int J = r * s.j0; J <= r * s.j1; ++J)
+        for (int I = r * s.i0; I <= r * s.i1; ++I) {
+          if (on_sides(I, J, nu, d.dirichlet_u)) { has_dir[sid] = true; continue; }
+          const int32_t node = J * m.mu + I;
+          s.codes.push_back(8 * node + K_UX);
+          s.codes.push_back(8 * node + K_UY);
+        }
+      for (int j = s.j0; j <= s.j1; ++j)
+        for (int i = s.i0; i <= s.i1; ++i) {
+          const int32_t node = j * m.n1 + i;
+          if (s.poro) {
+            s.codes.push_back(8 * node + K_ETA);
+            s.codes.push_back(8 * node + K_XIP);
+            if (!on_sides(i, j, n, d.dirichlet_p)) s.codes.push_back(8 * node + K_P);
+          } else {
+            s.codes.push_back(8 * node + K_XIE);
+          }
+        }
+      for (int32_t c : s.codes) owners[c].push_back(sid);
+    }
+  }
+  // categories and local order
+  for (SubHost& s : m.subs) {
+    s.floating = !has_dir[s.sid];
+    int32_t fixA = -1, fixB = -1, fixC = -1;
+    if (s.floating) {
+      const int32_t A = (r * s.j0) * m.mu + r * s.i0;
+      const int32_t C = (r * s.j1) * m.mu + r * s.i1;
+      fixA = 8 * A + K_UX; fixB = 8 * A + K_UY; fixC = 8 * C + K_UX;
+    }
+    struct Key { int cat, fo, node, comp; int32_t code; };
+    std::vector<Key> keys;
+    keys.reserve(s.codes.size());
+    for (int32_t c : s.codes) {
+      const int node = c / 8, kind = c % 8;
+      const bool shared = owners[c].size() > 1;
+      int cat;
+      if (c == fixA || c == fixB || c == fixC) cat = C_FIX;
+      else if (kind <= K_ETA) cat = shared ? C_BU : C_IU;
+      else cat = shared ? C_BP : C_IP;
+      keys.push_back({cat, field_order(kind), node, kind == K_UY ? 1 : 0, c});
+    }
+    std::sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
+      return std::tie(x.cat, x.fo, x.node, x.comp) < std::tie(y.cat, y.fo, y.node, y.comp);
+    });
+    s.codes.clear();
+    s.cats.clear();
+    for (const Key& k : keys) { s.codes.push_back(k.code); s.cats.push_back((int8_t)k.cat); }
+    s.ns = (int)s.codes.size();
+    s.nI = 0; s.nb = 0; s.nfix = 0;
+    for (int8_t c : s.cats) {
+      if (c < C_BU) ++s.nI; else ++s.nb;
+      if (c == C_FIX) ++s.nfix;
+    }
+    if (s.floating && s.nfix != 3) return "floating subdomain without its three fixed DOFs";
+  }
+  // offsets
+  int64_t off = 0, boff = 0;
+  for (SubHost& s : m.subs) {
+    s.off = off; s.boff = boff;
+    off += s.ns; boff += s.nb;
+    m.max_ns = std::max(m.max_ns, s.ns);
+    m.max_nb = std::max(m.max_nb, s.nb);
+  }
+  m.sum_ns = off;
+  m.sum_nb = boff;
+  // position of each code in each subdomain
+  std::vector<std::unordered_map<int32_t, int32_t>> pos(nsub);
+  for (SubHost& s : m.subs) {
+    pos[s.sid].reserve(s.codes.size() * 2);
+    for (int i = 0; i < s.ns; ++i) pos[s.sid][s.codes[i]] = i;
+  }
+  // jump rows sorted by (kind, node, pair index)
+  std::vector<int32_t> shared_codes;
+  for (auto& kv : owners)
+    if (kv.second.size() > 1) shared_codes.push_back(kv.first);
+  std::sort(shared_codes.begin(), shared_codes.end(), [](int32_t x, int32_t y) {
+    return std::make_pair(x % 8, x / 8) < std::make_pair(y % 8, y / 8);
+  });
+  for (int32_t c : shared_codes) {
+    std::vector<int32_t> S = owners[c];
+    std::sort(S.begin(), S.end());
+    const int gstart = (int)m.rows.size();
+    const int gsize = (int)S.size() - 1;
+    for (size_t k = 0; k + 1 < S.size(); ++k) {
+      JumpRow jr{};
+      jr.sub[0] = S[k]; jr.sub[1] = S[k + 1];
+      jr.loc[0] = pos[S[k]][c]; jr.loc[1] = pos[S[k + 1]][c];
+      jr.sign[0] = 1; jr.sign[1] = -1;
+      if (m.subs[S[k]].poro != m.subs[S[k + 1]].poro && !m.subs[S[k]].poro) {
+        jr.sign[0] = -1; jr.sign[1] = 1;
+      }
+      jr.code = c;
+      jr.mult = (int32_t)S.size();
+      jr.kind = c % 8;
+      m.rows.push_back(jr);
+      m.grp_start.push_back(gstart);
+      m.grp_size.push_back(gsize);
+    }
+    if (gsize > 3) return "a node shared by more than four subdomains";
+    // D block = (B_g B_g^T)^{-1} over this group's rows
+    double bbt[9] = {0};
+    for (int a = 0; a < gsize; ++a)
+      for (int b = 0; b < gsize; ++b) {
+        double v = 0.0;
+        const JumpRow& ra = m.rows[gstart + a];
+        const JumpRow& rb = m.rows[gstart + b];
+        for (int ea = 0; ea < 2; ++ea)
+          for (int eb = 0; eb < 2; ++eb)
+            if (ra.sub[ea] == rb.sub[eb]) v += (double)ra.sign[ea] * rb.sign[eb];
+        bbt[a * gsize + b] = v;
+      }
+    small_inverse(gsize, bbt);
+    for (int a = 0; a < gsize; ++a)
+      for (int b = 0; b < 3; ++b) m.dwt.push_back(b < gsize ? bbt[a * gsize + b] : 0.0);
+  }
+  m.n_lambda = (int64_t)m.rows.size();
+  // gather lists and jump maps in the concatenated interface space
+  m.bg_row.assign(2 * m.sum_nb, -1);
+  m.bg_sign.assign(2 * m.sum_nb, 0.0);
+  m.bd_row.assign(3 * m.sum_nb, -1);
+  m.bd_wt.assign(3 * m.sum_nb, 0.0);
+  m.jr_b.assign(2 * m.n_lambda, -1);
+  m.jr_sign.assign(2 * m.n_lambda, 0.0);
+  for (int64_t j = 0; j < m.n_lambda; ++j) {
+    const JumpRow& jr = m.rows[j];
+    for (int e = 0; e < 2; ++e) {
+      const SubHost& s = m.subs[jr.sub[e]];
+      const int bl = jr.loc[e] - s.nI;
+      if (bl < 0) return "jump row on an interior DOF";
+      const int64_t gb = s.boff + bl;
+      m.jr_b[2 * j + e] = (int32_t)gb;
+      m.jr_sign[2 * j + e] = jr.sign[e];
+      int slot = m.bg_row[2 * gb] < 0 ? 0 : 1;
+      if (m.bg_row[2 * gb + slot] >= 0) return "interface DOF in more than two jump rows";
+      m.bg_row[2 * gb + slot] = (int32_t)j;
+      m.bg_sign[2 * gb + slot] = jr.sign[e];
+    }
+  }
+  // scaled gather: (B^T D)[b, k] = sum_j B[j, b] D[j, k] over the group of b's DOF
+  for (int64_t gb = 0; gb < m.sum_nb; ++gb) {
+    if (m.bg_row[2 * gb] < 0) continue;
+    const int j0 = m.bg_row[2 * gb];
+    const int gs = m.grp_start[j0], gz = m.grp_size[j0];
+    for (int k = 0; k < gz; ++k) {
+      double v = 0.0;
+      for (int slot = 0; slot < 2; ++slot) {
+        const int j = m.bg_row[2 * gb + slot];
+        if (j < 0) continue;
+        v += m.bg_sign[2 * gb + slot] * m.dwt[3 * j + k];
+      }
+      m.bd_row[3 * gb + k] = gs + k;
+      m.bd_wt[3 * gb + k] = v;
+    }
+  }
+  // coarse space: rigid modes of floating subdomains
+  m.sub_float.assign(nsub, -1);
+  m.rb.assign(3 * m.sum_nb, 0.0);
+  m.rfull.assign(3 * m.sum_ns, 0.0);
+  const double hs = 1.0 / (double)nu;
+  for (SubHost& s : m.subs) {
+    if (!s.floating) continue;
+    m.sub_float[s.sid] = (int32_t)m.float_sub.size();
+    m.float_sub.push_back(s.sid);
+    const double xc = 0.5 * (s.i0 + s.i1) / (double)n, yc = 0.5 * (s.j0 + s.j1) / (double)n;
+    for (int i = 0; i < s.ns; ++i) {
+      const int32_t c = s.codes[i];
+      const int kind = c % 8, node = c / 8;
+      if (kind > K_UY) continue;
+      const double x = (node % m.mu) * hs, y = (node / m.mu) * hs;
+      double* R = &m.rfull[3 * (s.off + i)];
+      R[kind] = 1.0;
+      R[2] = kind == K_UX ? -(y - yc) : (x - xc);
+      if (i >= s.nI) {
+        double* Rb = &m.rb[3 * (s.boff + (i - s.nI))];
+        Rb[0] = R[0]; Rb[1] = R[1]; Rb[2] = R[2];
+      }
+    }
+  }
+  m.n_float = (int)m.float_sub.size();
+  // element tables
+  const int nloc = d.order_u == 2 ? 6 : 3;
+  m.edof = 2 * nloc + 9;  // u, then xi, eta, p (elastic: u, xi_E, unused)
+  m.sub_el_off.assign(nsub + 1, 0);
+  for (SubHost& s : m.subs) {
+    const auto& P = pos[s.sid];
+    for (int j = s.j0; j < s.j1; ++j)
+      for (int i = s.i0; i < s.i1; ++i)
+        for (int t = 0; t < 2; ++t) {
+          // vertices on the P1 lattice (counter-clockwise)
+          int vi[3], vj[3];
+          if (t == 0) { vi[0] = i; vj[0] = j; vi[1] = i + 1; vj[1] = j; vi[2] = i + 1; vj[2] = j + 1; }
+          else { vi[0] = i; vj[0] = j; vi[1] = i + 1; vj[1] = j + 1; vi[2] = i; vj[2] = j + 1; }
+          int32_t un[6];
+          for (int v = 0; v < 3; ++v) un[v] = (r * vj[v]) * m.mu + r * vi[v];
+          if (nloc == 6) {
+            const int pa[3] = {0, 1, 2}, pb[3] = {1, 2, 0};
+            for (int e = 0; e < 3; ++e) {
+              const int I = (r * vi[pa[e]] + r * vi[pb[e]]) / 2, J = (r * vj[pa[e]] + r * vj[pb[e]]) / 2;
+              un[3 + e] = J * m.mu + I;
+            }
+          }
+          m.el_sub.push_back(s.sid);
+          m.el_cell.push_back(j * n + i);
+          m.el_type.push_back(t);
+          std::vector<int32_t> codes(m.edof, -1);
+          for (int a = 0; a < nloc; ++a) {
+            codes[2 * a] = 8 * un[a] + K_UX;
+            codes[2 * a + 1] = 8 * un[a] + K_UY;
+          }
+          for (int v = 0; v < 3; ++v) {
+            const int32_t node = vj[v] * m.n1 + vi[v];
+            if (s.poro) {
+              codes[2 * nloc + v] = 8 * node + K_XIP;
+              codes[2 * nloc + 3 + v] = 8 * node + K_ETA;
+              codes[2 * nloc + 6 + v] = 8 * node + K_P;
+            } else {
+              codes[2 * nloc + v] = 8 * node + K_XIE;
+            }
+          }
+          for (int a = 0; a < m.edof; ++a) {
+            int32_t li = -1;
+            if (codes[a] >= 0) {
+              auto it = P.find(codes[a]);
+              if (it != P.end()) li = it->second;
+            }
+            m.el_ldof.push_back(li);
+            m.el_code.push_back(codes[a]);
+          }
+        }
+    m.sub_el_off[s.sid + 1] = (int32_t)m.el_sub.size();
+  }
+  return "";
+}
+
+}  // namespace feti

@@ -1,0 +1,106 @@
+// Device-side tables and kernel launchers of the FETI library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fem_device.h"
+#include "loads_device.h"
+
+namespace feti {
+
+// Device copies of the mesh and numbering tables (see MeshHost).
+struct DevMesh {
+  int nsub = 0, order = 2, ncell = 0, edof = 0, nelem = 0;
+  int64_t sum_ns = 0, sum_nb = 0, n_lambda = 0;
+  int n_float = 0, max_ns = 0, max_nb = 0;
+  // per subdomain
+  int32_t* ns = nullptr;        // local size
+  int32_t* nI = nullptr;        // interior size
+  int32_t* nb = nullptr;        // interface size (fixed DOFs included, trailing)
+  int32_t* nfix = nullptr;      // 0 or 3
+  int64_t* soff = nullptr;      // torn offset
+  int64_t* boff = nullptr;      // interface-space offset
+  int64_t* kofs = nullptr;      // offset of the dense n_s x ld block
+  int32_t* ld = nullptr;        // leading dimension of the dense block
+  int64_t* sofs = nullptr;      // offset of the dense n_b x ldb interface blocks
+  int32_t* ldb = nullptr;
+  uint8_t* sub_poro = nullptr;
+  int32_t* sub_float = nullptr; // index in the coarse space or -1
+  // per local DOF (torn)
+  int32_t* code = nullptr;
+  double* rfull = nullptr;      // 3 per DOF
+  // elements
+  int32_t *el_sub = nullptr, *el_cell = nullptr, *el_type = nullptr, *el_ldof = nullptr,
+          *el_code = nullptr;
+  // interface space
+  int32_t* bg_row = nullptr;    // 2 per b DOF
+  double* bg_sign = nullptr;
+  int32_t* bd_row = nullptr;    // 3 per b DOF
+  double* bd_wt = nullptr;
+  double* rb = nullptr;         // 3 per b DOF
+  int32_t* b_sub = nullptr;     // owning subdomain of each b DOF
+  int32_t* b_torn = nullptr;    // torn index of each b DOF
+  // multipliers
+  int32_t* jr_b = nullptr;      // 2 per row
+  double* jr_sign = nullptr;
+  int32_t* grp_start = nullptr;
+  int32_t* grp_size = nullptr;
+  double* dwt = nullptr;        // 3 per row
+  int32_t* row_kind = nullptr;  // DOF kind of each row
+  // coarse space
+  int32_t* float_sub = nullptr;
+};
+
+// assembly / right-hand side (kernels_fem.hip)
+void launch_assemble(const DevMesh& m, double* K, MatParams mpP, MatParams mpE, hipStream_t st);
+void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams mpP, MatParams mpE,
+                const LoadDev& L, hipStream_t st);
+void launch_init_eta(const DevMesh& m, double* u, const LoadDev& L, hipStream_t st);
+void launch_elem_matvec(const DevMesh& m, const double* x, double* y, MatParams mpP, MatParams mpE,
+                        hipStream_t st);
+
+// batched Gauss-Jordan elimination (kernels_gj.hip)
+struct GJPlan {
+  int nmat = 0;          // matrices in the batch
+  int nb = 32;           // panel width
+  int nsteps = 0;        // panel steps (max over matrices)
+  int max_n = 0;
+  // per (step, matrix): panel start and width (0 = idle), flag bit 0 = snapshot after this step
+  int32_t* pstart = nullptr;
+  int32_t* pwidth = nullptr;
+  int32_t* pflag = nullptr;
+  // per matrix
+  int64_t* aofs = nullptr;  // offset of the matrix
+  int32_t* lda = nullptr;
+  int32_t* n = nullptr;     // full size (rows/cols that are updated)
+  int64_t* snap_ofs = nullptr;  // where the trailing block is copied at the snapshot (-1 = none)
+  int32_t* snap_at = nullptr;   // first index of the snapshot block
+  int32_t* snap_ld = nullptr;
+  // workspace
+  double* pinv = nullptr;   // nmat x nb x nb
+  double* wrow = nullptr;   // nmat x nb x max_n
+  int32_t* status = nullptr;  // per matrix: 0 ok, 1 singular pivot
+};
+void launch_gj_step(const GJPlan& p, double* A, double* snap, int step, bool snap_now,
+                    hipStream_t st);
+void launch_gj_finalize(const GJPlan& p, double* A, const int32_t* nswept, hipStream_t st);
+
+// interface operators: see iface.h
+enum GatherMode { G_NONE = 0, G_SIGNED = 1, G_SCALED = 2 };
+struct GemvArgs {
+  const double* A = nullptr;     // matrix base
+  const int64_t* aofs = nullptr; // per subdomain offset
+  const int32_t* lda = nullptr;
+  int which_n = 0;               // 0: n = ns (full local), 1: n = nb (interface block)
+  const double* xbase = nullptr; // torn (full) or interface-space vector, or nullptr
+  const double* v = nullptr;     // multiplier vector gathered into the interface part
+  int gmode = G_NONE;
+  double gcoef = -1.0;           // x_b = xbase_b + gcoef * gather(v)
+  double* y = nullptr;           // output, torn (full) or interface space
+  const double* alpha_c = nullptr;  // optional: y += R alpha_c (full only)
+  const int32_t* skip = nullptr;    // optional: do nothing when *skip != 0
+};
+
+}  // namespace feti

@@ -1,0 +1,267 @@
+// Batched pivot-free symmetric Gauss-Jordan elimination on MFMA (FP64).
+//
+// Each local matrix K_s is swept pivot block by pivot block in its
+// [interior | interface] order.  Sweeping a pivot block P of
+//     [[P, C], [C^T, D]]  gives  [[-P^{-1}, P^{-1} C], [C^T P^{-1}, D - C^T P^{-1} C]],
+// so after the interior blocks the trailing block holds the interface Schur
+// complement S_bb = K_bb - K_bI K_II^{-1} K_Ib of eq. (reduced-system) (it is
+// copied out at that point), and after every non-fixed pivot the swept block
+// holds -K_ss^{-1}.  The pivots are the D of the LDL^T factorisation in the
+// same order: the order [I_U | I_P | b_U | b_P] makes K_s quasi-definite (the
+// U block is positive definite, the P Schur complement negative definite),
+// so no pivoting is needed (Theorem 3.1's reduction).
+//
+// The O(n^3) part is the rank-kw update D -= C^T W with W = P^{-1} C, done on
+// v_mfma_f64_16x16x4 tiles: each 64x64 output tile is owned by one workgroup
+// of four wavefronts, each computing a 32x32 quarter as 2x2 MFMA blocks.
+#include "kernels.h"
+
+namespace feti {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int GJ_NB = 32;  // maximum panel width (the plan may use less)
+
+// (1) invert the pivot block in LDS by in-place Gauss-Jordan
+__global__ void __launch_bounds__(256) k_gj_pivot(const int32_t* __restrict__ pstart,
+                                                  const int32_t* __restrict__ pwidth,
+                                                  const int64_t* __restrict__ aofs,
+                                                  const int32_t* __restrict__ lda,
+                                                  const double* __restrict__ A,
+                                                  double* __restrict__ pinv,
+                                                  int32_t* __restrict__ status, int nmat, int step,
+                                                  int nb) {
+  const int m = blockIdx.x;
+  const int kw = pwidth[step * nmat + m];
+  if (kw == 0) return;
+  const int k0 = pstart[step * nmat + m];
+  const double* Am = A + aofs[m];
+  const int ld = lda[m];
+  __shared__ double M[GJ_NB][GJ_NB + 1];
+  __shared__ double rowk[GJ_NB];
+  __shared__ double colk[GJ_NB];
+  for (int t = threadIdx.x; t < kw * kw; t += blockDim.x) {
+    const int i = t / kw, j = t % kw;
+    M[i][j] = Am[(int64_t)(k0 + i) * ld + k0 + j];
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int k = 0; k < kw; ++k) {
+    const double piv = M[k][k];
+    if (!(fabs(piv) > 0.0) || !isfinite(piv)) bad = true;
+    const double pinvk = 1.0 / piv;
+    for (int t = threadIdx.x; t < kw; t += blockDim.x) {
+      rowk[t] = t == k ? pinvk : M[k][t] * pinvk;
+      colk[t] = M[t][k];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kw * kw; t += blockDim.x) {
+      const int i = t / kw, j = t % kw;
+      if (i == k) continue;
+      if (j == k) M[i][j] = -colk[i] * pinvk;
+      else M[i][j] -= colk[i] * rowk[j];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kw; t += blockDim.x) M[k][t] = rowk[t];
+    __syncthreads();
+  }
+  if (bad && threadIdx.x == 0) status[m] = 1;
+  double* Pm = pinv + (int64_t)m * nb * nb;
+  for (int t = threadIdx.x; t < kw * kw; t += blockDim.x) {
+    const int i = t / kw, j = t % kw;
+    Pm[i * nb + j] = M[i][j];
+  }
+}
+
+// (2) W = P^{-1} C over all columns outside the panel (one thread per column)
+__global__ void __launch_bounds__(256) k_gj_row(const int32_t* __restrict__ pstart,
+                                                const int32_t* __restrict__ pwidth,
+                                                const int64_t* __restrict__ aofs,
+                                                const int32_t* __restrict__ lda,
+                                                const int32_t* __restrict__ nn,
+                                                const double* __restrict__ A,
+                                                const double* __restrict__ pinv,
+                                                double* __restrict__ wrow, int nmat, int step,
+                                                int nb, int max_n) {
+  const int m = blockIdx.y;
+  const int kw = pwidth[step * nmat + m];
+  if (kw == 0) return;
+  const int k0 = pstart[step * nmat + m];
+  const int n = nn[m];
+  __shared__ double P[GJ_NB][GJ_NB];
+  const double* Pm = pinv + (int64_t)m * nb * nb;
+  for (int t = threadIdx.x; t < GJ_NB * GJ_NB; t += blockDim.x) {
+    const int i = t / GJ_NB, k = t % GJ_NB;
+    P[i][k] = (i < kw && k < kw) ? Pm[i * nb + k] : 0.0;
+  }
+  __syncthreads();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n || (j >= k0 && j < k0 + kw)) return;
+  const double* Am = A + aofs[m];
+  const int ld = lda[m];
+  double c[GJ_NB];
+#pragma unroll
+  for (int k = 0; k < GJ_NB; ++k) c[k] = k < kw ? Am[(int64_t)(k0 + k) * ld + j] : 0.0;
+  double* W = wrow + (int64_t)m * nb * max_n;
+  for (int i = 0; i < kw; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < GJ_NB; ++k) s += P[i][k] * c[k];
+    W[(int64_t)i * max_n + j] = s;
+  }
+}
+
+// (3) D -= C^T W on 64x64 tiles outside the panel rows and columns (MFMA f64)
+__global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ pstart,
+                                                   const int32_t* __restrict__ pwidth,
+                                                   const int64_t* __restrict__ aofs,
+                                                   const int32_t* __restrict__ lda,
+                                                   const int32_t* __restrict__ nn,
+                                                   double* __restrict__ A,
+                                                   const double* __restrict__ wrow, int nmat,
+                                                   int step, int nb, int max_n) {
+  const int m = blockIdx.z;
+  const int kw = pwidth[step * nmat + m];
+  if (kw == 0) return;
+  const int n = nn[m];
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  if (i0 >= n || j0 >= n) return;
+  const int k0 = pstart[step * nmat + m];
+  // tiles fully inside the panel rows or columns have nothing to update
+  if ((i0 >= k0 && i0 + 64 <= k0 + kw) || (j0 >= k0 && j0 + 64 <= k0 + kw)) return;
+  double* Am = A + aofs[m];
+  const int ld = lda[m];
+  const double* W = wrow + (int64_t)m * nb * max_n;
+  __shared__ double Ct[GJ_NB][64];  // C[k][i0 + i]
+  __shared__ double Wt[GJ_NB][64];  // W[k][j0 + j]
+  const int kp = (kw + 3) & ~3;     // padded to the MFMA depth
+  for (int t = threadIdx.x; t < kp * 64; t += blockDim.x) {
+    const int k = t / 64, x = t % 64;
+    const bool kin = k < kw;
+    const int i = i0 + x, j = j0 + x;
+    Ct[k][x] = (kin && i < n) ? Am[(int64_t)(k0 + k) * ld + i] : 0.0;
+    Wt[k][x] = (kin && j < n && !(j >= k0 && j < k0 + kw)) ? W[(int64_t)k * max_n + j] : 0.0;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int lr = lane % 16, lk = lane / 16;
+  for (int k = 0; k < kp; k += 4) {
+    double av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = Ct[k + lk][wi + a * 16 + lr];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bv[b] = Wt[k + lk][wj + b * 16 + lr];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+  }
+  // D layout (v_mfma_f64_16x16x4 on gfx950, checked by a lane probe): register r
+  // of a lane holds row (lane / 16) + 4 r, column lane % 16
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wi + a * 16 + (lane / 16) + 4 * r;
+        const int j = j0 + wj + b * 16 + (lane % 16);
+        if (i >= n || j >= n) continue;
+        if ((i >= k0 && i < k0 + kw) || (j >= k0 && j < k0 + kw)) continue;
+        Am[(int64_t)i * ld + j] -= acc[a][b][r];
+      }
+}
+
+// (4) write the swept panel: rows W, columns W^T, pivot block -P^{-1}; and
+// copy the trailing block at a snapshot step
+__global__ void __launch_bounds__(256) k_gj_write(const int32_t* __restrict__ pstart,
+                                                  const int32_t* __restrict__ pwidth,
+                                                  const int64_t* __restrict__ aofs,
+                                                  const int32_t* __restrict__ lda,
+                                                  const int32_t* __restrict__ nn,
+                                                  double* __restrict__ A,
+                                                  const double* __restrict__ pinv,
+                                                  const double* __restrict__ wrow, int nmat,
+                                                  int step, int nb, int max_n) {
+  const int m = blockIdx.y;
+  const int kw = pwidth[step * nmat + m];
+  if (kw == 0) return;
+  const int k0 = pstart[step * nmat + m];
+  const int n = nn[m];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double* Am = A + aofs[m];
+  const int ld = lda[m];
+  const double* W = wrow + (int64_t)m * nb * max_n;
+  const double* Pm = pinv + (int64_t)m * nb * nb;
+  if (j >= k0 && j < k0 + kw) {
+    for (int i = 0; i < kw; ++i) Am[(int64_t)(k0 + i) * ld + j] = -Pm[i * nb + (j - k0)];
+  } else {
+    for (int i = 0; i < kw; ++i) {
+      const double v = W[(int64_t)i * max_n + j];
+      Am[(int64_t)(k0 + i) * ld + j] = v;
+      Am[(int64_t)j * ld + k0 + i] = v;
+    }
+  }
+}
+
+__global__ void k_gj_snapshot(const int32_t* __restrict__ pflag, const int64_t* __restrict__ aofs,
+                              const int32_t* __restrict__ lda, const int32_t* __restrict__ nn,
+                              const int64_t* __restrict__ snap_ofs,
+                              const int32_t* __restrict__ snap_at,
+                              const int32_t* __restrict__ snap_ld, const double* __restrict__ A,
+                              double* __restrict__ snap, int nmat, int step) {
+  const int m = blockIdx.y;
+  if (!(pflag[step * nmat + m] & 1) || snap_ofs[m] < 0) return;
+  const int n = nn[m], at = snap_at[m], nbm = n - at;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nbm * nbm) return;
+  const int i = (int)(t / nbm), j = (int)(t % nbm);
+  snap[snap_ofs[m] + (int64_t)i * snap_ld[m] + j] = A[aofs[m] + (int64_t)(at + i) * lda[m] + at + j];
+}
+
+// K^+ = -(swept block), zero on the rows and columns that were not swept
+__global__ void k_gj_finalize(const int64_t* __restrict__ aofs, const int32_t* __restrict__ lda,
+                              const int32_t* __restrict__ nn, const int32_t* __restrict__ nswept,
+                              double* __restrict__ A, int max_n) {
+  const int m = blockIdx.z;
+  const int n = nn[m], ns = nswept[m];
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || j >= n) return;
+  double* a = A + aofs[m] + (int64_t)i * lda[m] + j;
+  *a = (i < ns && j < ns) ? -*a : 0.0;
+}
+
+void launch_gj_step(const GJPlan& p, double* A, double* snap, int step, bool snap_now,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_gj_pivot, dim3(p.nmat), dim3(256), 0, st, p.pstart, p.pwidth, p.aofs, p.lda,
+                     A, p.pinv, p.status, p.nmat, step, p.nb);
+  hipLaunchKernelGGL(k_gj_row, dim3((p.max_n + 255) / 256, p.nmat), dim3(256), 0, st, p.pstart,
+                     p.pwidth, p.aofs, p.lda, p.n, A, p.pinv, p.wrow, p.nmat, step, p.nb, p.max_n);
+  const int nt = (p.max_n + 63) / 64;
+  hipLaunchKernelGGL(k_gj_update, dim3(nt, nt, p.nmat), dim3(256), 0, st, p.pstart, p.pwidth,
+                     p.aofs, p.lda, p.n, A, p.wrow, p.nmat, step, p.nb, p.max_n);
+  hipLaunchKernelGGL(k_gj_write, dim3((p.max_n + 255) / 256, p.nmat), dim3(256), 0, st, p.pstart,
+                     p.pwidth, p.aofs, p.lda, p.n, A, p.pinv, p.wrow, p.nmat, step, p.nb, p.max_n);
+  if (snap != nullptr && snap_now) {
+    const int64_t cnt = (int64_t)p.max_n * p.max_n;
+    hipLaunchKernelGGL(k_gj_snapshot, dim3((unsigned)((cnt + 255) / 256), p.nmat), dim3(256), 0, st,
+                       p.pflag, p.aofs, p.lda, p.n, p.snap_ofs, p.snap_at, p.snap_ld, A, snap,
+                       p.nmat, step);
+  }
+}
+
+void launch_gj_finalize(const GJPlan& p, double* A, const int32_t* nswept, hipStream_t st) {
+  hipLaunchKernelGGL(k_gj_finalize, dim3((p.max_n + 255) / 256, p.max_n, p.nmat), dim3(256), 0, st,
+                     p.aofs, p.lda, p.n, nswept, A, p.max_n);
+}
+
+}  // namespace feti

@@ -1,0 +1,533 @@
+// Interface kernels of the FETI iteration: batched symmetric GEMVs with the
+// local inverses and Schur complements, the signed Boolean gather/scatter
+// (B_s^T and sum_s B_s), the (B B^T)^{-1}-weighted gather/scatter of the
+// Dirichlet preconditioner, the coarse space G = [B_s R_s], and the FP64
+// vector updates and deterministic reductions of projected PCG.
+#include "kernels.h"
+#include "iface.h"
+
+namespace feti {
+
+// Multiplier-space value gathered onto interface DOF gb.
+__device__ inline double gather_b(const DevMesh& m, const double* __restrict__ v, int64_t gb,
+                                  int mode) {
+  if (mode == G_SIGNED) {
+    double s = 0.0;
+    const int r0 = m.bg_row[2 * gb], r1 = m.bg_row[2 * gb + 1];
+    if (r0 >= 0) s += m.bg_sign[2 * gb] * v[r0];
+    if (r1 >= 0) s += m.bg_sign[2 * gb + 1] * v[r1];
+    return s;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int r = m.bd_row[3 * gb + k];
+    if (r >= 0) s += m.bd_wt[3 * gb + k] * v[r];
+  }
+  return s;
+}
+
+// y_s = A_s x_s for every subdomain s.  A_s is symmetric, so column k of the
+// row-major block is read as row k: for a fixed k the 64 lanes of a wavefront
+// read 64 consecutive entries.  Each workgroup owns 64 output rows; its four
+// wavefronts split the k range and combine in LDS.  x_s is built in LDS.
+__global__ void __launch_bounds__(256) k_sgemv(DevMesh m, GemvArgs a) {
+  if (a.skip && *a.skip) return;
+  const int s = blockIdx.y;
+  const int ns = m.ns[s], nbs = m.nb[s];
+  const int n = a.which_n == 0 ? ns : nbs;
+  const int row0 = blockIdx.x * 64;
+  if (row0 >= n) return;
+  extern __shared__ double smem[];
+  double* xs = smem;              // n
+  double* red = smem + m.max_ns;  // 4 x 64
+  const int first_b = n - nbs;
+  const int64_t xoff = a.which_n == 0 ? m.soff[s] : m.boff[s];
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    double v = a.xbase ? a.xbase[xoff + t] : 0.0;
+    if (a.gmode != G_NONE && t >= first_b) v += a.gcoef * gather_b(m, a.v, m.boff[s] + (t - first_b), a.gmode);
+    xs[t] = v;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = row0 + lane;
+  const int kq = (n + 3) / 4;
+  const int kb = wave * kq, ke = min(n, kb + kq);
+  const double* A = a.A + a.aofs[s];
+  const int64_t ld = a.lda[s];
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  if (i < n) {
+    int k = kb;
+    for (; k + 4 <= ke; k += 4) {
+      acc0 += A[(int64_t)(k + 0) * ld + i] * xs[k + 0];
+      acc1 += A[(int64_t)(k + 1) * ld + i] * xs[k + 1];
+      acc2 += A[(int64_t)(k + 2) * ld + i] * xs[k + 2];
+      acc3 += A[(int64_t)(k + 3) * ld + i] * xs[k + 3];
+    }
+    for (; k < ke; ++k) acc0 += A[(int64_t)k * ld + i] * xs[k];
+  }
+  red[wave * 64 + lane] = (acc0 + acc1) + (acc2 + acc3);
+  __syncthreads();
+  if (wave == 0 && i < n) {
+    double yv = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+    if (a.alpha_c) {
+      const int f = m.sub_float[s];
+      if (f >= 0) {
+        const double* R = m.rfull + 3 * (m.soff[s] + i);
+        yv += R[0] * a.alpha_c[3 * f] + R[1] * a.alpha_c[3 * f + 1] + R[2] * a.alpha_c[3 * f + 2];
+      }
+    }
+    a.y[xoff + i] = yv;
+  }
+}
+
+// out_j = sum over the two entries of row j of sign * y_b (signed jump), or the
+// (B B^T)^{-1}-weighted jump over the row's group when scaled.
+__global__ void k_jump(DevMesh m, const double* __restrict__ yb, int from_torn,
+                       double* __restrict__ out, int scaled, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m.n_lambda) return;
+  auto jump = [&](int64_t r) {
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int64_t gb = m.jr_b[2 * r + e];
+      const int64_t idx = from_torn ? (int64_t)m.b_torn[gb] : gb;
+      s += m.jr_sign[2 * r + e] * yb[idx];
+    }
+    return s;
+  };
+  if (!scaled) {
+    out[j] = jump(j);
+    return;
+  }
+  const int gs = m.grp_start[j], gz = m.grp_size[j];
+  double s = 0.0;
+  for (int k = 0; k < gz; ++k) s += m.dwt[3 * j + k] * jump(gs + k);
+  out[j] = s;
+}
+
+// g_f = R_s^T x_s for each floating subdomain s = float_sub[f], with
+// x_s = base_s + gsign * B_s^T v (base torn and/or v multipliers).
+__global__ void __launch_bounds__(256) k_coarse_g(DevMesh m, const double* __restrict__ v,
+                                                  const double* __restrict__ base, double gsign,
+                                                  double* __restrict__ g,
+                                                  const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int f = blockIdx.x;
+  const int s = m.float_sub[f];
+  const int ns = m.ns[s], nbs = m.nb[s], first_b = ns - nbs;
+  const int64_t so = m.soff[s];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    double x = base ? base[so + i] : 0.0;
+    if (v && i >= first_b) x += gsign * gather_b(m, v, m.boff[s] + (i - first_b), G_SIGNED);
+    const double* R = m.rfull + 3 * (so + i);
+    acc[0] += R[0] * x;
+    acc[1] += R[1] * x;
+    acc[2] += R[2] * x;
+  }
+  __shared__ double red[3][256];
+  for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) g[3 * f + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// a = scale * Cinv g (Cinv symmetric n_c x n_c)
+__global__ void k_coarse_apply(int nc, const double* __restrict__ C, const double* __restrict__ g,
+                               double* __restrict__ a, double scale, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  double s = 0.0;
+  for (int k = 0; k < nc; ++k) s += C[(int64_t)k * nc + i] * g[k];
+  a[i] = scale * s;
+}
+
+// v_j = vin_j + scale * (G a)_j, (G a)_j = sum_e sign_e R_b(gb_e) . a_{float(sub(gb_e))}
+__global__ void k_coarse_correct(DevMesh m, const double* __restrict__ a, double scale,
+                                 const double* __restrict__ vin, double* __restrict__ v,
+                                 const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m.n_lambda) return;
+  double s = 0.0;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int64_t gb = m.jr_b[2 * j + e];
+    const int f = m.sub_float[m.b_sub[gb]];
+    if (f < 0) continue;
+    const double* R = m.rb + 3 * gb;
+    s += m.jr_sign[2 * j + e] * (R[0] * a[3 * f] + R[1] * a[3 * f + 1] + R[2] * a[3 * f + 2]);
+  }
+  v[j] = (vin ? vin[j] : 0.0) + scale * s;
+}
+
+// G^T G, one thread per entry (r, c): sum over the jump rows of subdomain float_sub[r/3]
+__global__ void k_gtg(DevMesh m, double* __restrict__ C, int nc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nc * nc) return;
+  const int r = (int)(t / nc), c = (int)(t % nc);
+  const int s = m.float_sub[r / 3], ca = r % 3;
+  const int st = m.float_sub[c / 3], cb = c % 3;
+  const int nbs = m.nb[s];
+  const int64_t b0 = m.boff[s];
+  double acc = 0.0;
+  for (int bl = 0; bl < nbs; ++bl) {
+    const int64_t gb = b0 + bl;
+    for (int slot = 0; slot < 2; ++slot) {
+      const int j = m.bg_row[2 * gb + slot];
+      if (j < 0) continue;
+      const double gs = m.bg_sign[2 * gb + slot] * m.rb[3 * gb + ca];
+      for (int e = 0; e < 2; ++e) {
+        const int64_t gb2 = m.jr_b[2 * (int64_t)j + e];
+        if (m.b_sub[gb2] != st) continue;
+        acc += gs * m.jr_sign[2 * (int64_t)j + e] * m.rb[3 * gb2 + cb];
+      }
+    }
+  }
+  C[t] = acc;
+}
+
+// ---- PCG vector kernels with deterministic two-level reductions ---------------
+
+// Per-block partial sums: slot 0: (x, y); slots 2..7: per-kind |nrm|^2; slots
+// 8..13: per-kind sum_j |mdiag_j| nrm_j^2.  Any pointer may be null.
+__global__ void __launch_bounds__(RED_BLOCK) k_partials(DevMesh m, const double* __restrict__ x,
+                                                        const double* __restrict__ y,
+                                                        const double* __restrict__ nrm,
+                                                        const double* __restrict__ mdiag,
+                                                        double* __restrict__ part,
+                                                        const int32_t* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double red[NPART][RED_BLOCK];
+  double acc[NPART];
+#pragma unroll
+  for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
+  const int64_t n = m.n_lambda;
+  const int64_t stride = (int64_t)gridDim.x * RED_BLOCK;
+  for (int64_t j = (int64_t)blockIdx.x * RED_BLOCK + threadIdx.x; j < n; j += stride) {
+    if (x) acc[0] += x[j] * y[j];
+    if (nrm) {
+      const double v2 = nrm[j] * nrm[j];
+      const int k = m.row_kind[j];
+      acc[2 + k] += v2;
+      acc[8 + k] += fabs(mdiag[j]) * v2;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int w = RED_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < NPART) part[blockIdx.x * NPART + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Relative residual of the iteration: the largest of the dual-energy ratio
+// |w|_M / ref_M and the per-kind ratios |w_k| / ref_k over the kinds whose
+// reference energy is not negligible (a kind without load data, whose jump
+// only carries rounding, is judged by the energy ratio alone).
+__device__ inline double rel_residual(const double* v, const double* sc) {
+  double etot = 0.0, eref = 0.0;
+  for (int k = 0; k < 6; ++k) {
+    etot += v[8 + k];
+    eref += sc[SC_EK + k];
+  }
+  const double den = sc[SC_EREF];
+  double rel = den > 0.0 ? sqrt(etot) / den : (etot > 0.0 ? 1.0 : 0.0);
+  for (int k = 0; k < 6; ++k) {
+    if (!(sc[SC_EK + k] > 1e-24 * eref)) continue;
+    const double nk = sqrt(v[2 + k]);
+    const double rk = sc[SC_REF + k] > 0.0 ? nk / sc[SC_REF + k] : 0.0;
+    rel = fmax(rel, rk);
+  }
+  return rel;
+}
+
+// M_jj = sum over the interface DOFs b of row j's group of (B^T D)[b, j]^2 S_bb[b, b]
+__global__ void k_precond_diag(DevMesh m, const double* __restrict__ S, double* __restrict__ md) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m.n_lambda) return;
+  const int gs = m.grp_start[j], gz = m.grp_size[j];
+  const int slot = (int)(j - gs);
+  double acc = 0.0;
+  for (int k = 0; k < gz; ++k) {
+    const int64_t r = gs + k;
+    for (int e = 0; e < 2; ++e) {
+      if (e == 1 && k + 1 < gz) continue;  // shared with the next row of the chain
+      const int64_t gb = m.jr_b[2 * r + e];
+      const int s = m.b_sub[gb];
+      const int bl = (int)(gb - m.boff[s]);
+      const double wgt = m.bd_wt[3 * gb + slot];
+      acc += wgt * wgt * S[m.sofs[s] + (int64_t)bl * m.ldb[s] + bl];
+    }
+  }
+  md[j] = acc;
+}
+
+// Sums the partials in a fixed order and runs the scalar part of one PCG phase.
+__global__ void k_scalar(const double* __restrict__ part, int nblk, double* __restrict__ sc,
+                         int32_t* __restrict__ ist, int phase) {
+  if (ist[IS_DONE] && phase != PH_INIT && phase != PH_REFNORM) return;
+  __shared__ double red[NPART][64];
+  const int t = threadIdx.x;
+  double acc[NPART];
+  for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
+  for (int b = t; b < nblk; b += 64)
+    for (int c = 0; c < NPART; ++c) acc[c] += part[b * NPART + c];
+  for (int c = 0; c < NPART; ++c) red[c][t] = acc[c];
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
+    if (t < w)
+      for (int c = 0; c < NPART; ++c) red[c][t] += red[c][t + w];
+    __syncthreads();
+  }
+  if (t != 0) return;
+  double v[NPART];
+  for (int c = 0; c < NPART; ++c) v[c] = red[c][0];
+  switch (phase) {
+    case PH_REFNORM: {
+      // references from P d: per-kind norms and energies, total energy norm
+      double e = 0.0;
+      for (int k = 0; k < 6; ++k) {
+        sc[SC_REF + k] = sqrt(v[2 + k]);
+        sc[SC_EK + k] = v[8 + k];
+        e += v[8 + k];
+      }
+      sc[SC_EREF] = sqrt(e);
+      break;
+    }
+    case PH_INIT: {
+      // rho = (w, y); the reference of each kind also covers its initial residual
+      sc[SC_RHO] = v[0];
+      double e = 0.0;
+      for (int k = 0; k < 6; ++k) {
+        sc[SC_REF + k] = fmax(sc[SC_REF + k], sqrt(v[2 + k]));
+        sc[SC_EK + k] = fmax(sc[SC_EK + k], v[8 + k]);
+        e += v[8 + k];
+      }
+      sc[SC_EREF] = fmax(sc[SC_EREF], sqrt(e));
+      const double rel = rel_residual(v, sc);
+      sc[SC_RES0] = rel;
+      sc[SC_RES] = rel;
+      ist[IS_ITERS] = 0;
+      ist[IS_STATUS] = 0;
+      ist[IS_DONE] = (rel <= sc[SC_TOL]) ? 1 : 0;
+      if (!isfinite(v[0]) || !isfinite(rel)) { ist[IS_STATUS] = FETI_ENAN; ist[IS_DONE] = 1; }
+      break;
+    }
+    case PH_ALPHA: {
+      const double pq = v[0];
+      if (!(fabs(pq) > 1e-300) || !isfinite(pq)) {
+        ist[IS_STATUS] = isfinite(pq) ? FETI_EBREAKDOWN : FETI_ENAN;
+        ist[IS_DONE] = 1;
+        sc[SC_ALPHA] = 0.0;
+        break;
+      }
+      sc[SC_ALPHA] = sc[SC_RHO] / pq;
+      break;
+    }
+    case PH_CONV: {
+      const double rel = rel_residual(v, sc);
+      sc[SC_RES] = rel;
+      ist[IS_ITERS] += 1;
+      if (!isfinite(rel)) { ist[IS_STATUS] = FETI_ENAN; ist[IS_DONE] = 1; }
+      else if (rel <= sc[SC_TOL]) ist[IS_DONE] = 1;
+      else if (ist[IS_ITERS] >= ist[IS_MAXIT]) { ist[IS_STATUS] = FETI_ENOTCONV; ist[IS_DONE] = 1; }
+      break;
+    }
+    case PH_BETA: {
+      const double rho_new = v[0];
+      if (!(fabs(sc[SC_RHO]) > 1e-300)) {
+        ist[IS_STATUS] = FETI_EBREAKDOWN;
+        ist[IS_DONE] = 1;
+        break;
+      }
+      sc[SC_BETA] = rho_new / sc[SC_RHO];
+      sc[SC_RHO] = rho_new;
+      break;
+    }
+  }
+}
+
+// lam += alpha p; r -= alpha q_raw; w -= alpha q
+__global__ void k_cg_lam(int64_t n, const double* __restrict__ sc, const int32_t* __restrict__ ist,
+                         const double* __restrict__ p, const double* __restrict__ qraw,
+                         const double* __restrict__ q, double* __restrict__ lam,
+                         double* __restrict__ r, double* __restrict__ w) {
+  if (ist[IS_DONE]) return;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double al = sc[SC_ALPHA];
+  lam[j] += al * p[j];
+  r[j] -= al * qraw[j];
+  w[j] -= al * q[j];
+}
+
+// p = y + beta p
+__global__ void k_cg_p(int64_t n, const double* __restrict__ sc, const int32_t* __restrict__ ist,
+                       const double* __restrict__ y, double* __restrict__ p) {
+  if (ist[IS_DONE]) return;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  p[j] = y[j] + sc[SC_BETA] * p[j];
+}
+
+// z = a x + b y (plain vector combination)
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
+                        const double* __restrict__ y, double* __restrict__ z) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  z[j] = a * x[j] + (y ? b * y[j] : 0.0);
+}
+
+// copy a dense block (rows x cols) between leading dimensions, batched
+__global__ void k_copy_block(const int64_t* __restrict__ src_ofs, const int32_t* __restrict__ src_ld,
+                             const int32_t* __restrict__ src_at, const int64_t* __restrict__ dst_ofs,
+                             const int32_t* __restrict__ dst_ld, const int32_t* __restrict__ cnt,
+                             const double* __restrict__ src, double* __restrict__ dst) {
+  const int s = blockIdx.y;
+  const int nbs = cnt[s], at = src_at[s];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nbs * nbs) return;
+  const int i = (int)(t / nbs), j = (int)(t % nbs);
+  dst[dst_ofs[s] + (int64_t)i * dst_ld[s] + j] = src[src_ofs[s] + (int64_t)(at + i) * src_ld[s] + at + j];
+}
+
+// r_b -= B_s^T lam on every interface DOF (torn vector r)
+__global__ void k_sub_gather(DevMesh m, const double* __restrict__ lam, double* __restrict__ r) {
+  const int64_t gb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gb >= m.sum_nb) return;
+  r[m.b_torn[gb]] -= gather_b(m, lam, gb, G_SIGNED);
+}
+
+// per-block, per-kind max |x| and max |y| over a torn vector (kinds from the DOF codes)
+__global__ void __launch_bounds__(256) k_kind_maxabs(DevMesh m, const double* __restrict__ x,
+                                                     const double* __restrict__ y,
+                                                     double* __restrict__ part) {
+  __shared__ double red[12][256];
+  double acc[12];
+  for (int c = 0; c < 12; ++c) acc[c] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m.sum_ns; i += stride) {
+    const int k = m.code[i] & 7;
+    acc[k] = fmax(acc[k], fabs(x[i]));
+    acc[6 + k] = fmax(acc[6 + k], fabs(y[i]));
+  }
+  for (int c = 0; c < 12; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 12; ++c) red[c][threadIdx.x] = fmax(red[c][threadIdx.x], red[c][threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 12) part[blockIdx.x * 12 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ---- launchers ---------------------------------------------------------------
+
+void launch_sub_gather(const DevMesh& m, const double* lam, double* r, hipStream_t st) {
+  const int blk = 256;
+  hipLaunchKernelGGL(k_sub_gather, dim3((unsigned)((m.sum_nb + blk - 1) / blk)), dim3(blk), 0, st, m,
+                     lam, r);
+}
+
+void launch_kind_maxabs(const DevMesh& m, const double* x, const double* y, double* part, int nblk,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_kind_maxabs, dim3(nblk), dim3(256), 0, st, m, x, y, part);
+}
+
+void launch_sgemv(const DevMesh& m, const GemvArgs& a, hipStream_t st) {
+  const int maxn = a.which_n == 0 ? m.max_ns : m.max_nb;
+  const size_t shm = sizeof(double) * ((size_t)m.max_ns + 4 * 64);
+  hipLaunchKernelGGL(k_sgemv, dim3((maxn + 63) / 64, m.nsub), dim3(256), shm, st, m, a);
+}
+
+void launch_jump(const DevMesh& m, const double* yb, int from_torn, double* out, int scaled,
+                 const int32_t* skip, hipStream_t st) {
+  const int blk = 256;
+  hipLaunchKernelGGL(k_jump, dim3((unsigned)((m.n_lambda + blk - 1) / blk)), dim3(blk), 0, st, m, yb,
+                     from_torn, out, scaled, skip);
+}
+
+void launch_coarse_g(const DevMesh& m, const double* v, const double* base, double gsign, double* g,
+                     const int32_t* skip, hipStream_t st) {
+  if (m.n_float == 0) return;
+  hipLaunchKernelGGL(k_coarse_g, dim3(m.n_float), dim3(256), 0, st, m, v, base, gsign, g, skip);
+}
+
+void launch_coarse_apply(int nc, const double* Cinv, const double* g, double* a, double scale,
+                         const int32_t* skip, hipStream_t st) {
+  if (nc == 0) return;
+  hipLaunchKernelGGL(k_coarse_apply, dim3((nc + 127) / 128), dim3(128), 0, st, nc, Cinv, g, a, scale,
+                     skip);
+}
+
+void launch_coarse_correct(const DevMesh& m, const double* a, double scale, const double* vin,
+                           double* v, const int32_t* skip, hipStream_t st) {
+  const int blk = 256;
+  hipLaunchKernelGGL(k_coarse_correct, dim3((unsigned)((m.n_lambda + blk - 1) / blk)), dim3(blk), 0,
+                     st, m, a, scale, vin, v, skip);
+}
+
+void launch_gtg(const DevMesh& m, double* C, int nc, hipStream_t st) {
+  if (nc == 0) return;
+  const int64_t cnt = (int64_t)nc * nc;
+  hipLaunchKernelGGL(k_gtg, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, m, C, nc);
+}
+
+void launch_partials(const DevMesh& m, const double* x, const double* y, const double* nrm,
+                     const double* mdiag, double* part, int nblk, const int32_t* done,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_partials, dim3(nblk), dim3(RED_BLOCK), 0, st, m, x, y, nrm, mdiag, part, done);
+}
+
+void launch_precond_diag(const DevMesh& m, const double* S, double* mdiag, hipStream_t st) {
+  const int blk = 256;
+  hipLaunchKernelGGL(k_precond_diag, dim3((unsigned)((m.n_lambda + blk - 1) / blk)), dim3(blk), 0, st,
+                     m, S, mdiag);
+}
+
+void launch_scalar(const double* part, int nblk, double* sc, int32_t* ist, int phase,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(64), 0, st, part, nblk, sc, ist, phase);
+}
+
+void launch_cg_lam(int64_t n, const double* sc, const int32_t* ist, const double* p,
+                   const double* qraw, const double* q, double* lam, double* r, double* w,
+                   hipStream_t st) {
+  const int blk = 256;
+  hipLaunchKernelGGL(k_cg_lam, dim3((unsigned)((n + blk - 1) / blk)), dim3(blk), 0, st, n, sc, ist, p,
+                     qraw, q, lam, r, w);
+}
+
+void launch_cg_p(int64_t n, const double* sc, const int32_t* ist, const double* y, double* p,
+                 hipStream_t st) {
+  const int blk = 256;
+  hipLaunchKernelGGL(k_cg_p, dim3((unsigned)((n + blk - 1) / blk)), dim3(blk), 0, st, n, sc, ist, y, p);
+}
+
+void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* z,
+                  hipStream_t st) {
+  const int blk = 256;
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + blk - 1) / blk)), dim3(blk), 0, st, n, a, x, b, y, z);
+}
+
+void launch_copy_block(int nsub, int maxn, const int64_t* src_ofs, const int32_t* src_ld,
+                       const int32_t* src_at, const int64_t* dst_ofs, const int32_t* dst_ld,
+                       const int32_t* cnt, const double* src, double* dst, hipStream_t st) {
+  const int64_t c = (int64_t)maxn * maxn;
+  hipLaunchKernelGGL(k_copy_block, dim3((unsigned)((c + 255) / 256), nsub), dim3(256), 0, st, src_ofs,
+                     src_ld, src_at, dst_ofs, dst_ld, cnt, src, dst);
+}
+
+}  // namespace feti

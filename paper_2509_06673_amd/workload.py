@@ -1,0 +1,59 @@
+"""Marshalling of a synthetic workload description into the C ABI structs."""
+from __future__ import annotations
+
+from typing import Dict, List
+
+from . import _binding as B
+
+_LAYOUT = {"xsplit": B.XSPLIT, "ysplit": B.YSPLIT, "core": B.CORE}
+_LOAD = {"manufactured": B.LOAD_MANUFACTURED, "periodic": B.LOAD_PERIODIC,
+         "point_source": B.LOAD_POINT_SOURCE, "patch": B.LOAD_PATCH}
+
+
+def mesh_args(w) -> Dict:
+    return dict(ncell=w.ncell, order_u=w.order_u, layout=_LAYOUT[w.layout], nsub_x=w.nsub_x,
+                nsub_y=w.nsub_y, dirichlet_u=w.dirichlet_u, dirichlet_p=w.dirichlet_p)
+
+
+def material(m) -> B.Material:
+    return B.Material(m.E, m.nu, m.alpha, m.c0, m.K, m.mu_f, m.lame_mode)
+
+
+def load(w, t: float) -> B.Load:
+    from workloads import PATCH_UX, PATCH_UY, PATCH_P
+    L = B.Load()
+    L.kind = _LOAD[w.load.kind]
+    L.t = t
+    prm: List[float] = [0.0] * 16
+    if w.load.kind == "patch":
+        nq = 6 if w.order_u == 2 else 3
+        ux = list(PATCH_UX[:nq]) + [0.0] * (6 - nq)
+        uy = list(PATCH_UY[:nq]) + [0.0] * (6 - nq)
+        pp = [PATCH_P[0], PATCH_P[1] if w.order_u == 2 else 0.0]
+        prm[:14] = ux + uy + pp
+    elif w.load.kind == "periodic":
+        prm[:3] = [w.load.amp, w.load.omega, w.load.phase]
+    elif w.load.kind == "point_source":
+        prm[:3] = [w.load.cx, w.load.cy, w.load.sigma]
+    for i, v in enumerate(prm):
+        L.params[i] = v
+    return L
+
+
+def opts(tol: float = 1e-10, max_it: int = 1000, start: int = B.START_PREVIOUS,
+         check_every: int = 8, ir_max: int = 0, ir_cold: int = 4, tol_corr: float = 1e-3,
+         ir_tol: float = 1e-9) -> B.SolveOpts:
+    """Solve options.  By default a step that starts without previous multipliers is
+    refined in FP64 until a correction changes no field by more than ir_tol
+    (relative, at most ir_cold corrections); warm-started steps get ir_max."""
+    return B.SolveOpts(tol, tol_corr, ir_tol, max_it, start, check_every, ir_max, ir_cold)
+
+
+def setup(w, stream=None, precision=B.FP64, precond=B.PRECOND_DIRICHLET) -> B.Feti:
+    """Create a context and run setup_mesh, assemble, factor_subdomains, init_state."""
+    f = B.Feti(stream)
+    f.setup_mesh(**mesh_args(w))
+    f.assemble(material(w.mat_p), material(w.mat_e), w.tau)
+    f.factor_subdomains(precision, precond)
+    f.init_state(load(w, 0.0))
+    return f

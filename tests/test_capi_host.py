@@ -1,0 +1,112 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* the shared library loads and exports every function include/feti.h declares;
+* the numbering built by the library's host code equals, bit for bit, the
+  independent statement in oracle/indexing.py (local DOF codes and order,
+  interface sizes, the two entries and signs of every jump row);
+* out-of-order calls and invalid descriptions return the documented codes.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import indexing as ix
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+P = pytest.importorskip("paper_2509_06673_amd")
+from paper_2509_06673_amd import _binding as B  # noqa: E402
+from paper_2509_06673_amd.workload import mesh_args  # noqa: E402
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "feti.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(feti_[a-z_A-Z0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load_library()
+    names = _declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _compare(w):
+    f = B.Feti()
+    f.setup_mesh(**mesh_args(w))
+    got = f.export_indexing()
+    spec = ix.build(w)
+    codes = np.concatenate([np.array(s.codes, dtype=np.int64) for s in spec.subs])
+    assert np.array_equal(got["code"].astype(np.int64), codes)
+    offs = np.concatenate([[0], np.cumsum([len(s.codes) for s in spec.subs])])
+    assert np.array_equal(got["sub_offset"], offs)
+    nb = np.array([sum(1 for c in s.cats if c >= 2) for s in spec.subs])
+    assert np.array_equal(got["sub_nb"], nb)
+    rows = spec.rows.reshape(-1, 3)
+    assert np.array_equal(got["brow_sub"], rows[:, 0])
+    assert np.array_equal(got["brow_local"], rows[:, 1])
+    assert np.array_equal(got["brow_sign"].astype(np.int64), rows[:, 2])
+    # interface DOFs are the trailing ones of each subdomain
+    for s, n_b in zip(spec.subs, nb):
+        assert all(c >= 2 for c in s.cats[len(s.cats) - n_b:])
+    sz = f.get_sizes()
+    assert sz["n_lambda"] == spec.n_lambda
+    assert sz["n_float"] == sum(s.floating for s in spec.subs)
+    f.close()
+
+
+@pytest.mark.parametrize("w", [
+    W.plain_fp64_small(),
+    W.nearly_incompressible_scaled(16, 4),
+    W.nearly_incompressible_scaled(24, 4).replace(nsub_y=3),
+    W.patch_case(order_u=1, ncell=8, nsub_x=4, nsub_y=3),
+    W.paper_table_case(2, 8, 0.3, nsteps=1),
+    W.pulsed_core(ncell=16, nsub=4, nsteps=1),
+    W.learned_start_case(1, nsteps=1),
+], ids=lambda w: w.name)
+def test_indexing_bit_exact_against_oracle(w):
+    _compare(w)
+
+
+def test_uneven_cuts_bit_exact():
+    # ncell not divisible by the grid: cuts at floor(a n / nsub)
+    w = W.nearly_incompressible_scaled(20, 4).replace(nsub_y=3, ncell=20)
+    _compare(w)
+
+
+def test_full_size_counts():
+    f = B.Feti()
+    f.setup_mesh(**mesh_args(W.nearly_incompressible_large()))
+    sz = f.get_sizes()
+    assert sz["n_lambda"] == 10677 and sz["max_ns"] == 3045 and sz["max_nb"] == 448
+    assert sz["n_float"] == 36 and sz["n_c"] == 108
+
+
+def test_call_order_and_invalid_input():
+    f = B.Feti()
+    with pytest.raises(B.FetiError) as e:
+        f.assemble(B.Material(1, 0.3, 1, 1, 1, 1, 0), B.Material(1, 0.3, 1, 1, 1, 1, 0), 0.1)
+    assert e.value.code == B.ESTATE
+    with pytest.raises(B.FetiError) as e:
+        f.setup_mesh(ncell=8, order_u=3, layout=0, nsub_x=2, nsub_y=1)
+    assert e.value.code == B.EINVAL
+    with pytest.raises(B.FetiError) as e:
+        # a subdomain straddling x = 1/2
+        f.setup_mesh(ncell=8, order_u=2, layout=0, nsub_x=3, nsub_y=1)
+    assert e.value.code == B.EINVAL
+    f.setup_mesh(ncell=8, order_u=2, layout=0, nsub_x=2, nsub_y=2)
+    with pytest.raises(B.FetiError) as e:
+        f.setup_mesh(ncell=8, order_u=2, layout=0, nsub_x=2, nsub_y=2)
+    assert e.value.code == B.ESTATE
+    with pytest.raises(B.FetiError) as e:
+        f.factor_subdomains()
+    assert e.value.code == B.ESTATE
+    # nu >= 1/2 is rejected before any device work
+    with pytest.raises(B.FetiError) as e:
+        f.assemble(B.Material(1, 0.5, 1, 1, 1, 1, 0), B.Material(1, 0.3, 1, 1, 1, 1, 0), 0.1)
+    assert e.value.code == B.EINVAL
