@@ -91,6 +91,8 @@ def main():
     t2 = time.perf_counter()
     f.init_state(load(w, 0.0))
     o = opts(tol=w.tol, max_it=2000, start=B.START_PREVIOUS, check_every=args.check_every)
+    iters_first = []
+    ir_steps = []
     n = 0
     iters = []
     for _ in range(args.warmup):
@@ -105,6 +107,8 @@ def main():
         n += 1
         st = f.step(load(w, n * w.tau), o)
         iters.append(st["iters"])
+        iters_first.append(st["iters_first"])
+        ir_steps.append(st["ir_steps"])
     ev1.record(stream)
     torch.cuda.synchronize()
     tb = time.perf_counter()
@@ -151,6 +155,8 @@ def main():
                    "max_ns": sizes["max_ns"], "max_nb": sizes["max_nb"], "tol": w.tol},
         "pcg_iters_mean": it_mean,
         "pcg_iters": iters,
+        "pcg_iters_first_solve": iters_first,
+        "refinement_corrections": ir_steps,
         "setup_s": {"assemble": t1 - t0, "factor": t2 - t1},
         "amortised_steps_per_s": amortised,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,

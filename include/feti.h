@@ -117,6 +117,7 @@ typedef struct {
 
 typedef struct {
     int32_t iters;        /* PCG iterations (summed over refinement corrections) */
+    int32_t iters_first;  /* PCG iterations of the first solve of the step */
     int32_t ir_steps;     /* refinement corrections performed */
     int32_t status;       /* FETI_OK or the failure code */
     int32_t start_used;   /* FETI_START_* actually used */

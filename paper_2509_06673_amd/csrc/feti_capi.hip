@@ -65,6 +65,13 @@ struct feti_ctx_s {
   int64_t nstep = 0;
   bool have_prev = false, have_prev2 = false;
   hipEvent_t ev[8] = {};
+  bool own_stream = false;
+  // captured PCG iteration chunks, keyed by the multiplier buffer they update
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    const double* lam = nullptr;
+    int chunk = 0;
+  } graphs[2];
 };
 
 namespace {
@@ -177,6 +184,9 @@ int upload_mesh(feti_ctx ctx) {
   RC(upload(ctx, &m.el_type, h.el_type));
   RC(upload(ctx, &m.el_ldof, h.el_ldof));
   RC(upload(ctx, &m.el_code, h.el_code));
+  RC(upload(ctx, &m.adj_ptr, h.adj_ptr));
+  RC(upload(ctx, &m.adj, h.adj));
+  RC(dalloc(ctx, &m.ebuf, (size_t)m.nelem * m.edof, ctx->allocs));
   RC(upload(ctx, &m.bg_row, h.bg_row));
   RC(upload(ctx, &m.bg_sign, h.bg_sign));
   RC(upload(ctx, &m.bd_row, h.bd_row));
@@ -228,7 +238,15 @@ int upload_mesh(feti_ctx ctx) {
   return FETI_OK;
 }
 
+void drop_graphs(feti_ctx ctx) {
+  for (auto& g : ctx->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = feti_ctx_s::Graph();
+  }
+}
+
 void free_all(feti_ctx ctx) {
+  drop_graphs(ctx);
   for (void* p : ctx->allocs) (void)hipFree(p);
   for (void* p : ctx->mat_allocs) (void)hipFree(p);
   ctx->allocs.clear();
@@ -263,19 +281,26 @@ void op_project(feti_ctx ctx, const double* in, double* out, const int32_t* skip
   launch_coarse_correct(m, ctx->ac, -1.0, in, out, skip, st);
 }
 
-void op_F(feti_ctx ctx, const double* x, double* y, const int32_t* skip) {
+// y_b = (K^+)_bb B^T x per subdomain; y = B y_b; with g: also g = G^T y (same pass)
+void op_F_raw(feti_ctx ctx, const double* x, double* y, double* g, const int32_t* skip) {
   DevMesh& m = ctx->dm;
   GemvArgs a;
   a.A = ctx->Splus; a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
   a.v = x; a.gmode = G_SIGNED; a.gcoef = 1.0; a.y = ctx->yb; a.skip = skip;
   launch_sgemv(m, a, ctx->stream);
-  launch_jump(m, ctx->yb, 0, y, 0, skip, ctx->stream);
+  launch_jump(m, ctx->yb, 0, y, 0, g, skip, ctx->stream);
 }
 
-void op_M(feti_ctx ctx, const double* x, double* y, const int32_t* skip) {
+void op_F(feti_ctx ctx, const double* x, double* y, const int32_t* skip) {
+  op_F_raw(ctx, x, y, nullptr, skip);
+}
+
+// z_b = S_bb (B^T D x)_s per subdomain; y = D B z_b; with g: also g = G^T y
+void op_M_raw(feti_ctx ctx, const double* x, double* y, double* g, const int32_t* skip) {
   DevMesh& m = ctx->dm;
   if (ctx->precond == FETI_PRECOND_NONE) {
     launch_axpby(m.n_lambda, 1.0, x, 0.0, nullptr, y, ctx->stream);
+    if (g) launch_coarse_g(m, y, nullptr, 1.0, g, skip, ctx->stream);
     return;
   }
   GemvArgs a;
@@ -283,7 +308,33 @@ void op_M(feti_ctx ctx, const double* x, double* y, const int32_t* skip) {
   a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
   a.v = x; a.gmode = G_SCALED; a.gcoef = 1.0; a.y = ctx->zb; a.skip = skip;
   launch_sgemv(m, a, ctx->stream);
-  launch_jump(m, ctx->zb, 0, y, 1, skip, ctx->stream);
+  launch_jump(m, ctx->zb, 0, y, 1, g, skip, ctx->stream);
+}
+
+void op_M(feti_ctx ctx, const double* x, double* y, const int32_t* skip) {
+  op_M_raw(ctx, x, y, nullptr, skip);
+}
+
+int32_t* counter(feti_ctx ctx, int phase) { return ctx->ist + IS_CNT0 + phase; }
+
+// One projected PCG iteration (kernels skip once the iteration has converged):
+//   q_raw = F p, q = P q_raw, alpha = rho / (p, q); lam += alpha p, r -= alpha q_raw,
+//   w -= alpha q; convergence test on w; z = M^{-1} w, y = P z, beta; p = y + beta p.
+void pcg_iteration(feti_ctx ctx, double* lam, const int32_t* done) {
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  const bool coarse = ctx->nc > 0;
+  op_F_raw(ctx, ctx->p, ctx->qraw, coarse ? ctx->g : nullptr, done);
+  if (coarse) launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, 1.0, done, st);
+  launch_correct_dot(m, coarse ? ctx->ac : nullptr, ctx->qraw, ctx->q, ctx->p, ctx->part,
+                     counter(ctx, PH_ALPHA), ctx->sc, ctx->ist, PH_ALPHA, st);
+  launch_cg_lam(m, ctx->p, ctx->qraw, ctx->q, lam, ctx->r, ctx->w, ctx->mdiag, ctx->part,
+                counter(ctx, PH_CONV), ctx->sc, ctx->ist, st);
+  op_M_raw(ctx, ctx->w, ctx->z, coarse ? ctx->g : nullptr, done);
+  if (coarse) launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, 1.0, done, st);
+  launch_correct_dot(m, coarse ? ctx->ac : nullptr, ctx->z, ctx->y, ctx->w, ctx->part,
+                     counter(ctx, PH_BETA), ctx->sc, ctx->ist, PH_BETA, st);
+  launch_cg_p(m.n_lambda, ctx->sc, ctx->ist, ctx->y, ctx->p, st);
 }
 
 // Projected PCG on F lambda = d with d = sum_s B_s K_s^+ f_s - c (c: prescribed jump
@@ -303,7 +354,7 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
     a.A = ctx->Kinv; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
     a.xbase = f; a.y = ctx->ytmp;
     launch_sgemv(m, a, st);
-    launch_jump(m, ctx->ytmp, 1, ctx->d, 0, nullptr, st);
+    launch_jump(m, ctx->ytmp, 1, ctx->d, 0, nullptr, nullptr, st);
     if (cj) launch_axpby(nl, 1.0, ctx->d, -1.0, cj, ctx->d, st);
   }
   // admissible start: lambda += G (G^T G)^{-1} (e - G^T lambda)
@@ -319,8 +370,8 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
   int32_t hist[IS_COUNT] = {0, 0, 0, std::max(o->max_it, 0)};
   HIPCHK(hipMemcpyAsync(ctx->ist, hist, sizeof(hist), hipMemcpyHostToDevice, st));
   op_project(ctx, ctx->d, ctx->tl, nullptr);
-  launch_partials(m, nullptr, nullptr, ctx->tl, ctx->mdiag, ctx->part, RED_NBLK, nullptr, st);
-  launch_scalar(ctx->part, RED_NBLK, ctx->sc, ctx->ist, PH_REFNORM, st);
+  launch_reduce(m, nullptr, nullptr, ctx->tl, ctx->mdiag, ctx->part, counter(ctx, PH_REFNORM), ctx->sc,
+                ctx->ist, PH_REFNORM, st);
   // r = d - F lambda; w = P r; y = P M^{-1} w; p = y
   op_F(ctx, lam, ctx->q, nullptr);
   launch_axpby(nl, 1.0, ctx->d, -1.0, ctx->q, ctx->r, st);
@@ -328,12 +379,13 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
   op_M(ctx, ctx->w, ctx->z, nullptr);
   op_project(ctx, ctx->z, ctx->y, nullptr);
   launch_axpby(nl, 1.0, ctx->y, 0.0, nullptr, ctx->p, st);
-  launch_partials(m, ctx->w, ctx->y, ctx->w, ctx->mdiag, ctx->part, RED_NBLK, nullptr, st);
-  launch_scalar(ctx->part, RED_NBLK, ctx->sc, ctx->ist, PH_INIT, st);
+  launch_reduce(m, ctx->w, ctx->y, ctx->w, ctx->mdiag, ctx->part, counter(ctx, PH_INIT), ctx->sc,
+                ctx->ist, PH_INIT, st);
   HIPCHK(hipEventRecord(ctx->ev[2], st));
   const int32_t* done = ctx->ist + IS_DONE;
   const int chunk = std::max(1, o->check_every);
   static const bool trace = std::getenv("FETI_TRACE") != nullptr;
+  static const bool use_graph = std::getenv("FETI_NO_GRAPH") == nullptr;
   for (;;) {
     HIPCHK(hipMemcpyAsync(ctx->h_ist, ctx->ist, IS_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     if (trace)
@@ -343,19 +395,27 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
       std::fprintf(stderr, "[feti] it %d res %.3e rho %.3e status %d\n", ctx->h_ist[IS_ITERS],
                    ctx->h_sc[SC_RES], ctx->h_sc[SC_RHO], ctx->h_ist[IS_STATUS]);
     if (ctx->h_ist[IS_DONE] || ctx->h_ist[IS_ITERS] >= o->max_it) break;
-    for (int it = 0; it < chunk; ++it) {
-      op_F(ctx, ctx->p, ctx->qraw, done);
-      op_project(ctx, ctx->qraw, ctx->q, done);
-      launch_partials(m, ctx->p, ctx->q, nullptr, nullptr, ctx->part, RED_NBLK, done, st);
-      launch_scalar(ctx->part, RED_NBLK, ctx->sc, ctx->ist, PH_ALPHA, st);
-      launch_cg_lam(nl, ctx->sc, ctx->ist, ctx->p, ctx->qraw, ctx->q, lam, ctx->r, ctx->w, st);
-      launch_partials(m, nullptr, nullptr, ctx->w, ctx->mdiag, ctx->part, RED_NBLK, done, st);
-      launch_scalar(ctx->part, RED_NBLK, ctx->sc, ctx->ist, PH_CONV, st);
-      op_M(ctx, ctx->w, ctx->z, done);
-      op_project(ctx, ctx->z, ctx->y, done);
-      launch_partials(m, ctx->w, ctx->y, nullptr, nullptr, ctx->part, RED_NBLK, done, st);
-      launch_scalar(ctx->part, RED_NBLK, ctx->sc, ctx->ist, PH_BETA, st);
-      launch_cg_p(nl, ctx->sc, ctx->ist, ctx->y, ctx->p, st);
+    // one chunk of iterations, replayed from a captured graph
+    feti_ctx_s::Graph* gr = nullptr;
+    if (use_graph) {
+      for (auto& g : ctx->graphs)
+        if (g.exec && g.lam == lam && g.chunk == chunk) gr = &g;
+      if (!gr) {
+        gr = ctx->graphs[0].exec == nullptr ? &ctx->graphs[0] : &ctx->graphs[1];
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        *gr = feti_ctx_s::Graph();
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int it = 0; it < chunk; ++it) pcg_iteration(ctx, lam, done);
+        HIPCHK(hipStreamEndCapture(st, &graph));
+        HIPCHK(hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(graph);
+        gr->lam = lam;
+        gr->chunk = chunk;
+      }
+      HIPCHK(hipGraphLaunch(gr->exec, st));
+    } else {
+      for (int it = 0; it < chunk; ++it) pcg_iteration(ctx, lam, done);
     }
   }
   HIPCHK(hipEventRecord(ctx->ev[3], st));
@@ -365,9 +425,11 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
     launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, -1.0, nullptr, st);
   }
   {
+    // K^+ f is already in ytmp (from d): only the interface columns of K^+ are read
     GemvArgs a;
     a.A = ctx->Kinv; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
-    a.xbase = f; a.v = lam; a.gmode = G_SIGNED; a.gcoef = -1.0;
+    a.kb_only = 1; a.ybase = ctx->ytmp;
+    a.v = lam; a.gmode = G_SIGNED; a.gcoef = -1.0;
     a.y = u; a.alpha_c = ctx->nc > 0 ? ctx->ac : nullptr;
     launch_sgemv(m, a, st);
   }
@@ -399,11 +461,10 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
 void torn_residual(feti_ctx ctx, const double* f, const double* u, const double* lam) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
-  (void)hipMemsetAsync(ctx->ytmp, 0, m.sum_ns * sizeof(double), st);
   launch_elem_matvec(m, u, ctx->ytmp, ctx->mpP, ctx->mpE, st);
   launch_axpby(m.sum_ns, 1.0, f, -1.0, ctx->ytmp, ctx->rf, st);
   launch_sub_gather(m, lam, ctx->rf, st);
-  launch_jump(m, u, 1, ctx->cj, 0, nullptr, st);
+  launch_jump(m, u, 1, ctx->cj, 0, nullptr, nullptr, st);
   launch_axpby(m.n_lambda, -1.0, ctx->cj, 0.0, nullptr, ctx->cj, st);
 }
 
@@ -414,6 +475,7 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
   int iters = 0;
   double res0 = 0, res = 0, r0c = 0, rc_ = 0;
   int rc = solve_torn(ctx, o, o->tol, ctx->f, nullptr, ctx->lam, ctx->u, stats, &iters, &res0, &res);
+  const int iters_first = iters;
   int done_ir = 0;
   double corr = 0.0;
   HIPCHK(hipEventRecord(ctx->ev[6], st));
@@ -442,6 +504,7 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
   HIPCHK(hipStreamSynchronize(st));
   if (stats) {
     stats->iters = iters;
+    stats->iters_first = iters_first;
     stats->ir_steps = done_ir;
     stats->res0 = res0;
     stats->res = res;
@@ -529,6 +592,7 @@ int feti_destroy(feti_ctx ctx) {
     if (ctx->h_ist) (void)hipHostFree(ctx->h_ist);
     if (ctx->h_sc) (void)hipHostFree(ctx->h_sc);
     if (ctx->h_kpart) (void)hipHostFree(ctx->h_kpart);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   }
   delete ctx;
   return FETI_OK;
@@ -596,6 +660,12 @@ int feti_assemble(feti_ctx ctx, const feti_material* P, const feti_material* E, 
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   ctx->device = dev;
+  if (ctx->stream == nullptr) {
+    // a stream of our own (blocking with respect to the null stream) so that the
+    // iteration chunks can be captured into graphs
+    HIPCHK(hipStreamCreate(&ctx->stream));
+    ctx->own_stream = true;
+  }
   ctx->matP = *P;
   ctx->matE = *E;
   ctx->tau = tau;
@@ -630,6 +700,7 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   if (precond < 0 || precond > 2) return fail(ctx, FETI_EINVAL, "bad preconditioner");
   ctx->precision = precision;
   ctx->precond = precond;
+  drop_graphs(ctx);
   hipStream_t st = ctx->stream;
   const MeshHost& h = ctx->mh;
   DevMesh& m = ctx->dm;
@@ -726,7 +797,6 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, fet
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
   HIPCHK(hipEventRecord(ctx->ev[0], st));
-  HIPCHK(hipMemsetAsync(ctx->f, 0, m.sum_ns * sizeof(double), st));
   LoadDev L = make_load(ctx, load);
   launch_rhs(m, ctx->u, ctx->f, ctx->mpP, ctx->mpE, L, st);
   // start vector

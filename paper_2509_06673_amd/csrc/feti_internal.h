@@ -58,6 +58,9 @@ struct MeshHost {
   std::vector<int32_t> el_ldof;   // edof per element: local index or -1
   std::vector<int32_t> el_code;   // edof per element: DOF code (for Dirichlet lifting)
   std::vector<int32_t> sub_el_off;   // n_sub + 1
+  // element contributions of every torn DOF, in element order: adj_ptr[sum_ns + 1],
+  // adj[...] = e * edof + element row
+  std::vector<int32_t> adj_ptr, adj;
   // gather lists per interface DOF (global b index): up to 2 (row, sign)
   std::vector<int32_t> bg_row;    // 2 per b DOF (-1 = none)
   std::vector<double> bg_sign;    // 2 per b DOF

@@ -327,6 +327,27 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
         }
     m.sub_el_off[s.sid + 1] = (int32_t)m.el_sub.size();
   }
+  // DOF -> (element, row) adjacency, elements in increasing order
+  const int64_t nel = (int64_t)m.el_sub.size();
+  std::vector<int32_t> cnt(m.sum_ns + 1, 0);
+  for (int64_t e = 0; e < nel; ++e) {
+    const SubHost& s = m.subs[m.el_sub[e]];
+    for (int a = 0; a < m.edof; ++a) {
+      const int li = m.el_ldof[e * m.edof + a];
+      if (li >= 0) ++cnt[s.off + li + 1];
+    }
+  }
+  m.adj_ptr.assign(m.sum_ns + 1, 0);
+  for (int64_t i = 0; i < m.sum_ns; ++i) m.adj_ptr[i + 1] = m.adj_ptr[i] + cnt[i + 1];
+  m.adj.assign(m.adj_ptr[m.sum_ns], 0);
+  std::vector<int32_t> fill(m.adj_ptr.begin(), m.adj_ptr.end() - 1);
+  for (int64_t e = 0; e < nel; ++e) {
+    const SubHost& s = m.subs[m.el_sub[e]];
+    for (int a = 0; a < m.edof; ++a) {
+      const int li = m.el_ldof[e * m.edof + a];
+      if (li >= 0) m.adj[fill[s.off + li]++] = (int32_t)(e * m.edof + a);
+    }
+  }
   return "";
 }
 

@@ -34,6 +34,8 @@ struct DevMesh {
   // elements
   int32_t *el_sub = nullptr, *el_cell = nullptr, *el_type = nullptr, *el_ldof = nullptr,
           *el_code = nullptr;
+  int32_t *adj_ptr = nullptr, *adj = nullptr;  // torn DOF -> element contributions
+  double* ebuf = nullptr;                      // nelem x edof element contributions
   // interface space
   int32_t* bg_row = nullptr;    // 2 per b DOF
   double* bg_sign = nullptr;
@@ -55,9 +57,11 @@ struct DevMesh {
 
 // assembly / right-hand side (kernels_fem.hip)
 void launch_assemble(const DevMesh& m, double* K, MatParams mpP, MatParams mpE, hipStream_t st);
+// f = torn right-hand side (overwriting f)
 void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams mpP, MatParams mpE,
                 const LoadDev& L, hipStream_t st);
 void launch_init_eta(const DevMesh& m, double* u, const LoadDev& L, hipStream_t st);
+// y = K x (torn, element by element, overwriting y)
 void launch_elem_matvec(const DevMesh& m, const double* x, double* y, MatParams mpP, MatParams mpE,
                         hipStream_t st);
 
@@ -101,6 +105,8 @@ struct GemvArgs {
   double* y = nullptr;           // output, torn (full) or interface space
   const double* alpha_c = nullptr;  // optional: y += R alpha_c (full only)
   const int32_t* skip = nullptr;    // optional: do nothing when *skip != 0
+  int kb_only = 0;                  // 1: sum only over the interface columns (x_I = 0)
+  const double* ybase = nullptr;    // optional: y = ybase + A x (+ R alpha_c)
 };
 
 }  // namespace feti

@@ -1,14 +1,18 @@
 // Element-parallel kernels: assembly of the dense local matrices, the
-// per-step right-hand side, the initial fluid content and the torn-system
-// residual.  Accumulation is deterministic without atomics: the elements of
-// a subdomain are processed in eight colours (cell parity in x and y, times
-// the two triangles of a cell); elements of one colour share no node, so
-// their scatter-adds never touch the same entry.
+// per-step right-hand side, the initial fluid content and the element-by-element
+// matrix-vector product of the refinement residual.  Accumulation is
+// deterministic without atomics: the assembly processes the elements of a
+// subdomain in eight colours (cell parity in x and y, times the two triangles of
+// a cell) whose elements share no node; the right-hand side and the product
+// write per-element contributions that a second kernel sums per DOF in a fixed
+// element order.
 #include "kernels.h"
 #include "fem_device.h"
 #include "loads_device.h"
 
 namespace feti {
+
+constexpr int MAX_EDOF_DEV = 21;
 
 __device__ inline int elem_colour(int cell, int type, int ncell) {
   const int i = cell % ncell, j = cell / ncell;
@@ -57,77 +61,100 @@ __device__ inline double dirichlet_value(const LoadDev& L, bool poro, int32_t co
   return 0.0;
 }
 
-// One thread per (element of the colour, element row): f_s += load integral
-// (rows 1 and 4 of eq. (linalg-system): F_u and -R eta^{n-1} - tau Z) minus
-// the Dirichlet lifting K_e[r, D] g_D.
-__global__ void k_rhs(const int32_t* __restrict__ el_sub, const int32_t* __restrict__ el_cell,
-                      const int32_t* __restrict__ el_type, const int32_t* __restrict__ el_ldof,
-                      const int32_t* __restrict__ el_code, const uint8_t* __restrict__ sub_poro,
-                      const int64_t* __restrict__ soff, const double* __restrict__ eta_prev,
-                      double* __restrict__ f, int nelem, int edof, int order, int ncell, int colour,
-                      MatParams mpP, MatParams mpE, LoadDev L) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t e = gid / edof;
-  const int r = (int)(gid % edof);
-  if (e >= nelem) return;
-  const int cell = el_cell[e], type = el_type[e];
-  if (elem_colour(cell, type, ncell) != colour) return;
-  const int lr = el_ldof[e * edof + r];
-  if (lr < 0) return;
-  const int s = el_sub[e];
-  const bool poro = sub_poro[s] != 0;
+// One thread per element: the element's right-hand side contributions (rows 1 and 4
+// of eq. (linalg-system): F_u = (f, theta) and -R eta^{n-1} - tau Z on the p rows,
+// minus the Dirichlet lifting K_e[r, D] g_D) into ebuf[e][row].
+__global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __restrict__ eta_prev,
+                                                  MatParams mpP, MatParams mpE, LoadDev L) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nelem) return;
+  const int edof = m.edof, order = m.order, ncell = m.ncell;
+  const int s = m.el_sub[e];
+  const bool poro = m.sub_poro[s] != 0;
   ElemGeom g;
-  elem_geom(cell, type, ncell, g);
+  elem_geom(m.el_cell[e], m.el_type[e], ncell, g);
   const MatParams& mp = poro ? mpP : mpE;
-  const int nu = order == 2 ? 12 : 6;
-  double acc = 0.0;
-  if (r < nu) {
-    // consistent load (f, theta_r) with the 7-point rule
-    const int a = r / 2, comp = r % 2;
-    for (int q = 0; q < 7; ++q) {
-      double l0, l1, l2, w;
-      radon_point(q, l0, l1, l2, w);
-      const double x = l0 * g.x[0] + l1 * g.x[1] + l2 * g.x[2];
-      const double y = l0 * g.y[0] + l1 * g.y[1] + l2 * g.y[2];
-      double fx, fy;
-      body_force(L, poro, x, y, fx, fy);
-      const double lam[3] = {l0, l1, l2};
+  const int nloc = order == 2 ? 6 : 3, nu = 2 * nloc;
+  double acc[MAX_EDOF_DEV];
+  for (int r = 0; r < MAX_EDOF_DEV; ++r) acc[r] = 0.0;
+  // loads at the 7 quadrature points
+  for (int q = 0; q < 7; ++q) {
+    double l0, l1, l2, w;
+    radon_point(q, l0, l1, l2, w);
+    const double x = l0 * g.x[0] + l1 * g.x[1] + l2 * g.x[2];
+    const double y = l0 * g.y[0] + l1 * g.y[1] + l2 * g.y[2];
+    double fx, fy;
+    body_force(L, poro, x, y, fx, fy);
+    const double wa = w * g.area;
+    const double lam[3] = {l0, l1, l2};
+    for (int a = 0; a < nloc; ++a) {
       double phi;
       if (order == 1) phi = lam[a];
       else if (a < 3) phi = lam[a] * (2 * lam[a] - 1);
       else phi = 4 * lam[a - 3] * lam[(a - 2) % 3];
-      acc += w * g.area * (comp == 0 ? fx : fy) * phi;
+      acc[2 * a] += wa * fx * phi;
+      acc[2 * a + 1] += wa * fy * phi;
     }
-  } else if (poro && r >= nu + 6) {
-    // p row: -(R eta^{n-1})_k - tau (z, lambda_k)
-    const int k = r - nu - 6;
-    const double* eta = eta_prev + soff[s];
-    for (int b = 0; b < 3; ++b) {
-      const int li = el_ldof[e * edof + nu + 3 + b];
-      acc -= moment2(g, k, b) * eta[li];
+    if (poro) {
+      const double z = source(L, x, y);
+      for (int k = 0; k < 3; ++k) acc[nu + 6 + k] -= mp.tau * wa * z * lam[k];
     }
-    double zk = 0.0;
-    for (int q = 0; q < 7; ++q) {
-      double l0, l1, l2, w;
-      radon_point(q, l0, l1, l2, w);
-      const double x = l0 * g.x[0] + l1 * g.x[1] + l2 * g.x[2];
-      const double y = l0 * g.y[0] + l1 * g.y[1] + l2 * g.y[2];
-      const double lam[3] = {l0, l1, l2};
-      zk += w * g.area * source(L, x, y) * lam[k];
-    }
-    acc -= mp.tau * zk;
+  }
+  const int32_t* ld = m.el_ldof + e * edof;
+  if (poro) {
+    const double* eta = eta_prev + m.soff[s];
+    double ev[3];
+    for (int b = 0; b < 3; ++b) ev[b] = eta[ld[nu + 3 + b]];
+    for (int k = 0; k < 3; ++k)
+      for (int b = 0; b < 3; ++b) acc[nu + 6 + k] -= moment2(g, k, b) * ev[b];
   }
   // Dirichlet lifting
   const int umu = order * ncell + 1;
   const double uh = 1.0 / (order * ncell), h = 1.0 / ncell;
   for (int c = 0; c < edof; ++c) {
-    if (el_ldof[e * edof + c] >= 0) continue;
-    const int32_t code = el_code[e * edof + c];
+    if (ld[c] >= 0) continue;
+    const int32_t code = m.el_code[e * edof + c];
     if (code < 0) continue;
     const double gv = dirichlet_value(L, poro, code, umu, uh, ncell + 1, h);
-    if (gv != 0.0) acc -= elem_entry(order, poro, g, mp, r, c) * gv;
+    if (gv == 0.0) continue;
+    for (int r = 0; r < edof; ++r)
+      if (ld[r] >= 0) acc[r] -= elem_entry(order, poro, g, mp, r, c) * gv;
   }
-  f[soff[s] + lr] += acc;
+  double* out = m.ebuf + e * edof;
+  for (int r = 0; r < edof; ++r) out[r] = acc[r];
+}
+
+// One thread per (element, row): ebuf[e][row] = (K_e x_e)[row]
+__global__ void k_elem_matvec(DevMesh m, const double* __restrict__ x, MatParams mpP, MatParams mpE) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int edof = m.edof;
+  const int64_t e = gid / edof;
+  const int r = (int)(gid % edof);
+  if (e >= m.nelem) return;
+  const int32_t* ld = m.el_ldof + e * edof;
+  double acc = 0.0;
+  if (ld[r] >= 0) {
+    const int s = m.el_sub[e];
+    const bool poro = m.sub_poro[s] != 0;
+    ElemGeom g;
+    elem_geom(m.el_cell[e], m.el_type[e], m.ncell, g);
+    const MatParams& mp = poro ? mpP : mpE;
+    const double* xs = x + m.soff[s];
+    for (int c = 0; c < edof; ++c) {
+      const int lc = ld[c];
+      if (lc >= 0) acc += elem_entry(m.order, poro, g, mp, r, c) * xs[lc];
+    }
+  }
+  m.ebuf[gid] = acc;
+}
+
+// y_i = sum of the element contributions of torn DOF i, in element order
+__global__ void k_gather_elem(DevMesh m, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m.sum_ns) return;
+  double s = 0.0;
+  for (int k = m.adj_ptr[i]; k < m.adj_ptr[i + 1]; ++k) s += m.ebuf[m.adj[k]];
+  y[i] = s;
 }
 
 // eta^0 at every local eta DOF (nodal interpolation of c0 p0 + alpha div u0)
@@ -140,36 +167,6 @@ __global__ void k_init_eta(const int32_t* __restrict__ code, double* __restrict_
   const int node = c >> 3;
   const double h = 1.0 / ncell;
   u[i] = initial_eta(L, (node % (ncell + 1)) * h, (node / (ncell + 1)) * h);
-}
-
-// y_s += K_e x_s over the elements of the colour (torn, sparse matrix-vector
-// product with the FP64 element matrices; used for refinement residuals)
-__global__ void k_elem_matvec(const int32_t* __restrict__ el_sub, const int32_t* __restrict__ el_cell,
-                              const int32_t* __restrict__ el_type, const int32_t* __restrict__ el_ldof,
-                              const uint8_t* __restrict__ sub_poro, const int64_t* __restrict__ soff,
-                              const double* __restrict__ x, double* __restrict__ y, int nelem, int edof,
-                              int order, int ncell, int colour, MatParams mpP, MatParams mpE) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t e = gid / edof;
-  const int r = (int)(gid % edof);
-  if (e >= nelem) return;
-  const int cell = el_cell[e], type = el_type[e];
-  if (elem_colour(cell, type, ncell) != colour) return;
-  const int lr = el_ldof[e * edof + r];
-  if (lr < 0) return;
-  const int s = el_sub[e];
-  const bool poro = sub_poro[s] != 0;
-  ElemGeom g;
-  elem_geom(cell, type, ncell, g);
-  const MatParams& mp = poro ? mpP : mpE;
-  const double* xs = x + soff[s];
-  double acc = 0.0;
-  for (int c = 0; c < edof; ++c) {
-    const int lc = el_ldof[e * edof + c];
-    if (lc < 0) continue;
-    acc += elem_entry(order, poro, g, mp, r, c) * xs[lc];
-  }
-  y[soff[s] + lr] += acc;
 }
 
 // ---- launchers ---------------------------------------------------------------
@@ -186,13 +183,8 @@ void launch_assemble(const DevMesh& m, double* K, MatParams mpP, MatParams mpE, 
 
 void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams mpP, MatParams mpE,
                 const LoadDev& L, hipStream_t st) {
-  const int64_t nthreads = (int64_t)m.nelem * m.edof;
-  const int blk = 256;
-  const int grid = (int)((nthreads + blk - 1) / blk);
-  for (int colour = 0; colour < 8; ++colour)
-    hipLaunchKernelGGL(k_rhs, dim3(grid), dim3(blk), 0, st, m.el_sub, m.el_cell, m.el_type,
-                       m.el_ldof, m.el_code, m.sub_poro, m.soff, eta_prev, f, m.nelem, m.edof,
-                       m.order, m.ncell, colour, mpP, mpE, L);
+  hipLaunchKernelGGL(k_rhs_elem, dim3((m.nelem + 127) / 128), dim3(128), 0, st, m, eta_prev, mpP, mpE, L);
+  hipLaunchKernelGGL(k_gather_elem, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, m, f);
 }
 
 void launch_init_eta(const DevMesh& m, double* u, const LoadDev& L, hipStream_t st) {
@@ -204,12 +196,9 @@ void launch_init_eta(const DevMesh& m, double* u, const LoadDev& L, hipStream_t 
 void launch_elem_matvec(const DevMesh& m, const double* x, double* y, MatParams mpP, MatParams mpE,
                         hipStream_t st) {
   const int64_t nthreads = (int64_t)m.nelem * m.edof;
-  const int blk = 256;
-  const int grid = (int)((nthreads + blk - 1) / blk);
-  for (int colour = 0; colour < 8; ++colour)
-    hipLaunchKernelGGL(k_elem_matvec, dim3(grid), dim3(blk), 0, st, m.el_sub, m.el_cell, m.el_type,
-                       m.el_ldof, m.sub_poro, m.soff, x, y, m.nelem, m.edof, m.order, m.ncell,
-                       colour, mpP, mpE);
+  hipLaunchKernelGGL(k_elem_matvec, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, m, x,
+                     mpP, mpE);
+  hipLaunchKernelGGL(k_gather_elem, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, m, y);
 }
 
 }  // namespace feti

@@ -3,6 +3,8 @@
 // (B_s^T and sum_s B_s), the (B B^T)^{-1}-weighted gather/scatter of the
 // Dirichlet preconditioner, the coarse space G = [B_s R_s], and the FP64
 // vector updates and deterministic reductions of projected PCG.
+#include <algorithm>
+
 #include "kernels.h"
 #include "iface.h"
 
@@ -27,211 +29,6 @@ __device__ inline double gather_b(const DevMesh& m, const double* __restrict__ v
   return s;
 }
 
-// y_s = A_s x_s for every subdomain s.  A_s is symmetric, so column k of the
-// row-major block is read as row k: for a fixed k the 64 lanes of a wavefront
-// read 64 consecutive entries.  Each workgroup owns 64 output rows; its four
-// wavefronts split the k range and combine in LDS.  x_s is built in LDS.
-__global__ void __launch_bounds__(256) k_sgemv(DevMesh m, GemvArgs a) {
-  if (a.skip && *a.skip) return;
-  const int s = blockIdx.y;
-  const int ns = m.ns[s], nbs = m.nb[s];
-  const int n = a.which_n == 0 ? ns : nbs;
-  const int row0 = blockIdx.x * 64;
-  if (row0 >= n) return;
-  extern __shared__ double smem[];
-  double* xs = smem;              // n
-  double* red = smem + m.max_ns;  // 4 x 64
-  const int first_b = n - nbs;
-  const int64_t xoff = a.which_n == 0 ? m.soff[s] : m.boff[s];
-  for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    double v = a.xbase ? a.xbase[xoff + t] : 0.0;
-    if (a.gmode != G_NONE && t >= first_b) v += a.gcoef * gather_b(m, a.v, m.boff[s] + (t - first_b), a.gmode);
-    xs[t] = v;
-  }
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = row0 + lane;
-  const int kq = (n + 3) / 4;
-  const int kb = wave * kq, ke = min(n, kb + kq);
-  const double* A = a.A + a.aofs[s];
-  const int64_t ld = a.lda[s];
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-  if (i < n) {
-    int k = kb;
-    for (; k + 4 <= ke; k += 4) {
-      acc0 += A[(int64_t)(k + 0) * ld + i] * xs[k + 0];
-      acc1 += A[(int64_t)(k + 1) * ld + i] * xs[k + 1];
-      acc2 += A[(int64_t)(k + 2) * ld + i] * xs[k + 2];
-      acc3 += A[(int64_t)(k + 3) * ld + i] * xs[k + 3];
-    }
-    for (; k < ke; ++k) acc0 += A[(int64_t)k * ld + i] * xs[k];
-  }
-  red[wave * 64 + lane] = (acc0 + acc1) + (acc2 + acc3);
-  __syncthreads();
-  if (wave == 0 && i < n) {
-    double yv = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
-    if (a.alpha_c) {
-      const int f = m.sub_float[s];
-      if (f >= 0) {
-        const double* R = m.rfull + 3 * (m.soff[s] + i);
-        yv += R[0] * a.alpha_c[3 * f] + R[1] * a.alpha_c[3 * f + 1] + R[2] * a.alpha_c[3 * f + 2];
-      }
-    }
-    a.y[xoff + i] = yv;
-  }
-}
-
-// out_j = sum over the two entries of row j of sign * y_b (signed jump), or the
-// (B B^T)^{-1}-weighted jump over the row's group when scaled.
-__global__ void k_jump(DevMesh m, const double* __restrict__ yb, int from_torn,
-                       double* __restrict__ out, int scaled, const int32_t* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m.n_lambda) return;
-  auto jump = [&](int64_t r) {
-    double s = 0.0;
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int64_t gb = m.jr_b[2 * r + e];
-      const int64_t idx = from_torn ? (int64_t)m.b_torn[gb] : gb;
-      s += m.jr_sign[2 * r + e] * yb[idx];
-    }
-    return s;
-  };
-  if (!scaled) {
-    out[j] = jump(j);
-    return;
-  }
-  const int gs = m.grp_start[j], gz = m.grp_size[j];
-  double s = 0.0;
-  for (int k = 0; k < gz; ++k) s += m.dwt[3 * j + k] * jump(gs + k);
-  out[j] = s;
-}
-
-// g_f = R_s^T x_s for each floating subdomain s = float_sub[f], with
-// x_s = base_s + gsign * B_s^T v (base torn and/or v multipliers).
-__global__ void __launch_bounds__(256) k_coarse_g(DevMesh m, const double* __restrict__ v,
-                                                  const double* __restrict__ base, double gsign,
-                                                  double* __restrict__ g,
-                                                  const int32_t* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int f = blockIdx.x;
-  const int s = m.float_sub[f];
-  const int ns = m.ns[s], nbs = m.nb[s], first_b = ns - nbs;
-  const int64_t so = m.soff[s];
-  double acc[3] = {0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-    double x = base ? base[so + i] : 0.0;
-    if (v && i >= first_b) x += gsign * gather_b(m, v, m.boff[s] + (i - first_b), G_SIGNED);
-    const double* R = m.rfull + 3 * (so + i);
-    acc[0] += R[0] * x;
-    acc[1] += R[1] * x;
-    acc[2] += R[2] * x;
-  }
-  __shared__ double red[3][256];
-  for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = acc[c];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x < 3) g[3 * f + threadIdx.x] = red[threadIdx.x][0];
-}
-
-// a = scale * Cinv g (Cinv symmetric n_c x n_c)
-__global__ void k_coarse_apply(int nc, const double* __restrict__ C, const double* __restrict__ g,
-                               double* __restrict__ a, double scale, const int32_t* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nc) return;
-  double s = 0.0;
-  for (int k = 0; k < nc; ++k) s += C[(int64_t)k * nc + i] * g[k];
-  a[i] = scale * s;
-}
-
-// v_j = vin_j + scale * (G a)_j, (G a)_j = sum_e sign_e R_b(gb_e) . a_{float(sub(gb_e))}
-__global__ void k_coarse_correct(DevMesh m, const double* __restrict__ a, double scale,
-                                 const double* __restrict__ vin, double* __restrict__ v,
-                                 const int32_t* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m.n_lambda) return;
-  double s = 0.0;
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int64_t gb = m.jr_b[2 * j + e];
-    const int f = m.sub_float[m.b_sub[gb]];
-    if (f < 0) continue;
-    const double* R = m.rb + 3 * gb;
-    s += m.jr_sign[2 * j + e] * (R[0] * a[3 * f] + R[1] * a[3 * f + 1] + R[2] * a[3 * f + 2]);
-  }
-  v[j] = (vin ? vin[j] : 0.0) + scale * s;
-}
-
-// G^T G, one thread per entry (r, c): sum over the jump rows of subdomain float_sub[r/3]
-__global__ void k_gtg(DevMesh m, double* __restrict__ C, int nc) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)nc * nc) return;
-  const int r = (int)(t / nc), c = (int)(t % nc);
-  const int s = m.float_sub[r / 3], ca = r % 3;
-  const int st = m.float_sub[c / 3], cb = c % 3;
-  const int nbs = m.nb[s];
-  const int64_t b0 = m.boff[s];
-  double acc = 0.0;
-  for (int bl = 0; bl < nbs; ++bl) {
-    const int64_t gb = b0 + bl;
-    for (int slot = 0; slot < 2; ++slot) {
-      const int j = m.bg_row[2 * gb + slot];
-      if (j < 0) continue;
-      const double gs = m.bg_sign[2 * gb + slot] * m.rb[3 * gb + ca];
-      for (int e = 0; e < 2; ++e) {
-        const int64_t gb2 = m.jr_b[2 * (int64_t)j + e];
-        if (m.b_sub[gb2] != st) continue;
-        acc += gs * m.jr_sign[2 * (int64_t)j + e] * m.rb[3 * gb2 + cb];
-      }
-    }
-  }
-  C[t] = acc;
-}
-
-// ---- PCG vector kernels with deterministic two-level reductions ---------------
-
-// Per-block partial sums: slot 0: (x, y); slots 2..7: per-kind |nrm|^2; slots
-// 8..13: per-kind sum_j |mdiag_j| nrm_j^2.  Any pointer may be null.
-__global__ void __launch_bounds__(RED_BLOCK) k_partials(DevMesh m, const double* __restrict__ x,
-                                                        const double* __restrict__ y,
-                                                        const double* __restrict__ nrm,
-                                                        const double* __restrict__ mdiag,
-                                                        double* __restrict__ part,
-                                                        const int32_t* __restrict__ done) {
-  if (done && *done) return;
-  __shared__ double red[NPART][RED_BLOCK];
-  double acc[NPART];
-#pragma unroll
-  for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
-  const int64_t n = m.n_lambda;
-  const int64_t stride = (int64_t)gridDim.x * RED_BLOCK;
-  for (int64_t j = (int64_t)blockIdx.x * RED_BLOCK + threadIdx.x; j < n; j += stride) {
-    if (x) acc[0] += x[j] * y[j];
-    if (nrm) {
-      const double v2 = nrm[j] * nrm[j];
-      const int k = m.row_kind[j];
-      acc[2 + k] += v2;
-      acc[8 + k] += fabs(mdiag[j]) * v2;
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = acc[c];
-  __syncthreads();
-  for (int w = RED_BLOCK / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x < NPART) part[blockIdx.x * NPART + threadIdx.x] = red[threadIdx.x][0];
-}
-
 // Relative residual of the iteration: the largest of the dual-energy ratio
 // |w|_M / ref_M and the per-kind ratios |w_k| / ref_k over the kinds whose
 // reference energy is not negligible (a kind without load data, whose jump
@@ -253,47 +50,9 @@ __device__ inline double rel_residual(const double* v, const double* sc) {
   return rel;
 }
 
-// M_jj = sum over the interface DOFs b of row j's group of (B^T D)[b, j]^2 S_bb[b, b]
-__global__ void k_precond_diag(DevMesh m, const double* __restrict__ S, double* __restrict__ md) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m.n_lambda) return;
-  const int gs = m.grp_start[j], gz = m.grp_size[j];
-  const int slot = (int)(j - gs);
-  double acc = 0.0;
-  for (int k = 0; k < gz; ++k) {
-    const int64_t r = gs + k;
-    for (int e = 0; e < 2; ++e) {
-      if (e == 1 && k + 1 < gz) continue;  // shared with the next row of the chain
-      const int64_t gb = m.jr_b[2 * r + e];
-      const int s = m.b_sub[gb];
-      const int bl = (int)(gb - m.boff[s]);
-      const double wgt = m.bd_wt[3 * gb + slot];
-      acc += wgt * wgt * S[m.sofs[s] + (int64_t)bl * m.ldb[s] + bl];
-    }
-  }
-  md[j] = acc;
-}
-
-// Sums the partials in a fixed order and runs the scalar part of one PCG phase.
-__global__ void k_scalar(const double* __restrict__ part, int nblk, double* __restrict__ sc,
-                         int32_t* __restrict__ ist, int phase) {
-  if (ist[IS_DONE] && phase != PH_INIT && phase != PH_REFNORM) return;
-  __shared__ double red[NPART][64];
-  const int t = threadIdx.x;
-  double acc[NPART];
-  for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
-  for (int b = t; b < nblk; b += 64)
-    for (int c = 0; c < NPART; ++c) acc[c] += part[b * NPART + c];
-  for (int c = 0; c < NPART; ++c) red[c][t] = acc[c];
-  __syncthreads();
-  for (int w = 32; w > 0; w >>= 1) {
-    if (t < w)
-      for (int c = 0; c < NPART; ++c) red[c][t] += red[c][t + w];
-    __syncthreads();
-  }
-  if (t != 0) return;
-  double v[NPART];
-  for (int c = 0; c < NPART; ++c) v[c] = red[c][0];
+// Scalar part of one PCG phase from the fully reduced sums v[NPART] (one thread).
+__device__ void scalar_phase(const double* v, double* __restrict__ sc, int32_t* __restrict__ ist,
+                             int phase) {
   switch (phase) {
     case PH_REFNORM: {
       // references from P d: per-kind norms and energies, total energy norm
@@ -359,18 +118,367 @@ __global__ void k_scalar(const double* __restrict__ part, int nblk, double* __re
   }
 }
 
-// lam += alpha p; r -= alpha q_raw; w -= alpha q
-__global__ void k_cg_lam(int64_t n, const double* __restrict__ sc, const int32_t* __restrict__ ist,
-                         const double* __restrict__ p, const double* __restrict__ qraw,
-                         const double* __restrict__ q, double* __restrict__ lam,
-                         double* __restrict__ r, double* __restrict__ w) {
-  if (ist[IS_DONE]) return;
+// Block-wide sums of acc[0..NPART) written to part[blockIdx.x]; the last block to
+// finish sums all partials in block order (deterministic) and runs the phase.
+// counter must be zero on entry; the last block resets it.
+__device__ void reduce_and_finalize(double* acc, double* __restrict__ part, int32_t* __restrict__ counter,
+                                    double* __restrict__ sc, int32_t* __restrict__ ist, int phase) {
+  __shared__ double red[NPART][RED_BLOCK];
+  __shared__ int is_last;
+  for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int w = RED_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < NPART) part[blockIdx.x * NPART + threadIdx.x] = red[threadIdx.x][0];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1) == (int)gridDim.x - 1);
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  const int nblk = gridDim.x;
+  for (int c = 0; c < NPART; ++c) {
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += RED_BLOCK) a += part[b * NPART + c];
+    red[c][threadIdx.x] = a;
+  }
+  __syncthreads();
+  for (int w = RED_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double v[NPART];
+    for (int c = 0; c < NPART; ++c) v[c] = red[c][0];
+    scalar_phase(v, sc, ist, phase);
+    *counter = 0;
+  }
+}
+
+// y_s = A_s x_s for every subdomain s.  A_s is symmetric, so column k of the
+// row-major block is read as row k: for a fixed k the 64 lanes of a wavefront
+// read 64 consecutive entries.  Each workgroup owns 64 output rows; its four
+// wavefronts split the k range and combine in LDS.  x_s is built in LDS.
+__global__ void __launch_bounds__(256) k_sgemv(DevMesh m, GemvArgs a) {
+  if (a.skip && *a.skip) return;
+  const int s = blockIdx.y;
+  const int ns = m.ns[s], nbs = m.nb[s];
+  const int n = a.which_n == 0 ? ns : nbs;
+  const int row0 = blockIdx.x * 64;
+  if (row0 >= n) return;
+  extern __shared__ double smem[];
+  double* xs = smem;              // n
+  double* red = smem + m.max_ns;  // 4 x 64
+  const int first_b = n - nbs;
+  const int64_t xoff = a.which_n == 0 ? m.soff[s] : m.boff[s];
+  for (int t = a.kb_only ? first_b + threadIdx.x : threadIdx.x; t < n; t += blockDim.x) {
+    double v = a.xbase ? a.xbase[xoff + t] : 0.0;
+    if (a.gmode != G_NONE && t >= first_b) v += a.gcoef * gather_b(m, a.v, m.boff[s] + (t - first_b), a.gmode);
+    xs[t] = v;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = row0 + lane;
+  const int k0 = a.kb_only ? first_b : 0;
+  const int kq = (n - k0 + 3) / 4;
+  const int kb = k0 + wave * kq, ke = min(n, kb + kq);
+  const double* A = a.A + a.aofs[s];
+  const int64_t ld = a.lda[s];
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  if (i < n) {
+    int k = kb;
+    for (; k + 4 <= ke; k += 4) {
+      acc0 += A[(int64_t)(k + 0) * ld + i] * xs[k + 0];
+      acc1 += A[(int64_t)(k + 1) * ld + i] * xs[k + 1];
+      acc2 += A[(int64_t)(k + 2) * ld + i] * xs[k + 2];
+      acc3 += A[(int64_t)(k + 3) * ld + i] * xs[k + 3];
+    }
+    for (; k < ke; ++k) acc0 += A[(int64_t)k * ld + i] * xs[k];
+  }
+  red[wave * 64 + lane] = (acc0 + acc1) + (acc2 + acc3);
+  __syncthreads();
+  if (wave == 0 && i < n) {
+    double yv = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+    if (a.ybase) yv += a.ybase[xoff + i];
+    if (a.alpha_c) {
+      const int f = m.sub_float[s];
+      if (f >= 0) {
+        const double* R = m.rfull + 3 * (m.soff[s] + i);
+        yv += R[0] * a.alpha_c[3 * f] + R[1] * a.alpha_c[3 * f + 1] + R[2] * a.alpha_c[3 * f + 2];
+      }
+    }
+    a.y[xoff + i] = yv;
+  }
+}
+
+__device__ inline double jump_raw(const DevMesh& m, const double* __restrict__ yb, int from_torn,
+                                  int64_t r) {
+  double s = 0.0;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int64_t gb = m.jr_b[2 * r + e];
+    const int64_t idx = from_torn ? (int64_t)m.b_torn[gb] : gb;
+    s += m.jr_sign[2 * r + e] * yb[idx];
+  }
+  return s;
+}
+
+// signed jump of row j, or its (B B^T)^{-1}-weighted version over the row's group
+__device__ inline double jump_row(const DevMesh& m, const double* __restrict__ yb, int from_torn,
+                                  int64_t j, int scaled) {
+  if (!scaled) return jump_raw(m, yb, from_torn, j);
+  const int gs = m.grp_start[j], gz = m.grp_size[j];
+  double s = 0.0;
+  for (int k = 0; k < gz; ++k) s += m.dwt[3 * j + k] * jump_raw(m, yb, from_torn, gs + k);
+  return s;
+}
+
+// Blocks [0, nlb): out_j = jump_row(yb).  Blocks [nlb, nlb + n_float) (when g is
+// given): g_f = R_b^T B_s^T out for the floating subdomain s = float_sub[f],
+// evaluated from yb directly, so G^T out needs no second pass.
+__global__ void __launch_bounds__(256) k_jump(DevMesh m, const double* __restrict__ yb, int from_torn,
+                                              double* __restrict__ out, int scaled,
+                                              double* __restrict__ g, int nlb,
+                                              const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  if ((int)blockIdx.x < nlb) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m.n_lambda) out[j] = jump_row(m, yb, from_torn, j, scaled);
+    return;
+  }
+  const int f = blockIdx.x - nlb;
+  const int s = m.float_sub[f];
+  const int nbs = m.nb[s];
+  const int64_t b0 = m.boff[s];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nbs; i += blockDim.x) {
+    const int64_t gb = b0 + i;
+    double v = 0.0;
+    for (int slot = 0; slot < 2; ++slot) {
+      const int r = m.bg_row[2 * gb + slot];
+      if (r >= 0) v += m.bg_sign[2 * gb + slot] * jump_row(m, yb, from_torn, r, scaled);
+    }
+    const double* R = m.rb + 3 * gb;
+    acc[0] += R[0] * v;
+    acc[1] += R[1] * v;
+    acc[2] += R[2] * v;
+  }
+  __shared__ double red[3][256];
+  for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) g[3 * f + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// g_f = R_s^T x_s for each floating subdomain s = float_sub[f], with
+// x_s = base_s + gsign * B_s^T v (base torn and/or v multipliers).
+__global__ void __launch_bounds__(256) k_coarse_g(DevMesh m, const double* __restrict__ v,
+                                                  const double* __restrict__ base, double gsign,
+                                                  double* __restrict__ g,
+                                                  const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int f = blockIdx.x;
+  const int s = m.float_sub[f];
+  const int ns = m.ns[s], nbs = m.nb[s], first_b = ns - nbs;
+  const int64_t so = m.soff[s];
+  double acc[3] = {0.0, 0.0, 0.0};
+  // without a torn base only the interface part is nonzero
+  for (int i = base ? threadIdx.x : first_b + threadIdx.x; i < ns; i += blockDim.x) {
+    double x = base ? base[so + i] : 0.0;
+    if (v && i >= first_b) x += gsign * gather_b(m, v, m.boff[s] + (i - first_b), G_SIGNED);
+    const double* R = m.rfull + 3 * (so + i);
+    acc[0] += R[0] * x;
+    acc[1] += R[1] * x;
+    acc[2] += R[2] * x;
+  }
+  __shared__ double red[3][256];
+  for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) g[3 * f + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// a = scale * Cinv g (Cinv symmetric n_c x n_c): one wavefront per row
+__global__ void __launch_bounds__(256) k_coarse_apply(int nc, const double* __restrict__ C,
+                                                      const double* __restrict__ g,
+                                                      double* __restrict__ a, double scale,
+                                                      const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= nc) return;
+  const double* Cr = C + (int64_t)row * nc;
+  double s = 0.0;
+  for (int k = lane; k < nc; k += 64) s += Cr[k] * g[k];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) a[row] = scale * s;
+}
+
+__device__ inline double coarse_G_row(const DevMesh& m, const double* __restrict__ a, int64_t j) {
+  double s = 0.0;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int64_t gb = m.jr_b[2 * j + e];
+    const int f = m.sub_float[m.b_sub[gb]];
+    if (f < 0) continue;
+    const double* R = m.rb + 3 * gb;
+    s += m.jr_sign[2 * j + e] * (R[0] * a[3 * f] + R[1] * a[3 * f + 1] + R[2] * a[3 * f + 2]);
+  }
+  return s;
+}
+
+// v_j = vin_j + scale * (G a)_j, (G a)_j = sum_e sign_e R_b(gb_e) . a_{float(sub(gb_e))}
+__global__ void k_coarse_correct(DevMesh m, const double* __restrict__ a, double scale,
+                                 const double* __restrict__ vin, double* __restrict__ v,
+                                 const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  if (j >= m.n_lambda) return;
+  v[j] = (vin ? vin[j] : 0.0) + scale * coarse_G_row(m, a, j);
+}
+
+// v = vin - G a (a may be null: v = vin), then (x, v) reduced; the last block runs phase
+__global__ void __launch_bounds__(RED_BLOCK) k_correct_dot(DevMesh m, const double* __restrict__ a,
+                                                           const double* __restrict__ vin,
+                                                           double* __restrict__ v,
+                                                           const double* __restrict__ x,
+                                                           double* __restrict__ part,
+                                                           int32_t* __restrict__ counter,
+                                                           double* __restrict__ sc,
+                                                           int32_t* __restrict__ ist, int phase) {
+  if (ist[IS_DONE]) return;
+  double acc[NPART];
+#pragma unroll
+  for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * RED_BLOCK;
+  for (int64_t j = (int64_t)blockIdx.x * RED_BLOCK + threadIdx.x; j < m.n_lambda; j += stride) {
+    const double vj = vin[j] - (a ? coarse_G_row(m, a, j) : 0.0);
+    v[j] = vj;
+    acc[0] += x[j] * vj;
+  }
+  reduce_and_finalize(acc, part, counter, sc, ist, phase);
+}
+
+// G^T G, one thread per entry (r, c): sum over the jump rows of subdomain float_sub[r/3]
+__global__ void k_gtg(DevMesh m, double* __restrict__ C, int nc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nc * nc) return;
+  const int r = (int)(t / nc), c = (int)(t % nc);
+  const int s = m.float_sub[r / 3], ca = r % 3;
+  const int st = m.float_sub[c / 3], cb = c % 3;
+  const int nbs = m.nb[s];
+  const int64_t b0 = m.boff[s];
+  double acc = 0.0;
+  for (int bl = 0; bl < nbs; ++bl) {
+    const int64_t gb = b0 + bl;
+    for (int slot = 0; slot < 2; ++slot) {
+      const int j = m.bg_row[2 * gb + slot];
+      if (j < 0) continue;
+      const double gs = m.bg_sign[2 * gb + slot] * m.rb[3 * gb + ca];
+      for (int e = 0; e < 2; ++e) {
+        const int64_t gb2 = m.jr_b[2 * (int64_t)j + e];
+        if (m.b_sub[gb2] != st) continue;
+        acc += gs * m.jr_sign[2 * (int64_t)j + e] * m.rb[3 * gb2 + cb];
+      }
+    }
+  }
+  C[t] = acc;
+}
+
+// ---- PCG vector kernels with deterministic two-level reductions ---------------
+
+// Reductions over the multipliers: slot 0: (x, y); slots 2..7: per-kind |nrm|^2;
+// slots 8..13: per-kind sum_j |mdiag_j| nrm_j^2 (any pointer may be null); the
+// last block runs the scalar phase.
+__global__ void __launch_bounds__(RED_BLOCK) k_reduce(DevMesh m, const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const double* __restrict__ nrm,
+                                                      const double* __restrict__ mdiag,
+                                                      double* __restrict__ part,
+                                                      int32_t* __restrict__ counter,
+                                                      double* __restrict__ sc,
+                                                      int32_t* __restrict__ ist, int phase) {
+  if (ist[IS_DONE] && phase != PH_INIT && phase != PH_REFNORM) return;
+  double acc[NPART];
+#pragma unroll
+  for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
+  const int64_t n = m.n_lambda;
+  const int64_t stride = (int64_t)gridDim.x * RED_BLOCK;
+  for (int64_t j = (int64_t)blockIdx.x * RED_BLOCK + threadIdx.x; j < n; j += stride) {
+    if (x) acc[0] += x[j] * y[j];
+    if (nrm) {
+      const double v2 = nrm[j] * nrm[j];
+      const int k = m.row_kind[j];
+      acc[2 + k] += v2;
+      acc[8 + k] += fabs(mdiag[j]) * v2;
+    }
+  }
+  reduce_and_finalize(acc, part, counter, sc, ist, phase);
+}
+
+// M_jj = sum over the interface DOFs b of row j's group of (B^T D)[b, j]^2 S_bb[b, b]
+__global__ void k_precond_diag(DevMesh m, const double* __restrict__ S, double* __restrict__ md) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m.n_lambda) return;
+  const int gs = m.grp_start[j], gz = m.grp_size[j];
+  const int slot = (int)(j - gs);
+  double acc = 0.0;
+  for (int k = 0; k < gz; ++k) {
+    const int64_t r = gs + k;
+    for (int e = 0; e < 2; ++e) {
+      if (e == 1 && k + 1 < gz) continue;  // shared with the next row of the chain
+      const int64_t gb = m.jr_b[2 * r + e];
+      const int s = m.b_sub[gb];
+      const int bl = (int)(gb - m.boff[s]);
+      const double wgt = m.bd_wt[3 * gb + slot];
+      acc += wgt * wgt * S[m.sofs[s] + (int64_t)bl * m.ldb[s] + bl];
+    }
+  }
+  md[j] = acc;
+}
+
+
+// lam += alpha p; r -= alpha q_raw; w -= alpha q; then the convergence norms of w
+__global__ void __launch_bounds__(RED_BLOCK) k_cg_lam(DevMesh m, const double* __restrict__ p,
+                                                      const double* __restrict__ qraw,
+                                                      const double* __restrict__ q,
+                                                      double* __restrict__ lam,
+                                                      double* __restrict__ r,
+                                                      double* __restrict__ w,
+                                                      const double* __restrict__ mdiag,
+                                                      double* __restrict__ part,
+                                                      int32_t* __restrict__ counter,
+                                                      double* __restrict__ sc,
+                                                      int32_t* __restrict__ ist) {
+  if (ist[IS_DONE]) return;
   const double al = sc[SC_ALPHA];
-  lam[j] += al * p[j];
-  r[j] -= al * qraw[j];
-  w[j] -= al * q[j];
+  double acc[NPART];
+#pragma unroll
+  for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * RED_BLOCK;
+  for (int64_t j = (int64_t)blockIdx.x * RED_BLOCK + threadIdx.x; j < m.n_lambda; j += stride) {
+    lam[j] += al * p[j];
+    r[j] -= al * qraw[j];
+    const double wn = w[j] - al * q[j];
+    w[j] = wn;
+    const double v2 = wn * wn;
+    const int k = m.row_kind[j];
+    acc[2 + k] += v2;
+    acc[8 + k] += fabs(mdiag[j]) * v2;
+  }
+  reduce_and_finalize(acc, part, counter, sc, ist, PH_CONV);
 }
 
 // p = y + beta p
@@ -453,10 +561,12 @@ void launch_sgemv(const DevMesh& m, const GemvArgs& a, hipStream_t st) {
 }
 
 void launch_jump(const DevMesh& m, const double* yb, int from_torn, double* out, int scaled,
-                 const int32_t* skip, hipStream_t st) {
+                 double* g, const int32_t* skip, hipStream_t st) {
   const int blk = 256;
-  hipLaunchKernelGGL(k_jump, dim3((unsigned)((m.n_lambda + blk - 1) / blk)), dim3(blk), 0, st, m, yb,
-                     from_torn, out, scaled, skip);
+  const int nlb = (int)((m.n_lambda + blk - 1) / blk);
+  const int extra = g ? m.n_float : 0;
+  hipLaunchKernelGGL(k_jump, dim3(nlb + extra), dim3(blk), 0, st, m, yb, from_torn, out, scaled, g, nlb,
+                     skip);
 }
 
 void launch_coarse_g(const DevMesh& m, const double* v, const double* base, double gsign, double* g,
@@ -468,8 +578,7 @@ void launch_coarse_g(const DevMesh& m, const double* v, const double* base, doub
 void launch_coarse_apply(int nc, const double* Cinv, const double* g, double* a, double scale,
                          const int32_t* skip, hipStream_t st) {
   if (nc == 0) return;
-  hipLaunchKernelGGL(k_coarse_apply, dim3((nc + 127) / 128), dim3(128), 0, st, nc, Cinv, g, a, scale,
-                     skip);
+  hipLaunchKernelGGL(k_coarse_apply, dim3((nc + 3) / 4), dim3(256), 0, st, nc, Cinv, g, a, scale, skip);
 }
 
 void launch_coarse_correct(const DevMesh& m, const double* a, double scale, const double* vin,
@@ -479,16 +588,29 @@ void launch_coarse_correct(const DevMesh& m, const double* a, double scale, cons
                      st, m, a, scale, vin, v, skip);
 }
 
+static int red_grid(const DevMesh& m) {
+  const int64_t b = (m.n_lambda + RED_BLOCK - 1) / RED_BLOCK;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, RED_NBLK));
+}
+
+void launch_correct_dot(const DevMesh& m, const double* a, const double* vin, double* v,
+                        const double* x, double* part, int32_t* counter, double* sc, int32_t* ist,
+                        int phase, hipStream_t st) {
+  hipLaunchKernelGGL(k_correct_dot, dim3(red_grid(m)), dim3(RED_BLOCK), 0, st, m, a, vin, v, x, part,
+                     counter, sc, ist, phase);
+}
+
 void launch_gtg(const DevMesh& m, double* C, int nc, hipStream_t st) {
   if (nc == 0) return;
   const int64_t cnt = (int64_t)nc * nc;
   hipLaunchKernelGGL(k_gtg, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, m, C, nc);
 }
 
-void launch_partials(const DevMesh& m, const double* x, const double* y, const double* nrm,
-                     const double* mdiag, double* part, int nblk, const int32_t* done,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_partials, dim3(nblk), dim3(RED_BLOCK), 0, st, m, x, y, nrm, mdiag, part, done);
+void launch_reduce(const DevMesh& m, const double* x, const double* y, const double* nrm,
+                   const double* mdiag, double* part, int32_t* counter, double* sc, int32_t* ist,
+                   int phase, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(red_grid(m)), dim3(RED_BLOCK), 0, st, m, x, y, nrm, mdiag, part,
+                     counter, sc, ist, phase);
 }
 
 void launch_precond_diag(const DevMesh& m, const double* S, double* mdiag, hipStream_t st) {
@@ -497,17 +619,11 @@ void launch_precond_diag(const DevMesh& m, const double* S, double* mdiag, hipSt
                      m, S, mdiag);
 }
 
-void launch_scalar(const double* part, int nblk, double* sc, int32_t* ist, int phase,
-                   hipStream_t st) {
-  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(64), 0, st, part, nblk, sc, ist, phase);
-}
-
-void launch_cg_lam(int64_t n, const double* sc, const int32_t* ist, const double* p,
-                   const double* qraw, const double* q, double* lam, double* r, double* w,
-                   hipStream_t st) {
-  const int blk = 256;
-  hipLaunchKernelGGL(k_cg_lam, dim3((unsigned)((n + blk - 1) / blk)), dim3(blk), 0, st, n, sc, ist, p,
-                     qraw, q, lam, r, w);
+void launch_cg_lam(const DevMesh& m, const double* p, const double* qraw, const double* q,
+                   double* lam, double* r, double* w, const double* mdiag, double* part,
+                   int32_t* counter, double* sc, int32_t* ist, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_lam, dim3(red_grid(m)), dim3(RED_BLOCK), 0, st, m, p, qraw, q, lam, r, w, mdiag,
+                     part, counter, sc, ist);
 }
 
 void launch_cg_p(int64_t n, const double* sc, const int32_t* ist, const double* y, double* p,

@@ -196,7 +196,7 @@ def test_start_vectors_and_zero_iterations_for_exact_start():
     lam2 = lam.clone()
     st2 = f.solve(fv, lam2, u2, opts(start=B.START_GIVEN))
     assert st1["iters"] > 5
-    assert st2["iters"] <= 1, st2
+    assert st2["iters_first"] <= 1, st2
     assert torch.allclose(lam2, lam, rtol=0, atol=1e-9 * lam.abs().max().item())
     f.close()
 
@@ -204,7 +204,7 @@ def test_start_vectors_and_zero_iterations_for_exact_start():
 def test_not_converged_is_reported_with_iterate():
     w = W.nearly_incompressible_scaled(16, 4)
     f = setup(w)
-    st = f.step(load(w, w.tau), opts(max_it=2, check_every=1, ir_cold=0), allow=(B.ENOTCONV,))
+    st = f.step(load(w, w.tau), opts(max_it=2, check_every=1, ir_cold=0, ir_max=0), allow=(B.ENOTCONV,))
     assert st["rc"] == B.ENOTCONV and st["iters"] == 2
     f.close()
 
@@ -214,7 +214,7 @@ def test_full_size_workload_matches_oracle():
     import time
     import torch
     w = W.nearly_incompressible_large()
-    nsteps = 3
+    nsteps = 4
     t0 = time.time()
     print("[full] oracle ...", flush=True)
     sysm, lats = oracle_reference(w, nsteps)
