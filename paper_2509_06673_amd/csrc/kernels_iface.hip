@@ -163,18 +163,22 @@ __device__ void reduce_and_finalize(double* acc, double* __restrict__ part, int3
 // row-major block is read as row k: for a fixed k the 64 lanes of a wavefront
 // read 64 consecutive entries.  Each workgroup owns 64 output rows; its four
 // wavefronts split the k range and combine in LDS.  x_s is built in LDS.
+// FULL = 1: the full local block (n = n_s, torn vectors); FULL = 0: the interface
+// block (n = n_b, interface-space vectors).  The two are separate kernels so that
+// profiles attribute the local solves and the interface iteration separately.
+template <int FULL>
 __global__ void __launch_bounds__(256) k_sgemv(DevMesh m, GemvArgs a) {
   if (a.skip && *a.skip) return;
   const int s = blockIdx.y;
   const int ns = m.ns[s], nbs = m.nb[s];
-  const int n = a.which_n == 0 ? ns : nbs;
+  const int n = FULL ? ns : nbs;
   const int row0 = blockIdx.x * 64;
   if (row0 >= n) return;
   extern __shared__ double smem[];
   double* xs = smem;              // n
   double* red = smem + m.max_ns;  // 4 x 64
   const int first_b = n - nbs;
-  const int64_t xoff = a.which_n == 0 ? m.soff[s] : m.boff[s];
+  const int64_t xoff = FULL ? m.soff[s] : m.boff[s];
   for (int t = a.kb_only ? first_b + threadIdx.x : threadIdx.x; t < n; t += blockDim.x) {
     double v = a.xbase ? a.xbase[xoff + t] : 0.0;
     if (a.gmode != G_NONE && t >= first_b) v += a.gcoef * gather_b(m, a.v, m.boff[s] + (t - first_b), a.gmode);
@@ -555,9 +559,13 @@ void launch_kind_maxabs(const DevMesh& m, const double* x, const double* y, doub
 }
 
 void launch_sgemv(const DevMesh& m, const GemvArgs& a, hipStream_t st) {
-  const int maxn = a.which_n == 0 ? m.max_ns : m.max_nb;
-  const size_t shm = sizeof(double) * ((size_t)m.max_ns + 4 * 64);
-  hipLaunchKernelGGL(k_sgemv, dim3((maxn + 63) / 64, m.nsub), dim3(256), shm, st, m, a);
+  if (a.which_n == 0) {
+    const size_t shm = sizeof(double) * ((size_t)m.max_ns + 4 * 64);
+    hipLaunchKernelGGL(k_sgemv<1>, dim3((m.max_ns + 63) / 64, m.nsub), dim3(256), shm, st, m, a);
+  } else {
+    const size_t shm = sizeof(double) * ((size_t)m.max_ns + 4 * 64);
+    hipLaunchKernelGGL(k_sgemv<0>, dim3((m.max_nb + 63) / 64, m.nsub), dim3(256), shm, st, m, a);
+  }
 }
 
 void launch_jump(const DevMesh& m, const double* yb, int from_torn, double* out, int scaled,
