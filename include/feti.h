@@ -60,7 +60,10 @@ enum { FETI_XSPLIT = 0, FETI_YSPLIT = 1, FETI_CORE = 2 };
 /* load kinds of feti_load */
 enum { FETI_LOAD_MANUFACTURED = 0, FETI_LOAD_PERIODIC = 1, FETI_LOAD_POINT_SOURCE = 2,
        FETI_LOAD_PATCH = 3 };
-/* precision of the subdomain factors */
+/* precision of the subdomain factors: FP64, or FP32 elimination on the matrix
+ * cores with FP32 storage of K_s^+, S_bb and the interface block, the FP64 torn
+ * residual and FP64 interface vectors, dot products and coarse problem winning
+ * the accuracy back by refinement (feti_solve_opts.ir_*) */
 enum { FETI_FP64 = 0, FETI_FP32_IR = 1 };
 /* preconditioner (Section 3.1 Dirichlet; Section 3.2 lumped) */
 enum { FETI_PRECOND_DIRICHLET = 0, FETI_PRECOND_LUMPED = 1, FETI_PRECOND_NONE = 2 };
@@ -113,6 +116,9 @@ typedef struct {
     int32_t check_every;  /* iterations between host convergence checks (>= 1) */
     int32_t ir_max;       /* refinement corrections on a step with previous multipliers */
     int32_t ir_cold;      /* refinement corrections on a step without them */
+    double tol_inner;     /* with FETI_FP32_IR factors: tolerance of the first solve of a step
+                             (its operators carry FP32 rounding, so a tighter first solve buys
+                             nothing that the FP64 corrections do not redo); 0 = tol */
 } feti_solve_opts;
 
 typedef struct {

@@ -48,7 +48,7 @@ class Load(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("tol_corr", C.c_double), ("ir_tol", C.c_double),
                 ("max_it", C.c_int32), ("start", C.c_int32), ("check_every", C.c_int32),
-                ("ir_max", C.c_int32), ("ir_cold", C.c_int32)]
+                ("ir_max", C.c_int32), ("ir_cold", C.c_int32), ("tol_inner", C.c_double)]
 
 
 class Stats(C.Structure):

@@ -23,6 +23,7 @@
 #include "feti_internal.h"
 #include "iface.h"
 #include "kernels.h"
+#include "pcg.h"
 
 using namespace feti;
 
@@ -48,6 +49,11 @@ struct feti_ctx_s {
   double* Splus = nullptr;  // (K_s^+)_bb
   double* Kbb = nullptr;    // K_bb (lumped preconditioner)
   double* Cinv = nullptr;   // (G^T G)^{-1}
+  double* H = nullptr;      // G (G^T G)^{-1} (small coarse spaces)
+  // FP32 factors (precision FETI_FP32_IR)
+  float* Kinv32 = nullptr;
+  float* Sbb32 = nullptr;
+  float* Splus32 = nullptr;
   int nc = 0;
   // vectors
   double *f = nullptr, *u = nullptr, *ytmp = nullptr, *yb = nullptr, *zb = nullptr;
@@ -66,6 +72,13 @@ struct feti_ctx_s {
   bool have_prev = false, have_prev2 = false;
   hipEvent_t ev[8] = {};
   bool own_stream = false;
+  // persistent PCG: interface GEMV row tiles, grid barrier, partial sums, grid size
+  int32_t* tile_sub = nullptr;
+  int32_t* tile_row0 = nullptr;
+  int ntile = 0;
+  GridBarrier* bar = nullptr;
+  double* ppart = nullptr;
+  int pgrid = 0;
   // captured PCG iteration chunks, keyed by the multiplier buffer they update
   struct Graph {
     hipGraphExec_t exec = nullptr;
@@ -224,6 +237,33 @@ int upload_mesh(feti_ctx ctx) {
   RC(dalloc(ctx, &ctx->part, (size_t)RED_NBLK * NPART, ctx->allocs));
   RC(dalloc(ctx, &ctx->sc, SC_COUNT, ctx->allocs));
   RC(dalloc(ctx, &ctx->ist, IS_COUNT, ctx->allocs));
+  // persistent PCG: 64-row tiles of the interface blocks, barrier, grid size
+  {
+    std::vector<int32_t> ts, tr;
+    for (int s = 0; s < (int)h.subs.size(); ++s)
+      for (int r0 = 0; r0 < h.subs[s].nb; r0 += 64) { ts.push_back(s); tr.push_back(r0); }
+    ctx->ntile = (int)ts.size();
+    if (ts.empty()) { ts.push_back(0); tr.push_back(0); }
+    RC(upload(ctx, &ctx->tile_sub, ts));
+    RC(upload(ctx, &ctx->tile_row0, tr));
+    GridBarrier* bar = nullptr;
+    RC(dalloc(ctx, &bar, 1, ctx->allocs));
+    ctx->bar = bar;
+    HIPCHK(hipMemsetAsync(ctx->bar, 0, sizeof(GridBarrier), ctx->stream));
+    int grid = pcg_max_grid(m);
+    (void)hipGetLastError();  // an unsupported query leaves no sticky error behind
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      grid = std::min(grid, 2 * cus);
+    // one 64-row interface tile per block when the chip holds that many
+    grid = std::min(grid, 192);
+    grid = std::min(grid, PCG_BAR_GROUP * PCG_BAR_MAXGRP);
+    if (const char* e = std::getenv("FETI_PCG_GRID"))
+      grid = std::min({pcg_max_grid(m), std::max(1, std::atoi(e)), PCG_BAR_GROUP * PCG_BAR_MAXGRP});
+    ctx->pgrid = std::max(0, grid);
+    RC(dalloc(ctx, &ctx->ppart, (size_t)2 * std::max(1, ctx->pgrid) * PCG_NPART, ctx->allocs));
+  }
   HIPCHK(hipMemsetAsync(ctx->u, 0, h.sum_ns * sizeof(double), ctx->stream));
   HIPCHK(hipMemsetAsync(ctx->lam_prev, 0, nl * sizeof(double), ctx->stream));
   HIPCHK(hipMemsetAsync(ctx->lam_prev2, 0, nl * sizeof(double), ctx->stream));
@@ -252,7 +292,8 @@ void free_all(feti_ctx ctx) {
   ctx->allocs.clear();
   ctx->mat_allocs.clear();
   ctx->dm = DevMesh();
-  ctx->K = ctx->Kinv = ctx->Sbb = ctx->Splus = ctx->Kbb = ctx->Cinv = nullptr;
+  ctx->K = ctx->Kinv = ctx->Sbb = ctx->Splus = ctx->Kbb = ctx->Cinv = ctx->H = nullptr;
+  ctx->Kinv32 = ctx->Sbb32 = ctx->Splus32 = nullptr;
 }
 
 LoadDev make_load(feti_ctx ctx, const feti_load* L) {
@@ -268,6 +309,18 @@ LoadDev make_load(feti_ctx ctx, const feti_load* L) {
 }
 
 // ---- interface operators ----------------------------------------------------
+
+// the factors of the current precision
+struct Factors {
+  const void* kinv;
+  const void* sbb;
+  const void* splus;
+  int f32;
+};
+Factors factors(feti_ctx ctx) {
+  if (ctx->precision == FETI_FP32_IR) return {ctx->Kinv32, ctx->Sbb32, ctx->Splus32, 1};
+  return {ctx->Kinv, ctx->Sbb, ctx->Splus, 0};
+}
 
 void op_project(feti_ctx ctx, const double* in, double* out, const int32_t* skip) {
   DevMesh& m = ctx->dm;
@@ -285,7 +338,8 @@ void op_project(feti_ctx ctx, const double* in, double* out, const int32_t* skip
 void op_F_raw(feti_ctx ctx, const double* x, double* y, double* g, const int32_t* skip) {
   DevMesh& m = ctx->dm;
   GemvArgs a;
-  a.A = ctx->Splus; a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
+  const Factors fc = factors(ctx);
+  a.A = fc.splus; a.a_f32 = fc.f32; a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
   a.v = x; a.gmode = G_SIGNED; a.gcoef = 1.0; a.y = ctx->yb; a.skip = skip;
   launch_sgemv(m, a, ctx->stream);
   launch_jump(m, ctx->yb, 0, y, 0, g, skip, ctx->stream);
@@ -304,7 +358,9 @@ void op_M_raw(feti_ctx ctx, const double* x, double* y, double* g, const int32_t
     return;
   }
   GemvArgs a;
-  a.A = ctx->precond == FETI_PRECOND_LUMPED ? ctx->Kbb : ctx->Sbb;
+  const Factors fc = factors(ctx);
+  if (ctx->precond == FETI_PRECOND_LUMPED) { a.A = ctx->Kbb; a.a_f32 = 0; }
+  else { a.A = fc.sbb; a.a_f32 = fc.f32; }
   a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
   a.v = x; a.gmode = G_SCALED; a.gcoef = 1.0; a.y = ctx->zb; a.skip = skip;
   launch_sgemv(m, a, ctx->stream);
@@ -351,7 +407,8 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
   // d = sum_s B_s K_s^+ f_s - c
   {
     GemvArgs a;
-    a.A = ctx->Kinv; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
+    const Factors fc = factors(ctx);
+    a.A = fc.kinv; a.a_f32 = fc.f32; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
     a.xbase = f; a.y = ctx->ytmp;
     launch_sgemv(m, a, st);
     launch_jump(m, ctx->ytmp, 1, ctx->d, 0, nullptr, nullptr, st);
@@ -386,14 +443,77 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
   const int chunk = std::max(1, o->check_every);
   static const bool trace = std::getenv("FETI_TRACE") != nullptr;
   static const bool use_graph = std::getenv("FETI_NO_GRAPH") == nullptr;
-  for (;;) {
+  static const bool use_persist = std::getenv("FETI_NO_PERSIST") == nullptr;
+  const bool persist = use_persist && !trace && ctx->pgrid > 0 && ctx->nc <= PCG_NC_LOCAL &&
+                       ctx->precond != FETI_PRECOND_NONE;
+  if (persist) {
+    // every iteration of the solve in one cooperative launch
+    HIPCHK(hipMemcpyAsync(ctx->h_ist, ctx->ist, IS_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (!ctx->h_ist[IS_DONE] && ctx->h_ist[IS_ITERS] < o->max_it) {
+      HIPCHK(hipMemsetAsync(ctx->bar, 0, sizeof(GridBarrier), st));
+      const Factors fc = factors(ctx);
+      PcgArgs pa;
+      pa.m = m;
+      pa.fm = fc.splus; pa.fm32 = fc.f32;
+      if (ctx->precond == FETI_PRECOND_LUMPED) { pa.mm = ctx->Kbb; pa.mm32 = 0; }
+      else { pa.mm = fc.sbb; pa.mm32 = fc.f32; }
+      pa.Cinv = ctx->Cinv; pa.H = ctx->H; pa.nc = ctx->nc;
+      pa.lam = lam; pa.r = ctx->r; pa.w = ctx->w; pa.z = ctx->z; pa.y = ctx->y; pa.p = ctx->p;
+      pa.q = ctx->q; pa.qraw = ctx->qraw; pa.yb = ctx->yb; pa.zb = ctx->zb; pa.g = ctx->g;
+      pa.mdiag = ctx->mdiag; pa.part = ctx->ppart; pa.sc = ctx->sc; pa.ist = ctx->ist; pa.bar = ctx->bar;
+      pa.tile_sub = ctx->tile_sub; pa.tile_row0 = ctx->tile_row0; pa.ntile = ctx->ntile;
+      static const bool ptrace = std::getenv("FETI_PCG_TRACE") != nullptr;
+      long long* ts = nullptr;
+      const int nts = 64;
+      if (ptrace) {
+        HIPCHK(hipMalloc(&ts, nts * 10 * sizeof(long long)));
+        HIPCHK(hipMemsetAsync(ts, 0, nts * 10 * sizeof(long long), st));
+        pa.tstamp = ts; pa.tstamp_iters = nts;
+      }
+      HIPCHK(launch_pcg_persistent(pa, ctx->pgrid, st));
+      if (ptrace) {
+        // stamps per iteration: 0 start, 1..4 after barriers A..D, 5 after the stopping
+        // test, 6..8 after barriers E..G (stamp 0 of a later iteration = stamp 8 before)
+        std::vector<long long> h(nts * 10);
+        HIPCHK(hipMemcpyAsync(h.data(), ts, h.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        (void)hipFree(ts);
+        int rate_khz = 0, dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
+        double sum[9] = {0}; int cnt = 0;
+        for (int it = 0; it < nts; ++it) {
+          if (h[it * 10 + 8] == 0) break;
+          for (int k = 0; k < 8; ++k) {
+            const long long a0 = k > 0 ? h[it * 10 + k] : (it == 0 ? h[0] : h[(it - 1) * 10 + 8]);
+            sum[k] += (double)(h[it * 10 + k + 1] - a0);
+          }
+          ++cnt;
+        }
+        if (cnt > 0 && rate_khz > 0) {
+          std::fprintf(stderr, "[pcg] grid %d, %d iterations, us: A %.2f B %.2f C %.2f D %.2f test %.2f E %.2f F %.2f G %.2f",
+                       ctx->pgrid, cnt, sum[0] / cnt / rate_khz * 1e3, sum[1] / cnt / rate_khz * 1e3,
+                       sum[2] / cnt / rate_khz * 1e3, sum[3] / cnt / rate_khz * 1e3, sum[4] / cnt / rate_khz * 1e3,
+                       sum[5] / cnt / rate_khz * 1e3, sum[6] / cnt / rate_khz * 1e3, sum[7] / cnt / rate_khz * 1e3);
+          std::fprintf(stderr, "\n");
+        }
+      }
+    }
+  }
+  for (; !persist;) {
     HIPCHK(hipMemcpyAsync(ctx->h_ist, ctx->ist, IS_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     if (trace)
       HIPCHK(hipMemcpyAsync(ctx->h_sc, ctx->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (trace)
-      std::fprintf(stderr, "[feti] it %d res %.3e rho %.3e status %d\n", ctx->h_ist[IS_ITERS],
-                   ctx->h_sc[SC_RES], ctx->h_sc[SC_RHO], ctx->h_ist[IS_STATUS]);
+      std::fprintf(stderr,
+                   "[feti] tol %.1e it %d res %.3e rho %.3e status %d energy %.2e kinds %.2e %.2e %.2e "
+                   "%.2e %.2e %.2e\n",
+                   ctx->h_sc[SC_TOL], ctx->h_ist[IS_ITERS], ctx->h_sc[SC_RES], ctx->h_sc[SC_RHO],
+                   ctx->h_ist[IS_STATUS], ctx->h_sc[SC_ERAT], ctx->h_sc[SC_KRAT], ctx->h_sc[SC_KRAT + 1],
+                   ctx->h_sc[SC_KRAT + 2], ctx->h_sc[SC_KRAT + 3], ctx->h_sc[SC_KRAT + 4],
+                   ctx->h_sc[SC_KRAT + 5]);
     if (ctx->h_ist[IS_DONE] || ctx->h_ist[IS_ITERS] >= o->max_it) break;
     // one chunk of iterations, replayed from a captured graph
     feti_ctx_s::Graph* gr = nullptr;
@@ -427,7 +547,8 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
   {
     // K^+ f is already in ytmp (from d): only the interface columns of K^+ are read
     GemvArgs a;
-    a.A = ctx->Kinv; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
+    const Factors fc = factors(ctx);
+    a.A = fc.kinv; a.a_f32 = fc.f32; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
     a.kb_only = 1; a.ybase = ctx->ytmp;
     a.v = lam; a.gmode = G_SIGNED; a.gcoef = -1.0;
     a.y = u; a.alpha_c = ctx->nc > 0 ? ctx->ac : nullptr;
@@ -450,6 +571,7 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
     hipEventElapsedTime(&ms, ctx->ev[3], ctx->ev[4]);
     stats->t_ms[3] += ms;
   }
+  if (status == FETI_EHIP) return fail(ctx, status, "persistent PCG: grid barrier timed out");
   if (status == FETI_ENOTCONV) return fail(ctx, status, "PCG did not converge within max_it");
   if (status == FETI_EBREAKDOWN) return fail(ctx, status, "PCG breakdown");
   if (status == FETI_ENAN) return fail(ctx, status, "non-finite value in the interface iteration");
@@ -474,7 +596,9 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
   hipStream_t st = ctx->stream;
   int iters = 0;
   double res0 = 0, res = 0, r0c = 0, rc_ = 0;
-  int rc = solve_torn(ctx, o, o->tol, ctx->f, nullptr, ctx->lam, ctx->u, stats, &iters, &res0, &res);
+  const double tol_first =
+      (ctx->precision == FETI_FP32_IR && o->tol_inner > 0.0) ? std::max(o->tol, o->tol_inner) : o->tol;
+  int rc = solve_torn(ctx, o, tol_first, ctx->f, nullptr, ctx->lam, ctx->u, stats, &iters, &res0, &res);
   const int iters_first = iters;
   int done_ir = 0;
   double corr = 0.0;
@@ -562,7 +686,9 @@ int build_gj_plan(feti_ctx ctx, GJPlan& P, std::vector<int32_t>& host_flag, int 
   RC(up(&P.snap_at, snap_at));
   RC(up(&P.snap_ld, snap_ld));
   RC(dalloc(ctx, &P.pinv, (size_t)nmat * nb * nb, list));
-  RC(dalloc(ctx, &P.wrow, (size_t)nmat * nb * P.max_n, list));
+  double* wrow = nullptr;  // sized for FP64, enough for either element type
+  RC(dalloc(ctx, &wrow, (size_t)nmat * nb * P.max_n, list));
+  P.wrow = wrow;
   RC(dalloc(ctx, &P.status, nmat, list));
   HIPCHK(hipMemsetAsync(P.status, 0, nmat * sizeof(int32_t), ctx->stream));
   return FETI_OK;
@@ -696,7 +822,8 @@ int feti_assemble(feti_ctx ctx, const feti_material* P, const feti_material* E, 
 int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   if (!ctx) return FETI_EINVAL;
   if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "factor before assemble");
-  if (precision != FETI_FP64) return fail(ctx, FETI_EINVAL, "precision not supported");
+  if (precision != FETI_FP64 && precision != FETI_FP32_IR)
+    return fail(ctx, FETI_EINVAL, "precision not supported");
   if (precond < 0 || precond > 2) return fail(ctx, FETI_EINVAL, "bad preconditioner");
   ctx->precision = precision;
   ctx->precond = precond;
@@ -705,13 +832,20 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   const MeshHost& h = ctx->mh;
   DevMesh& m = ctx->dm;
   const int nsub = m.nsub;
-  if (!ctx->Kinv) {
+  const bool f32 = precision == FETI_FP32_IR;
+  if (!ctx->Kbb) RC(dalloc(ctx, &ctx->Kbb, ctx->s_total, ctx->mat_allocs));
+  if (!f32 && !ctx->Kinv) {
     RC(dalloc(ctx, &ctx->Kinv, ctx->k_total, ctx->mat_allocs));
     RC(dalloc(ctx, &ctx->Sbb, ctx->s_total, ctx->mat_allocs));
     RC(dalloc(ctx, &ctx->Splus, ctx->s_total, ctx->mat_allocs));
-    RC(dalloc(ctx, &ctx->Kbb, ctx->s_total, ctx->mat_allocs));
   }
-  HIPCHK(hipMemcpyAsync(ctx->Kinv, ctx->K, ctx->k_total * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (f32 && !ctx->Kinv32) {
+    RC(dalloc(ctx, &ctx->Kinv32, ctx->k_total, ctx->mat_allocs));
+    RC(dalloc(ctx, &ctx->Sbb32, ctx->s_total, ctx->mat_allocs));
+    RC(dalloc(ctx, &ctx->Splus32, ctx->s_total, ctx->mat_allocs));
+  }
+  if (f32) launch_to_f32(ctx->k_total, ctx->K, ctx->Kinv32, st);
+  else HIPCHK(hipMemcpyAsync(ctx->Kinv, ctx->K, ctx->k_total * sizeof(double), hipMemcpyDeviceToDevice, st));
   // host copies of the per-subdomain geometry of the dense blocks
   std::vector<int> n(nsub), nI(nsub), nsw(nsub);
   std::vector<int64_t> aofs(nsub), sofs(nsub);
@@ -725,23 +859,33 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
     nbv[s] = sh.nb; nIv[s] = sh.nI;
   }
   // lumped preconditioner block K_bb (Section 3.2) from the assembled matrix
-  launch_copy_block(nsub, m.max_nb, m.kofs, m.ld, m.nI, m.sofs, m.ldb, m.nb, ctx->K, ctx->Kbb, st);
+  launch_copy_block(nsub, m.max_nb, m.kofs, m.ld, m.nI, m.sofs, m.ldb, m.nb, (const double*)ctx->K, ctx->Kbb,
+                    st);
   std::vector<void*> tmp;
   GJPlan P;
   std::vector<int32_t> hflag;
   int rc = build_gj_plan(ctx, P, hflag, nsub, n, nI, nsw, aofs, lda, sofs, ldb, 32, tmp);
   if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
-  for (int s = 0; s < P.nsteps; ++s) launch_gj_step(P, ctx->Kinv, ctx->Sbb, s, hflag[s] != 0, st);
   std::vector<int32_t> stat(nsub, 0);
   std::vector<int32_t> nswv(nsw.begin(), nsw.end());
   int32_t* d_nsw = nullptr;
   rc = upload(ctx, &d_nsw, nswv);
   if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
-  launch_gj_finalize(P, ctx->Kinv, d_nsw, st);
-  // weights of the dual-energy residual norm: |diag| of the Dirichlet preconditioner
-  launch_precond_diag(m, ctx->Sbb, ctx->mdiag, st);
-  // (K^+)_bb into the compact interface blocks
-  launch_copy_block(nsub, m.max_nb, m.kofs, m.ld, m.nI, m.sofs, m.ldb, m.nb, ctx->Kinv, ctx->Splus, st);
+  if (f32) {
+    for (int s = 0; s < P.nsteps; ++s) launch_gj_step(P, ctx->Kinv32, ctx->Sbb32, s, hflag[s] != 0, st);
+    launch_gj_finalize(P, ctx->Kinv32, d_nsw, st);
+    launch_precond_diag(m, (const float*)ctx->Sbb32, ctx->mdiag, st);
+    launch_copy_block(nsub, m.max_nb, m.kofs, m.ld, m.nI, m.sofs, m.ldb, m.nb, (const float*)ctx->Kinv32,
+                      ctx->Splus32, st);
+  } else {
+    for (int s = 0; s < P.nsteps; ++s) launch_gj_step(P, ctx->Kinv, ctx->Sbb, s, hflag[s] != 0, st);
+    launch_gj_finalize(P, ctx->Kinv, d_nsw, st);
+    // weights of the dual-energy residual norm: |diag| of the Dirichlet preconditioner
+    launch_precond_diag(m, (const double*)ctx->Sbb, ctx->mdiag, st);
+    // (K^+)_bb into the compact interface blocks
+    launch_copy_block(nsub, m.max_nb, m.kofs, m.ld, m.nI, m.sofs, m.ldb, m.nb, (const double*)ctx->Kinv,
+                      ctx->Splus, st);
+  }
   HIPCHK(hipMemcpyAsync(stat.data(), P.status, nsub * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   for (void* p : tmp) (void)hipFree(p);
@@ -757,7 +901,7 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
     std::vector<void*> ctmp;
     rc = build_gj_plan(ctx, C, cflag, 1, {nc}, {0}, {nc}, {0}, {nc}, {-1}, {nc}, 32, ctmp);
     if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
-    for (int s = 0; s < C.nsteps; ++s) launch_gj_step(C, ctx->Cinv, nullptr, s, false, st);
+    for (int s = 0; s < C.nsteps; ++s) launch_gj_step(C, ctx->Cinv, (double*)nullptr, s, false, st);
     int32_t* d_nc = nullptr;
     std::vector<int32_t> ncv{nc};
     rc = upload(ctx, &d_nc, ncv);
@@ -768,6 +912,10 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
     HIPCHK(hipStreamSynchronize(st));
     for (void* p : ctmp) (void)hipFree(p);
     if (cs) return fail(ctx, FETI_ESINGULAR, "singular coarse matrix G^T G");
+    if (nc <= PCG_NC_LOCAL) {
+      if (!ctx->H) RC(dalloc(ctx, &ctx->H, (size_t)nc * m.n_lambda, ctx->mat_allocs));
+      launch_build_h(m, ctx->Cinv, nc, ctx->H, st);
+    }
   }
   HIPCHK(hipGetLastError());
   ctx->state = 3;
@@ -888,6 +1036,22 @@ int feti_export_local(feti_ctx ctx, int32_t sub, int32_t which, double* out) {
     so += (int64_t)h.subs[s].nb * round8(h.subs[s].nb);
   }
   const SubHost& sh = h.subs[sub];
+  if (which != FETI_EXPORT_K && ctx->precision == FETI_FP32_IR) {
+    // FP32 factors: widen the block to FP64 on the way out
+    const bool sbb = which == FETI_EXPORT_SBB;
+    const int64_t nn = sbb ? sh.nb : sh.ns;
+    const int64_t ldv = round8(nn);
+    const float* src = sbb ? ctx->Sbb32 + so : ctx->Kinv32 + ko;
+    float* tmp32 = nullptr;
+    HIPCHK(hipMalloc(&tmp32, nn * nn * sizeof(float)));
+    hipError_t e = hipMemcpy2DAsync(tmp32, nn * sizeof(float), src, ldv * sizeof(float), nn * sizeof(float), nn,
+                                    hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) launch_to_f64(nn * nn, tmp32, out, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(tmp32);
+    if (e != hipSuccess) return fail(ctx, FETI_EHIP, hipGetErrorString(e));
+    return FETI_OK;
+  }
   if (which == FETI_EXPORT_SBB) {
     HIPCHK(hipMemcpy2DAsync(out, sh.nb * sizeof(double), ctx->Sbb + so, round8(sh.nb) * sizeof(double),
                             sh.nb * sizeof(double), sh.nb, hipMemcpyDeviceToDevice, ctx->stream));
@@ -943,15 +1107,18 @@ int feti_time_kernel(feti_ctx ctx, int32_t which, int32_t reps, double* avg_ms, 
     reps = 1;
   } else {
     GemvArgs a;
+    const Factors fc = factors(ctx);
+    const double esz = fc.f32 ? 4.0 : 8.0;  // bytes per matrix entry; vectors are FP64
+    a.a_f32 = fc.f32;
     if (which == FETI_KERNEL_LOCAL_SOLVE) {
-      a.A = ctx->Kinv; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0; a.xbase = ctx->f; a.y = ctx->ytmp;
-      for (const SubHost& sh : h.subs) w += 8.0 * ((double)sh.ns * sh.ns + 2.0 * sh.ns);
+      a.A = fc.kinv; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0; a.xbase = ctx->f; a.y = ctx->ytmp;
+      for (const SubHost& sh : h.subs) w += esz * sh.ns * sh.ns + 16.0 * sh.ns;
     } else {
-      a.A = which == FETI_KERNEL_IFACE_GEMV ? ctx->Splus : ctx->Sbb;
+      a.A = which == FETI_KERNEL_IFACE_GEMV ? fc.splus : fc.sbb;
       a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1; a.v = ctx->p;
       a.gmode = which == FETI_KERNEL_IFACE_GEMV ? G_SIGNED : G_SCALED; a.gcoef = 1.0;
       a.y = ctx->yb;
-      for (const SubHost& sh : h.subs) w += 8.0 * ((double)sh.nb * sh.nb + 2.0 * sh.nb);
+      for (const SubHost& sh : h.subs) w += esz * sh.nb * sh.nb + 16.0 * sh.nb;
     }
     launch_sgemv(m, a, st);  // warm-up launch
     HIPCHK(hipEventRecord(ctx->ev[6], st));

@@ -15,7 +15,9 @@ enum {
   SC_EREF = 6,  // reference of the dual-energy norm: max(|P d|_M, |w^(0)|_M)
   SC_REF = 8,   // 6 per-kind references max(|P d|_k, |w^(0)|_k)
   SC_EK = 16,   // 6 per-kind reference energies |P d|_{M,k}^2
-  SC_COUNT = 24
+  SC_ERAT = 23, // current dual-energy ratio
+  SC_KRAT = 24, // 6 current per-kind ratios (diagnostics)
+  SC_COUNT = 32
 };
 // device integer slots (IS_CNT0.. : counters of the last-block reductions)
 enum { IS_DONE = 0, IS_ITERS = 1, IS_STATUS = 2, IS_MAXIT = 3, IS_CNT0 = 4, IS_COUNT = 12 };
@@ -48,13 +50,18 @@ void launch_cg_p(int64_t n, const double* sc, const int32_t* ist, const double* 
                  hipStream_t st);
 void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* z,
                   hipStream_t st);
-// diagonal of the preconditioner M^{-1} = D B S B^T D from the S_bb blocks
-void launch_precond_diag(const DevMesh& m, const double* S, double* mdiag, hipStream_t st);
+// diagonal of the preconditioner M^{-1} = D B S B^T D from the S_bb blocks (double or float)
+template <class MT>
+void launch_precond_diag(const DevMesh& m, const MT* S, double* mdiag, hipStream_t st);
 void launch_sub_gather(const DevMesh& m, const double* lam, double* r, hipStream_t st);
 void launch_kind_maxabs(const DevMesh& m, const double* x, const double* y, double* part, int nblk,
                         hipStream_t st);
+// per subdomain: dst block (cnt x cnt) = src block at (src_at, src_at); TS, TD = double or float
+template <class TS, class TD>
 void launch_copy_block(int nsub, int maxn, const int64_t* src_ofs, const int32_t* src_ld,
                        const int32_t* src_at, const int64_t* dst_ofs, const int32_t* dst_ld,
-                       const int32_t* cnt, const double* src, double* dst, hipStream_t st);
+                       const int32_t* cnt, const TS* src, TD* dst, hipStream_t st);
+void launch_to_f32(int64_t n, const double* src, float* dst, hipStream_t st);
+void launch_to_f64(int64_t n, const float* src, double* dst, hipStream_t st);
 
 }  // namespace feti

@@ -83,18 +83,21 @@ struct GJPlan {
   int32_t* snap_at = nullptr;   // first index of the snapshot block
   int32_t* snap_ld = nullptr;
   // workspace
-  double* pinv = nullptr;   // nmat x nb x nb
-  double* wrow = nullptr;   // nmat x nb x max_n
+  double* pinv = nullptr;   // nmat x nb x nb (FP64 for either element type)
+  void* wrow = nullptr;     // nmat x nb x max_n of the element type
   int32_t* status = nullptr;  // per matrix: 0 ok, 1 singular pivot
 };
-void launch_gj_step(const GJPlan& p, double* A, double* snap, int step, bool snap_now,
-                    hipStream_t st);
-void launch_gj_finalize(const GJPlan& p, double* A, const int32_t* nswept, hipStream_t st);
+// T = double (FP64) or float (FP32)
+template <class T>
+void launch_gj_step(const GJPlan& p, T* A, T* snap, int step, bool snap_now, hipStream_t st);
+template <class T>
+void launch_gj_finalize(const GJPlan& p, T* A, const int32_t* nswept, hipStream_t st);
 
 // interface operators: see iface.h
 enum GatherMode { G_NONE = 0, G_SIGNED = 1, G_SCALED = 2 };
 struct GemvArgs {
-  const double* A = nullptr;     // matrix base
+  const void* A = nullptr;       // matrix base (double, or float when a_f32)
+  int a_f32 = 0;
   const int64_t* aofs = nullptr; // per subdomain offset
   const int32_t* lda = nullptr;
   int which_n = 0;               // 0: n = ns (full local), 1: n = nb (interface block)

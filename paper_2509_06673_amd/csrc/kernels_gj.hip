@@ -1,4 +1,4 @@
-// Batched pivot-free symmetric Gauss-Jordan elimination on MFMA (FP64).
+// Batched pivot-free symmetric Gauss-Jordan elimination on MFMA, in FP64 or FP32.
 //
 // Each local matrix K_s is swept pivot block by pivot block in its
 // [interior | interface] order.  Sweeping a pivot block P of
@@ -12,22 +12,46 @@
 // so no pivoting is needed (Theorem 3.1's reduction).
 //
 // The O(n^3) part is the rank-kw update D -= C^T W with W = P^{-1} C, done on
-// v_mfma_f64_16x16x4 tiles: each 64x64 output tile is owned by one workgroup
-// of four wavefronts, each computing a 32x32 quarter as 2x2 MFMA blocks.
+// v_mfma_f64_16x16x4 (FP64) or v_mfma_f32_16x16x4 (FP32) tiles: each 64x64
+// output tile is owned by one workgroup of four wavefronts, each computing a
+// 32x32 quarter as 2x2 MFMA blocks.  In the FP32 variant the small pivot
+// blocks are inverted and W is accumulated in FP64 before rounding to FP32;
+// the update runs in FP32 on the matrix cores.
 #include "kernels.h"
 
 namespace feti {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// One 16x16x4 MFMA per element type.  Operands: lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16].  Result register r of lane l holds column l % 16 and the
+// row given by row() (the two instructions differ; both checked by a lane probe).
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef dbl4 acc4;
+  __device__ static acc4 run(double a, double b, acc4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int r) { return (lane / 16) + 4 * r; }
+};
+template <> struct Mfma<float> {
+  typedef flt4 acc4;
+  __device__ static acc4 run(float a, float b, acc4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
 
 constexpr int GJ_NB = 32;  // maximum panel width (the plan may use less)
 
-// (1) invert the pivot block in LDS by in-place Gauss-Jordan
+// (1) invert the pivot block in LDS by in-place Gauss-Jordan (in FP64)
+template <class T>
 __global__ void __launch_bounds__(256) k_gj_pivot(const int32_t* __restrict__ pstart,
                                                   const int32_t* __restrict__ pwidth,
                                                   const int64_t* __restrict__ aofs,
                                                   const int32_t* __restrict__ lda,
-                                                  const double* __restrict__ A,
+                                                  const T* __restrict__ A,
                                                   double* __restrict__ pinv,
                                                   int32_t* __restrict__ status, int nmat, int step,
                                                   int nb) {
@@ -35,14 +59,14 @@ __global__ void __launch_bounds__(256) k_gj_pivot(const int32_t* __restrict__ ps
   const int kw = pwidth[step * nmat + m];
   if (kw == 0) return;
   const int k0 = pstart[step * nmat + m];
-  const double* Am = A + aofs[m];
+  const T* Am = A + aofs[m];
   const int ld = lda[m];
   __shared__ double M[GJ_NB][GJ_NB + 1];
   __shared__ double rowk[GJ_NB];
   __shared__ double colk[GJ_NB];
   for (int t = threadIdx.x; t < kw * kw; t += blockDim.x) {
     const int i = t / kw, j = t % kw;
-    M[i][j] = Am[(int64_t)(k0 + i) * ld + k0 + j];
+    M[i][j] = (double)Am[(int64_t)(k0 + i) * ld + k0 + j];
   }
   __syncthreads();
   bool bad = false;
@@ -73,15 +97,17 @@ __global__ void __launch_bounds__(256) k_gj_pivot(const int32_t* __restrict__ ps
   }
 }
 
-// (2) W = P^{-1} C over all columns outside the panel (one thread per column)
+// (2) W = P^{-1} C over all columns outside the panel (one thread per column,
+// FP64 accumulation, stored in T)
+template <class T>
 __global__ void __launch_bounds__(256) k_gj_row(const int32_t* __restrict__ pstart,
                                                 const int32_t* __restrict__ pwidth,
                                                 const int64_t* __restrict__ aofs,
                                                 const int32_t* __restrict__ lda,
                                                 const int32_t* __restrict__ nn,
-                                                const double* __restrict__ A,
+                                                const T* __restrict__ A,
                                                 const double* __restrict__ pinv,
-                                                double* __restrict__ wrow, int nmat, int step,
+                                                T* __restrict__ wrow, int nmat, int step,
                                                 int nb, int max_n) {
   const int m = blockIdx.y;
   const int kw = pwidth[step * nmat + m];
@@ -97,28 +123,29 @@ __global__ void __launch_bounds__(256) k_gj_row(const int32_t* __restrict__ psta
   __syncthreads();
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n || (j >= k0 && j < k0 + kw)) return;
-  const double* Am = A + aofs[m];
+  const T* Am = A + aofs[m];
   const int ld = lda[m];
   double c[GJ_NB];
 #pragma unroll
-  for (int k = 0; k < GJ_NB; ++k) c[k] = k < kw ? Am[(int64_t)(k0 + k) * ld + j] : 0.0;
-  double* W = wrow + (int64_t)m * nb * max_n;
+  for (int k = 0; k < GJ_NB; ++k) c[k] = k < kw ? (double)Am[(int64_t)(k0 + k) * ld + j] : 0.0;
+  T* W = wrow + (int64_t)m * nb * max_n;
   for (int i = 0; i < kw; ++i) {
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < GJ_NB; ++k) s += P[i][k] * c[k];
-    W[(int64_t)i * max_n + j] = s;
+    W[(int64_t)i * max_n + j] = (T)s;
   }
 }
 
-// (3) D -= C^T W on 64x64 tiles outside the panel rows and columns (MFMA f64)
+// (3) D -= C^T W on 64x64 tiles outside the panel rows and columns (MFMA)
+template <class T>
 __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ pstart,
                                                    const int32_t* __restrict__ pwidth,
                                                    const int64_t* __restrict__ aofs,
                                                    const int32_t* __restrict__ lda,
                                                    const int32_t* __restrict__ nn,
-                                                   double* __restrict__ A,
-                                                   const double* __restrict__ wrow, int nmat,
+                                                   T* __restrict__ A,
+                                                   const T* __restrict__ wrow, int nmat,
                                                    int step, int nb, int max_n) {
   const int m = blockIdx.z;
   const int kw = pwidth[step * nmat + m];
@@ -129,30 +156,30 @@ __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ p
   const int k0 = pstart[step * nmat + m];
   // tiles fully inside the panel rows or columns have nothing to update
   if ((i0 >= k0 && i0 + 64 <= k0 + kw) || (j0 >= k0 && j0 + 64 <= k0 + kw)) return;
-  double* Am = A + aofs[m];
+  T* Am = A + aofs[m];
   const int ld = lda[m];
-  const double* W = wrow + (int64_t)m * nb * max_n;
-  __shared__ double Ct[GJ_NB][64];  // C[k][i0 + i]
-  __shared__ double Wt[GJ_NB][64];  // W[k][j0 + j]
+  const T* W = wrow + (int64_t)m * nb * max_n;
+  __shared__ T Ct[GJ_NB][64];  // C[k][i0 + i]
+  __shared__ T Wt[GJ_NB][64];  // W[k][j0 + j]
   const int kp = (kw + 3) & ~3;     // padded to the MFMA depth
   for (int t = threadIdx.x; t < kp * 64; t += blockDim.x) {
     const int k = t / 64, x = t % 64;
     const bool kin = k < kw;
     const int i = i0 + x, j = j0 + x;
-    Ct[k][x] = (kin && i < n) ? Am[(int64_t)(k0 + k) * ld + i] : 0.0;
-    Wt[k][x] = (kin && j < n && !(j >= k0 && j < k0 + kw)) ? W[(int64_t)k * max_n + j] : 0.0;
+    Ct[k][x] = (kin && i < n) ? Am[(int64_t)(k0 + k) * ld + i] : T(0);
+    Wt[k][x] = (kin && j < n && !(j >= k0 && j < k0 + kw)) ? W[(int64_t)k * max_n + j] : T(0);
   }
   __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
-  dbl4 acc[2][2];
+  typename Mfma<T>::acc4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 2; ++b) acc[a][b] = typename Mfma<T>::acc4{T(0), T(0), T(0), T(0)};
   const int lr = lane % 16, lk = lane / 16;
   for (int k = 0; k < kp; k += 4) {
-    double av[2], bv[2];
+    T av[2], bv[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) av[a] = Ct[k + lk][wi + a * 16 + lr];
 #pragma unroll
@@ -161,17 +188,15 @@ __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ p
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = Mfma<T>::run(av[a], bv[b], acc[a][b]);
   }
-  // D layout (v_mfma_f64_16x16x4 on gfx950, checked by a lane probe): register r
-  // of a lane holds row (lane / 16) + 4 r, column lane % 16
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wi + a * 16 + (lane / 16) + 4 * r;
+        const int i = i0 + wi + a * 16 + Mfma<T>::row(lane, r);
         const int j = j0 + wj + b * 16 + (lane % 16);
         if (i >= n || j >= n) continue;
         if ((i >= k0 && i < k0 + kw) || (j >= k0 && j < k0 + kw)) continue;
@@ -181,14 +206,15 @@ __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ p
 
 // (4) write the swept panel: rows W, columns W^T, pivot block -P^{-1}; and
 // copy the trailing block at a snapshot step
+template <class T>
 __global__ void __launch_bounds__(256) k_gj_write(const int32_t* __restrict__ pstart,
                                                   const int32_t* __restrict__ pwidth,
                                                   const int64_t* __restrict__ aofs,
                                                   const int32_t* __restrict__ lda,
                                                   const int32_t* __restrict__ nn,
-                                                  double* __restrict__ A,
+                                                  T* __restrict__ A,
                                                   const double* __restrict__ pinv,
-                                                  const double* __restrict__ wrow, int nmat,
+                                                  const T* __restrict__ wrow, int nmat,
                                                   int step, int nb, int max_n) {
   const int m = blockIdx.y;
   const int kw = pwidth[step * nmat + m];
@@ -197,27 +223,28 @@ __global__ void __launch_bounds__(256) k_gj_write(const int32_t* __restrict__ ps
   const int n = nn[m];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  double* Am = A + aofs[m];
+  T* Am = A + aofs[m];
   const int ld = lda[m];
-  const double* W = wrow + (int64_t)m * nb * max_n;
+  const T* W = wrow + (int64_t)m * nb * max_n;
   const double* Pm = pinv + (int64_t)m * nb * nb;
   if (j >= k0 && j < k0 + kw) {
-    for (int i = 0; i < kw; ++i) Am[(int64_t)(k0 + i) * ld + j] = -Pm[i * nb + (j - k0)];
+    for (int i = 0; i < kw; ++i) Am[(int64_t)(k0 + i) * ld + j] = (T)(-Pm[i * nb + (j - k0)]);
   } else {
     for (int i = 0; i < kw; ++i) {
-      const double v = W[(int64_t)i * max_n + j];
+      const T v = W[(int64_t)i * max_n + j];
       Am[(int64_t)(k0 + i) * ld + j] = v;
       Am[(int64_t)j * ld + k0 + i] = v;
     }
   }
 }
 
+template <class T>
 __global__ void k_gj_snapshot(const int32_t* __restrict__ pflag, const int64_t* __restrict__ aofs,
                               const int32_t* __restrict__ lda, const int32_t* __restrict__ nn,
                               const int64_t* __restrict__ snap_ofs,
                               const int32_t* __restrict__ snap_at,
-                              const int32_t* __restrict__ snap_ld, const double* __restrict__ A,
-                              double* __restrict__ snap, int nmat, int step) {
+                              const int32_t* __restrict__ snap_ld, const T* __restrict__ A,
+                              T* __restrict__ snap, int nmat, int step) {
   const int m = blockIdx.y;
   if (!(pflag[step * nmat + m] & 1) || snap_ofs[m] < 0) return;
   const int n = nn[m], at = snap_at[m], nbm = n - at;
@@ -228,40 +255,48 @@ __global__ void k_gj_snapshot(const int32_t* __restrict__ pflag, const int64_t* 
 }
 
 // K^+ = -(swept block), zero on the rows and columns that were not swept
+template <class T>
 __global__ void k_gj_finalize(const int64_t* __restrict__ aofs, const int32_t* __restrict__ lda,
                               const int32_t* __restrict__ nn, const int32_t* __restrict__ nswept,
-                              double* __restrict__ A, int max_n) {
+                              T* __restrict__ A, int max_n) {
   const int m = blockIdx.z;
   const int n = nn[m], ns = nswept[m];
   const int i = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || j >= n) return;
-  double* a = A + aofs[m] + (int64_t)i * lda[m] + j;
-  *a = (i < ns && j < ns) ? -*a : 0.0;
+  T* a = A + aofs[m] + (int64_t)i * lda[m] + j;
+  *a = (i < ns && j < ns) ? -*a : T(0);
 }
 
-void launch_gj_step(const GJPlan& p, double* A, double* snap, int step, bool snap_now,
-                    hipStream_t st) {
-  hipLaunchKernelGGL(k_gj_pivot, dim3(p.nmat), dim3(256), 0, st, p.pstart, p.pwidth, p.aofs, p.lda,
+template <class T>
+void launch_gj_step(const GJPlan& p, T* A, T* snap, int step, bool snap_now, hipStream_t st) {
+  T* wrow = static_cast<T*>(p.wrow);
+  hipLaunchKernelGGL(k_gj_pivot<T>, dim3(p.nmat), dim3(256), 0, st, p.pstart, p.pwidth, p.aofs, p.lda,
                      A, p.pinv, p.status, p.nmat, step, p.nb);
-  hipLaunchKernelGGL(k_gj_row, dim3((p.max_n + 255) / 256, p.nmat), dim3(256), 0, st, p.pstart,
-                     p.pwidth, p.aofs, p.lda, p.n, A, p.pinv, p.wrow, p.nmat, step, p.nb, p.max_n);
+  hipLaunchKernelGGL(k_gj_row<T>, dim3((p.max_n + 255) / 256, p.nmat), dim3(256), 0, st, p.pstart,
+                     p.pwidth, p.aofs, p.lda, p.n, A, p.pinv, wrow, p.nmat, step, p.nb, p.max_n);
   const int nt = (p.max_n + 63) / 64;
-  hipLaunchKernelGGL(k_gj_update, dim3(nt, nt, p.nmat), dim3(256), 0, st, p.pstart, p.pwidth,
-                     p.aofs, p.lda, p.n, A, p.wrow, p.nmat, step, p.nb, p.max_n);
-  hipLaunchKernelGGL(k_gj_write, dim3((p.max_n + 255) / 256, p.nmat), dim3(256), 0, st, p.pstart,
-                     p.pwidth, p.aofs, p.lda, p.n, A, p.pinv, p.wrow, p.nmat, step, p.nb, p.max_n);
+  hipLaunchKernelGGL(k_gj_update<T>, dim3(nt, nt, p.nmat), dim3(256), 0, st, p.pstart, p.pwidth,
+                     p.aofs, p.lda, p.n, A, wrow, p.nmat, step, p.nb, p.max_n);
+  hipLaunchKernelGGL(k_gj_write<T>, dim3((p.max_n + 255) / 256, p.nmat), dim3(256), 0, st, p.pstart,
+                     p.pwidth, p.aofs, p.lda, p.n, A, p.pinv, wrow, p.nmat, step, p.nb, p.max_n);
   if (snap != nullptr && snap_now) {
     const int64_t cnt = (int64_t)p.max_n * p.max_n;
-    hipLaunchKernelGGL(k_gj_snapshot, dim3((unsigned)((cnt + 255) / 256), p.nmat), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_gj_snapshot<T>, dim3((unsigned)((cnt + 255) / 256), p.nmat), dim3(256), 0, st,
                        p.pflag, p.aofs, p.lda, p.n, p.snap_ofs, p.snap_at, p.snap_ld, A, snap,
                        p.nmat, step);
   }
 }
 
-void launch_gj_finalize(const GJPlan& p, double* A, const int32_t* nswept, hipStream_t st) {
-  hipLaunchKernelGGL(k_gj_finalize, dim3((p.max_n + 255) / 256, p.max_n, p.nmat), dim3(256), 0, st,
+template <class T>
+void launch_gj_finalize(const GJPlan& p, T* A, const int32_t* nswept, hipStream_t st) {
+  hipLaunchKernelGGL(k_gj_finalize<T>, dim3((p.max_n + 255) / 256, p.max_n, p.nmat), dim3(256), 0, st,
                      p.aofs, p.lda, p.n, nswept, A, p.max_n);
 }
+
+template void launch_gj_step<double>(const GJPlan&, double*, double*, int, bool, hipStream_t);
+template void launch_gj_step<float>(const GJPlan&, float*, float*, int, bool, hipStream_t);
+template void launch_gj_finalize<double>(const GJPlan&, double*, const int32_t*, hipStream_t);
+template void launch_gj_finalize<float>(const GJPlan&, float*, const int32_t*, hipStream_t);
 
 }  // namespace feti

@@ -7,48 +7,9 @@
 
 #include "kernels.h"
 #include "iface.h"
+#include "iface_device.h"
 
 namespace feti {
-
-// Multiplier-space value gathered onto interface DOF gb.
-__device__ inline double gather_b(const DevMesh& m, const double* __restrict__ v, int64_t gb,
-                                  int mode) {
-  if (mode == G_SIGNED) {
-    double s = 0.0;
-    const int r0 = m.bg_row[2 * gb], r1 = m.bg_row[2 * gb + 1];
-    if (r0 >= 0) s += m.bg_sign[2 * gb] * v[r0];
-    if (r1 >= 0) s += m.bg_sign[2 * gb + 1] * v[r1];
-    return s;
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int r = m.bd_row[3 * gb + k];
-    if (r >= 0) s += m.bd_wt[3 * gb + k] * v[r];
-  }
-  return s;
-}
-
-// Relative residual of the iteration: the largest of the dual-energy ratio
-// |w|_M / ref_M and the per-kind ratios |w_k| / ref_k over the kinds whose
-// reference energy is not negligible (a kind without load data, whose jump
-// only carries rounding, is judged by the energy ratio alone).
-__device__ inline double rel_residual(const double* v, const double* sc) {
-  double etot = 0.0, eref = 0.0;
-  for (int k = 0; k < 6; ++k) {
-    etot += v[8 + k];
-    eref += sc[SC_EK + k];
-  }
-  const double den = sc[SC_EREF];
-  double rel = den > 0.0 ? sqrt(etot) / den : (etot > 0.0 ? 1.0 : 0.0);
-  for (int k = 0; k < 6; ++k) {
-    if (!(sc[SC_EK + k] > 1e-24 * eref)) continue;
-    const double nk = sqrt(v[2 + k]);
-    const double rk = sc[SC_REF + k] > 0.0 ? nk / sc[SC_REF + k] : 0.0;
-    rel = fmax(rel, rk);
-  }
-  return rel;
-}
 
 // Scalar part of one PCG phase from the fully reduced sums v[NPART] (one thread).
 __device__ void scalar_phase(const double* v, double* __restrict__ sc, int32_t* __restrict__ ist,
@@ -97,6 +58,12 @@ __device__ void scalar_phase(const double* v, double* __restrict__ sc, int32_t* 
     }
     case PH_CONV: {
       const double rel = rel_residual(v, sc);
+      double et = 0.0;
+      for (int k = 0; k < 6; ++k) {
+        et += v[8 + k];
+        sc[SC_KRAT + k] = sc[SC_REF + k] > 0.0 ? sqrt(v[2 + k]) / sc[SC_REF + k] : 0.0;
+      }
+      sc[SC_ERAT] = sc[SC_EREF] > 0.0 ? sqrt(et) / sc[SC_EREF] : 0.0;
       sc[SC_RES] = rel;
       ist[IS_ITERS] += 1;
       if (!isfinite(rel)) { ist[IS_STATUS] = FETI_ENAN; ist[IS_DONE] = 1; }
@@ -166,7 +133,9 @@ __device__ void reduce_and_finalize(double* acc, double* __restrict__ part, int3
 // FULL = 1: the full local block (n = n_s, torn vectors); FULL = 0: the interface
 // block (n = n_b, interface-space vectors).  The two are separate kernels so that
 // profiles attribute the local solves and the interface iteration separately.
-template <int FULL>
+// MT is the stored matrix type (double, or float for the FP32 factors); vectors
+// and accumulation are FP64.
+template <int FULL, class MT>
 __global__ void __launch_bounds__(256) k_sgemv(DevMesh m, GemvArgs a) {
   if (a.skip && *a.skip) return;
   const int s = blockIdx.y;
@@ -190,18 +159,27 @@ __global__ void __launch_bounds__(256) k_sgemv(DevMesh m, GemvArgs a) {
   const int k0 = a.kb_only ? first_b : 0;
   const int kq = (n - k0 + 3) / 4;
   const int kb = k0 + wave * kq, ke = min(n, kb + kq);
-  const double* A = a.A + a.aofs[s];
+  const MT* A = static_cast<const MT*>(a.A) + a.aofs[s];
   const int64_t ld = a.lda[s];
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   if (i < n) {
+    // batches of eight independent column loads in flight before their FMAs
+    const MT* col = A + (int64_t)kb * ld + i;
     int k = kb;
-    for (; k + 4 <= ke; k += 4) {
-      acc0 += A[(int64_t)(k + 0) * ld + i] * xs[k + 0];
-      acc1 += A[(int64_t)(k + 1) * ld + i] * xs[k + 1];
-      acc2 += A[(int64_t)(k + 2) * ld + i] * xs[k + 2];
-      acc3 += A[(int64_t)(k + 3) * ld + i] * xs[k + 3];
+    for (; k + 8 <= ke; k += 8, col += 8 * ld) {
+      MT v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = col[(int64_t)u * ld];
+      acc0 += (double)v[0] * xs[k + 0];
+      acc1 += (double)v[1] * xs[k + 1];
+      acc2 += (double)v[2] * xs[k + 2];
+      acc3 += (double)v[3] * xs[k + 3];
+      acc0 += (double)v[4] * xs[k + 4];
+      acc1 += (double)v[5] * xs[k + 5];
+      acc2 += (double)v[6] * xs[k + 6];
+      acc3 += (double)v[7] * xs[k + 7];
     }
-    for (; k < ke; ++k) acc0 += A[(int64_t)k * ld + i] * xs[k];
+    for (; k < ke; ++k, col += ld) acc0 += (double)col[0] * xs[k];
   }
   red[wave * 64 + lane] = (acc0 + acc1) + (acc2 + acc3);
   __syncthreads();
@@ -217,28 +195,6 @@ __global__ void __launch_bounds__(256) k_sgemv(DevMesh m, GemvArgs a) {
     }
     a.y[xoff + i] = yv;
   }
-}
-
-__device__ inline double jump_raw(const DevMesh& m, const double* __restrict__ yb, int from_torn,
-                                  int64_t r) {
-  double s = 0.0;
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int64_t gb = m.jr_b[2 * r + e];
-    const int64_t idx = from_torn ? (int64_t)m.b_torn[gb] : gb;
-    s += m.jr_sign[2 * r + e] * yb[idx];
-  }
-  return s;
-}
-
-// signed jump of row j, or its (B B^T)^{-1}-weighted version over the row's group
-__device__ inline double jump_row(const DevMesh& m, const double* __restrict__ yb, int from_torn,
-                                  int64_t j, int scaled) {
-  if (!scaled) return jump_raw(m, yb, from_torn, j);
-  const int gs = m.grp_start[j], gz = m.grp_size[j];
-  double s = 0.0;
-  for (int k = 0; k < gz; ++k) s += m.dwt[3 * j + k] * jump_raw(m, yb, from_torn, gs + k);
-  return s;
 }
 
 // Blocks [0, nlb): out_j = jump_row(yb).  Blocks [nlb, nlb + n_float) (when g is
@@ -328,19 +284,6 @@ __global__ void __launch_bounds__(256) k_coarse_apply(int nc, const double* __re
   for (int k = lane; k < nc; k += 64) s += Cr[k] * g[k];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) a[row] = scale * s;
-}
-
-__device__ inline double coarse_G_row(const DevMesh& m, const double* __restrict__ a, int64_t j) {
-  double s = 0.0;
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int64_t gb = m.jr_b[2 * j + e];
-    const int f = m.sub_float[m.b_sub[gb]];
-    if (f < 0) continue;
-    const double* R = m.rb + 3 * gb;
-    s += m.jr_sign[2 * j + e] * (R[0] * a[3 * f] + R[1] * a[3 * f + 1] + R[2] * a[3 * f + 2]);
-  }
-  return s;
 }
 
 // v_j = vin_j + scale * (G a)_j, (G a)_j = sum_e sign_e R_b(gb_e) . a_{float(sub(gb_e))}
@@ -433,7 +376,8 @@ __global__ void __launch_bounds__(RED_BLOCK) k_reduce(DevMesh m, const double* _
 }
 
 // M_jj = sum over the interface DOFs b of row j's group of (B^T D)[b, j]^2 S_bb[b, b]
-__global__ void k_precond_diag(DevMesh m, const double* __restrict__ S, double* __restrict__ md) {
+template <class MT>
+__global__ void k_precond_diag(DevMesh m, const MT* __restrict__ S, double* __restrict__ md) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m.n_lambda) return;
   const int gs = m.grp_start[j], gz = m.grp_size[j];
@@ -447,7 +391,7 @@ __global__ void k_precond_diag(DevMesh m, const double* __restrict__ S, double* 
       const int s = m.b_sub[gb];
       const int bl = (int)(gb - m.boff[s]);
       const double wgt = m.bd_wt[3 * gb + slot];
-      acc += wgt * wgt * S[m.sofs[s] + (int64_t)bl * m.ldb[s] + bl];
+      acc += wgt * wgt * (double)S[m.sofs[s] + (int64_t)bl * m.ldb[s] + bl];
     }
   }
   md[j] = acc;
@@ -503,16 +447,17 @@ __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, doubl
 }
 
 // copy a dense block (rows x cols) between leading dimensions, batched
+template <class TS, class TD>
 __global__ void k_copy_block(const int64_t* __restrict__ src_ofs, const int32_t* __restrict__ src_ld,
                              const int32_t* __restrict__ src_at, const int64_t* __restrict__ dst_ofs,
                              const int32_t* __restrict__ dst_ld, const int32_t* __restrict__ cnt,
-                             const double* __restrict__ src, double* __restrict__ dst) {
+                             const TS* __restrict__ src, TD* __restrict__ dst) {
   const int s = blockIdx.y;
   const int nbs = cnt[s], at = src_at[s];
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)nbs * nbs) return;
   const int i = (int)(t / nbs), j = (int)(t % nbs);
-  dst[dst_ofs[s] + (int64_t)i * dst_ld[s] + j] = src[src_ofs[s] + (int64_t)(at + i) * src_ld[s] + at + j];
+  dst[dst_ofs[s] + (int64_t)i * dst_ld[s] + j] = (TD)src[src_ofs[s] + (int64_t)(at + i) * src_ld[s] + at + j];
 }
 
 // r_b -= B_s^T lam on every interface DOF (torn vector r)
@@ -559,12 +504,15 @@ void launch_kind_maxabs(const DevMesh& m, const double* x, const double* y, doub
 }
 
 void launch_sgemv(const DevMesh& m, const GemvArgs& a, hipStream_t st) {
+  const size_t shm = sizeof(double) * ((size_t)m.max_ns + 4 * 64);
   if (a.which_n == 0) {
-    const size_t shm = sizeof(double) * ((size_t)m.max_ns + 4 * 64);
-    hipLaunchKernelGGL(k_sgemv<1>, dim3((m.max_ns + 63) / 64, m.nsub), dim3(256), shm, st, m, a);
+    const dim3 grid((m.max_ns + 63) / 64, m.nsub);
+    if (a.a_f32) hipLaunchKernelGGL((k_sgemv<1, float>), grid, dim3(256), shm, st, m, a);
+    else hipLaunchKernelGGL((k_sgemv<1, double>), grid, dim3(256), shm, st, m, a);
   } else {
-    const size_t shm = sizeof(double) * ((size_t)m.max_ns + 4 * 64);
-    hipLaunchKernelGGL(k_sgemv<0>, dim3((m.max_nb + 63) / 64, m.nsub), dim3(256), shm, st, m, a);
+    const dim3 grid((m.max_nb + 63) / 64, m.nsub);
+    if (a.a_f32) hipLaunchKernelGGL((k_sgemv<0, float>), grid, dim3(256), shm, st, m, a);
+    else hipLaunchKernelGGL((k_sgemv<0, double>), grid, dim3(256), shm, st, m, a);
   }
 }
 
@@ -621,11 +569,14 @@ void launch_reduce(const DevMesh& m, const double* x, const double* y, const dou
                      counter, sc, ist, phase);
 }
 
-void launch_precond_diag(const DevMesh& m, const double* S, double* mdiag, hipStream_t st) {
+template <class MT>
+void launch_precond_diag(const DevMesh& m, const MT* S, double* mdiag, hipStream_t st) {
   const int blk = 256;
-  hipLaunchKernelGGL(k_precond_diag, dim3((unsigned)((m.n_lambda + blk - 1) / blk)), dim3(blk), 0, st,
-                     m, S, mdiag);
+  hipLaunchKernelGGL(k_precond_diag<MT>, dim3((unsigned)((m.n_lambda + blk - 1) / blk)), dim3(blk), 0,
+                     st, m, S, mdiag);
 }
+template void launch_precond_diag<double>(const DevMesh&, const double*, double*, hipStream_t);
+template void launch_precond_diag<float>(const DevMesh&, const float*, double*, hipStream_t);
 
 void launch_cg_lam(const DevMesh& m, const double* p, const double* qraw, const double* q,
                    double* lam, double* r, double* w, const double* mdiag, double* part,
@@ -646,12 +597,40 @@ void launch_axpby(int64_t n, double a, const double* x, double b, const double* 
   hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + blk - 1) / blk)), dim3(blk), 0, st, n, a, x, b, y, z);
 }
 
+template <class TS, class TD>
 void launch_copy_block(int nsub, int maxn, const int64_t* src_ofs, const int32_t* src_ld,
                        const int32_t* src_at, const int64_t* dst_ofs, const int32_t* dst_ld,
-                       const int32_t* cnt, const double* src, double* dst, hipStream_t st) {
+                       const int32_t* cnt, const TS* src, TD* dst, hipStream_t st) {
   const int64_t c = (int64_t)maxn * maxn;
-  hipLaunchKernelGGL(k_copy_block, dim3((unsigned)((c + 255) / 256), nsub), dim3(256), 0, st, src_ofs,
-                     src_ld, src_at, dst_ofs, dst_ld, cnt, src, dst);
+  hipLaunchKernelGGL((k_copy_block<TS, TD>), dim3((unsigned)((c + 255) / 256), nsub), dim3(256), 0, st,
+                     src_ofs, src_ld, src_at, dst_ofs, dst_ld, cnt, src, dst);
+}
+template void launch_copy_block<double, double>(int, int, const int64_t*, const int32_t*, const int32_t*,
+                                                const int64_t*, const int32_t*, const int32_t*,
+                                                const double*, double*, hipStream_t);
+template void launch_copy_block<float, float>(int, int, const int64_t*, const int32_t*, const int32_t*,
+                                              const int64_t*, const int32_t*, const int32_t*,
+                                              const float*, float*, hipStream_t);
+
+// dst = (float) src, n elements
+__global__ void k_to_f32(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
+void launch_to_f32(int64_t n, const double* src, float* dst, hipStream_t st) {
+  const int blk = 256;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + blk - 1) / blk)), dim3(blk), 0, st, n, src, dst);
+}
+
+__global__ void k_to_f64(int64_t n, const float* __restrict__ src, double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (double)src[i];
+}
+
+void launch_to_f64(int64_t n, const float* src, double* dst, hipStream_t st) {
+  const int blk = 256;
+  hipLaunchKernelGGL(k_to_f64, dim3((unsigned)((n + blk - 1) / blk)), dim3(blk), 0, st, n, src, dst);
 }
 
 }  // namespace feti

@@ -1,0 +1,491 @@
+// Persistent projected PCG on F lambda = d (Section 3, Algorithms 1 and 2, with the
+// FETI-1 projection and the Dirichlet preconditioner of eq.
+// (feti_dirichlet_preconditioner)).
+//
+// One cooperative launch runs every iteration of a solve (instead of a chain of
+// about ten dependent kernels per iteration).  An iteration is seven grid-wide
+// phases separated by barriers:
+//   A  y_b = (K_s^+)_bb B_s^T p      per 64-row tile, p = y + beta p_old formed on the fly
+//   B  q_raw = sum_s B_s y_b, g = G^T q_raw
+//   C  q = q_raw - G (G^T G)^{-1} g, partial sums of (p, q)      -> alpha in every block
+//   D  lam += alpha p, r -= alpha q_raw, w -= alpha q, p_old = p, residual norms
+//                                                                 -> stopping test in every block
+//   E  z_b = S_bb (B_s^T D w)
+//   F  z = D sum_s B_s z_b, g = G^T z
+//   G  y = z - G (G^T G)^{-1} g, partial sums of (w, y)          -> beta in every block
+// The scalars of a phase are reduced by every block from the same per-block
+// partials in the same order, so all blocks take identical decisions and leave
+// the loop together.  Consecutive reductions alternate between two partial
+// buffers: a buffer is rewritten only after a further barrier, which every
+// block passes only once it has read the buffer.  The coarse solve
+// (G^T G)^{-1} g is applied redundantly by each block that owns multiplier rows
+// (n_c is small).  Reductions are deterministic: fixed wave and block order.
+//
+// The barrier spins with a bound: a block that waits too long raises the abort
+// flag, every block leaves at its next barrier, and the host reports an error.
+#include <algorithm>
+
+#include "iface.h"
+#include "iface_device.h"
+#include "kernels.h"
+#include "pcg.h"
+
+namespace feti {
+
+constexpr int PB = PCG_BLOCK;
+constexpr long long PCG_SPIN_LIMIT = 1ll << 21;
+
+// Data that one block writes and another reads within the launch (the multiplier
+// vectors p, y, w, q, q_raw, z, the interface-space vectors, g and the partial
+// sums) moves through device-coherent
+// loads and stores (agent-scope relaxed atomics: no cache flush is needed);
+// everything a thread reads back only itself, and the read-only matrices, use
+// plain accesses.
+__device__ inline double ald(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void ast(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide barrier; returns false when the launch is being aborted.  Arrival
+// counters only grow (the host clears them before a launch): a group's counter
+// reaches (k + 1) * group size at barrier k, its last block then counts the group
+// at the top level, and the last group publishes gen = k + 1.
+// Every thread waits for its own stores to complete before its block arrives.
+__device__ bool grid_sync(GridBarrier* b, uint32_t nblk, uint32_t& gen, int* s_ok) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // two levels: groups of PCG_BAR_GROUP blocks, then the groups
+    const uint32_t grp = blockIdx.x / PCG_BAR_GROUP;
+    const uint32_t ngrp = (nblk + PCG_BAR_GROUP - 1) / PCG_BAR_GROUP;
+    const uint32_t gsize = min((uint32_t)PCG_BAR_GROUP, nblk - grp * PCG_BAR_GROUP);
+    int ok = 1;
+    bool last = false;
+    const uint32_t p1 =
+        __hip_atomic_fetch_add(&b->grp[grp * PCG_BAR_STRIDE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p1 == (gen + 1) * gsize - 1) {
+      const uint32_t p2 = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = p2 == (gen + 1) * ngrp - 1;
+    }
+    if (last) {
+      __hip_atomic_store(&b->gen, gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long long spins = 0;
+      while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= gen) {
+        if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+        if (++spins > PCG_SPIN_LIMIT) {
+          __hip_atomic_store(&b->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    gen += 1;
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+// jump of row j of the interface-space vector yb (signed sum of its two entries)
+__device__ inline double pjump_raw(const DevMesh& m, const double* yb, int64_t r) {
+  return m.jr_sign[2 * r] * ald(yb + m.jr_b[2 * r]) + m.jr_sign[2 * r + 1] * ald(yb + m.jr_b[2 * r + 1]);
+}
+__device__ inline double pjump_row(const DevMesh& m, const double* yb, int64_t j, int scaled) {
+  if (!scaled) return pjump_raw(m, yb, j);
+  const int gs = m.grp_start[j], gz = m.grp_size[j];
+  double s = 0.0;
+  for (int k = 0; k < gz; ++k) s += m.dwt[3 * j + k] * pjump_raw(m, yb, gs + k);
+  return s;
+}
+
+// Deterministic block-wide sums of v[0..NV); the result is valid in every thread.
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    double x = v[c];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    v[c] = x;
+  }
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) red[wave * NV + c] = v[c];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    double s = 0.0;
+    for (int wv = 0; wv < PB / 64; ++wv) s += red[wv * NV + c];
+    v[c] = s;
+  }
+  __syncthreads();
+}
+
+// Sum of the per-block partials part[b][0..NV) over all blocks, in block order.
+template <int NV>
+__device__ void grid_total(const double* part, int nblk, double (&v)[NV], double* red) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) v[c] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += PB)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] += ald(part + b * PCG_NPART + c);
+  block_sum<NV>(v, red);
+}
+
+// Phases A and E: yout_b = A_s x_b for every 64-row tile of every interface block.
+// SCALED = 0: x_b = B_s^T p with p = src + beta src2; SCALED = 1: x_b = B_s^T D src.
+// Each half of the block (four wavefronts) takes one tile; its wavefronts split the
+// column range and combine in LDS.
+template <class MT, int SCALED>
+__device__ void gemv_phase(const PcgArgs& a, const MT* A, const double* src, const double* src2,
+                           double beta, double* yout, double* xs2, double* red8) {
+  const DevMesh& m = a.m;
+  const int half = threadIdx.x / 256, ht = threadIdx.x % 256;
+  const int wave = ht >> 6, lane = ht & 63;
+  double* xs = xs2 + half * m.max_nb;
+  double* red4 = red8 + half * 256;
+  for (int t2 = blockIdx.x; 2 * t2 < a.ntile; t2 += gridDim.x) {
+    const int t = 2 * t2 + half;
+    const bool valid = t < a.ntile;
+    const int s = valid ? a.tile_sub[t] : 0, row0 = valid ? a.tile_row0[t] : 0;
+    const int nbs = valid ? m.nb[s] : 0;
+    const int64_t b0 = m.boff[s];
+    __syncthreads();  // xs and red4 of the previous tiles are consumed
+    for (int i = ht; i < nbs; i += 256) {
+      const int64_t gb = b0 + i;
+      double v = 0.0;
+      // branch-free: an absent entry reads row 0 with weight 0, so that all loads
+      // of the gather are in flight together
+      if (SCALED) {
+        int r[3];
+        double wt[3], x[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int rk = m.bd_row[3 * gb + k];
+          r[k] = rk >= 0 ? rk : 0;
+          wt[k] = rk >= 0 ? m.bd_wt[3 * gb + k] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) x[k] = ald(src + r[k]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v += wt[k] * x[k];
+      } else {
+        const int q0 = m.bg_row[2 * gb], q1 = m.bg_row[2 * gb + 1];
+        const int r0 = q0 >= 0 ? q0 : 0, r1 = q1 >= 0 ? q1 : 0;
+        const double s0 = q0 >= 0 ? m.bg_sign[2 * gb] : 0.0, s1 = q1 >= 0 ? m.bg_sign[2 * gb + 1] : 0.0;
+        const double y0 = ald(src + r0), p0 = ald(src2 + r0), y1 = ald(src + r1), p1 = ald(src2 + r1);
+        v = s0 * (y0 + beta * p0);
+        v += s1 * (y1 + beta * p1);
+      }
+      xs[i] = v;
+    }
+    __syncthreads();
+    const int i = row0 + lane;
+    const int kq = (nbs + 3) / 4;
+    const int kb = wave * kq, ke = min(nbs, kb + kq);
+    const MT* As = A + m.sofs[s];
+    const int64_t ld = m.ldb[s];
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    if (i < nbs) {
+      // batches of eight independent column loads in flight before their FMAs
+      const MT* col = As + (int64_t)kb * ld + i;
+      int k = kb;
+      for (; k + 8 <= ke; k += 8, col += 8 * ld) {
+        MT v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = col[(int64_t)u * ld];
+        acc0 += (double)v[0] * xs[k + 0];
+        acc1 += (double)v[1] * xs[k + 1];
+        acc2 += (double)v[2] * xs[k + 2];
+        acc3 += (double)v[3] * xs[k + 3];
+        acc0 += (double)v[4] * xs[k + 4];
+        acc1 += (double)v[5] * xs[k + 5];
+        acc2 += (double)v[6] * xs[k + 6];
+        acc3 += (double)v[7] * xs[k + 7];
+      }
+      for (; k < ke; ++k, col += ld) acc0 += (double)col[0] * xs[k];
+    }
+    red4[wave * 64 + lane] = (acc0 + acc1) + (acc2 + acc3);
+    __syncthreads();
+    if (wave == 0 && i < nbs)
+      ast(yout + b0 + i, (red4[lane] + red4[64 + lane]) + (red4[128 + lane] + red4[192 + lane]));
+  }
+}
+
+// Phases B and F: out_j = (scaled) jump of yb; g_f = R_s^T B_s^T out for the
+// floating subdomains (when there is a coarse space).
+__device__ void jump_phase(const PcgArgs& a, const double* yb, double* out, int scaled, double* red) {
+  const DevMesh& m = a.m;
+  const int64_t NL = m.n_lambda;
+  const int nlb = (int)((NL + PB - 1) / PB);
+  const int nitems = nlb + (a.nc > 0 ? m.n_float : 0);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    if (it < nlb) {
+      const int64_t j = (int64_t)it * PB + threadIdx.x;
+      if (j < NL) ast(out + j, pjump_row(m, yb, j, scaled));
+      continue;
+    }
+    const int f = it - nlb;
+    const int s = m.float_sub[f];
+    const int nbs = m.nb[s];
+    const int64_t b0 = m.boff[s];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nbs; i += PB) {
+      const int64_t gb = b0 + i;
+      double v = 0.0;
+      for (int slot = 0; slot < 2; ++slot) {
+        const int r = m.bg_row[2 * gb + slot];
+        if (r >= 0) v += m.bg_sign[2 * gb + slot] * pjump_row(m, yb, r, scaled);
+      }
+      const double* R = m.rb + 3 * gb;
+      acc[0] += R[0] * v;
+      acc[1] += R[1] * v;
+      acc[2] += R[2] * v;
+    }
+    block_sum<3>(acc, red);
+    if (threadIdx.x < 3) ast(a.g + 3 * f + threadIdx.x, acc[threadIdx.x]);
+  }
+}
+
+// Phases C and G: vout = vin - G (G^T G)^{-1} g and this block's partial of (x, vout),
+// x_j = x1_j + xbeta x2_j (x2 may be null).  With H = G (G^T G)^{-1} precomputed the
+// correction is one coalesced pass; otherwise (G^T G)^{-1} g is formed in LDS and
+// the rows of G are evaluated from the index tables.
+__device__ void correct_dot_phase(const PcgArgs& a, const double* vin, double* vout, const double* x1, const double* x2, double xbeta, double* part, double* acl,
+                                  double* red4, double* red) {
+  const DevMesh& m = a.m;
+  const int64_t NL = m.n_lambda;
+  const int64_t first = (int64_t)blockIdx.x * PB;
+  double acc[1] = {0.0};
+  if (a.H) {
+    // q_j = vin_j - sum_c H[c][j] g_c, H = G (G^T G)^{-1} (coarse-index major): each
+    // block takes 64-row chunks, its four wavefronts split the coarse index
+    if ((int64_t)blockIdx.x * 64 < NL) {
+      double* gl = acl + PCG_NC_LOCAL;
+      for (int k = threadIdx.x; k < a.nc; k += PB) gl[k] = ald(a.g + k);
+      __syncthreads();
+      constexpr int NW = PB / 64;
+      const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+      const int cq = (a.nc + NW - 1) / NW, cb = wave * cq, ce = min(a.nc, cb + cq);
+      for (int64_t j0 = (int64_t)blockIdx.x * 64; j0 < NL; j0 += (int64_t)gridDim.x * 64) {
+        const int64_t j = j0 + lane;
+        double c0 = 0.0, c1 = 0.0;
+        if (j < NL) {
+          int c = cb;
+          for (; c + 2 <= ce; c += 2) {
+            c0 += a.H[(int64_t)c * NL + j] * gl[c];
+            c1 += a.H[(int64_t)(c + 1) * NL + j] * gl[c + 1];
+          }
+          if (c < ce) c0 += a.H[(int64_t)c * NL + j] * gl[c];
+        }
+        red4[wave * 64 + lane] = c0 + c1;
+        __syncthreads();
+        if (wave == 0 && j < NL) {
+          double corr = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) corr += red4[w * 64 + lane];
+          const double vj = ald(vin + j) - corr;
+          ast(vout + j, vj);
+          const double xj = x2 ? ald(x1 + j) + xbeta * ald(x2 + j) : ald(x1 + j);
+          acc[0] += xj * vj;
+        }
+        __syncthreads();
+      }
+    }
+  } else if (first < NL) {
+    if (a.nc > 0) {
+      // ac = Cinv g: g staged in LDS, one thread per row; Cinv is symmetric, so row t
+      // is read as column t (consecutive threads, consecutive addresses)
+      double* gl = acl + PCG_NC_LOCAL;
+      for (int k = threadIdx.x; k < a.nc; k += PB) gl[k] = ald(a.g + k);
+      __syncthreads();
+      for (int t = threadIdx.x; t < a.nc; t += PB) {
+        double s0 = 0.0, s1 = 0.0;
+        int k = 0;
+        for (; k + 2 <= a.nc; k += 2) {
+          s0 += a.Cinv[(int64_t)k * a.nc + t] * gl[k];
+          s1 += a.Cinv[(int64_t)(k + 1) * a.nc + t] * gl[k + 1];
+        }
+        if (k < a.nc) s0 += a.Cinv[(int64_t)k * a.nc + t] * gl[k];
+        acl[t] = s0 + s1;
+      }
+      __syncthreads();
+    }
+    for (int64_t j = first + threadIdx.x; j < NL; j += (int64_t)gridDim.x * PB) {
+      const double vj = ald(vin + j) - (a.nc > 0 ? coarse_G_row(m, acl, j) : 0.0);
+      ast(vout + j, vj);
+      const double xj = x2 ? ald(x1 + j) + xbeta * ald(x2 + j) : ald(x1 + j);
+      acc[0] += xj * vj;
+    }
+  }
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) ast(part + blockIdx.x * PCG_NPART, acc[0]);
+}
+
+__global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
+  extern __shared__ double lds[];
+  __shared__ int s_ok;
+  const DevMesh& m = a.m;
+  double* xs = lds;                          // 2 x max_nb gathered vectors (one per tile)
+  double* red4 = xs + 2 * m.max_nb;          // PB partial rows
+  double* acl = red4 + PB;                   // coarse coefficients, then g (2 x PCG_NC_LOCAL)
+  double* red = acl + 2 * PCG_NC_LOCAL;
+  const int nblk = gridDim.x;
+  const int64_t NL = m.n_lambda;
+  uint32_t gen = 0;  // the host clears the barrier before the launch
+
+  const double tol = a.sc[SC_TOL];
+  double rho = a.sc[SC_RHO], beta = a.sc[SC_BETA], alpha = a.sc[SC_ALPHA], res = a.sc[SC_RES];
+  int iters = a.ist[IS_ITERS];
+  const int maxit = a.ist[IS_MAXIT];
+  int status = 0;
+  bool ok = true;
+  int rk = 0;  // reductions so far: partial buffer rk & 1
+  auto partbuf = [&](int k) { return a.part + (size_t)(k & 1) * nblk * PCG_NPART; };
+  double conv[7] = {0, 0, 0, 0, 0, 0, 0};
+  int it_local = 0, ph = 0;
+  auto stamp = [&]() {
+    if (a.tstamp && blockIdx.x == 0 && threadIdx.x == 0 && it_local < a.tstamp_iters)
+      a.tstamp[it_local * 10 + ph] = (long long)wall_clock64();
+    ++ph;
+  };
+  stamp();
+  for (;; ++it_local, ph = 1) {  // stamp 0 of a later iteration is stamp 8 of the one before
+    // (A) y_b = (K^+)_bb B^T p,  p = y + beta p_old
+    if (a.fm32) gemv_phase<float, 0>(a, (const float*)a.fm, a.y, a.p, beta, a.yb, xs, red4);
+    else gemv_phase<double, 0>(a, (const double*)a.fm, a.y, a.p, beta, a.yb, xs, red4);
+    if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
+    stamp();
+    // (B) q_raw = B y_b, g = G^T q_raw
+    jump_phase(a, a.yb, a.qraw, 0, red);
+    if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
+    stamp();
+    // (C) q = P q_raw, partial (p, q)
+    correct_dot_phase(a, a.qraw, a.q, a.y, a.p, beta, partbuf(rk), acl, red4, red);
+    if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
+    stamp();
+    {
+      double t[1];
+      grid_total<1>(partbuf(rk++), nblk, t, red);
+      const double pq = t[0];
+      if (!(fabs(pq) > 1e-300) || !isfinite(pq)) {
+        status = isfinite(pq) ? FETI_EBREAKDOWN : FETI_ENAN;
+        alpha = 0.0;
+        break;
+      }
+      alpha = rho / pq;
+    }
+    // (D) updates and the norms of w
+    {
+      double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+      for (int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x; j < NL; j += (int64_t)nblk * PB) {
+        const double pj = ald(a.y + j) + beta * ald(a.p + j);
+        a.lam[j] += alpha * pj;
+        a.r[j] -= alpha * ald(a.qraw + j);
+        const double wn = ald(a.w + j) - alpha * ald(a.q + j);
+        ast(a.w + j, wn);
+        ast(a.p + j, pj);
+        const double v2 = wn * wn;
+        const int k = m.row_kind[j];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] += (c == k) ? v2 : 0.0;
+        acc[6] += fabs(a.mdiag[j]) * v2;
+      }
+      block_sum<7>(acc, red);
+      if (threadIdx.x < 7) ast(partbuf(rk) + blockIdx.x * PCG_NPART + threadIdx.x, acc[threadIdx.x]);
+    }
+    if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
+    stamp();
+    {
+      grid_total<7>(partbuf(rk++), nblk, conv, red);
+      double v[NPART];
+      for (int c = 0; c < NPART; ++c) v[c] = 0.0;
+      for (int k = 0; k < 6; ++k) v[2 + k] = conv[k];
+      v[8] = conv[6];
+      res = rel_residual(v, a.sc);
+      iters += 1;
+      if (!isfinite(res)) { status = FETI_ENAN; break; }
+      if (res <= tol) break;
+      if (iters >= maxit) { status = FETI_ENOTCONV; break; }
+    }
+    stamp();
+    // (E) z_b = S_bb (B^T D w)
+    if (a.mm32) gemv_phase<float, 1>(a, (const float*)a.mm, a.w, nullptr, 0.0, a.zb, xs, red4);
+    else gemv_phase<double, 1>(a, (const double*)a.mm, a.w, nullptr, 0.0, a.zb, xs, red4);
+    if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
+    stamp();
+    // (F) z = D B z_b, g = G^T z
+    jump_phase(a, a.zb, a.z, 1, red);
+    if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
+    stamp();
+    // (G) y = P z, partial (w, y)
+    correct_dot_phase(a, a.z, a.y, a.w, nullptr, 0.0, partbuf(rk), acl, red4, red);
+    if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
+    stamp();
+    {
+      double t[1];
+      grid_total<1>(partbuf(rk++), nblk, t, red);
+      if (!(fabs(rho) > 1e-300)) { status = FETI_EBREAKDOWN; break; }
+      beta = t[0] / rho;
+      rho = t[0];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.sc[SC_RHO] = rho;
+    a.sc[SC_ALPHA] = alpha;
+    a.sc[SC_BETA] = beta;
+    a.sc[SC_RES] = res;
+    double et = 0.0;
+    for (int k = 0; k < 6; ++k) {
+      a.sc[SC_KRAT + k] = a.sc[SC_REF + k] > 0.0 ? sqrt(conv[k]) / a.sc[SC_REF + k] : 0.0;
+    }
+    et = conv[6];
+    a.sc[SC_ERAT] = a.sc[SC_EREF] > 0.0 ? sqrt(et) / a.sc[SC_EREF] : 0.0;
+    a.ist[IS_ITERS] = iters;
+    a.ist[IS_STATUS] = ok ? status : FETI_EHIP;
+    a.ist[IS_DONE] = 1;
+  }
+}
+
+// H[c][j] = (G (G^T G)^{-1})_{j c}: row c of the symmetric Cinv is its column c
+__global__ void k_build_h(DevMesh m, const double* __restrict__ Cinv, int nc, double* __restrict__ H) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (j >= m.n_lambda) return;
+  H[(int64_t)c * m.n_lambda + j] = coarse_G_row(m, Cinv + (int64_t)c * nc, j);
+}
+
+void launch_build_h(const DevMesh& m, const double* Cinv, int nc, double* H, hipStream_t st) {
+  if (nc == 0) return;
+  hipLaunchKernelGGL(k_build_h, dim3((unsigned)((m.n_lambda + 255) / 256), nc), dim3(256), 0, st, m, Cinv, nc, H);
+}
+
+size_t pcg_shmem(const DevMesh& m) {
+  return sizeof(double) * (2 * (size_t)m.max_nb + PB + 2 * PCG_NC_LOCAL + (PB / 64) * PCG_NPART);
+}
+
+int pcg_max_grid(const DevMesh& m) {
+  int dev = 0, coop = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg_persistent, PB, pcg_shmem(m)) != hipSuccess)
+    return 0;
+  return std::max(0, per_cu) * cus;
+}
+
+hipError_t launch_pcg_persistent(const PcgArgs& a, int grid, hipStream_t st) {
+  PcgArgs arg = a;
+  void* params[] = {&arg};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_pcg_persistent), dim3(grid), dim3(PB),
+                                    params, (unsigned)pcg_shmem(a.m), st);
+}
+
+}  // namespace feti

@@ -1,0 +1,59 @@
+// Persistent projected PCG (kernels_pcg.hip): one cooperative launch runs the
+// iterations of an interface solve, with grid-wide barriers between the phases
+// of an iteration instead of kernel boundaries.
+#pragma once
+
+#include "kernels.h"
+
+namespace feti {
+
+// Grid barrier state (device memory, zero-initialised).  gen counts completed
+// barriers; abort is raised by a block whose wait exceeds the spin limit, and
+// every block then leaves the launch at its next barrier.
+constexpr int PCG_BAR_GROUP = 16;    // blocks per first-level arrival counter
+constexpr int PCG_BAR_STRIDE = 64;   // uint32 words between counters (own 256-byte line)
+constexpr int PCG_BAR_MAXGRP = 64;
+struct GridBarrier {
+  uint32_t count;
+  uint32_t gen;
+  int32_t abort;
+  int32_t pad[PCG_BAR_STRIDE - 3];
+  uint32_t grp[PCG_BAR_MAXGRP * PCG_BAR_STRIDE];  // first-level counters
+};
+
+constexpr int PCG_BLOCK = 512;   // threads per block of the persistent launch (two GEMV tiles at once)
+constexpr int PCG_NPART = 8;     // partial sums per block
+constexpr int PCG_NC_LOCAL = 192;  // coarse sizes applied redundantly in every block
+
+struct PcgArgs {
+  DevMesh m;
+  const void* fm = nullptr;  // interface blocks (K_s^+)_bb (offsets m.sofs, leading dims m.ldb)
+  int fm32 = 0;              // 1: float
+  const void* mm = nullptr;  // preconditioner blocks (S_bb or K_bb), same layout
+  int mm32 = 0;
+  const double* Cinv = nullptr;  // (G^T G)^{-1}, n_c x n_c
+  const double* H = nullptr;     // optional G (G^T G)^{-1}, n_c x N_lambda (coarse-index major)
+  int nc = 0;
+  double *lam = nullptr, *r = nullptr, *w = nullptr, *z = nullptr, *y = nullptr, *p = nullptr,
+         *q = nullptr, *qraw = nullptr, *yb = nullptr, *zb = nullptr, *g = nullptr;
+  const double* mdiag = nullptr;
+  double* part = nullptr;  // 2 x grid x PCG_NPART (two alternating buffers)
+  double* sc = nullptr;
+  int32_t* ist = nullptr;
+  GridBarrier* bar = nullptr;
+  const int32_t* tile_sub = nullptr;   // GEMV row tiles (64 rows) over the interface blocks
+  const int32_t* tile_row0 = nullptr;
+  int ntile = 0;
+  long long* tstamp = nullptr;  // optional: block 0 records the wall clock after each barrier
+  int tstamp_iters = 0;         // iterations recorded (8 stamps each)
+};
+
+// dynamic LDS bytes of the launch
+size_t pcg_shmem(const DevMesh& m);
+// largest co-resident grid of the persistent kernel on the current device (0: none)
+int pcg_max_grid(const DevMesh& m);
+hipError_t launch_pcg_persistent(const PcgArgs& a, int grid, hipStream_t st);
+// H = G (G^T G)^{-1} from Cinv
+void launch_build_h(const DevMesh& m, const double* Cinv, int nc, double* H, hipStream_t st);
+
+}  // namespace feti

@@ -42,13 +42,22 @@ def load(w, t: float) -> B.Load:
 
 def opts(tol: float = 1e-10, max_it: int = 1000, start: int = B.START_PREVIOUS,
          check_every: int = 8, ir_max: int = 1, ir_cold: int = 4, tol_corr: float = 1e-3,
-         ir_tol: float = 1e-9) -> B.SolveOpts:
+         ir_tol: float = 1e-9, tol_inner: float = 0.0) -> B.SolveOpts:
     """Solve options.  Every step ends with FP64 iterative refinement on the torn
     system: up to ir_max corrections (ir_cold when the step starts without previous
     multipliers), stopping once a correction changes no field by more than ir_tol
     relative.  The pressure p = k1 xi + k2 eta is a small difference of large terms
-    at nu -> 1/2, so an interface residual of tol alone does not bound its error."""
-    return B.SolveOpts(tol, tol_corr, ir_tol, max_it, start, check_every, ir_max, ir_cold)
+    at nu -> 1/2, so an interface residual of tol alone does not bound its error.
+    tol_inner: first-solve tolerance with FP32 factors (0 = tol)."""
+    return B.SolveOpts(tol, tol_corr, ir_tol, max_it, start, check_every, ir_max, ir_cold, tol_inner)
+
+
+def opts_mixed(**kw) -> B.SolveOpts:
+    """Defaults of the FP32-factor path: a looser first solve (its operators carry
+    FP32 rounding) and more FP64 corrections."""
+    base = dict(tol_inner=1e-6, tol_corr=1e-4, ir_max=3, ir_cold=5, ir_tol=1e-9)
+    base.update(kw)
+    return opts(**base)
 
 
 def setup(w, stream=None, precision=B.FP64, precond=B.PRECOND_DIRICHLET) -> B.Feti:
