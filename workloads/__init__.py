@@ -210,3 +210,17 @@ def seeded_vector(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
 
 def seeded_matrix(m: int, n: int, seed: int, scale: float = 1.0) -> np.ndarray:
     return scale * np.random.default_rng(seed).standard_normal((m, n))
+
+
+def mlp_init(n_in: int, n_hidden: int, n_out: int, seed: int = 0):
+    """Seeded initial weights of the warm-start network (flat FP32, the layout of
+    oracle/mlp.py): uniform in +-sqrt(6 / (fan_in + fan_out)) for the weights, zero
+    biases; the last layer is scaled by 0.1 so that the untrained network predicts a
+    small correction."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for (fo, fi), scale in (((n_hidden, n_in), 1.0), ((n_hidden, n_hidden), 1.0), ((n_out, n_hidden), 0.1)):
+        lim = scale * math.sqrt(6.0 / (fi + fo))
+        parts.append(rng.uniform(-lim, lim, size=fo * fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)
