@@ -145,6 +145,61 @@ def pulsed_core_run(args):
     }
 
 
+def learned_start_run(args):
+    """The learned warm start on h = 1/64, 8 x 8 subdomains with periodic loads: samples
+    from 20 seeded trajectories of 200 steps of the plain solver, training with the
+    library's kernels, then 200 held-out steps (seed 1001) with the previous-step,
+    extrapolated and learned starts."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2509_06673_amd import _binding as B
+    from paper_2509_06673_amd import warmstart as WS
+    torch.cuda.set_device(0)
+    ntraj, nsteps = args.ws_trajectories, args.ws_steps
+    cases = [W.learned_start_case(s, nsteps=nsteps) for s in range(1, ntraj + 1)]
+    probe = WS.setup(cases[0])
+    nl = probe.get_sizes()["n_lambda"]
+    probe.close()
+    net = B.WarmStartNet(3 * nl, WS.HIDDEN, nl, 64, torch.cuda.current_stream())
+    net.set_params(torch.tensor(W.mlp_init(3 * nl, WS.HIDDEN, nl, seed=5), device="cuda"))
+    t0 = time.perf_counter()
+    X, T = WS.build_dataset(cases, nsteps, net)
+    t_data = time.perf_counter() - t0
+    print(f"[learned] {X.shape[0]} samples in {t_data:.1f} s", file=sys.stderr, flush=True)
+    hist = WS.train(net, X, T, epochs=args.ws_epochs, batch=64, lr=1e-3, seed=7)
+    print(f"[learned] training: loss {hist['loss'][0]:.3e} -> {hist['loss'][-1]:.3e} in {hist['seconds']:.1f} s",
+          file=sys.stderr, flush=True)
+    held = W.learned_start_case(1001, nsteps=200)
+    res = {}
+    for m in ("previous", "extrapolate", "learned"):
+        res[m] = WS.evaluate(held, net, 200, m)
+        print(f"[learned] {m}: first-solve iters {res[m]['mean_iters_first']:.2f}, iters {res[m]['mean_iters']:.2f}, "
+              f"{res[m]['mean_ms']:.2f} ms/step", file=sys.stderr, flush=True)
+    net.close()
+    lr_ = res["learned"]
+    return {
+        "metric": "time steps/s and PCG iters at rel. residual 1e-10 (learned warm start)",
+        "value": 1000.0 / lr_["mean_ms"], "unit": "time steps/s", "n_gpus": 1, "steps": len(lr_["ms"]),
+        "warmup": 2, "ms_per_step": lr_["mean_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 (solver), bf16/f32 (network)", "data": "synthetic",
+        "config": {"workload": held.name, "n_lambda": nl, "train_trajectories": ntraj, "train_steps": nsteps,
+                   "samples": int(X.shape[0]), "network": f"{3 * nl}-{WS.HIDDEN}-{WS.HIDDEN}-{nl}",
+                   "params": net_params(nl)},
+        "starts": {m: {"mean_pcg_iters_first_solve": r["mean_iters_first"], "mean_pcg_iters": r["mean_iters"],
+                       "ms_per_step": r["mean_ms"], "steps_per_s": 1000.0 / r["mean_ms"],
+                       "learned_start_kept": r["used_learned"]} for m, r in res.items()},
+        "training": {"data_s": t_data, "train_s": hist["seconds"], "adam_steps": hist["steps"],
+                     "loss_first_epoch": hist["loss"][0], "loss_last_epoch": hist["loss"][-1]},
+    }
+
+
+def net_params(nl):
+    from paper_2509_06673_amd import warmstart as WS
+    h = WS.HIDDEN
+    return 3 * nl * h + h + h * h + h + nl * h + nl
+
+
 def cpu_baseline(w, nsteps=3):
     """The FP64 oracle on the host, single-threaded, on a bounded sample of the workload."""
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
@@ -183,7 +238,11 @@ def main():
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="after the run, copy this many MB device to device (a known-size "
                          "reference for the HBM traffic counters of a profiler)")
-    ap.add_argument("--workload", default="nearly_incompressible", choices=["nearly_incompressible", "pulsed_core"],
+    ap.add_argument("--ws-trajectories", type=int, default=20, help="learned_start: training trajectories")
+    ap.add_argument("--ws-steps", type=int, default=200, help="learned_start: steps per training trajectory")
+    ap.add_argument("--ws-epochs", type=int, default=30, help="learned_start: training epochs")
+    ap.add_argument("--workload", default="nearly_incompressible",
+                    choices=["nearly_incompressible", "pulsed_core", "learned_start"],
                     help="pulsed_core: the h = 1/256 point-source run with the oscillation check")
     ap.add_argument("--pulsed-steps", type=int, default=200, help="time steps of the pulsed_core run")
     args = ap.parse_args()
@@ -193,6 +252,9 @@ def main():
         sys.exit(2)
     if args.workload == "pulsed_core":
         print(json.dumps(pulsed_core_run(args)), flush=True)
+        return
+    if args.workload == "learned_start":
+        print(json.dumps(learned_start_run(args)), flush=True)
         return
 
     import torch

@@ -69,7 +69,11 @@ enum { FETI_FP64 = 0, FETI_FP32_IR = 1 };
 enum { FETI_PRECOND_DIRICHLET = 0, FETI_PRECOND_LUMPED = 1, FETI_PRECOND_NONE = 2 };
 /* start vector of the interface iteration */
 enum { FETI_START_PREVIOUS = 0, FETI_START_ZERO = 1, FETI_START_EXTRAPOLATE = 2,
-       FETI_START_GIVEN = 3 };
+       FETI_START_GIVEN = 3,
+       /* the start set by feti_set_start (e.g. a learned prediction, feti_ws.h) if its
+        * projected residual w = P (d - F lambda), made admissible, is smaller in the
+        * dual-energy norm of the stopping test than that of the previous-step start */
+       FETI_START_BEST = 4 };
 
 /* Mesh and decomposition (Section 2.4 spaces on a structured right-triangle
  * mesh of the unit square; subdomains are an nsub_x x nsub_y grid of cell
@@ -199,8 +203,15 @@ int feti_solve(feti_ctx ctx, const double* f_dev, double* lambda_dev, double* u_
  * multipliers (N_lambda doubles) to device buffers; either may be NULL. */
 int feti_get_solution(feti_ctx ctx, double* u_dev, double* lambda_dev);
 
-/* Set the multiplier start of the next step (used with FETI_START_GIVEN). */
+/* Set the multiplier start of the next step (used with FETI_START_GIVEN and
+ * FETI_START_BEST). */
 int feti_set_start(feti_ctx ctx, const double* lambda_dev);
+
+/* The load of a step sampled at the node of every multiplier row (N_lambda doubles,
+ * device): the body force component of a displacement row (of the region of the
+ * row's first subdomain), the source for an eta, xi_P or p row, 0 for a xi_E row.
+ * These are the load features of the learned warm start (feti_ws.h). */
+int feti_interface_load(feti_ctx ctx, const feti_load* load, double* out_dev);
 
 /* ---- inspection (unit parity of each stage) ------------------------------- */
 

@@ -21,7 +21,7 @@ XSPLIT, YSPLIT, CORE = 0, 1, 2
 LOAD_MANUFACTURED, LOAD_PERIODIC, LOAD_POINT_SOURCE, LOAD_PATCH = 0, 1, 2, 3
 FP64, FP32_IR = 0, 1
 PRECOND_DIRICHLET, PRECOND_LUMPED, PRECOND_NONE = 0, 1, 2
-START_PREVIOUS, START_ZERO, START_EXTRAPOLATE, START_GIVEN = 0, 1, 2, 3
+START_PREVIOUS, START_ZERO, START_EXTRAPOLATE, START_GIVEN, START_BEST = 0, 1, 2, 3, 4
 EXPORT_K, EXPORT_SBB, EXPORT_KPLUS = 0, 1, 2
 KERNEL_LOCAL_SOLVE, KERNEL_IFACE_GEMV, KERNEL_PRECOND_GEMV, KERNEL_ELIMINATION = 0, 1, 2, 3
 
@@ -94,6 +94,21 @@ _SIGS = {
     "feti_get_rhs": [C.c_void_p, C.c_void_p],
     "feti_time_kernel": [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                          C.POINTER(C.c_double)],
+    "feti_interface_load": [C.c_void_p, C.POINTER(Load), C.c_void_p],
+    # learned warm start (include/feti_ws.h)
+    "feti_ws_create": [C.POINTER(C.c_void_p), C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
+    "feti_ws_destroy": [C.c_void_p],
+    "feti_ws_sizes": [C.c_void_p, C.POINTER(C.c_int64)],
+    "feti_ws_set_params": [C.c_void_p, C.c_void_p],
+    "feti_ws_get_params": [C.c_void_p, C.c_void_p],
+    "feti_ws_set_scaling": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "feti_ws_fit_scaling": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64],
+    "feti_ws_forward": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
+    "feti_ws_loss_grad": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p],
+    "feti_ws_train_step": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.POINTER(C.c_double)],
+    "feti_ws_make_features": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "feti_ws_make_target": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "feti_ws_predict": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
 }
 
 
@@ -110,6 +125,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         fn.restype = C.c_int
     lib.feti_last_error.argtypes = [C.c_void_p]
     lib.feti_last_error.restype = C.c_char_p
+    lib.feti_ws_last_error.argtypes = [C.c_void_p]
+    lib.feti_ws_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -215,6 +232,10 @@ class Feti:
     def set_start(self, lam):
         return self._check(self.lib.feti_set_start(self.ctx, _ptr(lam)), "feti_set_start")
 
+    def interface_load(self, load: Load, out):
+        return self._check(self.lib.feti_interface_load(self.ctx, C.byref(load), _ptr(out)),
+                           "feti_interface_load")
+
     # -- inspection ---------------------------------------------------------------
     def export_local(self, sub: int, which: int, out):
         return self._check(self.lib.feti_export_local(self.ctx, sub, which, _ptr(out)),
@@ -236,3 +257,81 @@ class Feti:
         self._check(self.lib.feti_time_kernel(self.ctx, which, reps, C.byref(ms), C.byref(work)),
                     "feti_time_kernel")
         return ms.value, work.value
+
+
+class WarmStartNet:
+    """The learned warm-start network of include/feti_ws.h on a torch stream."""
+
+    def __init__(self, n_in: int, n_hidden: int, n_out: int, max_batch: int, stream=None):
+        self.lib = load_library()
+        self.h = C.c_void_p()
+        sp = None
+        if stream is not None:
+            sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        rc = self.lib.feti_ws_create(C.byref(self.h), sp, n_in, n_hidden, n_out, max_batch)
+        if rc != OK:
+            raise FetiError(rc, "feti_ws_create")
+        self.n_in, self.n_hidden, self.n_out, self.max_batch = n_in, n_hidden, n_out, max_batch
+
+    def _check(self, rc: int, what: str):
+        if rc != OK:
+            msg = self.lib.feti_ws_last_error(self.h).decode() if self.h else ""
+            raise FetiError(rc, f"{what}: {msg}")
+        return rc
+
+    def close(self):
+        if self.h:
+            self.lib.feti_ws_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_params(self) -> int:
+        s = (C.c_int64 * 5)()
+        self._check(self.lib.feti_ws_sizes(self.h, s), "feti_ws_sizes")
+        return int(s[0])
+
+    def set_params(self, p):
+        return self._check(self.lib.feti_ws_set_params(self.h, _ptr(p)), "feti_ws_set_params")
+
+    def get_params(self, p):
+        return self._check(self.lib.feti_ws_get_params(self.h, _ptr(p)), "feti_ws_get_params")
+
+    def set_scaling(self, mean, inv_std, out_scale):
+        return self._check(self.lib.feti_ws_set_scaling(self.h, _ptr(mean), _ptr(inv_std), _ptr(out_scale)),
+                           "feti_ws_set_scaling")
+
+    def fit_scaling(self, x, t, nsamples: int):
+        return self._check(self.lib.feti_ws_fit_scaling(self.h, _ptr(x), _ptr(t), nsamples),
+                           "feti_ws_fit_scaling")
+
+    def forward(self, x, batch: int, y):
+        return self._check(self.lib.feti_ws_forward(self.h, _ptr(x), batch, _ptr(y)), "feti_ws_forward")
+
+    def loss_grad(self, x, t, batch: int, grad) -> float:
+        loss = C.c_double()
+        self._check(self.lib.feti_ws_loss_grad(self.h, _ptr(x), _ptr(t), batch, C.byref(loss), _ptr(grad)),
+                    "feti_ws_loss_grad")
+        return loss.value
+
+    def train_step(self, x, t, batch: int, lr: float, want_loss: bool = False):
+        loss = C.c_double()
+        self._check(self.lib.feti_ws_train_step(self.h, _ptr(x), _ptr(t), batch, lr,
+                                                C.byref(loss) if want_loss else None), "feti_ws_train_step")
+        return loss.value if want_loss else None
+
+    def make_features(self, n: int, lam_n, lam_nm1, load, x_row):
+        return self._check(self.lib.feti_ws_make_features(self.h, n, _ptr(lam_n), _ptr(lam_nm1), _ptr(load),
+                                                          _ptr(x_row)), "feti_ws_make_features")
+
+    def make_target(self, n: int, lam_np1, lam_n, lam_nm1, t_row):
+        return self._check(self.lib.feti_ws_make_target(self.h, n, _ptr(lam_np1), _ptr(lam_n), _ptr(lam_nm1),
+                                                        _ptr(t_row)), "feti_ws_make_target")
+
+    def predict(self, lam_n, lam_nm1, load, lam_out):
+        return self._check(self.lib.feti_ws_predict(self.h, _ptr(lam_n), _ptr(lam_nm1), _ptr(load),
+                                                    _ptr(lam_out)), "feti_ws_predict")

@@ -64,6 +64,7 @@ struct feti_ctx_s {
          *w = nullptr, *z = nullptr, *y = nullptr, *p = nullptr, *q = nullptr, *qraw = nullptr,
          *tl = nullptr;
   double *g = nullptr, *ac = nullptr;
+  double *lam_given = nullptr, *lam_alt = nullptr;  // start set by feti_set_start; scratch
   double *part = nullptr, *sc = nullptr;
   int32_t* ist = nullptr;
   int32_t* h_ist = nullptr;
@@ -229,7 +230,7 @@ int upload_mesh(feti_ctx ctx) {
   RC(dalloc(ctx, &ctx->mdiag, h.n_lambda, ctx->allocs));
   RC(dalloc(ctx, &ctx->kpart, (size_t)KMAX_NBLK * 12, ctx->allocs));
   double** lv[] = {&ctx->lam, &ctx->lam_prev, &ctx->lam_prev2, &ctx->d, &ctx->r, &ctx->w,
-                   &ctx->z, &ctx->y, &ctx->p, &ctx->q, &ctx->qraw, &ctx->tl};
+                   &ctx->z, &ctx->y, &ctx->p, &ctx->q, &ctx->qraw, &ctx->tl, &ctx->lam_given, &ctx->lam_alt};
   for (double** pp : lv) RC(dalloc(ctx, pp, nl, ctx->allocs));
   ctx->nc = 3 * h.n_float;
   RC(dalloc(ctx, &ctx->g, std::max(ctx->nc, 1), ctx->allocs));
@@ -397,9 +398,24 @@ void pcg_iteration(feti_ctx ctx, double* lam, const int32_t* done) {
 // of the primal solution, nullptr = 0).  lam holds the start guess on entry (any
 // vector) and the solution on exit; u receives the recovered torn primal solution.
 // iters_out accumulates the PCG iterations.
+// Dual-energy norm of the projected residual w = P (d - F lam) of an admissible lam.
+int start_residual(feti_ctx ctx, const double* lam, double* norm) {
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  op_F(ctx, lam, ctx->q, nullptr);
+  launch_axpby(m.n_lambda, 1.0, ctx->d, -1.0, ctx->q, ctx->r, st);
+  op_project(ctx, ctx->r, ctx->w, nullptr);
+  launch_reduce(m, nullptr, nullptr, ctx->w, ctx->mdiag, ctx->part, counter(ctx, PH_REFNORM), ctx->sc, ctx->ist,
+                PH_REFNORM, st);
+  HIPCHK(hipMemcpyAsync(ctx->h_sc, ctx->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *norm = ctx->h_sc[SC_EREF];
+  return FETI_OK;
+}
+
 int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double* f, const double* cj,
                double* lam, double* u, feti_stats* stats, int* iters_out, double* res0,
-               double* res) {
+               double* res, const double* cand = nullptr, int* took_cand = nullptr) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
   const int64_t nl = m.n_lambda;
@@ -415,10 +431,25 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
     if (cj) launch_axpby(nl, 1.0, ctx->d, -1.0, cj, ctx->d, st);
   }
   // admissible start: lambda += G (G^T G)^{-1} (e - G^T lambda)
-  if (ctx->nc > 0) {
-    launch_coarse_g(m, lam, f, -1.0, ctx->g, nullptr, st);
+  auto admissible = [&](double* v) {
+    if (ctx->nc == 0) return;
+    launch_coarse_g(m, v, f, -1.0, ctx->g, nullptr, st);
     launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, 1.0, nullptr, st);
-    launch_coarse_correct(m, ctx->ac, 1.0, lam, lam, nullptr, st);
+    launch_coarse_correct(m, ctx->ac, 1.0, v, v, nullptr, st);
+  };
+  admissible(lam);
+  if (took_cand) *took_cand = 0;
+  if (cand) {
+    // keep the candidate start if its projected residual is smaller
+    launch_axpby(nl, 1.0, cand, 0.0, nullptr, ctx->lam_alt, st);
+    admissible(ctx->lam_alt);
+    double n_lam = 0.0, n_alt = 0.0;
+    RC(start_residual(ctx, lam, &n_lam));
+    RC(start_residual(ctx, ctx->lam_alt, &n_alt));
+    if (n_alt < n_lam) {
+      launch_axpby(nl, 1.0, ctx->lam_alt, 0.0, nullptr, lam, st);
+      if (took_cand) *took_cand = 1;
+    }
   }
   // tolerance reference: per-kind norms of P d
   double hsc[SC_COUNT] = {0};
@@ -591,14 +622,16 @@ void torn_residual(feti_ctx ctx, const double* f, const double* u, const double*
 }
 
 // One FETI solve followed by up to nref FP64 refinement corrections.
-int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* stats) {
+int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* stats,
+                  const double* cand = nullptr, int* took_cand = nullptr) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
   int iters = 0;
   double res0 = 0, res = 0, r0c = 0, rc_ = 0;
   const double tol_first =
       (ctx->precision == FETI_FP32_IR && o->tol_inner > 0.0) ? std::max(o->tol, o->tol_inner) : o->tol;
-  int rc = solve_torn(ctx, o, tol_first, ctx->f, nullptr, ctx->lam, ctx->u, stats, &iters, &res0, &res);
+  int rc = solve_torn(ctx, o, tol_first, ctx->f, nullptr, ctx->lam, ctx->u, stats, &iters, &res0, &res, cand,
+                      took_cand);
   const int iters_first = iters;
   int done_ir = 0;
   double corr = 0.0;
@@ -949,7 +982,9 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, fet
   launch_rhs(m, ctx->u, ctx->f, ctx->mpP, ctx->mpE, L, st);
   // start vector
   int used = o->start;
-  if (o->start == FETI_START_ZERO || (o->start != FETI_START_GIVEN && !ctx->have_prev)) {
+  if (o->start == FETI_START_ZERO ||
+      (o->start != FETI_START_GIVEN && o->start != FETI_START_BEST && !ctx->have_prev) ||
+      (o->start == FETI_START_BEST && !ctx->have_prev)) {
     HIPCHK(hipMemsetAsync(ctx->lam, 0, m.n_lambda * sizeof(double), st));
     used = FETI_START_ZERO;
   }
@@ -959,11 +994,19 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, fet
     if (ctx->have_prev2) launch_axpby(m.n_lambda, 2.0, ctx->lam_prev, -1.0, ctx->lam_prev2, ctx->lam, st);
     else { launch_axpby(m.n_lambda, 1.0, ctx->lam_prev, 0.0, nullptr, ctx->lam, st); used = FETI_START_PREVIOUS; }
   }
-  // FETI_START_GIVEN: ctx->lam was set by feti_set_start
+  if (o->start == FETI_START_GIVEN) {
+    launch_axpby(m.n_lambda, 1.0, ctx->lam_given, 0.0, nullptr, ctx->lam, st);
+  } else if (o->start == FETI_START_BEST && ctx->have_prev) {
+    launch_axpby(m.n_lambda, 1.0, ctx->lam_prev, 0.0, nullptr, ctx->lam, st);
+    used = FETI_START_PREVIOUS;
+  }
   HIPCHK(hipGetLastError());
   const bool cold = !ctx->have_prev && o->start != FETI_START_GIVEN;
   if (stats) std::memset(stats, 0, sizeof(*stats));
-  int rc = solve_refined(ctx, o, cold ? std::max(o->ir_cold, o->ir_max) : o->ir_max, stats);
+  int took = 0;
+  const double* cand = (o->start == FETI_START_BEST) ? ctx->lam_given : nullptr;
+  int rc = solve_refined(ctx, o, cold ? std::max(o->ir_cold, o->ir_max) : o->ir_max, stats, cand, &took);
+  if (cand && took) used = FETI_START_GIVEN;
   // keep the multiplier history
   std::swap(ctx->lam_prev2, ctx->lam_prev);
   launch_axpby(m.n_lambda, 1.0, ctx->lam, 0.0, nullptr, ctx->lam_prev, st);
@@ -1018,9 +1061,17 @@ int feti_get_solution(feti_ctx ctx, double* u_dev, double* lambda_dev) {
 int feti_set_start(feti_ctx ctx, const double* lambda_dev) {
   if (!ctx || !lambda_dev) return FETI_EINVAL;
   if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "set_start before assemble");
-  HIPCHK(hipMemcpyAsync(ctx->lam, lambda_dev, ctx->dm.n_lambda * sizeof(double), hipMemcpyDeviceToDevice,
+  HIPCHK(hipMemcpyAsync(ctx->lam_given, lambda_dev, ctx->dm.n_lambda * sizeof(double), hipMemcpyDeviceToDevice,
                         ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FETI_OK;
+}
+
+int feti_interface_load(feti_ctx ctx, const feti_load* load, double* out_dev) {
+  if (!ctx || !load || !out_dev) return FETI_EINVAL;
+  if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "interface_load before assemble");
+  launch_interface_load(ctx->dm, make_load(ctx, load), out_dev, ctx->stream);
+  HIPCHK(hipGetLastError());
   return FETI_OK;
 }
 

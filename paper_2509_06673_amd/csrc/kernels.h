@@ -61,6 +61,8 @@ void launch_assemble(const DevMesh& m, double* K, MatParams mpP, MatParams mpE, 
 void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams mpP, MatParams mpE,
                 const LoadDev& L, hipStream_t st);
 void launch_init_eta(const DevMesh& m, double* u, const LoadDev& L, hipStream_t st);
+// load sampled at the node of every multiplier row (body force of u rows, source of eta, xi_P, p rows)
+void launch_interface_load(const DevMesh& m, const LoadDev& L, double* out, hipStream_t st);
 // y = K x (torn, element by element, overwriting y)
 void launch_elem_matvec(const DevMesh& m, const double* x, double* y, MatParams mpP, MatParams mpE,
                         hipStream_t st);

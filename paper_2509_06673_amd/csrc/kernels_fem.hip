@@ -169,7 +169,35 @@ __global__ void k_init_eta(const int32_t* __restrict__ code, double* __restrict_
   u[i] = initial_eta(L, (node % (ncell + 1)) * h, (node / (ncell + 1)) * h);
 }
 
+// load at the node of every multiplier row, read through the row's first interface DOF
+__global__ void k_interface_load(DevMesh m, LoadDev L, double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m.n_lambda) return;
+  const int64_t gb = m.jr_b[2 * j];
+  const int32_t code = m.code[m.b_torn[gb]];
+  const int kind = code & 7, node = code >> 3;
+  const bool poro = m.sub_poro[m.b_sub[gb]] != 0;
+  double v = 0.0;
+  if (kind <= 1) {
+    const int umu = m.order * m.ncell + 1;
+    const double uh = 1.0 / (m.order * m.ncell);
+    double fx, fy;
+    body_force(L, poro, (node % umu) * uh, (node / umu) * uh, fx, fy);
+    v = kind == 0 ? fx : fy;
+  } else if (kind <= 4) {
+    const int n1 = m.ncell + 1;
+    const double h = 1.0 / m.ncell;
+    v = source(L, (node % n1) * h, (node / n1) * h);
+  }
+  out[j] = v;
+}
+
 // ---- launchers ---------------------------------------------------------------
+
+void launch_interface_load(const DevMesh& m, const LoadDev& L, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_interface_load, dim3((unsigned)((m.n_lambda + 255) / 256)), dim3(256), 0, st, m, L, out);
+}
+
 
 void launch_assemble(const DevMesh& m, double* K, MatParams mpP, MatParams mpE, hipStream_t st) {
   const int64_t nthreads = (int64_t)m.nelem * m.edof;

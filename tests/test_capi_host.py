@@ -1,6 +1,7 @@
 """Host-side checks of the C-ABI library (no GPU needed).
 
-* the shared library loads and exports every function include/feti.h declares;
+* the shared library loads and exports every function include/feti.h and
+  include/feti_ws.h declare, and the binding covers each;
 * the numbering built by the library's host code equals, bit for bit, the
   independent statement in oracle/indexing.py (local DOF codes and order,
   interface sizes, the two entries and signs of every jump row);
@@ -22,18 +23,20 @@ from paper_2509_06673_amd import _binding as B  # noqa: E402
 from paper_2509_06673_amd.workload import mesh_args  # noqa: E402
 
 
-def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "feti.h")).read()
+def _declared_functions(header):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(feti_[a-z_A-Z0-9]+)\s*\(", src)))
 
 
-def test_library_exports_every_declared_symbol():
+@pytest.mark.parametrize("header,least", [("feti.h", 15), ("feti_ws.h", 12)])
+def test_library_exports_every_declared_symbol(header, least):
     lib = B.load_library()
-    names = _declared_functions()
-    assert len(names) >= 15
+    names = _declared_functions(header)
+    assert len(names) >= least
     for n in names:
         assert hasattr(lib, n), n
+        assert n in B._SIGS or n in ("feti_last_error", "feti_ws_last_error"), f"{n} has no binding"
 
 
 def _compare(w):
