@@ -167,10 +167,10 @@ def learned_start_run(args):
     X, T = WS.build_dataset(cases, nsteps, net)
     t_data = time.perf_counter() - t0
     print(f"[learned] {X.shape[0]} samples in {t_data:.1f} s", file=sys.stderr, flush=True)
-    hist = WS.train(net, X, T, epochs=args.ws_epochs, batch=64, lr=1e-3, seed=7)
+    hist = WS.train(net, X, T, epochs=args.ws_epochs, batch=64, lr=args.ws_lr, seed=7)
     print(f"[learned] training: loss {hist['loss'][0]:.3e} -> {hist['loss'][-1]:.3e} in {hist['seconds']:.1f} s",
           file=sys.stderr, flush=True)
-    held = W.learned_start_case(1001, nsteps=200)
+    held = W.learned_start_case(args.ws_eval_seed, nsteps=200)
     res = {}
     for m in ("previous", "extrapolate", "learned"):
         res[m] = WS.evaluate(held, net, 200, m)
@@ -240,7 +240,9 @@ def main():
                          "reference for the HBM traffic counters of a profiler)")
     ap.add_argument("--ws-trajectories", type=int, default=20, help="learned_start: training trajectories")
     ap.add_argument("--ws-steps", type=int, default=200, help="learned_start: steps per training trajectory")
-    ap.add_argument("--ws-epochs", type=int, default=30, help="learned_start: training epochs")
+    ap.add_argument("--ws-epochs", type=int, default=120, help="learned_start: training epochs")
+    ap.add_argument("--ws-lr", type=float, default=2e-4, help="learned_start: peak learning rate")
+    ap.add_argument("--ws-eval-seed", type=int, default=1001, help="learned_start: seed of the evaluated trajectory")
     ap.add_argument("--workload", default="nearly_incompressible",
                     choices=["nearly_incompressible", "pulsed_core", "learned_start"],
                     help="pulsed_core: the h = 1/256 point-source run with the oscillation check")

@@ -5,15 +5,18 @@
  * multipliers.  This library adds a small network that predicts the multipliers
  * of the next step from the last two steps and the next step's load:
  *
- *   x   = [lambda^n, lambda^{n-1}, load^{n+1}]      (3 N_lambda features, FP32)
- *   lambda^{n+1} ~ 2 lambda^n - lambda^{n-1} + s * MLP(std(x))
+ *   x   = [lambda^n, lambda^{n-1}, load^{n+1}] / rho      (3 N_lambda features, FP32)
+ *   lambda^{n+1} ~ 2 lambda^n - lambda^{n-1} + rho s * MLP(std(x))
  *
+ * with rho the root mean square of lambda^n: the discrete problem is linear, so
+ * dividing a sample by its own magnitude removes the load amplitude from what the
+ * network has to learn.
  * with std(x) = (x - mean) * inv_std per feature, s a per-output scale, and MLP a
  * three-layer perceptron  n_in -> h -> h -> n_out  with GELU activations (the erf
  * form).  Weights are kept as FP32 master copies and BF16 copies; every product
  * takes BF16 operands and accumulates in FP32 on the matrix cores; biases are FP32.
  * Training minimises the mean squared error of the scaled target
- * (lambda^{n+1} - 2 lambda^n + lambda^{n-1}) / s with Adam.  The solver keeps the
+ * (lambda^{n+1} - 2 lambda^n + lambda^{n-1}) / (rho s) with Adam.  The solver keeps the
  * prediction only when its projected residual beats the previous-step start
  * (FETI_START_BEST in feti.h).
  *
@@ -69,14 +72,15 @@ int feti_ws_loss_grad(feti_ws ws, const float* x_dev, const float* t_dev, int32_
 int feti_ws_train_step(feti_ws ws, const float* x_dev, const float* t_dev, int32_t batch, float lr,
                        double* loss_host);
 
-/* Raw feature row [lam_n, lam_nm1, load] (3 n FP32) and target row
- * lam_np1 - 2 lam_n + lam_nm1 (n FP32) from FP64 multiplier vectors. */
+/* Raw feature row [lam_n, lam_nm1, load] / rho (3 n FP32) and target row
+ * (lam_np1 - 2 lam_n + lam_nm1) / rho (n FP32) from FP64 multiplier vectors,
+ * rho = rms(lam_n) (1 if lam_n = 0). */
 int feti_ws_make_features(feti_ws ws, int64_t n, const double* lam_n_dev, const double* lam_nm1_dev,
                           const double* load_dev, float* x_row_dev);
 int feti_ws_make_target(feti_ws ws, int64_t n, const double* lam_np1_dev, const double* lam_n_dev,
                         const double* lam_nm1_dev, float* t_row_dev);
 
-/* Predicted multipliers lam_out = 2 lam_n - lam_nm1 + s * MLP(std(x)) (FP64, n_out). */
+/* Predicted multipliers lam_out = 2 lam_n - lam_nm1 + rho s * MLP(std(x)) (FP64, n_out). */
 int feti_ws_predict(feti_ws ws, const double* lam_n_dev, const double* lam_nm1_dev, const double* load_dev,
                     double* lam_out_dev);
 

@@ -269,45 +269,65 @@ void launch_column_rms(const float* x, int64_t rows, int cols, float* rms, hipSt
   hipLaunchKernelGGL(k_column_rms, dim3((cols + 255) / 256), dim3(256), 0, st, x, rows, cols, rms);
 }
 
-__global__ void k_ws_features(int64_t n, const double* __restrict__ lam_n, const double* __restrict__ lam_nm1,
-                              const double* __restrict__ load, float* __restrict__ x) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  x[i] = (float)lam_n[i];
-  x[n + i] = (float)lam_nm1[i];
-  x[2 * n + i] = (float)load[i];
+// rho = root mean square of v (1 for a zero vector), one block, fixed summation order
+__device__ double block_rms(int64_t n, const double* __restrict__ v) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += v[i] * v[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sqrt(red[0] / (double)n);
+  __syncthreads();
+  return r > 0.0 ? r : 1.0;
+}
+
+// One block: x = [lam_n, lam_nm1, load] / rho, rho = rms(lam_n)
+__global__ void __launch_bounds__(256) k_ws_features(int64_t n, const double* __restrict__ lam_n,
+                                                     const double* __restrict__ lam_nm1,
+                                                     const double* __restrict__ load, float* __restrict__ x) {
+  const double inv = 1.0 / block_rms(n, lam_n);
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    x[i] = (float)(lam_n[i] * inv);
+    x[n + i] = (float)(lam_nm1[i] * inv);
+    x[2 * n + i] = (float)(load[i] * inv);
+  }
 }
 
 void launch_ws_features(int64_t n, const double* lam_n, const double* lam_nm1, const double* load, float* x_row,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_ws_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, lam_n, lam_nm1, load,
-                     x_row);
+  hipLaunchKernelGGL(k_ws_features, dim3(1), dim3(256), 0, st, n, lam_n, lam_nm1, load, x_row);
 }
 
-__global__ void k_ws_target(int64_t n, const double* __restrict__ lam_np1, const double* __restrict__ lam_n,
-                            const double* __restrict__ lam_nm1, float* __restrict__ t) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  t[i] = (float)(lam_np1[i] - 2.0 * lam_n[i] + lam_nm1[i]);
+// One block: t = (lam_np1 - 2 lam_n + lam_nm1) / rho, rho = rms(lam_n)
+__global__ void __launch_bounds__(256) k_ws_target(int64_t n, const double* __restrict__ lam_np1,
+                                                   const double* __restrict__ lam_n,
+                                                   const double* __restrict__ lam_nm1, float* __restrict__ t) {
+  const double inv = 1.0 / block_rms(n, lam_n);
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+    t[i] = (float)((lam_np1[i] - 2.0 * lam_n[i] + lam_nm1[i]) * inv);
 }
 
 void launch_ws_target(int64_t n, const double* lam_np1, const double* lam_n, const double* lam_nm1, float* t_row,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_ws_target, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, lam_np1, lam_n, lam_nm1,
-                     t_row);
+  hipLaunchKernelGGL(k_ws_target, dim3(1), dim3(256), 0, st, n, lam_np1, lam_n, lam_nm1, t_row);
 }
 
-__global__ void k_ws_apply(int64_t n, const double* __restrict__ lam_n, const double* __restrict__ lam_nm1,
-                           const float* __restrict__ y, const float* __restrict__ out_scale, double* __restrict__ lam) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  lam[i] = 2.0 * lam_n[i] - lam_nm1[i] + (double)y[i] * (double)out_scale[i];
+// One block: lam = 2 lam_n - lam_nm1 + rho y out_scale, rho = rms(lam_n)
+__global__ void __launch_bounds__(256) k_ws_apply(int64_t n, const double* __restrict__ lam_n,
+                                                  const double* __restrict__ lam_nm1, const float* __restrict__ y,
+                                                  const float* __restrict__ out_scale, double* __restrict__ lam) {
+  const double rho = block_rms(n, lam_n);
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+    lam[i] = 2.0 * lam_n[i] - lam_nm1[i] + rho * (double)y[i] * (double)out_scale[i];
 }
 
 void launch_ws_apply(int64_t n, const double* lam_n, const double* lam_nm1, const float* y, const float* out_scale,
                      double* lam, hipStream_t st) {
-  hipLaunchKernelGGL(k_ws_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, lam_n, lam_nm1, y,
-                     out_scale, lam);
+  hipLaunchKernelGGL(k_ws_apply, dim3(1), dim3(256), 0, st, n, lam_n, lam_nm1, y, out_scale, lam);
 }
 
 }  // namespace feti

@@ -53,12 +53,13 @@ void launch_to_bf16(int64_t n, const float* x, uint16_t* out, hipStream_t st);
 void launch_column_stats(const float* x, int64_t rows, int cols, float* mean, float* inv_std, hipStream_t st);
 // per-column root mean square (1 for an all-zero column)
 void launch_column_rms(const float* x, int64_t rows, int cols, float* rms, hipStream_t st);
-// x_row = [lam_n, lam_nm1, load] (FP32); t_row = lam_np1 - 2 lam_n + lam_nm1 (any may be null)
+// x_row = [lam_n, lam_nm1, load] / rho (FP32); t_row = (lam_np1 - 2 lam_n + lam_nm1) / rho;
+// rho = root mean square of lam_n (1 if it is zero)
 void launch_ws_features(int64_t n, const double* lam_n, const double* lam_nm1, const double* load, float* x_row,
                         hipStream_t st);
 void launch_ws_target(int64_t n, const double* lam_np1, const double* lam_n, const double* lam_nm1, float* t_row,
                       hipStream_t st);
-// lam = 2 lam_n - lam_nm1 + y out_scale
+// lam = 2 lam_n - lam_nm1 + rho y out_scale
 void launch_ws_apply(int64_t n, const double* lam_n, const double* lam_nm1, const float* y, const float* out_scale,
                      double* lam, hipStream_t st);
 
