@@ -178,6 +178,12 @@ int feti_assemble(feti_ctx ctx, const feti_material* mat_p, const feti_material*
  * precision: FETI_FP64 | FETI_FP32_IR; precond: FETI_PRECOND_*. */
 int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond);
 
+/* Memory: keep the assembled K_s after the elimination (keep = 1, the default) or
+ * eliminate in place (keep = 0): the dense storage of the context halves, and K_s
+ * can then neither be exported after feti_factor_subdomains nor eliminated again.
+ * Call before feti_factor_subdomains. */
+int feti_set_keep_assembled(feti_ctx ctx, int32_t keep);
+
 /* ---- time stepping ----------------------------------------------------------- */
 
 /* Set eta^0 (the initial fluid content) from a load's initial data: nodal
@@ -212,6 +218,32 @@ int feti_set_start(feti_ctx ctx, const double* lambda_dev);
  * row's first subdomain), the source for an eta, xi_P or p row, 0 for a xi_E row.
  * These are the load features of the learned warm start (feti_ws.h). */
 int feti_interface_load(feti_ctx ctx, const feti_load* load, double* out_dev);
+
+/* ---- batches of independent problems -------------------------------------------- */
+
+/* A batch of factored contexts (same stream, same precision, Dirichlet or lumped
+ * preconditioner, at most 64 floating subdomains each) whose interface iterations
+ * run in one cooperative launch per solve: the work of every problem is spread over
+ * the whole chip, each problem keeps its own scalars and stopping test, and a
+ * finished problem drops out of the launch.  The contexts stay owned by the caller
+ * and must outlive the batch. */
+typedef struct feti_batch_s* feti_batch;
+int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob);  /* failure text: feti_last_error(ctxs[0]) */
+int feti_batch_destroy(feti_batch b);
+const char* feti_batch_last_error(feti_batch b);
+
+/* One backward-Euler step of every problem (loads[nprob], stats[nprob] may be NULL):
+ * right-hand sides, interface solves and recovery as feti_step, with the previous-
+ * step, extrapolated or zero start and a fixed number of refinement corrections
+ * (opts->ir_max, or ir_cold on a problem's first step). */
+int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts* opts, feti_stats* stats);
+
+/* Launch shape: grid > 0 fixes the number of blocks; grid = 0 (the default) lets the
+ * autotuner time candidate grids on the first launches and keep the fastest per
+ * iteration.  info: [0] grid in use, [1] 1 once the choice is final, [2] candidates,
+ * [3..] the candidate grids (up to 8). */
+int feti_batch_set_grid(feti_batch b, int32_t grid);
+int feti_batch_info(feti_batch b, int32_t* info_host);
 
 /* ---- inspection (unit parity of each stage) ------------------------------- */
 

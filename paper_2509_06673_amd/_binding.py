@@ -95,6 +95,12 @@ _SIGS = {
     "feti_time_kernel": [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                          C.POINTER(C.c_double)],
     "feti_interface_load": [C.c_void_p, C.POINTER(Load), C.c_void_p],
+    "feti_set_keep_assembled": [C.c_void_p, C.c_int32],
+    "feti_batch_create": [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32],
+    "feti_batch_destroy": [C.c_void_p],
+    "feti_batch_step": [C.c_void_p, C.POINTER(Load), C.POINTER(SolveOpts), C.POINTER(Stats)],
+    "feti_batch_set_grid": [C.c_void_p, C.c_int32],
+    "feti_batch_info": [C.c_void_p, C.POINTER(C.c_int32)],
     # learned warm start (include/feti_ws.h)
     "feti_ws_create": [C.POINTER(C.c_void_p), C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
     "feti_ws_destroy": [C.c_void_p],
@@ -127,6 +133,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.feti_last_error.restype = C.c_char_p
     lib.feti_ws_last_error.argtypes = [C.c_void_p]
     lib.feti_ws_last_error.restype = C.c_char_p
+    lib.feti_batch_last_error.argtypes = [C.c_void_p]
+    lib.feti_batch_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -232,6 +240,10 @@ class Feti:
     def set_start(self, lam):
         return self._check(self.lib.feti_set_start(self.ctx, _ptr(lam)), "feti_set_start")
 
+    def set_keep_assembled(self, keep: bool):
+        return self._check(self.lib.feti_set_keep_assembled(self.ctx, 1 if keep else 0),
+                           "feti_set_keep_assembled")
+
     def interface_load(self, load: Load, out):
         return self._check(self.lib.feti_interface_load(self.ctx, C.byref(load), _ptr(out)),
                            "feti_interface_load")
@@ -335,3 +347,50 @@ class WarmStartNet:
     def predict(self, lam_n, lam_nm1, load, lam_out):
         return self._check(self.lib.feti_ws_predict(self.h, _ptr(lam_n), _ptr(lam_nm1), _ptr(load),
                                                     _ptr(lam_out)), "feti_ws_predict")
+
+
+class Batch:
+    """Independent factored contexts stepped together (feti_batch_* of include/feti.h);
+    the contexts must outlive the batch."""
+
+    def __init__(self, ctxs):
+        self.lib = load_library()
+        self.ctxs = list(ctxs)
+        arr = (C.c_void_p * len(self.ctxs))(*[c.ctx.value for c in self.ctxs])
+        self.h = C.c_void_p()
+        rc = self.lib.feti_batch_create(C.byref(self.h), arr, len(self.ctxs))
+        if rc != OK:
+            raise FetiError(rc, self.ctxs[0].last_error())
+
+    def _check(self, rc: int, what: str, allow=()):
+        if rc != OK and rc not in allow:
+            msg = self.lib.feti_batch_last_error(self.h).decode() if self.h else ""
+            raise FetiError(rc, f"{what}: {msg}")
+        return rc
+
+    def close(self):
+        if self.h:
+            self.lib.feti_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, loads, opts: SolveOpts, allow=()):
+        n = len(self.ctxs)
+        la = (Load * n)(*loads)
+        st = (Stats * n)()
+        rc = self.lib.feti_batch_step(self.h, la, C.byref(opts), st)
+        self._check(rc, "feti_batch_step", allow)
+        return [s.as_dict() for s in st], rc
+
+    def set_grid(self, grid: int):
+        return self._check(self.lib.feti_batch_set_grid(self.h, grid), "feti_batch_set_grid")
+
+    def info(self):
+        buf = (C.c_int32 * 11)()
+        self._check(self.lib.feti_batch_info(self.h, buf), "feti_batch_info")
+        return {"grid": buf[0], "tuned": bool(buf[1]), "candidates": [buf[3 + k] for k in range(buf[2])]}

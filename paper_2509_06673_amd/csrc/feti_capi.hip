@@ -41,6 +41,7 @@ struct feti_ctx_s {
   MatParams mpP{}, mpE{};
   double lamP = 0, muP = 0, lamE = 0, muE = 0, tau = 0;
   int precision = FETI_FP64, precond = FETI_PRECOND_DIRICHLET;
+  bool keep_assembled = true;  // false: the elimination runs in place in K
   // dense blocks
   int64_t k_total = 0, s_total = 0;
   double* K = nullptr;      // assembled local matrices
@@ -413,13 +414,14 @@ int start_residual(feti_ctx ctx, const double* lam, double* norm) {
   return FETI_OK;
 }
 
-int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double* f, const double* cj,
-               double* lam, double* u, feti_stats* stats, int* iters_out, double* res0,
-               double* res, const double* cand = nullptr, int* took_cand = nullptr) {
+// First half of a torn solve (no host synchronisation unless a candidate start is
+// compared): d = sum_s B_s K_s^+ f_s - c, the admissible start, the scalar state,
+// the reference norms of P d, and r, w, y, p with rho = (w, y).
+int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, const double* f, const double* cj,
+               double* lam, const double* cand = nullptr, int* took_cand = nullptr) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
   const int64_t nl = m.n_lambda;
-  HIPCHK(hipEventRecord(ctx->ev[1], st));
   // d = sum_s B_s K_s^+ f_s - c
   {
     GemvArgs a;
@@ -452,11 +454,7 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
     }
   }
   // tolerance reference: per-kind norms of P d
-  double hsc[SC_COUNT] = {0};
-  hsc[SC_TOL] = tol;
-  HIPCHK(hipMemcpyAsync(ctx->sc, hsc, sizeof(hsc), hipMemcpyHostToDevice, st));
-  int32_t hist[IS_COUNT] = {0, 0, 0, std::max(o->max_it, 0)};
-  HIPCHK(hipMemcpyAsync(ctx->ist, hist, sizeof(hist), hipMemcpyHostToDevice, st));
+  launch_init_scalars(ctx->sc, ctx->ist, tol, std::max(o->max_it, 0), st);
   op_project(ctx, ctx->d, ctx->tl, nullptr);
   launch_reduce(m, nullptr, nullptr, ctx->tl, ctx->mdiag, ctx->part, counter(ctx, PH_REFNORM), ctx->sc,
                 ctx->ist, PH_REFNORM, st);
@@ -469,6 +467,37 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
   launch_axpby(nl, 1.0, ctx->y, 0.0, nullptr, ctx->p, st);
   launch_reduce(m, ctx->w, ctx->y, ctx->w, ctx->mdiag, ctx->part, counter(ctx, PH_INIT), ctx->sc,
                 ctx->ist, PH_INIT, st);
+  HIPCHK(hipGetLastError());
+  return FETI_OK;
+}
+
+// Second half of a torn solve: alpha_c = -(G^T G)^{-1} G^T r and the recovery
+// u = K^+ (f - B^T lam) + R alpha_c, where K^+ f is still in ytmp from torn_begin.
+int torn_end(feti_ctx ctx, const double* lam, double* u) {
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  if (ctx->nc > 0) {
+    launch_coarse_g(m, ctx->r, nullptr, 1.0, ctx->g, nullptr, st);
+    launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, -1.0, nullptr, st);
+  }
+  GemvArgs a;
+  const Factors fc = factors(ctx);
+  a.A = fc.kinv; a.a_f32 = fc.f32; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
+  a.kb_only = 1; a.ybase = ctx->ytmp;
+  a.v = lam; a.gmode = G_SIGNED; a.gcoef = -1.0;
+  a.y = u; a.alpha_c = ctx->nc > 0 ? ctx->ac : nullptr;
+  launch_sgemv(m, a, st);
+  HIPCHK(hipGetLastError());
+  return FETI_OK;
+}
+
+int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double* f, const double* cj,
+               double* lam, double* u, feti_stats* stats, int* iters_out, double* res0,
+               double* res, const double* cand = nullptr, int* took_cand = nullptr) {
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  HIPCHK(hipEventRecord(ctx->ev[1], st));
+  RC(torn_begin(ctx, o, tol, f, cj, lam, cand, took_cand));
   HIPCHK(hipEventRecord(ctx->ev[2], st));
   const int32_t* done = ctx->ist + IS_DONE;
   const int chunk = std::max(1, o->check_every);
@@ -478,10 +507,9 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
   const bool persist = use_persist && !trace && ctx->pgrid > 0 && ctx->nc <= PCG_NC_LOCAL &&
                        ctx->precond != FETI_PRECOND_NONE;
   if (persist) {
-    // every iteration of the solve in one cooperative launch
-    HIPCHK(hipMemcpyAsync(ctx->h_ist, ctx->ist, IS_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (!ctx->h_ist[IS_DONE] && ctx->h_ist[IS_ITERS] < o->max_it) {
+    // every iteration of the solve in one cooperative launch (a solve converged at
+    // its start leaves the launch at once)
+    {
       HIPCHK(hipMemsetAsync(ctx->bar, 0, sizeof(GridBarrier), st));
       const Factors fc = factors(ctx);
       PcgArgs pa;
@@ -570,21 +598,7 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
     }
   }
   HIPCHK(hipEventRecord(ctx->ev[3], st));
-  // recovery: alpha_c = -(G^T G)^{-1} G^T r,  u = K^+ (f - B^T lambda) + R alpha_c
-  if (ctx->nc > 0) {
-    launch_coarse_g(m, ctx->r, nullptr, 1.0, ctx->g, nullptr, st);
-    launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, -1.0, nullptr, st);
-  }
-  {
-    // K^+ f is already in ytmp (from d): only the interface columns of K^+ are read
-    GemvArgs a;
-    const Factors fc = factors(ctx);
-    a.A = fc.kinv; a.a_f32 = fc.f32; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
-    a.kb_only = 1; a.ybase = ctx->ytmp;
-    a.v = lam; a.gmode = G_SIGNED; a.gcoef = -1.0;
-    a.y = u; a.alpha_c = ctx->nc > 0 ? ctx->ac : nullptr;
-    launch_sgemv(m, a, st);
-  }
+  RC(torn_end(ctx, lam, u));
   HIPCHK(hipEventRecord(ctx->ev[4], st));
   HIPCHK(hipMemcpyAsync(ctx->h_ist, ctx->ist, IS_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(ctx->h_sc, ctx->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -867,10 +881,15 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   const int nsub = m.nsub;
   const bool f32 = precision == FETI_FP32_IR;
   if (!ctx->Kbb) RC(dalloc(ctx, &ctx->Kbb, ctx->s_total, ctx->mat_allocs));
-  if (!f32 && !ctx->Kinv) {
-    RC(dalloc(ctx, &ctx->Kinv, ctx->k_total, ctx->mat_allocs));
+  if (!ctx->keep_assembled && (ctx->state >= 3 || !ctx->K))
+    return fail(ctx, FETI_ESTATE, "factors computed in place cannot be recomputed");
+  if (!f32 && !ctx->Sbb) {
     RC(dalloc(ctx, &ctx->Sbb, ctx->s_total, ctx->mat_allocs));
     RC(dalloc(ctx, &ctx->Splus, ctx->s_total, ctx->mat_allocs));
+  }
+  if (!f32 && !ctx->Kinv) {
+    if (ctx->keep_assembled) RC(dalloc(ctx, &ctx->Kinv, ctx->k_total, ctx->mat_allocs));
+    else ctx->Kinv = ctx->K;  // eliminated in place
   }
   if (f32 && !ctx->Kinv32) {
     RC(dalloc(ctx, &ctx->Kinv32, ctx->k_total, ctx->mat_allocs));
@@ -878,7 +897,8 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
     RC(dalloc(ctx, &ctx->Splus32, ctx->s_total, ctx->mat_allocs));
   }
   if (f32) launch_to_f32(ctx->k_total, ctx->K, ctx->Kinv32, st);
-  else HIPCHK(hipMemcpyAsync(ctx->Kinv, ctx->K, ctx->k_total * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else if (ctx->Kinv != ctx->K)
+    HIPCHK(hipMemcpyAsync(ctx->Kinv, ctx->K, ctx->k_total * sizeof(double), hipMemcpyDeviceToDevice, st));
   // host copies of the per-subdomain geometry of the dense blocks
   std::vector<int> n(nsub), nI(nsub), nsw(nsub);
   std::vector<int64_t> aofs(nsub), sofs(nsub);
@@ -922,6 +942,13 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   HIPCHK(hipMemcpyAsync(stat.data(), P.status, nsub * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   for (void* p : tmp) (void)hipFree(p);
+  if (!ctx->keep_assembled && f32) {
+    // the FP32 factors no longer need the assembled FP64 matrices
+    auto it = std::find(ctx->mat_allocs.begin(), ctx->mat_allocs.end(), (void*)ctx->K);
+    if (it != ctx->mat_allocs.end()) ctx->mat_allocs.erase(it);
+    HIPCHK(hipFree(ctx->K));
+    ctx->K = nullptr;
+  }
   for (int s = 0; s < nsub; ++s)
     if (stat[s]) return fail(ctx, FETI_ESINGULAR, "zero or non-finite pivot in subdomain " + std::to_string(s));
   // coarse matrix G^T G and its inverse
@@ -1087,6 +1114,8 @@ int feti_export_local(feti_ctx ctx, int32_t sub, int32_t which, double* out) {
     so += (int64_t)h.subs[s].nb * round8(h.subs[s].nb);
   }
   const SubHost& sh = h.subs[sub];
+  if (which == FETI_EXPORT_K && (!ctx->K || (!ctx->keep_assembled && ctx->state >= 3)))
+    return fail(ctx, FETI_ESTATE, "the assembled matrices were eliminated in place");
   if (which != FETI_EXPORT_K && ctx->precision == FETI_FP32_IR) {
     // FP32 factors: widen the block to FP64 on the way out
     const bool sbb = which == FETI_EXPORT_SBB;
@@ -1150,6 +1179,7 @@ int feti_time_kernel(feti_ctx ctx, int32_t which, int32_t reps, double* avg_ms, 
   hipStream_t st = ctx->stream;
   double w = 0.0;
   if (which == FETI_KERNEL_ELIMINATION) {
+    if (!ctx->keep_assembled) return fail(ctx, FETI_ESTATE, "in-place factors cannot be recomputed");
     HIPCHK(hipEventRecord(ctx->ev[6], st));
     RC(feti_factor_subdomains(ctx, ctx->precision, ctx->precond));
     HIPCHK(hipEventRecord(ctx->ev[7], st));
@@ -1183,5 +1213,319 @@ int feti_time_kernel(feti_ctx ctx, int32_t which, int32_t reps, double* avg_ms, 
   *work = w;
   return FETI_OK;
 }
+
+
+int feti_set_keep_assembled(feti_ctx ctx, int32_t keep) {
+  if (!ctx) return FETI_EINVAL;
+  if (ctx->state >= 3) return fail(ctx, FETI_ESTATE, "set_keep_assembled after factor_subdomains");
+  ctx->keep_assembled = keep != 0;
+  return FETI_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Batches of independent problems
+
+struct feti_batch_s {
+  std::vector<feti_ctx> ctx;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int P = 0, f32 = 0, max_nb = 0;
+  ProbArgs* d_main = nullptr;  // problem tables of the first solve (multipliers lam)
+  ProbArgs* d_corr = nullptr;  // of the refinement corrections (multipliers dlam)
+  int32_t *tile_prob = nullptr, *tile_sub = nullptr, *tile_row0 = nullptr;
+  int32_t *row_prob = nullptr, *row_chunk = nullptr, *flt_prob = nullptr, *flt_f = nullptr;
+  int ntile = 0, nrow = 0, nflt = 0;
+  double *alpha = nullptr, *beta = nullptr, *rho = nullptr, *part = nullptr;
+  int32_t *done = nullptr, *iters = nullptr, *status = nullptr, *ndone = nullptr;
+  GridBarrier* bar = nullptr;
+  int32_t* h_buf = nullptr;  // pinned: iterations and statuses of the last launch
+  int grid = 0;
+  bool tuned = false;
+  std::vector<int> cand;
+  std::vector<double> cost;
+  int trial = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+int bfail(feti_batch b, int code, const std::string& msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+#define BCHK(expr)                                                                           \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess) return bfail(b, FETI_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+#define BRC(expr)                                                                       \
+  do {                                                                                  \
+    int _rc = (expr);                                                                   \
+    if (_rc != FETI_OK) return _rc;                                                     \
+  } while (0)
+
+template <class T>
+int balloc(feti_batch b, T** p, size_t count) {
+  *p = nullptr;
+  hipError_t e = hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return bfail(b, FETI_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  b->allocs.push_back(*p);
+  return FETI_OK;
+}
+
+template <class T>
+int bupload(feti_batch b, T** p, const std::vector<T>& v) {
+  BRC(balloc(b, p, v.size()));
+  if (!v.empty()) BCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return FETI_OK;
+}
+
+// one cooperative launch over every problem; adds each problem's iterations to its
+// stats and keeps the worst status
+int run_batch(feti_batch b, bool corr, std::vector<feti_stats>& acc) {
+  hipStream_t st = b->stream;
+  BCHK(hipMemsetAsync(b->bar, 0, sizeof(GridBarrier), st));
+  BCHK(hipMemsetAsync(b->ndone, 0, sizeof(int32_t), st));
+  BatchArgs a;
+  a.probs = corr ? b->d_corr : b->d_main;
+  a.P = b->P; a.f32 = b->f32;
+  a.tile_prob = b->tile_prob; a.tile_sub = b->tile_sub; a.tile_row0 = b->tile_row0; a.ntile = b->ntile;
+  a.row_prob = b->row_prob; a.row_chunk = b->row_chunk; a.nrow = b->nrow;
+  a.flt_prob = b->flt_prob; a.flt_f = b->flt_f; a.nflt = b->nflt;
+  a.alpha = b->alpha; a.beta = b->beta; a.rho = b->rho;
+  a.done = b->done; a.iters = b->iters; a.status = b->status; a.ndone = b->ndone; a.bar = b->bar;
+  a.max_nb = b->max_nb;
+  const int grid = b->tuned ? b->grid : b->cand[b->trial % b->cand.size()];
+  BCHK(hipEventRecord(b->e0, st));
+  BCHK(launch_pcg_batch(a, grid, st));
+  BCHK(hipEventRecord(b->e1, st));
+  BCHK(hipMemcpyAsync(b->h_buf, b->iters, b->P * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  BCHK(hipMemcpyAsync(b->h_buf + b->P, b->status, b->P * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  BCHK(hipStreamSynchronize(st));
+  int64_t total = 0;
+  for (int p = 0; p < b->P; ++p) {
+    acc[p].iters += b->h_buf[p];
+    total += b->h_buf[p];
+    if (b->h_buf[b->P + p] != 0 && acc[p].status == 0) acc[p].status = b->h_buf[b->P + p];
+  }
+  if (!b->tuned) {
+    // autotuner: time per iteration-problem of each candidate grid, then keep the best
+    float ms = 0.f;
+    BCHK(hipEventElapsedTime(&ms, b->e0, b->e1));
+    b->cost[b->trial % b->cand.size()] += ms / (double)std::max<int64_t>(total, 1);
+    b->trial += 1;
+    if (b->trial >= (int)b->cand.size() * 2) {
+      int best = 0;
+      for (int k = 1; k < (int)b->cand.size(); ++k)
+        if (b->cost[k] < b->cost[best]) best = k;
+      b->grid = b->cand[best];
+      b->tuned = true;
+    }
+  }
+  return FETI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob) {
+  if (!out || !ctxs || nprob < 1) return FETI_EINVAL;
+  *out = nullptr;
+  feti_batch b = new feti_batch_s();
+  // on failure the message goes to the first context (there is no batch handle)
+  auto bad = [&](int rc, const std::string& msg) {
+    for (void* p : b->allocs) (void)hipFree(p);
+    if (b->h_buf) (void)hipHostFree(b->h_buf);
+    delete b;
+    if (ctxs[0] && !msg.empty()) ctxs[0]->err = "feti_batch_create: " + msg;
+    return rc == FETI_OK ? FETI_EINVAL : rc;
+  };
+  b->P = nprob;
+  for (int p = 0; p < nprob; ++p) {
+    feti_ctx c = ctxs[p];
+    if (!c || c->state < 3) return bad(FETI_ESTATE, "batch of contexts that are not factored");
+    if (c->stream != ctxs[0]->stream)
+      return bad(FETI_EINVAL, "batch contexts on different streams (create them on one non-default stream)");
+    if (c->precision != ctxs[0]->precision) return bad(FETI_EINVAL, "batch contexts of different precision");
+    if (c->precond == FETI_PRECOND_NONE) return bad(FETI_EINVAL, "batch needs a preconditioner");
+    if (c->nc > PCG_NC_LOCAL) return bad(FETI_EINVAL, "coarse space too large for a batch");
+    b->ctx.push_back(c);
+  }
+  b->stream = ctxs[0]->stream;
+  b->f32 = ctxs[0]->precision == FETI_FP32_IR;
+  std::vector<int32_t> tp, ts, tr, rp, rcn, fp, ff;
+  std::vector<ProbArgs> pm(nprob), pc(nprob);
+  std::vector<int64_t> part_off(nprob);
+  int64_t npart = 0;
+  for (int p = 0; p < nprob; ++p) {
+    feti_ctx c = ctxs[p];
+    const MeshHost& h = c->mh;
+    for (int s = 0; s < (int)h.subs.size(); ++s)
+      for (int r0 = 0; r0 < h.subs[s].nb; r0 += 64) { tp.push_back(p); ts.push_back(s); tr.push_back(r0); }
+    const int nri = (int)((c->dm.n_lambda + PCG_BLOCK - 1) / PCG_BLOCK);
+    for (int k = 0; k < nri; ++k) { rp.push_back(p); rcn.push_back(k); }
+    if (c->nc > 0)
+      for (int f = 0; f < c->dm.n_float; ++f) { fp.push_back(p); ff.push_back(f); }
+    b->max_nb = std::max(b->max_nb, c->dm.max_nb);
+    part_off[p] = npart;
+    npart += (int64_t)nri * PCG_NPART;
+    ProbArgs& a = pm[p];
+    const Factors fc = factors(c);
+    a.m = c->dm;
+    a.fm = fc.splus;
+    a.mm = c->precond == FETI_PRECOND_LUMPED ? (const void*)c->Kbb : fc.sbb;
+    if (c->precond == FETI_PRECOND_LUMPED && b->f32) return bad(FETI_EINVAL, "lumped preconditioner in a FP32 batch");
+    a.Cinv = c->Cinv; a.nc = c->nc; a.nrow_items = nri;
+    a.lam = c->lam; a.r = c->r; a.w = c->w; a.z = c->z; a.y = c->y; a.p = c->p; a.q = c->q; a.qraw = c->qraw;
+    a.yb = c->yb; a.zb = c->zb; a.g = c->g; a.mdiag = c->mdiag; a.sc = c->sc; a.ist = c->ist;
+    pc[p] = a;
+    pc[p].lam = c->dlam;
+  }
+  b->ntile = (int)tp.size(); b->nrow = (int)rp.size(); b->nflt = (int)fp.size();
+  int rc = FETI_OK;
+  if ((rc = balloc(b, &b->part, npart))) return bad(rc, "");
+  for (int p = 0; p < nprob; ++p) { pm[p].part = b->part + part_off[p]; pc[p].part = pm[p].part; }
+  if ((rc = bupload(b, &b->d_main, pm)) || (rc = bupload(b, &b->d_corr, pc)) ||
+      (rc = bupload(b, &b->tile_prob, tp)) || (rc = bupload(b, &b->tile_sub, ts)) ||
+      (rc = bupload(b, &b->tile_row0, tr)) || (rc = bupload(b, &b->row_prob, rp)) ||
+      (rc = bupload(b, &b->row_chunk, rcn)) || (rc = bupload(b, &b->flt_prob, fp)) ||
+      (rc = bupload(b, &b->flt_f, ff)) || (rc = balloc(b, &b->alpha, nprob)) || (rc = balloc(b, &b->beta, nprob)) ||
+      (rc = balloc(b, &b->rho, nprob)) || (rc = balloc(b, &b->done, nprob)) || (rc = balloc(b, &b->iters, nprob)) ||
+      (rc = balloc(b, &b->status, nprob)) || (rc = balloc(b, &b->ndone, 1)) || (rc = balloc(b, &b->bar, 1)))
+    return bad(rc, "");
+  if (hipHostMalloc((void**)&b->h_buf, 2 * nprob * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+    return bad(FETI_ENOMEM, "");
+  if (hipEventCreate(&b->e0) != hipSuccess || hipEventCreate(&b->e1) != hipSuccess) return bad(FETI_EHIP, "");
+  const int maxg = pcg_batch_max_grid(b->max_nb);
+  (void)hipGetLastError();
+  if (maxg < 1) return bad(FETI_EHIP, "cooperative launch unavailable for the batch kernel");
+  int cus = 0, dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  for (int g : {cus / 2, cus, 2 * cus, 3 * cus, 4 * cus})
+    if (g >= 1 && g <= maxg && std::find(b->cand.begin(), b->cand.end(), g) == b->cand.end()) b->cand.push_back(g);
+  if (b->cand.empty()) b->cand.push_back(maxg);
+  b->cost.assign(b->cand.size(), 0.0);
+  b->grid = b->cand[0];
+  *out = b;
+  return FETI_OK;
+}
+
+int feti_batch_destroy(feti_batch b) {
+  if (!b) return FETI_EINVAL;
+  (void)hipStreamSynchronize(b->stream);
+  for (void* p : b->allocs) (void)hipFree(p);
+  if (b->h_buf) (void)hipHostFree(b->h_buf);
+  if (b->e0) (void)hipEventDestroy(b->e0);
+  if (b->e1) (void)hipEventDestroy(b->e1);
+  delete b;
+  return FETI_OK;
+}
+
+const char* feti_batch_last_error(feti_batch b) { return b ? b->err.c_str() : "null batch"; }
+
+int feti_batch_set_grid(feti_batch b, int32_t grid) {
+  if (!b || grid < 0) return FETI_EINVAL;
+  if (grid == 0) {
+    b->tuned = false;
+    b->trial = 0;
+    b->cost.assign(b->cand.size(), 0.0);
+    return FETI_OK;
+  }
+  const int maxg = pcg_batch_max_grid(b->max_nb);
+  if (grid > maxg) return bfail(b, FETI_EINVAL, "grid larger than the co-resident maximum");
+  b->grid = grid;
+  b->tuned = true;
+  return FETI_OK;
+}
+
+int feti_batch_info(feti_batch b, int32_t* info) {
+  if (!b || !info) return FETI_EINVAL;
+  info[0] = b->tuned ? b->grid : b->cand[b->trial % b->cand.size()];
+  info[1] = b->tuned ? 1 : 0;
+  info[2] = (int32_t)std::min<size_t>(b->cand.size(), 8);
+  for (int k = 0; k < info[2]; ++k) info[3 + k] = b->cand[k];
+  return FETI_OK;
+}
+
+int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts* o, feti_stats* stats) {
+  if (!b || !loads || !o) return FETI_EINVAL;
+  if (!(o->tol > 0.0) || o->max_it < 1) return bfail(b, FETI_EINVAL, "bad solve options");
+  if (o->start == FETI_START_GIVEN || o->start == FETI_START_BEST)
+    return bfail(b, FETI_EINVAL, "a batch step starts from the previous, extrapolated or zero multipliers");
+  const int P = b->P;
+  std::vector<feti_stats> acc(P);
+  for (auto& s : acc) std::memset(&s, 0, sizeof(s));
+  hipStream_t st = b->stream;
+  BCHK(hipEventRecord(b->ctx[0]->ev[0], st));
+  bool cold = false;
+  for (int p = 0; p < P; ++p) {
+    feti_ctx ctx = b->ctx[p];
+    DevMesh& m = ctx->dm;
+    launch_rhs(m, ctx->u, ctx->f, ctx->mpP, ctx->mpE, make_load(ctx, &loads[p]), st);
+    int used = o->start;
+    if (o->start == FETI_START_ZERO || !ctx->have_prev) {
+      launch_zero(m.n_lambda, ctx->lam, st);
+      used = FETI_START_ZERO;
+    } else if (o->start == FETI_START_EXTRAPOLATE && ctx->have_prev2) {
+      launch_axpby(m.n_lambda, 2.0, ctx->lam_prev, -1.0, ctx->lam_prev2, ctx->lam, st);
+    } else {
+      launch_axpby(m.n_lambda, 1.0, ctx->lam_prev, 0.0, nullptr, ctx->lam, st);
+      used = FETI_START_PREVIOUS;
+    }
+    acc[p].start_used = used;
+    cold = cold || !ctx->have_prev;
+    BRC(torn_begin(ctx, o, o->tol, ctx->f, nullptr, ctx->lam));
+  }
+  BRC(run_batch(b, false, acc));
+  for (int p = 0; p < P; ++p) {
+    acc[p].iters_first = acc[p].iters;
+    BRC(torn_end(b->ctx[p], b->ctx[p]->lam, b->ctx[p]->u));
+  }
+  const int nref = cold ? std::max(o->ir_cold, o->ir_max) : o->ir_max;
+  for (int k = 0; k < nref; ++k) {
+    for (int p = 0; p < P; ++p) {
+      feti_ctx ctx = b->ctx[p];
+      torn_residual(ctx, ctx->f, ctx->u, ctx->lam);
+      launch_zero(ctx->dm.n_lambda, ctx->dlam, st);
+      BRC(torn_begin(ctx, o, o->tol_corr, ctx->rf, ctx->cj, ctx->dlam));
+    }
+    BRC(run_batch(b, true, acc));
+    for (int p = 0; p < P; ++p) {
+      feti_ctx ctx = b->ctx[p];
+      BRC(torn_end(ctx, ctx->dlam, ctx->du));
+      launch_axpby(ctx->dm.sum_ns, 1.0, ctx->u, 1.0, ctx->du, ctx->u, st);
+      launch_axpby(ctx->dm.n_lambda, 1.0, ctx->lam, 1.0, ctx->dlam, ctx->lam, st);
+      acc[p].ir_steps += 1;
+    }
+  }
+  for (int p = 0; p < P; ++p) {
+    feti_ctx ctx = b->ctx[p];
+    std::swap(ctx->lam_prev2, ctx->lam_prev);
+    launch_axpby(ctx->dm.n_lambda, 1.0, ctx->lam, 0.0, nullptr, ctx->lam_prev, st);
+    ctx->have_prev2 = ctx->have_prev;
+    ctx->have_prev = true;
+    ctx->nstep += 1;
+  }
+  BCHK(hipEventRecord(b->ctx[0]->ev[5], st));
+  BCHK(hipGetLastError());
+  BCHK(hipStreamSynchronize(st));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, b->ctx[0]->ev[0], b->ctx[0]->ev[5]);
+  int worst = FETI_OK;
+  for (int p = 0; p < P; ++p) {
+    acc[p].t_ms[5] = ms;
+    if (acc[p].status != 0 && worst == FETI_OK) worst = acc[p].status;
+    if (stats) stats[p] = acc[p];
+  }
+  if (worst != FETI_OK) return bfail(b, worst, "a problem of the batch did not converge");
+  return FETI_OK;
+}
+
 
 }  // extern "C"

@@ -25,6 +25,9 @@ enum { IS_DONE = 0, IS_ITERS = 1, IS_STATUS = 2, IS_MAXIT = 3, IS_CNT0 = 4, IS_C
 enum { PH_REFNORM = 0, PH_INIT = 1, PH_ALPHA = 2, PH_CONV = 3, PH_BETA = 4 };
 
 void launch_sgemv(const DevMesh& m, const GemvArgs& a, hipStream_t st);
+// scalar state of a solve (tolerance, iteration cap, everything else zero)
+void launch_init_scalars(double* sc, int32_t* ist, double tol, int maxit, hipStream_t st);
+void launch_zero(int64_t n, double* z, hipStream_t st);
 // out = jump (or (B B^T)^{-1}-weighted jump) of yb; with g, also g = G^T out
 void launch_jump(const DevMesh& m, const double* yb, int from_torn, double* out, int scaled,
                  double* g, const int32_t* skip, hipStream_t st);

@@ -490,7 +490,29 @@ __global__ void __launch_bounds__(256) k_kind_maxabs(DevMesh m, const double* __
   if (threadIdx.x < 12) part[blockIdx.x * 12 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// scalar state of a solve: every slot cleared, the tolerance and the iteration cap set
+__global__ void k_init_scalars(double* __restrict__ sc, int32_t* __restrict__ ist, double tol, int maxit) {
+  const int t = threadIdx.x;
+  if (t < SC_COUNT) sc[t] = t == SC_TOL ? tol : 0.0;
+  if (t < IS_COUNT) ist[t] = t == IS_MAXIT ? maxit : 0;
+}
+
+// z = 0 (a kernel, so that graph captures hold no memset nodes)
+__global__ void k_zero(int64_t n, double* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = 0.0;
+}
+
 // ---- launchers ---------------------------------------------------------------
+
+void launch_init_scalars(double* sc, int32_t* ist, double tol, int maxit, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, sc, ist, tol, maxit);
+}
+
+void launch_zero(int64_t n, double* z, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, z);
+}
+
 
 void launch_sub_gather(const DevMesh& m, const double* lam, double* r, hipStream_t st) {
   const int blk = 256;

@@ -25,197 +25,22 @@
 // flag, every block leaves at its next barrier, and the host reports an error.
 #include <algorithm>
 
-#include "iface.h"
-#include "iface_device.h"
-#include "kernels.h"
-#include "pcg.h"
+#include "pcg_device.h"
 
 namespace feti {
 
-constexpr int PB = PCG_BLOCK;
-constexpr long long PCG_SPIN_LIMIT = 1ll << 21;
-
-// Data that one block writes and another reads within the launch (the multiplier
-// vectors p, y, w, q, q_raw, z, the interface-space vectors, g and the partial
-// sums) moves through device-coherent
-// loads and stores (agent-scope relaxed atomics: no cache flush is needed);
-// everything a thread reads back only itself, and the read-only matrices, use
-// plain accesses.
-__device__ inline double ald(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void ast(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Grid-wide barrier; returns false when the launch is being aborted.  Arrival
-// counters only grow (the host clears them before a launch): a group's counter
-// reaches (k + 1) * group size at barrier k, its last block then counts the group
-// at the top level, and the last group publishes gen = k + 1.
-// Every thread waits for its own stores to complete before its block arrives.
-__device__ bool grid_sync(GridBarrier* b, uint32_t nblk, uint32_t& gen, int* s_ok) {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    // two levels: groups of PCG_BAR_GROUP blocks, then the groups
-    const uint32_t grp = blockIdx.x / PCG_BAR_GROUP;
-    const uint32_t ngrp = (nblk + PCG_BAR_GROUP - 1) / PCG_BAR_GROUP;
-    const uint32_t gsize = min((uint32_t)PCG_BAR_GROUP, nblk - grp * PCG_BAR_GROUP);
-    int ok = 1;
-    bool last = false;
-    const uint32_t p1 =
-        __hip_atomic_fetch_add(&b->grp[grp * PCG_BAR_STRIDE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (p1 == (gen + 1) * gsize - 1) {
-      const uint32_t p2 = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      last = p2 == (gen + 1) * ngrp - 1;
-    }
-    if (last) {
-      __hip_atomic_store(&b->gen, gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      long long spins = 0;
-      while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= gen) {
-        if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
-        if (++spins > PCG_SPIN_LIMIT) {
-          __hip_atomic_store(&b->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    gen += 1;
-    *s_ok = ok;
-  }
-  __syncthreads();
-  return *s_ok != 0;
-}
-
-// jump of row j of the interface-space vector yb (signed sum of its two entries)
-__device__ inline double pjump_raw(const DevMesh& m, const double* yb, int64_t r) {
-  return m.jr_sign[2 * r] * ald(yb + m.jr_b[2 * r]) + m.jr_sign[2 * r + 1] * ald(yb + m.jr_b[2 * r + 1]);
-}
-__device__ inline double pjump_row(const DevMesh& m, const double* yb, int64_t j, int scaled) {
-  if (!scaled) return pjump_raw(m, yb, j);
-  const int gs = m.grp_start[j], gz = m.grp_size[j];
-  double s = 0.0;
-  for (int k = 0; k < gz; ++k) s += m.dwt[3 * j + k] * pjump_raw(m, yb, gs + k);
-  return s;
-}
-
-// Deterministic block-wide sums of v[0..NV); the result is valid in every thread.
-template <int NV>
-__device__ void block_sum(double (&v)[NV], double* red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    double x = v[c];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    v[c] = x;
-  }
-  __syncthreads();
-  if (lane == 0)
-#pragma unroll
-    for (int c = 0; c < NV; ++c) red[wave * NV + c] = v[c];
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    double s = 0.0;
-    for (int wv = 0; wv < PB / 64; ++wv) s += red[wv * NV + c];
-    v[c] = s;
-  }
-  __syncthreads();
-}
-
-// Sum of the per-block partials part[b][0..NV) over all blocks, in block order.
-template <int NV>
-__device__ void grid_total(const double* part, int nblk, double (&v)[NV], double* red) {
-#pragma unroll
-  for (int c = 0; c < NV; ++c) v[c] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += PB)
-#pragma unroll
-    for (int c = 0; c < NV; ++c) v[c] += ald(part + b * PCG_NPART + c);
-  block_sum<NV>(v, red);
-}
-
-// Phases A and E: yout_b = A_s x_b for every 64-row tile of every interface block.
-// SCALED = 0: x_b = B_s^T p with p = src + beta src2; SCALED = 1: x_b = B_s^T D src.
-// Each half of the block (four wavefronts) takes one tile; its wavefronts split the
-// column range and combine in LDS.
+// Phases A and E: every 64-row tile of every interface block, two tiles per block
+// at a time (one per half).
 template <class MT, int SCALED>
 __device__ void gemv_phase(const PcgArgs& a, const MT* A, const double* src, const double* src2,
                            double beta, double* yout, double* xs2, double* red8) {
   const DevMesh& m = a.m;
   const int half = threadIdx.x / 256, ht = threadIdx.x % 256;
-  const int wave = ht >> 6, lane = ht & 63;
-  double* xs = xs2 + half * m.max_nb;
-  double* red4 = red8 + half * 256;
   for (int t2 = blockIdx.x; 2 * t2 < a.ntile; t2 += gridDim.x) {
     const int t = 2 * t2 + half;
     const bool valid = t < a.ntile;
-    const int s = valid ? a.tile_sub[t] : 0, row0 = valid ? a.tile_row0[t] : 0;
-    const int nbs = valid ? m.nb[s] : 0;
-    const int64_t b0 = m.boff[s];
-    __syncthreads();  // xs and red4 of the previous tiles are consumed
-    for (int i = ht; i < nbs; i += 256) {
-      const int64_t gb = b0 + i;
-      double v = 0.0;
-      // branch-free: an absent entry reads row 0 with weight 0, so that all loads
-      // of the gather are in flight together
-      if (SCALED) {
-        int r[3];
-        double wt[3], x[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const int rk = m.bd_row[3 * gb + k];
-          r[k] = rk >= 0 ? rk : 0;
-          wt[k] = rk >= 0 ? m.bd_wt[3 * gb + k] : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) x[k] = ald(src + r[k]);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) v += wt[k] * x[k];
-      } else {
-        const int q0 = m.bg_row[2 * gb], q1 = m.bg_row[2 * gb + 1];
-        const int r0 = q0 >= 0 ? q0 : 0, r1 = q1 >= 0 ? q1 : 0;
-        const double s0 = q0 >= 0 ? m.bg_sign[2 * gb] : 0.0, s1 = q1 >= 0 ? m.bg_sign[2 * gb + 1] : 0.0;
-        const double y0 = ald(src + r0), p0 = ald(src2 + r0), y1 = ald(src + r1), p1 = ald(src2 + r1);
-        v = s0 * (y0 + beta * p0);
-        v += s1 * (y1 + beta * p1);
-      }
-      xs[i] = v;
-    }
-    __syncthreads();
-    const int i = row0 + lane;
-    const int kq = (nbs + 3) / 4;
-    const int kb = wave * kq, ke = min(nbs, kb + kq);
-    const MT* As = A + m.sofs[s];
-    const int64_t ld = m.ldb[s];
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-    if (i < nbs) {
-      // batches of eight independent column loads in flight before their FMAs
-      const MT* col = As + (int64_t)kb * ld + i;
-      int k = kb;
-      for (; k + 8 <= ke; k += 8, col += 8 * ld) {
-        MT v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = col[(int64_t)u * ld];
-        acc0 += (double)v[0] * xs[k + 0];
-        acc1 += (double)v[1] * xs[k + 1];
-        acc2 += (double)v[2] * xs[k + 2];
-        acc3 += (double)v[3] * xs[k + 3];
-        acc0 += (double)v[4] * xs[k + 4];
-        acc1 += (double)v[5] * xs[k + 5];
-        acc2 += (double)v[6] * xs[k + 6];
-        acc3 += (double)v[7] * xs[k + 7];
-      }
-      for (; k < ke; ++k, col += ld) acc0 += (double)col[0] * xs[k];
-    }
-    red4[wave * 64 + lane] = (acc0 + acc1) + (acc2 + acc3);
-    __syncthreads();
-    if (wave == 0 && i < nbs)
-      ast(yout + b0 + i, (red4[lane] + red4[64 + lane]) + (red4[128 + lane] + red4[192 + lane]));
+    gemv_tile<MT, SCALED>(m, A, valid ? a.tile_sub[t] : 0, valid ? a.tile_row0[t] : 0, valid, src, src2, beta,
+                          yout, xs2 + half * m.max_nb, red8 + half * 256, ht);
   }
 }
 
@@ -345,8 +170,9 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
   double rho = a.sc[SC_RHO], beta = a.sc[SC_BETA], alpha = a.sc[SC_ALPHA], res = a.sc[SC_RES];
   int iters = a.ist[IS_ITERS];
   const int maxit = a.ist[IS_MAXIT];
-  int status = 0;
+  int status = a.ist[IS_STATUS];
   bool ok = true;
+  const bool start_done = a.ist[IS_DONE] != 0 || iters >= maxit;  // the same in every block
   int rk = 0;  // reductions so far: partial buffer rk & 1
   auto partbuf = [&](int k) { return a.part + (size_t)(k & 1) * nblk * PCG_NPART; };
   double conv[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -357,7 +183,7 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
     ++ph;
   };
   stamp();
-  for (;; ++it_local, ph = 1) {  // stamp 0 of a later iteration is stamp 8 of the one before
+  for (; !start_done; ++it_local, ph = 1) {  // stamp 0 of a later iteration is stamp 8 of the one before
     // (A) y_b = (K^+)_bb B^T p,  p = y + beta p_old
     if (a.fm32) gemv_phase<float, 0>(a, (const float*)a.fm, a.y, a.p, beta, a.yb, xs, red4);
     else gemv_phase<double, 0>(a, (const double*)a.fm, a.y, a.p, beta, a.yb, xs, red4);

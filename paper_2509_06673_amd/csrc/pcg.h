@@ -48,6 +48,47 @@ struct PcgArgs {
   int tstamp_iters = 0;         // iterations recorded (8 stamps each)
 };
 
+// One problem of a batch (device array): its mesh tables, operators and vectors.
+struct ProbArgs {
+  DevMesh m;
+  const void* fm = nullptr;  // interface blocks (K_s^+)_bb
+  const void* mm = nullptr;  // preconditioner blocks
+  const double* Cinv = nullptr;
+  int nc = 0;
+  int nrow_items = 0;        // chunks of PCG_BLOCK multiplier rows
+  double *lam = nullptr, *r = nullptr, *w = nullptr, *z = nullptr, *y = nullptr, *p = nullptr,
+         *q = nullptr, *qraw = nullptr, *yb = nullptr, *zb = nullptr, *g = nullptr;
+  const double* mdiag = nullptr;
+  double* part = nullptr;    // nrow_items x PCG_NPART partial sums
+  double* sc = nullptr;
+  int32_t* ist = nullptr;
+};
+
+// The interface iterations of many independent problems in one cooperative launch.
+// Work lists span all problems; each problem keeps its own scalars (published by the
+// block with blockIdx = problem mod grid between barriers).
+struct BatchArgs {
+  const ProbArgs* probs = nullptr;
+  int P = 0;
+  int f32 = 0;  // every problem stores its blocks in float (1) or double (0)
+  const int32_t *tile_prob = nullptr, *tile_sub = nullptr, *tile_row0 = nullptr;
+  int ntile = 0;
+  const int32_t *row_prob = nullptr, *row_chunk = nullptr;  // chunks of PCG_BLOCK rows
+  int nrow = 0;
+  const int32_t *flt_prob = nullptr, *flt_f = nullptr;      // floating subdomains
+  int nflt = 0;
+  double *alpha = nullptr, *beta = nullptr, *rho = nullptr;  // per problem
+  int32_t* done = nullptr;    // per problem
+  int32_t* iters = nullptr;   // per problem: iterations of this launch
+  int32_t* status = nullptr;  // per problem: status at the end of this launch
+  int32_t* ndone = nullptr;   // problems finished
+  GridBarrier* bar = nullptr;
+  int max_nb = 0;
+};
+size_t pcg_batch_shmem(int max_nb);
+int pcg_batch_max_grid(int max_nb);
+hipError_t launch_pcg_batch(const BatchArgs& a, int grid, hipStream_t st);
+
 // dynamic LDS bytes of the launch
 size_t pcg_shmem(const DevMesh& m);
 // largest co-resident grid of the persistent kernel on the current device (0: none)

@@ -1,0 +1,100 @@
+"""Batched time steps: independent problems of uneven size in one cooperative launch
+per solve.  A seeded subset of 16 of the 256 draws steps as one batch; every
+problem must match its own single-problem run (same discretisation, same
+tolerances; the iterates differ only in reduction order) and, for the whole subset,
+the FP64 oracle at the 1e-8 bar of the FP64 path.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from feti_helpers import require_gpu, oracle_reference, torn_reference, per_kind_rel_error, sub_poro_flags
+
+pytestmark = pytest.mark.gpu
+
+B = pytest.importorskip("paper_2509_06673_amd._binding")
+from paper_2509_06673_amd.workload import setup, load, opts, mesh_args, material  # noqa: E402
+
+FP64_TOL = 1e-8
+
+
+def _subset(k=16, seed=3):
+    draws = W.batched_draws()
+    idx = np.sort(np.random.default_rng(seed).choice(len(draws), size=k, replace=False))
+    return [draws[i] for i in idx]
+
+
+_STREAM = []
+
+
+def _stream():
+    # a batch needs its contexts on one stream, and not the null stream (a context
+    # given the null stream makes a stream of its own)
+    import torch
+    if not _STREAM:
+        _STREAM.append(torch.cuda.Stream())
+    return _STREAM[0]
+
+
+def _ctx(w, keep=True):
+    f = B.Feti(_stream())
+    f.setup_mesh(**mesh_args(w))
+    f.assemble(material(w.mat_p), material(w.mat_e), w.tau)
+    f.set_keep_assembled(keep)
+    f.factor_subdomains(B.FP64, B.PRECOND_DIRICHLET)
+    f.init_state(load(w, 0.0))
+    return f
+
+
+def test_batch_matches_single_runs_and_oracle():
+    import torch
+    require_gpu()
+    ws = _subset()
+    nsteps = 2
+    print("[batch] " + " ".join(w.name for w in ws), flush=True)
+    ctxs = [_ctx(w, keep=False) for w in ws]
+    batch = B.Batch(ctxs)
+    o = opts(tol=1e-10, max_it=3000)
+    for n in range(1, nsteps + 1):
+        st, rc = batch.step([load(w, n * w.tau) for w in ws], o)
+        _stream().synchronize()
+        print(f"  step {n}: iterations per problem {[s['iters'] for s in st]} grid {batch.info()}", flush=True)
+        assert rc == 0 and all(s["status"] == 0 for s in st)
+    for k, (w, f) in enumerate(zip(ws, ctxs)):
+        idx = f.export_indexing()
+        codes = idx["code"].astype(np.int64)
+        u = torch.empty(len(codes), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        f.get_solution(u)
+        ub = u.cpu().numpy()
+        g = setup(w)
+        for n in range(1, nsteps + 1):
+            g.step(load(w, n * w.tau), o)
+        g.get_solution(u)
+        us = u.cpu().numpy()
+        g.close()
+        _, lats = oracle_reference(w, nsteps)
+        ref = torn_reference(codes, idx["sub_offset"], sub_poro_flags(w), lats[-1])
+        e_single = per_kind_rel_error(codes, ub, us)
+        e_oracle = per_kind_rel_error(codes, ub, ref)
+        print(f"  {w.name}: vs single {max(e_single.values()):.1e}, vs oracle {max(e_oracle.values()):.1e}",
+              flush=True)
+        assert max(e_single.values()) < FP64_TOL, (w.name, e_single)
+        assert max(e_oracle.values()) < FP64_TOL, (w.name, e_oracle)
+    batch.close()
+    for f in ctxs:
+        f.close()
+
+
+def test_in_place_factors_refuse_export_and_refactor():
+    require_gpu()
+    import torch
+    w = W.plain_fp64_small()
+    f = _ctx(w, keep=False)
+    n = f.get_sizes()["max_ns"]
+    out = torch.empty(n * n, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.FetiError):
+        f.export_local(0, B.EXPORT_K, out)
+    with pytest.raises(B.FetiError):
+        f.factor_subdomains(B.FP64, B.PRECOND_DIRICHLET)
+    f.close()
