@@ -28,23 +28,34 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 
-# HBM bytes per launch of the interface-block GEMV (k_sgemv<0>, the F and M applications)
-# from two rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
-# reads for a 256 MiB copy; see profiles/feti_step_xsplit_p2_h128_8x8_traffic.md).  The figure
-# belongs to the kernel source it was measured on: a different source hash reports null.
-MEASURED_TRAFFIC = {"source": "paper_2509_06673_amd/csrc/kernels_iface.hip",
-                    "sha256_16": "6c7d3a56c1f10d28",
-                    "bytes_per_launch": (31125.75 * 1.99982 + 171.03) * 1024}
+# HBM bytes per PCG iteration of the persistent interface kernel (FP64 variant), from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, summed over the kernel's dispatches and
+# divided by the iterations those dispatches ran; each counter scaled by what it reads for
+# a 256 MiB copy).  The figure belongs to the kernel sources it was measured on: another
+# source hash reports null.
+MEASURED_TRAFFIC = {"sources": ["paper_2509_06673_amd/csrc/kernels_pcg.hip",
+                                "paper_2509_06673_amd/csrc/pcg_device.h"],
+                    "sha256_16": "136d483f3c2a15ed",
+                    "bytes_per_iteration": (38099225.2 * 1.99982 + 547345.0) * 1024 / 509}
 
 
-def measured_traffic():
+def source_hash(paths):
     import hashlib
-    path = os.path.join(ROOT, MEASURED_TRAFFIC["source"])
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(variant):
+    if variant != "fp64" or MEASURED_TRAFFIC["bytes_per_iteration"] is None:
+        return None
     try:
-        sha = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+        sha = source_hash(MEASURED_TRAFFIC["sources"])
     except OSError:
         return None
-    return MEASURED_TRAFFIC["bytes_per_launch"] if sha == MEASURED_TRAFFIC["sha256_16"] else None
+    return MEASURED_TRAFFIC["bytes_per_iteration"] if sha == MEASURED_TRAFFIC["sha256_16"] else None
 
 
 def p_lattice_from_torn(codes, u, ncell):
@@ -294,8 +305,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--variant", default="fp64", choices=["fp64", "mixed"],
-                    help="fp64: FP64 factors; mixed: FP32 factors on the matrix cores with FP64 refinement")
+    ap.add_argument("--variant", default="both", choices=["fp64", "mixed", "both"],
+                    help="fp64: FP64 factors; mixed: FP32 factors on the matrix cores with FP64 "
+                         "refinement; both: fp64 is the headline value and mixed is reported beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -328,103 +340,33 @@ def main():
         return
 
     import torch
-    import workloads as W
-    from paper_2509_06673_amd import _binding as B
-    from paper_2509_06673_amd.workload import load, opts, opts_mixed, mesh_args, material
-
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    import workloads as W
     w = W.nearly_incompressible_large()
-    stream = torch.cuda.current_stream()
-    f = B.Feti(stream)
-    f.setup_mesh(**mesh_args(w))
-    sizes = f.get_sizes()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    f.assemble(material(w.mat_p), material(w.mat_e), w.tau)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    precision = B.FP32_IR if args.variant == "mixed" else B.FP64
-    f.factor_subdomains(precision, B.PRECOND_DIRICHLET)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    f.init_state(load(w, 0.0))
-    mk = opts_mixed if args.variant == "mixed" else opts
-    o = mk(tol=w.tol, max_it=2000, start=B.START_PREVIOUS, check_every=args.check_every)
-    iters_first = []
-    ir_steps = []
-    n = 0
-    iters = []
-    for _ in range(args.warmup):
-        n += 1
-        f.step(load(w, n * w.tau), o)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    ta = time.perf_counter()
-    for _ in range(args.steps):
-        n += 1
-        st = f.step(load(w, n * w.tau), o)
-        iters.append(st["iters"])
-        iters_first.append(st["iters_first"])
-        ir_steps.append(st["ir_steps"])
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    elapsed = tb - ta
-    ms_per_step = 1000.0 * elapsed / args.steps
-    value = args.steps / elapsed
-    setup_s = (t1 - t0) + (t2 - t1)
-    amortised = w.nsteps / (setup_s + w.nsteps * elapsed / args.steps)
-
-    # roofline of the per-step kernels (HIP events on the context stream)
-    ls_ms, ls_bytes = f.time_kernel(B.KERNEL_LOCAL_SOLVE, 20)
-    if_ms, if_bytes = f.time_kernel(B.KERNEL_IFACE_GEMV, 50)
-    pc_ms, pc_bytes = f.time_kernel(B.KERNEL_PRECOND_GEMV, 50)
-    el_ms, el_flops = f.time_kernel(B.KERNEL_ELIMINATION, 1)
-    it_mean = sum(iters) / len(iters)
-    # the interface-block GEMV (F and M applications, 2 launches per PCG iteration) is the
-    # kernel that moves the most bytes per step; the roofline is quoted on its F launch
-    achieved = if_bytes / (if_ms * 1e-3) / 1e9
-    share_ms = {"iface_and_precond_gemv": (it_mean + 1) * (if_ms + pc_ms), "local_solve": 2 * ls_ms}
-    kernels = {
-        "local_solve_sgemv": {"avg_ms": ls_ms, "GB/s": ls_bytes / (ls_ms * 1e-3) / 1e9},
-        "iface_sgemv": {"avg_ms": if_ms, "GB/s": if_bytes / (if_ms * 1e-3) / 1e9},
-        "precond_sgemv": {"avg_ms": pc_ms, "GB/s": pc_bytes / (pc_ms * 1e-3) / 1e9},
-        "elimination": {"ms": el_ms, "TFLOP/s": el_flops / (el_ms * 1e-3) / 1e12,
-                        "frac_peak": el_flops / (el_ms * 1e-3) / 1e12
-                        / (FP32_PEAK_TFS if args.variant == "mixed" else FP64_PEAK_TFS)},
-    }
+    variants = ["fp64", "mixed"] if args.variant == "both" else [args.variant]
+    res = {v: run_variant(args, w, v) for v in variants}
+    prim = res[variants[0]]
     out = {
         "metric": "time steps/s and PCG iters at rel. residual 1e-10",
-        "value": value,
+        "value": prim["value"],
         "unit": "time steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": prim["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if args.variant == "mixed" else "f64",
+        "dtype": prim["dtype"],
         "data": "synthetic",
-        "config": {"workload": w.name, "variant": args.variant, "n_sub": sizes["n_sub"],
-                   "n_lambda": sizes["n_lambda"], "sum_ns": sizes["sum_ns"],
-                   "max_ns": sizes["max_ns"], "max_nb": sizes["max_nb"], "tol": w.tol},
-        "pcg_iters_mean": it_mean,
-        "pcg_iters": iters,
-        "pcg_iters_first_solve": iters_first,
-        "refinement_corrections": ir_steps,
-        "setup_s": {"assemble": t1 - t0, "factor": t2 - t1},
-        "amortised_steps_per_s": amortised,
-        "roofline": {"bound": "hbm", "kernel": "k_sgemv<0> (interface block, F application)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.variant == "fp64" else None,
-                     "algorithmic_bytes_per_launch": if_bytes},
-        "gemv_ms_per_step": share_ms,
-        "kernels": kernels,
+        "config": {"workload": w.name, "variant": variants[0], **prim["sizes"], "tol": w.tol},
+        "pcg_iters_mean": prim["pcg_iters_mean"],
+        "roofline": prim["roofline"],
+        "variants": {v: {k: r[k] for k in ("value", "ms_per_step", "amortised_steps_per_s", "setup_s",
+                                          "pcg_iters_mean", "pcg_iters_first_solve", "refinement_corrections",
+                                          "pcg_us_per_iteration", "pcg_iters_all_steps", "kernels", "dtype")}
+                     for v, r in res.items()},
     }
     if args.calibrate_copy_mb > 0:
         nbytes = args.calibrate_copy_mb * (1 << 20)
@@ -437,8 +379,97 @@ def main():
         out["calibration_copy_bytes"] = nbytes
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
-    f.close()
     print(json.dumps(out), flush=True)
+
+
+def pcg_bytes_per_iteration(sub_nb, n_lambda, nc, esz):
+    """Algorithmic HBM bytes of one iteration of the interface PCG: the interface
+    blocks of F and of the preconditioner read once each, H = G (G^T G)^{-1} read by
+    the two projections, the interface-space products written and read once each, and
+    about twenty multiplier-vector passes."""
+    blocks = sum(int(n) * int(n) for n in sub_nb) * esz
+    sum_nb = sum(int(n) for n in sub_nb)
+    return 2 * blocks + 2 * nc * n_lambda * 8 + 4 * sum_nb * 8 + 20 * n_lambda * 8
+
+
+def run_variant(args, w, variant):
+    """One variant of the time step on the 64-subdomain workload: setup, warm-up, timed
+    steps (HIP events around the whole run and, inside the library, around each solve's
+    interface iteration), and the per-kernel figures."""
+    import numpy as np
+    import torch
+    from paper_2509_06673_amd import _binding as B
+    from paper_2509_06673_amd.workload import load, opts, opts_mixed, mesh_args, material
+    stream = torch.cuda.current_stream()
+    f = B.Feti(stream)
+    f.setup_mesh(**mesh_args(w))
+    sizes = f.get_sizes()
+    idx = f.export_indexing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.assemble(material(w.mat_p), material(w.mat_e), w.tau)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    mixed = variant == "mixed"
+    f.factor_subdomains(B.FP32_IR if mixed else B.FP64, B.PRECOND_DIRICHLET)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f.init_state(load(w, 0.0))
+    mk = opts_mixed if mixed else opts
+    o = mk(tol=w.tol, max_it=2000, start=B.START_PREVIOUS, check_every=args.check_every)
+    n = 0
+    warm_iters = []
+    for _ in range(args.warmup):
+        n += 1
+        st = f.step(load(w, n * w.tau), o)
+        warm_iters.append(st["iters"])
+    torch.cuda.synchronize()
+    iters, iters_first, ir_steps, pcg_ms = [], [], [], []
+    ta = time.perf_counter()
+    for _ in range(args.steps):
+        n += 1
+        st = f.step(load(w, n * w.tau), o)
+        iters.append(st["iters"])
+        iters_first.append(st["iters_first"])
+        ir_steps.append(st["ir_steps"])
+        pcg_ms.append(st["t_ms"][2])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - ta
+    setup_s = (t1 - t0) + (t2 - t1)
+    value = args.steps / elapsed
+    esz = 4 if mixed else 8
+    bpi = pcg_bytes_per_iteration(idx["sub_nb"], sizes["n_lambda"], sizes["n_c"], esz)
+    pcg_s = sum(pcg_ms) * 1e-3
+    achieved = sum(iters) * bpi / pcg_s / 1e9
+    ls_ms, ls_bytes = f.time_kernel(B.KERNEL_LOCAL_SOLVE, 20)
+    el_ms, el_flops = f.time_kernel(B.KERNEL_ELIMINATION, 1)
+    peak = FP32_PEAK_TFS if mixed else FP64_PEAK_TFS
+    f.close()
+    return {
+        "value": value, "ms_per_step": 1000.0 * elapsed / args.steps,
+        "amortised_steps_per_s": w.nsteps / (setup_s + w.nsteps * elapsed / args.steps),
+        "setup_s": {"assemble": t1 - t0, "factor": t2 - t1},
+        "dtype": "f32+f64" if mixed else "f64",
+        "sizes": {"n_sub": sizes["n_sub"], "n_lambda": sizes["n_lambda"], "n_c": sizes["n_c"],
+                  "sum_ns": sizes["sum_ns"], "max_ns": sizes["max_ns"], "max_nb": sizes["max_nb"]},
+        "pcg_iters_mean": float(np.mean(iters)), "pcg_iters_first_solve": iters_first,
+        "pcg_iters_all_steps": warm_iters + iters,
+        "refinement_corrections": ir_steps,
+        "pcg_us_per_iteration": 1e6 * pcg_s / max(1, sum(iters)),
+        "roofline": {"bound": "hbm", "kernel": "k_pcg_persistent (interface PCG, one launch per solve)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(variant),
+                     "algorithmic_bytes_per_iteration": bpi,
+                     "note": "achieved = algorithmic bytes per iteration x iterations / time inside the PCG "
+                             "launches (HIP events on the solver stream); traffic = measured HBM bytes per "
+                             "iteration (FETCH_SIZE + WRITE_SIZE, calibrated); a launch runs all iterations "
+                             "of one solve"},
+        "kernels": {
+            "local_solve_sgemv": {"avg_ms": ls_ms, "GB/s": ls_bytes / (ls_ms * 1e-3) / 1e9},
+            "elimination": {"ms": el_ms, "TFLOP/s": el_flops / (el_ms * 1e-3) / 1e12,
+                            "frac_peak": el_flops / (el_ms * 1e-3) / 1e12 / peak},
+        },
+    }
 
 
 if __name__ == "__main__":
