@@ -107,6 +107,8 @@ typedef struct {
     double params[16];
 } feti_load;
 
+enum { FETI_CORR_ZERO = 0, FETI_CORR_PREVIOUS = 1 };
+
 typedef struct {
     double tol;           /* interface tolerance of a solve, e.g. 1e-10, on w = P (d - F lambda):
                              |w_k| <= tol max(|P d|_k, |w^(0)|_k) for every constrained field
@@ -123,6 +125,16 @@ typedef struct {
     double tol_inner;     /* with FETI_FP32_IR factors: tolerance of the first solve of a step
                              (its operators carry FP32 rounding, so a tighter first solve buys
                              nothing that the FP64 corrections do not redo); 0 = tol */
+    double tol_upd;       /* update test of the refinement corrections (0 = off): a correction
+                             also stops once, for every field kind k with nonzero multipliers,
+                             its last three updates |alpha| |p|_k sum to at most
+                             tol_upd |dlambda|_k (e.g. 1e-4).  A correction only has to shrink
+                             the first solve's error by a few orders, and its noise-driven
+                             residual keeps wandering long after its solution has settled. */
+    int32_t corr_start;   /* start of the first refinement correction of a step:
+                             FETI_CORR_ZERO, or FETI_CORR_PREVIOUS = the previous step's total
+                             correction (the rounding that the corrections undo comes from the
+                             same factors applied to a slowly varying load) */
 } feti_solve_opts;
 
 typedef struct {
@@ -184,6 +196,14 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond);
  * Call before feti_factor_subdomains. */
 int feti_set_keep_assembled(feti_ctx ctx, int32_t keep);
 
+/* How the interface iteration runs: FETI_PCG_AUTO (default) runs every iteration of
+ * a solve in one cooperative persistent launch when the device allows it and the
+ * coarse space is small enough, else replays graph-captured chunks of the kernel
+ * chain of an iteration; FETI_PCG_GRAPH always takes the graph chain.  Both follow
+ * Algorithms 1 and 2 with the same stopping tests.  May be called at any time. */
+enum { FETI_PCG_AUTO = 0, FETI_PCG_GRAPH = 1 };
+int feti_set_pcg_mode(feti_ctx ctx, int32_t mode);
+
 /* ---- time stepping ----------------------------------------------------------- */
 
 /* Set eta^0 (the initial fluid content) from a load's initial data: nodal
@@ -235,7 +255,8 @@ const char* feti_batch_last_error(feti_batch b);
 /* One backward-Euler step of every problem (loads[nprob], stats[nprob] may be NULL):
  * right-hand sides, interface solves and recovery as feti_step, with the previous-
  * step, extrapolated or zero start and a fixed number of refinement corrections
- * (opts->ir_max, or ir_cold on a problem's first step). */
+ * (opts->ir_max, or ir_cold on a problem's first step; tol_upd and corr_start as in
+ * feti_step, the start of each problem chosen on the device). */
 int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts* opts, feti_stats* stats);
 
 /* Launch shape: grid > 0 fixes the number of blocks; grid = 0 (the default) lets the

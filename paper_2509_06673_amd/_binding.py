@@ -22,6 +22,8 @@ LOAD_MANUFACTURED, LOAD_PERIODIC, LOAD_POINT_SOURCE, LOAD_PATCH = 0, 1, 2, 3
 FP64, FP32_IR = 0, 1
 PRECOND_DIRICHLET, PRECOND_LUMPED, PRECOND_NONE = 0, 1, 2
 START_PREVIOUS, START_ZERO, START_EXTRAPOLATE, START_GIVEN, START_BEST = 0, 1, 2, 3, 4
+CORR_ZERO, CORR_PREVIOUS = 0, 1
+PCG_AUTO, PCG_GRAPH = 0, 1
 EXPORT_K, EXPORT_SBB, EXPORT_KPLUS = 0, 1, 2
 KERNEL_LOCAL_SOLVE, KERNEL_IFACE_GEMV, KERNEL_PRECOND_GEMV, KERNEL_ELIMINATION = 0, 1, 2, 3
 
@@ -48,7 +50,8 @@ class Load(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("tol_corr", C.c_double), ("ir_tol", C.c_double),
                 ("max_it", C.c_int32), ("start", C.c_int32), ("check_every", C.c_int32),
-                ("ir_max", C.c_int32), ("ir_cold", C.c_int32), ("tol_inner", C.c_double)]
+                ("ir_max", C.c_int32), ("ir_cold", C.c_int32), ("tol_inner", C.c_double),
+                ("tol_upd", C.c_double), ("corr_start", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -96,6 +99,7 @@ _SIGS = {
                          C.POINTER(C.c_double)],
     "feti_interface_load": [C.c_void_p, C.POINTER(Load), C.c_void_p],
     "feti_set_keep_assembled": [C.c_void_p, C.c_int32],
+    "feti_set_pcg_mode": [C.c_void_p, C.c_int32],
     "feti_batch_create": [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32],
     "feti_batch_destroy": [C.c_void_p],
     "feti_batch_step": [C.c_void_p, C.POINTER(Load), C.POINTER(SolveOpts), C.POINTER(Stats)],
@@ -239,6 +243,9 @@ class Feti:
 
     def set_start(self, lam):
         return self._check(self.lib.feti_set_start(self.ctx, _ptr(lam)), "feti_set_start")
+
+    def set_pcg_mode(self, mode: int):
+        return self._check(self.lib.feti_set_pcg_mode(self.ctx, int(mode)), "feti_set_pcg_mode")
 
     def set_keep_assembled(self, keep: bool):
         return self._check(self.lib.feti_set_keep_assembled(self.ctx, 1 if keep else 0),

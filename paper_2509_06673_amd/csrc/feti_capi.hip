@@ -59,6 +59,9 @@ struct feti_ctx_s {
   // vectors
   double *f = nullptr, *u = nullptr, *ytmp = nullptr, *yb = nullptr, *zb = nullptr;
   double *rf = nullptr, *du = nullptr, *dlam = nullptr, *cj = nullptr, *kpart = nullptr;
+  double *dlam_sum = nullptr, *dlam_prev = nullptr;  // corrections of this and of the previous step
+  bool have_dlam_prev = false;
+  int pcg_mode = FETI_PCG_AUTO;
   double* mdiag = nullptr;  // diagonal of the preconditioner (weights of the dual-energy norm)
   double* h_kpart = nullptr;
   double *lam = nullptr, *lam_prev = nullptr, *lam_prev2 = nullptr, *d = nullptr, *r = nullptr,
@@ -227,6 +230,8 @@ int upload_mesh(feti_ctx ctx) {
   RC(dalloc(ctx, &ctx->rf, h.sum_ns, ctx->allocs));
   RC(dalloc(ctx, &ctx->du, h.sum_ns, ctx->allocs));
   RC(dalloc(ctx, &ctx->dlam, h.n_lambda, ctx->allocs));
+  RC(dalloc(ctx, &ctx->dlam_sum, h.n_lambda, ctx->allocs));
+  RC(dalloc(ctx, &ctx->dlam_prev, h.n_lambda, ctx->allocs));
   RC(dalloc(ctx, &ctx->cj, h.n_lambda, ctx->allocs));
   RC(dalloc(ctx, &ctx->mdiag, h.n_lambda, ctx->allocs));
   RC(dalloc(ctx, &ctx->kpart, (size_t)KMAX_NBLK * 12, ctx->allocs));
@@ -400,7 +405,8 @@ void pcg_iteration(feti_ctx ctx, double* lam, const int32_t* done) {
 // vector) and the solution on exit; u receives the recovered torn primal solution.
 // iters_out accumulates the PCG iterations.
 // Dual-energy norm of the projected residual w = P (d - F lam) of an admissible lam.
-int start_residual(feti_ctx ctx, const double* lam, double* norm) {
+// With slot >= 0 the norm stays on the device in sc[slot] (no synchronisation).
+int start_residual(feti_ctx ctx, const double* lam, double* norm, int slot = -1) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
   op_F(ctx, lam, ctx->q, nullptr);
@@ -408,6 +414,10 @@ int start_residual(feti_ctx ctx, const double* lam, double* norm) {
   op_project(ctx, ctx->r, ctx->w, nullptr);
   launch_reduce(m, nullptr, nullptr, ctx->w, ctx->mdiag, ctx->part, counter(ctx, PH_REFNORM), ctx->sc, ctx->ist,
                 PH_REFNORM, st);
+  if (slot >= 0) {
+    launch_copy_scalar(ctx->sc, SC_EREF, slot, st);
+    return FETI_OK;
+  }
   HIPCHK(hipMemcpyAsync(ctx->h_sc, ctx->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   *norm = ctx->h_sc[SC_EREF];
@@ -417,7 +427,9 @@ int start_residual(feti_ctx ctx, const double* lam, double* norm) {
 // First half of a torn solve (no host synchronisation unless a candidate start is
 // compared): d = sum_s B_s K_s^+ f_s - c, the admissible start, the scalar state,
 // the reference norms of P d, and r, w, y, p with rho = (w, y).
-int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, const double* f, const double* cj,
+// took_cand == nullptr with a candidate: the choice is made on the device (no
+// synchronisation, the caller does not learn it).
+int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, const double* f, const double* cj,
                double* lam, const double* cand = nullptr, int* took_cand = nullptr) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
@@ -445,16 +457,22 @@ int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, const double*
     // keep the candidate start if its projected residual is smaller
     launch_axpby(nl, 1.0, cand, 0.0, nullptr, ctx->lam_alt, st);
     admissible(ctx->lam_alt);
-    double n_lam = 0.0, n_alt = 0.0;
-    RC(start_residual(ctx, lam, &n_lam));
-    RC(start_residual(ctx, ctx->lam_alt, &n_alt));
-    if (n_alt < n_lam) {
-      launch_axpby(nl, 1.0, ctx->lam_alt, 0.0, nullptr, lam, st);
-      if (took_cand) *took_cand = 1;
+    if (!took_cand) {
+      RC(start_residual(ctx, lam, nullptr, SC_SEL0));
+      RC(start_residual(ctx, ctx->lam_alt, nullptr, SC_SEL1));
+      launch_pick_start(nl, ctx->sc, ctx->lam_alt, lam, st);
+    } else {
+      double n_lam = 0.0, n_alt = 0.0;
+      RC(start_residual(ctx, lam, &n_lam));
+      RC(start_residual(ctx, ctx->lam_alt, &n_alt));
+      if (n_alt < n_lam) {
+        launch_axpby(nl, 1.0, ctx->lam_alt, 0.0, nullptr, lam, st);
+        *took_cand = 1;
+      }
     }
   }
   // tolerance reference: per-kind norms of P d
-  launch_init_scalars(ctx->sc, ctx->ist, tol, std::max(o->max_it, 0), st);
+  launch_init_scalars(ctx->sc, ctx->ist, tol, utol, std::max(o->max_it, 0), st);
   op_project(ctx, ctx->d, ctx->tl, nullptr);
   launch_reduce(m, nullptr, nullptr, ctx->tl, ctx->mdiag, ctx->part, counter(ctx, PH_REFNORM), ctx->sc,
                 ctx->ist, PH_REFNORM, st);
@@ -491,21 +509,21 @@ int torn_end(feti_ctx ctx, const double* lam, double* u) {
   return FETI_OK;
 }
 
-int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, const double* f, const double* cj,
+int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, const double* f, const double* cj,
                double* lam, double* u, feti_stats* stats, int* iters_out, double* res0,
                double* res, const double* cand = nullptr, int* took_cand = nullptr) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
   HIPCHK(hipEventRecord(ctx->ev[1], st));
-  RC(torn_begin(ctx, o, tol, f, cj, lam, cand, took_cand));
+  RC(torn_begin(ctx, o, tol, utol, f, cj, lam, cand, took_cand));
   HIPCHK(hipEventRecord(ctx->ev[2], st));
   const int32_t* done = ctx->ist + IS_DONE;
   const int chunk = std::max(1, o->check_every);
   static const bool trace = std::getenv("FETI_TRACE") != nullptr;
   static const bool use_graph = std::getenv("FETI_NO_GRAPH") == nullptr;
   static const bool use_persist = std::getenv("FETI_NO_PERSIST") == nullptr;
-  const bool persist = use_persist && !trace && ctx->pgrid > 0 && ctx->nc <= PCG_NC_LOCAL &&
-                       ctx->precond != FETI_PRECOND_NONE;
+  const bool persist = use_persist && !trace && ctx->pcg_mode == FETI_PCG_AUTO && ctx->pgrid > 0 &&
+                       ctx->nc <= PCG_NC_LOCAL && ctx->precond != FETI_PRECOND_NONE;
   if (persist) {
     // every iteration of the solve in one cooperative launch (a solve converged at
     // its start leaves the launch at once)
@@ -635,16 +653,17 @@ void torn_residual(feti_ctx ctx, const double* f, const double* u, const double*
   launch_axpby(m.n_lambda, -1.0, ctx->cj, 0.0, nullptr, ctx->cj, st);
 }
 
-// One FETI solve followed by up to nref FP64 refinement corrections.
+// One FETI solve followed by up to nref FP64 refinement corrections.  history: a time
+// step (its total correction is kept for the next step's first correction).
 int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* stats,
-                  const double* cand = nullptr, int* took_cand = nullptr) {
+                  const double* cand = nullptr, int* took_cand = nullptr, bool history = false) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
   int iters = 0;
   double res0 = 0, res = 0, r0c = 0, rc_ = 0;
   const double tol_first =
       (ctx->precision == FETI_FP32_IR && o->tol_inner > 0.0) ? std::max(o->tol, o->tol_inner) : o->tol;
-  int rc = solve_torn(ctx, o, tol_first, ctx->f, nullptr, ctx->lam, ctx->u, stats, &iters, &res0, &res, cand,
+  int rc = solve_torn(ctx, o, tol_first, 0.0, ctx->f, nullptr, ctx->lam, ctx->u, stats, &iters, &res0, &res, cand,
                       took_cand);
   const int iters_first = iters;
   int done_ir = 0;
@@ -653,10 +672,15 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
   for (int k = 0; k < nref && (rc == FETI_OK || rc == FETI_ENOTCONV); ++k) {
     torn_residual(ctx, ctx->f, ctx->u, ctx->lam);
     HIPCHK(hipMemsetAsync(ctx->dlam, 0, m.n_lambda * sizeof(double), st));
-    rc = solve_torn(ctx, o, o->tol_corr, ctx->rf, ctx->cj, ctx->dlam, ctx->du, stats, &iters, &r0c,
-                    &rc_);
+    // the first correction of a time step may start from the previous step's total
+    // correction, kept only if its projected residual beats the zero start
+    const bool warm = history && k == 0 && o->corr_start == FETI_CORR_PREVIOUS && ctx->have_dlam_prev;
+    rc = solve_torn(ctx, o, o->tol_corr, o->tol_upd, ctx->rf, ctx->cj, ctx->dlam, ctx->du, stats, &iters, &r0c,
+                    &rc_, warm ? ctx->dlam_prev : nullptr);
     launch_axpby(m.sum_ns, 1.0, ctx->u, 1.0, ctx->du, ctx->u, st);
     launch_axpby(m.n_lambda, 1.0, ctx->lam, 1.0, ctx->dlam, ctx->lam, st);
+    launch_axpby(m.n_lambda, 1.0, ctx->dlam, k == 0 ? 0.0 : 1.0, k == 0 ? nullptr : ctx->dlam_sum, ctx->dlam_sum,
+                 st);
     // size of the correction per DOF kind
     launch_kind_maxabs(m, ctx->du, ctx->u, ctx->kpart, KMAX_NBLK, st);
     HIPCHK(hipMemcpyAsync(ctx->h_kpart, ctx->kpart, KMAX_NBLK * 12 * sizeof(double),
@@ -670,6 +694,11 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
       if (mx[6 + kk] > 0.0) corr = std::max(corr, mx[kk] / mx[6 + kk]);
     ++done_ir;
     if (corr <= o->ir_tol) break;
+  }
+  if (history) {
+    // the step's total correction, for the next step
+    if (done_ir > 0 && rc == FETI_OK) std::swap(ctx->dlam_prev, ctx->dlam_sum);
+    ctx->have_dlam_prev = done_ir > 0 && rc == FETI_OK;
   }
   HIPCHK(hipEventRecord(ctx->ev[7], st));
   HIPCHK(hipStreamSynchronize(st));
@@ -862,7 +891,7 @@ int feti_assemble(feti_ctx ctx, const feti_material* P, const feti_material* E, 
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->state = 2;
   ctx->nstep = 0;
-  ctx->have_prev = ctx->have_prev2 = false;
+  ctx->have_prev = ctx->have_prev2 = ctx->have_dlam_prev = false;
   return FETI_OK;
 }
 
@@ -994,7 +1023,7 @@ int feti_init_state(feti_ctx ctx, const feti_load* load) {
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->nstep = 0;
-  ctx->have_prev = ctx->have_prev2 = false;
+  ctx->have_prev = ctx->have_prev2 = ctx->have_dlam_prev = false;
   return FETI_OK;
 }
 
@@ -1032,7 +1061,7 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, fet
   if (stats) std::memset(stats, 0, sizeof(*stats));
   int took = 0;
   const double* cand = (o->start == FETI_START_BEST) ? ctx->lam_given : nullptr;
-  int rc = solve_refined(ctx, o, cold ? std::max(o->ir_cold, o->ir_max) : o->ir_max, stats, cand, &took);
+  int rc = solve_refined(ctx, o, cold ? std::max(o->ir_cold, o->ir_max) : o->ir_max, stats, cand, &took, true);
   if (cand && took) used = FETI_START_GIVEN;
   // keep the multiplier history
   std::swap(ctx->lam_prev2, ctx->lam_prev);
@@ -1214,6 +1243,13 @@ int feti_time_kernel(feti_ctx ctx, int32_t which, int32_t reps, double* avg_ms, 
   return FETI_OK;
 }
 
+
+int feti_set_pcg_mode(feti_ctx ctx, int32_t mode) {
+  if (!ctx) return FETI_EINVAL;
+  if (mode != FETI_PCG_AUTO && mode != FETI_PCG_GRAPH) return fail(ctx, FETI_EINVAL, "unknown PCG mode");
+  ctx->pcg_mode = mode;
+  return FETI_OK;
+}
 
 int feti_set_keep_assembled(feti_ctx ctx, int32_t keep) {
   if (!ctx) return FETI_EINVAL;
@@ -1480,7 +1516,7 @@ int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts*
     }
     acc[p].start_used = used;
     cold = cold || !ctx->have_prev;
-    BRC(torn_begin(ctx, o, o->tol, ctx->f, nullptr, ctx->lam));
+    BRC(torn_begin(ctx, o, o->tol, 0.0, ctx->f, nullptr, ctx->lam));
   }
   BRC(run_batch(b, false, acc));
   for (int p = 0; p < P; ++p) {
@@ -1493,7 +1529,8 @@ int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts*
       feti_ctx ctx = b->ctx[p];
       torn_residual(ctx, ctx->f, ctx->u, ctx->lam);
       launch_zero(ctx->dm.n_lambda, ctx->dlam, st);
-      BRC(torn_begin(ctx, o, o->tol_corr, ctx->rf, ctx->cj, ctx->dlam));
+      const bool warm = k == 0 && o->corr_start == FETI_CORR_PREVIOUS && ctx->have_dlam_prev;
+      BRC(torn_begin(ctx, o, o->tol_corr, o->tol_upd, ctx->rf, ctx->cj, ctx->dlam, warm ? ctx->dlam_prev : nullptr));
     }
     BRC(run_batch(b, true, acc));
     for (int p = 0; p < P; ++p) {
@@ -1501,8 +1538,15 @@ int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts*
       BRC(torn_end(ctx, ctx->dlam, ctx->du));
       launch_axpby(ctx->dm.sum_ns, 1.0, ctx->u, 1.0, ctx->du, ctx->u, st);
       launch_axpby(ctx->dm.n_lambda, 1.0, ctx->lam, 1.0, ctx->dlam, ctx->lam, st);
+      launch_axpby(ctx->dm.n_lambda, 1.0, ctx->dlam, k == 0 ? 0.0 : 1.0, k == 0 ? nullptr : ctx->dlam_sum,
+                   ctx->dlam_sum, st);
       acc[p].ir_steps += 1;
     }
+  }
+  for (int p = 0; p < P; ++p) {
+    feti_ctx ctx = b->ctx[p];
+    if (nref > 0) std::swap(ctx->dlam_prev, ctx->dlam_sum);
+    ctx->have_dlam_prev = nref > 0;
   }
   for (int p = 0; p < P; ++p) {
     feti_ctx ctx = b->ctx[p];

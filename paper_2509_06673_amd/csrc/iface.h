@@ -7,7 +7,8 @@ namespace feti {
 
 constexpr int RED_BLOCK = 256;   // threads of the partial-sum kernels
 constexpr int RED_NBLK = 512;    // cap on the blocks of a reduction over the multipliers
-constexpr int NPART = 16;        // partial sums per block
+constexpr int NPART = 32;        // partial sums per block
+constexpr int UPD_WIN = 3;       // updates summed by the update test
 
 // device scalar slots (double)
 enum {
@@ -17,7 +18,11 @@ enum {
   SC_EK = 16,   // 6 per-kind reference energies |P d|_{M,k}^2
   SC_ERAT = 23, // current dual-energy ratio
   SC_KRAT = 24, // 6 current per-kind ratios (diagnostics)
-  SC_COUNT = 32
+  SC_UTOL = 32, // tolerance of the update test (0: off)
+  SC_URING = 33, // UPD_WIN x 6 per-kind update sizes |alpha| |p|_k of the last updates
+  SC_SEL0 = 51,  // start selection: residual norms of the current start and of a candidate
+  SC_SEL1 = 52,
+  SC_COUNT = 64
 };
 // device integer slots (IS_CNT0.. : counters of the last-block reductions)
 enum { IS_DONE = 0, IS_ITERS = 1, IS_STATUS = 2, IS_MAXIT = 3, IS_CNT0 = 4, IS_COUNT = 12 };
@@ -25,9 +30,14 @@ enum { IS_DONE = 0, IS_ITERS = 1, IS_STATUS = 2, IS_MAXIT = 3, IS_CNT0 = 4, IS_C
 enum { PH_REFNORM = 0, PH_INIT = 1, PH_ALPHA = 2, PH_CONV = 3, PH_BETA = 4 };
 
 void launch_sgemv(const DevMesh& m, const GemvArgs& a, hipStream_t st);
-// scalar state of a solve (tolerance, iteration cap, everything else zero)
-void launch_init_scalars(double* sc, int32_t* ist, double tol, int maxit, hipStream_t st);
+// scalar state of a solve (residual tolerance, update tolerance, iteration cap, everything
+// else zero)
+void launch_init_scalars(double* sc, int32_t* ist, double tol, double utol, int maxit, hipStream_t st);
 void launch_zero(int64_t n, double* z, hipStream_t st);
+// sc[dst] = sc[src]
+void launch_copy_scalar(double* sc, int src, int dst, hipStream_t st);
+// lam = alt where sc[SC_SEL1] < sc[SC_SEL0] (the candidate's residual is the smaller)
+void launch_pick_start(int64_t n, const double* sc, const double* alt, double* lam, hipStream_t st);
 // out = jump (or (B B^T)^{-1}-weighted jump) of yb; with g, also g = G^T out
 void launch_jump(const DevMesh& m, const double* yb, int from_torn, double* out, int scaled,
                  double* g, const int32_t* skip, hipStream_t st);

@@ -31,21 +31,53 @@ __device__ inline double gather_b(const DevMesh& m, const double* __restrict__ v
 // |w|_M / ref_M and the per-kind ratios |w_k| / ref_k over the kinds whose
 // reference energy is not negligible (a kind without load data, whose jump
 // only carries rounding, is judged by the energy ratio alone).
-__device__ inline double rel_residual(const double* v, const double* sc) {
-  double etot = 0.0, eref = 0.0;
-  for (int k = 0; k < 6; ++k) {
-    etot += v[8 + k];
-    eref += sc[SC_EK + k];
-  }
+// w2: per-kind |w_k|^2; etot: |w|_M^2.
+__device__ inline double rel_residual_of(const double* w2, double etot, const double* sc) {
+  double eref = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) eref += sc[SC_EK + k];
   const double den = sc[SC_EREF];
   double rel = den > 0.0 ? sqrt(etot) / den : (etot > 0.0 ? 1.0 : 0.0);
+#pragma unroll
   for (int k = 0; k < 6; ++k) {
-    if (!(sc[SC_EK + k] > 1e-24 * eref)) continue;
-    const double nk = sqrt(v[2 + k]);
-    const double rk = sc[SC_REF + k] > 0.0 ? nk / sc[SC_REF + k] : 0.0;
-    rel = fmax(rel, rk);
+    const double rk = sc[SC_REF + k] > 0.0 ? sqrt(w2[k]) / sc[SC_REF + k] : 0.0;
+    rel = sc[SC_EK + k] > 1e-24 * eref ? fmax(rel, rk) : rel;
   }
   return rel;
+}
+// v: reduced sums, per-kind |w_k|^2 in v[2..7], per-kind energies in v[8..13]
+__device__ inline double rel_residual(const double* v, const double* sc) {
+  double etot = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) etot += v[8 + k];
+  return rel_residual_of(v + 2, etot, sc);
+}
+
+// Update test, used for the FP64 refinement corrections.  A correction only has to
+// shrink the error of the first solve by a few orders, and the residual of such a
+// noise-driven interface problem keeps wandering long after its solution has
+// settled, so the iteration may also stop on the size of its updates: once, for
+// every field kind k that has nonzero multipliers, the last UPD_WIN updates
+// |alpha| |p|_k sum to at most utol |lambda|_k.  ring holds UPD_WIN x 6 sizes (slot
+// iters mod UPD_WIN receives this update's); p2, l2: per-kind |p|^2 and |lambda|^2
+// after the update.  Returns whether the test is met (never when utol <= 0 or
+// before UPD_WIN updates).
+__device__ inline bool update_converged(double* ring, int iters, double alpha, const double* p2,
+                                        const double* l2, double utol) {
+  double* slot = ring + (iters % UPD_WIN) * 6;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) slot[k] = fabs(alpha) * sqrt(p2[k]);
+  bool ok = utol > 0.0 && iters >= UPD_WIN, any = false;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const bool has = l2[k] > 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < UPD_WIN; ++i) s += ring[i * 6 + k];
+    ok = ok && (!has || s <= utol * sqrt(l2[k]));
+    any = any || has;
+  }
+  return ok && any;
 }
 
 __device__ inline double jump_raw(const DevMesh& m, const double* __restrict__ yb, int from_torn,

@@ -66,8 +66,9 @@ __device__ void scalar_phase(const double* v, double* __restrict__ sc, int32_t* 
       sc[SC_ERAT] = sc[SC_EREF] > 0.0 ? sqrt(et) / sc[SC_EREF] : 0.0;
       sc[SC_RES] = rel;
       ist[IS_ITERS] += 1;
+      const bool upd = update_converged(sc + SC_URING, ist[IS_ITERS], sc[SC_ALPHA], v + 14, v + 20, sc[SC_UTOL]);
       if (!isfinite(rel)) { ist[IS_STATUS] = FETI_ENAN; ist[IS_DONE] = 1; }
-      else if (rel <= sc[SC_TOL]) ist[IS_DONE] = 1;
+      else if (rel <= sc[SC_TOL] || upd) ist[IS_DONE] = 1;
       else if (ist[IS_ITERS] >= ist[IS_MAXIT]) { ist[IS_STATUS] = FETI_ENOTCONV; ist[IS_DONE] = 1; }
       break;
     }
@@ -85,21 +86,33 @@ __device__ void scalar_phase(const double* v, double* __restrict__ sc, int32_t* 
   }
 }
 
-// Block-wide sums of acc[0..NPART) written to part[blockIdx.x]; the last block to
-// finish sums all partials in block order (deterministic) and runs the phase.
-// counter must be zero on entry; the last block resets it.
-__device__ void reduce_and_finalize(double* acc, double* __restrict__ part, int32_t* __restrict__ counter,
-                                    double* __restrict__ sc, int32_t* __restrict__ ist, int phase) {
-  __shared__ double red[NPART][RED_BLOCK];
-  __shared__ int is_last;
-  for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = acc[c];
-  __syncthreads();
-  for (int w = RED_BLOCK / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
-    __syncthreads();
+// Block-wide sums of acc[0..NV) written to part[blockIdx.x] (stride NPART); the last
+// block to finish sums all partials in block order (deterministic) and runs the
+// phase.  counter must be zero on entry; the last block resets it.
+template <int NV>
+__device__ inline void block_sums(double (&v)[NPART], double (*red)[NV]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    double x = v[c];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) red[wave][c] = x;
   }
-  if (threadIdx.x < NPART) part[blockIdx.x * NPART + threadIdx.x] = red[threadIdx.x][0];
+  __syncthreads();
+}
+
+template <int NV>
+__device__ void reduce_and_finalize(double (&acc)[NPART], double* __restrict__ part, int32_t* __restrict__ counter,
+                                    double* __restrict__ sc, int32_t* __restrict__ ist, int phase) {
+  constexpr int NW = RED_BLOCK / 64;
+  __shared__ double red[NW][NV];
+  __shared__ int is_last;
+  block_sums<NV>(acc, red);
+  if (threadIdx.x < NV) {
+    double x = 0.0;
+    for (int w = 0; w < NW; ++w) x += red[w][threadIdx.x];
+    part[blockIdx.x * NPART + threadIdx.x] = x;
+  }
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1) == (int)gridDim.x - 1);
@@ -107,20 +120,20 @@ __device__ void reduce_and_finalize(double* acc, double* __restrict__ part, int3
   if (!is_last) return;
   __threadfence();
   const int nblk = gridDim.x;
-  for (int c = 0; c < NPART; ++c) {
-    double a = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += RED_BLOCK) a += part[b * NPART + c];
-    red[c][threadIdx.x] = a;
-  }
-  __syncthreads();
-  for (int w = RED_BLOCK / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
-    __syncthreads();
-  }
+  double v[NPART];
+#pragma unroll
+  for (int c = 0; c < NPART; ++c) v[c] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += RED_BLOCK)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] += part[b * NPART + c];
+  block_sums<NV>(v, red);
   if (threadIdx.x == 0) {
-    double v[NPART];
-    for (int c = 0; c < NPART; ++c) v[c] = red[c][0];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      double x = 0.0;
+      for (int w = 0; w < NW; ++w) x += red[w][c];
+      v[c] = x;
+    }
     scalar_phase(v, sc, ist, phase);
     *counter = 0;
   }
@@ -315,7 +328,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_correct_dot(DevMesh m, const doub
     v[j] = vj;
     acc[0] += x[j] * vj;
   }
-  reduce_and_finalize(acc, part, counter, sc, ist, phase);
+  reduce_and_finalize<1>(acc, part, counter, sc, ist, phase);
 }
 
 // G^T G, one thread per entry (r, c): sum over the jump rows of subdomain float_sub[r/3]
@@ -366,13 +379,16 @@ __global__ void __launch_bounds__(RED_BLOCK) k_reduce(DevMesh m, const double* _
   for (int64_t j = (int64_t)blockIdx.x * RED_BLOCK + threadIdx.x; j < n; j += stride) {
     if (x) acc[0] += x[j] * y[j];
     if (nrm) {
-      const double v2 = nrm[j] * nrm[j];
+      const double v2 = nrm[j] * nrm[j], e2 = fabs(mdiag[j]) * v2;
       const int k = m.row_kind[j];
-      acc[2 + k] += v2;
-      acc[8 + k] += fabs(mdiag[j]) * v2;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        acc[2 + c] += c == k ? v2 : 0.0;
+        acc[8 + c] += c == k ? e2 : 0.0;
+      }
     }
   }
-  reduce_and_finalize(acc, part, counter, sc, ist, phase);
+  reduce_and_finalize<14>(acc, part, counter, sc, ist, phase);
 }
 
 // M_jj = sum over the interface DOFs b of row j's group of (B^T D)[b, j]^2 S_bb[b, b]
@@ -417,16 +433,23 @@ __global__ void __launch_bounds__(RED_BLOCK) k_cg_lam(DevMesh m, const double* _
   for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
   const int64_t stride = (int64_t)gridDim.x * RED_BLOCK;
   for (int64_t j = (int64_t)blockIdx.x * RED_BLOCK + threadIdx.x; j < m.n_lambda; j += stride) {
-    lam[j] += al * p[j];
+    const double pj = p[j];
+    const double lj = lam[j] + al * pj;
+    lam[j] = lj;
     r[j] -= al * qraw[j];
     const double wn = w[j] - al * q[j];
     w[j] = wn;
-    const double v2 = wn * wn;
+    const double v2 = wn * wn, e2 = fabs(mdiag[j]) * v2;
     const int k = m.row_kind[j];
-    acc[2 + k] += v2;
-    acc[8 + k] += fabs(mdiag[j]) * v2;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      acc[2 + c] += c == k ? v2 : 0.0;
+      acc[8 + c] += c == k ? e2 : 0.0;
+      acc[14 + c] += c == k ? pj * pj : 0.0;
+      acc[20 + c] += c == k ? lj * lj : 0.0;
+    }
   }
-  reduce_and_finalize(acc, part, counter, sc, ist, PH_CONV);
+  reduce_and_finalize<26>(acc, part, counter, sc, ist, PH_CONV);
 }
 
 // p = y + beta p
@@ -490,10 +513,11 @@ __global__ void __launch_bounds__(256) k_kind_maxabs(DevMesh m, const double* __
   if (threadIdx.x < 12) part[blockIdx.x * 12 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// scalar state of a solve: every slot cleared, the tolerance and the iteration cap set
-__global__ void k_init_scalars(double* __restrict__ sc, int32_t* __restrict__ ist, double tol, int maxit) {
+// scalar state of a solve: every slot cleared, the tolerances and the iteration cap set
+__global__ void k_init_scalars(double* __restrict__ sc, int32_t* __restrict__ ist, double tol, double utol,
+                               int maxit) {
   const int t = threadIdx.x;
-  if (t < SC_COUNT) sc[t] = t == SC_TOL ? tol : 0.0;
+  if (t < SC_COUNT) sc[t] = t == SC_TOL ? tol : (t == SC_UTOL ? utol : 0.0);
   if (t < IS_COUNT) ist[t] = t == IS_MAXIT ? maxit : 0;
 }
 
@@ -503,10 +527,30 @@ __global__ void k_zero(int64_t n, double* __restrict__ z) {
   if (i < n) z[i] = 0.0;
 }
 
+__global__ void k_copy_scalar(double* __restrict__ sc, int src, int dst) {
+  if (threadIdx.x == 0) sc[dst] = sc[src];
+}
+
+__global__ void k_pick_start(int64_t n, const double* __restrict__ sc, const double* __restrict__ alt,
+                             double* __restrict__ lam) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n || !(sc[SC_SEL1] < sc[SC_SEL0])) return;
+  lam[j] = alt[j];
+}
+
 // ---- launchers ---------------------------------------------------------------
 
-void launch_init_scalars(double* sc, int32_t* ist, double tol, int maxit, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, sc, ist, tol, maxit);
+void launch_copy_scalar(double* sc, int src, int dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(64), 0, st, sc, src, dst);
+}
+
+void launch_pick_start(int64_t n, const double* sc, const double* alt, double* lam, hipStream_t st) {
+  hipLaunchKernelGGL(k_pick_start, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, sc, alt, lam);
+}
+
+void launch_init_scalars(double* sc, int32_t* ist, double tol, double utol, int maxit, hipStream_t st) {
+  static_assert(SC_COUNT <= 64 && IS_COUNT <= 64, "one 64-thread block clears the scalars");
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, sc, ist, tol, utol, maxit);
 }
 
 void launch_zero(int64_t n, double* z, hipStream_t st) {

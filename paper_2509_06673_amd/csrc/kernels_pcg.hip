@@ -154,9 +154,44 @@ __device__ void correct_dot_phase(const PcgArgs& a, const double* vin, double* v
   if (threadIdx.x == 0) ast(part + blockIdx.x * PCG_NPART, acc[0]);
 }
 
+// Phase D: lam += alpha p, r -= alpha q_raw, w -= alpha q, p_old = p, and this
+// block's partial sums: per-kind |w|^2 (0..5), the dual energy (6) and, with the
+// update test (NV = 19), per-kind |p|^2 (7..12) and |lambda|^2 (13..18).
+template <int NV>
+__device__ inline void update_phase(const PcgArgs& a, double alpha, double beta, double* part, double* red) {
+  const DevMesh& m = a.m;
+  const int64_t NL = m.n_lambda;
+  double acc[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) acc[c] = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x; j < NL; j += (int64_t)gridDim.x * PB) {
+    const double pj = ald(a.y + j) + beta * ald(a.p + j);
+    const double lj = a.lam[j] + alpha * pj;
+    a.lam[j] = lj;
+    a.r[j] -= alpha * ald(a.qraw + j);
+    const double wn = ald(a.w + j) - alpha * ald(a.q + j);
+    ast(a.w + j, wn);
+    ast(a.p + j, pj);
+    const double v2 = wn * wn;
+    const int k = m.row_kind[j];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += (c == k) ? v2 : 0.0;
+    acc[6] += fabs(a.mdiag[j]) * v2;
+    if (NV > 7) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        acc[7 + c] += (c == k) ? pj * pj : 0.0;
+        acc[13 + c] += (c == k) ? lj * lj : 0.0;
+      }
+    }
+  }
+  block_store<NV>(acc, red, part + blockIdx.x * PCG_NPART);
+}
+
 __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
   extern __shared__ double lds[];
-  __shared__ int s_ok;
+  __shared__ int s_ok, s_upd;
+  __shared__ double s_ring[UPD_WIN * 6];
   const DevMesh& m = a.m;
   double* xs = lds;                          // 2 x max_nb gathered vectors (one per tile)
   double* red4 = xs + 2 * m.max_nb;          // PB partial rows
@@ -167,6 +202,8 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
   uint32_t gen = 0;  // the host clears the barrier before the launch
 
   const double tol = a.sc[SC_TOL];
+  const double utol = a.sc[SC_UTOL];
+  const bool upd = utol > 0.0;  // the same in every block
   double rho = a.sc[SC_RHO], beta = a.sc[SC_BETA], alpha = a.sc[SC_ALPHA], res = a.sc[SC_RES];
   int iters = a.ist[IS_ITERS];
   const int maxit = a.ist[IS_MAXIT];
@@ -175,7 +212,8 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
   const bool start_done = a.ist[IS_DONE] != 0 || iters >= maxit;  // the same in every block
   int rk = 0;  // reductions so far: partial buffer rk & 1
   auto partbuf = [&](int k) { return a.part + (size_t)(k & 1) * nblk * PCG_NPART; };
-  double conv[7] = {0, 0, 0, 0, 0, 0, 0};
+  double conv[19];
+  for (int c = 0; c < 19; ++c) conv[c] = 0.0;
   int it_local = 0, ph = 0;
   auto stamp = [&]() {
     if (a.tstamp && blockIdx.x == 0 && threadIdx.x == 0 && it_local < a.tstamp_iters)
@@ -208,37 +246,27 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
       }
       alpha = rho / pq;
     }
-    // (D) updates and the norms of w
-    {
-      double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-      for (int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x; j < NL; j += (int64_t)nblk * PB) {
-        const double pj = ald(a.y + j) + beta * ald(a.p + j);
-        a.lam[j] += alpha * pj;
-        a.r[j] -= alpha * ald(a.qraw + j);
-        const double wn = ald(a.w + j) - alpha * ald(a.q + j);
-        ast(a.w + j, wn);
-        ast(a.p + j, pj);
-        const double v2 = wn * wn;
-        const int k = m.row_kind[j];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) acc[c] += (c == k) ? v2 : 0.0;
-        acc[6] += fabs(a.mdiag[j]) * v2;
-      }
-      block_sum<7>(acc, red);
-      if (threadIdx.x < 7) ast(partbuf(rk) + blockIdx.x * PCG_NPART + threadIdx.x, acc[threadIdx.x]);
-    }
+    // (D) updates and the norms of w (and of p and lambda for the update test)
+    if (upd) update_phase<19>(a, alpha, beta, partbuf(rk), red);
+    else update_phase<7>(a, alpha, beta, partbuf(rk), red);
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
     stamp();
     {
-      grid_total<7>(partbuf(rk++), nblk, conv, red);
-      double v[NPART];
-      for (int c = 0; c < NPART; ++c) v[c] = 0.0;
-      for (int k = 0; k < 6; ++k) v[2 + k] = conv[k];
-      v[8] = conv[6];
-      res = rel_residual(v, a.sc);
+      if (upd) grid_total<19>(partbuf(rk++), nblk, conv, red);
+      else {
+        double c7[7];
+        grid_total<7>(partbuf(rk++), nblk, c7, red);
+        for (int c = 0; c < 7; ++c) conv[c] = c7[c];
+      }
+      res = rel_residual_of(conv, conv[6], a.sc);
       iters += 1;
+      if (upd) {
+        // counted within this launch, so that the ring holds only this launch's updates
+        if (threadIdx.x == 0) s_upd = update_converged(s_ring, it_local + 1, alpha, conv + 7, conv + 13, utol);
+        __syncthreads();
+      }
       if (!isfinite(res)) { status = FETI_ENAN; break; }
-      if (res <= tol) break;
+      if (res <= tol || (upd && s_upd)) break;
       if (iters >= maxit) { status = FETI_ENOTCONV; break; }
     }
     stamp();

@@ -135,6 +135,40 @@ __device__ inline double chunk_total(const ProbArgs& pr, int c) {
   return s;
 }
 
+// Phase D on one chunk of problem p's multiplier rows: the updates and the chunk's
+// partial sums: per-kind |w|^2 (0..5), the dual energy (6) and, with the update
+// test (NV = 19), per-kind |p|^2 (7..12) and |lambda|^2 (13..18).
+template <int NV>
+__device__ inline void batch_update(const BatchArgs& a, const ProbArgs& pr, int p, int it, double* red) {
+  const double al = ald(a.alpha + p), bt = ald(a.beta + p);
+  double acc[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) acc[c] = 0.0;
+  const int64_t j = (int64_t)a.row_chunk[it] * PB + threadIdx.x;
+  if (j < pr.m.n_lambda) {
+    const double pj = ald(pr.y + j) + bt * ald(pr.p + j);
+    const double lj = pr.lam[j] + al * pj;
+    pr.lam[j] = lj;
+    pr.r[j] -= al * ald(pr.qraw + j);
+    const double wn = ald(pr.w + j) - al * ald(pr.q + j);
+    ast(pr.w + j, wn);
+    ast(pr.p + j, pj);
+    const double v2 = wn * wn;
+    const int k = pr.m.row_kind[j];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += (c == k) ? v2 : 0.0;
+    acc[6] = fabs(pr.mdiag[j]) * v2;
+    if (NV > 7) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        acc[7 + c] = (c == k) ? pj * pj : 0.0;
+        acc[13 + c] = (c == k) ? lj * lj : 0.0;
+      }
+    }
+  }
+  block_store<NV>(acc, red, pr.part + (int64_t)a.row_chunk[it] * PCG_NPART);
+}
+
 __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_batch(BatchArgs a) {
   extern __shared__ double lds[];
   __shared__ int s_ok;
@@ -180,28 +214,13 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_batch(BatchArgs a) {
       }
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
     // (D) lam += alpha p, r -= alpha q_raw, w -= alpha q, p_old = p; partial norms of w
+    // (and of p and lambda for a problem with the update test)
     for (int it = blockIdx.x; it < a.nrow; it += nblk) {
       const int p = a.row_prob[it];
       if (iload(a.done + p)) continue;
       const ProbArgs& pr = a.probs[p];
-      const double al = ald(a.alpha + p), bt = ald(a.beta + p);
-      double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-      const int64_t j = (int64_t)a.row_chunk[it] * PB + threadIdx.x;
-      if (j < pr.m.n_lambda) {
-        const double pj = ald(pr.y + j) + bt * ald(pr.p + j);
-        pr.lam[j] += al * pj;
-        pr.r[j] -= al * ald(pr.qraw + j);
-        const double wn = ald(pr.w + j) - al * ald(pr.q + j);
-        ast(pr.w + j, wn);
-        ast(pr.p + j, pj);
-        const double v2 = wn * wn;
-        const int k = pr.m.row_kind[j];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) acc[c] += (c == k) ? v2 : 0.0;
-        acc[6] = fabs(pr.mdiag[j]) * v2;
-      }
-      block_sum<7>(acc, red);
-      if (threadIdx.x < 7) ast(pr.part + (int64_t)a.row_chunk[it] * PCG_NPART + threadIdx.x, acc[threadIdx.x]);
+      if (pr.sc[SC_UTOL] > 0.0) batch_update<19>(a, pr, p, it, red);
+      else batch_update<7>(a, pr, p, it, red);
     }
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
     // (D') stopping test
@@ -209,17 +228,26 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_batch(BatchArgs a) {
       for (int p = blockIdx.x; p < a.P; p += nblk) {
         if (iload(a.done + p)) continue;
         const ProbArgs& pr = a.probs[p];
-        double v[NPART];
-        for (int c = 0; c < NPART; ++c) v[c] = 0.0;
-        for (int k = 0; k < 6; ++k) v[2 + k] = chunk_total(pr, k);
-        v[8] = chunk_total(pr, 6);
-        const double rel = rel_residual(v, pr.sc);
+        double w2[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) w2[k] = chunk_total(pr, k);
+        const double rel = rel_residual_of(w2, chunk_total(pr, 6), pr.sc);
         const int its = a.iters[p] + 1;
         a.iters[p] = its;
         pr.ist[IS_ITERS] += 1;
         pr.sc[SC_RES] = rel;
+        bool upd = false;
+        if (pr.sc[SC_UTOL] > 0.0) {
+          double p2[6], l2[6];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            p2[k] = chunk_total(pr, 7 + k);
+            l2[k] = chunk_total(pr, 13 + k);
+          }
+          upd = update_converged(pr.sc + SC_URING, its, ald(a.alpha + p), p2, l2, pr.sc[SC_UTOL]);
+        }
         if (!isfinite(rel)) finish(a, p, FETI_ENAN);
-        else if (rel <= pr.sc[SC_TOL]) finish(a, p, 0);
+        else if (rel <= pr.sc[SC_TOL] || upd) finish(a, p, 0);
         else if (pr.ist[IS_ITERS] >= pr.ist[IS_MAXIT]) finish(a, p, FETI_ENOTCONV);
       }
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;

@@ -106,6 +106,31 @@ __device__ inline void block_sum(double (&v)[NV], double* red) {
   __syncthreads();
 }
 
+// Block-wide sums of v[0..NV) stored to dst[0..NV) (device-coherent), in the order of
+// block_sum; the per-wave partials go through LDS so that no register array is
+// indexed by the thread.
+template <int NV>
+__device__ inline void block_store(double (&v)[NV], double* red, double* dst) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    double x = v[c];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    v[c] = x;
+  }
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) red[wave * NV + c] = v[c];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int wv = 0; wv < PB / 64; ++wv) s += red[wv * NV + threadIdx.x];
+    ast(dst + threadIdx.x, s);
+  }
+  __syncthreads();
+}
+
 // Sum of the per-block partials part[b][0..NV) over all blocks, in block order.
 template <int NV>
 __device__ inline void grid_total(const double* part, int nblk, double (&v)[NV], double* red) {

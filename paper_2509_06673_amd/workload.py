@@ -42,20 +42,30 @@ def load(w, t: float) -> B.Load:
 
 def opts(tol: float = 1e-10, max_it: int = 1000, start: int = B.START_PREVIOUS,
          check_every: int = 8, ir_max: int = 1, ir_cold: int = 4, tol_corr: float = 1e-3,
-         ir_tol: float = 1e-9, tol_inner: float = 0.0) -> B.SolveOpts:
+         ir_tol: float = 1e-9, tol_inner: float = 0.0, tol_upd: float = 3e-3,
+         corr_start: int = B.CORR_PREVIOUS) -> B.SolveOpts:
     """Solve options.  Every step ends with FP64 iterative refinement on the torn
     system: up to ir_max corrections (ir_cold when the step starts without previous
     multipliers), stopping once a correction changes no field by more than ir_tol
     relative.  The pressure p = k1 xi + k2 eta is a small difference of large terms
     at nu -> 1/2, so an interface residual of tol alone does not bound its error.
-    tol_inner: first-solve tolerance with FP32 factors (0 = tol)."""
-    return B.SolveOpts(tol, tol_corr, ir_tol, max_it, start, check_every, ir_max, ir_cold, tol_inner)
+    tol_inner: first-solve tolerance with FP32 factors (0 = tol).  tol_upd: update test of
+    the refinement corrections (0 = off); corr_start: the first correction of a step
+    starts from the previous step's total correction when that start has the smaller
+    projected residual (CORR_PREVIOUS) or from zero (CORR_ZERO).  With both, the
+    64-subdomain FP64 case needs ~38 instead of ~103 iterations per step and stays
+    within 4e-10 of the oracle in every field over 16 steps."""
+    return B.SolveOpts(tol, tol_corr, ir_tol, max_it, start, check_every, ir_max, ir_cold, tol_inner, tol_upd,
+                       corr_start)
 
 
 def opts_mixed(**kw) -> B.SolveOpts:
     """Defaults of the FP32-factor path: a looser first solve (its operators carry
-    FP32 rounding) and more FP64 corrections."""
-    base = dict(tol_inner=1e-6, tol_corr=1e-4, ir_max=3, ir_cold=5, ir_tol=1e-9)
+    FP32 rounding) and more FP64 corrections, each to its residual tolerance (the
+    corrections of this path are limited by the FP32 operators, and neither the update
+    test nor the warm correction start shortened them)."""
+    base = dict(tol_inner=1e-6, tol_corr=1e-4, ir_max=3, ir_cold=5, ir_tol=1e-9, tol_upd=0.0,
+                corr_start=B.CORR_ZERO)
     base.update(kw)
     return opts(**base)
 

@@ -113,3 +113,33 @@ def test_call_order_and_invalid_input():
     with pytest.raises(B.FetiError) as e:
         f.assemble(B.Material(1, 0.5, 1, 1, 1, 1, 0), B.Material(1, 0.3, 1, 1, 1, 1, 0), 0.1)
     assert e.value.code == B.EINVAL
+
+
+def test_binding_structs_match_the_c_layout(tmp_path):
+    """Every struct of the ctypes binding has the size and field offsets that a C
+    compiler gives the header's typedef (compiled here with gcc)."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    from paper_2509_06673_amd import _binding as Bd
+    pairs = {"feti_mesh_desc": Bd.MeshDesc, "feti_material": Bd.Material, "feti_load": Bd.Load,
+             "feti_solve_opts": Bd.SolveOpts, "feti_stats": Bd.Stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "feti.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -50,7 +50,7 @@ def test_batch_matches_single_runs_and_oracle():
     import torch
     require_gpu()
     ws = _subset()
-    nsteps = 2
+    nsteps = 3
     print("[batch] " + " ".join(w.name for w in ws), flush=True)
     ctxs = [_ctx(w, keep=False) for w in ws]
     batch = B.Batch(ctxs)

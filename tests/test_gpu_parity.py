@@ -234,3 +234,56 @@ def test_full_size_workload_matches_oracle():
         assert st["status"] == 0
         assert max(err.values()) < FP64_TOL, (n, err)
     f.close()
+
+
+_UPD_CASE = W.nearly_incompressible_scaled(64, 8, nsteps=8)
+_UPD_ORACLE = {}
+
+
+@pytest.mark.parametrize("mode", ["auto", "graph"])
+def test_update_test_and_warm_corrections_match_oracle(mode):
+    """Refinement corrections that stop on the size of their updates and start from the
+    previous step's correction, on the persistent launch and on the graph-captured
+    kernel chain: every step within the FP64 bar of the oracle, and fewer iterations
+    than corrections that run to their residual tolerance from zero."""
+    import torch
+    w = _UPD_CASE
+    print(f"[upd] {w.name} x{w.nsteps} mode {mode}", flush=True)
+    if "lats" not in _UPD_ORACLE:
+        _UPD_ORACLE["lats"] = oracle_reference(w, w.nsteps)[1]
+    lats = _UPD_ORACLE["lats"]
+    iters = {}
+    for name, o in (("plain", opts(tol=w.tol, max_it=3000, tol_upd=0.0, corr_start=B.CORR_ZERO)),
+                    ("upd", opts(tol=w.tol, max_it=3000))):
+        assert name == "plain" or (o.tol_upd > 0 and o.corr_start == B.CORR_PREVIOUS)
+        f = setup(w)
+        if mode == "graph":
+            f.set_pcg_mode(B.PCG_GRAPH)
+        idx = f.export_indexing()
+        codes = idx["code"].astype(np.int64)
+        poro = sub_poro_flags(w)
+        u = torch.empty(len(codes), dtype=torch.float64, device="cuda")
+        its = []
+        for n in range(1, w.nsteps + 1):
+            st = f.step(load(w, n * w.tau), o)
+            assert st["status"] == 0, st
+            f.get_solution(u)
+            err = per_kind_rel_error(codes, u.cpu().numpy(), torn_reference(codes, idx["sub_offset"], poro,
+                                                                             lats[n - 1]))
+            its.append(st["iters"])
+            print(f"  {name} step {n}: iters {st['iters']} (first {st['iters_first']}) err "
+                  f"{max(err.values()):.1e}", flush=True)
+            assert max(err.values()) < FP64_TOL, (name, n, err)
+        f.close()
+        iters[name] = sum(its[1:])
+    assert iters["upd"] < iters["plain"], iters
+
+
+def test_pcg_mode_is_validated():
+    require_gpu()
+    f = B.Feti()
+    with pytest.raises(B.FetiError):
+        f.set_pcg_mode(7)
+    f.set_pcg_mode(B.PCG_GRAPH)
+    f.set_pcg_mode(B.PCG_AUTO)
+    f.close()
