@@ -128,9 +128,12 @@ typedef struct {
     double tol_upd;       /* update test of the refinement corrections (0 = off): a correction
                              also stops once, for every field kind k with nonzero multipliers,
                              its last three updates |alpha| |p|_k sum to at most
-                             tol_upd |dlambda|_k (e.g. 1e-4).  A correction only has to shrink
+                             tol_upd |dlambda|_k (e.g. 3e-3).  A correction only has to shrink
                              the first solve's error by a few orders, and its noise-driven
-                             residual keeps wandering long after its solution has settled. */
+                             residual keeps wandering long after its solution has settled.
+                             Every kind counts, also those whose correction is tiny: at
+                             nu -> 1/2 the pressure p = kappa_1 xi + kappa_2 eta magnifies the
+                             error of the xi and eta multipliers. */
     int32_t corr_start;   /* start of the first refinement correction of a step:
                              FETI_CORR_ZERO, or FETI_CORR_PREVIOUS = the previous step's total
                              correction (the rounding that the corrections undo comes from the
@@ -146,6 +149,9 @@ typedef struct {
     double res0, res;     /* max over kinds of the relative interface residual, start / end */
     double rho;           /* size of the last refinement correction, max_k |du_k|/|u_k| (0 if none) */
     double t_ms[8];       /* phase times (ms): rhs, d + start, pcg, recovery, refinement, total */
+    int32_t iters_corr[4]; /* PCG iterations of the first four refinement corrections */
+    int32_t corr_warm;    /* 1: the first correction started from the previous step's correction
+                             (feti_step only; a batch chooses on the device and reports 0) */
 } feti_stats;
 
 /* ---- lifetime ---------------------------------------------------------- */

@@ -58,13 +58,15 @@ class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("iters_first", C.c_int32), ("ir_steps", C.c_int32),
                 ("status", C.c_int32),
                 ("start_used", C.c_int32), ("res0", C.c_double), ("res", C.c_double),
-                ("rho", C.c_double), ("t_ms", C.c_double * 8)]
+                ("rho", C.c_double), ("t_ms", C.c_double * 8), ("iters_corr", C.c_int32 * 4),
+                ("corr_warm", C.c_int32)]
 
     def as_dict(self) -> Dict:
         return {"iters": self.iters, "iters_first": self.iters_first, "ir_steps": self.ir_steps,
                 "status": self.status,
                 "start_used": self.start_used, "res0": self.res0, "res": self.res,
-                "rho": self.rho, "t_ms": list(self.t_ms)}
+                "rho": self.rho, "t_ms": list(self.t_ms), "iters_corr": list(self.iters_corr),
+                "corr_warm": self.corr_warm}
 
 
 class FetiError(RuntimeError):

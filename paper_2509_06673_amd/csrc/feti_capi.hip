@@ -522,8 +522,10 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
   static const bool trace = std::getenv("FETI_TRACE") != nullptr;
   static const bool use_graph = std::getenv("FETI_NO_GRAPH") == nullptr;
   static const bool use_persist = std::getenv("FETI_NO_PERSIST") == nullptr;
+  // (the persistent kernel projects with H = G (G^T G)^{-1}, built when n_c <= PCG_NC_LOCAL)
   const bool persist = use_persist && !trace && ctx->pcg_mode == FETI_PCG_AUTO && ctx->pgrid > 0 &&
-                       ctx->nc <= PCG_NC_LOCAL && ctx->precond != FETI_PRECOND_NONE;
+                       ctx->nc <= PCG_NC_LOCAL && (ctx->nc == 0 || ctx->H != nullptr) &&
+                       ctx->precond != FETI_PRECOND_NONE;
   if (persist) {
     // every iteration of the solve in one cooperative launch (a solve converged at
     // its start leaves the launch at once)
@@ -550,8 +552,8 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
       }
       HIPCHK(launch_pcg_persistent(pa, ctx->pgrid, st));
       if (ptrace) {
-        // stamps per iteration: 0 start, 1..4 after barriers A..D, 5 after the stopping
-        // test, 6..8 after barriers E..G (stamp 0 of a later iteration = stamp 8 before)
+        // stamps per iteration: 0 start, 1..3 after barriers A, B, D, 4 after the stopping
+        // test, 5..7 after barriers E..G (stamp 0 of a later iteration = stamp 7 before)
         std::vector<long long> h(nts * 10);
         HIPCHK(hipMemcpyAsync(h.data(), ts, h.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -559,20 +561,20 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
         int rate_khz = 0, dev = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
-        double sum[9] = {0}; int cnt = 0;
+        double sum[8] = {0}; int cnt = 0;
         for (int it = 0; it < nts; ++it) {
-          if (h[it * 10 + 8] == 0) break;
-          for (int k = 0; k < 8; ++k) {
-            const long long a0 = k > 0 ? h[it * 10 + k] : (it == 0 ? h[0] : h[(it - 1) * 10 + 8]);
+          if (h[it * 10 + 7] == 0) break;
+          for (int k = 0; k < 7; ++k) {
+            const long long a0 = k > 0 ? h[it * 10 + k] : (it == 0 ? h[0] : h[(it - 1) * 10 + 7]);
             sum[k] += (double)(h[it * 10 + k + 1] - a0);
           }
           ++cnt;
         }
         if (cnt > 0 && rate_khz > 0) {
-          std::fprintf(stderr, "[pcg] grid %d, %d iterations, us: A %.2f B %.2f C %.2f D %.2f test %.2f E %.2f F %.2f G %.2f",
-                       ctx->pgrid, cnt, sum[0] / cnt / rate_khz * 1e3, sum[1] / cnt / rate_khz * 1e3,
-                       sum[2] / cnt / rate_khz * 1e3, sum[3] / cnt / rate_khz * 1e3, sum[4] / cnt / rate_khz * 1e3,
-                       sum[5] / cnt / rate_khz * 1e3, sum[6] / cnt / rate_khz * 1e3, sum[7] / cnt / rate_khz * 1e3);
+          const double us = 1e3 / rate_khz / cnt;
+          std::fprintf(stderr, "[pcg] grid %d, %d iterations, us: A %.2f B %.2f D %.2f test %.2f E %.2f F %.2f G %.2f",
+                       ctx->pgrid, cnt, sum[0] * us, sum[1] * us, sum[2] * us, sum[3] * us, sum[4] * us, sum[5] * us,
+                       sum[6] * us);
           std::fprintf(stderr, "\n");
         }
       }
@@ -583,7 +585,7 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
     if (trace)
       HIPCHK(hipMemcpyAsync(ctx->h_sc, ctx->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (trace)
+    if (trace) {
       std::fprintf(stderr,
                    "[feti] tol %.1e it %d res %.3e rho %.3e status %d energy %.2e kinds %.2e %.2e %.2e "
                    "%.2e %.2e %.2e\n",
@@ -591,6 +593,18 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
                    ctx->h_ist[IS_STATUS], ctx->h_sc[SC_ERAT], ctx->h_sc[SC_KRAT], ctx->h_sc[SC_KRAT + 1],
                    ctx->h_sc[SC_KRAT + 2], ctx->h_sc[SC_KRAT + 3], ctx->h_sc[SC_KRAT + 4],
                    ctx->h_sc[SC_KRAT + 5]);
+      if (ctx->h_sc[SC_UTOL] > 0.0) {
+        // per kind: recent update sizes / |lambda|_k (the update test passes when all are <= utol)
+        std::fprintf(stderr, "[feti]   update ratios");
+        for (int k = 0; k < 6; ++k) {
+          double s = 0.0;
+          for (int i = 0; i < UPD_WIN; ++i) s += ctx->h_sc[SC_URING + i * 6 + k];
+          const double l = ctx->h_sc[SC_ULAM + k];
+          std::fprintf(stderr, " %.2e(|l| %.1e)", l > 0.0 ? s / l : 0.0, l);
+        }
+        std::fprintf(stderr, "\n");
+      }
+    }
     if (ctx->h_ist[IS_DONE] || ctx->h_ist[IS_ITERS] >= o->max_it) break;
     // one chunk of iterations, replayed from a captured graph
     feti_ctx_s::Graph* gr = nullptr;
@@ -675,8 +689,12 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
     // the first correction of a time step may start from the previous step's total
     // correction, kept only if its projected residual beats the zero start
     const bool warm = history && k == 0 && o->corr_start == FETI_CORR_PREVIOUS && ctx->have_dlam_prev;
-    rc = solve_torn(ctx, o, o->tol_corr, o->tol_upd, ctx->rf, ctx->cj, ctx->dlam, ctx->du, stats, &iters, &r0c,
-                    &rc_, warm ? ctx->dlam_prev : nullptr);
+    int took_warm = 0, it_corr = 0;
+    rc = solve_torn(ctx, o, o->tol_corr, o->tol_upd, ctx->rf, ctx->cj, ctx->dlam, ctx->du, stats, &it_corr, &r0c,
+                    &rc_, warm ? ctx->dlam_prev : nullptr, warm ? &took_warm : nullptr);
+    iters += it_corr;
+    if (stats && k < 4) stats->iters_corr[k] = it_corr;
+    if (stats && k == 0) stats->corr_warm = took_warm;
     launch_axpby(m.sum_ns, 1.0, ctx->u, 1.0, ctx->du, ctx->u, st);
     launch_axpby(m.n_lambda, 1.0, ctx->lam, 1.0, ctx->dlam, ctx->lam, st);
     launch_axpby(m.n_lambda, 1.0, ctx->dlam, k == 0 ? 0.0 : 1.0, k == 0 ? nullptr : ctx->dlam_sum, ctx->dlam_sum,
@@ -884,6 +902,8 @@ int feti_assemble(feti_ctx ctx, const feti_material* P, const feti_material* E, 
   ctx->mpE.lam_inv = 1.0 / ctx->lamE;
   ctx->mpE.tau = tau;
   RC(upload_mesh(ctx));
+  RC(dalloc(ctx, &ctx->dm.emat, (size_t)ctx->dm.nelem * ctx->dm.edof * ctx->dm.edof, ctx->allocs));
+  launch_elem_store(ctx->dm, ctx->mpP, ctx->mpE, ctx->stream);
   RC(dalloc(ctx, &ctx->K, ctx->k_total, ctx->mat_allocs));
   HIPCHK(hipMemsetAsync(ctx->K, 0, ctx->k_total * sizeof(double), ctx->stream));
   launch_assemble(ctx->dm, ctx->K, ctx->mpP, ctx->mpE, ctx->stream);

@@ -22,6 +22,7 @@ enum {
   SC_URING = 33, // UPD_WIN x 6 per-kind update sizes |alpha| |p|_k of the last updates
   SC_SEL0 = 51,  // start selection: residual norms of the current start and of a candidate
   SC_SEL1 = 52,
+  SC_ULAM = 53,  // 6 per-kind |lambda|_k at the last update test (graph path; diagnostics)
   SC_COUNT = 64
 };
 // device integer slots (IS_CNT0.. : counters of the last-block reductions)

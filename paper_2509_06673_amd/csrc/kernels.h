@@ -36,6 +36,7 @@ struct DevMesh {
           *el_code = nullptr;
   int32_t *adj_ptr = nullptr, *adj = nullptr;  // torn DOF -> element contributions
   double* ebuf = nullptr;                      // nelem x edof element contributions
+  double* emat = nullptr;                      // nelem x edof x edof element matrices K_e
   // interface space
   int32_t* bg_row = nullptr;    // 2 per b DOF
   double* bg_sign = nullptr;
@@ -64,6 +65,8 @@ void launch_init_eta(const DevMesh& m, double* u, const LoadDev& L, hipStream_t 
 // load sampled at the node of every multiplier row (body force of u rows, source of eta, xi_P, p rows)
 void launch_interface_load(const DevMesh& m, const LoadDev& L, double* out, hipStream_t st);
 // y = K x (torn, element by element, overwriting y)
+// K_e of every element into m.emat (once the materials and tau are known)
+void launch_elem_store(const DevMesh& m, MatParams mpP, MatParams mpE, hipStream_t st);
 void launch_elem_matvec(const DevMesh& m, const double* x, double* y, MatParams mpP, MatParams mpE,
                         hipStream_t st);
 

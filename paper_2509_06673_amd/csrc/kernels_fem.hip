@@ -125,7 +125,24 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
 }
 
 // One thread per (element, row): ebuf[e][row] = (K_e x_e)[row]
-__global__ void k_elem_matvec(DevMesh m, const double* __restrict__ x, MatParams mpP, MatParams mpE) {
+// One thread per (element, row): row r of K_e into emat (every entry, also those of
+// Dirichlet DOFs, which the products skip)
+__global__ void k_elem_store(DevMesh m, MatParams mpP, MatParams mpE) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int edof = m.edof;
+  const int64_t e = gid / edof;
+  const int r = (int)(gid % edof);
+  if (e >= m.nelem) return;
+  const bool poro = m.sub_poro[m.el_sub[e]] != 0;
+  ElemGeom g;
+  elem_geom(m.el_cell[e], m.el_type[e], m.ncell, g);
+  const MatParams& mp = poro ? mpP : mpE;
+  double* row = m.emat + gid * edof;
+  for (int c = 0; c < edof; ++c) row[c] = elem_entry(m.order, poro, g, mp, r, c);
+}
+
+// One thread per (element, row): ebuf[e][row] = (K_e x_e)[row], K_e read from emat
+__global__ void k_elem_matvec(DevMesh m, const double* __restrict__ x) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int edof = m.edof;
   const int64_t e = gid / edof;
@@ -134,15 +151,11 @@ __global__ void k_elem_matvec(DevMesh m, const double* __restrict__ x, MatParams
   const int32_t* ld = m.el_ldof + e * edof;
   double acc = 0.0;
   if (ld[r] >= 0) {
-    const int s = m.el_sub[e];
-    const bool poro = m.sub_poro[s] != 0;
-    ElemGeom g;
-    elem_geom(m.el_cell[e], m.el_type[e], m.ncell, g);
-    const MatParams& mp = poro ? mpP : mpE;
-    const double* xs = x + m.soff[s];
+    const double* xs = x + m.soff[m.el_sub[e]];
+    const double* row = m.emat + gid * edof;
     for (int c = 0; c < edof; ++c) {
       const int lc = ld[c];
-      if (lc >= 0) acc += elem_entry(m.order, poro, g, mp, r, c) * xs[lc];
+      if (lc >= 0) acc += row[c] * xs[lc];
     }
   }
   m.ebuf[gid] = acc;
@@ -221,11 +234,17 @@ void launch_init_eta(const DevMesh& m, double* u, const LoadDev& L, hipStream_t 
   hipLaunchKernelGGL(k_init_eta, dim3(grid), dim3(blk), 0, st, m.code, u, m.sum_ns, m.ncell, L);
 }
 
+void launch_elem_store(const DevMesh& m, MatParams mpP, MatParams mpE, hipStream_t st) {
+  const int64_t nthreads = (int64_t)m.nelem * m.edof;
+  hipLaunchKernelGGL(k_elem_store, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, m, mpP, mpE);
+}
+
 void launch_elem_matvec(const DevMesh& m, const double* x, double* y, MatParams mpP, MatParams mpE,
                         hipStream_t st) {
+  (void)mpP;
+  (void)mpE;
   const int64_t nthreads = (int64_t)m.nelem * m.edof;
-  hipLaunchKernelGGL(k_elem_matvec, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, m, x,
-                     mpP, mpE);
+  hipLaunchKernelGGL(k_elem_matvec, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, m, x);
   hipLaunchKernelGGL(k_gather_elem, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, m, y);
 }
 

@@ -67,6 +67,7 @@ __device__ void scalar_phase(const double* v, double* __restrict__ sc, int32_t* 
       sc[SC_RES] = rel;
       ist[IS_ITERS] += 1;
       const bool upd = update_converged(sc + SC_URING, ist[IS_ITERS], sc[SC_ALPHA], v + 14, v + 20, sc[SC_UTOL]);
+      for (int k = 0; k < 6; ++k) sc[SC_ULAM + k] = sqrt(v[20 + k]);
       if (!isfinite(rel)) { ist[IS_STATUS] = FETI_ENAN; ist[IS_DONE] = 1; }
       else if (rel <= sc[SC_TOL] || upd) ist[IS_DONE] = 1;
       else if (ist[IS_ITERS] >= ist[IS_MAXIT]) { ist[IS_STATUS] = FETI_ENOTCONV; ist[IS_DONE] = 1; }

@@ -3,16 +3,19 @@
 // (feti_dirichlet_preconditioner)).
 //
 // One cooperative launch runs every iteration of a solve (instead of a chain of
-// about ten dependent kernels per iteration).  An iteration is seven grid-wide
+// about ten dependent kernels per iteration).  An iteration is six grid-wide
 // phases separated by barriers:
 //   A  y_b = (K_s^+)_bb B_s^T p      per 64-row tile, p = y + beta p_old formed on the fly
-//   B  q_raw = sum_s B_s y_b, g = G^T q_raw
-//   C  q = q_raw - G (G^T G)^{-1} g, partial sums of (p, q)      -> alpha in every block
-//   D  lam += alpha p, r -= alpha q_raw, w -= alpha q, p_old = p, residual norms
-//                                                                 -> stopping test in every block
+//   B  q_raw = sum_s B_s y_b, g = G^T q_raw, partial sums of (p, q_raw)
+//                                                                 -> alpha in every block
+//   D  q = q_raw - G (G^T G)^{-1} g, lam += alpha p, r -= alpha q_raw, w -= alpha q,
+//      p_old = p, residual norms                                  -> stopping test in every block
 //   E  z_b = S_bb (B_s^T D w)
 //   F  z = D sum_s B_s z_b, g = G^T z
 //   G  y = z - G (G^T G)^{-1} g, partial sums of (w, y)          -> beta in every block
+// p stays in the range of the projection P (it is built from projected vectors), and
+// P is orthogonal, so (p, P q_raw) = (p, q_raw): alpha needs no projected q, and the
+// projection of q is applied row by row inside the updates.
 // The scalars of a phase are reduced by every block from the same per-block
 // partials in the same order, so all blocks take identical decisions and leave
 // the loop together.  Consecutive reductions alternate between two partial
@@ -46,15 +49,23 @@ __device__ void gemv_phase(const PcgArgs& a, const MT* A, const double* src, con
 
 // Phases B and F: out_j = (scaled) jump of yb; g_f = R_s^T B_s^T out for the
 // floating subdomains (when there is a coarse space).
-__device__ void jump_phase(const PcgArgs& a, const double* yb, double* out, int scaled, double* red) {
+// With part: also this block's partial of (x, out), x = x1 + xbeta x2.
+__device__ void jump_phase(const PcgArgs& a, const double* yb, double* out, int scaled, double* red,
+                           const double* x1 = nullptr, const double* x2 = nullptr, double xbeta = 0.0,
+                           double* part = nullptr) {
   const DevMesh& m = a.m;
   const int64_t NL = m.n_lambda;
   const int nlb = (int)((NL + PB - 1) / PB);
   const int nitems = nlb + (a.nc > 0 ? m.n_float : 0);
+  double dot[1] = {0.0};
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     if (it < nlb) {
       const int64_t j = (int64_t)it * PB + threadIdx.x;
-      if (j < NL) ast(out + j, pjump_row(m, yb, j, scaled));
+      if (j < NL) {
+        const double v = pjump_row(m, yb, j, scaled);
+        ast(out + j, v);
+        if (part) dot[0] += (ald(x1 + j) + xbeta * ald(x2 + j)) * v;
+      }
       continue;
     }
     const int f = it - nlb;
@@ -76,6 +87,10 @@ __device__ void jump_phase(const PcgArgs& a, const double* yb, double* out, int 
     }
     block_sum<3>(acc, red);
     if (threadIdx.x < 3) ast(a.g + 3 * f + threadIdx.x, acc[threadIdx.x]);
+  }
+  if (part) {
+    block_sum<1>(dot, red);
+    if (threadIdx.x == 0) ast(part + blockIdx.x * PCG_NPART, dot[0]);
   }
 }
 
@@ -154,35 +169,65 @@ __device__ void correct_dot_phase(const PcgArgs& a, const double* vin, double* v
   if (threadIdx.x == 0) ast(part + blockIdx.x * PCG_NPART, acc[0]);
 }
 
-// Phase D: lam += alpha p, r -= alpha q_raw, w -= alpha q, p_old = p, and this
-// block's partial sums: per-kind |w|^2 (0..5), the dual energy (6) and, with the
-// update test (NV = 19), per-kind |p|^2 (7..12) and |lambda|^2 (13..18).
+// Phase D: q = q_raw - H g (H = G (G^T G)^{-1}, coarse-index major; 64-row chunks, the
+// wavefronts of the block split the coarse index), then lam += alpha p,
+// r -= alpha q_raw, w -= alpha q, p_old = p, and this block's partial sums: per-kind
+// |w|^2 (0..5), the dual energy (6) and, with the update test (NV = 19), per-kind
+// |p|^2 (7..12) and |lambda|^2 (13..18).
 template <int NV>
-__device__ inline void update_phase(const PcgArgs& a, double alpha, double beta, double* part, double* red) {
+__device__ inline void update_phase(const PcgArgs& a, double alpha, double beta, double* part, double* acl,
+                                    double* red4, double* red) {
   const DevMesh& m = a.m;
   const int64_t NL = m.n_lambda;
   double acc[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) acc[c] = 0.0;
-  for (int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x; j < NL; j += (int64_t)gridDim.x * PB) {
-    const double pj = ald(a.y + j) + beta * ald(a.p + j);
-    const double lj = a.lam[j] + alpha * pj;
-    a.lam[j] = lj;
-    a.r[j] -= alpha * ald(a.qraw + j);
-    const double wn = ald(a.w + j) - alpha * ald(a.q + j);
-    ast(a.w + j, wn);
-    ast(a.p + j, pj);
-    const double v2 = wn * wn;
-    const int k = m.row_kind[j];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] += (c == k) ? v2 : 0.0;
-    acc[6] += fabs(a.mdiag[j]) * v2;
-    if (NV > 7) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        acc[7 + c] += (c == k) ? pj * pj : 0.0;
-        acc[13 + c] += (c == k) ? lj * lj : 0.0;
+  if ((int64_t)blockIdx.x * 64 < NL) {
+    double* gl = acl + PCG_NC_LOCAL;
+    for (int k = threadIdx.x; k < a.nc; k += PB) gl[k] = ald(a.g + k);
+    __syncthreads();
+    constexpr int NW = PB / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cq = (a.nc + NW - 1) / NW, cb = wave * cq, ce = min(a.nc, cb + cq);
+    for (int64_t j0 = (int64_t)blockIdx.x * 64; j0 < NL; j0 += (int64_t)gridDim.x * 64) {
+      const int64_t j = j0 + lane;
+      double c0 = 0.0, c1 = 0.0;
+      if (j < NL) {
+        int c = cb;
+        for (; c + 2 <= ce; c += 2) {
+          c0 += a.H[(int64_t)c * NL + j] * gl[c];
+          c1 += a.H[(int64_t)(c + 1) * NL + j] * gl[c + 1];
+        }
+        if (c < ce) c0 += a.H[(int64_t)c * NL + j] * gl[c];
       }
+      red4[wave * 64 + lane] = c0 + c1;
+      __syncthreads();
+      if (wave == 0 && j < NL) {
+        double corr = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) corr += red4[w * 64 + lane];
+        const double qr = ald(a.qraw + j);
+        const double pj = ald(a.y + j) + beta * ald(a.p + j);
+        const double lj = a.lam[j] + alpha * pj;
+        a.lam[j] = lj;
+        a.r[j] -= alpha * qr;
+        const double wn = ald(a.w + j) - alpha * (qr - corr);
+        ast(a.w + j, wn);
+        ast(a.p + j, pj);
+        const double v2 = wn * wn;
+        const int k = m.row_kind[j];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] += (c == k) ? v2 : 0.0;
+        acc[6] += fabs(a.mdiag[j]) * v2;
+        if (NV > 7) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            acc[7 + c] += (c == k) ? pj * pj : 0.0;
+            acc[13 + c] += (c == k) ? lj * lj : 0.0;
+          }
+        }
+      }
+      __syncthreads();
     }
   }
   block_store<NV>(acc, red, part + blockIdx.x * PCG_NPART);
@@ -227,12 +272,8 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
     else gemv_phase<double, 0>(a, (const double*)a.fm, a.y, a.p, beta, a.yb, xs, red4);
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
     stamp();
-    // (B) q_raw = B y_b, g = G^T q_raw
-    jump_phase(a, a.yb, a.qraw, 0, red);
-    if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
-    stamp();
-    // (C) q = P q_raw, partial (p, q)
-    correct_dot_phase(a, a.qraw, a.q, a.y, a.p, beta, partbuf(rk), acl, red4, red);
+    // (B) q_raw = B y_b, g = G^T q_raw, partial (p, q_raw)
+    jump_phase(a, a.yb, a.qraw, 0, red, a.y, a.p, beta, partbuf(rk));
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
     stamp();
     {
@@ -246,9 +287,9 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
       }
       alpha = rho / pq;
     }
-    // (D) updates and the norms of w (and of p and lambda for the update test)
-    if (upd) update_phase<19>(a, alpha, beta, partbuf(rk), red);
-    else update_phase<7>(a, alpha, beta, partbuf(rk), red);
+    // (D) q = P q_raw, updates and the norms of w (and of p and lambda for the update test)
+    if (upd) update_phase<19>(a, alpha, beta, partbuf(rk), acl, red4, red);
+    else update_phase<7>(a, alpha, beta, partbuf(rk), acl, red4, red);
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
     stamp();
     {
