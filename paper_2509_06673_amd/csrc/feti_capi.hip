@@ -55,6 +55,8 @@ struct feti_ctx_s {
   float* Kinv32 = nullptr;
   float* Sbb32 = nullptr;
   float* Splus32 = nullptr;
+  // packed lower 64 x 64 tiles of K_s^+ for the local solves (beside the dense blocks)
+  SymArgs sym;
   int nc = 0;
   // vectors
   double *f = nullptr, *u = nullptr, *ytmp = nullptr, *yb = nullptr, *zb = nullptr;
@@ -301,6 +303,7 @@ void free_all(feti_ctx ctx) {
   ctx->dm = DevMesh();
   ctx->K = ctx->Kinv = ctx->Sbb = ctx->Splus = ctx->Kbb = ctx->Cinv = ctx->H = nullptr;
   ctx->Kinv32 = ctx->Sbb32 = ctx->Splus32 = nullptr;
+  ctx->sym = SymArgs();
 }
 
 LoadDev make_load(feti_ctx ctx, const feti_load* L) {
@@ -436,11 +439,15 @@ int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
   const int64_t nl = m.n_lambda;
   // d = sum_s B_s K_s^+ f_s - c
   {
-    GemvArgs a;
-    const Factors fc = factors(ctx);
-    a.A = fc.kinv; a.a_f32 = fc.f32; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
-    a.xbase = f; a.y = ctx->ytmp;
-    launch_sgemv(m, a, st);
+    if (ctx->sym.P) {
+      launch_sym_gemv(m, ctx->sym, f, ctx->ytmp, st);
+    } else {
+      GemvArgs a;
+      const Factors fc = factors(ctx);
+      a.A = fc.kinv; a.a_f32 = fc.f32; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
+      a.xbase = f; a.y = ctx->ytmp;
+      launch_sgemv(m, a, st);
+    }
     launch_jump(m, ctx->ytmp, 1, ctx->d, 0, nullptr, nullptr, st);
     if (cj) launch_axpby(nl, 1.0, ctx->d, -1.0, cj, ctx->d, st);
   }
@@ -735,6 +742,62 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
   return rc;
 }
 
+// Tile tables (once per mesh) and the packed lower tiles of K_s^+ in the precision of the
+// factors.
+int build_sym(feti_ctx ctx, bool f32) {
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  SymArgs& a = ctx->sym;
+  if (!a.t_sub) {
+    const int nsub = m.nsub;
+    std::vector<int32_t> ts, ti, tj, nt(nsub);
+    std::vector<int64_t> tb(nsub);
+    for (int s = 0; s < nsub; ++s) {
+      const int T = (ctx->mh.subs[s].ns + 63) / 64;
+      nt[s] = T;
+      tb[s] = (int64_t)ts.size();
+      for (int I = 0; I < T; ++I)
+        for (int J = 0; J <= I; ++J) {
+          ts.push_back(s);
+          ti.push_back(I);
+          tj.push_back(J);
+        }
+    }
+    int32_t *d_ts = nullptr, *d_ti = nullptr, *d_tj = nullptr, *d_nt = nullptr;
+    int64_t* d_tb = nullptr;
+    RC(upload(ctx, &d_ts, ts));
+    RC(upload(ctx, &d_ti, ti));
+    RC(upload(ctx, &d_tj, tj));
+    RC(upload(ctx, &d_nt, nt));
+    RC(upload(ctx, &d_tb, tb));
+    RC(dalloc(ctx, &a.part, ts.size() * 128, ctx->allocs));
+    HIPCHK(hipStreamSynchronize(st));  // the host tables leave scope
+    a.ntile = (int)ts.size();
+    a.t_sub = d_ts; a.t_I = d_ti; a.t_J = d_tj; a.nt = d_nt; a.tbase = d_tb;
+  }
+  if (a.P && a.f32 != (int)f32) {
+    auto it = std::find(ctx->mat_allocs.begin(), ctx->mat_allocs.end(), const_cast<void*>(a.P));
+    if (it != ctx->mat_allocs.end()) ctx->mat_allocs.erase(it);
+    HIPCHK(hipFree(const_cast<void*>(a.P)));
+    a.P = nullptr;
+  }
+  const size_t ne = (size_t)a.ntile * 4096;
+  if (f32) {
+    float* P = (float*)a.P;
+    if (!P) RC(dalloc(ctx, &P, ne, ctx->mat_allocs));
+    launch_sym_pack(a, (const float*)ctx->Kinv32, m.kofs, m.ld, m.ns, P, st);
+    a.P = P;
+  } else {
+    double* P = (double*)a.P;
+    if (!P) RC(dalloc(ctx, &P, ne, ctx->mat_allocs));
+    launch_sym_pack(a, (const double*)ctx->Kinv, m.kofs, m.ld, m.ns, P, st);
+    a.P = P;
+  }
+  a.f32 = f32 ? 1 : 0;
+  HIPCHK(hipGetLastError());
+  return FETI_OK;
+}
+
 int build_gj_plan(feti_ctx ctx, GJPlan& P, std::vector<int32_t>& host_flag, int nmat,
                   const std::vector<int>& n, const std::vector<int>& nI, const std::vector<int>& nsw,
                   const std::vector<int64_t>& aofs, const std::vector<int32_t>& lda,
@@ -987,6 +1050,12 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
     // (K^+)_bb into the compact interface blocks
     launch_copy_block(nsub, m.max_nb, m.kofs, m.ld, m.nI, m.sofs, m.ldb, m.nb, (const double*)ctx->Kinv,
                       ctx->Splus, st);
+  }
+  // packed lower tiles of K_s^+ for the local solves, kept beside the dense blocks (an
+  // in-place elimination saves memory and does without them)
+  if (ctx->keep_assembled) {
+    rc = build_sym(ctx, f32);
+    if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
   }
   HIPCHK(hipMemcpyAsync(stat.data(), P.status, nsub * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1242,7 +1311,9 @@ int feti_time_kernel(feti_ctx ctx, int32_t which, int32_t reps, double* avg_ms, 
     a.a_f32 = fc.f32;
     if (which == FETI_KERNEL_LOCAL_SOLVE) {
       a.A = fc.kinv; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0; a.xbase = ctx->f; a.y = ctx->ytmp;
-      for (const SubHost& sh : h.subs) w += esz * sh.ns * sh.ns + 16.0 * sh.ns;
+      // with the packed tiles, the distinct entries of the symmetric K_s^+ are the work
+      for (const SubHost& sh : h.subs)
+        w += ctx->sym.P ? esz * 0.5 * sh.ns * (sh.ns + 1.0) + 16.0 * sh.ns : esz * sh.ns * sh.ns + 16.0 * sh.ns;
     } else {
       a.A = which == FETI_KERNEL_IFACE_GEMV ? fc.splus : fc.sbb;
       a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1; a.v = ctx->p;
@@ -1250,9 +1321,14 @@ int feti_time_kernel(feti_ctx ctx, int32_t which, int32_t reps, double* avg_ms, 
       a.y = ctx->yb;
       for (const SubHost& sh : h.subs) w += esz * sh.nb * sh.nb + 16.0 * sh.nb;
     }
-    launch_sgemv(m, a, st);  // warm-up launch
+    const bool sym = which == FETI_KERNEL_LOCAL_SOLVE && ctx->sym.P;
+    auto run = [&]() {
+      if (sym) launch_sym_gemv(m, ctx->sym, ctx->f, ctx->ytmp, st);
+      else launch_sgemv(m, a, st);
+    };
+    run();  // warm-up launch
     HIPCHK(hipEventRecord(ctx->ev[6], st));
-    for (int i = 0; i < reps; ++i) launch_sgemv(m, a, st);
+    for (int i = 0; i < reps; ++i) run();
     HIPCHK(hipEventRecord(ctx->ev[7], st));
     HIPCHK(hipEventSynchronize(ctx->ev[7]));
   }

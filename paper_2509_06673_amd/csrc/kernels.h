@@ -117,4 +117,23 @@ struct GemvArgs {
   const double* ybase = nullptr;    // optional: y = ybase + A x (+ R alpha_c)
 };
 
+// Local solves from the packed lower tiles of the symmetric K_s^+ (kernels_sym.hip).
+struct SymArgs {
+  int ntile = 0;
+  const int32_t* t_sub = nullptr;   // per stored tile: subdomain, tile row I, tile column J <= I
+  const int32_t* t_I = nullptr;
+  const int32_t* t_J = nullptr;
+  const int64_t* tbase = nullptr;   // per subdomain: first tile; tile (I, J) = tbase + I (I + 1) / 2 + J
+  const int32_t* nt = nullptr;      // per subdomain: tile rows
+  const void* P = nullptr;          // ntile x 64 x 64 column-major tiles (double, or float when f32)
+  int f32 = 0;
+  double* part = nullptr;           // ntile x 2 x 64 partial products
+};
+// packed tiles P from the dense row-major blocks K (offsets kofs, leading dims ld)
+template <class T>
+void launch_sym_pack(const SymArgs& a, const T* K, const int64_t* kofs, const int32_t* ld, const int32_t* ns, T* P,
+                     hipStream_t st);
+// y = K_s^+ x_s for every subdomain (torn vectors)
+void launch_sym_gemv(const DevMesh& m, const SymArgs& a, const double* x, double* y, hipStream_t st);
+
 }  // namespace feti
