@@ -267,9 +267,9 @@ int upload_mesh(feti_ctx ctx) {
       grid = std::min(grid, 2 * cus);
     // one 64-row interface tile per block when the chip holds that many
     grid = std::min(grid, 192);
-    grid = std::min(grid, PCG_BAR_GROUP * PCG_BAR_MAXGRP);
+    grid = std::min({grid, PCG_BAR_GROUP * PCG_BAR_MAXGRP, PCG_MAX_GRID});
     if (const char* e = std::getenv("FETI_PCG_GRID"))
-      grid = std::min({pcg_max_grid(m), std::max(1, std::atoi(e)), PCG_BAR_GROUP * PCG_BAR_MAXGRP});
+      grid = std::min({pcg_max_grid(m), std::max(1, std::atoi(e)), PCG_BAR_GROUP * PCG_BAR_MAXGRP, PCG_MAX_GRID});
     ctx->pgrid = std::max(0, grid);
     RC(dalloc(ctx, &ctx->ppart, (size_t)2 * std::max(1, ctx->pgrid) * PCG_NPART, ctx->allocs));
   }

@@ -32,6 +32,23 @@
 
 namespace feti {
 
+// sum over c in [cb, ce) of H[c][j] g[c] into c0 (even offsets) and c1 (odd offsets):
+// the loads of up to 16 coarse indices are in flight together (indices past ce read
+// row ce - 1 and are not used), so a lane's share costs one round trip
+__device__ inline void h_rows(const double* __restrict__ H, int64_t NL, int64_t j, int cb, int ce,
+                              const double* gl, double& c0, double& c1) {
+  for (int c = cb; c < ce; c += 16) {
+    double h[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) h[u] = H[(int64_t)min(c + u, ce - 1) * NL + j];
+#pragma unroll
+    for (int u = 0; u < 16; u += 2) {
+      if (c + u < ce) c0 += h[u] * gl[c + u];
+      if (c + u + 1 < ce) c1 += h[u + 1] * gl[c + u + 1];
+    }
+  }
+}
+
 // Phases A and E: every 64-row tile of every interface block, two tiles per block
 // at a time (one per half).
 template <class MT, int SCALED>
@@ -117,14 +134,7 @@ __device__ void correct_dot_phase(const PcgArgs& a, const double* vin, double* v
       for (int64_t j0 = (int64_t)blockIdx.x * 64; j0 < NL; j0 += (int64_t)gridDim.x * 64) {
         const int64_t j = j0 + lane;
         double c0 = 0.0, c1 = 0.0;
-        if (j < NL) {
-          int c = cb;
-          for (; c + 2 <= ce; c += 2) {
-            c0 += a.H[(int64_t)c * NL + j] * gl[c];
-            c1 += a.H[(int64_t)(c + 1) * NL + j] * gl[c + 1];
-          }
-          if (c < ce) c0 += a.H[(int64_t)c * NL + j] * gl[c];
-        }
+        if (j < NL) h_rows(a.H, NL, j, cb, ce, gl, c0, c1);
         red4[wave * 64 + lane] = c0 + c1;
         __syncthreads();
         if (wave == 0 && j < NL) {
@@ -192,14 +202,7 @@ __device__ inline void update_phase(const PcgArgs& a, double alpha, double beta,
     for (int64_t j0 = (int64_t)blockIdx.x * 64; j0 < NL; j0 += (int64_t)gridDim.x * 64) {
       const int64_t j = j0 + lane;
       double c0 = 0.0, c1 = 0.0;
-      if (j < NL) {
-        int c = cb;
-        for (; c + 2 <= ce; c += 2) {
-          c0 += a.H[(int64_t)c * NL + j] * gl[c];
-          c1 += a.H[(int64_t)(c + 1) * NL + j] * gl[c + 1];
-        }
-        if (c < ce) c0 += a.H[(int64_t)c * NL + j] * gl[c];
-      }
+      if (j < NL) h_rows(a.H, NL, j, cb, ce, gl, c0, c1);
       red4[wave * 64 + lane] = c0 + c1;
       __syncthreads();
       if (wave == 0 && j < NL) {
@@ -230,18 +233,33 @@ __device__ inline void update_phase(const PcgArgs& a, double alpha, double beta,
       __syncthreads();
     }
   }
-  block_store<NV>(acc, red, part + blockIdx.x * PCG_NPART);
+  // only wavefront 0 holds row sums: a shuffle reduction there, lane 0 stores
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      double x = acc[c];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+      acc[c] = x;
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int c = 0; c < NV; ++c) ast(part + blockIdx.x * PCG_NPART + c, acc[c]);
+  }
 }
+
+static_assert(PCG_MAX_GRID * 19 <= GT_LOADS * PB, "the stopping test stages every partial sum once");
 
 __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
   extern __shared__ double lds[];
   __shared__ int s_ok, s_upd;
+  __shared__ double s_res;
   __shared__ double s_ring[UPD_WIN * 6];
   const DevMesh& m = a.m;
   double* xs = lds;                          // 2 x max_nb gathered vectors (one per tile)
   double* red4 = xs + 2 * m.max_nb;          // PB partial rows
   double* acl = red4 + PB;                   // coarse coefficients, then g (2 x PCG_NC_LOCAL)
   double* red = acl + 2 * PCG_NC_LOCAL;
+  double* stage = red + (PB / 64) * PCG_NPART;  // nblk x 19 staged partial sums
   const int nblk = gridDim.x;
   const int64_t NL = m.n_lambda;
   uint32_t gen = 0;  // the host clears the barrier before the launch
@@ -257,8 +275,9 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
   const bool start_done = a.ist[IS_DONE] != 0 || iters >= maxit;  // the same in every block
   int rk = 0;  // reductions so far: partial buffer rk & 1
   auto partbuf = [&](int k) { return a.part + (size_t)(k & 1) * nblk * PCG_NPART; };
-  double conv[19];
-  for (int c = 0; c < 19; ++c) conv[c] = 0.0;
+  __shared__ double conv[19];  // totals of the last stopping test
+  if (threadIdx.x < 19) conv[threadIdx.x] = 0.0;
+  __syncthreads();
   int it_local = 0, ph = 0;
   auto stamp = [&]() {
     if (a.tstamp && blockIdx.x == 0 && threadIdx.x == 0 && it_local < a.tstamp_iters)
@@ -266,7 +285,7 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
     ++ph;
   };
   stamp();
-  for (; !start_done; ++it_local, ph = 1) {  // stamp 0 of a later iteration is stamp 8 of the one before
+  for (; !start_done; ++it_local, ph = 1) {  // stamp 0 of a later iteration is stamp 7 of the one before
     // (A) y_b = (K^+)_bb B^T p,  p = y + beta p_old
     if (a.fm32) gemv_phase<float, 0>(a, (const float*)a.fm, a.y, a.p, beta, a.yb, xs, red4);
     else gemv_phase<double, 0>(a, (const double*)a.fm, a.y, a.p, beta, a.yb, xs, red4);
@@ -293,21 +312,19 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
     stamp();
     {
-      if (upd) grid_total<19>(partbuf(rk++), nblk, conv, red);
-      else {
-        double c7[7];
-        grid_total<7>(partbuf(rk++), nblk, c7, red);
-        for (int c = 0; c < 7; ++c) conv[c] = c7[c];
-      }
-      res = rel_residual_of(conv, conv[6], a.sc);
-      iters += 1;
-      if (upd) {
+      // thread 0 forms the totals and the decisions; the block reads them from LDS
+      if (upd) grid_total_t0<19>(partbuf(rk++), nblk, conv, stage, red);
+      else grid_total_t0<7>(partbuf(rk++), nblk, conv, stage, red);
+      if (threadIdx.x == 0) {
+        s_res = rel_residual_of(conv, conv[6], a.sc);
         // counted within this launch, so that the ring holds only this launch's updates
-        if (threadIdx.x == 0) s_upd = update_converged(s_ring, it_local + 1, alpha, conv + 7, conv + 13, utol);
-        __syncthreads();
+        s_upd = upd ? update_converged(s_ring, it_local + 1, alpha, conv + 7, conv + 13, utol) : 0;
       }
+      __syncthreads();
+      res = s_res;
+      iters += 1;
       if (!isfinite(res)) { status = FETI_ENAN; break; }
-      if (res <= tol || (upd && s_upd)) break;
+      if (res <= tol || s_upd) break;
       if (iters >= maxit) { status = FETI_ENOTCONV; break; }
     }
     stamp();
@@ -363,7 +380,8 @@ void launch_build_h(const DevMesh& m, const double* Cinv, int nc, double* H, hip
 }
 
 size_t pcg_shmem(const DevMesh& m) {
-  return sizeof(double) * (2 * (size_t)m.max_nb + PB + 2 * PCG_NC_LOCAL + (PB / 64) * PCG_NPART);
+  return sizeof(double) * (2 * (size_t)m.max_nb + PB + 2 * PCG_NC_LOCAL + (PB / 64) * PCG_NPART +
+                           (size_t)PCG_MAX_GRID * 19);
 }
 
 int pcg_max_grid(const DevMesh& m) {

@@ -24,6 +24,7 @@ struct GridBarrier {
 constexpr int PCG_BLOCK = 512;   // threads per block of the persistent launch (two GEMV tiles at once)
 constexpr int PCG_NPART = 24;    // partial sums per block
 constexpr int PCG_NC_LOCAL = 192;  // coarse sizes applied redundantly in every block
+constexpr int PCG_MAX_GRID = 256;  // largest grid of the single-problem launch (stopping-test staging)
 
 struct PcgArgs {
   DevMesh m;

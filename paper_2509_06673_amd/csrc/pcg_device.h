@@ -11,6 +11,11 @@
 namespace feti {
 
 constexpr int PB = PCG_BLOCK;
+#ifndef FETI_GEMV_BATCH
+#define FETI_GEMV_BATCH 8
+#endif
+constexpr int GEMV_BATCH = FETI_GEMV_BATCH;  // column loads in flight per lane (multiple of 4)
+static_assert(GEMV_BATCH % 4 == 0, "GEMV batches are consumed four at a time");
 constexpr long long PCG_SPIN_LIMIT = 1ll << 21;
 
 // Data that one block writes and another reads within the launch (the multiplier
@@ -142,6 +147,34 @@ __device__ inline void grid_total(const double* part, int nblk, double (&v)[NV],
   block_sum<NV>(v, red);
 }
 
+// Sum of the per-block partials part[b][0..NV) over all blocks, in block order, into
+// v[0..NV) (LDS, valid after the call in every thread).  The nblk x NV coherent loads
+// are spread over the threads (at most GT_LOADS each, issued together) and staged in
+// LDS (stage: nblk x NV doubles); thread c then adds value c over the blocks.
+constexpr int GT_LOADS = 10;
+template <int NV>
+__device__ inline void grid_total_t0(const double* part, int nblk, double* v, double* stage, double* red) {
+  const int total = nblk * NV;  // <= GT_LOADS * PB (checked on the host)
+  double t[GT_LOADS];
+#pragma unroll
+  for (int k = 0; k < GT_LOADS; ++k) {
+    const int idx = threadIdx.x + k * PB;
+    t[k] = idx < total ? ald(part + (idx / NV) * PCG_NPART + idx % NV) : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < GT_LOADS; ++k) {
+    const int idx = threadIdx.x + k * PB;
+    if (idx < total) stage[idx] = t[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double x = 0.0;
+    for (int b = 0; b < nblk; ++b) x += stage[b * NV + threadIdx.x];
+    v[threadIdx.x] = x;
+  }
+  __syncthreads();  // v complete; stage free again
+}
+
 // One 64-row tile of y_b = A_s x_b (interface block of subdomain s) by one half of
 // the block (four wavefronts, threads ht = 0..255): x_b gathered into xs, the
 // wavefronts split the column range and combine in red4.  SCALED = 0: x_b = B_s^T p
@@ -190,21 +223,22 @@ __device__ inline void gemv_tile(const DevMesh& m, const MT* A, int s, int row0,
   if (i < nbs) {
     const MT* As = A + m.sofs[s];
     const int64_t ld = m.ldb[s];
-    // batches of eight independent column loads in flight before their FMAs
+    // batches of GEMV_BATCH independent column loads in flight before their FMAs: a
+    // lane's column range is a chain of dependent round trips to HBM, so the batch
+    // size sets the bytes in flight
     const MT* col = As + (int64_t)kb * ld + i;
     int k = kb;
-    for (; k + 8 <= ke; k += 8, col += 8 * ld) {
-      MT v[8];
+    for (; k + GEMV_BATCH <= ke; k += GEMV_BATCH, col += GEMV_BATCH * ld) {
+      MT v[GEMV_BATCH];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = col[(int64_t)u * ld];
-      acc0 += (double)v[0] * xs[k + 0];
-      acc1 += (double)v[1] * xs[k + 1];
-      acc2 += (double)v[2] * xs[k + 2];
-      acc3 += (double)v[3] * xs[k + 3];
-      acc0 += (double)v[4] * xs[k + 4];
-      acc1 += (double)v[5] * xs[k + 5];
-      acc2 += (double)v[6] * xs[k + 6];
-      acc3 += (double)v[7] * xs[k + 7];
+      for (int u = 0; u < GEMV_BATCH; ++u) v[u] = col[(int64_t)u * ld];
+#pragma unroll
+      for (int u = 0; u < GEMV_BATCH; u += 4) {
+        acc0 += (double)v[u + 0] * xs[k + u + 0];
+        acc1 += (double)v[u + 1] * xs[k + u + 1];
+        acc2 += (double)v[u + 2] * xs[k + u + 2];
+        acc3 += (double)v[u + 3] * xs[k + u + 3];
+      }
     }
     for (; k < ke; ++k, col += ld) acc0 += (double)col[0] * xs[k];
   }
