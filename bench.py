@@ -34,9 +34,11 @@ FP32_PEAK_TFS = 157.3
 # a 256 MiB copy).  The figure belongs to the kernel sources it was measured on: another
 # source hash reports null.
 MEASURED_TRAFFIC = {"sources": ["paper_2509_06673_amd/csrc/kernels_pcg.hip",
-                                "paper_2509_06673_amd/csrc/pcg_device.h"],
-                    "sha256_16": "136d483f3c2a15ed",
-                    "bytes_per_iteration": (38099225.2 * 1.99982 + 547345.0) * 1024 / 509}
+                                "paper_2509_06673_amd/csrc/pcg_device.h",
+                                "paper_2509_06673_amd/csrc/pcg.h",
+                                "paper_2509_06673_amd/csrc/iface_device.h"],
+                    "sha256_16": "d0483ffe60873f43",
+                    "bytes_per_iteration": (39924678.0 * 1.99982 + 567758.4) * 1024 / 533}
 
 
 def source_hash(paths):

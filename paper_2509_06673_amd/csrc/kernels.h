@@ -36,7 +36,7 @@ struct DevMesh {
           *el_code = nullptr;
   int32_t *adj_ptr = nullptr, *adj = nullptr;  // torn DOF -> element contributions
   double* ebuf = nullptr;                      // nelem x edof element contributions
-  double* emat = nullptr;                      // nelem x edof x edof element matrices K_e
+  double* emat = nullptr;                      // nelem x edof x edof element matrices K_e (column-major)
   // interface space
   int32_t* bg_row = nullptr;    // 2 per b DOF
   double* bg_sign = nullptr;

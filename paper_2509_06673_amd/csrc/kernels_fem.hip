@@ -125,8 +125,10 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
 }
 
 // One thread per (element, row): ebuf[e][row] = (K_e x_e)[row]
-// One thread per (element, row): row r of K_e into emat (every entry, also those of
-// Dirichlet DOFs, which the products skip)
+// One thread per (element, row): row r of K_e into emat, column-major per element
+// (entry (r, c) at (e edof + c) edof + r, so that the threads of consecutive rows read
+// consecutive addresses); every entry, also those of Dirichlet DOFs, which the
+// products skip
 __global__ void k_elem_store(DevMesh m, MatParams mpP, MatParams mpE) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int edof = m.edof;
@@ -137,8 +139,8 @@ __global__ void k_elem_store(DevMesh m, MatParams mpP, MatParams mpE) {
   ElemGeom g;
   elem_geom(m.el_cell[e], m.el_type[e], m.ncell, g);
   const MatParams& mp = poro ? mpP : mpE;
-  double* row = m.emat + gid * edof;
-  for (int c = 0; c < edof; ++c) row[c] = elem_entry(m.order, poro, g, mp, r, c);
+  double* col0 = m.emat + e * edof * edof + r;
+  for (int c = 0; c < edof; ++c) col0[(int64_t)c * edof] = elem_entry(m.order, poro, g, mp, r, c);
 }
 
 // One thread per (element, row): ebuf[e][row] = (K_e x_e)[row], K_e read from emat
@@ -152,10 +154,10 @@ __global__ void k_elem_matvec(DevMesh m, const double* __restrict__ x) {
   double acc = 0.0;
   if (ld[r] >= 0) {
     const double* xs = x + m.soff[m.el_sub[e]];
-    const double* row = m.emat + gid * edof;
+    const double* col0 = m.emat + e * edof * edof + r;
     for (int c = 0; c < edof; ++c) {
       const int lc = ld[c];
-      if (lc >= 0) acc += row[c] * xs[lc];
+      if (lc >= 0) acc += col0[(int64_t)c * edof] * xs[lc];
     }
   }
   m.ebuf[gid] = acc;
