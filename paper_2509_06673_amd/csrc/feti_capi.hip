@@ -74,6 +74,14 @@ struct feti_ctx_s {
   double *part = nullptr, *sc = nullptr;
   int32_t* ist = nullptr;
   int32_t* h_ist = nullptr;
+  // per-solve records of a time step (status, iterations, residuals, phase events), read
+  // after the step's single synchronisation
+  static constexpr int NREC = 8;
+  int32_t* h_rec_ist = nullptr;  // NREC x IS_COUNT (pinned)
+  double* h_rec_sc = nullptr;    // NREC x SC_COUNT (pinned)
+  hipEvent_t rec_ev[NREC][4] = {};
+  int32_t* d_pick = nullptr;     // device-side start choice of the last candidate comparison
+  int32_t* h_pick = nullptr;     // (pinned copy)
   double* h_sc = nullptr;
   int64_t nstep = 0;
   bool have_prev = false, have_prev2 = false;
@@ -237,6 +245,7 @@ int upload_mesh(feti_ctx ctx) {
   RC(dalloc(ctx, &ctx->cj, h.n_lambda, ctx->allocs));
   RC(dalloc(ctx, &ctx->mdiag, h.n_lambda, ctx->allocs));
   RC(dalloc(ctx, &ctx->kpart, (size_t)KMAX_NBLK * 12, ctx->allocs));
+  RC(dalloc(ctx, &ctx->d_pick, 1, ctx->allocs));
   double** lv[] = {&ctx->lam, &ctx->lam_prev, &ctx->lam_prev2, &ctx->d, &ctx->r, &ctx->w,
                    &ctx->z, &ctx->y, &ctx->p, &ctx->q, &ctx->qraw, &ctx->tl, &ctx->lam_given, &ctx->lam_alt};
   for (double** pp : lv) RC(dalloc(ctx, pp, nl, ctx->allocs));
@@ -281,6 +290,12 @@ int upload_mesh(feti_ctx ctx) {
     HIPCHK(hipHostMalloc((void**)&ctx->h_ist, IS_COUNT * sizeof(int32_t), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&ctx->h_sc, SC_COUNT * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&ctx->h_kpart, KMAX_NBLK * 12 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&ctx->h_rec_ist, feti_ctx_s::NREC * IS_COUNT * sizeof(int32_t), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&ctx->h_rec_sc, feti_ctx_s::NREC * SC_COUNT * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&ctx->h_pick, sizeof(int32_t), hipHostMallocDefault));
+    for (auto& r : ctx->rec_ev)
+      for (auto& e : r)
+        if (!e) HIPCHK(hipEventCreate(&e));
   }
   for (auto& e : ctx->ev)
     if (!e) HIPCHK(hipEventCreate(&e));
@@ -467,7 +482,7 @@ int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
     if (!took_cand) {
       RC(start_residual(ctx, lam, nullptr, SC_SEL0));
       RC(start_residual(ctx, ctx->lam_alt, nullptr, SC_SEL1));
-      launch_pick_start(nl, ctx->sc, ctx->lam_alt, lam, st);
+      launch_pick_start(nl, ctx->sc, ctx->lam_alt, lam, ctx->d_pick, st);
     } else {
       double n_lam = 0.0, n_alt = 0.0;
       RC(start_residual(ctx, lam, &n_lam));
@@ -516,14 +531,17 @@ int torn_end(feti_ctx ctx, const double* lam, double* u) {
   return FETI_OK;
 }
 
+// Enqueues one torn solve; its status, iterations, residuals and phase events go to
+// record slot (read by finish_solve once the stream has been synchronised).  Returns
+// only launch failures.
 int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, const double* f, const double* cj,
-               double* lam, double* u, feti_stats* stats, int* iters_out, double* res0,
-               double* res, const double* cand = nullptr, int* took_cand = nullptr) {
+               double* lam, double* u, int slot, const double* cand = nullptr, int* took_cand = nullptr) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
-  HIPCHK(hipEventRecord(ctx->ev[1], st));
+  hipEvent_t* ev = ctx->rec_ev[slot];
+  HIPCHK(hipEventRecord(ev[0], st));
   RC(torn_begin(ctx, o, tol, utol, f, cj, lam, cand, took_cand));
-  HIPCHK(hipEventRecord(ctx->ev[2], st));
+  HIPCHK(hipEventRecord(ev[1], st));
   const int32_t* done = ctx->ist + IS_DONE;
   const int chunk = std::max(1, o->check_every);
   static const bool trace = std::getenv("FETI_TRACE") != nullptr;
@@ -636,24 +654,32 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
       for (int it = 0; it < chunk; ++it) pcg_iteration(ctx, lam, done);
     }
   }
-  HIPCHK(hipEventRecord(ctx->ev[3], st));
+  HIPCHK(hipEventRecord(ev[2], st));
   RC(torn_end(ctx, lam, u));
-  HIPCHK(hipEventRecord(ctx->ev[4], st));
-  HIPCHK(hipMemcpyAsync(ctx->h_ist, ctx->ist, IS_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(ctx->h_sc, ctx->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  const int status = ctx->h_ist[IS_STATUS];
-  if (iters_out) *iters_out += ctx->h_ist[IS_ITERS];
-  if (res0) *res0 = ctx->h_sc[SC_RES0];
-  if (res) *res = ctx->h_sc[SC_RES];
+  HIPCHK(hipEventRecord(ev[3], st));
+  HIPCHK(hipMemcpyAsync(ctx->h_rec_ist + slot * IS_COUNT, ctx->ist, IS_COUNT * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ctx->h_rec_sc + slot * SC_COUNT, ctx->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                        st));
+  return FETI_OK;
+}
+
+// Outcome of the solve recorded in slot (the stream has been synchronised since):
+// accumulates its iterations and phase times, returns its status (with the message).
+int finish_solve(feti_ctx ctx, int slot, feti_stats* stats, int* iters_out, double* res0, double* res) {
+  const int32_t* hi = ctx->h_rec_ist + slot * IS_COUNT;
+  const double* hs = ctx->h_rec_sc + slot * SC_COUNT;
+  const int status = hi[IS_STATUS];
+  if (iters_out) *iters_out += hi[IS_ITERS];
+  if (res0) *res0 = hs[SC_RES0];
+  if (res) *res = hs[SC_RES];
   if (stats) {
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]);
-    stats->t_ms[1] += ms;
-    hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]);
-    stats->t_ms[2] += ms;
-    hipEventElapsedTime(&ms, ctx->ev[3], ctx->ev[4]);
-    stats->t_ms[3] += ms;
+    const hipEvent_t* ev = ctx->rec_ev[slot];
+    for (int k = 0; k < 3; ++k) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      stats->t_ms[1 + k] += ms;
+    }
   }
   if (status == FETI_EHIP) return fail(ctx, status, "persistent PCG: grid barrier timed out");
   if (status == FETI_ENOTCONV) return fail(ctx, status, "PCG did not converge within max_it");
@@ -675,33 +701,55 @@ void torn_residual(feti_ctx ctx, const double* f, const double* u, const double*
 }
 
 // One FETI solve followed by up to nref FP64 refinement corrections.  history: a time
-// step (its total correction is kept for the next step's first correction).
+// step (its total correction is kept for the next step's first correction, and the
+// multiplier history is advanced).  The stream is synchronised once at the end, and
+// between corrections only when a later one may be skipped (nref > 1).
 int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* stats,
                   const double* cand = nullptr, int* took_cand = nullptr, bool history = false) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
-  int iters = 0;
-  double res0 = 0, res = 0, r0c = 0, rc_ = 0;
   const double tol_first =
       (ctx->precision == FETI_FP32_IR && o->tol_inner > 0.0) ? std::max(o->tol, o->tol_inner) : o->tol;
-  int rc = solve_torn(ctx, o, tol_first, 0.0, ctx->f, nullptr, ctx->lam, ctx->u, stats, &iters, &res0, &res, cand,
-                      took_cand);
-  const int iters_first = iters;
-  int done_ir = 0;
-  double corr = 0.0;
+  int nrec = 0, nfin = 0, rc = FETI_OK, iters = 0, iters_first = 0, done_ir = 0;
+  double res0 = 0, res = 0, r0c = 0, rc_ = 0, corr = 0.0;
+  int it_corr[feti_ctx_s::NREC] = {0};
+  RC(solve_torn(ctx, o, tol_first, 0.0, ctx->f, nullptr, ctx->lam, ctx->u, nrec++, cand, took_cand));
+  // outcome of every enqueued solve not read yet (after a synchronisation)
+  auto finish = [&]() {
+    for (; nfin < nrec; ++nfin) {
+      int its = 0;
+      const int s = nfin == 0 ? finish_solve(ctx, 0, stats, &its, &res0, &res)
+                              : finish_solve(ctx, nfin, stats, &its, &r0c, &rc_);
+      if (nfin == 0) iters_first = its;
+      else it_corr[nfin - 1] = its;
+      iters += its;
+      if (s != FETI_OK && (rc == FETI_OK || rc == FETI_ENOTCONV)) rc = s;
+    }
+  };
+  auto correction_size = [&]() {
+    double mx[12] = {0};
+    for (int b = 0; b < KMAX_NBLK; ++b)
+      for (int c = 0; c < 12; ++c) mx[c] = std::max(mx[c], ctx->h_kpart[b * 12 + c]);
+    double cs = 0.0;
+    for (int kk = 0; kk < 6; ++kk)
+      if (mx[6 + kk] > 0.0) cs = std::max(cs, mx[kk] / mx[6 + kk]);
+    return cs;
+  };
   HIPCHK(hipEventRecord(ctx->ev[6], st));
-  for (int k = 0; k < nref && (rc == FETI_OK || rc == FETI_ENOTCONV); ++k) {
+  bool warm_used = false;
+  for (int k = 0; k < nref && nrec < feti_ctx_s::NREC; ++k) {
     torn_residual(ctx, ctx->f, ctx->u, ctx->lam);
     HIPCHK(hipMemsetAsync(ctx->dlam, 0, m.n_lambda * sizeof(double), st));
     // the first correction of a time step may start from the previous step's total
-    // correction, kept only if its projected residual beats the zero start
+    // correction, kept only if its projected residual beats the zero start (chosen on
+    // the device)
     const bool warm = history && k == 0 && o->corr_start == FETI_CORR_PREVIOUS && ctx->have_dlam_prev;
-    int took_warm = 0, it_corr = 0;
-    rc = solve_torn(ctx, o, o->tol_corr, o->tol_upd, ctx->rf, ctx->cj, ctx->dlam, ctx->du, stats, &it_corr, &r0c,
-                    &rc_, warm ? ctx->dlam_prev : nullptr, warm ? &took_warm : nullptr);
-    iters += it_corr;
-    if (stats && k < 4) stats->iters_corr[k] = it_corr;
-    if (stats && k == 0) stats->corr_warm = took_warm;
+    RC(solve_torn(ctx, o, o->tol_corr, o->tol_upd, ctx->rf, ctx->cj, ctx->dlam, ctx->du, nrec++,
+                  warm ? ctx->dlam_prev : nullptr, nullptr));
+    if (warm) {
+      HIPCHK(hipMemcpyAsync(ctx->h_pick, ctx->d_pick, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      warm_used = true;
+    }
     launch_axpby(m.sum_ns, 1.0, ctx->u, 1.0, ctx->du, ctx->u, st);
     launch_axpby(m.n_lambda, 1.0, ctx->lam, 1.0, ctx->dlam, ctx->lam, st);
     launch_axpby(m.n_lambda, 1.0, ctx->dlam, k == 0 ? 0.0 : 1.0, k == 0 ? nullptr : ctx->dlam_sum, ctx->dlam_sum,
@@ -710,27 +758,38 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
     launch_kind_maxabs(m, ctx->du, ctx->u, ctx->kpart, KMAX_NBLK, st);
     HIPCHK(hipMemcpyAsync(ctx->h_kpart, ctx->kpart, KMAX_NBLK * 12 * sizeof(double),
                           hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    double mx[12] = {0};
-    for (int b = 0; b < KMAX_NBLK; ++b)
-      for (int c = 0; c < 12; ++c) mx[c] = std::max(mx[c], ctx->h_kpart[b * 12 + c]);
-    corr = 0.0;
-    for (int kk = 0; kk < 6; ++kk)
-      if (mx[6 + kk] > 0.0) corr = std::max(corr, mx[kk] / mx[6 + kk]);
     ++done_ir;
-    if (corr <= o->ir_tol) break;
+    if (k + 1 < nref) {
+      // a later correction runs only if this one still changed the fields
+      HIPCHK(hipStreamSynchronize(st));
+      finish();
+      if (!(rc == FETI_OK || rc == FETI_ENOTCONV)) break;
+      corr = correction_size();
+      if (corr <= o->ir_tol) break;
+    }
   }
+  if (history) {
+    // multiplier history for the next step's start
+    std::swap(ctx->lam_prev2, ctx->lam_prev);
+    launch_axpby(m.n_lambda, 1.0, ctx->lam, 0.0, nullptr, ctx->lam_prev, st);
+    HIPCHK(hipEventRecord(ctx->ev[5], st));
+  }
+  HIPCHK(hipEventRecord(ctx->ev[7], st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  finish();
+  if (done_ir > 0) corr = correction_size();
   if (history) {
     // the step's total correction, for the next step
     if (done_ir > 0 && rc == FETI_OK) std::swap(ctx->dlam_prev, ctx->dlam_sum);
     ctx->have_dlam_prev = done_ir > 0 && rc == FETI_OK;
   }
-  HIPCHK(hipEventRecord(ctx->ev[7], st));
-  HIPCHK(hipStreamSynchronize(st));
   if (stats) {
     stats->iters = iters;
     stats->iters_first = iters_first;
     stats->ir_steps = done_ir;
+    for (int k = 0; k < 4 && k < done_ir; ++k) stats->iters_corr[k] = it_corr[k];
+    stats->corr_warm = warm_used ? *ctx->h_pick : 0;
     stats->res0 = res0;
     stats->res = res;
     stats->rho = corr;
@@ -875,6 +934,12 @@ int feti_destroy(feti_ctx ctx) {
     if (ctx->h_ist) (void)hipHostFree(ctx->h_ist);
     if (ctx->h_sc) (void)hipHostFree(ctx->h_sc);
     if (ctx->h_kpart) (void)hipHostFree(ctx->h_kpart);
+    if (ctx->h_rec_ist) (void)hipHostFree(ctx->h_rec_ist);
+    if (ctx->h_rec_sc) (void)hipHostFree(ctx->h_rec_sc);
+    if (ctx->h_pick) (void)hipHostFree(ctx->h_pick);
+    for (auto& r : ctx->rec_ev)
+      for (auto& e : r)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   }
   delete ctx;
@@ -1150,20 +1215,16 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, fet
   if (stats) std::memset(stats, 0, sizeof(*stats));
   int took = 0;
   const double* cand = (o->start == FETI_START_BEST) ? ctx->lam_given : nullptr;
+  // (solve_refined advances the multiplier history and synchronises the stream)
   int rc = solve_refined(ctx, o, cold ? std::max(o->ir_cold, o->ir_max) : o->ir_max, stats, cand, &took, true);
   if (cand && took) used = FETI_START_GIVEN;
-  // keep the multiplier history
-  std::swap(ctx->lam_prev2, ctx->lam_prev);
-  launch_axpby(m.n_lambda, 1.0, ctx->lam, 0.0, nullptr, ctx->lam_prev, st);
   ctx->have_prev2 = ctx->have_prev;
   ctx->have_prev = true;
   ctx->nstep += 1;
-  HIPCHK(hipEventRecord(ctx->ev[5], st));
-  HIPCHK(hipStreamSynchronize(st));
   if (stats) {
     stats->start_used = used;
     float ms = 0.f;
-    hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]);
+    hipEventElapsedTime(&ms, ctx->ev[0], ctx->rec_ev[0][0]);  // right-hand side, up to the first solve
     stats->t_ms[0] = ms;
     hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[5]);
     stats->t_ms[5] = ms;

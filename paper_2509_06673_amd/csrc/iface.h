@@ -38,7 +38,8 @@ void launch_zero(int64_t n, double* z, hipStream_t st);
 // sc[dst] = sc[src]
 void launch_copy_scalar(double* sc, int src, int dst, hipStream_t st);
 // lam = alt where sc[SC_SEL1] < sc[SC_SEL0] (the candidate's residual is the smaller)
-void launch_pick_start(int64_t n, const double* sc, const double* alt, double* lam, hipStream_t st);
+// (flag, when given, receives 1 if the candidate was taken, else 0)
+void launch_pick_start(int64_t n, const double* sc, const double* alt, double* lam, int32_t* flag, hipStream_t st);
 // out = jump (or (B B^T)^{-1}-weighted jump) of yb; with g, also g = G^T out
 void launch_jump(const DevMesh& m, const double* yb, int from_torn, double* out, int scaled,
                  double* g, const int32_t* skip, hipStream_t st);

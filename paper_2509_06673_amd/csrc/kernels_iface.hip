@@ -533,9 +533,11 @@ __global__ void k_copy_scalar(double* __restrict__ sc, int src, int dst) {
 }
 
 __global__ void k_pick_start(int64_t n, const double* __restrict__ sc, const double* __restrict__ alt,
-                             double* __restrict__ lam) {
+                             double* __restrict__ lam, int32_t* __restrict__ flag) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n || !(sc[SC_SEL1] < sc[SC_SEL0])) return;
+  const bool take = sc[SC_SEL1] < sc[SC_SEL0];
+  if (j == 0 && flag) *flag = take ? 1 : 0;
+  if (j >= n || !take) return;
   lam[j] = alt[j];
 }
 
@@ -545,8 +547,8 @@ void launch_copy_scalar(double* sc, int src, int dst, hipStream_t st) {
   hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(64), 0, st, sc, src, dst);
 }
 
-void launch_pick_start(int64_t n, const double* sc, const double* alt, double* lam, hipStream_t st) {
-  hipLaunchKernelGGL(k_pick_start, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, sc, alt, lam);
+void launch_pick_start(int64_t n, const double* sc, const double* alt, double* lam, int32_t* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_pick_start, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, sc, alt, lam, flag);
 }
 
 void launch_init_scalars(double* sc, int32_t* ist, double tol, double utol, int maxit, hipStream_t st) {
