@@ -71,6 +71,7 @@ struct feti_ctx_s {
          *tl = nullptr;
   double *g = nullptr, *ac = nullptr;
   double *lam_given = nullptr, *lam_alt = nullptr;  // start set by feti_set_start; scratch
+  double *r_alt = nullptr, *w_alt = nullptr, *gd = nullptr, *gq = nullptr;  // start comparison, G^T d, G^T F lam
   double *part = nullptr, *sc = nullptr;
   int32_t* ist = nullptr;
   int32_t* h_ist = nullptr;
@@ -247,11 +248,14 @@ int upload_mesh(feti_ctx ctx) {
   RC(dalloc(ctx, &ctx->kpart, (size_t)KMAX_NBLK * 12, ctx->allocs));
   RC(dalloc(ctx, &ctx->d_pick, 1, ctx->allocs));
   double** lv[] = {&ctx->lam, &ctx->lam_prev, &ctx->lam_prev2, &ctx->d, &ctx->r, &ctx->w,
-                   &ctx->z, &ctx->y, &ctx->p, &ctx->q, &ctx->qraw, &ctx->tl, &ctx->lam_given, &ctx->lam_alt};
+                   &ctx->z, &ctx->y, &ctx->p, &ctx->q, &ctx->qraw, &ctx->tl, &ctx->lam_given, &ctx->lam_alt,
+                   &ctx->r_alt, &ctx->w_alt};
   for (double** pp : lv) RC(dalloc(ctx, pp, nl, ctx->allocs));
   ctx->nc = 3 * h.n_float;
   RC(dalloc(ctx, &ctx->g, std::max(ctx->nc, 1), ctx->allocs));
   RC(dalloc(ctx, &ctx->ac, std::max(ctx->nc, 1), ctx->allocs));
+  RC(dalloc(ctx, &ctx->gd, std::max(ctx->nc, 1), ctx->allocs));
+  RC(dalloc(ctx, &ctx->gq, std::max(ctx->nc, 1), ctx->allocs));
   RC(dalloc(ctx, &ctx->part, (size_t)RED_NBLK * NPART, ctx->allocs));
   RC(dalloc(ctx, &ctx->sc, SC_COUNT, ctx->allocs));
   RC(dalloc(ctx, &ctx->ist, IS_COUNT, ctx->allocs));
@@ -475,6 +479,43 @@ int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
   };
   admissible(lam);
   if (took_cand) *took_cand = 0;
+  if (ctx->H && !took_cand) {
+    static_assert(HPROJ_NC_MAX >= PCG_NC_LOCAL, "H exists for every coarse size the projection kernel takes");
+    // with H: a projection is one pass (P v = v - H G^T v), G^T of d and of F lam come
+    // with their own passes, r = d - F lam and w = P r are formed together, and a
+    // compared candidate keeps its r and w
+    launch_coarse_g(m, ctx->d, nullptr, 1.0, ctx->gd, nullptr, st);
+    auto start_rw = [&](const double* v, double* r, double* w) {
+      op_F_raw(ctx, v, ctx->q, ctx->gq, nullptr);
+      launch_h_project(nl, ctx->nc, ctx->H, ctx->d, ctx->q, ctx->gd, ctx->gq, w, r, nullptr, st);
+    };
+    start_rw(lam, ctx->r, ctx->w);
+    if (cand) {
+      // keep the candidate start if its projected residual (dual-energy norm) is smaller
+      launch_axpby(nl, 1.0, cand, 0.0, nullptr, ctx->lam_alt, st);
+      admissible(ctx->lam_alt);
+      start_rw(ctx->lam_alt, ctx->r_alt, ctx->w_alt);
+      launch_reduce(m, nullptr, nullptr, ctx->w, ctx->mdiag, ctx->part, counter(ctx, PH_REFNORM), ctx->sc, ctx->ist,
+                    PH_REFNORM, st);
+      launch_copy_scalar(ctx->sc, SC_EREF, SC_SEL0, st);
+      launch_reduce(m, nullptr, nullptr, ctx->w_alt, ctx->mdiag, ctx->part, counter(ctx, PH_REFNORM), ctx->sc,
+                    ctx->ist, PH_REFNORM, st);
+      launch_copy_scalar(ctx->sc, SC_EREF, SC_SEL1, st);
+      launch_pick_start(nl, ctx->sc, ctx->lam_alt, lam, ctx->d_pick, st, ctx->r_alt, ctx->r, ctx->w_alt, ctx->w);
+    }
+    // tolerance reference: per-kind norms of P d
+    launch_init_scalars(ctx->sc, ctx->ist, tol, utol, std::max(o->max_it, 0), st);
+    launch_h_project(nl, ctx->nc, ctx->H, ctx->d, nullptr, ctx->gd, nullptr, ctx->tl, nullptr, nullptr, st);
+    launch_reduce(m, nullptr, nullptr, ctx->tl, ctx->mdiag, ctx->part, counter(ctx, PH_REFNORM), ctx->sc,
+                  ctx->ist, PH_REFNORM, st);
+    // y = P M^{-1} w, p = y
+    op_M_raw(ctx, ctx->w, ctx->z, ctx->gq, nullptr);
+    launch_h_project(nl, ctx->nc, ctx->H, ctx->z, nullptr, ctx->gq, nullptr, ctx->y, nullptr, ctx->p, st);
+    launch_reduce(m, ctx->w, ctx->y, ctx->w, ctx->mdiag, ctx->part, counter(ctx, PH_INIT), ctx->sc,
+                  ctx->ist, PH_INIT, st);
+    HIPCHK(hipGetLastError());
+    return FETI_OK;
+  }
   if (cand) {
     // keep the candidate start if its projected residual is smaller
     launch_axpby(nl, 1.0, cand, 0.0, nullptr, ctx->lam_alt, st);

@@ -38,8 +38,17 @@ void launch_zero(int64_t n, double* z, hipStream_t st);
 // sc[dst] = sc[src]
 void launch_copy_scalar(double* sc, int src, int dst, hipStream_t st);
 // lam = alt where sc[SC_SEL1] < sc[SC_SEL0] (the candidate's residual is the smaller)
-// (flag, when given, receives 1 if the candidate was taken, else 0)
-void launch_pick_start(int64_t n, const double* sc, const double* alt, double* lam, int32_t* flag, hipStream_t st);
+// (flag, when given, receives 1 if the candidate was taken, else 0; alt2/dst2 and
+// alt3/dst3, when given, are copied along with it)
+void launch_pick_start(int64_t n, const double* sc, const double* alt, double* lam, int32_t* flag, hipStream_t st,
+                       const double* alt2 = nullptr, double* dst2 = nullptr, const double* alt3 = nullptr,
+                       double* dst3 = nullptr);
+// Projection with H = G (G^T G)^{-1} (coarse-index major, nc x n, nc <= HPROJ_NC_MAX):
+// v = a - b, out = v - H (g1 - g2) (b, g2 may be null); r_out (optional) = v, out2
+// (optional) = out.  With g1 - g2 = G^T v this is out = P v.
+constexpr int HPROJ_NC_MAX = 192;
+void launch_h_project(int64_t n, int nc, const double* H, const double* a, const double* b, const double* g1,
+                      const double* g2, double* out, double* r_out, double* out2, hipStream_t st);
 // out = jump (or (B B^T)^{-1}-weighted jump) of yb; with g, also g = G^T out
 void launch_jump(const DevMesh& m, const double* yb, int from_torn, double* out, int scaled,
                  double* g, const int32_t* skip, hipStream_t st);

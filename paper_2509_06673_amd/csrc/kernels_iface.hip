@@ -533,12 +533,50 @@ __global__ void k_copy_scalar(double* __restrict__ sc, int src, int dst) {
 }
 
 __global__ void k_pick_start(int64_t n, const double* __restrict__ sc, const double* __restrict__ alt,
-                             double* __restrict__ lam, int32_t* __restrict__ flag) {
+                             double* __restrict__ lam, int32_t* __restrict__ flag, const double* __restrict__ alt2,
+                             double* __restrict__ dst2, const double* __restrict__ alt3, double* __restrict__ dst3) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool take = sc[SC_SEL1] < sc[SC_SEL0];
   if (j == 0 && flag) *flag = take ? 1 : 0;
   if (j >= n || !take) return;
   lam[j] = alt[j];
+  if (alt2) dst2[j] = alt2[j];
+  if (alt3) dst3[j] = alt3[j];
+}
+
+// 64 rows per block; the four wavefronts split the coarse index, wavefront 0 finishes
+__global__ void __launch_bounds__(256) k_h_project(int64_t n, int nc, const double* __restrict__ H,
+                                                   const double* __restrict__ a, const double* __restrict__ b,
+                                                   const double* __restrict__ g1, const double* __restrict__ g2,
+                                                   double* __restrict__ out, double* __restrict__ r_out,
+                                                   double* __restrict__ out2) {
+  __shared__ double gl[HPROJ_NC_MAX];
+  __shared__ double red[4][64];
+  for (int k = threadIdx.x; k < nc; k += blockDim.x) gl[k] = g1[k] - (g2 ? g2[k] : 0.0);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  const int cq = (nc + 3) / 4, cb = wave * cq, ce = min(nc, cb + cq);
+  double acc = 0.0;
+  if (j < n)
+    for (int c = cb; c < ce; c += 16) {
+      double h[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) h[u] = H[(int64_t)min(c + u, ce - 1) * n + j];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (c + u < ce) acc += h[u] * gl[c + u];
+    }
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && j < n) {
+    const double corr = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    const double v = a[j] - (b ? b[j] : 0.0);
+    if (r_out) r_out[j] = v;
+    const double o = v - corr;
+    out[j] = o;
+    if (out2) out2[j] = o;
+  }
 }
 
 // ---- launchers ---------------------------------------------------------------
@@ -547,8 +585,16 @@ void launch_copy_scalar(double* sc, int src, int dst, hipStream_t st) {
   hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(64), 0, st, sc, src, dst);
 }
 
-void launch_pick_start(int64_t n, const double* sc, const double* alt, double* lam, int32_t* flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_pick_start, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, sc, alt, lam, flag);
+void launch_pick_start(int64_t n, const double* sc, const double* alt, double* lam, int32_t* flag, hipStream_t st,
+                       const double* alt2, double* dst2, const double* alt3, double* dst3) {
+  hipLaunchKernelGGL(k_pick_start, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, sc, alt, lam, flag, alt2,
+                     dst2, alt3, dst3);
+}
+
+void launch_h_project(int64_t n, int nc, const double* H, const double* a, const double* b, const double* g1,
+                      const double* g2, double* out, double* r_out, double* out2, hipStream_t st) {
+  hipLaunchKernelGGL(k_h_project, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, n, nc, H, a, b, g1, g2, out,
+                     r_out, out2);
 }
 
 void launch_init_scalars(double* sc, int32_t* ist, double tol, double utol, int maxit, hipStream_t st) {
