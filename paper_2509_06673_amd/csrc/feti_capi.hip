@@ -481,13 +481,16 @@ int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
   if (took_cand) *took_cand = 0;
   if (ctx->H && !took_cand) {
     static_assert(HPROJ_NC_MAX >= PCG_NC_LOCAL, "H exists for every coarse size the projection kernel takes");
-    // with H: a projection is one pass (P v = v - H G^T v), G^T of d and of F lam come
-    // with their own passes, r = d - F lam and w = P r are formed together, and a
-    // compared candidate keeps its r and w
+    // with H: a projection is one pass after G^T v (P v = v - H G^T v), and a compared
+    // candidate keeps its r and w.  G^T r is summed from r itself: at a warm start r is
+    // tiny, and G^T d - G^T F lam would cancel down to the rounding of G^T d, leaving w
+    // a part outside the range of P that no iteration removes.
     launch_coarse_g(m, ctx->d, nullptr, 1.0, ctx->gd, nullptr, st);
     auto start_rw = [&](const double* v, double* r, double* w) {
-      op_F_raw(ctx, v, ctx->q, ctx->gq, nullptr);
-      launch_h_project(nl, ctx->nc, ctx->H, ctx->d, ctx->q, ctx->gd, ctx->gq, w, r, nullptr, st);
+      op_F(ctx, v, ctx->q, nullptr);
+      launch_axpby(nl, 1.0, ctx->d, -1.0, ctx->q, r, st);
+      launch_coarse_g(m, r, nullptr, 1.0, ctx->gq, nullptr, st);
+      launch_h_project(nl, ctx->nc, ctx->H, r, nullptr, ctx->gq, nullptr, w, nullptr, nullptr, st);
     };
     start_rw(lam, ctx->r, ctx->w);
     if (cand) {

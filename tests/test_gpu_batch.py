@@ -98,3 +98,31 @@ def test_in_place_factors_refuse_export_and_refactor():
     with pytest.raises(B.FetiError):
         f.factor_subdomains(B.FP64, B.PRECOND_DIRICHLET)
     f.close()
+
+
+def test_warm_step_of_a_draw_with_a_large_coarse_load_converges():
+    """Draw 246 of the batch set converges at its warm steps.  Its interface load is
+    dominated by the coarse (rigid-mode) part, so the projected start residual must take
+    G^T r from r itself: formed as G^T d - G^T F lambda it cancels down to the rounding of
+    G^T d, and the first solve of step 2 then cannot reach its tolerance."""
+    import torch
+    require_gpu()
+    w = W.batched_draws()[246]
+    nsteps = 3
+    print(f"[draw 246] {w.name}", flush=True)
+    f = setup(w)
+    o = opts(tol=1e-10, max_it=3000)
+    for n in range(1, nsteps + 1):
+        st = f.step(load(w, n * w.tau), o)
+        print(f"  step {n}: first {st['iters_first']} corrections {st['iters_corr'][:st['ir_steps']]}", flush=True)
+        assert st["status"] == 0 and st["iters_first"] < 3000, st
+    idx = f.export_indexing()
+    codes = idx["code"].astype(np.int64)
+    u = torch.empty(len(codes), dtype=torch.float64, device="cuda")
+    f.get_solution(u)
+    _, lats = oracle_reference(w, nsteps)
+    ref = torn_reference(codes, idx["sub_offset"], sub_poro_flags(w), lats[-1])
+    err = per_kind_rel_error(codes, u.cpu().numpy(), ref)
+    print(f"  vs oracle {max(err.values()):.1e}", flush=True)
+    assert max(err.values()) < FP64_TOL, err
+    f.close()
