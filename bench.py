@@ -37,8 +37,8 @@ MEASURED_TRAFFIC = {"sources": ["paper_2509_06673_amd/csrc/kernels_pcg.hip",
                                 "paper_2509_06673_amd/csrc/pcg_device.h",
                                 "paper_2509_06673_amd/csrc/pcg.h",
                                 "paper_2509_06673_amd/csrc/iface_device.h"],
-                    "sha256_16": "d0483ffe60873f43",
-                    "bytes_per_iteration": (39924678.0 * 1.99982 + 567758.4) * 1024 / 533}
+                    "sha256_16": "0b1ccdd940df7c35",
+                    "bytes_per_iteration": (41580817.6 * 1.99982 + 590937.8) * 1024 / 555}
 
 
 def source_hash(paths):

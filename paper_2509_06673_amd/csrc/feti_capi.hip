@@ -754,7 +754,10 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
   hipStream_t st = ctx->stream;
   const double tol_first =
       (ctx->precision == FETI_FP32_IR && o->tol_inner > 0.0) ? std::max(o->tol, o->tol_inner) : o->tol;
-  int nrec = 0, nfin = 0, rc = FETI_OK, iters = 0, iters_first = 0, done_ir = 0;
+  // status of the step: that of the last solve (a first solve that ran out of iterations
+  // is repaired by the corrections), but a breakdown, a non-finite value or a barrier
+  // timeout in any solve is kept
+  int nrec = 0, nfin = 0, rc = FETI_OK, hard = FETI_OK, last = FETI_OK, iters = 0, iters_first = 0, done_ir = 0;
   double res0 = 0, res = 0, r0c = 0, rc_ = 0, corr = 0.0;
   int it_corr[feti_ctx_s::NREC] = {0};
   RC(solve_torn(ctx, o, tol_first, 0.0, ctx->f, nullptr, ctx->lam, ctx->u, nrec++, cand, took_cand));
@@ -767,8 +770,10 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
       if (nfin == 0) iters_first = its;
       else it_corr[nfin - 1] = its;
       iters += its;
-      if (s != FETI_OK && (rc == FETI_OK || rc == FETI_ENOTCONV)) rc = s;
+      last = s;
+      if (s != FETI_OK && s != FETI_ENOTCONV && hard == FETI_OK) hard = s;
     }
+    rc = hard != FETI_OK ? hard : last;
   };
   auto correction_size = [&]() {
     double mx[12] = {0};
@@ -807,7 +812,7 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
       // a later correction runs only if this one still changed the fields
       HIPCHK(hipStreamSynchronize(st));
       finish();
-      if (!(rc == FETI_OK || rc == FETI_ENOTCONV)) break;
+      if (hard != FETI_OK) break;
       corr = correction_size();
       if (corr <= o->ir_tol) break;
     }
