@@ -204,6 +204,9 @@ def learned_start_run(args):
                        "learned_start_kept": r["used_learned"]} for m, r in res.items()},
         "training": {"data_s": t_data, "train_s": hist["seconds"], "adam_steps": hist["steps"],
                      "loss_first_epoch": hist["loss"][0], "loss_last_epoch": hist["loss"][-1]},
+        "start_error": {"prediction": lr_["mean_err_pred"], "previous_step": lr_["mean_err_prev"],
+                        "extrapolation": lr_["mean_err_extrap"],
+                        "note": "mean |start - solved multipliers| / |solved multipliers| on the held-out steps"},
     }
 
 

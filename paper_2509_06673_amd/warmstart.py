@@ -101,7 +101,8 @@ def evaluate(w, net, nsteps: int, mode: str, opts=None) -> Dict:
     lam_hist: List = []
     pred = torch.empty(nl, dtype=torch.float64, device="cuda")
     ld = torch.empty(nl, dtype=torch.float64, device="cuda")
-    rec = {"iters": [], "iters_first": [], "ms": [], "used_learned": 0}
+    rec = {"iters": [], "iters_first": [], "ms": [], "used_learned": 0, "err_pred": [], "err_prev": [],
+           "err_extrap": []}
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for n in range(1, nsteps + 1):
@@ -121,6 +122,12 @@ def evaluate(w, net, nsteps: int, mode: str, opts=None) -> Dict:
         torch.cuda.synchronize()
         lam = torch.empty(nl, dtype=torch.float64, device="cuda")
         f.get_solution(lam=lam)
+        if mode == "learned" and len(lam_hist) >= 2:
+            # distance of each start to the multipliers the step solved for
+            nrm = float(torch.linalg.norm(lam))
+            rec["err_pred"].append(float(torch.linalg.norm(pred - lam)) / nrm)
+            rec["err_prev"].append(float(torch.linalg.norm(lam_hist[-1] - lam)) / nrm)
+            rec["err_extrap"].append(float(torch.linalg.norm(2 * lam_hist[-1] - lam_hist[-2] - lam)) / nrm)
         lam_hist = (lam_hist + [lam])[-2:]
         if n >= 3:  # every mode has two previous steps from here on
             rec["iters"].append(st["iters"])
@@ -131,4 +138,6 @@ def evaluate(w, net, nsteps: int, mode: str, opts=None) -> Dict:
     rec["mean_iters"] = float(np.mean(rec["iters"]))
     rec["mean_iters_first"] = float(np.mean(rec["iters_first"]))
     rec["mean_ms"] = float(np.mean(rec["ms"]))
+    for k in ("err_pred", "err_prev", "err_extrap"):
+        rec["mean_" + k] = float(np.mean(rec[k])) if rec[k] else float("nan")
     return rec
