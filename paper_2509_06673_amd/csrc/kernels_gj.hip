@@ -137,7 +137,11 @@ __global__ void __launch_bounds__(256) k_gj_row(const int32_t* __restrict__ psta
   }
 }
 
-// (3) D -= C^T W on 64x64 tiles outside the panel rows and columns (MFMA)
+// (3) D -= C^T W outside the panel rows and columns (MFMA).  One workgroup per
+// 64-row strip of a matrix: the strip's panel block C[k][i0 + i] is staged in LDS
+// once, and the workgroup walks the 64-column tiles of the row, staging W[k][j0 + j]
+// and updating the 64x64 tile of A (four wavefronts, a 32x32 quarter each as 2x2
+// MFMA blocks).
 template <class T>
 __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ pstart,
                                                    const int32_t* __restrict__ pwidth,
@@ -147,15 +151,15 @@ __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ p
                                                    T* __restrict__ A,
                                                    const T* __restrict__ wrow, int nmat,
                                                    int step, int nb, int max_n) {
-  const int m = blockIdx.z;
+  const int m = blockIdx.y;
   const int kw = pwidth[step * nmat + m];
   if (kw == 0) return;
   const int n = nn[m];
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  if (i0 >= n || j0 >= n) return;
+  const int i0 = blockIdx.x * 64;
+  if (i0 >= n) return;
   const int k0 = pstart[step * nmat + m];
-  // tiles fully inside the panel rows or columns have nothing to update
-  if ((i0 >= k0 && i0 + 64 <= k0 + kw) || (j0 >= k0 && j0 + 64 <= k0 + kw)) return;
+  // strips fully inside the panel rows have nothing to update
+  if (i0 >= k0 && i0 + 64 <= k0 + kw) return;
   T* Am = A + aofs[m];
   const int ld = lda[m];
   const T* W = wrow + (int64_t)m * nb * max_n;
@@ -164,44 +168,66 @@ __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ p
   const int kp = (kw + 3) & ~3;     // padded to the MFMA depth
   for (int t = threadIdx.x; t < kp * 64; t += blockDim.x) {
     const int k = t / 64, x = t % 64;
-    const bool kin = k < kw;
-    const int i = i0 + x, j = j0 + x;
-    Ct[k][x] = (kin && i < n) ? Am[(int64_t)(k0 + k) * ld + i] : T(0);
-    Wt[k][x] = (kin && j < n && !(j >= k0 && j < k0 + kw)) ? W[(int64_t)k * max_n + j] : T(0);
+    const int i = i0 + x;
+    Ct[k][x] = (k < kw && i < n) ? Am[(int64_t)(k0 + k) * ld + i] : T(0);
   }
-  __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
-  typename Mfma<T>::acc4 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = typename Mfma<T>::acc4{T(0), T(0), T(0), T(0)};
   const int lr = lane % 16, lk = lane / 16;
-  for (int k = 0; k < kp; k += 4) {
-    T av[2], bv[2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) av[a] = Ct[k + lk][wi + a * 16 + lr];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) bv[b] = Wt[k + lk][wj + b * 16 + lr];
+  for (int j0 = 0; j0 < n; j0 += 64) {
+    // column tiles fully inside the panel columns have nothing to update
+    if (j0 >= k0 && j0 + 64 <= k0 + kw) continue;
+    __syncthreads();  // Ct staged, or the previous Wt consumed
+    for (int t = threadIdx.x; t < kp * 64; t += blockDim.x) {
+      const int k = t / 64, x = t % 64;
+      const int j = j0 + x;
+      Wt[k][x] = (k < kw && j < n && !(j >= k0 && j < k0 + kw)) ? W[(int64_t)k * max_n + j] : T(0);
+    }
+    __syncthreads();
+    // the lane's 16 entries of the A tile are loaded before the products, so that their
+    // latency overlaps the matrix-core work (entries outside the update read as 0)
+    T old[2][2][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
-        acc[a][b] = Mfma<T>::run(av[a], bv[b], acc[a][b]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + wi + a * 16 + Mfma<T>::row(lane, r);
+          const int j = j0 + wj + b * 16 + (lane % 16);
+          const bool upd = i < n && j < n && !(i >= k0 && i < k0 + kw) && !(j >= k0 && j < k0 + kw);
+          old[a][b][r] = upd ? Am[(int64_t)i * ld + j] : T(0);
+        }
+    typename Mfma<T>::acc4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = typename Mfma<T>::acc4{T(0), T(0), T(0), T(0)};
+    for (int k = 0; k < kp; k += 4) {
+      T av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = Ct[k + lk][wi + a * 16 + lr];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Wt[k + lk][wj + b * 16 + lr];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = Mfma<T>::run(av[a], bv[b], acc[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + wi + a * 16 + Mfma<T>::row(lane, r);
+          const int j = j0 + wj + b * 16 + (lane % 16);
+          if (i >= n || j >= n) continue;
+          if ((i >= k0 && i < k0 + kw) || (j >= k0 && j < k0 + kw)) continue;
+          Am[(int64_t)i * ld + j] = old[a][b][r] - acc[a][b][r];
+        }
   }
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wi + a * 16 + Mfma<T>::row(lane, r);
-        const int j = j0 + wj + b * 16 + (lane % 16);
-        if (i >= n || j >= n) continue;
-        if ((i >= k0 && i < k0 + kw) || (j >= k0 && j < k0 + kw)) continue;
-        Am[(int64_t)i * ld + j] -= acc[a][b][r];
-      }
 }
 
 // (4) write the swept panel: rows W, columns W^T, pivot block -P^{-1}; and
@@ -276,7 +302,7 @@ void launch_gj_step(const GJPlan& p, T* A, T* snap, int step, bool snap_now, hip
   hipLaunchKernelGGL(k_gj_row<T>, dim3((p.max_n + 255) / 256, p.nmat), dim3(256), 0, st, p.pstart,
                      p.pwidth, p.aofs, p.lda, p.n, A, p.pinv, wrow, p.nmat, step, p.nb, p.max_n);
   const int nt = (p.max_n + 63) / 64;
-  hipLaunchKernelGGL(k_gj_update<T>, dim3(nt, nt, p.nmat), dim3(256), 0, st, p.pstart, p.pwidth,
+  hipLaunchKernelGGL(k_gj_update<T>, dim3(nt, p.nmat), dim3(256), 0, st, p.pstart, p.pwidth,
                      p.aofs, p.lda, p.n, A, wrow, p.nmat, step, p.nb, p.max_n);
   hipLaunchKernelGGL(k_gj_write<T>, dim3((p.max_n + 255) / 256, p.nmat), dim3(256), 0, st, p.pstart,
                      p.pwidth, p.aofs, p.lda, p.n, A, p.pinv, wrow, p.nmat, step, p.nb, p.max_n);
