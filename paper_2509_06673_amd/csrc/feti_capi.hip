@@ -621,8 +621,8 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
       }
       HIPCHK(launch_pcg_persistent(pa, ctx->pgrid, st));
       if (ptrace) {
-        // stamps per iteration: 0 start, 1..3 after barriers A, B, D, 4 after the stopping
-        // test, 5..7 after barriers E..G (stamp 0 of a later iteration = stamp 7 before)
+        // stamps per iteration: 0 start, 1..6 after the barriers of phases A, B, D, E (with
+        // the stopping test), F, G (stamp 0 of a later iteration = stamp 6 before)
         std::vector<long long> h(nts * 10);
         HIPCHK(hipMemcpyAsync(h.data(), ts, h.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -630,20 +630,19 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
         int rate_khz = 0, dev = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
-        double sum[8] = {0}; int cnt = 0;
+        double sum[6] = {0}; int cnt = 0;
         for (int it = 0; it < nts; ++it) {
-          if (h[it * 10 + 7] == 0) break;
-          for (int k = 0; k < 7; ++k) {
-            const long long a0 = k > 0 ? h[it * 10 + k] : (it == 0 ? h[0] : h[(it - 1) * 10 + 7]);
+          if (h[it * 10 + 6] == 0) break;
+          for (int k = 0; k < 6; ++k) {
+            const long long a0 = k > 0 ? h[it * 10 + k] : (it == 0 ? h[0] : h[(it - 1) * 10 + 6]);
             sum[k] += (double)(h[it * 10 + k + 1] - a0);
           }
           ++cnt;
         }
         if (cnt > 0 && rate_khz > 0) {
           const double us = 1e3 / rate_khz / cnt;
-          std::fprintf(stderr, "[pcg] grid %d, %d iterations, us: A %.2f B %.2f D %.2f test %.2f E %.2f F %.2f G %.2f",
-                       ctx->pgrid, cnt, sum[0] * us, sum[1] * us, sum[2] * us, sum[3] * us, sum[4] * us, sum[5] * us,
-                       sum[6] * us);
+          std::fprintf(stderr, "[pcg] grid %d, %d iterations, us: A %.2f B %.2f D %.2f E+test %.2f F %.2f G %.2f",
+                       ctx->pgrid, cnt, sum[0] * us, sum[1] * us, sum[2] * us, sum[3] * us, sum[4] * us, sum[5] * us);
           std::fprintf(stderr, "\n");
         }
       }

@@ -179,16 +179,35 @@ __device__ void correct_dot_phase(const PcgArgs& a, const double* vin, double* v
   if (threadIdx.x == 0) ast(part + blockIdx.x * PCG_NPART, acc[0]);
 }
 
-// Phase D: q = q_raw - H g (H = G (G^T G)^{-1}, coarse-index major; 64-row chunks, the
-// wavefronts of the block split the coarse index), then lam += alpha p,
-// r -= alpha q_raw, w -= alpha q, p_old = p, and this block's partial sums: per-kind
-// |w|^2 (0..5), the dual energy (6) and, with the update test (NV = 19), per-kind
-// |p|^2 (7..12) and |lambda|^2 (13..18).
+// alpha = rho / (p, q_raw) from the block sum pq of the partials; false (with status
+// set) on a breakdown.  Every block sees the same sum, so all take the same branch.
+__device__ inline bool alpha_of(double pq, double rho, double& alpha, int& status) {
+  if (!(fabs(pq) > 1e-300) || !isfinite(pq)) {
+    status = isfinite(pq) ? FETI_EBREAKDOWN : FETI_ENAN;
+    alpha = 0.0;
+    return false;
+  }
+  alpha = rho / pq;
+  return true;
+}
+
+// Phase D: alpha = rho / (p, q_raw) from the partials apart of phase B, q = q_raw - H g
+// (H = G (G^T G)^{-1}, coarse-index major; 64-row chunks, the wavefronts of the block
+// split the coarse index), then lam += alpha p, r -= alpha q_raw, w -= alpha q,
+// p_old = p, and this block's partial sums: per-kind |w|^2 (0..5), the dual energy (6)
+// and, with the update test (NV = 19), per-kind |p|^2 (7..12) and |lambda|^2 (13..18).
+// The partials of (p, q_raw) are loaded with g and summed after the projection sums
+// of the first chunk, so that their latency overlaps the H loads.  Returns false on a
+// breakdown of alpha (before any update).
 template <int NV>
-__device__ inline void update_phase(const PcgArgs& a, double alpha, double beta, double* part, double* acl,
-                                    double* red4, double* red) {
+__device__ inline bool update_phase(const PcgArgs& a, const double* apart, int nblk, double rho, double& alpha,
+                                    int& status, double beta, double* part, double* acl, double* red4,
+                                    double* red) {
   const DevMesh& m = a.m;
   const int64_t NL = m.n_lambda;
+  double pq[1] = {0.0};
+  for (int b = threadIdx.x; b < nblk; b += PB) pq[0] += ald(apart + b * PCG_NPART);
+  bool have_alpha = false;
   double acc[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) acc[c] = 0.0;
@@ -204,6 +223,11 @@ __device__ inline void update_phase(const PcgArgs& a, double alpha, double beta,
       double c0 = 0.0, c1 = 0.0;
       if (j < NL) h_rows(a.H, NL, j, cb, ce, gl, c0, c1);
       red4[wave * 64 + lane] = c0 + c1;
+      if (!have_alpha) {
+        block_sum<1>(pq, red);  // its barriers also publish red4
+        have_alpha = true;
+        if (!alpha_of(pq[0], rho, alpha, status)) return false;
+      }
       __syncthreads();
       if (wave == 0 && j < NL) {
         double corr = 0.0;
@@ -233,6 +257,10 @@ __device__ inline void update_phase(const PcgArgs& a, double alpha, double beta,
       __syncthreads();
     }
   }
+  if (!have_alpha) {
+    block_sum<1>(pq, red);
+    if (!alpha_of(pq[0], rho, alpha, status)) return false;
+  }
   // only wavefront 0 holds row sums: a shuffle reduction there, lane 0 stores
   if (threadIdx.x < 64) {
 #pragma unroll
@@ -245,6 +273,7 @@ __device__ inline void update_phase(const PcgArgs& a, double alpha, double beta,
 #pragma unroll
       for (int c = 0; c < NV; ++c) ast(part + blockIdx.x * PCG_NPART + c, acc[c]);
   }
+  return true;
 }
 
 static_assert(PCG_MAX_GRID * 19 <= GT_LOADS * PB, "the stopping test stages every partial sum once");
@@ -254,6 +283,7 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
   __shared__ int s_ok, s_upd;
   __shared__ double s_res;
   __shared__ double s_ring[UPD_WIN * 6];
+  __shared__ double s_kc[14];  // references of the stopping test (see stop_test_wave0)
   const DevMesh& m = a.m;
   double* xs = lds;                          // 2 x max_nb gathered vectors (one per tile)
   double* red4 = xs + 2 * m.max_nb;          // PB partial rows
@@ -261,7 +291,6 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
   double* red = acl + 2 * PCG_NC_LOCAL;
   double* stage = red + (PB / 64) * PCG_NPART;  // nblk x 19 staged partial sums
   const int nblk = gridDim.x;
-  const int64_t NL = m.n_lambda;
   uint32_t gen = 0;  // the host clears the barrier before the launch
 
   const double tol = a.sc[SC_TOL];
@@ -277,6 +306,16 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
   auto partbuf = [&](int k) { return a.part + (size_t)(k & 1) * nblk * PCG_NPART; };
   __shared__ double conv[19];  // totals of the last stopping test
   if (threadIdx.x < 19) conv[threadIdx.x] = 0.0;
+  if (threadIdx.x < 6) {
+    s_kc[threadIdx.x] = a.sc[SC_REF + threadIdx.x];
+    s_kc[6 + threadIdx.x] = a.sc[SC_EK + threadIdx.x];
+  }
+  if (threadIdx.x == 0) {
+    s_kc[12] = a.sc[SC_EREF];
+    double eref = 0.0;
+    for (int k = 0; k < 6; ++k) eref += a.sc[SC_EK + k];
+    s_kc[13] = eref;
+  }
   __syncthreads();
   int it_local = 0, ph = 0;
   auto stamp = [&]() {
@@ -285,7 +324,7 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
     ++ph;
   };
   stamp();
-  for (; !start_done; ++it_local, ph = 1) {  // stamp 0 of a later iteration is stamp 7 of the one before
+  for (; !start_done; ++it_local, ph = 1) {  // stamp 0 of a later iteration is stamp 6 of the one before
     // (A) y_b = (K^+)_bb B^T p,  p = y + beta p_old
     if (a.fm32) gemv_phase<float, 0>(a, (const float*)a.fm, a.y, a.p, beta, a.yb, xs, red4);
     else gemv_phase<double, 0>(a, (const double*)a.fm, a.y, a.p, beta, a.yb, xs, red4);
@@ -295,31 +334,30 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
     jump_phase(a, a.yb, a.qraw, 0, red, a.y, a.p, beta, partbuf(rk));
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
     stamp();
+    // (D) alpha, q = P q_raw, updates and the norms of w (and of p and lambda for the
+    // update test)
     {
-      double t[1];
-      grid_total<1>(partbuf(rk++), nblk, t, red);
-      const double pq = t[0];
-      if (!(fabs(pq) > 1e-300) || !isfinite(pq)) {
-        status = isfinite(pq) ? FETI_EBREAKDOWN : FETI_ENAN;
-        alpha = 0.0;
-        break;
-      }
-      alpha = rho / pq;
+      const double* apart = partbuf(rk++);
+      const bool good = upd ? update_phase<19>(a, apart, nblk, rho, alpha, status, beta, partbuf(rk), acl, red4, red)
+                            : update_phase<7>(a, apart, nblk, rho, alpha, status, beta, partbuf(rk), acl, red4, red);
+      if (!good) break;
     }
-    // (D) q = P q_raw, updates and the norms of w (and of p and lambda for the update test)
-    if (upd) update_phase<19>(a, alpha, beta, partbuf(rk), acl, red4, red);
-    else update_phase<7>(a, alpha, beta, partbuf(rk), acl, red4, red);
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
     stamp();
+    // (E) z_b = S_bb (B^T D w), then the stopping test.  Its partial sums are loaded
+    // before the products, which do not depend on its outcome, so that their latency
+    // overlaps the gather; the products of the last iteration are not used.
     {
-      // thread 0 forms the totals and the decisions; the block reads them from LDS
-      if (upd) grid_total_t0<19>(partbuf(rk++), nblk, conv, stage, red);
-      else grid_total_t0<7>(partbuf(rk++), nblk, conv, stage, red);
-      if (threadIdx.x == 0) {
-        s_res = rel_residual_of(conv, conv[6], a.sc);
-        // counted within this launch, so that the ring holds only this launch's updates
-        s_upd = upd ? update_converged(s_ring, it_local + 1, alpha, conv + 7, conv + 13, utol) : 0;
-      }
+      double tl[GT_LOADS];
+      if (upd) gt_issue<19>(partbuf(rk), nblk, tl);
+      else gt_issue<7>(partbuf(rk), nblk, tl);
+      if (a.mm32) gemv_phase<float, 1>(a, (const float*)a.mm, a.w, nullptr, 0.0, a.zb, xs, red4);
+      else gemv_phase<double, 1>(a, (const double*)a.mm, a.w, nullptr, 0.0, a.zb, xs, red4);
+      if (upd) gt_finish<19>(tl, nblk, conv, stage);
+      else gt_finish<7>(tl, nblk, conv, stage);
+      ++rk;
+      // counted within this launch, so that the ring holds only this launch's updates
+      if (threadIdx.x < 64) stop_test_wave0(conv, s_kc, s_ring, it_local + 1, alpha, utol, upd, &s_res, &s_upd);
       __syncthreads();
       res = s_res;
       iters += 1;
@@ -327,10 +365,6 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
       if (res <= tol || s_upd) break;
       if (iters >= maxit) { status = FETI_ENOTCONV; break; }
     }
-    stamp();
-    // (E) z_b = S_bb (B^T D w)
-    if (a.mm32) gemv_phase<float, 1>(a, (const float*)a.mm, a.w, nullptr, 0.0, a.zb, xs, red4);
-    else gemv_phase<double, 1>(a, (const double*)a.mm, a.w, nullptr, 0.0, a.zb, xs, red4);
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
     stamp();
     // (F) z = D B z_b, g = G^T z

@@ -46,7 +46,7 @@ struct PcgArgs {
   const int32_t* tile_row0 = nullptr;
   int ntile = 0;
   long long* tstamp = nullptr;  // optional: block 0 records the wall clock after each barrier
-  int tstamp_iters = 0;         // iterations recorded (8 stamps each)
+  int tstamp_iters = 0;         // iterations recorded (7 stamps each, 10 slots apart)
 };
 
 // One problem of a batch (device array): its mesh tables, operators and vectors.

@@ -148,19 +148,24 @@ __device__ inline void grid_total(const double* part, int nblk, double (&v)[NV],
 }
 
 // Sum of the per-block partials part[b][0..NV) over all blocks, in block order, into
-// v[0..NV) (LDS, valid after the call in every thread).  The nblk x NV coherent loads
-// are spread over the threads (at most GT_LOADS each, issued together) and staged in
-// LDS (stage: nblk x NV doubles); thread c then adds value c over the blocks.
+// v[0..NV) (LDS), in two parts so that the loads overlap other work: gt_issue spreads
+// the nblk x NV device-coherent loads over the threads (at most GT_LOADS each, issued
+// together) into registers; gt_finish stages them in LDS (stage: nblk x NV doubles)
+// and thread c adds value c over the blocks.  v is valid in every thread after
+// gt_finish.
 constexpr int GT_LOADS = 10;
 template <int NV>
-__device__ inline void grid_total_t0(const double* part, int nblk, double* v, double* stage, double* red) {
+__device__ inline void gt_issue(const double* part, int nblk, double (&t)[GT_LOADS]) {
   const int total = nblk * NV;  // <= GT_LOADS * PB (checked on the host)
-  double t[GT_LOADS];
 #pragma unroll
   for (int k = 0; k < GT_LOADS; ++k) {
     const int idx = threadIdx.x + k * PB;
     t[k] = idx < total ? ald(part + (idx / NV) * PCG_NPART + idx % NV) : 0.0;
   }
+}
+template <int NV>
+__device__ inline void gt_finish(const double (&t)[GT_LOADS], int nblk, double* v, double* stage) {
+  const int total = nblk * NV;
 #pragma unroll
   for (int k = 0; k < GT_LOADS; ++k) {
     const int idx = threadIdx.x + k * PB;
@@ -168,11 +173,63 @@ __device__ inline void grid_total_t0(const double* part, int nblk, double* v, do
   }
   __syncthreads();
   if (threadIdx.x < NV) {
+    // in block order; the LDS reads of 16 blocks are issued before their additions
     double x = 0.0;
-    for (int b = 0; b < nblk; ++b) x += stage[b * NV + threadIdx.x];
+    int b = 0;
+    for (; b + 16 <= nblk; b += 16) {
+      double u[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) u[k] = stage[(b + k) * NV + threadIdx.x];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x += u[k];
+    }
+    for (; b < nblk; ++b) x += stage[b * NV + threadIdx.x];
     v[threadIdx.x] = x;
   }
   __syncthreads();  // v complete; stage free again
+}
+
+// The stopping decisions of an iteration from the totals conv (LDS; per-kind |w_k|^2
+// in 0..5, |w|_M^2 in 6, per-kind |p|^2 in 7..12 and |lambda|^2 in 13..18), evaluated
+// by wavefront 0 with kind k in lane k: the relative residual of rel_residual_of and,
+// with upd, the update test of update_converged (the same operations on the same
+// values, so the same results).  kc (LDS): the references sc[SC_REF..+6) in 0..5,
+// sc[SC_EK..+6) in 6..11, sc[SC_EREF] in 12 and the sum of the six reference
+// energies in 13.  Lane 0 stores the residual in *res and the update-test result in
+// *upd_ok.
+__device__ inline void stop_test_wave0(const double* conv, const double* kc, double* ring, int iters,
+                                       double alpha, double utol, bool upd, double* res, int* upd_ok) {
+  const int lane = threadIdx.x & 63;
+  const bool kl = lane < 6;
+  const int k = kl ? lane : 0;
+  const double nan = __builtin_nan("");
+  // residual: the largest of the energy ratio and the ratios of the included kinds
+  // (fmax ignores NaN operands, so NaN stands for an excluded kind)
+  const double rk = kc[k] > 0.0 ? sqrt(conv[k]) / kc[k] : 0.0;
+  double rel = kl && kc[6 + k] > 1e-24 * kc[13] ? rk : nan;
+  if (lane == 0) {
+    const double den = kc[12], et = conv[6];
+    rel = fmax(den > 0.0 ? sqrt(et) / den : (et > 0.0 ? 1.0 : 0.0), rel);
+  }
+  for (int off = 4; off > 0; off >>= 1) rel = fmax(rel, __shfl_xor(rel, off, 64));
+  // update test
+  bool ok = true, has = false;
+  if (upd && kl) {
+    double* slot = ring + (iters % UPD_WIN) * 6;
+    slot[k] = fabs(alpha) * sqrt(conv[7 + k]);
+    const double l2 = conv[13 + k];
+    has = l2 > 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < UPD_WIN; ++i) s += ring[i * 6 + k];
+    ok = !has || s <= utol * sqrt(l2);
+  }
+  const bool all_ok = __ballot(!ok) == 0ull;
+  const bool any_has = __ballot(has) != 0ull;
+  if (lane == 0) {
+    *res = rel;
+    *upd_ok = upd && utol > 0.0 && iters >= UPD_WIN && all_ok && any_has;
+  }
 }
 
 // One 64-row tile of y_b = A_s x_b (interface block of subdomain s) by one half of
