@@ -244,33 +244,60 @@ __device__ inline void gemv_tile(const DevMesh& m, const MT* A, int s, int row0,
   const int nbs = valid ? m.nb[s] : 0;
   const int64_t b0 = valid ? m.boff[s] : 0;
   __syncthreads();  // xs and red4 of the previous tiles are consumed
-  for (int i = ht; i < nbs; i += 256) {
-    const int64_t gb = b0 + i;
-    double v = 0.0;
-    // branch-free: an absent entry reads row 0 with weight 0, so that all loads
-    // of the gather are in flight together
+  // two entries per thread and pass, their loads issued together; branch-free: an
+  // absent entry (or one past nbs) reads row 0 with weight 0
+  for (int i0 = ht; i0 < nbs; i0 += 512) {
+    double v[2] = {0.0, 0.0};
     if (SCALED) {
-      int r[3];
-      double wt[3], x[3];
+      int r[2][3];
+      double wt[2][3], x[2][3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int rk = m.bd_row[3 * gb + k];
-        r[k] = rk >= 0 ? rk : 0;
-        wt[k] = rk >= 0 ? m.bd_wt[3 * gb + k] : 0.0;
+      for (int h = 0; h < 2; ++h) {
+        const bool in = i0 + 256 * h < nbs;
+        const int64_t gb = b0 + (in ? i0 + 256 * h : 0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int rk = in ? m.bd_row[3 * gb + k] : -1;
+          r[h][k] = rk >= 0 ? rk : 0;
+          wt[h][k] = rk >= 0 ? m.bd_wt[3 * gb + k] : 0.0;
+        }
       }
 #pragma unroll
-      for (int k = 0; k < 3; ++k) x[k] = ald(src + r[k]);
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) v += wt[k] * x[k];
+        for (int k = 0; k < 3; ++k) x[h][k] = ald(src + r[h][k]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[h] += wt[h][k] * x[h][k];
     } else {
-      const int q0 = m.bg_row[2 * gb], q1 = m.bg_row[2 * gb + 1];
-      const int r0 = q0 >= 0 ? q0 : 0, r1 = q1 >= 0 ? q1 : 0;
-      const double s0 = q0 >= 0 ? m.bg_sign[2 * gb] : 0.0, s1 = q1 >= 0 ? m.bg_sign[2 * gb + 1] : 0.0;
-      const double y0 = ald(src + r0), p0 = ald(src2 + r0), y1 = ald(src + r1), p1 = ald(src2 + r1);
-      v = s0 * (y0 + beta * p0);
-      v += s1 * (y1 + beta * p1);
+      int r0[2], r1[2];
+      double s0[2], s1[2], y0[2], p0[2], y1[2], p1[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool in = i0 + 256 * h < nbs;
+        const int64_t gb = b0 + (in ? i0 + 256 * h : 0);
+        const int q0 = in ? m.bg_row[2 * gb] : -1, q1 = in ? m.bg_row[2 * gb + 1] : -1;
+        r0[h] = q0 >= 0 ? q0 : 0;
+        r1[h] = q1 >= 0 ? q1 : 0;
+        s0[h] = q0 >= 0 ? m.bg_sign[2 * gb] : 0.0;
+        s1[h] = q1 >= 0 ? m.bg_sign[2 * gb + 1] : 0.0;
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        y0[h] = ald(src + r0[h]);
+        p0[h] = ald(src2 + r0[h]);
+        y1[h] = ald(src + r1[h]);
+        p1[h] = ald(src2 + r1[h]);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        v[h] = s0[h] * (y0[h] + beta * p0[h]);
+        v[h] += s1[h] * (y1[h] + beta * p1[h]);
+      }
     }
-    xs[i] = v;
+    xs[i0] = v[0];
+    if (i0 + 256 < nbs) xs[i0 + 256] = v[1];
   }
   __syncthreads();
   const int i = row0 + lane;
@@ -297,7 +324,15 @@ __device__ inline void gemv_tile(const DevMesh& m, const MT* A, int s, int row0,
         acc3 += (double)v[u + 3] * xs[k + u + 3];
       }
     }
-    for (; k < ke; ++k, col += ld) acc0 += (double)col[0] * xs[k];
+    if (k < ke) {
+      // the last (ke - k < GEMV_BATCH) columns: loads together, products in order
+      MT v[GEMV_BATCH];
+#pragma unroll
+      for (int u = 0; u < GEMV_BATCH; ++u) v[u] = k + u < ke ? col[(int64_t)u * ld] : (MT)0;
+#pragma unroll
+      for (int u = 0; u < GEMV_BATCH; ++u)
+        if (k + u < ke) acc0 += (double)v[u] * xs[k + u];
+    }
   }
   red4[wave * 64 + lane] = (acc0 + acc1) + (acc2 + acc3);
   __syncthreads();
