@@ -133,17 +133,21 @@ __device__ void correct_dot_phase(const PcgArgs& a, const double* vin, double* v
       const int cq = (a.nc + NW - 1) / NW, cb = wave * cq, ce = min(a.nc, cb + cq);
       for (int64_t j0 = (int64_t)blockIdx.x * 64; j0 < NL; j0 += (int64_t)gridDim.x * 64) {
         const int64_t j = j0 + lane;
+        // wavefront 0's row operands first: their loads overlap those of the sums
+        const bool row = wave == 0 && j < NL;
+        const double vin_j = row ? ald(vin + j) : 0.0;
+        const double x1_j = row ? ald(x1 + j) : 0.0, x2_j = row && x2 ? ald(x2 + j) : 0.0;
         double c0 = 0.0, c1 = 0.0;
         if (j < NL) h_rows(a.H, NL, j, cb, ce, gl, c0, c1);
         red4[wave * 64 + lane] = c0 + c1;
         __syncthreads();
-        if (wave == 0 && j < NL) {
+        if (row) {
           double corr = 0.0;
 #pragma unroll
           for (int w = 0; w < NW; ++w) corr += red4[w * 64 + lane];
-          const double vj = ald(vin + j) - corr;
+          const double vj = vin_j - corr;
           ast(vout + j, vj);
-          const double xj = x2 ? ald(x1 + j) + xbeta * ald(x2 + j) : ald(x1 + j);
+          const double xj = x2 ? x1_j + xbeta * x2_j : x1_j;
           acc[0] += xj * vj;
         }
         __syncthreads();
@@ -220,6 +224,12 @@ __device__ inline bool update_phase(const PcgArgs& a, const double* apart, int n
     const int cq = (a.nc + NW - 1) / NW, cb = wave * cq, ce = min(a.nc, cb + cq);
     for (int64_t j0 = (int64_t)blockIdx.x * 64; j0 < NL; j0 += (int64_t)gridDim.x * 64) {
       const int64_t j = j0 + lane;
+      // wavefront 0's update operands first: their loads overlap those of the sums
+      const bool row = wave == 0 && j < NL;
+      const double qr = row ? ald(a.qraw + j) : 0.0, yj = row ? ald(a.y + j) : 0.0;
+      const double pold = row ? ald(a.p + j) : 0.0, wj = row ? ald(a.w + j) : 0.0;
+      const double lam_j = row ? a.lam[j] : 0.0, r_j = row ? a.r[j] : 0.0, md = row ? a.mdiag[j] : 0.0;
+      const int kind = row ? m.row_kind[j] : 0;
       double c0 = 0.0, c1 = 0.0;
       if (j < NL) h_rows(a.H, NL, j, cb, ce, gl, c0, c1);
       red4[wave * 64 + lane] = c0 + c1;
@@ -229,23 +239,22 @@ __device__ inline bool update_phase(const PcgArgs& a, const double* apart, int n
         if (!alpha_of(pq[0], rho, alpha, status)) return false;
       }
       __syncthreads();
-      if (wave == 0 && j < NL) {
+      if (row) {
         double corr = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) corr += red4[w * 64 + lane];
-        const double qr = ald(a.qraw + j);
-        const double pj = ald(a.y + j) + beta * ald(a.p + j);
-        const double lj = a.lam[j] + alpha * pj;
+        const double pj = yj + beta * pold;
+        const double lj = lam_j + alpha * pj;
         a.lam[j] = lj;
-        a.r[j] -= alpha * qr;
-        const double wn = ald(a.w + j) - alpha * (qr - corr);
+        a.r[j] = r_j - alpha * qr;
+        const double wn = wj - alpha * (qr - corr);
         ast(a.w + j, wn);
         ast(a.p + j, pj);
         const double v2 = wn * wn;
-        const int k = m.row_kind[j];
+        const int k = kind;
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c] += (c == k) ? v2 : 0.0;
-        acc[6] += fabs(a.mdiag[j]) * v2;
+        acc[6] += fabs(md) * v2;
         if (NV > 7) {
 #pragma unroll
           for (int c = 0; c < 6; ++c) {

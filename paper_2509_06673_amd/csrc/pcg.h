@@ -10,7 +10,10 @@ namespace feti {
 // Grid barrier state (device memory, zero-initialised).  gen counts completed
 // barriers; abort is raised by a block whose wait exceeds the spin limit, and
 // every block then leaves the launch at its next barrier.
-constexpr int PCG_BAR_GROUP = 96;    // blocks per first-level arrival counter (two groups at grid 192)
+#ifndef FETI_BAR_GROUP
+#define FETI_BAR_GROUP 192
+#endif
+constexpr int PCG_BAR_GROUP = FETI_BAR_GROUP;  // blocks per first-level arrival counter
 constexpr int PCG_BAR_STRIDE = 64;   // uint32 words between counters (own 256-byte line)
 constexpr int PCG_BAR_MAXGRP = 64;
 struct GridBarrier {

@@ -51,8 +51,12 @@ __device__ inline bool grid_sync(GridBarrier* b, uint32_t nblk, uint32_t& gen, i
     const uint32_t p1 =
         __hip_atomic_fetch_add(&b->grp[grp * PCG_BAR_STRIDE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (p1 == (gen + 1) * gsize - 1) {
-      const uint32_t p2 = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      last = p2 == (gen + 1) * ngrp - 1;
+      if (ngrp == 1) {
+        last = true;  // one group: its last block publishes at once
+      } else {
+        const uint32_t p2 = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = p2 == (gen + 1) * ngrp - 1;
+      }
     }
     if (last) {
       __hip_atomic_store(&b->gen, gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
