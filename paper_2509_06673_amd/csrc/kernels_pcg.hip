@@ -52,8 +52,8 @@ __device__ inline void h_rows(const double* __restrict__ H, int64_t NL, int64_t 
 // Phases A and E: every 64-row tile of every interface block, two tiles per block
 // at a time (one per half).
 template <class MT, int SCALED>
-__device__ void gemv_phase(const PcgArgs& a, const MT* A, const double* src, const double* src2,
-                           double beta, double* yout, double* xs2, double* red8) {
+__device__ __forceinline__ void gemv_phase(const PcgArgs& a, const MT* A, const double* src, const double* src2,
+                                           double beta, double* yout, double* xs2, double* red8) {
   const DevMesh& m = a.m;
   const int half = threadIdx.x / 256, ht = threadIdx.x % 256;
   for (int t2 = blockIdx.x; 2 * t2 < a.ntile; t2 += gridDim.x) {
@@ -62,6 +62,78 @@ __device__ void gemv_phase(const PcgArgs& a, const MT* A, const double* src, con
     gemv_tile<MT, SCALED>(m, A, valid ? a.tile_sub[t] : 0, valid ? a.tile_row0[t] : 0, valid, src, src2, beta,
                           yout, xs2 + half * m.max_nb, red8 + half * 256, ht);
   }
+}
+
+// Phase A when beta is still to be formed from the partials bpart of phase G (each
+// thread loads the partials of blocks threadIdx.x + k PB, then a block sum): the partial loads are issued with those of the first
+// gather pass (y and p_old at the entries' rows), the block sum follows, and then
+// p = y + beta p_old is formed and the products run as in gemv_phase.  Returns the sum
+// (the caller forms beta = sum / rho).
+template <class MT>
+__device__ __forceinline__ double gemv_phase_a(const PcgArgs& a, const MT* A, const double* bpart, int nblk,
+                                               double rho, double& beta, double* yout, double* xs2, double* red8,
+                                               double* red) {
+  const DevMesh& m = a.m;
+  const int half = threadIdx.x / 256, ht = threadIdx.x % 256;
+  const int wave = ht >> 6, lane = ht & 63;
+  double bs[1] = {0.0};
+  for (int b = threadIdx.x; b < nblk; b += PB) bs[0] += ald(bpart + b * PCG_NPART);
+  bool have = false;
+  auto finish_beta = [&]() {
+    block_sum<1>(bs, red);
+    beta = bs[0] / rho;
+    have = true;
+  };
+  for (int t2 = blockIdx.x; 2 * t2 < a.ntile; t2 += gridDim.x) {
+    const int t = 2 * t2 + half;
+    const bool valid = t < a.ntile;
+    const int s = valid ? a.tile_sub[t] : 0, row0 = valid ? a.tile_row0[t] : 0;
+    const int nbs = valid ? m.nb[s] : 0;
+    const int64_t b0 = valid ? m.boff[s] : 0;
+    double* xs = xs2 + half * m.max_nb;
+    double* red4 = red8 + half * 256;
+    __syncthreads();  // xs and red4 of the previous tiles are consumed
+    if (!have) {
+      // first pass of the gather (entries ht and ht + 256) with beta pending
+      double s0[2], s1[2], y0[2], p0[2], y1[2], p1[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool in = ht + 256 * h < nbs;
+        const int64_t gb = b0 + (in ? ht + 256 * h : 0);
+        const int q0 = in ? m.bg_row[2 * gb] : -1, q1 = in ? m.bg_row[2 * gb + 1] : -1;
+        const int r0 = q0 >= 0 ? q0 : 0, r1 = q1 >= 0 ? q1 : 0;
+        s0[h] = q0 >= 0 ? m.bg_sign[2 * gb] : 0.0;
+        s1[h] = q1 >= 0 ? m.bg_sign[2 * gb + 1] : 0.0;
+        y0[h] = ald(a.y + r0);
+        p0[h] = ald(a.p + r0);
+        y1[h] = ald(a.y + r1);
+        p1[h] = ald(a.p + r1);
+      }
+      finish_beta();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double v = s0[h] * (y0[h] + beta * p0[h]);
+        v += s1[h] * (y1[h] + beta * p1[h]);
+        if (ht + 256 * h < nbs) xs[ht + 256 * h] = v;
+      }
+      // later passes (n_b > 512)
+      if (nbs > 512) gather_x<0>(m, nbs - 512, b0 + 512, a.y, a.p, beta, xs + 512, ht);
+    } else {
+      gather_x<0>(m, nbs, b0, a.y, a.p, beta, xs, ht);
+    }
+    __syncthreads();
+    const int i = row0 + lane;
+    const int kq = (nbs + 3) / 4;
+    const int kb = wave * kq, ke = min(nbs, kb + kq);
+    double v = 0.0;
+    if (i < nbs) v = tile_cols<MT>(A + m.sofs[s], m.ldb[s], i, kb, ke, xs);
+    red4[wave * 64 + lane] = v;
+    __syncthreads();
+    if (wave == 0 && i < nbs)
+      ast(yout + b0 + i, (red4[lane] + red4[64 + lane]) + (red4[128 + lane] + red4[192 + lane]));
+  }
+  if (!have) finish_beta();
+  return bs[0];
 }
 
 // Phases B and F: out_j = (scaled) jump of yb; g_f = R_s^T B_s^T out for the
@@ -334,9 +406,17 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
   };
   stamp();
   for (; !start_done; ++it_local, ph = 1) {  // stamp 0 of a later iteration is stamp 6 of the one before
-    // (A) y_b = (K^+)_bb B^T p,  p = y + beta p_old
-    if (a.fm32) gemv_phase<float, 0>(a, (const float*)a.fm, a.y, a.p, beta, a.yb, xs, red4);
-    else gemv_phase<double, 0>(a, (const double*)a.fm, a.y, a.p, beta, a.yb, xs, red4);
+    // (A) y_b = (K^+)_bb B^T p,  p = y + beta p_old (beta from the partials of phase G,
+    // except in the first iteration of a launch)
+    if (it_local == 0) {
+      if (a.fm32) gemv_phase<float, 0>(a, (const float*)a.fm, a.y, a.p, beta, a.yb, xs, red4);
+      else gemv_phase<double, 0>(a, (const double*)a.fm, a.y, a.p, beta, a.yb, xs, red4);
+    } else {
+      const double t0 = a.fm32 ? gemv_phase_a<float>(a, (const float*)a.fm, partbuf(rk), nblk, rho, beta, a.yb, xs, red4, red)
+                               : gemv_phase_a<double>(a, (const double*)a.fm, partbuf(rk), nblk, rho, beta, a.yb, xs, red4, red);
+      ++rk;
+      rho = t0;
+    }
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
     stamp();
     // (B) q_raw = B y_b, g = G^T q_raw, partial (p, q_raw)
@@ -384,13 +464,8 @@ __global__ void __launch_bounds__(PCG_BLOCK) k_pcg_persistent(PcgArgs a) {
     correct_dot_phase(a, a.z, a.y, a.w, nullptr, 0.0, partbuf(rk), acl, red4, red);
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
     stamp();
-    {
-      double t[1];
-      grid_total<1>(partbuf(rk++), nblk, t, red);
-      if (!(fabs(rho) > 1e-300)) { status = FETI_EBREAKDOWN; break; }
-      beta = t[0] / rho;
-      rho = t[0];
-    }
+    // beta = (w, y) / rho is formed at the start of the next phase A
+    if (!(fabs(rho) > 1e-300)) { status = FETI_EBREAKDOWN; break; }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.sc[SC_RHO] = rho;

@@ -140,17 +140,6 @@ __device__ inline void block_store(double (&v)[NV], double* red, double* dst) {
   __syncthreads();
 }
 
-// Sum of the per-block partials part[b][0..NV) over all blocks, in block order.
-template <int NV>
-__device__ inline void grid_total(const double* part, int nblk, double (&v)[NV], double* red) {
-#pragma unroll
-  for (int c = 0; c < NV; ++c) v[c] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += PB)
-#pragma unroll
-    for (int c = 0; c < NV; ++c) v[c] += ald(part + b * PCG_NPART + c);
-  block_sum<NV>(v, red);
-}
-
 // Sum of the per-block partials part[b][0..NV) over all blocks, in block order, into
 // v[0..NV) (LDS), in two parts so that the loads overlap other work: gt_issue spreads
 // the nblk x NV device-coherent loads over the threads (at most GT_LOADS each, issued
@@ -236,18 +225,12 @@ __device__ inline void stop_test_wave0(const double* conv, const double* kc, dou
   }
 }
 
-// One 64-row tile of y_b = A_s x_b (interface block of subdomain s) by one half of
-// the block (four wavefronts, threads ht = 0..255): x_b gathered into xs, the
-// wavefronts split the column range and combine in red4.  SCALED = 0: x_b = B_s^T p
-// with p = src + beta src2; SCALED = 1: x_b = B_s^T D src.  valid = false: the half
-// only takes part in the block's barriers.
-template <class MT, int SCALED>
-__device__ inline void gemv_tile(const DevMesh& m, const MT* A, int s, int row0, bool valid, const double* src,
-                          const double* src2, double beta, double* yout, double* xs, double* red4, int ht) {
-  const int wave = ht >> 6, lane = ht & 63;
-  const int nbs = valid ? m.nb[s] : 0;
-  const int64_t b0 = valid ? m.boff[s] : 0;
-  __syncthreads();  // xs and red4 of the previous tiles are consumed
+// x_b of subdomain block (nbs entries from b0) gathered into xs by the threads
+// ht = 0..255: SCALED = 0: x_b = B_s^T p with p = src + beta src2; SCALED = 1:
+// x_b = B_s^T D src.
+template <int SCALED>
+__device__ inline void gather_x(const DevMesh& m, int nbs, int64_t b0, const double* src, const double* src2,
+                                double beta, double* xs, int ht) {
   // two entries per thread and pass, their loads issued together; branch-free: an
   // absent entry (or one past nbs) reads row 0 with weight 0
   for (int i0 = ht; i0 < nbs; i0 += 512) {
@@ -303,42 +286,60 @@ __device__ inline void gemv_tile(const DevMesh& m, const MT* A, int s, int row0,
     xs[i0] = v[0];
     if (i0 + 256 < nbs) xs[i0 + 256] = v[1];
   }
+}
+
+// sum over the columns k in [kb, ke) of A_s[i][k] xs[k] (A_s column-major with leading
+// dimension ld): batches of GEMV_BATCH independent column loads in flight before their
+// FMAs (a lane's column range is a chain of dependent round trips to HBM, so the
+// batch size sets the bytes in flight), the last columns as one batch
+template <class MT>
+__device__ inline double tile_cols(const MT* As, int64_t ld, int i, int kb, int ke, const double* xs) {
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  const MT* col = As + (int64_t)kb * ld + i;
+  int k = kb;
+  for (; k + GEMV_BATCH <= ke; k += GEMV_BATCH, col += GEMV_BATCH * ld) {
+    MT v[GEMV_BATCH];
+#pragma unroll
+    for (int u = 0; u < GEMV_BATCH; ++u) v[u] = col[(int64_t)u * ld];
+#pragma unroll
+    for (int u = 0; u < GEMV_BATCH; u += 4) {
+      acc0 += (double)v[u + 0] * xs[k + u + 0];
+      acc1 += (double)v[u + 1] * xs[k + u + 1];
+      acc2 += (double)v[u + 2] * xs[k + u + 2];
+      acc3 += (double)v[u + 3] * xs[k + u + 3];
+    }
+  }
+  if (k < ke) {
+    // the last (ke - k < GEMV_BATCH) columns: loads together, products in order
+    MT v[GEMV_BATCH];
+#pragma unroll
+    for (int u = 0; u < GEMV_BATCH; ++u) v[u] = k + u < ke ? col[(int64_t)u * ld] : (MT)0;
+#pragma unroll
+    for (int u = 0; u < GEMV_BATCH; ++u)
+      if (k + u < ke) acc0 += (double)v[u] * xs[k + u];
+  }
+  return (acc0 + acc1) + (acc2 + acc3);
+}
+
+// One 64-row tile of y_b = A_s x_b (interface block of subdomain s) by one half of
+// the block (four wavefronts, threads ht = 0..255): x_b gathered into xs, the
+// wavefronts split the column range and combine in red4.  SCALED as in gather_x.
+// valid = false: the half only takes part in the block's barriers.
+template <class MT, int SCALED>
+__device__ inline void gemv_tile(const DevMesh& m, const MT* A, int s, int row0, bool valid, const double* src,
+                          const double* src2, double beta, double* yout, double* xs, double* red4, int ht) {
+  const int wave = ht >> 6, lane = ht & 63;
+  const int nbs = valid ? m.nb[s] : 0;
+  const int64_t b0 = valid ? m.boff[s] : 0;
+  __syncthreads();  // xs and red4 of the previous tiles are consumed
+  gather_x<SCALED>(m, nbs, b0, src, src2, beta, xs, ht);
   __syncthreads();
   const int i = row0 + lane;
   const int kq = (nbs + 3) / 4;
   const int kb = wave * kq, ke = min(nbs, kb + kq);
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-  if (i < nbs) {
-    const MT* As = A + m.sofs[s];
-    const int64_t ld = m.ldb[s];
-    // batches of GEMV_BATCH independent column loads in flight before their FMAs: a
-    // lane's column range is a chain of dependent round trips to HBM, so the batch
-    // size sets the bytes in flight
-    const MT* col = As + (int64_t)kb * ld + i;
-    int k = kb;
-    for (; k + GEMV_BATCH <= ke; k += GEMV_BATCH, col += GEMV_BATCH * ld) {
-      MT v[GEMV_BATCH];
-#pragma unroll
-      for (int u = 0; u < GEMV_BATCH; ++u) v[u] = col[(int64_t)u * ld];
-#pragma unroll
-      for (int u = 0; u < GEMV_BATCH; u += 4) {
-        acc0 += (double)v[u + 0] * xs[k + u + 0];
-        acc1 += (double)v[u + 1] * xs[k + u + 1];
-        acc2 += (double)v[u + 2] * xs[k + u + 2];
-        acc3 += (double)v[u + 3] * xs[k + u + 3];
-      }
-    }
-    if (k < ke) {
-      // the last (ke - k < GEMV_BATCH) columns: loads together, products in order
-      MT v[GEMV_BATCH];
-#pragma unroll
-      for (int u = 0; u < GEMV_BATCH; ++u) v[u] = k + u < ke ? col[(int64_t)u * ld] : (MT)0;
-#pragma unroll
-      for (int u = 0; u < GEMV_BATCH; ++u)
-        if (k + u < ke) acc0 += (double)v[u] * xs[k + u];
-    }
-  }
-  red4[wave * 64 + lane] = (acc0 + acc1) + (acc2 + acc3);
+  double v = 0.0;
+  if (i < nbs) v = tile_cols<MT>(A + m.sofs[s], m.ldb[s], i, kb, ke, xs);
+  red4[wave * 64 + lane] = v;
   __syncthreads();
   if (wave == 0 && i < nbs)
     ast(yout + b0 + i, (red4[lane] + red4[64 + lane]) + (red4[128 + lane] + red4[192 + lane]));
