@@ -4,8 +4,9 @@
 // blocks, and the product is bound by HBM bandwidth.
 //
 // One wavefront per stored tile (I, J), J <= I: the row part A_IJ x_J comes from the
-// coalesced column loads of the tile, which are also staged in LDS (32 columns at a
-// time) for the transposed part A_IJ^T x_I (off-diagonal tiles only).  Both parts go
+// coalesced column loads of the tile, which are also staged in LDS (16 columns at a
+// time, so that four blocks fit a CU) for the transposed part A_IJ^T x_I (off-diagonal
+// tiles only).  Both parts go
 // to a partial buffer; a second kernel sums, for every row, the partials of its
 // tile row and tile column in a fixed order (deterministic, no atomics).
 #include "kernels.h"
@@ -15,7 +16,8 @@ namespace feti {
 constexpr int SYM_TS = 64;                 // tile size
 constexpr int SYM_TE = SYM_TS * SYM_TS;    // elements per tile
 constexpr int SYM_WAVES = 4;               // tiles per block
-constexpr int SYM_LD = 65;                 // LDS row stride of a staged half tile
+constexpr int SYM_Q = 16;                  // tile columns staged in LDS at a time
+constexpr int SYM_LD = 65;                 // LDS row stride of the staged columns
 
 // Tile t of the packed storage: column-major 64 x 64, element (i, k) of tile (I, J)
 // at t * 4096 + k * 64 + i = K_s[I * 64 + i][J * 64 + k] (zero outside n_s).
@@ -37,7 +39,7 @@ __global__ void __launch_bounds__(256) k_sym_pack(SymArgs a, const T* __restrict
 template <class T>
 __global__ void __launch_bounds__(256) k_sym_tiles(SymArgs a, const T* __restrict__ P, const int64_t* __restrict__ soff,
                                                    const int32_t* __restrict__ ns, const double* __restrict__ x) {
-  __shared__ double L[SYM_WAVES][32 * SYM_LD];
+  __shared__ double L[SYM_WAVES][SYM_Q * SYM_LD];
   __shared__ double xv[SYM_WAVES][2][SYM_TS];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int t = blockIdx.x * SYM_WAVES + wave;
@@ -52,27 +54,28 @@ __global__ void __launch_bounds__(256) k_sym_tiles(SymArgs a, const T* __restric
   const T* tile = P + (int64_t)(valid ? t : 0) * SYM_TE;
   double* Lw = L[wave];
   double u = 0.0;
-  for (int h = 0; h < 2; ++h) {
-    __syncthreads();  // xv written, or the previous half consumed
+  for (int h = 0; h < SYM_TS / SYM_Q; ++h) {
+    __syncthreads();  // xv written, or the previous columns consumed
     if (valid) {
-#pragma unroll 8
-      for (int kk = 0; kk < 32; ++kk) {
-        const int k = h * 32 + kk;
+#pragma unroll
+      for (int kk = 0; kk < SYM_Q; ++kk) {
+        const int k = h * SYM_Q + kk;
         const double v = (double)tile[k * SYM_TS + lane];
         u += v * xJ[k];
         Lw[kk * SYM_LD + lane] = v;
       }
     }
     __syncthreads();
-    if (valid && I != J) {
-      // (A^T x_I)_k for the 32 columns k of this half: lanes l and l + 32 take the two
-      // halves of the i range of column h * 32 + l % 32
-      const int kk = lane & 31, i0 = (lane >> 5) * 32;
+    if (valid && I != J && (lane & 16) == 0) {
+      // (A^T x_I)_k for the SYM_Q columns k of this step: lanes l and l + 32 (l < 16) take
+      // the two halves of the i range of column h * SYM_Q + l (the shuffle pairs only
+      // lanes of this branch)
+      const int kk = lane & (SYM_Q - 1), i0 = (lane >> 5) * 32;
       double v = 0.0;
 #pragma unroll 8
       for (int i = 0; i < 32; ++i) v += Lw[kk * SYM_LD + i0 + i] * xI[i0 + i];
       v += __shfl_xor(v, 32, 64);
-      if (lane < 32) a.part[(int64_t)t * 2 * SYM_TS + SYM_TS + h * 32 + kk] = v;
+      if (lane < 32) a.part[(int64_t)t * 2 * SYM_TS + SYM_TS + h * SYM_Q + kk] = v;
     }
   }
   if (valid) a.part[(int64_t)t * 2 * SYM_TS + lane] = u;
