@@ -57,6 +57,11 @@ struct feti_ctx_s {
   float* Splus32 = nullptr;
   // packed lower 64 x 64 tiles of K_s^+ for the local solves (beside the dense blocks)
   SymArgs sym;
+  // load parts of the element right-hand sides for time-independent loads, and the load
+  // and material parameters they were computed for
+  double* ecache = nullptr;
+  bool ecache_valid = false;
+  unsigned char ekey[sizeof(LoadDev) + 2 * sizeof(MatParams)] = {};
   int nc = 0;
   // vectors
   double *f = nullptr, *u = nullptr, *ytmp = nullptr, *yb = nullptr, *zb = nullptr;
@@ -323,6 +328,8 @@ void free_all(feti_ctx ctx) {
   ctx->K = ctx->Kinv = ctx->Sbb = ctx->Splus = ctx->Kbb = ctx->Cinv = ctx->H = nullptr;
   ctx->Kinv32 = ctx->Sbb32 = ctx->Splus32 = nullptr;
   ctx->sym = SymArgs();
+  ctx->ecache = nullptr;
+  ctx->ecache_valid = false;
 }
 
 LoadDev make_load(feti_ctx ctx, const feti_load* L) {
@@ -1237,7 +1244,26 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, fet
   hipStream_t st = ctx->stream;
   HIPCHK(hipEventRecord(ctx->ev[0], st));
   LoadDev L = make_load(ctx, load);
-  launch_rhs(m, ctx->u, ctx->f, ctx->mpP, ctx->mpE, L, st);
+  int cmode = 0;
+  if (L.kind == FETI_LOAD_MANUFACTURED || L.kind == FETI_LOAD_PATCH) {
+    // these loads do not depend on t: the quadrature of a step repeats that of the last
+    // step with the same load and material parameters
+    unsigned char key[sizeof(ctx->ekey)];
+    LoadDev Lk = L;
+    Lk.t = 0.0;
+    std::memcpy(key, &Lk, sizeof(LoadDev));
+    std::memcpy(key + sizeof(LoadDev), &ctx->mpP, sizeof(MatParams));
+    std::memcpy(key + sizeof(LoadDev) + sizeof(MatParams), &ctx->mpE, sizeof(MatParams));
+    if (!ctx->ecache) RC(dalloc(ctx, &ctx->ecache, (size_t)m.nelem * m.edof, ctx->allocs));
+    if (ctx->ecache_valid && std::memcmp(key, ctx->ekey, sizeof(key)) == 0) {
+      cmode = 2;
+    } else {
+      cmode = 1;
+      std::memcpy(ctx->ekey, key, sizeof(key));
+      ctx->ecache_valid = true;
+    }
+  }
+  launch_rhs(m, ctx->u, ctx->f, ctx->mpP, ctx->mpE, L, st, ctx->ecache, cmode);
   // start vector
   int used = o->start;
   if (o->start == FETI_START_ZERO ||

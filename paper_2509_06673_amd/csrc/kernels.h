@@ -58,9 +58,10 @@ struct DevMesh {
 
 // assembly / right-hand side (kernels_fem.hip)
 void launch_assemble(const DevMesh& m, double* K, MatParams mpP, MatParams mpE, hipStream_t st);
-// f = torn right-hand side (overwriting f)
+// f = torn right-hand side (overwriting f); with cache (nelem x edof doubles), cmode 1
+// also stores the elements' load parts there and cmode 2 takes them from there
 void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams mpP, MatParams mpE,
-                const LoadDev& L, hipStream_t st);
+                const LoadDev& L, hipStream_t st, double* cache = nullptr, int cmode = 0);
 void launch_init_eta(const DevMesh& m, double* u, const LoadDev& L, hipStream_t st);
 // load sampled at the node of every multiplier row (body force of u rows, source of eta, xi_P, p rows)
 void launch_interface_load(const DevMesh& m, const LoadDev& L, double* out, hipStream_t st);

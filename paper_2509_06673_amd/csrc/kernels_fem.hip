@@ -64,8 +64,12 @@ __device__ inline double dirichlet_value(const LoadDev& L, bool poro, int32_t co
 // One thread per element: the element's right-hand side contributions (rows 1 and 4
 // of eq. (linalg-system): F_u = (f, theta) and -R eta^{n-1} - tau Z on the p rows,
 // minus the Dirichlet lifting K_e[r, D] g_D) into ebuf[e][row].
+// cmode 1: the element's load part (after the quadrature) is also stored in cache[e][row];
+// cmode 2: the load part is read from cache instead of being recomputed (loads that do
+// not depend on time, same material parameters); the terms that follow are the same.
 __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __restrict__ eta_prev,
-                                                  MatParams mpP, MatParams mpE, LoadDev L) {
+                                                  MatParams mpP, MatParams mpE, LoadDev L, double* cache,
+                                                  int cmode) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m.nelem) return;
   const int edof = m.edof, order = m.order, ncell = m.ncell;
@@ -77,8 +81,11 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
   const int nloc = order == 2 ? 6 : 3, nu = 2 * nloc;
   double acc[MAX_EDOF_DEV];
   for (int r = 0; r < MAX_EDOF_DEV; ++r) acc[r] = 0.0;
+  if (cmode == 2) {
+    for (int r = 0; r < edof; ++r) acc[r] = cache[e * edof + r];
+  }
   // loads at the 7 quadrature points
-  for (int q = 0; q < 7; ++q) {
+  for (int q = 0; q < (cmode == 2 ? 0 : 7); ++q) {
     double l0, l1, l2, w;
     radon_point(q, l0, l1, l2, w);
     const double x = l0 * g.x[0] + l1 * g.x[1] + l2 * g.x[2];
@@ -100,6 +107,8 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
       for (int k = 0; k < 3; ++k) acc[nu + 6 + k] -= mp.tau * wa * z * lam[k];
     }
   }
+  if (cmode == 1)
+    for (int r = 0; r < edof; ++r) cache[e * edof + r] = acc[r];
   const int32_t* ld = m.el_ldof + e * edof;
   if (poro) {
     const double* eta = eta_prev + m.soff[s];
@@ -117,11 +126,54 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
     if (code < 0) continue;
     const double gv = dirichlet_value(L, poro, code, umu, uh, ncell + 1, h);
     if (gv == 0.0) continue;
+    // K_e[r][c] from the stored element matrices (the same values elem_entry gives)
+    const double* Kc = m.emat ? m.emat + (e * edof + c) * edof : nullptr;
     for (int r = 0; r < edof; ++r)
-      if (ld[r] >= 0) acc[r] -= elem_entry(order, poro, g, mp, r, c) * gv;
+      if (ld[r] >= 0) acc[r] -= (Kc ? Kc[r] : elem_entry(order, poro, g, mp, r, c)) * gv;
   }
   double* out = m.ebuf + e * edof;
   for (int r = 0; r < edof; ++r) out[r] = acc[r];
+}
+
+// The right-hand side from the cached load parts (cmode 2 of k_rhs_elem), one thread per
+// (element, row): row r of the element takes the same terms in the same order as there
+// (the eta moments on the p rows, then the lifting columns in order), with K_e read
+// from the stored element matrices.
+__global__ void __launch_bounds__(256) k_rhs_rows(DevMesh m, const double* __restrict__ eta_prev, MatParams mpP,
+                                                  MatParams mpE, LoadDev L, const double* __restrict__ cache) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int edof = m.edof;
+  const int64_t e = gid / edof;
+  const int r = (int)(gid % edof);
+  if (e >= m.nelem) return;
+  const int order = m.order, ncell = m.ncell;
+  const int s = m.el_sub[e];
+  const bool poro = m.sub_poro[s] != 0;
+  const int nloc = order == 2 ? 6 : 3, nu = 2 * nloc;
+  const int32_t* ld = m.el_ldof + e * edof;
+  double acc = cache[gid];
+  const bool prow = poro && r >= nu + 6 && r < nu + 9;
+  ElemGeom g;
+  if (prow || !m.emat) elem_geom(m.el_cell[e], m.el_type[e], ncell, g);
+  if (prow) {
+    const double* eta = eta_prev + m.soff[s];
+    const int k = r - (nu + 6);
+    for (int b = 0; b < 3; ++b) acc -= moment2(g, k, b) * eta[ld[nu + 3 + b]];
+  }
+  if (ld[r] >= 0) {
+    const MatParams& mp = poro ? mpP : mpE;
+    const int umu = order * ncell + 1;
+    const double uh = 1.0 / (order * ncell), h = 1.0 / ncell;
+    for (int c = 0; c < edof; ++c) {
+      if (ld[c] >= 0) continue;
+      const int32_t code = m.el_code[e * edof + c];
+      if (code < 0) continue;
+      const double gv = dirichlet_value(L, poro, code, umu, uh, ncell + 1, h);
+      if (gv == 0.0) continue;
+      acc -= (m.emat ? m.emat[(e * edof + c) * edof + r] : elem_entry(order, poro, g, mp, r, c)) * gv;
+    }
+  }
+  m.ebuf[gid] = acc;
 }
 
 // One thread per (element, row): ebuf[e][row] = (K_e x_e)[row]
@@ -225,8 +277,15 @@ void launch_assemble(const DevMesh& m, double* K, MatParams mpP, MatParams mpE, 
 }
 
 void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams mpP, MatParams mpE,
-                const LoadDev& L, hipStream_t st) {
-  hipLaunchKernelGGL(k_rhs_elem, dim3((m.nelem + 127) / 128), dim3(128), 0, st, m, eta_prev, mpP, mpE, L);
+                const LoadDev& L, hipStream_t st, double* cache, int cmode) {
+  if (cache && cmode == 2) {
+    const int64_t nthreads = (int64_t)m.nelem * m.edof;
+    hipLaunchKernelGGL(k_rhs_rows, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, m, eta_prev, mpP, mpE,
+                       L, cache);
+  } else {
+    hipLaunchKernelGGL(k_rhs_elem, dim3((m.nelem + 127) / 128), dim3(128), 0, st, m, eta_prev, mpP, mpE, L,
+                       cache, cache ? cmode : 0);
+  }
   hipLaunchKernelGGL(k_gather_elem, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, m, f);
 }
 

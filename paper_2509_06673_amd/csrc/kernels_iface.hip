@@ -109,24 +109,29 @@ __device__ void reduce_and_finalize(double (&acc)[NPART], double* __restrict__ p
   __shared__ double red[NW][NV];
   __shared__ int is_last;
   block_sums<NV>(acc, red);
+  // the partials move between blocks through device-coherent stores and loads, and the
+  // stores complete before the block is counted (no cache-wide fence needed)
   if (threadIdx.x < NV) {
     double x = 0.0;
     for (int w = 0; w < NW; ++w) x += red[w][threadIdx.x];
-    part[blockIdx.x * NPART + threadIdx.x] = x;
+    __hip_atomic_store(part + blockIdx.x * NPART + threadIdx.x, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  __threadfence();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __syncthreads();
-  if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1) == (int)gridDim.x - 1);
+  if (threadIdx.x == 0)
+    is_last = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (int)gridDim.x - 1;
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
   const int nblk = gridDim.x;
   double v[NPART];
 #pragma unroll
   for (int c = 0; c < NPART; ++c) v[c] = 0.0;
   for (int b = threadIdx.x; b < nblk; b += RED_BLOCK)
 #pragma unroll
-    for (int c = 0; c < NV; ++c) v[c] += part[b * NPART + c];
+    for (int c = 0; c < NV; ++c)
+      v[c] += __hip_atomic_load(part + b * NPART + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   block_sums<NV>(v, red);
   if (threadIdx.x == 0) {
 #pragma unroll
