@@ -140,12 +140,11 @@ __device__ inline void block_store(double (&v)[NV], double* red, double* dst) {
   __syncthreads();
 }
 
-// Sum of the per-block partials part[b][0..NV) over all blocks, in block order, into
+// Sum of the per-block partials part[b][0..NV) over all blocks into
 // v[0..NV) (LDS), in two parts so that the loads overlap other work: gt_issue spreads
 // the nblk x NV device-coherent loads over the threads (at most GT_LOADS each, issued
 // together) into registers; gt_finish stages them in LDS (stage: nblk x NV doubles)
-// and thread c adds value c over the blocks.  v is valid in every thread after
-// gt_finish.
+// and adds them in a fixed order.  v is valid in every thread after gt_finish.
 constexpr int GT_LOADS = 10;
 template <int NV>
 __device__ inline void gt_issue(const double* part, int nblk, double (&t)[GT_LOADS]) {
@@ -165,19 +164,25 @@ __device__ inline void gt_finish(const double (&t)[GT_LOADS], int nblk, double* 
     if (idx < total) stage[idx] = t[k];
   }
   __syncthreads();
-  if (threadIdx.x < NV) {
-    // in block order; the LDS reads of 16 blocks are issued before their additions
+  // value c is summed by the 16 lanes 16 c .. 16 c + 15 (lane q: blocks q, q + 16, ...,
+  // in order), then by a fixed shuffle tree over the 16 lanes
+  static_assert(NV * 16 <= PB, "16 lanes per summed value");
+  const int c = threadIdx.x >> 4, q = threadIdx.x & 15;
+  if (c < NV) {
     double x = 0.0;
-    int b = 0;
-    for (; b + 16 <= nblk; b += 16) {
-      double u[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) u[k] = stage[(b + k) * NV + threadIdx.x];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) x += u[k];
+    int b = q;
+    for (; b + 48 < nblk; b += 64) {
+      const double u0 = stage[b * NV + c], u1 = stage[(b + 16) * NV + c];
+      const double u2 = stage[(b + 32) * NV + c], u3 = stage[(b + 48) * NV + c];
+      x += u0;
+      x += u1;
+      x += u2;
+      x += u3;
     }
-    for (; b < nblk; ++b) x += stage[b * NV + threadIdx.x];
-    v[threadIdx.x] = x;
+    for (; b < nblk; b += 16) x += stage[b * NV + c];
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) x += __shfl_xor(x, off, 16);
+    if (q == 0) v[c] = x;
   }
   __syncthreads();  // v complete; stage free again
 }
