@@ -124,12 +124,25 @@ _SIGS = {
 }
 
 
+def _torch_device_first():
+    """Initialise torch's HIP state before the library makes its first HIP call: a
+    torch initialised after that has been seen to find no device.  Nothing happens
+    without torch or without a GPU."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2509_06673_amd.build`")
+    _torch_device_first()
     lib = C.CDLL(path)
     for name, args in _SIGS.items():
         fn = getattr(lib, name)
