@@ -51,7 +51,7 @@ def source_hash(paths):
 
 
 def measured_traffic(variant):
-    if variant != "fp64" or MEASURED_TRAFFIC["bytes_per_iteration"] is None:
+    if variant not in ("fp64", "fp64x") or MEASURED_TRAFFIC["bytes_per_iteration"] is None:
         return None
     try:
         sha = source_hash(MEASURED_TRAFFIC["sources"])
@@ -310,9 +310,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--variant", default="both", choices=["fp64", "mixed", "both"],
-                    help="fp64: FP64 factors; mixed: FP32 factors on the matrix cores with FP64 "
-                         "refinement; both: fp64 is the headline value and mixed is reported beside it")
+    ap.add_argument("--variant", default="both", choices=["fp64", "fp64x", "mixed", "both"],
+                    help="fp64: FP64 factors, each first solve from the previous step's multipliers; "
+                         "fp64x: the same from the extrapolation 2 lambda^n - lambda^(n-1); mixed: "
+                         "FP32 factors on the matrix cores with FP64 refinement; both: fp64 is the "
+                         "headline value and fp64x and mixed are reported beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -349,7 +351,7 @@ def main():
     torch.cuda.set_device(0)
     import workloads as W
     w = W.nearly_incompressible_large()
-    variants = ["fp64", "mixed"] if args.variant == "both" else [args.variant]
+    variants = ["fp64", "fp64x", "mixed"] if args.variant == "both" else [args.variant]
     res = {v: run_variant(args, w, v) for v in variants}
     prim = res[variants[0]]
     out = {
@@ -421,7 +423,8 @@ def run_variant(args, w, variant):
     t2 = time.perf_counter()
     f.init_state(load(w, 0.0))
     mk = opts_mixed if mixed else opts
-    o = mk(tol=w.tol, max_it=2000, start=B.START_PREVIOUS, check_every=args.check_every)
+    start = B.START_EXTRAPOLATE if variant == "fp64x" else B.START_PREVIOUS
+    o = mk(tol=w.tol, max_it=2000, start=start, check_every=args.check_every)
     n = 0
     warm_iters = []
     for _ in range(args.warmup):

@@ -137,7 +137,9 @@ typedef struct {
     int32_t corr_start;   /* start of the first refinement correction of a step:
                              FETI_CORR_ZERO, or FETI_CORR_PREVIOUS = the previous step's total
                              correction (the rounding that the corrections undo comes from the
-                             same factors applied to a slowly varying load) */
+                             same factors applied to a slowly varying load), kept only if its
+                             projected residual is smaller than the zero start's.  Any other
+                             value: FETI_EINVAL. */
 } feti_solve_opts;
 
 typedef struct {

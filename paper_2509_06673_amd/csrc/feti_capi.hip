@@ -1239,7 +1239,8 @@ int feti_init_state(feti_ctx ctx, const feti_load* load) {
 int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, feti_stats* stats) {
   if (!ctx || !load || !o) return FETI_EINVAL;
   if (ctx->state < 3) return fail(ctx, FETI_ESTATE, "step before factor_subdomains");
-  if (!(o->tol > 0.0) || o->max_it < 1) return fail(ctx, FETI_EINVAL, "bad solve options");
+  if (!(o->tol > 0.0) || o->max_it < 1 || o->corr_start < FETI_CORR_ZERO || o->corr_start > FETI_CORR_PREVIOUS)
+    return fail(ctx, FETI_EINVAL, "bad solve options");
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
   HIPCHK(hipEventRecord(ctx->ev[0], st));
@@ -1722,7 +1723,8 @@ int feti_batch_info(feti_batch b, int32_t* info) {
 
 int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts* o, feti_stats* stats) {
   if (!b || !loads || !o) return FETI_EINVAL;
-  if (!(o->tol > 0.0) || o->max_it < 1) return bfail(b, FETI_EINVAL, "bad solve options");
+  if (!(o->tol > 0.0) || o->max_it < 1 || o->corr_start < FETI_CORR_ZERO || o->corr_start > FETI_CORR_PREVIOUS)
+    return bfail(b, FETI_EINVAL, "bad solve options");
   if (o->start == FETI_START_GIVEN || o->start == FETI_START_BEST)
     return bfail(b, FETI_EINVAL, "a batch step starts from the previous, extrapolated or zero multipliers");
   const int P = b->P;

@@ -209,22 +209,29 @@ def test_not_converged_is_reported_with_iterate():
     f.close()
 
 
-def test_full_size_workload_matches_oracle():
-    """The 64-subdomain h = 1/128 workload, as bench.py runs it, against the oracle."""
+_FULL_ORACLE = {}
+
+
+@pytest.mark.parametrize("start", [B.START_PREVIOUS, B.START_EXTRAPOLATE], ids=["previous", "extrapolated"])
+def test_full_size_workload_matches_oracle(start):
+    """The 64-subdomain h = 1/128 workload, as bench.py runs it (first solves from the
+    previous step's multipliers, or from their extrapolation), against the oracle."""
     import time
     import torch
     w = W.nearly_incompressible_large()
     nsteps = 4
-    t0 = time.time()
-    print("[full] oracle ...", flush=True)
-    sysm, lats = oracle_reference(w, nsteps)
-    print(f"[full] oracle done in {time.time() - t0:.1f} s", flush=True)
+    if not _FULL_ORACLE:
+        t0 = time.time()
+        print("[full] oracle ...", flush=True)
+        _FULL_ORACLE["lats"] = oracle_reference(w, nsteps)[1]
+        print(f"[full] oracle done in {time.time() - t0:.1f} s", flush=True)
+    lats = _FULL_ORACLE["lats"]
     f = setup(w)
     idx = f.export_indexing()
     codes = idx["code"].astype(np.int64)
     poro = sub_poro_flags(w)
     u = torch.empty(len(codes), dtype=torch.float64, device="cuda")
-    o = opts(tol=w.tol, max_it=3000)
+    o = opts(tol=w.tol, max_it=3000, start=start)
     for n in range(1, nsteps + 1):
         st = f.step(load(w, n * w.tau), o)
         f.get_solution(u)
@@ -290,6 +297,17 @@ def test_pcg_mode_is_validated():
         f.set_pcg_mode(7)
     f.set_pcg_mode(B.PCG_GRAPH)
     f.set_pcg_mode(B.PCG_AUTO)
+    f.close()
+
+
+def test_correction_start_is_validated():
+    w = W.nearly_incompressible_scaled(8, 2)
+    require_gpu()
+    f = setup(w)
+    with pytest.raises(B.FetiError):
+        f.step(load(w, w.tau), opts(corr_start=2))
+    st = f.step(load(w, w.tau), opts(corr_start=B.CORR_ZERO))
+    assert st["status"] == 0, st
     f.close()
 
 
