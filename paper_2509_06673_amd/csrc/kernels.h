@@ -58,8 +58,9 @@ struct DevMesh {
 
 // assembly / right-hand side (kernels_fem.hip)
 void launch_assemble(const DevMesh& m, double* K, MatParams mpP, MatParams mpE, hipStream_t st);
-// f = torn right-hand side (overwriting f); with cache (nelem x edof doubles), cmode 1
-// also stores the elements' load parts there and cmode 2 takes them from there
+// f = torn right-hand side (overwriting f); with cache (nelem x edof doubles), for loads
+// and Dirichlet data that do not depend on time: cmode 1 also stores there the parts of
+// the element rows that do not depend on the state, cmode 2 starts from them
 void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams mpP, MatParams mpE,
                 const LoadDev& L, hipStream_t st, double* cache = nullptr, int cmode = 0);
 void launch_init_eta(const DevMesh& m, double* u, const LoadDev& L, hipStream_t st);

@@ -64,9 +64,11 @@ __device__ inline double dirichlet_value(const LoadDev& L, bool poro, int32_t co
 // One thread per element: the element's right-hand side contributions (rows 1 and 4
 // of eq. (linalg-system): F_u = (f, theta) and -R eta^{n-1} - tau Z on the p rows,
 // minus the Dirichlet lifting K_e[r, D] g_D) into ebuf[e][row].
-// cmode 1: the element's load part (after the quadrature) is also stored in cache[e][row];
-// cmode 2: the load part is read from cache instead of being recomputed (loads that do
-// not depend on time, same material parameters); the terms that follow are the same.
+// cmode 1 (loads and Dirichlet data that do not depend on time): cache[e][row] also
+// receives the part of the row that does not depend on the state: the final value of a
+// row without eta terms (the load part minus the lifting), the load part of a p row of
+// a poroelastic element (whose eta terms come before the lifting); k_rhs_rows then
+// forms later steps from it with the same terms in the same order.
 __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __restrict__ eta_prev,
                                                   MatParams mpP, MatParams mpE, LoadDev L, double* cache,
                                                   int cmode) {
@@ -81,11 +83,8 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
   const int nloc = order == 2 ? 6 : 3, nu = 2 * nloc;
   double acc[MAX_EDOF_DEV];
   for (int r = 0; r < MAX_EDOF_DEV; ++r) acc[r] = 0.0;
-  if (cmode == 2) {
-    for (int r = 0; r < edof; ++r) acc[r] = cache[e * edof + r];
-  }
   // loads at the 7 quadrature points
-  for (int q = 0; q < (cmode == 2 ? 0 : 7); ++q) {
+  for (int q = 0; q < 7; ++q) {
     double l0, l1, l2, w;
     radon_point(q, l0, l1, l2, w);
     const double x = l0 * g.x[0] + l1 * g.x[1] + l2 * g.x[2];
@@ -107,8 +106,9 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
       for (int k = 0; k < 3; ++k) acc[nu + 6 + k] -= mp.tau * wa * z * lam[k];
     }
   }
-  if (cmode == 1)
-    for (int r = 0; r < edof; ++r) cache[e * edof + r] = acc[r];
+  double pload[3] = {0.0, 0.0, 0.0};  // load parts of the p rows
+  if (poro)
+    for (int k = 0; k < 3; ++k) pload[k] = acc[nu + 6 + k];
   const int32_t* ld = m.el_ldof + e * edof;
   if (poro) {
     const double* eta = eta_prev + m.soff[s];
@@ -133,12 +133,15 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
   }
   double* out = m.ebuf + e * edof;
   for (int r = 0; r < edof; ++r) out[r] = acc[r];
+  if (cmode == 1)
+    for (int r = 0; r < edof; ++r)
+      cache[e * edof + r] = poro && r >= nu + 6 && r < nu + 9 ? pload[r - nu - 6] : acc[r];
 }
 
-// The right-hand side from the cached load parts (cmode 2 of k_rhs_elem), one thread per
-// (element, row): row r of the element takes the same terms in the same order as there
-// (the eta moments on the p rows, then the lifting columns in order), with K_e read
-// from the stored element matrices.
+// The right-hand side from the cached parts (cmode 2 of k_rhs_elem), one thread per
+// (element, row): a row without eta terms is its cached value; a p row of a poroelastic
+// element takes its eta moments and then the lifting columns in order, as there, with
+// K_e read from the stored element matrices.
 __global__ void __launch_bounds__(256) k_rhs_rows(DevMesh m, const double* __restrict__ eta_prev, MatParams mpP,
                                                   MatParams mpE, LoadDev L, const double* __restrict__ cache) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -153,9 +156,13 @@ __global__ void __launch_bounds__(256) k_rhs_rows(DevMesh m, const double* __res
   const int32_t* ld = m.el_ldof + e * edof;
   double acc = cache[gid];
   const bool prow = poro && r >= nu + 6 && r < nu + 9;
+  if (!prow) {
+    m.ebuf[gid] = acc;
+    return;
+  }
   ElemGeom g;
-  if (prow || !m.emat) elem_geom(m.el_cell[e], m.el_type[e], ncell, g);
-  if (prow) {
+  elem_geom(m.el_cell[e], m.el_type[e], ncell, g);
+  {
     const double* eta = eta_prev + m.soff[s];
     const int k = r - (nu + 6);
     for (int b = 0; b < 3; ++b) acc -= moment2(g, k, b) * eta[ld[nu + 3 + b]];
@@ -284,7 +291,7 @@ void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams m
                        L, cache);
   } else {
     hipLaunchKernelGGL(k_rhs_elem, dim3((m.nelem + 127) / 128), dim3(128), 0, st, m, eta_prev, mpP, mpE, L,
-                       cache, cache ? cmode : 0);
+                       cache, cache && cmode == 1 ? 1 : 0);
   }
   hipLaunchKernelGGL(k_gather_elem, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, m, f);
 }
