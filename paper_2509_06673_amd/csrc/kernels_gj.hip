@@ -14,7 +14,10 @@
 // The O(n^3) part is the rank-kw update D -= C^T W with W = P^{-1} C, done on
 // v_mfma_f64_16x16x4 (FP64) or v_mfma_f32_16x16x4 (FP32) tiles: each 64x64
 // output tile is owned by one workgroup of four wavefronts, each computing a
-// 32x32 quarter as 2x2 MFMA blocks.  In the FP32 variant the small pivot
+// 32x32 quarter as 2x2 MFMA blocks.  The swept matrix stays symmetric, so only the
+// tiles on and below the diagonal are updated: every entry is read from the lower
+// triangle (row max(i, j), column min(i, j)), the panel rows and columns are written
+// on both sides, and the end result is mirrored once.  In the FP32 variant the small pivot
 // blocks are inverted and W is accumulated in FP64 before rounding to FP32;
 // the update runs in FP32 on the matrix cores.
 #include "kernels.h"
@@ -66,7 +69,7 @@ __global__ void __launch_bounds__(256) k_gj_pivot(const int32_t* __restrict__ ps
   __shared__ double colk[GJ_NB];
   for (int t = threadIdx.x; t < kw * kw; t += blockDim.x) {
     const int i = t / kw, j = t % kw;
-    M[i][j] = (double)Am[(int64_t)(k0 + i) * ld + k0 + j];
+    M[i][j] = (double)Am[(int64_t)(k0 + max(i, j)) * ld + k0 + min(i, j)];
   }
   __syncthreads();
   bool bad = false;
@@ -127,7 +130,8 @@ __global__ void __launch_bounds__(256) k_gj_row(const int32_t* __restrict__ psta
   const int ld = lda[m];
   double c[GJ_NB];
 #pragma unroll
-  for (int k = 0; k < GJ_NB; ++k) c[k] = k < kw ? (double)Am[(int64_t)(k0 + k) * ld + j] : 0.0;
+  for (int k = 0; k < GJ_NB; ++k)
+    c[k] = k < kw ? (double)Am[(int64_t)max(k0 + k, j) * ld + min(k0 + k, j)] : 0.0;
   T* W = wrow + (int64_t)m * nb * max_n;
   for (int i = 0; i < kw; ++i) {
     double s = 0.0;
@@ -137,11 +141,11 @@ __global__ void __launch_bounds__(256) k_gj_row(const int32_t* __restrict__ psta
   }
 }
 
-// (3) D -= C^T W outside the panel rows and columns (MFMA).  One workgroup per
-// 64-row strip of a matrix: the strip's panel block C[k][i0 + i] is staged in LDS
-// once, and the workgroup walks the 64-column tiles of the row, staging W[k][j0 + j]
-// and updating the 64x64 tile of A (four wavefronts, a 32x32 quarter each as 2x2
-// MFMA blocks).
+// (3) D -= C^T W outside the panel rows and columns (MFMA), on the tiles on and
+// below the diagonal.  One workgroup per 64-row strip of a matrix: the strip's panel
+// block C[k][i0 + i] is staged in LDS once, and the workgroup walks the 64-column
+// tiles j0 <= i0 of the row, staging W[k][j0 + j] and updating the 64x64 tile of A
+// (four wavefronts, a 32x32 quarter each as 2x2 MFMA blocks).
 template <class T>
 __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ pstart,
                                                    const int32_t* __restrict__ pwidth,
@@ -169,12 +173,12 @@ __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ p
   for (int t = threadIdx.x; t < kp * 64; t += blockDim.x) {
     const int k = t / 64, x = t % 64;
     const int i = i0 + x;
-    Ct[k][x] = (k < kw && i < n) ? Am[(int64_t)(k0 + k) * ld + i] : T(0);
+    Ct[k][x] = (k < kw && i < n) ? Am[(int64_t)max(k0 + k, i) * ld + min(k0 + k, i)] : T(0);
   }
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
   const int lr = lane % 16, lk = lane / 16;
-  for (int j0 = 0; j0 < n; j0 += 64) {
+  for (int j0 = 0; j0 <= i0; j0 += 64) {
     // column tiles fully inside the panel columns have nothing to update
     if (j0 >= k0 && j0 + 64 <= k0 + kw) continue;
     __syncthreads();  // Ct staged, or the previous Wt consumed
@@ -277,10 +281,11 @@ __global__ void k_gj_snapshot(const int32_t* __restrict__ pflag, const int64_t* 
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)nbm * nbm) return;
   const int i = (int)(t / nbm), j = (int)(t % nbm);
-  snap[snap_ofs[m] + (int64_t)i * snap_ld[m] + j] = A[aofs[m] + (int64_t)(at + i) * lda[m] + at + j];
+  snap[snap_ofs[m] + (int64_t)i * snap_ld[m] + j] = A[aofs[m] + (int64_t)(at + max(i, j)) * lda[m] + at + min(i, j)];
 }
 
-// K^+ = -(swept block), zero on the rows and columns that were not swept
+// K^+ = -(swept block), zero on the rows and columns that were not swept: the thread
+// of a lower entry (i >= j) writes it and its mirror
 template <class T>
 __global__ void k_gj_finalize(const int64_t* __restrict__ aofs, const int32_t* __restrict__ lda,
                               const int32_t* __restrict__ nn, const int32_t* __restrict__ nswept,
@@ -289,9 +294,12 @@ __global__ void k_gj_finalize(const int64_t* __restrict__ aofs, const int32_t* _
   const int n = nn[m], ns = nswept[m];
   const int i = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || j >= n) return;
-  T* a = A + aofs[m] + (int64_t)i * lda[m] + j;
-  *a = (i < ns && j < ns) ? -*a : T(0);
+  if (i >= n || j > i) return;
+  T* a = A + aofs[m];
+  const int64_t ld = lda[m];
+  const T v = (i < ns && j < ns) ? -a[(int64_t)i * ld + j] : T(0);
+  a[(int64_t)i * ld + j] = v;
+  if (j != i) a[(int64_t)j * ld + i] = v;
 }
 
 template <class T>
