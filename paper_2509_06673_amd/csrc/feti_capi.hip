@@ -1255,7 +1255,7 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, fet
     std::memcpy(key, &Lk, sizeof(LoadDev));
     std::memcpy(key + sizeof(LoadDev), &ctx->mpP, sizeof(MatParams));
     std::memcpy(key + sizeof(LoadDev) + sizeof(MatParams), &ctx->mpE, sizeof(MatParams));
-    if (!ctx->ecache) RC(dalloc(ctx, &ctx->ecache, (size_t)m.nelem * m.edof, ctx->allocs));
+    if (!ctx->ecache) RC(dalloc(ctx, &ctx->ecache, (size_t)m.nelem * (m.edof + 3), ctx->allocs));
     if (ctx->ecache_valid && std::memcmp(key, ctx->ekey, sizeof(key)) == 0) {
       cmode = 2;
     } else {

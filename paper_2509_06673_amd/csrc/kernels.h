@@ -58,9 +58,10 @@ struct DevMesh {
 
 // assembly / right-hand side (kernels_fem.hip)
 void launch_assemble(const DevMesh& m, double* K, MatParams mpP, MatParams mpE, hipStream_t st);
-// f = torn right-hand side (overwriting f); with cache (nelem x edof doubles), for loads
-// and Dirichlet data that do not depend on time: cmode 1 also stores there the parts of
-// the element rows that do not depend on the state, cmode 2 starts from them
+// f = torn right-hand side (overwriting f); with cache (nelem x (edof + 3) doubles), for
+// loads and Dirichlet data that do not depend on time: cmode 1 also stores there the
+// element contributions and the load parts of the p rows, cmode 2 rewrites only the p
+// rows and gathers from the cache
 void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams mpP, MatParams mpE,
                 const LoadDev& L, hipStream_t st, double* cache = nullptr, int cmode = 0);
 void launch_init_eta(const DevMesh& m, double* u, const LoadDev& L, hipStream_t st);

@@ -64,11 +64,11 @@ __device__ inline double dirichlet_value(const LoadDev& L, bool poro, int32_t co
 // One thread per element: the element's right-hand side contributions (rows 1 and 4
 // of eq. (linalg-system): F_u = (f, theta) and -R eta^{n-1} - tau Z on the p rows,
 // minus the Dirichlet lifting K_e[r, D] g_D) into ebuf[e][row].
-// cmode 1 (loads and Dirichlet data that do not depend on time): cache[e][row] also
-// receives the part of the row that does not depend on the state: the final value of a
-// row without eta terms (the load part minus the lifting), the load part of a p row of
-// a poroelastic element (whose eta terms come before the lifting); k_rhs_rows then
-// forms later steps from it with the same terms in the same order.
+// cmode 1 (loads and Dirichlet data that do not depend on time): cache (nelem x edof,
+// then nelem x 3) also receives the element contributions and the load parts of the p
+// rows of poroelastic elements (whose eta terms come before the lifting).  Rows without
+// eta terms do not change from step to step; k_rhs_prows forms the p rows of later
+// steps from their load parts with the same terms in the same order.
 __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __restrict__ eta_prev,
                                                   MatParams mpP, MatParams mpE, LoadDev L, double* cache,
                                                   int cmode) {
@@ -133,54 +133,47 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
   }
   double* out = m.ebuf + e * edof;
   for (int r = 0; r < edof; ++r) out[r] = acc[r];
-  if (cmode == 1)
-    for (int r = 0; r < edof; ++r)
-      cache[e * edof + r] = poro && r >= nu + 6 && r < nu + 9 ? pload[r - nu - 6] : acc[r];
+  if (cmode == 1) {
+    for (int r = 0; r < edof; ++r) cache[e * edof + r] = acc[r];
+    double* pl = cache + (int64_t)m.nelem * edof + e * 3;
+    for (int k = 0; k < 3; ++k) pl[k] = pload[k];
+  }
 }
 
-// The right-hand side from the cached parts (cmode 2 of k_rhs_elem), one thread per
-// (element, row): a row without eta terms is its cached value; a p row of a poroelastic
-// element takes its eta moments and then the lifting columns in order, as there, with
-// K_e read from the stored element matrices.
-__global__ void __launch_bounds__(256) k_rhs_rows(DevMesh m, const double* __restrict__ eta_prev, MatParams mpP,
-                                                  MatParams mpE, LoadDev L, const double* __restrict__ cache) {
+// A later step of a time-independent load (cmode 2): one thread per p row of every
+// element (elastic elements return at once) rewrites that row of the cached element
+// contributions from its load part: the eta moments, then the lifting columns in
+// order, as k_rhs_elem, with K_e read from the stored element matrices.
+__global__ void __launch_bounds__(256) k_rhs_prows(DevMesh m, const double* __restrict__ eta_prev, MatParams mpP,
+                                                   MatParams mpE, LoadDev L, double* __restrict__ cache) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int edof = m.edof;
-  const int64_t e = gid / edof;
-  const int r = (int)(gid % edof);
+  const int64_t e = gid / 3;
+  const int k = (int)(gid % 3);
   if (e >= m.nelem) return;
-  const int order = m.order, ncell = m.ncell;
   const int s = m.el_sub[e];
-  const bool poro = m.sub_poro[s] != 0;
+  if (m.sub_poro[s] == 0) return;
+  const int edof = m.edof, order = m.order, ncell = m.ncell;
   const int nloc = order == 2 ? 6 : 3, nu = 2 * nloc;
+  const int r = nu + 6 + k;
   const int32_t* ld = m.el_ldof + e * edof;
-  double acc = cache[gid];
-  const bool prow = poro && r >= nu + 6 && r < nu + 9;
-  if (!prow) {
-    m.ebuf[gid] = acc;
-    return;
-  }
+  double acc = cache[(int64_t)m.nelem * edof + e * 3 + k];
   ElemGeom g;
   elem_geom(m.el_cell[e], m.el_type[e], ncell, g);
-  {
-    const double* eta = eta_prev + m.soff[s];
-    const int k = r - (nu + 6);
-    for (int b = 0; b < 3; ++b) acc -= moment2(g, k, b) * eta[ld[nu + 3 + b]];
-  }
+  const double* eta = eta_prev + m.soff[s];
+  for (int b = 0; b < 3; ++b) acc -= moment2(g, k, b) * eta[ld[nu + 3 + b]];
   if (ld[r] >= 0) {
-    const MatParams& mp = poro ? mpP : mpE;
     const int umu = order * ncell + 1;
     const double uh = 1.0 / (order * ncell), h = 1.0 / ncell;
     for (int c = 0; c < edof; ++c) {
       if (ld[c] >= 0) continue;
       const int32_t code = m.el_code[e * edof + c];
       if (code < 0) continue;
-      const double gv = dirichlet_value(L, poro, code, umu, uh, ncell + 1, h);
+      const double gv = dirichlet_value(L, true, code, umu, uh, ncell + 1, h);
       if (gv == 0.0) continue;
-      acc -= (m.emat ? m.emat[(e * edof + c) * edof + r] : elem_entry(order, poro, g, mp, r, c)) * gv;
+      acc -= (m.emat ? m.emat[(e * edof + c) * edof + r] : elem_entry(order, true, g, mpP, r, c)) * gv;
     }
   }
-  m.ebuf[gid] = acc;
+  cache[e * edof + r] = acc;
 }
 
 // One thread per (element, row): ebuf[e][row] = (K_e x_e)[row]
@@ -286,13 +279,16 @@ void launch_assemble(const DevMesh& m, double* K, MatParams mpP, MatParams mpE, 
 void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams mpP, MatParams mpE,
                 const LoadDev& L, hipStream_t st, double* cache, int cmode) {
   if (cache && cmode == 2) {
-    const int64_t nthreads = (int64_t)m.nelem * m.edof;
-    hipLaunchKernelGGL(k_rhs_rows, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, m, eta_prev, mpP, mpE,
-                       L, cache);
-  } else {
-    hipLaunchKernelGGL(k_rhs_elem, dim3((m.nelem + 127) / 128), dim3(128), 0, st, m, eta_prev, mpP, mpE, L,
-                       cache, cache && cmode == 1 ? 1 : 0);
+    const int64_t nthreads = (int64_t)m.nelem * 3;
+    hipLaunchKernelGGL(k_rhs_prows, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, m, eta_prev, mpP,
+                       mpE, L, cache);
+    DevMesh mc = m;  // the gather reads the cached element contributions
+    mc.ebuf = cache;
+    hipLaunchKernelGGL(k_gather_elem, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, mc, f);
+    return;
   }
+  hipLaunchKernelGGL(k_rhs_elem, dim3((m.nelem + 127) / 128), dim3(128), 0, st, m, eta_prev, mpP, mpE, L, cache,
+                     cache && cmode == 1 ? 1 : 0);
   hipLaunchKernelGGL(k_gather_elem, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, m, f);
 }
 
