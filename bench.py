@@ -474,8 +474,14 @@ def run_variant(args, w, variant):
                              "of one solve"},
         "kernels": {
             "local_solve_sgemv": {"avg_ms": ls_ms, "GB/s": ls_bytes / (ls_ms * 1e-3) / 1e9},
+            # el_flops = sum_s n_s^3 (a symmetric inversion); each panel step of 32 pivots
+            # reads and writes the lower half of every matrix, n^2 / 2 entries twice, so
+            # the elimination moves sum_s n_s^3 esz / 32 bytes: 4 flop per byte in FP64,
+            # below the ridge point of the chip, so HBM bounds it
             "elimination": {"ms": el_ms, "TFLOP/s": el_flops / (el_ms * 1e-3) / 1e12,
-                            "frac_peak": el_flops / (el_ms * 1e-3) / 1e12 / peak},
+                            "frac_peak": el_flops / (el_ms * 1e-3) / 1e12 / peak,
+                            "GB/s": el_flops * esz / 32 / (el_ms * 1e-3) / 1e9,
+                            "frac_hbm": el_flops * esz / 32 / (el_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         },
     }
 
