@@ -198,7 +198,15 @@ __global__ void __launch_bounds__(256) k_sgemv(DevMesh m, GemvArgs a) {
       acc2 += (double)v[6] * xs[k + 6];
       acc3 += (double)v[7] * xs[k + 7];
     }
-    for (; k < ke; ++k, col += ld) acc0 += (double)col[0] * xs[k];
+    if (k < ke) {
+      // the last (ke - k < 8) columns: loads together, products in order
+      MT v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = k + u < ke ? col[(int64_t)u * ld] : (MT)0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k + u < ke) acc0 += (double)v[u] * xs[k + u];
+    }
   }
   red[wave * 64 + lane] = (acc0 + acc1) + (acc2 + acc3);
   __syncthreads();
