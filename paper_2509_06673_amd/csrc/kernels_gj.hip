@@ -234,8 +234,11 @@ __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ p
   }
 }
 
-// (4) write the swept panel: rows W, columns W^T, pivot block -P^{-1}; and
-// copy the trailing block at a snapshot step
+// (4) write the swept panel into the lower triangle: the panel rows W left of the panel,
+// the panel columns W^T below it, the pivot block -P^{-1}.  One workgroup per 64 columns
+// j0 .. j0 + 63 of a matrix: W[k][j0 + x] is staged in LDS (coalesced reads), then the
+// rows are written along j and the columns along k (32 consecutive entries of a row of
+// A per 32 threads).  The upper triangle is never read again.
 template <class T>
 __global__ void __launch_bounds__(256) k_gj_write(const int32_t* __restrict__ pstart,
                                                   const int32_t* __restrict__ pwidth,
@@ -251,20 +254,32 @@ __global__ void __launch_bounds__(256) k_gj_write(const int32_t* __restrict__ ps
   if (kw == 0) return;
   const int k0 = pstart[step * nmat + m];
   const int n = nn[m];
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  const int j0 = blockIdx.x * 64;
+  if (j0 >= n) return;
   T* Am = A + aofs[m];
-  const int ld = lda[m];
+  const int64_t ld = lda[m];
   const T* W = wrow + (int64_t)m * nb * max_n;
   const double* Pm = pinv + (int64_t)m * nb * nb;
-  if (j >= k0 && j < k0 + kw) {
-    for (int i = 0; i < kw; ++i) Am[(int64_t)(k0 + i) * ld + j] = (T)(-Pm[i * nb + (j - k0)]);
-  } else {
-    for (int i = 0; i < kw; ++i) {
-      const T v = W[(int64_t)i * max_n + j];
-      Am[(int64_t)(k0 + i) * ld + j] = v;
-      Am[(int64_t)j * ld + k0 + i] = v;
-    }
+  __shared__ T Ws[GJ_NB][65];
+  for (int t = threadIdx.x; t < kw * 64; t += blockDim.x) {
+    const int k = t / 64, x = t % 64;
+    const int j = j0 + x;
+    Ws[k][x] = (j < n && !(j >= k0 && j < k0 + kw)) ? W[(int64_t)k * max_n + j] : T(0);
+  }
+  __syncthreads();
+  // rows k0 + k, columns j < k0 (lower triangle): along j
+  for (int t = threadIdx.x; t < kw * 64; t += blockDim.x) {
+    const int k = t / 64, x = t % 64;
+    const int j = j0 + x;
+    if (j < n && j < k0) Am[(int64_t)(k0 + k) * ld + j] = Ws[k][x];
+  }
+  // columns k0 + k, rows j >= k0 + kw (lower triangle), and the pivot block: along k
+  for (int t = threadIdx.x; t < kw * 64; t += blockDim.x) {
+    const int x = t / kw, k = t % kw;
+    const int j = j0 + x;
+    if (j >= n) continue;
+    if (j >= k0 + kw) Am[(int64_t)j * ld + k0 + k] = Ws[k][x];
+    else if (j >= k0) Am[(int64_t)j * ld + k0 + k] = (T)(-Pm[(j - k0) * nb + k]);
   }
 }
 
@@ -312,7 +327,7 @@ void launch_gj_step(const GJPlan& p, T* A, T* snap, int step, bool snap_now, hip
   const int nt = (p.max_n + 63) / 64;
   hipLaunchKernelGGL(k_gj_update<T>, dim3(nt, p.nmat), dim3(256), 0, st, p.pstart, p.pwidth,
                      p.aofs, p.lda, p.n, A, wrow, p.nmat, step, p.nb, p.max_n);
-  hipLaunchKernelGGL(k_gj_write<T>, dim3((p.max_n + 255) / 256, p.nmat), dim3(256), 0, st, p.pstart,
+  hipLaunchKernelGGL(k_gj_write<T>, dim3((p.max_n + 63) / 64, p.nmat), dim3(256), 0, st, p.pstart,
                      p.pwidth, p.aofs, p.lda, p.n, A, p.pinv, wrow, p.nmat, step, p.nb, p.max_n);
   if (snap != nullptr && snap_now) {
     const int64_t cnt = (int64_t)p.max_n * p.max_n;
