@@ -850,7 +850,7 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
     stats->rho = corr;
     stats->status = rc;
     float ms = 0.f;
-    hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]);
+    (void)hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]);
     stats->t_ms[4] = ms;
   }
   return rc;
@@ -1299,9 +1299,9 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, fet
   if (stats) {
     stats->start_used = used;
     float ms = 0.f;
-    hipEventElapsedTime(&ms, ctx->ev[0], ctx->rec_ev[0][0]);  // right-hand side, up to the first solve
+    (void)hipEventElapsedTime(&ms, ctx->ev[0], ctx->rec_ev[0][0]);  // right-hand side, up to the first solve
     stats->t_ms[0] = ms;
-    hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[5]);
+    (void)hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[5]);
     stats->t_ms[5] = ms;
   }
   return rc;

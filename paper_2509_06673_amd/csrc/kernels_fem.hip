@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
 // contributions from its load part: the eta moments, then the lifting columns in
 // order, as k_rhs_elem, with K_e read from the stored element matrices.
 __global__ void __launch_bounds__(256) k_rhs_prows(DevMesh m, const double* __restrict__ eta_prev, MatParams mpP,
-                                                   MatParams mpE, LoadDev L, double* __restrict__ cache) {
+                                                   LoadDev L, double* __restrict__ cache) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t e = gid / 3;
   const int k = (int)(gid % 3);
@@ -280,8 +280,8 @@ void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams m
                 const LoadDev& L, hipStream_t st, double* cache, int cmode) {
   if (cache && cmode == 2) {
     const int64_t nthreads = (int64_t)m.nelem * 3;
-    hipLaunchKernelGGL(k_rhs_prows, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, m, eta_prev, mpP,
-                       mpE, L, cache);
+    hipLaunchKernelGGL(k_rhs_prows, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, m, eta_prev, mpP, L,
+                       cache);
     DevMesh mc = m;  // the gather reads the cached element contributions
     mc.ebuf = cache;
     hipLaunchKernelGGL(k_gather_elem, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, mc, f);

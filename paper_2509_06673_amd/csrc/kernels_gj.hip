@@ -304,7 +304,7 @@ __global__ void k_gj_snapshot(const int32_t* __restrict__ pflag, const int64_t* 
 template <class T>
 __global__ void k_gj_finalize(const int64_t* __restrict__ aofs, const int32_t* __restrict__ lda,
                               const int32_t* __restrict__ nn, const int32_t* __restrict__ nswept,
-                              T* __restrict__ A, int max_n) {
+                              T* __restrict__ A) {
   const int m = blockIdx.z;
   const int n = nn[m], ns = nswept[m];
   const int i = blockIdx.y;
@@ -340,7 +340,7 @@ void launch_gj_step(const GJPlan& p, T* A, T* snap, int step, bool snap_now, hip
 template <class T>
 void launch_gj_finalize(const GJPlan& p, T* A, const int32_t* nswept, hipStream_t st) {
   hipLaunchKernelGGL(k_gj_finalize<T>, dim3((p.max_n + 255) / 256, p.max_n, p.nmat), dim3(256), 0, st,
-                     p.aofs, p.lda, p.n, nswept, A, p.max_n);
+                     p.aofs, p.lda, p.n, nswept, A);
 }
 
 template void launch_gj_step<double>(const GJPlan&, double*, double*, int, bool, hipStream_t);

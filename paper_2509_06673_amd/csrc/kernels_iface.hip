@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(256) k_jump(DevMesh m, const double* __restric
   for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = acc[c];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
+    if ((int)threadIdx.x < w)
       for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
     __syncthreads();
   }
@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(256) k_coarse_g(DevMesh m, const double* __res
   for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = acc[c];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
+    if ((int)threadIdx.x < w)
       for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
     __syncthreads();
   }
@@ -520,7 +520,7 @@ __global__ void __launch_bounds__(256) k_kind_maxabs(DevMesh m, const double* __
   for (int c = 0; c < 12; ++c) red[c][threadIdx.x] = acc[c];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
+    if ((int)threadIdx.x < w)
       for (int c = 0; c < 12; ++c) red[c][threadIdx.x] = fmax(red[c][threadIdx.x], red[c][threadIdx.x + w]);
     __syncthreads();
   }
