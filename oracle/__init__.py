@@ -25,7 +25,10 @@ monolithic  global assembly of eq. (linalg-system), Dirichlet lifting,
             SuperLU, time stepping, L-infinity(L2) errors.
 indexing    an independent statement of the subdomain numbering and the
             signed Boolean jump maps used by the FETI path (bit-exact checks).
-dense       small dense references (Schur complements, Gauss-Jordan
-            inverses by a textbook formula) used by the unit tests.
-mlp         FP64 forward/backward of the warm-start MLP (gradient checks).
+local       the torn per-subdomain matrices and right-hand sides, and the
+            plain-definition references the unit tests compare with: the
+            interface Schur complement of eq. (reduced-system) and the
+            generalised inverse of a floating subdomain.
+mlp         FP64 forward/backward of the warm-start MLP (BF16 weights, the
+            specification's reference) and Adam, for the gradient checks.
 """

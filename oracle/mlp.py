@@ -2,11 +2,18 @@
 
 A three-layer perceptron  x -> h -> h -> out  with GELU activations (the erf
 form, GELU(z) = z Phi(z)), the mean squared error over all outputs of a batch,
-and Adam.  The GPU path keeps BF16 copies of the weights, rounds each layer's
-input and each backward product's output gradient to BF16, and accumulates in
-FP32; with bf=True the functions here round at exactly those points (each value
-goes to FP32 first, then to BF16 with round-to-nearest-even), so both agree up to
-the order and precision of accumulation.  Biases stay in full precision.
+and Adam.  The network is specified by BF16 weights and FP32 accumulation;
+its reference here is that specification taken literally:
+
+  bf="weights"  (the reference) the weight matrices are rounded to BF16 (through
+                FP32, round to nearest, ties to even); inputs, activations,
+                gradients and every sum stay in FP64.  Biases stay in full
+                precision.
+  bf=False      plain FP64 (finite-difference and closed-form pins).
+  bf=True       a diagnostic only: additionally rounds every layer input and each
+                backward product's output gradient to BF16, the points where one
+                possible kernel design stores them.  It is not a reference, since
+                those points are a design choice and not part of the specification.
 
 Parameter layout (flat): W1 [h, in], b1 [h], W2 [h, h], b2 [h], W3 [out, h], b3 [out].
 """
@@ -53,22 +60,36 @@ def pack(arrs):
     return np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in arrs])
 
 
-def forward(params, shapes, X, bf=False):
+def _rounders(bf):
+    """(weight rounding, activation / gradient rounding) of a mode."""
+    full = (lambda a: np.asarray(a, dtype=np.float64))
+    if bf == "weights":
+        return bf16, full
+    if bf is True:
+        return bf16, bf16
+    if bf is False:
+        return full, full
+    raise ValueError(f"unknown BF16 mode {bf!r}")
+
+
+def forward(params, shapes, X, bf="weights"):
     """Network output and the cached intermediate values."""
-    r = bf16 if bf else (lambda a: np.asarray(a, dtype=np.float64))
+    rw, r = _rounders(bf)
     W1, b1, W2, b2, W3, b3 = unpack(params, shapes)
     A0 = r(X)
-    Z1 = A0 @ r(W1).T + b1
+    Z1 = A0 @ rw(W1).T + b1
     A1 = r(gelu(Z1))
-    Z2 = A1 @ r(W2).T + b2
+    Z2 = A1 @ rw(W2).T + b2
     A2 = r(gelu(Z2))
-    Y = A2 @ r(W3).T + b3
+    Y = A2 @ rw(W3).T + b3
     return Y, (A0, Z1, A1, Z2, A2)
 
 
-def loss_grad(params, shapes, X, T, bf=False):
-    """Mean squared error sum((Y - T)^2) / Y.size and its gradient (flat, like params)."""
-    r = bf16 if bf else (lambda a: np.asarray(a, dtype=np.float64))
+def loss_grad(params, shapes, X, T, bf="weights"):
+    """Mean squared error sum((Y - T)^2) / Y.size and its gradient (flat, like params),
+    with respect to the master weights (the BF16 rounding is taken as identity in the
+    backward pass, as usual for low-precision weight copies)."""
+    rw, r = _rounders(bf)
     W1, b1, W2, b2, W3, b3 = unpack(params, shapes)
     Y, (A0, Z1, A1, Z2, A2) = forward(params, shapes, X, bf)
     D = Y - T
@@ -77,11 +98,11 @@ def loss_grad(params, shapes, X, T, bf=False):
     G3 = r(dY)
     dW3 = G3.T @ A2
     db3 = dY.sum(axis=0)
-    dZ2 = (G3 @ r(W3)) * gelu_grad(Z2)
+    dZ2 = (G3 @ rw(W3)) * gelu_grad(Z2)
     G2 = r(dZ2)
     dW2 = G2.T @ A1
     db2 = dZ2.sum(axis=0)
-    dZ1 = (G2 @ r(W2)) * gelu_grad(Z1)
+    dZ1 = (G2 @ rw(W2)) * gelu_grad(Z1)
     G1 = r(dZ1)
     dW1 = G1.T @ A0
     db1 = dZ1.sum(axis=0)

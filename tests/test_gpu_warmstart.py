@@ -1,13 +1,21 @@
 """Learned warm start: the network's kernels against the FP64 oracle, and what the
 trained network gains over the previous-step start.
 
-Tolerances.  The GPU path rounds weights, layer inputs and backward output
-gradients to BF16 at the same points as oracle/mlp.py with bf=True, so the two
-differ only by (a) FP32 instead of FP64 accumulation, about sqrt(K) * 6e-8 relative
-for K <= 16287 terms (< 1e-5), and (b) the rare BF16 rounding decisions that flip
-because the FP32 and FP64 pre-rounding values differ (each flip moves one value by
-one BF16 step, 2^-8 relative).  Normwise, per parameter block, both stay far
-below 2e-3, the bound used here.
+Reference.  The network is specified by BF16 weights and FP32 accumulation, so the
+reference is oracle/mlp.py with bf="weights": BF16-rounded weights, everything else in
+FP64.  The kernels also store the layer inputs (X, A1, A2) and the backward output
+gradients (G3, G2, G1) in BF16 for the matrix cores; these are design choices the
+specification does not fix, so the tolerance has to cover them.
+
+Tolerances.  Rounding a vector to BF16 (round to nearest) perturbs every entry by at
+most u = 2^-8 relative, hence normwise by at most u.  A layer with about unit gain
+passes such a perturbation on unchanged and adds its own, so the network output
+carries at most 3u (three forward rounding points) and the first layer's weight
+gradient at most 6u (three forward, three backward); every other block has fewer.
+FP32 accumulation adds about sqrt(K) 6e-8 <= 1e-5 for K <= 16287 terms.  The bounds
+used are TOL_FWD = 3u = 1.2e-2 and TOL_GRAD = 6u = 2.3e-2 (measured: about 3e-3 and
+5e-3).  The loss is a function of the output: |dL| / L <= 2 |dY| |Y - T| / |Y - T|^2
++ |dY|^2 / |Y - T|^2, evaluated with |dY| <= TOL_FWD |Y|.
 """
 import numpy as np
 import pytest
@@ -22,7 +30,9 @@ B = pytest.importorskip("paper_2509_06673_amd._binding")
 from paper_2509_06673_amd import warmstart as WS  # noqa: E402
 from paper_2509_06673_amd.workload import opts  # noqa: E402
 
-TOL = 2e-3
+U_BF16 = 2.0 ** -8
+TOL_FWD = 3 * U_BF16
+TOL_GRAD = 6 * U_BF16
 
 
 def _net(n_in, h, n_out, batch, seed):
@@ -53,18 +63,22 @@ def test_forward_and_gradient_match_oracle(dims):
     xd, td = torch.tensor(X, device="cuda"), torch.tensor(T, device="cuda")
     y = torch.empty((b, n_out), dtype=torch.float32, device="cuda")
     net.forward(xd, b, y)
-    Yref, _ = mlp.forward(p.astype(np.float64), shapes, X.astype(np.float64), bf=True)
+    Yref, _ = mlp.forward(p.astype(np.float64), shapes, X.astype(np.float64), bf="weights")
     ey = np.linalg.norm(y.cpu().numpy() - Yref) / np.linalg.norm(Yref)
     g = torch.empty(net.num_params(), dtype=torch.float32, device="cuda")
     loss = net.loss_grad(xd, td, b, g)
-    lref, gref = mlp.loss_grad(p.astype(np.float64), shapes, X.astype(np.float64), T.astype(np.float64), bf=True)
+    lref, gref = mlp.loss_grad(p.astype(np.float64), shapes, X.astype(np.float64), T.astype(np.float64),
+                               bf="weights")
+    dyn = TOL_FWD * np.linalg.norm(Yref)
+    ymt = np.linalg.norm(Yref - T.astype(np.float64))
+    tol_loss = 2 * dyn / ymt + (dyn / ymt) ** 2
     errs = [np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-300)
             for a, r in zip(_blocks(g.cpu().numpy().astype(np.float64), shapes), _blocks(gref, shapes))]
     print(f"  forward rel err {ey:.2e}, loss {loss:.6e} vs {lref:.6e}, grad block errs "
           + " ".join(f"{e:.1e}" for e in errs), flush=True)
-    assert ey < TOL
-    assert abs(loss - lref) <= TOL * lref
-    assert max(errs) < TOL
+    assert ey < TOL_FWD
+    assert abs(loss - lref) <= tol_loss * lref
+    assert max(errs) < TOL_GRAD
     net.close()
 
 
@@ -80,7 +94,7 @@ def test_adam_steps_match_oracle():
     pr, m, v = p.astype(np.float64), np.zeros(p.size), np.zeros(p.size)
     for k in range(1, 4):
         net.train_step(xd, td, b, lr)
-        _, gr = mlp.loss_grad(pr, shapes, X.astype(np.float64), T.astype(np.float64), bf=True)
+        _, gr = mlp.loss_grad(pr, shapes, X.astype(np.float64), T.astype(np.float64), bf="weights")
         pr, m, v = mlp.adam_step(pr, gr, m, v, k, lr)
     got = torch.empty(p.size, dtype=torch.float32, device="cuda")
     net.get_params(got)

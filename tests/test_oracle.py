@@ -290,3 +290,34 @@ def test_floating_subdomain_kernel_and_generalized_inverse():
         assert np.abs(K @ Kp @ K - K).max() < 1e-8 * np.abs(K).max()
         assert np.linalg.matrix_rank(K, tol=1e-9 * np.abs(K).max()) == len(s.codes) - 3
     assert nfloat == 4
+
+
+def test_schur_complement_inverse_is_the_interface_block_of_the_inverse():
+    # Block elimination of eq. (reduced-system): with K ordered [I | b], the inverse of the
+    # Schur complement S_bb = K_bb - K_bI K_II^{-1} K_Ib is the trailing b x b block of K^{-1}.
+    # For a floating subdomain K is singular; removing its fixed DOFs (which sit in b) leaves
+    # K_ss nonsingular, the same identity holds for the remaining interface set b', and the
+    # rigid-mode traces span the kernel of S_bb.  A swapped I / b index set or a transposed
+    # coupling block fails here.
+    w = W.nearly_incompressible_scaled(16, 4).replace(mat_p=W.Material(E=10.0, nu=0.3, c0=0.5, K=0.2),
+                                                       mat_e=W.Material(E=10.0, nu=0.3))
+    L = lo.build_local(w)
+    seen = {True: 0, False: 0}
+    for s, K in zip(L.spec.subs, L.K):
+        cats = np.asarray(s.cats)
+        b = np.nonzero(cats >= 2)[0]
+        S = lo.schur_bb(K, s.cats)
+        assert S.shape == (len(b), len(b))
+        assert np.abs(S - S.T).max() <= 1e-12 * np.abs(S).max()
+        keep = np.nonzero(cats != 4)[0]                 # all DOFs but the fixed ones
+        bk = np.nonzero(cats[b] != 4)[0]                # b' inside b
+        Kinv = np.linalg.inv(K[np.ix_(keep, keep)])
+        pos = {g: i for i, g in enumerate(keep)}
+        tail = Kinv[np.ix_([pos[g] for g in b[bk]], [pos[g] for g in b[bk]])]
+        Sinv = np.linalg.inv(S[np.ix_(bk, bk)])
+        assert np.abs(Sinv - tail).max() <= 1e-9 * np.abs(tail).max(), s.sid
+        if s.floating:
+            R = ix.rigid_modes(w, s)[b]
+            assert np.abs(S @ R).max() <= 1e-10 * np.abs(S).max() * np.abs(R).max()
+        seen[bool(s.floating)] += 1
+    assert seen[True] > 0 and seen[False] > 0

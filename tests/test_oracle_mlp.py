@@ -39,29 +39,57 @@ def _tiny(seed=3):
 
 def test_gradient_matches_central_differences():
     p, shapes, X, T = _tiny()
-    loss, g = mlp.loss_grad(p, shapes, X, T)
+    loss, g = mlp.loss_grad(p, shapes, X, T, bf=False)
     fd = np.empty_like(p)
     for i in range(len(p)):
         e = np.zeros_like(p)
         e[i] = 1e-6
-        fd[i] = (mlp.loss_grad(p + e, shapes, X, T)[0] - mlp.loss_grad(p - e, shapes, X, T)[0]) / 2e-6
+        fd[i] = (mlp.loss_grad(p + e, shapes, X, T, bf=False)[0]
+                 - mlp.loss_grad(p - e, shapes, X, T, bf=False)[0]) / 2e-6
     assert np.abs(fd - g).max() <= 1e-7 * max(1.0, np.abs(g).max())
 
 
 def test_loss_is_mean_squared_error_and_zero_at_the_target():
     p, shapes, X, _ = _tiny()
-    Y, _ = mlp.forward(p, shapes, X)
-    loss, g = mlp.loss_grad(p, shapes, X, Y)
-    assert loss == 0.0 and np.abs(g).max() == 0.0
-    loss2, _ = mlp.loss_grad(p, shapes, X, Y + 0.5)
-    assert abs(loss2 - 0.25) < 1e-15
+    for mode in (False, "weights"):
+        Y, _ = mlp.forward(p, shapes, X, bf=mode)
+        loss, g = mlp.loss_grad(p, shapes, X, Y, bf=mode)
+        assert loss == 0.0 and np.abs(g).max() == 0.0
+        loss2, _ = mlp.loss_grad(p, shapes, X, Y + 0.5, bf=mode)
+        assert abs(loss2 - 0.25) < 1e-15
+
+
+def test_weights_mode_is_fp64_on_bf16_weights():
+    # the specification's reference: BF16 weights, everything else exact.  On weights that
+    # already lie on the BF16 grid it is the FP64 network; biases are never rounded.
+    p, shapes, X, T = _tiny()
+    blocks = mlp.unpack(p, shapes)
+    on_grid = mlp.pack([mlp.bf16(a) if i % 2 == 0 else a for i, a in enumerate(blocks)])
+    Yw, _ = mlp.forward(p, shapes, X, bf="weights")
+    Y0, _ = mlp.forward(on_grid, shapes, X, bf=False)
+    assert np.array_equal(Yw, Y0)
+    lw, gw = mlp.loss_grad(p, shapes, X, T, bf="weights")
+    l0, g0 = mlp.loss_grad(on_grid, shapes, X, T, bf=False)
+    assert lw == l0 and np.array_equal(gw, g0)
+    # off the grid the weights move by at most 2^-8 relative, and so does a linear layer
+    Yf, _ = mlp.forward(p, shapes, X, bf=False)
+    assert 0.0 < np.abs(Yw - Yf).max() < 0.05 * np.abs(Yf).max()
+    # the activation-rounding diagnostic differs from the reference
+    Yb, _ = mlp.forward(p, shapes, X, bf=True)
+    assert not np.array_equal(Yb, Yw)
+    try:
+        mlp.forward(p, shapes, X, bf="bogus")
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("unknown mode accepted")
 
 
 def test_bf16_mode_rounds_weights_and_layer_inputs():
     # with weights and inputs already on the BF16 grid and a linear-regime network the
     # two modes agree to the rounding of the hidden activations
     p, shapes, X, T = _tiny()
-    Y, _ = mlp.forward(p, shapes, X)
+    Y, _ = mlp.forward(p, shapes, X, bf=False)
     Yb, _ = mlp.forward(p, shapes, X, bf=True)
     assert np.abs(Y - Yb).max() < 0.05 * np.abs(Y).max()
     pb, Xb = mlp.bf16(p), mlp.bf16(X)
