@@ -229,13 +229,46 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* opts,
  * caller-given torn right-hand side (device, sum n_s doubles).  lambda_dev
  * (N_lambda doubles) is the start on input when opts->start is
  * FETI_START_GIVEN and the solution on output; u_dev receives the torn primal
- * solution. */
+ * solution.  The time-stepping state (eta^n, the multiplier history and the
+ * right-hand side returned by feti_get_rhs) is left as it was, so solves may be
+ * interleaved with steps; feti_get_solution still returns the last step's. */
 int feti_solve(feti_ctx ctx, const double* f_dev, double* lambda_dev, double* u_dev,
                const feti_solve_opts* opts, feti_stats* stats);
 
 /* Copy the torn primal solution of the last step (sum n_s doubles) and the
  * multipliers (N_lambda doubles) to device buffers; either may be NULL. */
 int feti_get_solution(feti_ctx ctx, double* u_dev, double* lambda_dev);
+
+/* ---- checkpoint / resume and field export ------------------------------------ */
+
+/* The backward-Euler scheme of Section 2.5 carries eta^n from one step to the next
+ * (row 4 of eq. (linalg-system) reads eta^{n-1}); the solver also carries the
+ * multipliers lambda^n, lambda^{n-1} of the last two steps (starts of the interface
+ * iteration) and the last step's total refinement correction.  The state is a flat
+ * device vector of feti_state_size() doubles:
+ *   [ torn primal solution of the last step (sum n_s; its eta entries are eta^n)
+ *   | lambda^n (N_lambda) | lambda^{n-1} (N_lambda) | total correction (N_lambda) ]
+ * and four host integers meta = {steps taken, have lambda^n, have lambda^{n-1},
+ * have a correction}.  feti_set_state on a context built with the same mesh,
+ * materials and time step continues the trajectory bit for bit: steps 1..10 equal
+ * steps 1..5, get_state, set_state (on a fresh context) and steps 6..10.  Both
+ * synchronise the context stream.  set_state returns FETI_EINVAL on flags that
+ * are not 0/1 or on lambda^{n-1} without lambda^n. */
+int feti_state_size(feti_ctx ctx, int64_t* n_doubles_host);
+int feti_get_state(feti_ctx ctx, double* state_dev, int64_t* meta_host);
+int feti_set_state(feti_ctx ctx, const double* state_dev, const int64_t* meta_host);
+
+/* Fields of the last step on their global lattice (outputs u_h^n, xi_h^n, eta_h^n,
+ * p_h^n of eq. (linalg-system)): field = DOF kind (FETI_FIELD_UX, UY on the
+ * displacement lattice of spacing h/k, (u_lattice)^2 doubles; ETA, XI_P, P, XI_E on
+ * the P1 lattice of spacing h, (n1)^2 doubles; sizes [8] and [7] of feti_get_sizes).
+ * A node shared by several subdomains takes the value of the lowest-numbered one
+ * (the copies agree to the interface tolerance); nodes that carry no unknown of the
+ * field (Dirichlet nodes, nodes outside the field's region) are set to 0.
+ * out_dev: device, caller-owned.  Synchronises the context stream. */
+enum { FETI_FIELD_UX = 0, FETI_FIELD_UY = 1, FETI_FIELD_ETA = 2, FETI_FIELD_XI_P = 3, FETI_FIELD_P = 4,
+       FETI_FIELD_XI_E = 5 };
+int feti_get_field(feti_ctx ctx, int32_t field, double* out_dev);
 
 /* Set the multiplier start of the next step (used with FETI_START_GIVEN and
  * FETI_START_BEST). */

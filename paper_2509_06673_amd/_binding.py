@@ -26,6 +26,7 @@ CORR_ZERO, CORR_PREVIOUS = 0, 1
 PCG_AUTO, PCG_GRAPH = 0, 1
 EXPORT_K, EXPORT_SBB, EXPORT_KPLUS = 0, 1, 2
 KERNEL_LOCAL_SOLVE, KERNEL_IFACE_GEMV, KERNEL_PRECOND_GEMV, KERNEL_ELIMINATION = 0, 1, 2, 3
+FIELD_UX, FIELD_UY, FIELD_ETA, FIELD_XI_P, FIELD_P, FIELD_XI_E = 0, 1, 2, 3, 4, 5
 
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM", EHIP: "EHIP",
                 ESINGULAR: "ESINGULAR", ENOTCONV: "ENOTCONV", EBREAKDOWN: "EBREAKDOWN",
@@ -93,6 +94,10 @@ _SIGS = {
                    C.POINTER(Stats)],
     "feti_get_solution": [C.c_void_p, C.c_void_p, C.c_void_p],
     "feti_set_start": [C.c_void_p, C.c_void_p],
+    "feti_state_size": [C.c_void_p, C.POINTER(C.c_int64)],
+    "feti_get_state": [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)],
+    "feti_set_state": [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)],
+    "feti_get_field": [C.c_void_p, C.c_int32, C.c_void_p],
     "feti_export_local": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p],
     "feti_apply_F": [C.c_void_p, C.c_void_p, C.c_void_p],
     "feti_apply_precond": [C.c_void_p, C.c_void_p, C.c_void_p],
@@ -258,6 +263,24 @@ class Feti:
 
     def set_start(self, lam):
         return self._check(self.lib.feti_set_start(self.ctx, _ptr(lam)), "feti_set_start")
+
+    def state_size(self) -> int:
+        n = C.c_int64()
+        self._check(self.lib.feti_state_size(self.ctx, C.byref(n)), "feti_state_size")
+        return n.value
+
+    def get_state(self, state):
+        """Copies the checkpoint state into the device buffer state; returns the 4 flags."""
+        meta = (C.c_int64 * 4)()
+        self._check(self.lib.feti_get_state(self.ctx, _ptr(state), meta), "feti_get_state")
+        return list(meta)
+
+    def set_state(self, state, meta):
+        m = (C.c_int64 * 4)(*[int(v) for v in meta])
+        return self._check(self.lib.feti_set_state(self.ctx, _ptr(state), m), "feti_set_state")
+
+    def get_field(self, field: int, out):
+        return self._check(self.lib.feti_get_field(self.ctx, int(field), _ptr(out)), "feti_get_field")
 
     def set_pcg_mode(self, mode: int):
         return self._check(self.lib.feti_set_pcg_mode(self.ctx, int(mode)), "feti_set_pcg_mode")

@@ -67,6 +67,7 @@ struct feti_ctx_s {
   double *f = nullptr, *u = nullptr, *ytmp = nullptr, *yb = nullptr, *zb = nullptr;
   double *rf = nullptr, *du = nullptr, *dlam = nullptr, *cj = nullptr, *kpart = nullptr;
   double *dlam_sum = nullptr, *dlam_prev = nullptr;  // corrections of this and of the previous step
+  double *u_save = nullptr, *f_save = nullptr;        // time-stepping state kept across feti_solve
   bool have_dlam_prev = false;
   int pcg_mode = FETI_PCG_AUTO;
   double* mdiag = nullptr;  // diagonal of the preconditioner (weights of the dual-energy norm)
@@ -86,7 +87,7 @@ struct feti_ctx_s {
   int32_t* h_rec_ist = nullptr;  // NREC x IS_COUNT (pinned)
   double* h_rec_sc = nullptr;    // NREC x SC_COUNT (pinned)
   hipEvent_t rec_ev[NREC][4] = {};
-  int32_t* d_pick = nullptr;     // device-side start choice of the last candidate comparison
+  int32_t* d_pick = nullptr;     // device-side start choices: [0] first correction, [1] first solve
   int32_t* h_pick = nullptr;     // (pinned copy)
   double* h_sc = nullptr;
   int64_t nstep = 0;
@@ -212,6 +213,19 @@ int upload_mesh(feti_ctx ctx) {
   RC(upload(ctx, &m.sub_poro, poro));
   RC(upload(ctx, &m.sub_float, sfl));
   RC(upload(ctx, &m.code, code));
+  {
+    // first occurrence of every code in torn (subdomain-major) order
+    std::vector<uint8_t> first(h.sum_ns, 0);
+    std::vector<int32_t> sorted(code);
+    std::sort(sorted.begin(), sorted.end());
+    sorted.erase(std::unique(sorted.begin(), sorted.end()), sorted.end());
+    std::vector<uint8_t> seen(sorted.size(), 0);
+    for (int64_t i = 0; i < h.sum_ns; ++i) {
+      const size_t k = std::lower_bound(sorted.begin(), sorted.end(), code[i]) - sorted.begin();
+      if (!seen[k]) { seen[k] = 1; first[i] = 1; }
+    }
+    RC(upload(ctx, &m.first, first));
+  }
   RC(upload(ctx, &m.rfull, h.rfull));
   RC(upload(ctx, &m.el_sub, h.el_sub));
   RC(upload(ctx, &m.el_cell, h.el_cell));
@@ -245,13 +259,15 @@ int upload_mesh(feti_ctx ctx) {
   RC(dalloc(ctx, &ctx->zb, h.sum_nb, ctx->allocs));
   RC(dalloc(ctx, &ctx->rf, h.sum_ns, ctx->allocs));
   RC(dalloc(ctx, &ctx->du, h.sum_ns, ctx->allocs));
+  RC(dalloc(ctx, &ctx->u_save, h.sum_ns, ctx->allocs));
+  RC(dalloc(ctx, &ctx->f_save, h.sum_ns, ctx->allocs));
   RC(dalloc(ctx, &ctx->dlam, h.n_lambda, ctx->allocs));
   RC(dalloc(ctx, &ctx->dlam_sum, h.n_lambda, ctx->allocs));
   RC(dalloc(ctx, &ctx->dlam_prev, h.n_lambda, ctx->allocs));
   RC(dalloc(ctx, &ctx->cj, h.n_lambda, ctx->allocs));
   RC(dalloc(ctx, &ctx->mdiag, h.n_lambda, ctx->allocs));
   RC(dalloc(ctx, &ctx->kpart, (size_t)KMAX_NBLK * 12, ctx->allocs));
-  RC(dalloc(ctx, &ctx->d_pick, 1, ctx->allocs));
+  RC(dalloc(ctx, &ctx->d_pick, 2, ctx->allocs));
   double** lv[] = {&ctx->lam, &ctx->lam_prev, &ctx->lam_prev2, &ctx->d, &ctx->r, &ctx->w,
                    &ctx->z, &ctx->y, &ctx->p, &ctx->q, &ctx->qraw, &ctx->tl, &ctx->lam_given, &ctx->lam_alt,
                    &ctx->r_alt, &ctx->w_alt};
@@ -301,7 +317,7 @@ int upload_mesh(feti_ctx ctx) {
     HIPCHK(hipHostMalloc((void**)&ctx->h_kpart, KMAX_NBLK * 12 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&ctx->h_rec_ist, feti_ctx_s::NREC * IS_COUNT * sizeof(int32_t), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&ctx->h_rec_sc, feti_ctx_s::NREC * SC_COUNT * sizeof(double), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&ctx->h_pick, sizeof(int32_t), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&ctx->h_pick, 2 * sizeof(int32_t), hipHostMallocDefault));
     for (auto& r : ctx->rec_ev)
       for (auto& e : r)
         if (!e) HIPCHK(hipEventCreate(&e));
@@ -453,13 +469,12 @@ int start_residual(feti_ctx ctx, const double* lam, double* norm, int slot = -1)
   return FETI_OK;
 }
 
-// First half of a torn solve (no host synchronisation unless a candidate start is
-// compared): d = sum_s B_s K_s^+ f_s - c, the admissible start, the scalar state,
-// the reference norms of P d, and r, w, y, p with rho = (w, y).
-// took_cand == nullptr with a candidate: the choice is made on the device (no
-// synchronisation, the caller does not learn it).
+// First half of a torn solve (no host synchronisation): d = sum_s B_s K_s^+ f_s - c,
+// the admissible start, the scalar state, the reference norms of P d, and r, w, y, p
+// with rho = (w, y).  With a candidate start the choice between it and lam is made on
+// the device; pick_flag (device, may be null) receives 1 if the candidate was taken.
 int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, const double* f, const double* cj,
-               double* lam, const double* cand = nullptr, int* took_cand = nullptr) {
+               double* lam, const double* cand = nullptr, int32_t* pick_flag = nullptr) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
   const int64_t nl = m.n_lambda;
@@ -485,8 +500,8 @@ int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
     launch_coarse_correct(m, ctx->ac, 1.0, v, v, nullptr, st);
   };
   admissible(lam);
-  if (took_cand) *took_cand = 0;
-  if (ctx->H && !took_cand) {
+  int32_t* flag = pick_flag ? pick_flag : ctx->d_pick;
+  if (ctx->H) {
     static_assert(HPROJ_NC_MAX >= PCG_NC_LOCAL, "H exists for every coarse size the projection kernel takes");
     // with H: a projection is one pass after G^T v (P v = v - H G^T v), and a compared
     // candidate keeps its r and w.  G^T r is summed from r itself: at a warm start r is
@@ -511,7 +526,7 @@ int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
       launch_reduce(m, nullptr, nullptr, ctx->w_alt, ctx->mdiag, ctx->part, counter(ctx, PH_REFNORM), ctx->sc,
                     ctx->ist, PH_REFNORM, st);
       launch_copy_scalar(ctx->sc, SC_EREF, SC_SEL1, st);
-      launch_pick_start(nl, ctx->sc, ctx->lam_alt, lam, ctx->d_pick, st, ctx->r_alt, ctx->r, ctx->w_alt, ctx->w);
+      launch_pick_start(nl, ctx->sc, ctx->lam_alt, lam, flag, st, ctx->r_alt, ctx->r, ctx->w_alt, ctx->w);
     }
     // tolerance reference: per-kind norms of P d
     launch_init_scalars(ctx->sc, ctx->ist, tol, utol, std::max(o->max_it, 0), st);
@@ -530,19 +545,9 @@ int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
     // keep the candidate start if its projected residual is smaller
     launch_axpby(nl, 1.0, cand, 0.0, nullptr, ctx->lam_alt, st);
     admissible(ctx->lam_alt);
-    if (!took_cand) {
-      RC(start_residual(ctx, lam, nullptr, SC_SEL0));
-      RC(start_residual(ctx, ctx->lam_alt, nullptr, SC_SEL1));
-      launch_pick_start(nl, ctx->sc, ctx->lam_alt, lam, ctx->d_pick, st);
-    } else {
-      double n_lam = 0.0, n_alt = 0.0;
-      RC(start_residual(ctx, lam, &n_lam));
-      RC(start_residual(ctx, ctx->lam_alt, &n_alt));
-      if (n_alt < n_lam) {
-        launch_axpby(nl, 1.0, ctx->lam_alt, 0.0, nullptr, lam, st);
-        *took_cand = 1;
-      }
-    }
+    RC(start_residual(ctx, lam, nullptr, SC_SEL0));
+    RC(start_residual(ctx, ctx->lam_alt, nullptr, SC_SEL1));
+    launch_pick_start(nl, ctx->sc, ctx->lam_alt, lam, flag, st);
   }
   // tolerance reference: per-kind norms of P d
   launch_init_scalars(ctx->sc, ctx->ist, tol, utol, std::max(o->max_it, 0), st);
@@ -586,12 +591,12 @@ int torn_end(feti_ctx ctx, const double* lam, double* u) {
 // record slot (read by finish_solve once the stream has been synchronised).  Returns
 // only launch failures.
 int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, const double* f, const double* cj,
-               double* lam, double* u, int slot, const double* cand = nullptr, int* took_cand = nullptr) {
+               double* lam, double* u, int slot, const double* cand = nullptr, int32_t* pick_flag = nullptr) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
   hipEvent_t* ev = ctx->rec_ev[slot];
   HIPCHK(hipEventRecord(ev[0], st));
-  RC(torn_begin(ctx, o, tol, utol, f, cj, lam, cand, took_cand));
+  RC(torn_begin(ctx, o, tol, utol, f, cj, lam, cand, pick_flag));
   HIPCHK(hipEventRecord(ev[1], st));
   const int32_t* done = ctx->ist + IS_DONE;
   const int chunk = std::max(1, o->check_every);
@@ -766,7 +771,9 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
   int nrec = 0, nfin = 0, rc = FETI_OK, hard = FETI_OK, last = FETI_OK, iters = 0, iters_first = 0, done_ir = 0;
   double res0 = 0, res = 0, r0c = 0, rc_ = 0, corr = 0.0;
   int it_corr[feti_ctx_s::NREC] = {0};
-  RC(solve_torn(ctx, o, tol_first, 0.0, ctx->f, nullptr, ctx->lam, ctx->u, nrec++, cand, took_cand));
+  // the first solve's start choice goes to d_pick[1] (d_pick[0] serves the corrections)
+  RC(solve_torn(ctx, o, tol_first, 0.0, ctx->f, nullptr, ctx->lam, ctx->u, nrec++, cand, ctx->d_pick + 1));
+  if (cand) HIPCHK(hipMemcpyAsync(ctx->h_pick + 1, ctx->d_pick + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   // outcome of every enqueued solve not read yet (after a synchronisation)
   auto finish = [&]() {
     for (; nfin < nrec; ++nfin) {
@@ -833,6 +840,7 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
   finish();
+  if (took_cand) *took_cand = cand ? ctx->h_pick[1] : 0;
   if (done_ir > 0) corr = correction_size();
   if (history) {
     // the step's total correction, for the next step
@@ -1311,8 +1319,14 @@ int feti_solve(feti_ctx ctx, const double* f_dev, double* lambda_dev, double* u_
                const feti_solve_opts* o, feti_stats* stats) {
   if (!ctx || !f_dev || !o) return FETI_EINVAL;
   if (ctx->state < 3) return fail(ctx, FETI_ESTATE, "solve before factor_subdomains");
+  if (!(o->tol > 0.0) || o->max_it < 1 || o->corr_start < FETI_CORR_ZERO || o->corr_start > FETI_CORR_PREVIOUS)
+    return fail(ctx, FETI_EINVAL, "bad solve options");
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
+  // the time-stepping state (eta^n inside u, the prepared right-hand side) survives the
+  // solve: the solve works in the context's vectors and restores them afterwards
+  HIPCHK(hipMemcpyAsync(ctx->u_save, ctx->u, m.sum_ns * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->f_save, ctx->f, m.sum_ns * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipEventRecord(ctx->ev[0], st));
   HIPCHK(hipMemcpyAsync(ctx->f, f_dev, m.sum_ns * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (o->start == FETI_START_GIVEN && lambda_dev)
@@ -1324,6 +1338,8 @@ int feti_solve(feti_ctx ctx, const double* f_dev, double* lambda_dev, double* u_
   if (lambda_dev)
     HIPCHK(hipMemcpyAsync(lambda_dev, ctx->lam, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (u_dev) HIPCHK(hipMemcpyAsync(u_dev, ctx->u, m.sum_ns * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->u, ctx->u_save, m.sum_ns * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->f, ctx->f_save, m.sum_ns * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   return rc;
 }
@@ -1344,6 +1360,72 @@ int feti_set_start(feti_ctx ctx, const double* lambda_dev) {
   if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "set_start before assemble");
   HIPCHK(hipMemcpyAsync(ctx->lam_given, lambda_dev, ctx->dm.n_lambda * sizeof(double), hipMemcpyDeviceToDevice,
                         ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FETI_OK;
+}
+
+int feti_state_size(feti_ctx ctx, int64_t* n_doubles) {
+  if (!ctx || !n_doubles) return FETI_EINVAL;
+  if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "state_size before assemble");
+  *n_doubles = ctx->dm.sum_ns + 3 * ctx->dm.n_lambda;
+  return FETI_OK;
+}
+
+int feti_get_state(feti_ctx ctx, double* state_dev, int64_t* meta) {
+  if (!ctx || !state_dev || !meta) return FETI_EINVAL;
+  if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "get_state before assemble");
+  const DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  double* o = state_dev;
+  HIPCHK(hipMemcpyAsync(o, ctx->u, m.sum_ns * sizeof(double), hipMemcpyDeviceToDevice, st));
+  o += m.sum_ns;
+  HIPCHK(hipMemcpyAsync(o, ctx->lam_prev, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
+  o += m.n_lambda;
+  HIPCHK(hipMemcpyAsync(o, ctx->lam_prev2, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
+  o += m.n_lambda;
+  HIPCHK(hipMemcpyAsync(o, ctx->dlam_prev, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  meta[0] = ctx->nstep;
+  meta[1] = ctx->have_prev ? 1 : 0;
+  meta[2] = ctx->have_prev2 ? 1 : 0;
+  meta[3] = ctx->have_dlam_prev ? 1 : 0;
+  return FETI_OK;
+}
+
+int feti_set_state(feti_ctx ctx, const double* state_dev, const int64_t* meta) {
+  if (!ctx || !state_dev || !meta) return FETI_EINVAL;
+  if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "set_state before assemble");
+  if (meta[0] < 0 || meta[1] < 0 || meta[1] > 1 || meta[2] < 0 || meta[2] > 1 || meta[3] < 0 || meta[3] > 1 ||
+      (meta[2] && !meta[1]))
+    return fail(ctx, FETI_EINVAL, "inconsistent state flags");
+  const DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  const double* i = state_dev;
+  HIPCHK(hipMemcpyAsync(ctx->u, i, m.sum_ns * sizeof(double), hipMemcpyDeviceToDevice, st));
+  i += m.sum_ns;
+  HIPCHK(hipMemcpyAsync(ctx->lam_prev, i, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
+  i += m.n_lambda;
+  HIPCHK(hipMemcpyAsync(ctx->lam_prev2, i, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
+  i += m.n_lambda;
+  HIPCHK(hipMemcpyAsync(ctx->dlam_prev, i, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  ctx->nstep = meta[0];
+  ctx->have_prev = meta[1] != 0;
+  ctx->have_prev2 = meta[2] != 0;
+  ctx->have_dlam_prev = meta[3] != 0;
+  return FETI_OK;
+}
+
+int feti_get_field(feti_ctx ctx, int32_t field, double* out_dev) {
+  if (!ctx || !out_dev) return FETI_EINVAL;
+  if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "get_field before assemble");
+  if (field < FETI_FIELD_UX || field > FETI_FIELD_XI_E) return fail(ctx, FETI_EINVAL, "unknown field");
+  const DevMesh& m = ctx->dm;
+  const MeshHost& h = ctx->mh;
+  const int64_t nlat = field <= FETI_FIELD_UY ? (int64_t)h.mu * h.mu : (int64_t)h.n1 * h.n1;
+  launch_zero(nlat, out_dev, ctx->stream);
+  launch_field_scatter(m, ctx->u, field, out_dev, ctx->stream);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return FETI_OK;
 }

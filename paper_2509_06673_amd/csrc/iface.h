@@ -35,6 +35,8 @@ void launch_sgemv(const DevMesh& m, const GemvArgs& a, hipStream_t st);
 // else zero)
 void launch_init_scalars(double* sc, int32_t* ist, double tol, double utol, int maxit, hipStream_t st);
 void launch_zero(int64_t n, double* z, hipStream_t st);
+// out[node] = x at the first torn DOF of every code of the given kind
+void launch_field_scatter(const DevMesh& m, const double* x, int kind, double* out, hipStream_t st);
 // sc[dst] = sc[src]
 void launch_copy_scalar(double* sc, int src, int dst, hipStream_t st);
 // lam = alt where sc[SC_SEL1] < sc[SC_SEL0] (the candidate's residual is the smaller)

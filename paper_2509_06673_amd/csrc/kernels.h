@@ -30,6 +30,7 @@ struct DevMesh {
   int32_t* sub_float = nullptr; // index in the coarse space or -1
   // per local DOF (torn)
   int32_t* code = nullptr;
+  uint8_t* first = nullptr;     // 1 at the first torn DOF (lowest subdomain) of each code
   double* rfull = nullptr;      // 3 per DOF
   // elements
   int32_t *el_sub = nullptr, *el_cell = nullptr, *el_type = nullptr, *el_ldof = nullptr,

@@ -741,6 +741,20 @@ template void launch_copy_block<float, float>(int, int, const int64_t*, const in
                                               const float*, float*, hipStream_t);
 
 // dst = (float) src, n elements
+// out[node] = x at the first torn DOF (lowest subdomain) of each code of kind `kind`
+__global__ void k_field_scatter(int64_t n, const int32_t* __restrict__ code, const uint8_t* __restrict__ first,
+                                const double* __restrict__ x, int kind, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !first[i]) return;
+  const int32_t c = code[i];
+  if ((c & 7) == kind) out[c >> 3] = x[i];
+}
+
+void launch_field_scatter(const DevMesh& m, const double* x, int kind, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_field_scatter, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, m.sum_ns, m.code,
+                     m.first, x, kind, out);
+}
+
 __global__ void k_to_f32(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = (float)src[i];

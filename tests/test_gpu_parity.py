@@ -215,11 +215,12 @@ _FULL_ORACLE = {}
 @pytest.mark.parametrize("start", [B.START_PREVIOUS, B.START_EXTRAPOLATE], ids=["previous", "extrapolated"])
 def test_full_size_workload_matches_oracle(start):
     """The 64-subdomain h = 1/128 workload, as bench.py runs it (first solves from the
-    previous step's multipliers, or from their extrapolation), against the oracle."""
+    previous step's multipliers, or from their extrapolation), against the oracle at
+    every step of the bench's horizon (5 warm-up and 20 timed steps)."""
     import time
     import torch
     w = W.nearly_incompressible_large()
-    nsteps = 4
+    nsteps = 25
     if not _FULL_ORACLE:
         t0 = time.time()
         print("[full] oracle ...", flush=True)
