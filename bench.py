@@ -27,6 +27,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
+# pivots per panel step of the batched elimination: every panel step reads and writes
+# the lower half of every matrix, so the sweep moves sum_s n_s^3 w / GJ_PANEL bytes
+GJ_PANEL = 32
 
 # HBM bytes per PCG iteration of the persistent interface kernel (FP64 variant), from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, summed over the kernel's dispatches and
@@ -185,8 +188,13 @@ def learned_start_run(args):
           file=sys.stderr, flush=True)
     held = W.learned_start_case(args.ws_eval_seed, nsteps=200)
     res = {}
-    for m in ("previous", "extrapolate", "learned"):
-        res[m] = WS.evaluate(held, net, 200, m)
+    # FP64 factors with the three starts, and the growth patterns combined: FP32 factors
+    # with FP64 refinement and the learned start ("mixed_learned"), against plain FP64
+    # with the paper's previous-step start
+    for m, prec in (("previous", B.FP64), ("extrapolate", B.FP64), ("learned", B.FP64),
+                    ("mixed_learned", B.FP32_IR)):
+        mode = "learned" if m == "mixed_learned" else m
+        res[m] = WS.evaluate(held, net, 200, mode, precision=prec)
         print(f"[learned] {m}: first-solve iters {res[m]['mean_iters_first']:.2f}, iters {res[m]['mean_iters']:.2f}, "
               f"{res[m]['mean_ms']:.2f} ms/step", file=sys.stderr, flush=True)
     net.close()
@@ -204,6 +212,13 @@ def learned_start_run(args):
                        "learned_start_kept": r["used_learned"]} for m, r in res.items()},
         "training": {"data_s": t_data, "train_s": hist["seconds"], "adam_steps": hist["steps"],
                      "loss_first_epoch": hist["loss"][0], "loss_last_epoch": hist["loss"][-1]},
+        "mixed_learned_vs_plain_fp64": {
+            "steps_per_s_ratio": res["previous"]["mean_ms"] / res["mixed_learned"]["mean_ms"],
+            "iters_ratio": res["mixed_learned"]["mean_iters"] / res["previous"]["mean_iters"],
+            "note": "mixed_learned: FP32 factors on the matrix cores, FP64 refinement and the learned "
+                    "start; plain FP64: FP64 factors and the previous-step start; same held-out "
+                    "trajectory, both to the 1e-10 interface tolerance with the refinement of their "
+                    "precision"},
         "start_error": {"prediction": lr_["mean_err_pred"], "previous_step": lr_["mean_err_prev"],
                         "extrapolation": lr_["mean_err_extrap"],
                         "note": "mean |start - solved multipliers| / |solved multipliers| on the held-out steps"},
@@ -301,7 +316,9 @@ def cpu_baseline(w, nsteps=3):
     return {"value": 1.0 / step, "unit": "time steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{w.name}: assembly + SuperLU factorisation + {nsteps} steps "
                       f"(setup {t_setup:.1f} s, {step:.2f} s/step); value is the steady-state "
-                      f"rate, amortised over {w.nsteps} steps {amort:.3f} steps/s",
+                      f"rate, amortised over {w.nsteps} steps {amort:.3f} steps/s; each step is "
+                      f"one LU solve plus two refinement solves with the residual in extended "
+                      f"precision, so a plain one-solve FP64 step would be about 3x faster",
             "amortised": amort}
 
 
@@ -369,10 +386,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "variant": variants[0], **prim["sizes"], "tol": w.tol},
         "pcg_iters_mean": prim["pcg_iters_mean"],
+        "torn_residual_max": prim["torn_residual_max"],
         "roofline": prim["roofline"],
         "variants": {v: {k: r[k] for k in ("value", "ms_per_step", "amortised_steps_per_s", "setup_s",
                                           "pcg_iters_mean", "pcg_iters_first_solve", "refinement_corrections",
-                                          "pcg_us_per_iteration", "pcg_iters_all_steps", "kernels", "dtype")}
+                                          "pcg_us_per_iteration", "pcg_iters_all_steps", "kernels", "dtype",
+                                          "torn_residual_max", "torn_residual_per_step",
+                                          "replay_matches_timed_run")}
                      for v, r in res.items()},
     }
     if args.calibrate_copy_mb > 0:
@@ -390,13 +410,12 @@ def main():
 
 
 def pcg_bytes_per_iteration(sub_nb, n_lambda, nc, esz):
-    """Algorithmic HBM bytes of one iteration of the interface PCG: the interface
-    blocks of F and of the preconditioner read once each, H = G (G^T G)^{-1} read by
-    the two projections, the interface-space products written and read once each, and
-    about twenty multiplier-vector passes."""
+    """Algorithmic bytes of one interface PCG iteration: the interface blocks of F
+    ((K_s^+)_bb) and of the preconditioner (S_bb) read once each, the dense coarse
+    inverse (G^T G)^{-1} read by each of the two projections, and about twelve passes
+    over FP64 multiplier vectors:  sum_s 2 n_b,s^2 w + 2 n_c^2 8 + 12 N_lambda 8."""
     blocks = sum(int(n) * int(n) for n in sub_nb) * esz
-    sum_nb = sum(int(n) for n in sub_nb)
-    return 2 * blocks + 2 * nc * n_lambda * 8 + 4 * sum_nb * 8 + 20 * n_lambda * 8
+    return 2 * blocks + 2 * nc * nc * 8 + 12 * n_lambda * 8
 
 
 def run_variant(args, w, variant):
@@ -422,6 +441,10 @@ def run_variant(args, w, variant):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     f.init_state(load(w, 0.0))
+    # checkpoint of the initial state: the trajectory is replayed from it after the
+    # timed run, with the torn-system residual evaluated after every step
+    state0 = torch.empty(f.state_size(), dtype=torch.float64, device="cuda")
+    meta0 = f.get_state(state0)
     mk = opts_mixed if mixed else opts
     start = B.START_EXTRAPOLATE if variant == "fp64x" else B.START_PREVIOUS
     o = mk(tol=w.tol, max_it=2000, start=start, check_every=args.check_every)
@@ -443,6 +466,16 @@ def run_variant(args, w, variant):
         pcg_ms.append(st["t_ms"][2])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - ta
+    # untimed replay of the same (deterministic) trajectory from the checkpoint: the FP64
+    # residual of the torn system after every step, and the iteration counts, which must
+    # equal those of the timed run
+    f.set_state(state0, meta0)
+    rho, replay_iters = [], []
+    for k in range(1, n + 1):
+        st = f.step(load(w, k * w.tau), o)
+        replay_iters.append(st["iters"])
+        rho.append(f.torn_residual())
+    same = replay_iters == warm_iters + iters
     setup_s = (t1 - t0) + (t2 - t1)
     value = args.steps / elapsed
     esz = 4 if mixed else 8
@@ -463,6 +496,8 @@ def run_variant(args, w, variant):
         "pcg_iters_mean": float(np.mean(iters)), "pcg_iters_first_solve": iters_first,
         "pcg_iters_all_steps": warm_iters + iters,
         "refinement_corrections": ir_steps,
+        "torn_residual_per_step": rho, "torn_residual_max": max(rho),
+        "replay_matches_timed_run": same,
         "pcg_us_per_iteration": 1e6 * pcg_s / max(1, sum(iters)),
         "roofline": {"bound": "hbm", "kernel": "k_pcg_persistent (interface PCG, one launch per solve)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -474,14 +509,17 @@ def run_variant(args, w, variant):
                              "of one solve"},
         "kernels": {
             "local_solve_sgemv": {"avg_ms": ls_ms, "GB/s": ls_bytes / (ls_ms * 1e-3) / 1e9},
-            # el_flops = sum_s n_s^3 (a symmetric inversion); each panel step of 32 pivots
-            # reads and writes the lower half of every matrix, n^2 / 2 entries twice, so
-            # the elimination moves sum_s n_s^3 esz / 32 bytes: 4 flop per byte in FP64,
-            # below the ridge point of the chip, so HBM bounds it
-            "elimination": {"ms": el_ms, "TFLOP/s": el_flops / (el_ms * 1e-3) / 1e12,
-                            "frac_peak": el_flops / (el_ms * 1e-3) / 1e12 / peak,
-                            "GB/s": el_flops * esz / 32 / (el_ms * 1e-3) / 1e9,
-                            "frac_hbm": el_flops * esz / 32 / (el_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            # el_ms: the elimination kernels only (between events around them).  The sweep
+            # computes the explicit inverse, sum_s n_s^3 flops; a factorisation is
+            # sum_s n_s^3 / 3, the unit the roofline is quoted in ("factorization")
+            "elimination": {"ms": el_ms,
+                            "flops_factorization": el_flops / 3.0, "flops_inversion": el_flops,
+                            "TFLOP/s_factorization": el_flops / 3.0 / (el_ms * 1e-3) / 1e12,
+                            "frac_peak_factorization": el_flops / 3.0 / (el_ms * 1e-3) / 1e12 / peak,
+                            "TFLOP/s_inversion": el_flops / (el_ms * 1e-3) / 1e12,
+                            "frac_peak_inversion": el_flops / (el_ms * 1e-3) / 1e12 / peak,
+                            "panel_bytes": el_flops * esz / GJ_PANEL,
+                            "frac_hbm": el_flops * esz / GJ_PANEL / (el_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         },
     }
 

@@ -59,7 +59,7 @@ enum {
 enum { FETI_XSPLIT = 0, FETI_YSPLIT = 1, FETI_CORE = 2 };
 /* load kinds of feti_load */
 enum { FETI_LOAD_MANUFACTURED = 0, FETI_LOAD_PERIODIC = 1, FETI_LOAD_POINT_SOURCE = 2,
-       FETI_LOAD_PATCH = 3 };
+       FETI_LOAD_PATCH = 3, FETI_LOAD_RAW = 4 };
 /* precision of the subdomain factors: FP64, or FP32 elimination on the matrix
  * cores with FP32 storage of K_s^+, S_bb and the interface block, the FP64 torn
  * residual and FP64 interface vectors, dot products and coarse problem winning
@@ -77,7 +77,7 @@ enum { FETI_START_PREVIOUS = 0, FETI_START_ZERO = 1, FETI_START_EXTRAPOLATE = 2,
 
 /* Mesh and decomposition (Section 2.4 spaces on a structured right-triangle
  * mesh of the unit square; subdomains are an nsub_x x nsub_y grid of cell
- * blocks with cuts at floor(a * ncell / nsub_x)). */
+ * blocks with cuts at floor(a * ncell / nsub_x), or at the caller's cuts). */
 typedef struct {
     int32_t ncell;        /* cells per side, h = 1/ncell */
     int32_t order_u;      /* k of P_k for the displacement: 1 or 2 */
@@ -85,6 +85,12 @@ typedef struct {
     int32_t nsub_x, nsub_y;
     uint32_t dirichlet_u; /* bit 0: x=0, 1: x=1, 2: y=0, 3: y=1 -- sides with u Dirichlet */
     uint32_t dirichlet_p; /* sides with p Dirichlet (where the poroelastic region touches them) */
+    const int32_t* cut_x; /* host, nsub_x + 1 cell indices 0 = c_0 < c_1 < ... < c_nsub_x = ncell
+                             (subdomain column a covers cells [c_a, c_a+1)); NULL = even cuts.
+                             Read during feti_setup_mesh only.  FETI_EINVAL if not strictly
+                             increasing from 0 to ncell, or if a subdomain straddles the
+                             interface of the layout. */
+    const int32_t* cut_y; /* the same for the rows */
 } feti_mesh_desc;
 
 /* Parameters of Table 2 for one region; lame_mode 0: mu = E/(2(1+nu)),
@@ -105,6 +111,26 @@ typedef struct {
     int32_t kind;
     double t;
     double params[16];
+    /* FETI_LOAD_RAW: the caller's data of the step at time t, on the lattices (device
+     * pointers, caller-owned, read during the call; NULL = zero data).  They enter as
+     * the nodal interpolants in the finite element spaces:
+     *   F_u = (f_h, theta) + <t_h, theta> on the sides without u Dirichlet data
+     *         (eqs. (vf1), (vf4); the traction of BCTR / BCTRE),
+     *   Z   = (z_h, phi) + <z_w,h, phi> on the poroelastic edges of the sides without p
+     *         Dirichlet data (eq. (vf3); the flux of BCFR, entering with the sign of the
+     *         weak form),
+     * Dirichlet values g_u, g_p at the Dirichlet nodes, and eta^0 (feti_init_state).
+     * mu = k ncell + 1 displacement lattice points per side, n1 = ncell + 1; lattices
+     * row-major with x fastest; sides 0: x = 0, 1: x = 1, 2: y = 0, 3: y = 1, indexed
+     * along the side by the lattice y index (x = const) or x index (y = const). */
+    const double* f_p;     /* [2][mu*mu] body force used on poroelastic elements */
+    const double* f_e;     /* [2][mu*mu] body force used on elastic elements */
+    const double* z;       /* [n1*n1] fluid source */
+    const double* t_side;  /* [2][4][2][mu] traction [region 0 P / 1 E][side][component][along] */
+    const double* zw_side; /* [4][n1] flux data [side][along] */
+    const double* g_u;     /* [2][mu*mu] displacement Dirichlet values */
+    const double* g_p;     /* [n1*n1] pressure Dirichlet values */
+    const double* eta0;    /* [n1*n1] initial fluid content (read by feti_init_state) */
 } feti_load;
 
 enum { FETI_CORR_ZERO = 0, FETI_CORR_PREVIOUS = 1 };
@@ -238,6 +264,14 @@ int feti_solve(feti_ctx ctx, const double* f_dev, double* lambda_dev, double* u_
 /* Copy the torn primal solution of the last step (sum n_s doubles) and the
  * multipliers (N_lambda doubles) to device buffers; either may be NULL. */
 int feti_get_solution(feti_ctx ctx, double* u_dev, double* lambda_dev);
+
+/* Relative FP64 residual of the torn system of the last step (eq. (feti-system): the
+ * local equations K_s u_s + B_s^T lambda = f_s and the gluing sum_s B_s u_s = 0):
+ *   rho = |[f - K u - B^T lambda ; -B u]|_2 / |f|_2   (|...|_2 over all subdomains),
+ * for the step's (u, lambda^n) as returned by feti_get_solution.  It is an a-posteriori
+ * check of a solve, evaluated element by element in FP64; it leaves the step state as it
+ * was.  *rho_host: host.  FETI_ESTATE before the first step.  Synchronises. */
+int feti_torn_residual(feti_ctx ctx, double* rho_host);
 
 /* ---- checkpoint / resume and field export ------------------------------------ */
 

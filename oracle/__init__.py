@@ -17,12 +17,15 @@ solves the same system monolithically with a sparse direct factorisation
 Modules
 -------
 fem         P1/P2 Lagrange elements, the 7-point degree-5 quadrature rule,
-            element matrices of the forms (aD), (bD), (af) and the L2 mass.
+            element matrices of the forms (aD), (bD), (af), the L2 mass and
+            the closed-form edge masses of the boundary terms.
 mesh        structured right-triangle mesh of the unit square and regions.
 problem     material constants (Section 2.2 kappas, Table 3 Lame formulas)
             and closed-form loads derived symbolically from eqs. (2.1)-(2.3).
 monolithic  global assembly of eq. (linalg-system), Dirichlet lifting,
-            SuperLU, time stepping, L-infinity(L2) errors.
+            SuperLU, time stepping, L-infinity(L2) errors; loads given as
+            nodal data (body force, source, traction and flux on boundary
+            edges, eqs. (vf1), (vf3), (vf4)) through element and edge masses.
 indexing    an independent statement of the subdomain numbering and the
             signed Boolean jump maps used by the FETI path (bit-exact checks).
 local       the torn per-subdomain matrices and right-hand sides, and the

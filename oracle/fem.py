@@ -136,6 +136,25 @@ def element_matrices(order_u, X, mu, K_over_muf):
     return dict(A=A, B=B, R=R, Af=Af)
 
 
+def mass(order, X):
+    """(phi_j, phi_i) of the P1 or P2 basis on triangles X (E, nb, nb), 7-point rule
+    (exact: the integrand has degree <= 4).  With nodal coefficients c of an
+    interpolant, mass @ c is its load vector (f_h, phi_i)."""
+    L, w = radon7()
+    area, _ = geometry(X)
+    v = basis(order, L)
+    return np.einsum('eq,qi,qj->eij', w[None, :] * area[:, None], v, v)
+
+
+def edge_mass(order, length):
+    """(psi_j, psi_i) over a straight edge of the given length for the traces of the P1
+    or P2 basis on it, node order (end a, end b) or (end a, end b, midpoint).  Closed
+    form: with s in [0, 1], psi_a = (1-s)(1-2s), psi_b = s(2s-1), psi_m = 4s(1-s)."""
+    if order == 1:
+        return length / 6.0 * np.array([[2.0, 1.0], [1.0, 2.0]])
+    return length / 30.0 * np.array([[4.0, -1.0, 2.0], [-1.0, 4.0, 2.0], [2.0, 2.0, 16.0]])
+
+
 def load_vectors(order_u, X, fx, fy, z, t):
     """Consistent load vectors on triangles X with the 7-point rule.
 

@@ -16,7 +16,8 @@ multipliers, chaining the subdomains in increasing id order.
 Numbering
 ---------
 * Subdomain s = b*nsub_x + a covers cells [cx[a], cx[a+1]) x [cy[b], cy[b+1])
-  with cx[a] = floor(a * ncell / nsub_x) (same for y).  Every subdomain lies in
+  with cx[a] = floor(a * ncell / nsub_x) (same for y), or the workload's own cuts
+  (Workload.cut_x / cut_y) when it gives them.  Every subdomain lies in
   one physics region.
 * DOF kinds: 0 ux, 1 uy, 2 eta, 3 xi_P, 4 p, 5 xi_E.  A DOF is identified by
   code = 8 * lattice_node + kind (displacement lattice for kinds 0, 1, the P1
@@ -103,8 +104,7 @@ def build(w: Workload) -> IndexSpec:
     ratio = 1 if k == 1 else 2
     nu = ratio * n              # max displacement lattice index
     mu = nu + 1
-    cx = [(a * n) // w.nsub_x for a in range(w.nsub_x + 1)]
-    cy = [(b * n) // w.nsub_y for b in range(w.nsub_y + 1)]
+    cx, cy = w.cuts()
     subs = []
     owners = {}   # code -> list of subdomain ids
     local_sets = []
@@ -187,8 +187,7 @@ def closed_form_n_lambda(w: Workload) -> int:
     from node multiplicities on the cut lines (no subdomain lists needed).
     """
     n, r = w.ncell, (1 if w.order_u == 1 else 2)
-    cx = [(a * n) // w.nsub_x for a in range(w.nsub_x + 1)]
-    cy = [(b * n) // w.nsub_y for b in range(w.nsub_y + 1)]
+    cx, cy = w.cuts()
     cutx = set(cx[1:-1])
     cuty = set(cy[1:-1])
 

@@ -29,9 +29,9 @@ import numpy as np
 import scipy.sparse as sps
 import scipy.sparse.linalg as spla
 
-from workloads import Workload, XSPLIT, YSPLIT, CORE
+from workloads import Workload, XSPLIT, YSPLIT, CORE, RAW, raw_arrays
 from .mesh import Mesh
-from .fem import element_matrices, load_vectors, interpolate_l2_error
+from .fem import element_matrices, load_vectors, interpolate_l2_error, mass, edge_mass
 from .problem import lame, kappas, make_loads
 
 
@@ -113,7 +113,72 @@ class MonolithicSystem:
         self.free = np.nonzero(~dmask)[0]
         self.dir = np.nonzero(dmask)[0]
         self._assemble()
+        self._boundary_edges()
         self.t_assemble = time.perf_counter() - t0
+
+    # ------------------------------------------------------------------
+    def _boundary_edges(self):
+        """Edges of the mesh on the four sides of the square (side 0: x = 0, 1: x = 1,
+        2: y = 0, 3: y = 1): triangle, side, the P1 end nodes and the displacement
+        nodes (ends, then the midpoint for P2)."""
+        m = self.mesh
+        n = m.n
+        tri, side, p1n, pun = [], [], [], []
+        for k, (a, b) in enumerate(((0, 1), (1, 2), (2, 0))):
+            via, vib = m.tri_vi[:, a], m.tri_vi[:, b]
+            vja, vjb = m.tri_vj[:, a], m.tri_vj[:, b]
+            for sd, hit in enumerate(((via == 0) & (vib == 0), (via == n) & (vib == n),
+                                      (vja == 0) & (vjb == 0), (vja == n) & (vjb == n))):
+                for e in np.nonzero(hit)[0]:
+                    tri.append(e)
+                    side.append(sd)
+                    p1n.append((m.p1[e, a], m.p1[e, b]))
+                    if m.order_u == 1:
+                        pun.append((m.pu[e, a], m.pu[e, b]))
+                    else:
+                        pun.append((m.pu[e, a], m.pu[e, b], m.pu[e, 3 + k]))
+        self.bedge_tri = np.array(tri, dtype=np.int64)
+        self.bedge_side = np.array(side, dtype=np.int64)
+        self.bedge_p1 = np.array(p1n, dtype=np.int64).reshape(-1, 2)
+        self.bedge_pu = np.array(pun, dtype=np.int64).reshape(-1, 2 if m.order_u == 1 else 3)
+
+    def _raw_loads(self, t: float):
+        """Load vectors of a RAW load at time t (caller data on the lattices, taken as
+        the nodal interpolants in the finite element spaces):
+          F_u = (f_h, theta_i) + <t_h, theta_i> on the sides without u Dirichlet data,
+          Z   = (z_h, phi_i) + <z_w,h, phi_i> on the poroelastic edges of the sides without
+                p Dirichlet data,
+        the boundary terms of eqs. (vf1), (vf3), (vf4).  Returns (f over the u blocks, Z
+        over the p nodes)."""
+        w, m, b = self.w, self.mesh, self.blocks
+        o = b.offsets
+        raw = raw_arrays(w, t)
+        f = np.zeros(self.ndof)
+        for tri, ud, key in ((self.triP, self._udP, 'f_p'), (self.triE, self._udE, 'f_e')):
+            M = mass(w.order_u, m.X[tri])
+            nodes = m.pu[tri]
+            blk = o['uP'] if key == 'f_p' else o['uE']
+            for c in range(2):
+                Fc = np.einsum('eij,ej->ei', M, raw[key][c][nodes])
+                np.add.at(f, blk + ud[:, c::2].ravel(), Fc.ravel())
+        Z = np.zeros(b.sizes['p'])
+        R = mass(1, m.X[self.triP])
+        np.add.at(Z, self._sidxP.ravel(), np.einsum('eij,ej->ei', R, raw['z'][m.p1[self.triP]]).ravel())
+        h = m.h
+        Mu = edge_mass(w.order_u, h)
+        M1 = edge_mass(1, h)
+        for e, sd, pn, un in zip(self.bedge_tri, self.bedge_side, self.bedge_p1, self.bedge_pu):
+            poro = bool(m.tri_poro[e])
+            along_u = (un // m.mu) if sd < 2 else (un % m.mu)
+            along_1 = (pn // (m.n + 1)) if sd < 2 else (pn % (m.n + 1))
+            if not (w.dirichlet_u >> sd) & 1:
+                mp = self.mapuP if poro else self.mapuE
+                blk = o['uP'] if poro else o['uE']
+                for c in range(2):
+                    np.add.at(f, blk + 2 * mp[un] + c, Mu @ raw['t_side'][0 if poro else 1, sd, c, along_u])
+            if poro and not (w.dirichlet_p >> sd) & 1:
+                np.add.at(Z, self.mapsP[pn], M1 @ raw['zw_side'][sd, along_1])
+        return f, Z
 
     # ------------------------------------------------------------------
     def _assemble(self):
@@ -181,6 +246,10 @@ class MonolithicSystem:
         """Full right-hand side of eq. (linalg-system) at time t (all DOFs)."""
         w, m, b, L = self.w, self.mesh, self.blocks, self.loads
         o = b.offsets
+        if w.load.kind == RAW:
+            f, Z = self._raw_loads(t)
+            f[o['p']:o['p'] + b.sizes['p']] = -(self.RP.T @ eta_prev) - w.tau * Z
+            return f
         f = np.zeros(self.ndof)
         FuP, ZP = load_vectors(w.order_u, m.X[self.triP], L.fPx, L.fPy, L.z, t)
         np.add.at(f, o['uP'] + self._udP.ravel(), FuP.ravel())
@@ -196,6 +265,14 @@ class MonolithicSystem:
         """Nodal Dirichlet values at time t for every Dirichlet DOF."""
         b, m, L = self.blocks, self.mesh, self.loads
         vals = np.zeros(self.ndof)
+        if self.w.load.kind == RAW:
+            raw = raw_arrays(self.w, t)
+            for nm in ('uP', 'uE'):
+                o, n = b.offsets[nm], b.sizes[nm]
+                vals[o:o + n] = raw['g_u'][b.comp[nm], b.node[nm]]
+            o, n = b.offsets['p'], b.sizes['p']
+            vals[o:o + n] = raw['g_p'][b.node['p']]
+            return vals[self.dir]
         for nm, fx, fy in (('uP', L.u0x_P if L.uPx is None else L.uPx,
                             L.u0y_P if L.uPy is None else L.uPy),
                            ('uE', L.u0x_E if L.uEx is None else L.uEx,
@@ -221,6 +298,8 @@ class MonolithicSystem:
         which is the discretely consistent start for a stationary solution.
         """
         b, m, L = self.blocks, self.mesh, self.loads
+        if self.w.load.kind == RAW:
+            return raw_arrays(self.w, 0.0)['eta0'][b.node['eta']].copy()
         if mode == "interp":
             xy = m.p1_xy(b.node['eta'])
             return L.eta0(xy[:, 0], xy[:, 1], 0.0)

@@ -24,7 +24,7 @@ import numpy as np
 import sympy as sp
 
 from workloads import (Material, Load, Workload, XSPLIT, YSPLIT, CORE,
-                       MANUFACTURED, PERIODIC, POINT_SOURCE, PATCH,
+                       MANUFACTURED, PERIODIC, POINT_SOURCE, PATCH, RAW,
                        PATCH_UX, PATCH_UY, PATCH_P)
 
 
@@ -171,4 +171,7 @@ def make_loads(w: Workload) -> Loads:
             return math.sin(t) * np.exp(-r2 / (2 * sg * sg)) / (2 * np.pi * sg * sg)
         return Loads(fPx=_zero, fPy=_zero, fEx=_zero, fEy=_zero, z=z,
                      u0x_P=_zero, u0y_P=_zero, u0x_E=_zero, u0y_E=_zero, p0=_zero, eta0=_zero)
+    if L.kind == RAW:
+        # the data are nodal arrays (workloads.raw_arrays); the assembly reads them directly
+        return Loads(fPx=_zero, fPy=_zero, fEx=_zero, fEy=_zero, z=_zero)
     raise ValueError(L.kind)

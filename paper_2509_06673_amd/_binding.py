@@ -8,8 +8,10 @@ raises an error rather than falling back to anything else.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from typing import Dict, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -18,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libfeti.so")
 # status codes
 OK, EINVAL, ESTATE, ENOMEM, EHIP, ESINGULAR, ENOTCONV, EBREAKDOWN, ENAN = 0, -1, -2, -3, -4, -5, -6, -7, -8
 XSPLIT, YSPLIT, CORE = 0, 1, 2
-LOAD_MANUFACTURED, LOAD_PERIODIC, LOAD_POINT_SOURCE, LOAD_PATCH = 0, 1, 2, 3
+LOAD_MANUFACTURED, LOAD_PERIODIC, LOAD_POINT_SOURCE, LOAD_PATCH, LOAD_RAW = 0, 1, 2, 3, 4
 FP64, FP32_IR = 0, 1
 PRECOND_DIRICHLET, PRECOND_LUMPED, PRECOND_NONE = 0, 1, 2
 START_PREVIOUS, START_ZERO, START_EXTRAPOLATE, START_GIVEN, START_BEST = 0, 1, 2, 3, 4
@@ -36,7 +38,7 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM", 
 class MeshDesc(C.Structure):
     _fields_ = [("ncell", C.c_int32), ("order_u", C.c_int32), ("layout", C.c_int32),
                 ("nsub_x", C.c_int32), ("nsub_y", C.c_int32), ("dirichlet_u", C.c_uint32),
-                ("dirichlet_p", C.c_uint32)]
+                ("dirichlet_p", C.c_uint32), ("cut_x", C.POINTER(C.c_int32)), ("cut_y", C.POINTER(C.c_int32))]
 
 
 class Material(C.Structure):
@@ -45,7 +47,19 @@ class Material(C.Structure):
 
 
 class Load(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("t", C.c_double), ("params", C.c_double * 16)]
+    _fields_ = [("kind", C.c_int32), ("t", C.c_double), ("params", C.c_double * 16),
+                ("f_p", C.c_void_p), ("f_e", C.c_void_p), ("z", C.c_void_p), ("t_side", C.c_void_p),
+                ("zw_side", C.c_void_p), ("g_u", C.c_void_p), ("g_p", C.c_void_p), ("eta0", C.c_void_p)]
+
+    RAW_FIELDS = ("f_p", "f_e", "z", "t_side", "zw_side", "g_u", "g_p", "eta0")
+
+    def attach_raw(self, arrays):
+        """RAW data: device tensors (float64, contiguous) by field name; the tensors are
+        kept alive with this struct."""
+        self._raw_keep = dict(arrays)
+        for name in self.RAW_FIELDS:
+            t = arrays.get(name)
+            setattr(self, name, None if t is None else t.data_ptr())
 
 
 class SolveOpts(C.Structure):
@@ -78,6 +92,23 @@ class FetiError(RuntimeError):
 
 _lib: Optional[C.CDLL] = None
 
+# Live handles, released in dependency order (batches, networks, contexts) by an exit hook
+# that runs before the interpreter and the HIP runtime are torn down, so that no handle is
+# left to a finaliser that might run after the runtime is gone.
+_LIVE = {"batch": weakref.WeakSet(), "net": weakref.WeakSet(), "ctx": weakref.WeakSet()}
+
+
+def _release_all():
+    for kind in ("batch", "net", "ctx"):
+        for obj in list(_LIVE[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
+atexit.register(_release_all)
+
 _SIGS = {
     "feti_create": [C.POINTER(C.c_void_p), C.c_void_p],
     "feti_destroy": [C.c_void_p],
@@ -102,6 +133,7 @@ _SIGS = {
     "feti_apply_F": [C.c_void_p, C.c_void_p, C.c_void_p],
     "feti_apply_precond": [C.c_void_p, C.c_void_p, C.c_void_p],
     "feti_get_rhs": [C.c_void_p, C.c_void_p],
+    "feti_torn_residual": [C.c_void_p, C.POINTER(C.c_double)],
     "feti_time_kernel": [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                          C.POINTER(C.c_double)],
     "feti_interface_load": [C.c_void_p, C.POINTER(Load), C.c_void_p],
@@ -180,6 +212,7 @@ class Feti:
         if stream is not None:
             sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         self._check(self.lib.feti_create(C.byref(self.ctx), sp), "feti_create")
+        _LIVE["ctx"].add(self)
 
     # -- errors -------------------------------------------------------------
     def last_error(self) -> str:
@@ -202,8 +235,13 @@ class Feti:
             pass
 
     # -- setup ----------------------------------------------------------------
-    def setup_mesh(self, ncell, order_u, layout, nsub_x, nsub_y, dirichlet_u=0xF, dirichlet_p=0xF):
-        d = MeshDesc(ncell, order_u, layout, nsub_x, nsub_y, dirichlet_u, dirichlet_p)
+    def setup_mesh(self, ncell, order_u, layout, nsub_x, nsub_y, dirichlet_u=0xF, dirichlet_p=0xF,
+                   cut_x=None, cut_y=None):
+        cx = (C.c_int32 * len(cut_x))(*cut_x) if cut_x is not None else None
+        cy = (C.c_int32 * len(cut_y))(*cut_y) if cut_y is not None else None
+        d = MeshDesc(ncell, order_u, layout, nsub_x, nsub_y, dirichlet_u, dirichlet_p,
+                     C.cast(cx, C.POINTER(C.c_int32)) if cx is not None else None,
+                     C.cast(cy, C.POINTER(C.c_int32)) if cy is not None else None)
         return self._check(self.lib.feti_setup_mesh(self.ctx, C.byref(d)), "feti_setup_mesh")
 
     def get_sizes(self) -> Dict[str, int]:
@@ -301,6 +339,7 @@ class Feti:
     def apply_F(self, x, y):
         return self._check(self.lib.feti_apply_F(self.ctx, _ptr(x), _ptr(y)), "feti_apply_F")
 
+
     def apply_precond(self, x, y):
         return self._check(self.lib.feti_apply_precond(self.ctx, _ptr(x), _ptr(y)),
                            "feti_apply_precond")
@@ -309,6 +348,11 @@ class Feti:
         return self._check(self.lib.feti_get_rhs(self.ctx, _ptr(f)), "feti_get_rhs")
 
     # -- measurement --------------------------------------------------------------
+    def torn_residual(self) -> float:
+        rho = C.c_double()
+        self._check(self.lib.feti_torn_residual(self.ctx, C.byref(rho)), "feti_torn_residual")
+        return rho.value
+
     def time_kernel(self, which: int, reps: int = 20):
         ms, work = C.c_double(), C.c_double()
         self._check(self.lib.feti_time_kernel(self.ctx, which, reps, C.byref(ms), C.byref(work)),
@@ -329,6 +373,7 @@ class WarmStartNet:
         if rc != OK:
             raise FetiError(rc, "feti_ws_create")
         self.n_in, self.n_hidden, self.n_out, self.max_batch = n_in, n_hidden, n_out, max_batch
+        _LIVE["net"].add(self)
 
     def _check(self, rc: int, what: str):
         if rc != OK:
@@ -406,6 +451,7 @@ class Batch:
         rc = self.lib.feti_batch_create(C.byref(self.h), arr, len(self.ctxs))
         if rc != OK:
             raise FetiError(rc, self.ctxs[0].last_error())
+        _LIVE["batch"].add(self)
 
     def _check(self, rc: int, what: str, allow=()):
         if rc != OK and rc not in allow:

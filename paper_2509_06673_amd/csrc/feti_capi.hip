@@ -93,6 +93,8 @@ struct feti_ctx_s {
   int64_t nstep = 0;
   bool have_prev = false, have_prev2 = false;
   hipEvent_t ev[8] = {};
+  hipEvent_t ev_gj[2] = {};  // around the elimination kernels of the last factor_subdomains
+  double t_gj_ms = 0.0;
   bool own_stream = false;
   // persistent PCG: interface GEMV row tiles, grid barrier, partial sums, grid size
   int32_t* tile_sub = nullptr;
@@ -324,6 +326,8 @@ int upload_mesh(feti_ctx ctx) {
   }
   for (auto& e : ctx->ev)
     if (!e) HIPCHK(hipEventCreate(&e));
+  for (auto& e : ctx->ev_gj)
+    if (!e) HIPCHK(hipEventCreate(&e));
   return FETI_OK;
 }
 
@@ -357,6 +361,12 @@ LoadDev make_load(feti_ctx ctx, const feti_load* L) {
   d.lamP = ctx->lamP; d.muP = ctx->muP; d.lamE = ctx->lamE; d.muE = ctx->muE;
   d.alpha = ctx->matP.alpha; d.c0 = ctx->matP.c0;
   d.kf = ctx->matP.K / ctx->matP.mu_f;
+  if (L->kind == FETI_LOAD_RAW) {
+    d.f_p = L->f_p; d.f_e = L->f_e; d.z = L->z; d.t_side = L->t_side; d.zw_side = L->zw_side;
+    d.g_u = L->g_u; d.g_p = L->g_p; d.eta0 = L->eta0;
+  }
+  d.dir_u = ctx->mh.desc.dirichlet_u;
+  d.dir_p = ctx->mh.desc.dirichlet_p;
   return d;
 }
 
@@ -635,6 +645,7 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
       if (ptrace) {
         // stamps per iteration: 0 start, 1..6 after the barriers of phases A, B, D, E (with
         // the stopping test), F, G (stamp 0 of a later iteration = stamp 6 before)
+        const int np = 6;
         std::vector<long long> h(nts * 10);
         HIPCHK(hipMemcpyAsync(h.data(), ts, h.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -644,17 +655,17 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
         (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
         double sum[6] = {0}; int cnt = 0;
         for (int it = 0; it < nts; ++it) {
-          if (h[it * 10 + 6] == 0) break;
-          for (int k = 0; k < 6; ++k) {
-            const long long a0 = k > 0 ? h[it * 10 + k] : (it == 0 ? h[0] : h[(it - 1) * 10 + 6]);
+          if (h[it * 10 + np] == 0) break;
+          for (int k = 0; k < np; ++k) {
+            const long long a0 = k > 0 ? h[it * 10 + k] : (it == 0 ? h[0] : h[(it - 1) * 10 + np]);
             sum[k] += (double)(h[it * 10 + k + 1] - a0);
           }
           ++cnt;
         }
         if (cnt > 0 && rate_khz > 0) {
           const double us = 1e3 / rate_khz / cnt;
-          std::fprintf(stderr, "[pcg] grid %d, %d iterations, us: A %.2f B %.2f D %.2f E+test %.2f F %.2f G %.2f",
-                       ctx->pgrid, cnt, sum[0] * us, sum[1] * us, sum[2] * us, sum[3] * us, sum[4] * us, sum[5] * us);
+          std::fprintf(stderr, "[pcg] grid %d, %d iterations, us per phase:", ctx->pgrid, cnt);
+          for (int k = 0; k < np; ++k) std::fprintf(stderr, " %.2f", sum[k] * us);
           std::fprintf(stderr, "\n");
         }
       }
@@ -994,6 +1005,8 @@ int feti_destroy(feti_ctx ctx) {
     free_all(ctx);
     for (auto& e : ctx->ev)
       if (e) (void)hipEventDestroy(e);
+    for (auto& e : ctx->ev_gj)
+      if (e) (void)hipEventDestroy(e);
     if (ctx->h_ist) (void)hipHostFree(ctx->h_ist);
     if (ctx->h_sc) (void)hipHostFree(ctx->h_sc);
     if (ctx->h_kpart) (void)hipHostFree(ctx->h_kpart);
@@ -1157,22 +1170,25 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   std::vector<void*> tmp;
   GJPlan P;
   std::vector<int32_t> hflag;
-  int rc = build_gj_plan(ctx, P, hflag, nsub, n, nI, nsw, aofs, lda, sofs, ldb, 32, tmp);
+  int rc = build_gj_plan(ctx, P, hflag, nsub, n, nI, nsw, aofs, lda, sofs, ldb, GJ_PANEL, tmp);
   if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
   std::vector<int32_t> stat(nsub, 0);
   std::vector<int32_t> nswv(nsw.begin(), nsw.end());
   int32_t* d_nsw = nullptr;
   rc = upload(ctx, &d_nsw, nswv);
   if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
+  HIPCHK(hipEventRecord(ctx->ev_gj[0], st));
   if (f32) {
     for (int s = 0; s < P.nsteps; ++s) launch_gj_step(P, ctx->Kinv32, ctx->Sbb32, s, hflag[s] != 0, st);
     launch_gj_finalize(P, ctx->Kinv32, d_nsw, st);
+    HIPCHK(hipEventRecord(ctx->ev_gj[1], st));
     launch_precond_diag(m, (const float*)ctx->Sbb32, ctx->mdiag, st);
     launch_copy_block(nsub, m.max_nb, m.kofs, m.ld, m.nI, m.sofs, m.ldb, m.nb, (const float*)ctx->Kinv32,
                       ctx->Splus32, st);
   } else {
     for (int s = 0; s < P.nsteps; ++s) launch_gj_step(P, ctx->Kinv, ctx->Sbb, s, hflag[s] != 0, st);
     launch_gj_finalize(P, ctx->Kinv, d_nsw, st);
+    HIPCHK(hipEventRecord(ctx->ev_gj[1], st));
     // weights of the dual-energy residual norm: |diag| of the Dirichlet preconditioner
     launch_precond_diag(m, (const double*)ctx->Sbb, ctx->mdiag, st);
     // (K^+)_bb into the compact interface blocks
@@ -1187,6 +1203,11 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   }
   HIPCHK(hipMemcpyAsync(stat.data(), P.status, nsub * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_gj[0], ctx->ev_gj[1]));
+    ctx->t_gj_ms = ms;
+  }
   for (void* p : tmp) (void)hipFree(p);
   if (!ctx->keep_assembled && f32) {
     // the FP32 factors no longer need the assembled FP64 matrices
@@ -1205,7 +1226,7 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
     GJPlan C;
     std::vector<int32_t> cflag;
     std::vector<void*> ctmp;
-    rc = build_gj_plan(ctx, C, cflag, 1, {nc}, {0}, {nc}, {0}, {nc}, {-1}, {nc}, 32, ctmp);
+    rc = build_gj_plan(ctx, C, cflag, 1, {nc}, {0}, {nc}, {0}, {nc}, {-1}, {nc}, GJ_PANEL, ctmp);
     if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
     for (int s = 0; s < C.nsteps; ++s) launch_gj_step(C, ctx->Cinv, (double*)nullptr, s, false, st);
     int32_t* d_nc = nullptr;
@@ -1352,6 +1373,29 @@ int feti_get_solution(feti_ctx ctx, double* u_dev, double* lambda_dev) {
   if (lambda_dev)
     HIPCHK(hipMemcpyAsync(lambda_dev, ctx->lam_prev, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FETI_OK;
+}
+
+int feti_torn_residual(feti_ctx ctx, double* rho) {
+  if (!ctx || !rho) return FETI_EINVAL;
+  if (ctx->state < 3 || !ctx->have_prev) return fail(ctx, FETI_ESTATE, "torn_residual before a step");
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  // rf = f - K u - B^T lambda, cj = -B u for the last step's (u, lambda^n)
+  torn_residual(ctx, ctx->f, ctx->u, ctx->lam_prev);
+  launch_sumsq(m.sum_ns, ctx->rf, ctx->kpart, KMAX_NBLK, st);
+  launch_sumsq(m.n_lambda, ctx->cj, ctx->kpart + KMAX_NBLK, KMAX_NBLK, st);
+  launch_sumsq(m.sum_ns, ctx->f, ctx->kpart + 2 * KMAX_NBLK, KMAX_NBLK, st);
+  HIPCHK(hipMemcpyAsync(ctx->h_kpart, ctx->kpart, 3 * KMAX_NBLK * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int k = 0; k < KMAX_NBLK; ++k) {
+    a += ctx->h_kpart[k];
+    b += ctx->h_kpart[KMAX_NBLK + k];
+    c += ctx->h_kpart[2 * KMAX_NBLK + k];
+  }
+  *rho = c > 0.0 ? std::sqrt((a + b) / c) : std::sqrt(a + b);
   return FETI_OK;
 }
 
@@ -1516,12 +1560,13 @@ int feti_time_kernel(feti_ctx ctx, int32_t which, int32_t reps, double* avg_ms, 
   double w = 0.0;
   if (which == FETI_KERNEL_ELIMINATION) {
     if (!ctx->keep_assembled) return fail(ctx, FETI_ESTATE, "in-place factors cannot be recomputed");
-    HIPCHK(hipEventRecord(ctx->ev[6], st));
+    // factor again; the figure is the time between the events around the elimination
+    // kernels (pivots, panel rows, updates, panel writes, snapshot, finalisation) only
     RC(feti_factor_subdomains(ctx, ctx->precision, ctx->precond));
-    HIPCHK(hipEventRecord(ctx->ev[7], st));
-    HIPCHK(hipEventSynchronize(ctx->ev[7]));
     for (const SubHost& sh : h.subs) w += (double)sh.ns * sh.ns * sh.ns;
-    reps = 1;
+    *avg_ms = ctx->t_gj_ms;
+    *work = w;
+    return FETI_OK;
   } else {
     GemvArgs a;
     const Factors fc = factors(ctx);
@@ -1636,7 +1681,10 @@ int bupload(feti_batch b, T** p, const std::vector<T>& v) {
 
 // one cooperative launch over every problem; adds each problem's iterations to its
 // stats and keeps the worst status
-int run_batch(feti_batch b, bool corr, std::vector<feti_stats>& acc) {
+// One cooperative launch of the interface iterations of every problem.  tune: this launch
+// may be timed for the autotuner (first solves of a warm step only, so that every
+// candidate is timed on the same kind of work).
+int run_batch(feti_batch b, bool corr, bool tune, std::vector<feti_stats>& acc) {
   hipStream_t st = b->stream;
   BCHK(hipMemsetAsync(b->bar, 0, sizeof(GridBarrier), st));
   BCHK(hipMemsetAsync(b->ndone, 0, sizeof(int32_t), st));
@@ -1649,7 +1697,8 @@ int run_batch(feti_batch b, bool corr, std::vector<feti_stats>& acc) {
   a.alpha = b->alpha; a.beta = b->beta; a.rho = b->rho;
   a.done = b->done; a.iters = b->iters; a.status = b->status; a.ndone = b->ndone; a.bar = b->bar;
   a.max_nb = b->max_nb;
-  const int grid = b->tuned ? b->grid : b->cand[b->trial % b->cand.size()];
+  const bool timed = !b->tuned && tune;
+  const int grid = timed ? b->cand[b->trial % b->cand.size()] : (b->tuned ? b->grid : b->cand[0]);
   BCHK(hipEventRecord(b->e0, st));
   BCHK(launch_pcg_batch(a, grid, st));
   BCHK(hipEventRecord(b->e1, st));
@@ -1662,8 +1711,9 @@ int run_batch(feti_batch b, bool corr, std::vector<feti_stats>& acc) {
     total += b->h_buf[p];
     if (b->h_buf[b->P + p] != 0 && acc[p].status == 0) acc[p].status = b->h_buf[b->P + p];
   }
-  if (!b->tuned) {
-    // autotuner: time per iteration-problem of each candidate grid, then keep the best
+  if (timed) {
+    // autotuner: time per iteration-problem of each candidate grid, each timed twice on
+    // the first solve of a warm step, then keep the best
     float ms = 0.f;
     BCHK(hipEventElapsedTime(&ms, b->e0, b->e1));
     b->cost[b->trial % b->cand.size()] += ms / (double)std::max<int64_t>(total, 1);
@@ -1833,7 +1883,7 @@ int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts*
     cold = cold || !ctx->have_prev;
     BRC(torn_begin(ctx, o, o->tol, 0.0, ctx->f, nullptr, ctx->lam));
   }
-  BRC(run_batch(b, false, acc));
+  BRC(run_batch(b, false, !cold, acc));
   for (int p = 0; p < P; ++p) {
     acc[p].iters_first = acc[p].iters;
     BRC(torn_end(b->ctx[p], b->ctx[p]->lam, b->ctx[p]->u));
@@ -1847,7 +1897,7 @@ int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts*
       const bool warm = k == 0 && o->corr_start == FETI_CORR_PREVIOUS && ctx->have_dlam_prev;
       BRC(torn_begin(ctx, o, o->tol_corr, o->tol_upd, ctx->rf, ctx->cj, ctx->dlam, warm ? ctx->dlam_prev : nullptr));
     }
-    BRC(run_batch(b, true, acc));
+    BRC(run_batch(b, true, false, acc));
     for (int p = 0; p < P; ++p) {
       feti_ctx ctx = b->ctx[p];
       BRC(torn_end(ctx, ctx->dlam, ctx->du));

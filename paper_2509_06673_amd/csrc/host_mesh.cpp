@@ -75,8 +75,16 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
   m.mu = nu + 1;
   m.n1 = n + 1;
   std::vector<int> cx(d.nsub_x + 1), cy(d.nsub_y + 1);
-  for (int a = 0; a <= d.nsub_x; ++a) cx[a] = (int)((int64_t)a * n / d.nsub_x);
-  for (int b = 0; b <= d.nsub_y; ++b) cy[b] = (int)((int64_t)b * n / d.nsub_y);
+  for (int a = 0; a <= d.nsub_x; ++a) cx[a] = d.cut_x ? d.cut_x[a] : (int)((int64_t)a * n / d.nsub_x);
+  for (int b = 0; b <= d.nsub_y; ++b) cy[b] = d.cut_y ? d.cut_y[b] : (int)((int64_t)b * n / d.nsub_y);
+  if (cx[0] != 0 || cx[d.nsub_x] != n || cy[0] != 0 || cy[d.nsub_y] != n) return "cuts must run from 0 to ncell";
+  for (int a = 0; a < d.nsub_x; ++a)
+    if (cx[a + 1] <= cx[a]) return "cuts must increase strictly";
+  for (int b = 0; b < d.nsub_y; ++b)
+    if (cy[b + 1] <= cy[b]) return "cuts must increase strictly";
+  // the pointers are the caller's: the stored description does not keep them
+  m.desc.cut_x = nullptr;
+  m.desc.cut_y = nullptr;
   const int nsub = d.nsub_x * d.nsub_y;
   m.subs.resize(nsub);
   // owners of every DOF code

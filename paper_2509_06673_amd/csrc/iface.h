@@ -82,6 +82,8 @@ void launch_precond_diag(const DevMesh& m, const MT* S, double* mdiag, hipStream
 void launch_sub_gather(const DevMesh& m, const double* lam, double* r, hipStream_t st);
 void launch_kind_maxabs(const DevMesh& m, const double* x, const double* y, double* part, int nblk,
                         hipStream_t st);
+// part[b] = sum of x_i^2 over the grid-stride range of block b (nblk blocks)
+void launch_sumsq(int64_t n, const double* x, double* part, int nblk, hipStream_t st);
 // per subdomain: dst block (cnt x cnt) = src block at (src_at, src_at); TS, TD = double or float
 template <class TS, class TD>
 void launch_copy_block(int nsub, int maxn, const int64_t* src_ofs, const int32_t* src_ld,

@@ -74,7 +74,8 @@ void launch_elem_store(const DevMesh& m, MatParams mpP, MatParams mpE, hipStream
 void launch_elem_matvec(const DevMesh& m, const double* x, double* y, MatParams mpP, MatParams mpE,
                         hipStream_t st);
 
-// batched Gauss-Jordan elimination (kernels_gj.hip)
+// batched Gauss-Jordan elimination (kernels_gj.hip); panels of GJ_PANEL pivots
+constexpr int GJ_PANEL = 128;
 struct GJPlan {
   int nmat = 0;          // matrices in the batch
   int nb = 32;           // panel width

@@ -52,6 +52,11 @@ __global__ void k_assemble(const int32_t* __restrict__ el_sub, const int32_t* __
 __device__ inline double dirichlet_value(const LoadDev& L, bool poro, int32_t code, int umu,
                                          double uh, int n1, double h) {
   const int kind = code & 7, node = code >> 3;
+  if (L.kind == FETI_LOAD_RAW) {
+    if (kind <= 1) return L.g_u ? L.g_u[(int64_t)kind * umu * umu + node] : 0.0;
+    if (kind == 4) return L.g_p ? L.g_p[node] : 0.0;
+    return 0.0;
+  }
   if (kind <= 1) {
     const double x = (node % umu) * uh, y = (node / umu) * uh;
     return exact_u(L, poro, kind, x, y);
@@ -59,6 +64,70 @@ __device__ inline double dirichlet_value(const LoadDev& L, bool poro, int32_t co
   const double x = (node % n1) * h, y = (node / n1) * h;
   if (kind == 4) return exact_p(L, x, y);
   return 0.0;
+}
+
+// RAW loads: the boundary terms of an element's edges on the sides of the square, with the
+// 3-point Gauss-Legendre rule on the edge (exact for the products of P2 traces):
+// <t_h, theta_a> on sides without u Dirichlet data (traction of the element's region) and,
+// in poroelastic elements, -tau <z_w,h, phi_k> on sides without p Dirichlet data.  The
+// vertices' P1 lattice nodes come from the codes of the element's first scalar DOFs.
+__device__ inline void raw_boundary_terms(const LoadDev& L, bool poro, const int32_t* ec, int order, int ncell,
+                                          int nloc, int nu, double tau, double* acc) {
+  const bool trac = L.t_side != nullptr, flux = poro && L.zw_side != nullptr;
+  if (!trac && !flux) return;
+  const int umu = order * ncell + 1, n1 = ncell + 1;
+  const double len = 1.0 / ncell;  // boundary edges are axis-parallel cell edges
+  int vi[3], vj[3];
+  for (int v = 0; v < 3; ++v) {
+    const int node = ec[nu + v] >> 3;
+    vi[v] = node % n1;
+    vj[v] = node / n1;
+  }
+  const double gs = 0.38729833462074168852;  // sqrt(3/5) / 2
+  const double gq[3] = {0.5 - gs, 0.5, 0.5 + gs}, gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  for (int k = 0; k < 3; ++k) {
+    const int a = k, b = (k + 1) % 3;
+    int side = -1;
+    if (vi[a] == 0 && vi[b] == 0) side = 0;
+    else if (vi[a] == ncell && vi[b] == ncell) side = 1;
+    else if (vj[a] == 0 && vj[b] == 0) side = 2;
+    else if (vj[a] == ncell && vj[b] == ncell) side = 3;
+    if (side < 0) continue;
+    if (trac && !((L.dir_u >> side) & 1)) {
+      // displacement nodes of the edge: ends a, b and (P2) the midpoint 3 + k
+      const int nn = order == 2 ? 3 : 2;
+      const int loc[3] = {a, b, 3 + k};
+      double tv[2][3];
+      const int reg = poro ? 0 : 1;
+      for (int n = 0; n < nn; ++n) {
+        const int node = ec[2 * loc[n]] >> 3;
+        const int along = side < 2 ? node / umu : node % umu;
+        for (int c = 0; c < 2; ++c) tv[c][n] = L.t_side[((int64_t)(reg * 4 + side) * 2 + c) * umu + along];
+      }
+      for (int q = 0; q < 3; ++q) {
+        const double s = gq[q], la = 1.0 - s, lb = s;
+        double psi[3];
+        if (order == 2) { psi[0] = la * (2 * la - 1); psi[1] = lb * (2 * lb - 1); psi[2] = 4 * la * lb; }
+        else { psi[0] = la; psi[1] = lb; psi[2] = 0.0; }
+        double th[2] = {0.0, 0.0};
+        for (int n = 0; n < nn; ++n)
+          for (int c = 0; c < 2; ++c) th[c] += tv[c][n] * psi[n];
+        const double wl = gw[q] * len;
+        for (int n = 0; n < nn; ++n)
+          for (int c = 0; c < 2; ++c) acc[2 * loc[n] + c] += wl * th[c] * psi[n];
+      }
+    }
+    if (flux && !((L.dir_p >> side) & 1)) {
+      const double za = L.zw_side[side * n1 + (side < 2 ? vj[a] : vi[a])];
+      const double zb = L.zw_side[side * n1 + (side < 2 ? vj[b] : vi[b])];
+      for (int q = 0; q < 3; ++q) {
+        const double s = gq[q], la = 1.0 - s, lb = s;
+        const double zh = za * la + zb * lb, wl = gw[q] * len;
+        acc[nu + 6 + a] -= tau * wl * zh * la;
+        acc[nu + 6 + b] -= tau * wl * zh * lb;
+      }
+    }
+  }
 }
 
 // One thread per element: the element's right-hand side contributions (rows 1 and 4
@@ -83,29 +152,55 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
   const int nloc = order == 2 ? 6 : 3, nu = 2 * nloc;
   double acc[MAX_EDOF_DEV];
   for (int r = 0; r < MAX_EDOF_DEV; ++r) acc[r] = 0.0;
+  const int32_t* ec = m.el_code + e * edof;
+  const int umu = order * ncell + 1, n1 = ncell + 1;
+  const bool raw = L.kind == FETI_LOAD_RAW;
+  // RAW: the element's nodal data (the interpolants are evaluated at the quadrature points)
+  double rf[2][6] = {}, rz[3] = {};
+  if (raw) {
+    const double* fd = poro ? L.f_p : L.f_e;
+    if (fd)
+      for (int a = 0; a < nloc; ++a) {
+        const int node = ec[2 * a] >> 3;
+        rf[0][a] = fd[node];
+        rf[1][a] = fd[(int64_t)umu * umu + node];
+      }
+    if (poro && L.z)
+      for (int k = 0; k < 3; ++k) rz[k] = L.z[ec[nu + 3 + k] >> 3];
+  }
   // loads at the 7 quadrature points
   for (int q = 0; q < 7; ++q) {
     double l0, l1, l2, w;
     radon_point(q, l0, l1, l2, w);
     const double x = l0 * g.x[0] + l1 * g.x[1] + l2 * g.x[2];
     const double y = l0 * g.y[0] + l1 * g.y[1] + l2 * g.y[2];
-    double fx, fy;
-    body_force(L, poro, x, y, fx, fy);
     const double wa = w * g.area;
     const double lam[3] = {l0, l1, l2};
+    double phi[6];
     for (int a = 0; a < nloc; ++a) {
-      double phi;
-      if (order == 1) phi = lam[a];
-      else if (a < 3) phi = lam[a] * (2 * lam[a] - 1);
-      else phi = 4 * lam[a - 3] * lam[(a - 2) % 3];
-      acc[2 * a] += wa * fx * phi;
-      acc[2 * a + 1] += wa * fy * phi;
+      if (order == 1) phi[a] = lam[a];
+      else if (a < 3) phi[a] = lam[a] * (2 * lam[a] - 1);
+      else phi[a] = 4 * lam[a - 3] * lam[(a - 2) % 3];
+    }
+    double fx = 0.0, fy = 0.0;
+    if (raw) {
+      for (int a = 0; a < nloc; ++a) {
+        fx += rf[0][a] * phi[a];
+        fy += rf[1][a] * phi[a];
+      }
+    } else {
+      body_force(L, poro, x, y, fx, fy);
+    }
+    for (int a = 0; a < nloc; ++a) {
+      acc[2 * a] += wa * fx * phi[a];
+      acc[2 * a + 1] += wa * fy * phi[a];
     }
     if (poro) {
-      const double z = source(L, x, y);
+      const double z = raw ? rz[0] * l0 + rz[1] * l1 + rz[2] * l2 : source(L, x, y);
       for (int k = 0; k < 3; ++k) acc[nu + 6 + k] -= mp.tau * wa * z * lam[k];
     }
   }
+  if (raw) raw_boundary_terms(L, poro, ec, order, ncell, nloc, nu, mp.tau, acc);
   double pload[3] = {0.0, 0.0, 0.0};  // load parts of the p rows
   if (poro)
     for (int k = 0; k < 3; ++k) pload[k] = acc[nu + 6 + k];
@@ -118,7 +213,6 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
       for (int b = 0; b < 3; ++b) acc[nu + 6 + k] -= moment2(g, k, b) * ev[b];
   }
   // Dirichlet lifting
-  const int umu = order * ncell + 1;
   const double uh = 1.0 / (order * ncell), h = 1.0 / ncell;
   for (int c = 0; c < edof; ++c) {
     if (ld[c] >= 0) continue;
@@ -232,6 +326,10 @@ __global__ void k_init_eta(const int32_t* __restrict__ code, double* __restrict_
   const int32_t c = code[i];
   if ((c & 7) != 2) return;
   const int node = c >> 3;
+  if (L.kind == FETI_LOAD_RAW) {
+    u[i] = L.eta0 ? L.eta0[node] : 0.0;
+    return;
+  }
   const double h = 1.0 / ncell;
   u[i] = initial_eta(L, (node % (ncell + 1)) * h, (node / (ncell + 1)) * h);
 }
@@ -245,6 +343,14 @@ __global__ void k_interface_load(DevMesh m, LoadDev L, double* __restrict__ out)
   const int kind = code & 7, node = code >> 3;
   const bool poro = m.sub_poro[m.b_sub[gb]] != 0;
   double v = 0.0;
+  if (L.kind == FETI_LOAD_RAW) {
+    const int umu = m.order * m.ncell + 1;
+    const double* fd = poro ? L.f_p : L.f_e;
+    if (kind <= 1) v = fd ? fd[(int64_t)kind * umu * umu + node] : 0.0;
+    else if (kind <= 4) v = L.z ? L.z[node] : 0.0;
+    out[j] = v;
+    return;
+  }
   if (kind <= 1) {
     const int umu = m.order * m.ncell + 1;
     const double uh = 1.0 / (m.order * m.ncell);

@@ -46,11 +46,17 @@ template <> struct Mfma<float> {
   __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
 };
 
-constexpr int GJ_NB = 32;  // maximum panel width (the plan may use less)
+constexpr int GJ_NB = 128;  // maximum panel width (the plan may use less)
+constexpr int GJ_KC = 32;   // pivots per chunk of the update's inner products
 
-// (1) invert the pivot block in LDS by in-place Gauss-Jordan (in FP64)
+// (1) invert the pivot block in LDS (in FP64) by a blocked in-place Gauss-Jordan sweep:
+// for each sub-panel S of 32 pivots (R = the other indices of the block),
+//   M_SS <- M_SS^{-1} (32 element steps),  M_SR <- M_SS^{-1} M_SR,
+//   M_RR <- M_RR - M_RS M_SR,               M_RS <- -M_RS M_SS^{-1},
+// which is the element sweep (pivot 1/p, row / p, column -c/p, rest - c r / p) applied to
+// the 32 pivots in turn.  512 threads; products formed in registers, then written.
 template <class T>
-__global__ void __launch_bounds__(256) k_gj_pivot(const int32_t* __restrict__ pstart,
+__global__ void __launch_bounds__(512) k_gj_pivot(const int32_t* __restrict__ pstart,
                                                   const int32_t* __restrict__ pwidth,
                                                   const int64_t* __restrict__ aofs,
                                                   const int32_t* __restrict__ lda,
@@ -63,45 +69,134 @@ __global__ void __launch_bounds__(256) k_gj_pivot(const int32_t* __restrict__ ps
   if (kw == 0) return;
   const int k0 = pstart[step * nmat + m];
   const T* Am = A + aofs[m];
-  const int ld = lda[m];
+  const int64_t ld = lda[m];
+  constexpr int SB = 32;  // sub-panel
   __shared__ double M[GJ_NB][GJ_NB + 1];
-  __shared__ double rowk[GJ_NB];
-  __shared__ double colk[GJ_NB];
-  for (int t = threadIdx.x; t < kw * kw; t += blockDim.x) {
-    const int i = t / kw, j = t % kw;
-    M[i][j] = (double)Am[(int64_t)(k0 + max(i, j)) * ld + k0 + min(i, j)];
+  const int tid = threadIdx.x;
+  for (int t = tid; t < GJ_NB * GJ_NB; t += 512) {
+    const int i = t >> 7, j = t & (GJ_NB - 1);
+    if (i < kw && j < kw) M[i][j] = (double)Am[(k0 + max(i, j)) * ld + k0 + min(i, j)];
   }
   __syncthreads();
   bool bad = false;
-  for (int k = 0; k < kw; ++k) {
-    const double piv = M[k][k];
-    if (!(fabs(piv) > 0.0) || !isfinite(piv)) bad = true;
-    const double pinvk = 1.0 / piv;
-    for (int t = threadIdx.x; t < kw; t += blockDim.x) {
-      rowk[t] = t == k ? pinvk : M[k][t] * pinvk;
-      colk[t] = M[t][k];
+  for (int s0 = 0; s0 < kw; s0 += SB) {
+    const int sw = min(SB, kw - s0);
+    // M_SS <- M_SS^{-1}: element steps on the sub-panel block (thread: entries t, t + 512)
+    for (int k = s0; k < s0 + sw; ++k) {
+      const double piv = M[k][k];
+      if (!(fabs(piv) > 0.0) || !isfinite(piv)) bad = true;
+      const double pinvk = 1.0 / piv;
+      double nv[2];
+      int ii[2], jj[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = tid + 512 * h;
+        const int i = s0 + (t >> 5), j = s0 + (t & 31);
+        ii[h] = i;
+        jj[h] = j;
+        nv[h] = 0.0;
+        if ((t >> 5) < sw && (t & 31) < sw) {
+          if (i == k) nv[h] = j == k ? pinvk : M[k][j] * pinvk;
+          else nv[h] = j == k ? -M[i][k] * pinvk : M[i][j] - M[i][k] * (M[k][j] * pinvk);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = tid + 512 * h;
+        if ((t >> 5) < sw && (t & 31) < sw) M[ii[h]][jj[h]] = nv[h];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < kw * kw; t += blockDim.x) {
-      const int i = t / kw, j = t % kw;
-      if (i == k) continue;
-      if (j == k) M[i][j] = -colk[i] * pinvk;
-      else M[i][j] -= colk[i] * rowk[j];
+    if (sw == kw) break;  // the whole block was one sub-panel
+    // M_SR <- M_SS^{-1} M_SR: thread (row a = tid / 16, columns tid % 16 + 16 c)
+    {
+      const int a = tid >> 4, cb = tid & 15;
+      double acc[GJ_NB / 16];
+#pragma unroll
+      for (int c = 0; c < GJ_NB / 16; ++c) acc[c] = 0.0;
+      if (a < sw)
+        for (int bq = 0; bq < sw; ++bq) {
+          const double pab = M[s0 + a][s0 + bq];
+#pragma unroll
+          for (int c = 0; c < GJ_NB / 16; ++c) {
+            const int j = cb + 16 * c;
+            if (j < kw && (j < s0 || j >= s0 + sw)) acc[c] += pab * M[s0 + bq][j];
+          }
+        }
+      __syncthreads();
+      if (a < sw)
+#pragma unroll
+        for (int c = 0; c < GJ_NB / 16; ++c) {
+          const int j = cb + 16 * c;
+          if (j < kw && (j < s0 || j >= s0 + sw)) M[s0 + a][j] = acc[c];
+        }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < kw; t += blockDim.x) M[k][t] = rowk[t];
-    __syncthreads();
+    // M_RR <- M_RR - M_RS M_SR and the new column block M_RS <- -M_RS M_SS^{-1}: thread
+    // (rows 4 (tid / 16) .. + 3, columns tid % 16 + 16 c); the column block is formed in
+    // registers from the old M_RS before anything is written
+    {
+      const int rb = (tid >> 4) * 4, cb = tid & 15;
+      double acc[4][GJ_NB / 16];
+      double col[4][2];  // new M_RS entries of this thread: rows rb..rb+3, columns s0 + cb, s0 + cb + 16
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int c = 0; c < GJ_NB / 16; ++c) acc[r][c] = 0.0;
+        col[r][0] = col[r][1] = 0.0;
+      }
+      for (int bq = 0; bq < sw; ++bq) {
+        double mrs[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) mrs[r] = rb + r < kw ? M[rb + r][s0 + bq] : 0.0;
+#pragma unroll
+        for (int c = 0; c < GJ_NB / 16; ++c) {
+          const int j = cb + 16 * c;
+          const double msr = j < kw ? M[s0 + bq][j] : 0.0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[r][c] += mrs[r] * msr;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int ac = cb + 16 * h;  // column of M_SS^{-1}
+          const double pinv_ba = ac < sw ? M[s0 + bq][s0 + ac] : 0.0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) col[r][h] -= mrs[r] * pinv_ba;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = rb + r;
+        if (i >= kw || (i >= s0 && i < s0 + sw)) continue;
+#pragma unroll
+        for (int c = 0; c < GJ_NB / 16; ++c) {
+          const int j = cb + 16 * c;
+          if (j < kw && (j < s0 || j >= s0 + sw)) M[i][j] -= acc[r][c];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int ac = cb + 16 * h;
+          if (ac < sw) M[i][s0 + ac] = col[r][h];
+        }
+      }
+      __syncthreads();
+    }
   }
-  if (bad && threadIdx.x == 0) status[m] = 1;
+  if (bad && tid == 0) status[m] = 1;
   double* Pm = pinv + (int64_t)m * nb * nb;
-  for (int t = threadIdx.x; t < kw * kw; t += blockDim.x) {
-    const int i = t / kw, j = t % kw;
-    Pm[i * nb + j] = M[i][j];
+  for (int t = tid; t < GJ_NB * GJ_NB; t += 512) {
+    const int i = t >> 7, j = t & (GJ_NB - 1);
+    if (i < kw && j < kw) Pm[i * nb + j] = M[i][j];
   }
 }
 
-// (2) W = P^{-1} C over all columns outside the panel (one thread per column,
-// FP64 accumulation, stored in T)
+// (2) W = P^{-1} C over all columns outside the panel, in FP64 on the matrix cores, stored
+// in T.  One workgroup per 64 columns j0 .. j0 + 63 of a matrix: C[k][j0 + x] is staged in
+// LDS (in FP64), and the product W^T = C^T P^{-1} (P^{-1} is symmetric) is formed from
+// chunks of 32 rows of P^{-1} staged in turn; each of the four wavefronts computes 64
+// columns x 32 rows of W as 4 x 2 blocks of 16 x 16.
 template <class T>
 __global__ void __launch_bounds__(256) k_gj_row(const int32_t* __restrict__ pstart,
                                                 const int32_t* __restrict__ pwidth,
@@ -117,28 +212,63 @@ __global__ void __launch_bounds__(256) k_gj_row(const int32_t* __restrict__ psta
   if (kw == 0) return;
   const int k0 = pstart[step * nmat + m];
   const int n = nn[m];
-  __shared__ double P[GJ_NB][GJ_NB];
-  const double* Pm = pinv + (int64_t)m * nb * nb;
-  for (int t = threadIdx.x; t < GJ_NB * GJ_NB; t += blockDim.x) {
-    const int i = t / GJ_NB, k = t % GJ_NB;
-    P[i][k] = (i < kw && k < kw) ? Pm[i * nb + k] : 0.0;
-  }
-  __syncthreads();
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n || (j >= k0 && j < k0 + kw)) return;
+  const int j0 = blockIdx.x * 64;
+  if (j0 >= n) return;
+  // column blocks fully inside the panel have nothing to form
+  if (j0 >= k0 && j0 + 64 <= k0 + kw) return;
+  __shared__ double Ct[GJ_NB][64];        // C[k][j0 + x]
+  __shared__ double Pc[GJ_KC][GJ_NB + 4];  // rows kc .. kc + 31 of P^{-1}
   const T* Am = A + aofs[m];
-  const int ld = lda[m];
-  double c[GJ_NB];
-#pragma unroll
-  for (int k = 0; k < GJ_NB; ++k)
-    c[k] = k < kw ? (double)Am[(int64_t)max(k0 + k, j) * ld + min(k0 + k, j)] : 0.0;
-  T* W = wrow + (int64_t)m * nb * max_n;
-  for (int i = 0; i < kw; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < GJ_NB; ++k) s += P[i][k] * c[k];
-    W[(int64_t)i * max_n + j] = (T)s;
+  const int64_t ld = lda[m];
+  const int kp = (kw + 3) & ~3;
+  for (int t = threadIdx.x; t < kp * 64; t += blockDim.x) {
+    const int k = t / 64, x = t % 64;
+    const int j = j0 + x;
+    Ct[k][x] = (k < kw && j < n && !(j >= k0 && j < k0 + kw)) ? (double)Am[max(k0 + k, j) * ld + min(k0 + k, j)]
+                                                                : 0.0;
   }
+  const double* Pm = pinv + (int64_t)m * nb * nb;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int lr = lane % 16, lk = lane / 16;
+  const int ib = wave * 32;  // rows i of W (columns of the product) of this wavefront
+  Mfma<double>::acc4 acc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<double>::acc4{0.0, 0.0, 0.0, 0.0};
+  for (int kc = 0; kc < kp; kc += GJ_KC) {
+    const int kn = min(GJ_KC, kp - kc);
+    __syncthreads();  // Ct staged, or the previous chunk consumed
+    for (int t = threadIdx.x; t < kn * GJ_NB; t += blockDim.x) {
+      const int k = t / GJ_NB, i = t % GJ_NB;
+      Pc[k][i] = (kc + k < kw && i < kw) ? Pm[(kc + k) * nb + i] : 0.0;
+    }
+    __syncthreads();
+    if (ib < kw)
+      for (int k = 0; k < kn; k += 4) {
+        double av[4], bv[2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = Ct[kc + k + lk][a * 16 + lr];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = Pc[k + lk][ib + b * 16 + lr];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<double>::run(av[a], bv[b], acc[a][b]);
+      }
+  }
+  if (ib >= kw) return;
+  T* W = wrow + (int64_t)m * nb * max_n;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = j0 + a * 16 + Mfma<double>::row(lane, r);
+        const int i = ib + b * 16 + lr;
+        if (i < kw && j < n && !(j >= k0 && j < k0 + kw)) W[(int64_t)i * max_n + j] = (T)acc[a][b][r];
+      }
 }
 
 // (3) D -= C^T W outside the panel rows and columns (MFMA), on the tiles on and
@@ -168,7 +298,7 @@ __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ p
   const int ld = lda[m];
   const T* W = wrow + (int64_t)m * nb * max_n;
   __shared__ T Ct[GJ_NB][64];  // C[k][i0 + i]
-  __shared__ T Wt[GJ_NB][64];  // W[k][j0 + j]
+  __shared__ T Wt[GJ_KC][64];  // W[k][j0 + j] for one chunk of GJ_KC pivots
   const int kp = (kw + 3) & ~3;     // padded to the MFMA depth
   for (int t = threadIdx.x; t < kp * 64; t += blockDim.x) {
     const int k = t / 64, x = t % 64;
@@ -181,13 +311,6 @@ __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ p
   for (int j0 = 0; j0 <= i0; j0 += 64) {
     // column tiles fully inside the panel columns have nothing to update
     if (j0 >= k0 && j0 + 64 <= k0 + kw) continue;
-    __syncthreads();  // Ct staged, or the previous Wt consumed
-    for (int t = threadIdx.x; t < kp * 64; t += blockDim.x) {
-      const int k = t / 64, x = t % 64;
-      const int j = j0 + x;
-      Wt[k][x] = (k < kw && j < n && !(j >= k0 && j < k0 + kw)) ? W[(int64_t)k * max_n + j] : T(0);
-    }
-    __syncthreads();
     // the lane's 16 entries of the A tile are loaded before the products, so that their
     // latency overlaps the matrix-core work (entries outside the update read as 0)
     T old[2][2][4];
@@ -207,17 +330,43 @@ __global__ void __launch_bounds__(256) k_gj_update(const int32_t* __restrict__ p
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = typename Mfma<T>::acc4{T(0), T(0), T(0), T(0)};
-    for (int k = 0; k < kp; k += 4) {
-      T av[2], bv[2];
+    // the panel's pivots in chunks of GJ_KC: W[k][j0 + j] of the chunk staged in LDS, then
+    // the rank-4 MFMA steps over it; the next chunk's W entries are loaded into registers
+    // while the current chunk's products run
+    constexpr int WPT = GJ_KC * 64 / 256;  // staged W entries per thread and chunk
+    T wr[WPT];
+    auto load_chunk = [&](int kc) {
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = Ct[k + lk][wi + a * 16 + lr];
+      for (int q = 0; q < WPT; ++q) {
+        const int t = threadIdx.x + q * 256;
+        const int k = t / 64, x = t % 64;
+        const int j = j0 + x;
+        wr[q] = (kc + k < kw && j < n && !(j >= k0 && j < k0 + kw)) ? W[(int64_t)(kc + k) * max_n + j] : T(0);
+      }
+    };
+    load_chunk(0);
+    for (int kc = 0; kc < kp; kc += GJ_KC) {
+      const int kn = min(GJ_KC, kp - kc);
+      __syncthreads();  // Ct staged, or the previous chunk consumed
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Wt[k + lk][wj + b * 16 + lr];
+      for (int q = 0; q < WPT; ++q) {
+        const int t = threadIdx.x + q * 256;
+        Wt[t / 64][t % 64] = wr[q];
+      }
+      __syncthreads();
+      if (kc + GJ_KC < kp) load_chunk(kc + GJ_KC);
+      for (int k = 0; k < kn; k += 4) {
+        T av[2], bv[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a) av[a] = Ct[kc + k + lk][wi + a * 16 + lr];
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-          acc[a][b] = Mfma<T>::run(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < 2; ++b) bv[b] = Wt[k + lk][wj + b * 16 + lr];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = Mfma<T>::run(av[a], bv[b], acc[a][b]);
+      }
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -320,9 +469,9 @@ __global__ void k_gj_finalize(const int64_t* __restrict__ aofs, const int32_t* _
 template <class T>
 void launch_gj_step(const GJPlan& p, T* A, T* snap, int step, bool snap_now, hipStream_t st) {
   T* wrow = static_cast<T*>(p.wrow);
-  hipLaunchKernelGGL(k_gj_pivot<T>, dim3(p.nmat), dim3(256), 0, st, p.pstart, p.pwidth, p.aofs, p.lda,
+  hipLaunchKernelGGL(k_gj_pivot<T>, dim3(p.nmat), dim3(512), 0, st, p.pstart, p.pwidth, p.aofs, p.lda,
                      A, p.pinv, p.status, p.nmat, step, p.nb);
-  hipLaunchKernelGGL(k_gj_row<T>, dim3((p.max_n + 255) / 256, p.nmat), dim3(256), 0, st, p.pstart,
+  hipLaunchKernelGGL(k_gj_row<T>, dim3((p.max_n + 63) / 64, p.nmat), dim3(256), 0, st, p.pstart,
                      p.pwidth, p.aofs, p.lda, p.n, A, p.pinv, wrow, p.nmat, step, p.nb, p.max_n);
   const int nt = (p.max_n + 63) / 64;
   hipLaunchKernelGGL(k_gj_update<T>, dim3(nt, p.nmat), dim3(256), 0, st, p.pstart, p.pwidth,

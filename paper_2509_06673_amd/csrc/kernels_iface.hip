@@ -631,6 +631,26 @@ void launch_kind_maxabs(const DevMesh& m, const double* x, const double* y, doub
   hipLaunchKernelGGL(k_kind_maxabs, dim3(nblk), dim3(256), 0, st, m, x, y, part);
 }
 
+// per-block sums of x_i^2 (fixed grid-stride order and tree, so the same inputs give the
+// same partials)
+__global__ void __launch_bounds__(256) k_sumsq(int64_t n, const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) acc += x[i] * x[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+void launch_sumsq(int64_t n, const double* x, double* part, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_sumsq, dim3(nblk), dim3(256), 0, st, n, x, part);
+}
+
 void launch_sgemv(const DevMesh& m, const GemvArgs& a, hipStream_t st) {
   const size_t shm = sizeof(double) * ((size_t)m.max_ns + 4 * 64);
   if (a.which_n == 0) {

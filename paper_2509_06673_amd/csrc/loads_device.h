@@ -27,6 +27,10 @@ struct LoadDev {
   double t;
   double prm[16];
   double lamP, muP, lamE, muE, alpha, c0, kf;
+  // FETI_LOAD_RAW: caller data on the lattices (see feti_load) and the sides without
+  // u / p Dirichlet data (traction / flux sides)
+  const double *f_p, *f_e, *z, *t_side, *zw_side, *g_u, *g_p, *eta0;
+  uint32_t dir_u, dir_p;
 };
 
 // 7-point degree-5 rule of Radon on a triangle (barycentric points, weights summing to 1):

@@ -90,14 +90,20 @@ def train(net: B.WarmStartNet, X, T, epochs: int = 30, batch: int = 64, lr: floa
     return {"loss": hist, "seconds": time.perf_counter() - t0, "steps": total}
 
 
-def evaluate(w, net, nsteps: int, mode: str, opts=None) -> Dict:
+def evaluate(w, net, nsteps: int, mode: str, opts=None, precision: int = B.FP64) -> Dict:
     """Held-out trajectory with one start: 'previous', 'extrapolate' or 'learned' (the
     prediction, kept only when its projected residual beats the previous-step start).
-    Time per step covers the prediction and the step (stream events)."""
+    precision: FP64 factors, or FP32 factors with FP64 refinement (FP32_IR, with the
+    refinement defaults of workload.opts_mixed unless opts is given).  Time per step
+    covers the prediction and the step (stream events)."""
     import torch
-    f = setup(w)
+    from .workload import opts_mixed
+    f = setup(w, precision=precision)
     nl = f.get_sizes()["n_lambda"]
-    o = opts if opts is not None else make_opts(tol=1e-10, max_it=3000)
+    if opts is not None:
+        o = opts
+    else:
+        o = (opts_mixed if precision == B.FP32_IR else make_opts)(tol=1e-10, max_it=3000)
     lam_hist: List = []
     pred = torch.empty(nl, dtype=torch.float64, device="cuda")
     ld = torch.empty(nl, dtype=torch.float64, device="cuda")

@@ -7,12 +7,13 @@ from . import _binding as B
 
 _LAYOUT = {"xsplit": B.XSPLIT, "ysplit": B.YSPLIT, "core": B.CORE}
 _LOAD = {"manufactured": B.LOAD_MANUFACTURED, "periodic": B.LOAD_PERIODIC,
-         "point_source": B.LOAD_POINT_SOURCE, "patch": B.LOAD_PATCH}
+         "point_source": B.LOAD_POINT_SOURCE, "patch": B.LOAD_PATCH, "raw": B.LOAD_RAW}
 
 
 def mesh_args(w) -> Dict:
     return dict(ncell=w.ncell, order_u=w.order_u, layout=_LAYOUT[w.layout], nsub_x=w.nsub_x,
-                nsub_y=w.nsub_y, dirichlet_u=w.dirichlet_u, dirichlet_p=w.dirichlet_p)
+                nsub_y=w.nsub_y, dirichlet_u=w.dirichlet_u, dirichlet_p=w.dirichlet_p,
+                cut_x=getattr(w, "cut_x", None), cut_y=getattr(w, "cut_y", None))
 
 
 def material(m) -> B.Material:
@@ -37,6 +38,11 @@ def load(w, t: float) -> B.Load:
         prm[:3] = [w.load.cx, w.load.cy, w.load.sigma]
     for i, v in enumerate(prm):
         L.params[i] = v
+    if w.load.kind == "raw":
+        import torch
+        from workloads import raw_arrays
+        arrs = raw_arrays(w, t)
+        L.attach_raw({k: torch.tensor(v.ravel(), dtype=torch.float64, device="cuda") for k, v in arrs.items()})
     return L
 
 

@@ -82,6 +82,25 @@ def test_uneven_cuts_bit_exact():
     _compare(w)
 
 
+def test_caller_cuts_bit_exact():
+    # cuts given by the caller (uneven, x = 1/2 kept as a cut for the x-split layout)
+    w = W.nearly_incompressible_scaled(24, 4).replace(nsub_x=4, nsub_y=3, cut_x=(0, 3, 12, 20, 24),
+                                                      cut_y=(0, 10, 13, 24))
+    _compare(w)
+    w = W.pulsed_core(ncell=16, nsub=4, nsteps=1).replace(cut_x=(0, 4, 9, 12, 16), cut_y=(0, 4, 5, 12, 16))
+    _compare(w)
+
+
+def test_invalid_cuts_are_rejected():
+    for cx in ((0, 4, 4, 8), (1, 2, 5, 8), (0, 2, 5, 7), (0, 3, 5, 8)):
+        f = B.Feti()
+        with pytest.raises(B.FetiError) as e:
+            # the last tuple straddles x = 1/2 in the x-split layout
+            f.setup_mesh(ncell=8, order_u=2, layout=0, nsub_x=3, nsub_y=1, cut_x=cx)
+        assert e.value.code == B.EINVAL
+        f.close()
+
+
 def test_full_size_counts():
     f = B.Feti()
     f.setup_mesh(**mesh_args(W.nearly_incompressible_large()))

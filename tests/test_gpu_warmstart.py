@@ -107,9 +107,15 @@ def test_adam_steps_match_oracle():
     net.close()
 
 
-def test_learned_start_predicts_better_than_the_previous_step():
+_LEARNED = {}
+
+
+def _trained_and_evaluated():
+    """One network trained on six short seeded trajectories (h = 1/32, 4 x 4 subdomains)
+    and the held-out trajectory run with each start; shared by the tests below."""
     import torch
-    require_gpu()
+    if _LEARNED:
+        return _LEARNED
     cases = [W.learned_start_case(s, nsteps=40, ncell=32).replace(nsub_x=4, nsub_y=4) for s in range(1, 7)]
     probe = WS.setup(cases[0])
     nl = probe.get_sizes()["n_lambda"]
@@ -121,7 +127,6 @@ def test_learned_start_predicts_better_than_the_previous_step():
     hist = WS.train(net, X, T, epochs=40, batch=32, lr=2e-3, seed=7)
     print(f"[ws train] {X.shape[0]} samples, loss {hist['loss'][0]:.3e} -> {hist['loss'][-1]:.3e} "
           f"in {hist['seconds']:.1f} s", flush=True)
-    assert hist["loss"][-1] < 0.5 * hist["loss"][0]
     held = W.learned_start_case(1001, nsteps=30, ncell=32).replace(nsub_x=4, nsub_y=4)
     res = {m: WS.evaluate(held, net, 30, m) for m in ("previous", "extrapolate", "learned")}
     for m, r in res.items():
@@ -130,11 +135,30 @@ def test_learned_start_predicts_better_than_the_previous_step():
     r = res["learned"]
     print(f"  start error vs the solved multipliers: prediction {r['mean_err_pred']:.3e}, previous step "
           f"{r['mean_err_prev']:.3e}, extrapolation {r['mean_err_extrap']:.3e}", flush=True)
-    # the network predicts the next multipliers better than the previous step does (the
-    # iteration counts respond weakly and erratically to the start on this indefinite F)
+    net.close()
+    _LEARNED.update(hist=hist, res=res)
+    return _LEARNED
+
+
+def test_learned_start_predicts_better_than_the_previous_step():
+    require_gpu()
+    d = _trained_and_evaluated()
+    assert d["hist"]["loss"][-1] < 0.5 * d["hist"]["loss"][0]
+    r = d["res"]["learned"]
+    # the network predicts the next multipliers better than the previous step does
     assert r["mean_err_pred"] < r["mean_err_prev"]
     assert r["used_learned"] > 0
-    net.close()
+
+
+@pytest.mark.xfail(strict=False, reason="measured: the learned start does not save first-solve iterations "
+                   "over both the previous-step and the extrapolated start on these trajectories (the "
+                   "iteration on the indefinite F responds weakly to the start's accuracy); kept to report "
+                   "the gain if a later network or solver achieves one")
+def test_learned_start_saves_first_solve_iterations():
+    require_gpu()
+    res = _trained_and_evaluated()["res"]
+    best_plain = min(res["previous"]["mean_iters_first"], res["extrapolate"]["mean_iters_first"])
+    assert res["learned"]["mean_iters_first"] < best_plain
 
 
 def test_best_start_returns_the_same_solution():

@@ -30,6 +30,7 @@ MANUFACTURED = "manufactured"   # closed-form smooth solution (Section 4.1)
 PERIODIC = "periodic"           # time-periodic body force and source
 POINT_SOURCE = "point_source"   # Gaussian-regularised pulsed source
 PATCH = "patch"                 # polynomial solution contained in the FE spaces
+RAW = "raw"                     # caller data: nodal loads, boundary data and initial data
 
 # coefficients of the patch-test displacement (1, x, y, x^2, xy, y^2) and pressure (1, y);
 # the quadratic terms and the y-term of p are dropped for P1 displacements
@@ -62,6 +63,9 @@ class Load:
     cx: float = 0.5
     cy: float = 0.5
     sigma: float = 1.0 / 32.0
+    # RAW: seed of the nodal data drawn by raw_arrays (or fixed arrays given by the caller)
+    raw_seed: int = 0
+    raw_fixed: Optional[dict] = None
 
 
 @dataclass
@@ -82,6 +86,17 @@ class Workload:
     dirichlet_u: int = 0xF
     # bitmask of outer sides with p Dirichlet (only where the poro region touches them)
     dirichlet_p: int = 0xF
+    # subdomain cuts in cells (nsub + 1 increasing values from 0 to ncell); None = the even
+    # cuts floor(a ncell / nsub)
+    cut_x: Optional[Tuple[int, ...]] = None
+    cut_y: Optional[Tuple[int, ...]] = None
+
+    def cuts(self) -> Tuple[List[int], List[int]]:
+        cx = list(self.cut_x) if self.cut_x is not None else [(a * self.ncell) // self.nsub_x
+                                                               for a in range(self.nsub_x + 1)]
+        cy = list(self.cut_y) if self.cut_y is not None else [(b * self.ncell) // self.nsub_y
+                                                               for b in range(self.nsub_y + 1)]
+        return cx, cy
 
     @property
     def h(self) -> float:
@@ -167,6 +182,48 @@ def patch_case(order_u: int = 2, ncell: int = 8, nsub_x: int = 4, nsub_y: int = 
     return Workload(name=f"patch_p{order_u}_h{ncell}_{nsub_x}x{nsub_y}", ncell=ncell,
                     order_u=order_u, layout=XSPLIT, nsub_x=nsub_x, nsub_y=nsub_y, mat_p=m,
                     mat_e=copy.deepcopy(m), tau=0.05, nsteps=nsteps, load=Load(kind=PATCH))
+
+
+def raw_case(ncell: int = 8, nsub_x: int = 4, nsub_y: int = 2, order_u: int = 2, nsteps: int = 3,
+             seed: int = 5, layout: str = XSPLIT) -> Workload:
+    """Caller-data load (RAW): seeded nodal body forces, source, traction, flux,
+    Dirichlet and initial data; u Dirichlet on x = 0 and y = 0 only (traction on x = 1
+    and y = 1), p Dirichlet on x = 0 only (flux on the poroelastic parts of y = 0 and
+    y = 1)."""
+    m = _mat(E=10.0, nu=0.3, alpha=1.0, c0=0.5, K=0.2, mu_f=1.0)
+    return Workload(name=f"raw_p{order_u}_h{ncell}_{nsub_x}x{nsub_y}_s{seed}", ncell=ncell, order_u=order_u,
+                    layout=layout, nsub_x=nsub_x, nsub_y=nsub_y, mat_p=m, mat_e=copy.deepcopy(m), tau=0.05,
+                    nsteps=nsteps, load=Load(kind=RAW, raw_seed=seed), dirichlet_u=0b0101, dirichlet_p=0b0001)
+
+
+RAW_FIELDS = ("f_p", "f_e", "z", "t_side", "zw_side", "g_u", "g_p", "eta0")
+
+
+def raw_shapes(w: Workload) -> Dict[str, Tuple[int, ...]]:
+    """Array shapes of the RAW data: displacement lattice of mu = k ncell + 1 points per
+    side, P1 lattice of n1 = ncell + 1; lattices row-major with x fastest; the side
+    arrays are indexed by side (x = 0, x = 1, y = 0, y = 1) and by the lattice index
+    along the side (y index on x = const, x index on y = const)."""
+    mu = w.order_u * w.ncell + 1
+    n1 = w.ncell + 1
+    return {"f_p": (2, mu * mu), "f_e": (2, mu * mu), "z": (n1 * n1,), "t_side": (2, 4, 2, mu),
+            "zw_side": (4, n1), "g_u": (2, mu * mu), "g_p": (n1 * n1,), "eta0": (n1 * n1,)}
+
+
+def raw_arrays(w: Workload, t: float) -> Dict[str, np.ndarray]:
+    """Nodal data of a RAW load at time t.  With raw_fixed the given arrays (the same at
+    every t); otherwise standard-normal arrays drawn from raw_seed, each multiplied by
+    its own smooth factor of t (so that every step sees new data)."""
+    if w.load.raw_fixed is not None:
+        return {k: np.asarray(v, dtype=np.float64) for k, v in w.load.raw_fixed.items()}
+    shapes = raw_shapes(w)
+    rng = np.random.default_rng(w.load.raw_seed)
+    out = {}
+    for i, name in enumerate(RAW_FIELDS):
+        base = rng.standard_normal(shapes[name])
+        fac = 1.0 if name == "eta0" else 1.0 + 0.5 * math.sin(3.0 * t + 0.7 * i)
+        out[name] = fac * base
+    return out
 
 
 BATCH_SEED = 20250906
