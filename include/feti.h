@@ -353,6 +353,18 @@ enum { FETI_EXPORT_K = 0, FETI_EXPORT_SBB = 1, FETI_EXPORT_KPLUS = 2 };
 int feti_apply_F(feti_ctx ctx, const double* x_dev, double* y_dev);
 int feti_apply_precond(feti_ctx ctx, const double* x_dev, double* y_dev);
 
+/* y = F x as feti_apply_F, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * interface-space products live in a static per-GPU device array of 2^20 doubles
+ * (8 MiB, held by every GPU that loads the library until the process ends) instead of
+ * the context's buffers, and the call neither allocates nor frees anything.  It is
+ * stream-ordered on the context stream and does not synchronise.  The context must be
+ * factored and its device current.  FETI_EINVAL when the interface space (sum_s n_b,s)
+ * exceeds 2^20 entries or another device is current.  Calls that overlap on one GPU
+ * (several streams or host threads) share the array and race; the result is the same
+ * as feti_apply_F's, bit for bit. */
+int feti_apply_F_noalloc(feti_ctx ctx, const double* x_dev, double* y_dev);
+
 /* Torn right-hand side of the last prepared step (sum n_s doubles). */
 int feti_get_rhs(feti_ctx ctx, double* f_dev);
 

@@ -131,6 +131,7 @@ _SIGS = {
     "feti_get_field": [C.c_void_p, C.c_int32, C.c_void_p],
     "feti_export_local": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p],
     "feti_apply_F": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "feti_apply_F_noalloc": [C.c_void_p, C.c_void_p, C.c_void_p],
     "feti_apply_precond": [C.c_void_p, C.c_void_p, C.c_void_p],
     "feti_get_rhs": [C.c_void_p, C.c_void_p],
     "feti_torn_residual": [C.c_void_p, C.POINTER(C.c_double)],
@@ -340,6 +341,10 @@ class Feti:
         return self._check(self.lib.feti_apply_F(self.ctx, _ptr(x), _ptr(y)), "feti_apply_F")
 
 
+    def apply_F_noalloc(self, x, y):
+        """y = F x through the entry point that allocates nothing (stream-ordered, no
+        synchronisation)."""
+        return self._check(self.lib.feti_apply_F_noalloc(self.ctx, _ptr(x), _ptr(y)), "feti_apply_F_noalloc")
     def apply_precond(self, x, y):
         return self._check(self.lib.feti_apply_precond(self.ctx, _ptr(x), _ptr(y)),
                            "feti_apply_precond")

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -431,6 +432,30 @@ void op_M_raw(feti_ctx ctx, const double* x, double* y, double* g, const int32_t
 
 void op_M(feti_ctx ctx, const double* x, double* y, const int32_t* skip) {
   op_M_raw(ctx, x, y, nullptr, skip);
+}
+
+// Scratch of feti_apply_F_noalloc: the interface-space products y_b of every subdomain,
+// in a file-scope device array (each GPU that loads the library holds its own copy until
+// the process ends).  Host code refers to it only through the per-device address that
+// hipGetSymbolAddress returns; the array's name is a host-side stand-in.
+constexpr int64_t FETI_NOALLOC_SCRATCH = 1 << 20;  // doubles (8 MiB)
+static __device__ __align__(256) double scratch[FETI_NOALLOC_SCRATCH];
+constexpr int FETI_MAX_DEVICES = 64;
+static double* g_scratch_ptr[FETI_MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+// Address of this device's scratch (dev must be current), looked up once per device.
+int noalloc_scratch(feti_ctx ctx, int dev, double** out) {
+  if (dev < 0 || dev >= FETI_MAX_DEVICES) return fail(ctx, FETI_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ctx, FETI_EHIP, "hipGetSymbolAddress returned no address for the scratch");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return FETI_OK;
 }
 
 int32_t* counter(feti_ctx ctx, int phase) { return ctx->ist + IS_CNT0 + phase; }
@@ -1539,6 +1564,27 @@ int feti_apply_precond(feti_ctx ctx, const double* x, double* y) {
   op_M(ctx, x, y, nullptr);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FETI_OK;
+}
+
+int feti_apply_F_noalloc(feti_ctx ctx, const double* x, double* y) {
+  if (!ctx || !x || !y) return FETI_EINVAL;
+  if (ctx->state < 3) return fail(ctx, FETI_ESTATE, "apply_F_noalloc before factor_subdomains");
+  DevMesh& m = ctx->dm;
+  if (m.sum_nb > FETI_NOALLOC_SCRATCH) return fail(ctx, FETI_EINVAL, "interface space larger than the static scratch");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != ctx->device) return fail(ctx, FETI_EINVAL, "apply_F_noalloc called with another device current");
+  double* yb = nullptr;
+  RC(noalloc_scratch(ctx, dev, &yb));
+  GemvArgs a;
+  const Factors fc = factors(ctx);
+  a.A = fc.splus; a.a_f32 = fc.f32; a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
+  a.v = x; a.gmode = G_SIGNED; a.gcoef = 1.0; a.y = yb;
+  // every entry of the scratch that the jump reads is written by the GEMV first
+  launch_sgemv(m, a, ctx->stream);
+  launch_jump(m, yb, 0, y, 0, nullptr, nullptr, ctx->stream);
+  HIPCHK(hipGetLastError());
   return FETI_OK;
 }
 
