@@ -29,7 +29,7 @@ FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 # pivots per panel step of the batched elimination: every panel step reads and writes
 # the lower half of every matrix, so the sweep moves sum_s n_s^3 w / GJ_PANEL bytes
-GJ_PANEL = 32
+GJ_PANEL = 128
 
 # HBM bytes per PCG iteration of the persistent interface kernel (FP64 variant), from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, summed over the kernel's dispatches and

@@ -21,6 +21,7 @@
 #include <string>
 #include <vector>
 
+#include "bstep.h"
 #include "feti_internal.h"
 #include "iface.h"
 #include "kernels.h"
@@ -1689,6 +1690,14 @@ struct feti_batch_s {
   int trial = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   std::vector<void*> allocs;
+  // batched set-up, recovery and refinement residual: problem table (device, and the host
+  // copy it was uploaded from), per-step values (device, and pinned staging) and launch
+  // dimensions
+  BProb* d_probs = nullptr;
+  std::vector<BProb> h_probs;
+  BStepVals* d_vals = nullptr;
+  BStepVals* h_vals = nullptr;
+  BDims dims;
 };
 
 namespace {
@@ -1775,6 +1784,133 @@ int run_batch(feti_batch b, bool corr, bool tune, std::vector<feti_stats>& acc) 
   return FETI_OK;
 }
 
+// The problem table of the batched launches from the contexts' current buffers.
+BProb prob_of(feti_ctx c) {
+  BProb a;
+  const Factors fc = factors(c);
+  a.m = c->dm;
+  a.mpP = c->mpP;
+  a.mpE = c->mpE;
+  a.kinv = fc.kinv;
+  a.splus = fc.splus;
+  a.sbb = c->precond == FETI_PRECOND_LUMPED ? (const void*)c->Kbb : fc.sbb;
+  a.f32 = fc.f32;
+  a.H = c->H;
+  a.Cinv = c->Cinv;
+  a.nc = c->nc;
+  a.mdiag = c->mdiag;
+  double** v = a.v;
+  v[BV_U] = c->u; v[BV_F] = c->f; v[BV_D] = c->d; v[BV_YTMP] = c->ytmp; v[BV_LAM] = c->lam; v[BV_DLAM] = c->dlam;
+  v[BV_R] = c->r; v[BV_W] = c->w; v[BV_Z] = c->z; v[BV_Y] = c->y; v[BV_P] = c->p; v[BV_Q] = c->q;
+  v[BV_YB] = c->yb; v[BV_ZB] = c->zb; v[BV_G] = c->g; v[BV_GD] = c->gd; v[BV_GQ] = c->gq; v[BV_AC] = c->ac;
+  v[BV_TL] = c->tl; v[BV_RF] = c->rf; v[BV_CJ] = c->cj; v[BV_DU] = c->du; v[BV_LAMP] = c->lam_prev;
+  v[BV_LAMP2] = c->lam_prev2; v[BV_DLAMP] = c->dlam_prev; v[BV_DLAMS] = c->dlam_sum; v[BV_LALT] = c->lam_alt;
+  v[BV_RALT] = c->r_alt; v[BV_WALT] = c->w_alt;
+  a.sc = c->sc;
+  a.ist = c->ist;
+  a.part = c->part;
+  return a;
+}
+
+// Uploads the problem table again when a context's buffers have moved since the last
+// upload (a single-problem step swaps the multiplier histories).
+int sync_probs(feti_batch b) {
+  bool same = (int)b->h_probs.size() == b->P;
+  std::vector<BProb> now(b->P);
+  for (int p = 0; p < b->P; ++p) {
+    now[p] = prob_of(b->ctx[p]);
+    const BProb& o = b->h_probs.empty() ? now[p] : b->h_probs[p];
+    if (same)
+      same = std::memcmp(now[p].v, o.v, sizeof(o.v)) == 0 && now[p].kinv == o.kinv && now[p].splus == o.splus &&
+             now[p].sbb == o.sbb && now[p].f32 == o.f32 && now[p].H == o.H && now[p].Cinv == o.Cinv &&
+             now[p].mdiag == o.mdiag && now[p].m.ebuf == o.m.ebuf && now[p].m.emat == o.m.emat;
+  }
+  if (same) return FETI_OK;
+  b->h_probs = now;
+  BCHK(hipMemcpyAsync(b->d_probs, b->h_probs.data(), b->P * sizeof(BProb), hipMemcpyHostToDevice, b->stream));
+  BCHK(hipStreamSynchronize(b->stream));  // the host table may change before the next step
+  return FETI_OK;
+}
+
+// Batched form of torn_begin (the projection through H = G (G^T G)^{-1}, which every
+// problem of a batch has): d = sum_s B_s K_s^+ f_s - c, the admissible start, r, w = P r,
+// the tolerance references from P d, z = M^{-1} w, y = P z, p = y and rho = (w, y).  With
+// cand, the first correction compares the previous step's total correction as a start
+// (problems whose step values have cand = 0 keep their own start).
+void btorn_begin(feti_batch b, double tol, double utol, int maxit, int f, int cj, int lam, int cand) {
+  const BProb* P = b->d_probs;
+  const BDims& d = b->dims;
+  hipStream_t st = b->stream;
+  const int f32 = b->f32;
+  BGemv g;
+  g.mat = BM_KINV; g.full = 1; g.xbase = f; g.y = BV_YTMP;
+  launchb_sgemv(P, d, g, f32, st);
+  launchb_jump(P, d, BV_YTMP, 1, BV_D, 0, BV_NONE, st);
+  if (cj != BV_NONE) launchb_axpby(P, d, BL_LAMBDA, 1.0, BV_D, -1.0, cj, BV_D, st);
+  auto admissible = [&](int v) {
+    launchb_coarse_g(P, d, v, f, -1.0, BV_G, st);
+    launchb_coarse_apply(P, d, BV_G, BV_AC, 1.0, st);
+    launchb_coarse_correct(P, d, BV_AC, 1.0, v, v, st);
+  };
+  admissible(lam);
+  launchb_coarse_g(P, d, BV_D, BV_NONE, 1.0, BV_GD, st);
+  auto start_rw = [&](int v, int r, int w) {
+    BGemv a;
+    a.mat = BM_SPLUS; a.full = 0; a.v = v; a.gmode = G_SIGNED; a.gcoef = 1.0; a.y = BV_YB;
+    launchb_sgemv(P, d, a, f32, st);
+    launchb_jump(P, d, BV_YB, 0, BV_Q, 0, BV_NONE, st);
+    launchb_axpby(P, d, BL_LAMBDA, 1.0, BV_D, -1.0, BV_Q, r, st);
+    launchb_coarse_g(P, d, r, BV_NONE, 1.0, BV_GQ, st);
+    launchb_h_project(P, d, r, BV_NONE, BV_GQ, BV_NONE, w, BV_NONE, BV_NONE, st);
+  };
+  start_rw(lam, BV_R, BV_W);
+  if (cand != BV_NONE) {
+    launchb_axpby(P, d, BL_LAMBDA, 1.0, cand, 0.0, BV_NONE, BV_LALT, st);
+    admissible(BV_LALT);
+    start_rw(BV_LALT, BV_RALT, BV_WALT);
+    launchb_reduce(P, d, BV_NONE, BV_NONE, BV_W, PH_REFNORM, st);
+    launchb_copy_scalar(P, d, SC_EREF, SC_SEL0, st);
+    launchb_reduce(P, d, BV_NONE, BV_NONE, BV_WALT, PH_REFNORM, st);
+    launchb_copy_scalar(P, d, SC_EREF, SC_SEL1, st);
+    launchb_pick_start(P, b->d_vals, d, BV_LALT, lam, BV_RALT, BV_R, BV_WALT, BV_W, st);
+  }
+  launchb_init_scalars(P, d, tol, utol, std::max(maxit, 0), st);
+  launchb_h_project(P, d, BV_D, BV_NONE, BV_GD, BV_NONE, BV_TL, BV_NONE, BV_NONE, st);
+  launchb_reduce(P, d, BV_NONE, BV_NONE, BV_TL, PH_REFNORM, st);
+  BGemv m;
+  m.mat = BM_SBB; m.full = 0; m.v = BV_W; m.gmode = G_SCALED; m.gcoef = 1.0; m.y = BV_ZB;
+  launchb_sgemv(P, d, m, f32, st);
+  launchb_jump(P, d, BV_ZB, 0, BV_Z, 1, BV_GQ, st);
+  launchb_h_project(P, d, BV_Z, BV_NONE, BV_GQ, BV_NONE, BV_Y, BV_NONE, BV_P, st);
+  launchb_reduce(P, d, BV_W, BV_Y, BV_W, PH_INIT, st);
+}
+
+// Batched torn_end: alpha_c = -(G^T G)^{-1} G^T r and u = K^+ f - K^+ B^T lam + R alpha_c,
+// with K^+ f still in ytmp.
+void btorn_end(feti_batch b, int lam, int u) {
+  const BProb* P = b->d_probs;
+  const BDims& d = b->dims;
+  hipStream_t st = b->stream;
+  launchb_coarse_g(P, d, BV_R, BV_NONE, 1.0, BV_G, st);
+  launchb_coarse_apply(P, d, BV_G, BV_AC, -1.0, st);
+  BGemv g;
+  g.mat = BM_KINV; g.full = 1; g.kb_only = 1; g.ybase = BV_YTMP; g.v = lam; g.gmode = G_SIGNED; g.gcoef = -1.0;
+  g.y = u; g.alpha_c = BV_AC;
+  launchb_sgemv(P, d, g, b->f32, st);
+}
+
+// Batched torn_residual: rf = f - K u - B^T lam, cj = -sum_s B_s u_s.
+void btorn_residual(feti_batch b) {
+  const BProb* P = b->d_probs;
+  const BDims& d = b->dims;
+  hipStream_t st = b->stream;
+  launchb_elem_matvec(P, d, BV_U, BV_YTMP, st);
+  launchb_axpby(P, d, BL_TORN, 1.0, BV_F, -1.0, BV_YTMP, BV_RF, st);
+  launchb_sub_gather(P, d, BV_LAM, BV_RF, st);
+  launchb_jump(P, d, BV_U, 1, BV_CJ, 0, BV_NONE, st);
+  launchb_axpby(P, d, BL_LAMBDA, -1.0, BV_CJ, 0.0, BV_NONE, BV_CJ, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1787,6 +1923,7 @@ int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob) {
   auto bad = [&](int rc, const std::string& msg) {
     for (void* p : b->allocs) (void)hipFree(p);
     if (b->h_buf) (void)hipHostFree(b->h_buf);
+    if (b->h_vals) (void)hipHostFree(b->h_vals);
     delete b;
     if (ctxs[0] && !msg.empty()) ctxs[0]->err = "feti_batch_create: " + msg;
     return rc == FETI_OK ? FETI_EINVAL : rc;
@@ -1846,6 +1983,43 @@ int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob) {
     return bad(rc, "");
   if (hipHostMalloc((void**)&b->h_buf, 2 * nprob * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
     return bad(FETI_ENOMEM, "");
+  // batched launches: table, per-step values, dimensions and GEMV work items
+  {
+    BDims& d = b->dims;
+    d.P = nprob;
+    std::vector<int32_t> fi, ii;
+    for (int p = 0; p < nprob; ++p) {
+      feti_ctx c = ctxs[p];
+      const DevMesh& m = c->dm;
+      const int64_t nl = m.n_lambda;
+      d.nl_blk = std::max(d.nl_blk, (int)((nl + 255) / 256));
+      d.nl64_blk = std::max(d.nl64_blk, (int)((nl + 63) / 64));
+      d.ns_blk = std::max(d.ns_blk, (int)((m.sum_ns + 255) / 256));
+      d.nb_blk = std::max(d.nb_blk, (int)((m.sum_nb + 255) / 256));
+      d.red_blk = std::max(d.red_blk, (int)std::max<int64_t>(1, std::min<int64_t>((nl + RED_BLOCK - 1) / RED_BLOCK,
+                                                                                   RED_NBLK)));
+      d.nflt = std::max(d.nflt, c->nc > 0 ? m.n_float : 0);
+      d.nc_blk = std::max(d.nc_blk, (c->nc + 3) / 4);
+      d.elem_blk = std::max(d.elem_blk, (m.nelem + 127) / 128);
+      d.erow_blk = std::max(d.erow_blk, (int)(((int64_t)m.nelem * m.edof + 255) / 256));
+      d.max_ns = std::max(d.max_ns, m.max_ns);
+      const MeshHost& h = c->mh;
+      for (int s = 0; s < (int)h.subs.size(); ++s) {
+        for (int t = 0; t * 64 < h.subs[s].ns; ++t) { fi.push_back(p); fi.push_back(s); fi.push_back(t); }
+        for (int t = 0; t * 64 < h.subs[s].nb; ++t) { ii.push_back(p); ii.push_back(s); ii.push_back(t); }
+      }
+    }
+    int32_t *dfi = nullptr, *dii = nullptr;
+    if ((rc = bupload(b, &dfi, fi)) || (rc = bupload(b, &dii, ii)) || (rc = balloc(b, &b->d_probs, nprob)) ||
+        (rc = balloc(b, &b->d_vals, nprob)))
+      return bad(rc, "");
+    d.full_items = dfi;
+    d.iface_items = dii;
+    d.n_full_items = (int)(fi.size() / 3);
+    d.n_iface_items = (int)(ii.size() / 3);
+    if (hipHostMalloc((void**)&b->h_vals, nprob * sizeof(BStepVals), hipHostMallocDefault) != hipSuccess)
+      return bad(FETI_ENOMEM, "");
+  }
   if (hipEventCreate(&b->e0) != hipSuccess || hipEventCreate(&b->e1) != hipSuccess) return bad(FETI_EHIP, "");
   const int maxg = pcg_batch_max_grid(b->max_nb);
   (void)hipGetLastError();
@@ -1867,6 +2041,7 @@ int feti_batch_destroy(feti_batch b) {
   (void)hipStreamSynchronize(b->stream);
   for (void* p : b->allocs) (void)hipFree(p);
   if (b->h_buf) (void)hipHostFree(b->h_buf);
+  if (b->h_vals) (void)hipHostFree(b->h_vals);
   if (b->e0) (void)hipEventDestroy(b->e0);
   if (b->e1) (void)hipEventDestroy(b->e1);
   delete b;
@@ -1909,60 +2084,59 @@ int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts*
   std::vector<feti_stats> acc(P);
   for (auto& s : acc) std::memset(&s, 0, sizeof(s));
   hipStream_t st = b->stream;
+  BRC(sync_probs(b));
   BCHK(hipEventRecord(b->ctx[0]->ev[0], st));
-  bool cold = false;
+  // per-problem step values: the load, the start of the first solve, the warm correction
+  bool cold = false, any_cand = false;
   for (int p = 0; p < P; ++p) {
     feti_ctx ctx = b->ctx[p];
-    DevMesh& m = ctx->dm;
-    launch_rhs(m, ctx->u, ctx->f, ctx->mpP, ctx->mpE, make_load(ctx, &loads[p]), st);
+    BStepVals& v = b->h_vals[p];
+    v.L = make_load(ctx, &loads[p]);
     int used = o->start;
     if (o->start == FETI_START_ZERO || !ctx->have_prev) {
-      launch_zero(m.n_lambda, ctx->lam, st);
+      v.a_prev = 0.0; v.b_prev2 = 0.0;
       used = FETI_START_ZERO;
     } else if (o->start == FETI_START_EXTRAPOLATE && ctx->have_prev2) {
-      launch_axpby(m.n_lambda, 2.0, ctx->lam_prev, -1.0, ctx->lam_prev2, ctx->lam, st);
+      v.a_prev = 2.0; v.b_prev2 = -1.0;
     } else {
-      launch_axpby(m.n_lambda, 1.0, ctx->lam_prev, 0.0, nullptr, ctx->lam, st);
+      v.a_prev = 1.0; v.b_prev2 = 0.0;
       used = FETI_START_PREVIOUS;
     }
+    v.cand = o->corr_start == FETI_CORR_PREVIOUS && ctx->have_dlam_prev ? 1 : 0;
+    any_cand = any_cand || v.cand;
     acc[p].start_used = used;
     cold = cold || !ctx->have_prev;
-    BRC(torn_begin(ctx, o, o->tol, 0.0, ctx->f, nullptr, ctx->lam));
   }
+  BCHK(hipMemcpyAsync(b->d_vals, b->h_vals, P * sizeof(BStepVals), hipMemcpyHostToDevice, st));
+  const BProb* PT = b->d_probs;
+  const BDims& dm = b->dims;
+  launchb_rhs(PT, b->d_vals, dm, st);
+  launchb_start(PT, b->d_vals, dm, st);
+  btorn_begin(b, o->tol, 0.0, o->max_it, BV_F, BV_NONE, BV_LAM, BV_NONE);
+  BCHK(hipGetLastError());
   BRC(run_batch(b, false, !cold, acc));
-  for (int p = 0; p < P; ++p) {
-    acc[p].iters_first = acc[p].iters;
-    BRC(torn_end(b->ctx[p], b->ctx[p]->lam, b->ctx[p]->u));
-  }
+  for (int p = 0; p < P; ++p) acc[p].iters_first = acc[p].iters;
+  btorn_end(b, BV_LAM, BV_U);
   const int nref = cold ? std::max(o->ir_cold, o->ir_max) : o->ir_max;
   for (int k = 0; k < nref; ++k) {
-    for (int p = 0; p < P; ++p) {
-      feti_ctx ctx = b->ctx[p];
-      torn_residual(ctx, ctx->f, ctx->u, ctx->lam);
-      launch_zero(ctx->dm.n_lambda, ctx->dlam, st);
-      const bool warm = k == 0 && o->corr_start == FETI_CORR_PREVIOUS && ctx->have_dlam_prev;
-      BRC(torn_begin(ctx, o, o->tol_corr, o->tol_upd, ctx->rf, ctx->cj, ctx->dlam, warm ? ctx->dlam_prev : nullptr));
-    }
+    btorn_residual(b);
+    launchb_axpby(PT, dm, BL_LAMBDA, 0.0, BV_NONE, 0.0, BV_NONE, BV_DLAM, st);
+    btorn_begin(b, o->tol_corr, o->tol_upd, o->max_it, BV_RF, BV_CJ, BV_DLAM, k == 0 && any_cand ? BV_DLAMP : BV_NONE);
+    BCHK(hipGetLastError());
     BRC(run_batch(b, true, false, acc));
-    for (int p = 0; p < P; ++p) {
-      feti_ctx ctx = b->ctx[p];
-      BRC(torn_end(ctx, ctx->dlam, ctx->du));
-      launch_axpby(ctx->dm.sum_ns, 1.0, ctx->u, 1.0, ctx->du, ctx->u, st);
-      launch_axpby(ctx->dm.n_lambda, 1.0, ctx->lam, 1.0, ctx->dlam, ctx->lam, st);
-      launch_axpby(ctx->dm.n_lambda, 1.0, ctx->dlam, k == 0 ? 0.0 : 1.0, k == 0 ? nullptr : ctx->dlam_sum,
-                   ctx->dlam_sum, st);
-      acc[p].ir_steps += 1;
-    }
+    btorn_end(b, BV_DLAM, BV_DU);
+    launchb_axpby(PT, dm, BL_TORN, 1.0, BV_U, 1.0, BV_DU, BV_U, st);
+    launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_LAM, 1.0, BV_DLAM, BV_LAM, st);
+    launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_DLAM, k == 0 ? 0.0 : 1.0, k == 0 ? BV_NONE : BV_DLAMS, BV_DLAMS, st);
+    for (int p = 0; p < P; ++p) acc[p].ir_steps += 1;
   }
+  // histories: this step's total correction, and lam_prev2 <- lam_prev <- lam
+  if (nref > 0) launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_DLAMS, 0.0, BV_NONE, BV_DLAMP, st);
+  launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_LAMP, 0.0, BV_NONE, BV_LAMP2, st);
+  launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_LAM, 0.0, BV_NONE, BV_LAMP, st);
   for (int p = 0; p < P; ++p) {
     feti_ctx ctx = b->ctx[p];
-    if (nref > 0) std::swap(ctx->dlam_prev, ctx->dlam_sum);
     ctx->have_dlam_prev = nref > 0;
-  }
-  for (int p = 0; p < P; ++p) {
-    feti_ctx ctx = b->ctx[p];
-    std::swap(ctx->lam_prev2, ctx->lam_prev);
-    launch_axpby(ctx->dm.n_lambda, 1.0, ctx->lam, 0.0, nullptr, ctx->lam_prev, st);
     ctx->have_prev2 = ctx->have_prev;
     ctx->have_prev = true;
     ctx->nstep += 1;

@@ -6,6 +6,7 @@
 // a cell) whose elements share no node; the right-hand side and the product
 // write per-element contributions that a second kernel sums per DOF in a fixed
 // element order.
+#include "bstep.h"
 #include "kernels.h"
 #include "fem_device.h"
 #include "loads_device.h"
@@ -138,10 +139,10 @@ __device__ inline void raw_boundary_terms(const LoadDev& L, bool poro, const int
 // rows of poroelastic elements (whose eta terms come before the lifting).  Rows without
 // eta terms do not change from step to step; k_rhs_prows forms the p rows of later
 // steps from their load parts with the same terms in the same order.
-__global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __restrict__ eta_prev,
-                                                  MatParams mpP, MatParams mpE, LoadDev L, double* cache,
-                                                  int cmode) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rhs_elem_body(const DevMesh& m, const double* __restrict__ eta_prev,
+                                              const MatParams& mpP, const MatParams& mpE, const LoadDev& L,
+                                              double* cache, int cmode, int bx) {
+  const int64_t e = (int64_t)bx * blockDim.x + threadIdx.x;
   if (e >= m.nelem) return;
   const int edof = m.edof, order = m.order, ncell = m.ncell;
   const int s = m.el_sub[e];
@@ -234,6 +235,12 @@ __global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __res
   }
 }
 
+__global__ void __launch_bounds__(128) k_rhs_elem(DevMesh m, const double* __restrict__ eta_prev,
+                                                  MatParams mpP, MatParams mpE, LoadDev L, double* cache,
+                                                  int cmode) {
+  rhs_elem_body(m, eta_prev, mpP, mpE, L, cache, cmode, blockIdx.x);
+}
+
 // A later step of a time-independent load (cmode 2): one thread per p row of every
 // element (elastic elements return at once) rewrites that row of the cached element
 // contributions from its load part: the eta moments, then the lifting columns in
@@ -290,8 +297,8 @@ __global__ void k_elem_store(DevMesh m, MatParams mpP, MatParams mpE) {
 }
 
 // One thread per (element, row): ebuf[e][row] = (K_e x_e)[row], K_e read from emat
-__global__ void k_elem_matvec(DevMesh m, const double* __restrict__ x) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void elem_matvec_body(const DevMesh& m, const double* __restrict__ x, int bx) {
+  const int64_t gid = (int64_t)bx * blockDim.x + threadIdx.x;
   const int edof = m.edof;
   const int64_t e = gid / edof;
   const int r = (int)(gid % edof);
@@ -309,14 +316,19 @@ __global__ void k_elem_matvec(DevMesh m, const double* __restrict__ x) {
   m.ebuf[gid] = acc;
 }
 
+__global__ void k_elem_matvec(DevMesh m, const double* __restrict__ x) { elem_matvec_body(m, x, blockIdx.x); }
+
 // y_i = sum of the element contributions of torn DOF i, in element order
-__global__ void k_gather_elem(DevMesh m, double* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gather_elem_body(const DevMesh& m, const double* __restrict__ ebuf,
+                                                 double* __restrict__ y, int bx) {
+  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
   if (i >= m.sum_ns) return;
   double s = 0.0;
-  for (int k = m.adj_ptr[i]; k < m.adj_ptr[i + 1]; ++k) s += m.ebuf[m.adj[k]];
+  for (int k = m.adj_ptr[i]; k < m.adj_ptr[i + 1]; ++k) s += ebuf[m.adj[k]];
   y[i] = s;
 }
+
+__global__ void k_gather_elem(DevMesh m, double* __restrict__ y) { gather_elem_body(m, m.ebuf, y, blockIdx.x); }
 
 // eta^0 at every local eta DOF (nodal interpolation of c0 p0 + alpha div u0)
 __global__ void k_init_eta(const int32_t* __restrict__ code, double* __restrict__ u, int64_t n,
@@ -416,6 +428,33 @@ void launch_elem_matvec(const DevMesh& m, const double* x, double* y, MatParams 
   const int64_t nthreads = (int64_t)m.nelem * m.edof;
   hipLaunchKernelGGL(k_elem_matvec, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, m, x);
   hipLaunchKernelGGL(k_gather_elem, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, m, y);
+}
+
+// ---- batched launches (problem = blockIdx.y) ----------------------------------
+
+__global__ void __launch_bounds__(128) kb_rhs_elem(const BProb* __restrict__ P, const BStepVals* __restrict__ V) {
+  const BProb& p = P[blockIdx.y];
+  rhs_elem_body(p.m, p.v[BV_U], p.mpP, p.mpE, V[blockIdx.y].L, nullptr, 0, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) kb_elem_matvec(const BProb* __restrict__ P, int x) {
+  const BProb& p = P[blockIdx.y];
+  elem_matvec_body(p.m, p.v[x], blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) kb_gather_elem(const BProb* __restrict__ P, int y) {
+  const BProb& p = P[blockIdx.y];
+  gather_elem_body(p.m, p.m.ebuf, p.v[y], blockIdx.x);
+}
+
+void launchb_rhs(const BProb* P, const BStepVals* V, const BDims& d, hipStream_t st) {
+  hipLaunchKernelGGL(kb_rhs_elem, dim3(d.elem_blk, d.P), dim3(128), 0, st, P, V);
+  hipLaunchKernelGGL(kb_gather_elem, dim3(d.ns_blk, d.P), dim3(256), 0, st, P, (int)BV_F);
+}
+
+void launchb_elem_matvec(const BProb* P, const BDims& d, int x, int y, hipStream_t st) {
+  hipLaunchKernelGGL(kb_elem_matvec, dim3(d.erow_blk, d.P), dim3(256), 0, st, P, x);
+  hipLaunchKernelGGL(kb_gather_elem, dim3(d.ns_blk, d.P), dim3(256), 0, st, P, y);
 }
 
 }  // namespace feti

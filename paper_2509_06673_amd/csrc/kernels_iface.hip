@@ -5,6 +5,7 @@
 // vector updates and deterministic reductions of projected PCG.
 #include <algorithm>
 
+#include "bstep.h"
 #include "kernels.h"
 #include "iface.h"
 #include "iface_device.h"
@@ -104,7 +105,7 @@ __device__ inline void block_sums(double (&v)[NPART], double (*red)[NV]) {
 
 template <int NV>
 __device__ void reduce_and_finalize(double (&acc)[NPART], double* __restrict__ part, int32_t* __restrict__ counter,
-                                    double* __restrict__ sc, int32_t* __restrict__ ist, int phase) {
+                                    double* __restrict__ sc, int32_t* __restrict__ ist, int phase, int bx, int nbx) {
   constexpr int NW = RED_BLOCK / 64;
   __shared__ double red[NW][NV];
   __shared__ int is_last;
@@ -114,17 +115,17 @@ __device__ void reduce_and_finalize(double (&acc)[NPART], double* __restrict__ p
   if (threadIdx.x < NV) {
     double x = 0.0;
     for (int w = 0; w < NW; ++w) x += red[w][threadIdx.x];
-    __hip_atomic_store(part + blockIdx.x * NPART + threadIdx.x, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(part + bx * NPART + threadIdx.x, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __syncthreads();
   if (threadIdx.x == 0)
-    is_last = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (int)gridDim.x - 1;
+    is_last = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nbx - 1;
   __syncthreads();
   if (!is_last) return;
-  const int nblk = gridDim.x;
+  const int nblk = nbx;
   double v[NPART];
 #pragma unroll
   for (int c = 0; c < NPART; ++c) v[c] = 0.0;
@@ -155,12 +156,12 @@ __device__ void reduce_and_finalize(double (&acc)[NPART], double* __restrict__ p
 // MT is the stored matrix type (double, or float for the FP32 factors); vectors
 // and accumulation are FP64.
 template <int FULL, class MT>
-__global__ void __launch_bounds__(256) k_sgemv(DevMesh m, GemvArgs a) {
+__device__ __forceinline__ void sgemv_body(const DevMesh& m, const GemvArgs& a, int bx, int s) {
   if (a.skip && *a.skip) return;
-  const int s = blockIdx.y;
+  if (s >= m.nsub) return;
   const int ns = m.ns[s], nbs = m.nb[s];
   const int n = FULL ? ns : nbs;
-  const int row0 = blockIdx.x * 64;
+  const int row0 = bx * 64;
   if (row0 >= n) return;
   extern __shared__ double smem[];
   double* xs = smem;              // n
@@ -224,20 +225,25 @@ __global__ void __launch_bounds__(256) k_sgemv(DevMesh m, GemvArgs a) {
   }
 }
 
+template <int FULL, class MT>
+__global__ void __launch_bounds__(256) k_sgemv(DevMesh m, GemvArgs a) {
+  sgemv_body<FULL, MT>(m, a, blockIdx.x, blockIdx.y);
+}
+
 // Blocks [0, nlb): out_j = jump_row(yb).  Blocks [nlb, nlb + n_float) (when g is
 // given): g_f = R_b^T B_s^T out for the floating subdomain s = float_sub[f],
 // evaluated from yb directly, so G^T out needs no second pass.
-__global__ void __launch_bounds__(256) k_jump(DevMesh m, const double* __restrict__ yb, int from_torn,
-                                              double* __restrict__ out, int scaled,
-                                              double* __restrict__ g, int nlb,
-                                              const int32_t* __restrict__ skip) {
+__device__ __forceinline__ void jump_body(const DevMesh& m, const double* __restrict__ yb, int from_torn,
+                                          double* __restrict__ out, int scaled, double* __restrict__ g, int nlb,
+                                          const int32_t* __restrict__ skip, int bx) {
   if (skip && *skip) return;
-  if ((int)blockIdx.x < nlb) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (bx < nlb) {
+    const int64_t j = (int64_t)bx * blockDim.x + threadIdx.x;
     if (j < m.n_lambda) out[j] = jump_row(m, yb, from_torn, j, scaled);
     return;
   }
-  const int f = blockIdx.x - nlb;
+  const int f = bx - nlb;
+  if (!g || f >= m.n_float) return;
   const int s = m.float_sub[f];
   const int nbs = m.nb[s];
   const int64_t b0 = m.boff[s];
@@ -265,14 +271,20 @@ __global__ void __launch_bounds__(256) k_jump(DevMesh m, const double* __restric
   if (threadIdx.x < 3) g[3 * f + threadIdx.x] = red[threadIdx.x][0];
 }
 
+__global__ void __launch_bounds__(256) k_jump(DevMesh m, const double* __restrict__ yb, int from_torn,
+                                              double* __restrict__ out, int scaled,
+                                              double* __restrict__ g, int nlb,
+                                              const int32_t* __restrict__ skip) {
+  jump_body(m, yb, from_torn, out, scaled, g, nlb, skip, blockIdx.x);
+}
+
 // g_f = R_s^T x_s for each floating subdomain s = float_sub[f], with
 // x_s = base_s + gsign * B_s^T v (base torn and/or v multipliers).
-__global__ void __launch_bounds__(256) k_coarse_g(DevMesh m, const double* __restrict__ v,
-                                                  const double* __restrict__ base, double gsign,
-                                                  double* __restrict__ g,
-                                                  const int32_t* __restrict__ skip) {
+__device__ __forceinline__ void coarse_g_body(const DevMesh& m, const double* __restrict__ v,
+                                              const double* __restrict__ base, double gsign, double* __restrict__ g,
+                                              const int32_t* __restrict__ skip, int f) {
   if (skip && *skip) return;
-  const int f = blockIdx.x;
+  if (f >= m.n_float) return;
   const int s = m.float_sub[f];
   const int ns = m.ns[s], nbs = m.nb[s], first_b = ns - nbs;
   const int64_t so = m.soff[s];
@@ -297,13 +309,19 @@ __global__ void __launch_bounds__(256) k_coarse_g(DevMesh m, const double* __res
   if (threadIdx.x < 3) g[3 * f + threadIdx.x] = red[threadIdx.x][0];
 }
 
+__global__ void __launch_bounds__(256) k_coarse_g(DevMesh m, const double* __restrict__ v,
+                                                  const double* __restrict__ base, double gsign,
+                                                  double* __restrict__ g,
+                                                  const int32_t* __restrict__ skip) {
+  coarse_g_body(m, v, base, gsign, g, skip, blockIdx.x);
+}
+
 // a = scale * Cinv g (Cinv symmetric n_c x n_c): one wavefront per row
-__global__ void __launch_bounds__(256) k_coarse_apply(int nc, const double* __restrict__ C,
-                                                      const double* __restrict__ g,
-                                                      double* __restrict__ a, double scale,
-                                                      const int32_t* __restrict__ skip) {
+__device__ __forceinline__ void coarse_apply_body(int nc, const double* __restrict__ C, const double* __restrict__ g,
+                                                  double* __restrict__ a, double scale,
+                                                  const int32_t* __restrict__ skip, int bx) {
   if (skip && *skip) return;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int row = bx * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= nc) return;
   const double* Cr = C + (int64_t)row * nc;
@@ -313,14 +331,27 @@ __global__ void __launch_bounds__(256) k_coarse_apply(int nc, const double* __re
   if (lane == 0) a[row] = scale * s;
 }
 
+__global__ void __launch_bounds__(256) k_coarse_apply(int nc, const double* __restrict__ C,
+                                                      const double* __restrict__ g,
+                                                      double* __restrict__ a, double scale,
+                                                      const int32_t* __restrict__ skip) {
+  coarse_apply_body(nc, C, g, a, scale, skip, blockIdx.x);
+}
+
 // v_j = vin_j + scale * (G a)_j, (G a)_j = sum_e sign_e R_b(gb_e) . a_{float(sub(gb_e))}
+__device__ __forceinline__ void coarse_correct_body(const DevMesh& m, const double* __restrict__ a, double scale,
+                                                    const double* __restrict__ vin, double* __restrict__ v,
+                                                    const int32_t* __restrict__ skip, int bx) {
+  if (skip && *skip) return;
+  const int64_t j = (int64_t)bx * blockDim.x + threadIdx.x;
+  if (j >= m.n_lambda) return;
+  v[j] = (vin ? vin[j] : 0.0) + scale * coarse_G_row(m, a, j);
+}
+
 __global__ void k_coarse_correct(DevMesh m, const double* __restrict__ a, double scale,
                                  const double* __restrict__ vin, double* __restrict__ v,
                                  const int32_t* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m.n_lambda) return;
-  v[j] = (vin ? vin[j] : 0.0) + scale * coarse_G_row(m, a, j);
+  coarse_correct_body(m, a, scale, vin, v, skip, blockIdx.x);
 }
 
 // v = vin - G a (a may be null: v = vin), then (x, v) reduced; the last block runs phase
@@ -342,7 +373,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_correct_dot(DevMesh m, const doub
     v[j] = vj;
     acc[0] += x[j] * vj;
   }
-  reduce_and_finalize<1>(acc, part, counter, sc, ist, phase);
+  reduce_and_finalize<1>(acc, part, counter, sc, ist, phase, blockIdx.x, gridDim.x);
 }
 
 // G^T G, one thread per entry (r, c): sum over the jump rows of subdomain float_sub[r/3]
@@ -376,21 +407,18 @@ __global__ void k_gtg(DevMesh m, double* __restrict__ C, int nc) {
 // Reductions over the multipliers: slot 0: (x, y); slots 2..7: per-kind |nrm|^2;
 // slots 8..13: per-kind sum_j |mdiag_j| nrm_j^2 (any pointer may be null); the
 // last block runs the scalar phase.
-__global__ void __launch_bounds__(RED_BLOCK) k_reduce(DevMesh m, const double* __restrict__ x,
-                                                      const double* __restrict__ y,
-                                                      const double* __restrict__ nrm,
-                                                      const double* __restrict__ mdiag,
-                                                      double* __restrict__ part,
-                                                      int32_t* __restrict__ counter,
-                                                      double* __restrict__ sc,
-                                                      int32_t* __restrict__ ist, int phase) {
+__device__ __forceinline__ void reduce_body(const DevMesh& m, const double* __restrict__ x,
+                                            const double* __restrict__ y, const double* __restrict__ nrm,
+                                            const double* __restrict__ mdiag, double* __restrict__ part,
+                                            int32_t* __restrict__ counter, double* __restrict__ sc,
+                                            int32_t* __restrict__ ist, int phase, int bx, int nbx) {
   if (ist[IS_DONE] && phase != PH_INIT && phase != PH_REFNORM) return;
   double acc[NPART];
 #pragma unroll
   for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
   const int64_t n = m.n_lambda;
-  const int64_t stride = (int64_t)gridDim.x * RED_BLOCK;
-  for (int64_t j = (int64_t)blockIdx.x * RED_BLOCK + threadIdx.x; j < n; j += stride) {
+  const int64_t stride = (int64_t)nbx * RED_BLOCK;
+  for (int64_t j = (int64_t)bx * RED_BLOCK + threadIdx.x; j < n; j += stride) {
     if (x) acc[0] += x[j] * y[j];
     if (nrm) {
       const double v2 = nrm[j] * nrm[j], e2 = fabs(mdiag[j]) * v2;
@@ -402,7 +430,18 @@ __global__ void __launch_bounds__(RED_BLOCK) k_reduce(DevMesh m, const double* _
       }
     }
   }
-  reduce_and_finalize<14>(acc, part, counter, sc, ist, phase);
+  reduce_and_finalize<14>(acc, part, counter, sc, ist, phase, bx, nbx);
+}
+
+__global__ void __launch_bounds__(RED_BLOCK) k_reduce(DevMesh m, const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const double* __restrict__ nrm,
+                                                      const double* __restrict__ mdiag,
+                                                      double* __restrict__ part,
+                                                      int32_t* __restrict__ counter,
+                                                      double* __restrict__ sc,
+                                                      int32_t* __restrict__ ist, int phase) {
+  reduce_body(m, x, y, nrm, mdiag, part, counter, sc, ist, phase, blockIdx.x, gridDim.x);
 }
 
 // M_jj = sum over the interface DOFs b of row j's group of (B^T D)[b, j]^2 S_bb[b, b]
@@ -463,7 +502,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_cg_lam(DevMesh m, const double* _
       acc[20 + c] += c == k ? lj * lj : 0.0;
     }
   }
-  reduce_and_finalize<26>(acc, part, counter, sc, ist, PH_CONV);
+  reduce_and_finalize<26>(acc, part, counter, sc, ist, PH_CONV, blockIdx.x, gridDim.x);
 }
 
 // p = y + beta p
@@ -476,11 +515,16 @@ __global__ void k_cg_p(int64_t n, const double* __restrict__ sc, const int32_t* 
 }
 
 // z = a x + b y (plain vector combination)
+__device__ __forceinline__ void axpby_body(int64_t n, double a, const double* __restrict__ x, double b,
+                                           const double* __restrict__ y, double* __restrict__ z, int bx) {
+  const int64_t j = (int64_t)bx * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  z[j] = (x ? a * x[j] : 0.0) + (y ? b * y[j] : 0.0);
+}
+
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
                         const double* __restrict__ y, double* __restrict__ z) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  z[j] = a * x[j] + (y ? b * y[j] : 0.0);
+  axpby_body(n, a, x, b, y, z, blockIdx.x);
 }
 
 // copy a dense block (rows x cols) between leading dimensions, batched
@@ -498,10 +542,15 @@ __global__ void k_copy_block(const int64_t* __restrict__ src_ofs, const int32_t*
 }
 
 // r_b -= B_s^T lam on every interface DOF (torn vector r)
-__global__ void k_sub_gather(DevMesh m, const double* __restrict__ lam, double* __restrict__ r) {
-  const int64_t gb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sub_gather_body(const DevMesh& m, const double* __restrict__ lam,
+                                                double* __restrict__ r, int bx) {
+  const int64_t gb = (int64_t)bx * blockDim.x + threadIdx.x;
   if (gb >= m.sum_nb) return;
   r[m.b_torn[gb]] -= gather_b(m, lam, gb, G_SIGNED);
+}
+
+__global__ void k_sub_gather(DevMesh m, const double* __restrict__ lam, double* __restrict__ r) {
+  sub_gather_body(m, lam, r, blockIdx.x);
 }
 
 // per-block, per-kind max |x| and max |y| over a torn vector (kinds from the DOF codes)
@@ -545,11 +594,13 @@ __global__ void k_copy_scalar(double* __restrict__ sc, int src, int dst) {
   if (threadIdx.x == 0) sc[dst] = sc[src];
 }
 
-__global__ void k_pick_start(int64_t n, const double* __restrict__ sc, const double* __restrict__ alt,
-                             double* __restrict__ lam, int32_t* __restrict__ flag, const double* __restrict__ alt2,
-                             double* __restrict__ dst2, const double* __restrict__ alt3, double* __restrict__ dst3) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool take = sc[SC_SEL1] < sc[SC_SEL0];
+__device__ __forceinline__ void pick_start_body(int64_t n, const double* __restrict__ sc, const double* __restrict__ alt,
+                                                double* __restrict__ lam, int32_t* __restrict__ flag,
+                                                const double* __restrict__ alt2, double* __restrict__ dst2,
+                                                const double* __restrict__ alt3, double* __restrict__ dst3, bool allow,
+                                                int bx) {
+  const int64_t j = (int64_t)bx * blockDim.x + threadIdx.x;
+  const bool take = allow && sc[SC_SEL1] < sc[SC_SEL0];
   if (j == 0 && flag) *flag = take ? 1 : 0;
   if (j >= n || !take) return;
   lam[j] = alt[j];
@@ -557,18 +608,24 @@ __global__ void k_pick_start(int64_t n, const double* __restrict__ sc, const dou
   if (alt3) dst3[j] = alt3[j];
 }
 
+__global__ void k_pick_start(int64_t n, const double* __restrict__ sc, const double* __restrict__ alt,
+                             double* __restrict__ lam, int32_t* __restrict__ flag, const double* __restrict__ alt2,
+                             double* __restrict__ dst2, const double* __restrict__ alt3, double* __restrict__ dst3) {
+  pick_start_body(n, sc, alt, lam, flag, alt2, dst2, alt3, dst3, true, blockIdx.x);
+}
+
 // 64 rows per block; the four wavefronts split the coarse index, wavefront 0 finishes
-__global__ void __launch_bounds__(256) k_h_project(int64_t n, int nc, const double* __restrict__ H,
-                                                   const double* __restrict__ a, const double* __restrict__ b,
-                                                   const double* __restrict__ g1, const double* __restrict__ g2,
-                                                   double* __restrict__ out, double* __restrict__ r_out,
-                                                   double* __restrict__ out2) {
+__device__ __forceinline__ void h_project_body(int64_t n, int nc, const double* __restrict__ H,
+                                               const double* __restrict__ a, const double* __restrict__ b,
+                                               const double* __restrict__ g1, const double* __restrict__ g2,
+                                               double* __restrict__ out, double* __restrict__ r_out,
+                                               double* __restrict__ out2, int bx) {
   __shared__ double gl[HPROJ_NC_MAX];
   __shared__ double red[4][64];
   for (int k = threadIdx.x; k < nc; k += blockDim.x) gl[k] = g1[k] - (g2 ? g2[k] : 0.0);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t j = (int64_t)bx * 64 + lane;
   const int cq = (nc + 3) / 4, cb = wave * cq, ce = min(nc, cb + cq);
   double acc = 0.0;
   if (j < n)
@@ -590,6 +647,14 @@ __global__ void __launch_bounds__(256) k_h_project(int64_t n, int nc, const doub
     out[j] = o;
     if (out2) out2[j] = o;
   }
+}
+
+__global__ void __launch_bounds__(256) k_h_project(int64_t n, int nc, const double* __restrict__ H,
+                                                   const double* __restrict__ a, const double* __restrict__ b,
+                                                   const double* __restrict__ g1, const double* __restrict__ g2,
+                                                   double* __restrict__ out, double* __restrict__ r_out,
+                                                   double* __restrict__ out2) {
+  h_project_body(n, nc, H, a, b, g1, g2, out, r_out, out2, blockIdx.x);
 }
 
 // ---- launchers ---------------------------------------------------------------
@@ -793,6 +858,188 @@ __global__ void k_to_f64(int64_t n, const float* __restrict__ src, double* __res
 void launch_to_f64(int64_t n, const float* src, double* dst, hipStream_t st) {
   const int blk = 256;
   hipLaunchKernelGGL(k_to_f64, dim3((unsigned)((n + blk - 1) / blk)), dim3(blk), 0, st, n, src, dst);
+}
+
+// ---- batched launches: the same operation on every problem of a batch --------
+// The problem is the last grid dimension; each problem's blocks beyond its own need
+// return at once.  Vectors are named by role (BVec), so that one launch reaches the
+// same vector of every problem.
+
+__device__ inline int64_t blen(const BProb& p, int len) { return len == BL_TORN ? p.m.sum_ns : p.m.n_lambda; }
+__device__ inline double* bvec(const BProb& p, int r) { return r >= 0 ? p.v[r] : nullptr; }
+
+__global__ void __launch_bounds__(256) kb_axpby(const BProb* __restrict__ P, int len, double a, int x, double b, int y,
+                                                int z) {
+  const BProb& p = P[blockIdx.y];
+  axpby_body(blen(p, len), a, bvec(p, x), b, bvec(p, y), p.v[z], blockIdx.x);
+}
+
+// start of the first solve: lam = a lam_prev + b lam_prev2 (terms with a zero
+// coefficient are not read)
+__global__ void __launch_bounds__(256) kb_start(const BProb* __restrict__ P, const BStepVals* __restrict__ V) {
+  const BProb& p = P[blockIdx.y];
+  const BStepVals& v = V[blockIdx.y];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= p.m.n_lambda) return;
+  const double* lp = p.v[BV_LAMP];
+  const double* lp2 = p.v[BV_LAMP2];
+  double x = 0.0;
+  if (v.a_prev != 0.0) x = v.a_prev * lp[j] + (v.b_prev2 != 0.0 ? v.b_prev2 * lp2[j] : 0.0);
+  p.v[BV_LAM][j] = x;
+}
+
+template <int FULL, class MT>
+__global__ void __launch_bounds__(256) kb_sgemv(const BProb* __restrict__ P, BGemv g, const int32_t* __restrict__ items) {
+  // work item blockIdx.x: (problem, subdomain, 64-row tile)
+  const int32_t* it = items + 3 * (int64_t)blockIdx.x;
+  const BProb& p = P[it[0]];
+  GemvArgs a;
+  a.A = g.mat == BM_KINV ? p.kinv : (g.mat == BM_SPLUS ? p.splus : p.sbb);
+  a.a_f32 = p.f32;
+  a.aofs = FULL ? p.m.kofs : p.m.sofs;
+  a.lda = FULL ? p.m.ld : p.m.ldb;
+  a.which_n = FULL ? 0 : 1;
+  a.xbase = bvec(p, g.xbase);
+  a.v = bvec(p, g.v);
+  a.gmode = g.gmode;
+  a.gcoef = g.gcoef;
+  a.y = p.v[g.y];
+  a.alpha_c = p.nc > 0 ? bvec(p, g.alpha_c) : nullptr;
+  a.kb_only = g.kb_only;
+  a.ybase = bvec(p, g.ybase);
+  sgemv_body<FULL, MT>(p.m, a, it[2], it[1]);
+}
+
+__global__ void __launch_bounds__(256) kb_jump(const BProb* __restrict__ P, int yb, int from_torn, int out, int scaled,
+                                               int g) {
+  const BProb& p = P[blockIdx.y];
+  const int nlb = (int)((p.m.n_lambda + 255) / 256);
+  jump_body(p.m, p.v[yb], from_torn, p.v[out], scaled, p.nc > 0 ? bvec(p, g) : nullptr, nlb, nullptr, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) kb_coarse_g(const BProb* __restrict__ P, int v, int base, double gsign, int g) {
+  const BProb& p = P[blockIdx.y];
+  if (p.nc == 0) return;
+  coarse_g_body(p.m, bvec(p, v), bvec(p, base), gsign, p.v[g], nullptr, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) kb_coarse_apply(const BProb* __restrict__ P, int g, int a, double scale) {
+  const BProb& p = P[blockIdx.y];
+  if (p.nc == 0) return;
+  coarse_apply_body(p.nc, p.Cinv, p.v[g], p.v[a], scale, nullptr, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) kb_coarse_correct(const BProb* __restrict__ P, int a, double scale, int vin,
+                                                         int v) {
+  const BProb& p = P[blockIdx.y];
+  if (p.nc == 0 && vin == v) return;  // no coarse space: v = vin
+  coarse_correct_body(p.m, p.v[a], p.nc > 0 ? scale : 0.0, bvec(p, vin), p.v[v], nullptr, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) kb_h_project(const BProb* __restrict__ P, int a, int b, int g1, int g2, int out,
+                                                    int r_out, int out2) {
+  const BProb& p = P[blockIdx.y];
+  h_project_body(p.m.n_lambda, p.nc, p.H, p.v[a], bvec(p, b), p.v[g1], bvec(p, g2), p.v[out], bvec(p, r_out),
+                 bvec(p, out2), blockIdx.x);
+}
+
+__global__ void __launch_bounds__(RED_BLOCK) kb_reduce(const BProb* __restrict__ P, int x, int y, int nrm, int phase) {
+  const BProb& p = P[blockIdx.y];
+  reduce_body(p.m, bvec(p, x), bvec(p, y), bvec(p, nrm), p.mdiag, p.part, p.ist + IS_CNT0 + phase, p.sc, p.ist, phase,
+              blockIdx.x, gridDim.x);
+}
+
+__global__ void kb_init_scalars(const BProb* __restrict__ P, double tol, double utol, int maxit) {
+  const BProb& p = P[blockIdx.y];
+  const int t = threadIdx.x;
+  if (t < SC_COUNT) p.sc[t] = t == SC_TOL ? tol : (t == SC_UTOL ? utol : 0.0);
+  if (t < IS_COUNT) p.ist[t] = t == IS_MAXIT ? maxit : 0;
+}
+
+__global__ void kb_copy_scalar(const BProb* __restrict__ P, int src, int dst) {
+  const BProb& p = P[blockIdx.y];
+  if (threadIdx.x == 0) p.sc[dst] = p.sc[src];
+}
+
+__global__ void __launch_bounds__(256) kb_pick_start(const BProb* __restrict__ P, const BStepVals* __restrict__ V,
+                                                     int alt, int lam, int alt2, int dst2, int alt3, int dst3) {
+  const BProb& p = P[blockIdx.y];
+  pick_start_body(p.m.n_lambda, p.sc, p.v[alt], p.v[lam], nullptr, bvec(p, alt2), bvec(p, dst2), bvec(p, alt3),
+                  bvec(p, dst3), V[blockIdx.y].cand != 0, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) kb_sub_gather(const BProb* __restrict__ P, int lam, int r) {
+  const BProb& p = P[blockIdx.y];
+  sub_gather_body(p.m, p.v[lam], p.v[r], blockIdx.x);
+}
+
+void launchb_axpby(const BProb* P, const BDims& d, int len, double a, int x, double b, int y, int z, hipStream_t st) {
+  hipLaunchKernelGGL(kb_axpby, dim3(len == BL_TORN ? d.ns_blk : d.nl_blk, d.P), dim3(256), 0, st, P, len, a, x, b, y,
+                     z);
+}
+
+void launchb_start(const BProb* P, const BStepVals* V, const BDims& d, hipStream_t st) {
+  hipLaunchKernelGGL(kb_start, dim3(d.nl_blk, d.P), dim3(256), 0, st, P, V);
+}
+
+void launchb_sgemv(const BProb* P, const BDims& d, const BGemv& g, int f32, hipStream_t st) {
+  const size_t shm = sizeof(double) * ((size_t)d.max_ns + 4 * 64);
+  if (g.full) {
+    if (d.n_full_items == 0) return;
+    const dim3 grid(d.n_full_items);
+    if (f32) hipLaunchKernelGGL((kb_sgemv<1, float>), grid, dim3(256), shm, st, P, g, d.full_items);
+    else hipLaunchKernelGGL((kb_sgemv<1, double>), grid, dim3(256), shm, st, P, g, d.full_items);
+  } else {
+    if (d.n_iface_items == 0) return;
+    const dim3 grid(d.n_iface_items);
+    if (f32) hipLaunchKernelGGL((kb_sgemv<0, float>), grid, dim3(256), shm, st, P, g, d.iface_items);
+    else hipLaunchKernelGGL((kb_sgemv<0, double>), grid, dim3(256), shm, st, P, g, d.iface_items);
+  }
+}
+
+void launchb_jump(const BProb* P, const BDims& d, int yb, int from_torn, int out, int scaled, int g, hipStream_t st) {
+  hipLaunchKernelGGL(kb_jump, dim3(d.nl_blk + (g >= 0 ? d.nflt : 0), d.P), dim3(256), 0, st, P, yb, from_torn, out,
+                     scaled, g);
+}
+
+void launchb_coarse_g(const BProb* P, const BDims& d, int v, int base, double gsign, int g, hipStream_t st) {
+  if (d.nflt == 0) return;
+  hipLaunchKernelGGL(kb_coarse_g, dim3(d.nflt, d.P), dim3(256), 0, st, P, v, base, gsign, g);
+}
+
+void launchb_coarse_apply(const BProb* P, const BDims& d, int g, int a, double scale, hipStream_t st) {
+  if (d.nc_blk == 0) return;
+  hipLaunchKernelGGL(kb_coarse_apply, dim3(d.nc_blk, d.P), dim3(256), 0, st, P, g, a, scale);
+}
+
+void launchb_coarse_correct(const BProb* P, const BDims& d, int a, double scale, int vin, int v, hipStream_t st) {
+  hipLaunchKernelGGL(kb_coarse_correct, dim3(d.nl_blk, d.P), dim3(256), 0, st, P, a, scale, vin, v);
+}
+
+void launchb_h_project(const BProb* P, const BDims& d, int a, int b, int g1, int g2, int out, int r_out, int out2,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(kb_h_project, dim3(d.nl64_blk, d.P), dim3(256), 0, st, P, a, b, g1, g2, out, r_out, out2);
+}
+
+void launchb_reduce(const BProb* P, const BDims& d, int x, int y, int nrm, int phase, hipStream_t st) {
+  hipLaunchKernelGGL(kb_reduce, dim3(d.red_blk, d.P), dim3(RED_BLOCK), 0, st, P, x, y, nrm, phase);
+}
+
+void launchb_init_scalars(const BProb* P, const BDims& d, double tol, double utol, int maxit, hipStream_t st) {
+  hipLaunchKernelGGL(kb_init_scalars, dim3(1, d.P), dim3(64), 0, st, P, tol, utol, maxit);
+}
+
+void launchb_copy_scalar(const BProb* P, const BDims& d, int src, int dst, hipStream_t st) {
+  hipLaunchKernelGGL(kb_copy_scalar, dim3(1, d.P), dim3(64), 0, st, P, src, dst);
+}
+
+void launchb_pick_start(const BProb* P, const BStepVals* V, const BDims& d, int alt, int lam, int alt2, int dst2,
+                        int alt3, int dst3, hipStream_t st) {
+  hipLaunchKernelGGL(kb_pick_start, dim3(d.nl_blk, d.P), dim3(256), 0, st, P, V, alt, lam, alt2, dst2, alt3, dst3);
+}
+
+void launchb_sub_gather(const BProb* P, const BDims& d, int lam, int r, hipStream_t st) {
+  hipLaunchKernelGGL(kb_sub_gather, dim3(d.nb_blk, d.P), dim3(256), 0, st, P, lam, r);
 }
 
 }  // namespace feti
