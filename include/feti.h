@@ -336,10 +336,20 @@ int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts*
 
 /* Launch shape: grid > 0 fixes the number of blocks; grid = 0 (the default) lets the
  * autotuner time candidate grids on the first launches and keep the fastest per
- * iteration.  info: [0] grid in use, [1] 1 once the choice is final, [2] candidates,
- * [3..] the candidate grids (up to 8). */
+ * iteration.  info (12 entries): [0] grid in use, [1] 1 once the choice is final,
+ * [2] candidates, [3..10] the candidate grids (up to 8, zero-padded), [11] 1 if the last
+ * step ran as a captured graph (feti_batch_set_capture). */
 int feti_batch_set_grid(feti_batch b, int32_t grid);
 int feti_batch_info(feti_batch b, int32_t* info_host);
+
+/* Graph capture of the batch step (on by default).  Once the grid is fixed (set, or
+ * chosen by the autotuner), every warm step runs as one hipGraph launch: the step's
+ * kernels, its cooperative interface launches and its copies, captured at the first such
+ * step and captured again when the number of corrections, the warm correction start,
+ * the grid or any solve option changes.  The loads and starts of each step enter through
+ * a pinned staging copy that the graph reads when it runs.  on = 0 runs every step from
+ * the host, launch by launch (same kernels, same order, same results). */
+int feti_batch_set_capture(feti_batch b, int32_t on);
 
 /* ---- inspection (unit parity of each stage) ------------------------------- */
 

@@ -144,6 +144,7 @@ _SIGS = {
     "feti_batch_destroy": [C.c_void_p],
     "feti_batch_step": [C.c_void_p, C.POINTER(Load), C.POINTER(SolveOpts), C.POINTER(Stats)],
     "feti_batch_set_grid": [C.c_void_p, C.c_int32],
+    "feti_batch_set_capture": [C.c_void_p, C.c_int32],
     "feti_batch_info": [C.c_void_p, C.POINTER(C.c_int32)],
     # learned warm start (include/feti_ws.h)
     "feti_ws_create": [C.POINTER(C.c_void_p), C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
@@ -486,7 +487,11 @@ class Batch:
     def set_grid(self, grid: int):
         return self._check(self.lib.feti_batch_set_grid(self.h, grid), "feti_batch_set_grid")
 
+    def set_capture(self, on: bool):
+        return self._check(self.lib.feti_batch_set_capture(self.h, 1 if on else 0), "feti_batch_set_capture")
+
     def info(self):
-        buf = (C.c_int32 * 11)()
+        buf = (C.c_int32 * 12)()
         self._check(self.lib.feti_batch_info(self.h, buf), "feti_batch_info")
-        return {"grid": buf[0], "tuned": bool(buf[1]), "candidates": [buf[3 + k] for k in range(buf[2])]}
+        return {"grid": buf[0], "tuned": bool(buf[1]), "candidates": [buf[3 + k] for k in range(buf[2])],
+                "graph": bool(buf[11])}

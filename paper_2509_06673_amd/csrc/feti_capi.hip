@@ -1682,7 +1682,9 @@ struct feti_batch_s {
   double *alpha = nullptr, *beta = nullptr, *rho = nullptr, *part = nullptr;
   int32_t *done = nullptr, *iters = nullptr, *status = nullptr, *ndone = nullptr;
   GridBarrier* bar = nullptr;
-  int32_t* h_buf = nullptr;  // pinned: iterations and statuses of the last launch
+  int32_t* h_buf = nullptr;  // pinned: iterations and statuses of each launch of a step (2 P per slot)
+  int nslot = 0;              // slots of h_buf
+  int timed_slot = -1;        // launch of the current step timed for the autotuner
   int grid = 0;
   bool tuned = false;
   std::vector<int> cand;
@@ -1698,6 +1700,12 @@ struct feti_batch_s {
   BStepVals* d_vals = nullptr;
   BStepVals* h_vals = nullptr;
   BDims dims;
+  // the step captured as a graph (warm steps with a fixed grid), and the shape it holds
+  bool use_graph = true;
+  hipGraphExec_t gexec = nullptr;
+  int g_nref = -1, g_cand = -1, g_grid = 0;
+  feti_solve_opts g_opts{};  // options whose values the captured launches hold
+  bool last_graph = false;   // the last step ran as a graph launch
 };
 
 namespace {
@@ -1734,15 +1742,18 @@ int bupload(feti_batch b, T** p, const std::vector<T>& v) {
   return FETI_OK;
 }
 
-// one cooperative launch over every problem; adds each problem's iterations to its
-// stats and keeps the worst status
-// One cooperative launch of the interface iterations of every problem.  tune: this launch
-// may be timed for the autotuner (first solves of a warm step only, so that every
-// candidate is timed on the same kind of work).
-int run_batch(feti_batch b, bool corr, bool tune, std::vector<feti_stats>& acc) {
+// One cooperative launch of the interface iterations of every problem (enqueued only;
+// the step reads the results after its single synchronisation).  Its iterations and
+// statuses go to slot `slot` of the pinned record.  tune: this launch may be timed for
+// the autotuner (first solves of a warm step only, so that every candidate is timed on
+// the same kind of work).
+int run_batch(feti_batch b, bool corr, bool tune, int slot) {
   hipStream_t st = b->stream;
-  BCHK(hipMemsetAsync(b->bar, 0, sizeof(GridBarrier), st));
-  BCHK(hipMemsetAsync(b->ndone, 0, sizeof(int32_t), st));
+  // fill kernels instead of memsets, so that a captured step holds no memset nodes (the
+  // finished count is allocated as two words, one double)
+  static_assert(sizeof(GridBarrier) % sizeof(double) == 0, "the barrier is cleared as doubles");
+  launch_zero(sizeof(GridBarrier) / sizeof(double), reinterpret_cast<double*>(b->bar), st);
+  launch_zero(1, reinterpret_cast<double*>(b->ndone), st);
   BatchArgs a;
   a.probs = corr ? b->d_corr : b->d_main;
   a.P = b->P; a.f32 = b->f32;
@@ -1754,21 +1765,37 @@ int run_batch(feti_batch b, bool corr, bool tune, std::vector<feti_stats>& acc) 
   a.max_nb = b->max_nb;
   const bool timed = !b->tuned && tune;
   const int grid = timed ? b->cand[b->trial % b->cand.size()] : (b->tuned ? b->grid : b->cand[0]);
-  BCHK(hipEventRecord(b->e0, st));
+  if (timed) BCHK(hipEventRecord(b->e0, st));
   BCHK(launch_pcg_batch(a, grid, st));
-  BCHK(hipEventRecord(b->e1, st));
-  BCHK(hipMemcpyAsync(b->h_buf, b->iters, b->P * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  BCHK(hipMemcpyAsync(b->h_buf + b->P, b->status, b->P * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  BCHK(hipStreamSynchronize(st));
-  int64_t total = 0;
-  for (int p = 0; p < b->P; ++p) {
-    acc[p].iters += b->h_buf[p];
-    total += b->h_buf[p];
-    if (b->h_buf[b->P + p] != 0 && acc[p].status == 0) acc[p].status = b->h_buf[b->P + p];
-  }
   if (timed) {
+    BCHK(hipEventRecord(b->e1, st));
+    b->timed_slot = slot;
+  }
+  int32_t* rec = b->h_buf + (size_t)slot * 2 * b->P;
+  BCHK(hipMemcpyAsync(rec, b->iters, b->P * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  BCHK(hipMemcpyAsync(rec + b->P, b->status, b->P * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  return FETI_OK;
+}
+
+// After the step's synchronisation: each problem's iterations and worst status over the
+// step's launches, and the autotuner's record of a timed launch.
+int collect_batch(feti_batch b, int nlaunch, std::vector<feti_stats>& acc) {
+  const int P = b->P;
+  for (int k = 0; k < nlaunch; ++k) {
+    const int32_t* rec = b->h_buf + (size_t)k * 2 * P;
+    for (int p = 0; p < P; ++p) {
+      acc[p].iters += rec[p];
+      if (k == 0) acc[p].iters_first = rec[p];
+      if (rec[P + p] != 0 && acc[p].status == 0) acc[p].status = rec[P + p];
+    }
+  }
+  if (b->timed_slot >= 0) {
     // autotuner: time per iteration-problem of each candidate grid, each timed twice on
     // the first solve of a warm step, then keep the best
+    const int32_t* rec = b->h_buf + (size_t)b->timed_slot * 2 * P;
+    int64_t total = 0;
+    for (int p = 0; p < P; ++p) total += rec[p];
+    b->timed_slot = -1;
     float ms = 0.f;
     BCHK(hipEventElapsedTime(&ms, b->e0, b->e1));
     b->cost[b->trial % b->cand.size()] += ms / (double)std::max<int64_t>(total, 1);
@@ -1979,9 +2006,11 @@ int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob) {
       (rc = bupload(b, &b->row_chunk, rcn)) || (rc = bupload(b, &b->flt_prob, fp)) ||
       (rc = bupload(b, &b->flt_f, ff)) || (rc = balloc(b, &b->alpha, nprob)) || (rc = balloc(b, &b->beta, nprob)) ||
       (rc = balloc(b, &b->rho, nprob)) || (rc = balloc(b, &b->done, nprob)) || (rc = balloc(b, &b->iters, nprob)) ||
-      (rc = balloc(b, &b->status, nprob)) || (rc = balloc(b, &b->ndone, 1)) || (rc = balloc(b, &b->bar, 1)))
+      (rc = balloc(b, &b->status, nprob)) || (rc = balloc(b, &b->ndone, 2)) || (rc = balloc(b, &b->bar, 1)))
     return bad(rc, "");
-  if (hipHostMalloc((void**)&b->h_buf, 2 * nprob * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+  b->nslot = 8;
+  if (hipHostMalloc((void**)&b->h_buf, (size_t)b->nslot * 2 * nprob * sizeof(int32_t), hipHostMallocDefault) !=
+      hipSuccess)
     return bad(FETI_ENOMEM, "");
   // batched launches: table, per-step values, dimensions and GEMV work items
   {
@@ -2024,6 +2053,12 @@ int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob) {
   const int maxg = pcg_batch_max_grid(b->max_nb);
   (void)hipGetLastError();
   if (maxg < 1) return bad(FETI_EHIP, "cooperative launch unavailable for the batch kernel");
+  if (std::getenv("FETI_TRACE")) {
+    char desc[256];
+    pcg_batch_describe(b->max_nb, desc, sizeof(desc));
+    std::fprintf(stderr, "[batch] %d problems, largest n_b %d, %zu bytes of LDS per block, co-resident grid %d; %s\n",
+                 nprob, b->max_nb, pcg_batch_shmem(b->max_nb), maxg, desc);
+  }
   int cus = 0, dev = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -2042,6 +2077,7 @@ int feti_batch_destroy(feti_batch b) {
   for (void* p : b->allocs) (void)hipFree(p);
   if (b->h_buf) (void)hipHostFree(b->h_buf);
   if (b->h_vals) (void)hipHostFree(b->h_vals);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->e0) (void)hipEventDestroy(b->e0);
   if (b->e1) (void)hipEventDestroy(b->e1);
   delete b;
@@ -2070,7 +2106,8 @@ int feti_batch_info(feti_batch b, int32_t* info) {
   info[0] = b->tuned ? b->grid : b->cand[b->trial % b->cand.size()];
   info[1] = b->tuned ? 1 : 0;
   info[2] = (int32_t)std::min<size_t>(b->cand.size(), 8);
-  for (int k = 0; k < info[2]; ++k) info[3 + k] = b->cand[k];
+  for (int k = 0; k < 8; ++k) info[3 + k] = k < info[2] ? b->cand[k] : 0;
+  info[11] = b->last_graph ? 1 : 0;
   return FETI_OK;
 }
 
@@ -2085,7 +2122,6 @@ int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts*
   for (auto& s : acc) std::memset(&s, 0, sizeof(s));
   hipStream_t st = b->stream;
   BRC(sync_probs(b));
-  BCHK(hipEventRecord(b->ctx[0]->ev[0], st));
   // per-problem step values: the load, the start of the first solve, the warm correction
   bool cold = false, any_cand = false;
   for (int p = 0; p < P; ++p) {
@@ -2107,43 +2143,99 @@ int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts*
     acc[p].start_used = used;
     cold = cold || !ctx->have_prev;
   }
-  BCHK(hipMemcpyAsync(b->d_vals, b->h_vals, P * sizeof(BStepVals), hipMemcpyHostToDevice, st));
-  const BProb* PT = b->d_probs;
-  const BDims& dm = b->dims;
-  launchb_rhs(PT, b->d_vals, dm, st);
-  launchb_start(PT, b->d_vals, dm, st);
-  btorn_begin(b, o->tol, 0.0, o->max_it, BV_F, BV_NONE, BV_LAM, BV_NONE);
-  BCHK(hipGetLastError());
-  BRC(run_batch(b, false, !cold, acc));
-  for (int p = 0; p < P; ++p) acc[p].iters_first = acc[p].iters;
-  btorn_end(b, BV_LAM, BV_U);
   const int nref = cold ? std::max(o->ir_cold, o->ir_max) : o->ir_max;
-  for (int k = 0; k < nref; ++k) {
-    btorn_residual(b);
-    launchb_axpby(PT, dm, BL_LAMBDA, 0.0, BV_NONE, 0.0, BV_NONE, BV_DLAM, st);
-    btorn_begin(b, o->tol_corr, o->tol_upd, o->max_it, BV_RF, BV_CJ, BV_DLAM, k == 0 && any_cand ? BV_DLAMP : BV_NONE);
-    BCHK(hipGetLastError());
-    BRC(run_batch(b, true, false, acc));
-    btorn_end(b, BV_DLAM, BV_DU);
-    launchb_axpby(PT, dm, BL_TORN, 1.0, BV_U, 1.0, BV_DU, BV_U, st);
-    launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_LAM, 1.0, BV_DLAM, BV_LAM, st);
-    launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_DLAM, k == 0 ? 0.0 : 1.0, k == 0 ? BV_NONE : BV_DLAMS, BV_DLAMS, st);
-    for (int p = 0; p < P; ++p) acc[p].ir_steps += 1;
+  const int nlaunch = 1 + std::max(nref, 0);
+  if (nlaunch > b->nslot) {
+    // a larger record of the launches (a captured step refers to the old one)
+    BCHK(hipStreamSynchronize(st));
+    int32_t* nb = nullptr;
+    if (hipHostMalloc((void**)&nb, (size_t)nlaunch * 2 * P * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+      return bfail(b, FETI_ENOMEM, "pinned record of the batch launches");
+    (void)hipHostFree(b->h_buf);
+    b->h_buf = nb;
+    b->nslot = nlaunch;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
   }
-  // histories: this step's total correction, and lam_prev2 <- lam_prev <- lam
-  if (nref > 0) launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_DLAMS, 0.0, BV_NONE, BV_DLAMP, st);
-  launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_LAMP, 0.0, BV_NONE, BV_LAMP2, st);
-  launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_LAM, 0.0, BV_NONE, BV_LAMP, st);
+  // The work of the step, in stream order (no host synchronisation inside).
+  auto enqueue = [&]() -> int {
+    const BProb* PT = b->d_probs;
+    const BDims& dm = b->dims;
+    BCHK(hipMemcpyAsync(b->d_vals, b->h_vals, P * sizeof(BStepVals), hipMemcpyHostToDevice, st));
+    launchb_rhs(PT, b->d_vals, dm, st);
+    launchb_start(PT, b->d_vals, dm, st);
+    btorn_begin(b, o->tol, 0.0, o->max_it, BV_F, BV_NONE, BV_LAM, BV_NONE);
+    BRC(run_batch(b, false, !cold, 0));
+    btorn_end(b, BV_LAM, BV_U);
+    for (int k = 0; k < nref; ++k) {
+      btorn_residual(b);
+      launchb_axpby(PT, dm, BL_LAMBDA, 0.0, BV_NONE, 0.0, BV_NONE, BV_DLAM, st);
+      btorn_begin(b, o->tol_corr, o->tol_upd, o->max_it, BV_RF, BV_CJ, BV_DLAM,
+                  k == 0 && any_cand ? BV_DLAMP : BV_NONE);
+      BRC(run_batch(b, true, false, 1 + k));
+      btorn_end(b, BV_DLAM, BV_DU);
+      launchb_axpby(PT, dm, BL_TORN, 1.0, BV_U, 1.0, BV_DU, BV_U, st);
+      launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_LAM, 1.0, BV_DLAM, BV_LAM, st);
+      launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_DLAM, k == 0 ? 0.0 : 1.0, k == 0 ? BV_NONE : BV_DLAMS, BV_DLAMS, st);
+    }
+    // histories: this step's total correction, and lam_prev2 <- lam_prev <- lam
+    if (nref > 0) launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_DLAMS, 0.0, BV_NONE, BV_DLAMP, st);
+    launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_LAMP, 0.0, BV_NONE, BV_LAMP2, st);
+    launchb_axpby(PT, dm, BL_LAMBDA, 1.0, BV_LAM, 0.0, BV_NONE, BV_LAMP, st);
+    BCHK(hipGetLastError());
+    return FETI_OK;
+  };
+  BCHK(hipEventRecord(b->ctx[0]->ev[0], st));
+  // A warm step with a fixed grid runs as one graph launch; the graph is captured at the
+  // first such step and again when the step's shape (corrections, warm correction start,
+  // grid) changes.  The per-step values enter through the pinned staging copy it holds.
+  const bool graph = b->use_graph && b->tuned && !cold;
+  if (graph) {
+    const int gc = any_cand ? 1 : 0;
+    if (b->gexec && (b->g_nref != nref || b->g_cand != gc || b->g_grid != b->grid ||
+                     std::memcmp(&b->g_opts, o, sizeof(*o)) != 0)) {
+      (void)hipGraphExecDestroy(b->gexec);
+      b->gexec = nullptr;
+    }
+    if (!b->gexec) {
+      hipGraph_t g = nullptr;
+      BCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      const int rc = enqueue();
+      hipGraph_t gcap = nullptr;
+      const hipError_t e = hipStreamEndCapture(st, &gcap);
+      g = gcap;
+      if (rc != FETI_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return bfail(b, FETI_EHIP, std::string("capture of the batch step: ") + hipGetErrorString(e));
+      const hipError_t ei = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        b->gexec = nullptr;
+        return bfail(b, FETI_EHIP, std::string("instantiation of the batch step: ") + hipGetErrorString(ei));
+      }
+      b->g_nref = nref;
+      b->g_cand = gc;
+      b->g_grid = b->grid;
+      std::memcpy(&b->g_opts, o, sizeof(*o));
+    }
+    BCHK(hipGraphLaunch(b->gexec, st));
+  } else {
+    BRC(enqueue());
+  }
+  b->last_graph = graph;
+  BCHK(hipEventRecord(b->ctx[0]->ev[5], st));
+  BCHK(hipStreamSynchronize(st));
+  BRC(collect_batch(b, nlaunch, acc));
   for (int p = 0; p < P; ++p) {
     feti_ctx ctx = b->ctx[p];
     ctx->have_dlam_prev = nref > 0;
     ctx->have_prev2 = ctx->have_prev;
     ctx->have_prev = true;
     ctx->nstep += 1;
+    acc[p].ir_steps = nref;
   }
-  BCHK(hipEventRecord(b->ctx[0]->ev[5], st));
-  BCHK(hipGetLastError());
-  BCHK(hipStreamSynchronize(st));
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, b->ctx[0]->ev[0], b->ctx[0]->ev[5]);
   int worst = FETI_OK;
@@ -2153,6 +2245,17 @@ int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts*
     if (stats) stats[p] = acc[p];
   }
   if (worst != FETI_OK) return bfail(b, worst, "a problem of the batch did not converge");
+  return FETI_OK;
+}
+
+int feti_batch_set_capture(feti_batch b, int32_t on) {
+  if (!b) return FETI_EINVAL;
+  b->use_graph = on != 0;
+  if (!b->use_graph && b->gexec) {
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
   return FETI_OK;
 }
 

@@ -11,6 +11,8 @@
 // barrier, so an iteration has ten barriers: A | B | C | C' | D | D' | E | F | G | G'.
 // A finished problem drops out of the work lists; the launch ends when every
 // problem has finished.
+#include <cstdio>
+
 #include "pcg_device.h"
 
 namespace feti {
@@ -291,6 +293,16 @@ int pcg_batch_max_grid(int max_nb) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg_batch, PB, pcg_batch_shmem(max_nb)) != hipSuccess)
     return 0;
   return std::max(0, per_cu) * cus;
+}
+
+void pcg_batch_describe(int max_nb, char* buf, size_t n) {
+  hipFuncAttributes fa{};
+  (void)hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_pcg_batch));
+  int per_cu = 0, per_cu256 = 0;
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg_batch, PB, pcg_batch_shmem(max_nb));
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu256, k_pcg_batch, 256, pcg_batch_shmem(max_nb));
+  std::snprintf(buf, n, "regs %d, max threads %d, static LDS %zu, local %zu; blocks per CU %d (of 256 threads: %d)",
+                fa.numRegs, fa.maxThreadsPerBlock, fa.sharedSizeBytes, fa.localSizeBytes, per_cu, per_cu256);
 }
 
 hipError_t launch_pcg_batch(const BatchArgs& a, int grid, hipStream_t st) {

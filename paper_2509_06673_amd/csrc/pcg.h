@@ -92,6 +92,8 @@ struct BatchArgs {
 size_t pcg_batch_shmem(int max_nb);
 int pcg_batch_max_grid(int max_nb);
 hipError_t launch_pcg_batch(const BatchArgs& a, int grid, hipStream_t st);
+// register, LDS and occupancy figures of the batch kernel (diagnostics)
+void pcg_batch_describe(int max_nb, char* buf, size_t n);
 
 // dynamic LDS bytes of the launch
 size_t pcg_shmem(const DevMesh& m);

@@ -127,3 +127,44 @@ def test_warm_step_of_a_draw_with_a_large_coarse_load_converges():
     print(f"  vs oracle {max(err.values()):.1e}", flush=True)
     assert max(err.values()) < FP64_TOL, err
     f.close()
+
+
+def test_graph_captured_batch_steps_match_host_launched_steps():
+    """The batch step replayed as a captured graph gives the same bits as the same step
+    launched kernel by kernel from the host, at every step (several replays, with the
+    host-launched batch's own work and synchronisations between them)."""
+    import torch
+    require_gpu()
+    ws = _subset(k=8, seed=5)
+    nsteps = 6
+    print("[graph batch] " + " ".join(w.name for w in ws), flush=True)
+    ga = [_ctx(w, keep=False) for w in ws]
+    ea = [_ctx(w, keep=False) for w in ws]
+    bg, be = B.Batch(ga), B.Batch(ea)
+    for b in (bg, be):
+        b.set_grid(256)
+    bg.set_capture(True)
+    be.set_capture(False)
+    o = opts(tol=1e-10, max_it=3000)
+    for n in range(1, nsteps + 1):
+        stg, rcg = bg.step([load(w, n * w.tau) for w in ws], o)
+        ste, rce = be.step([load(w, n * w.tau) for w in ws], o)
+        _stream().synchronize()
+        assert rcg == 0 and rce == 0
+        assert [s["iters"] for s in stg] == [s["iters"] for s in ste], n
+        assert bg.info()["graph"] == (n > 1) and not be.info()["graph"], n
+        for f, g in zip(ga, ea):
+            nu = f.get_sizes()["sum_ns"]
+            nl = f.get_sizes()["n_lambda"]
+            u1 = torch.empty(nu, dtype=torch.float64, device="cuda")
+            u2 = torch.empty_like(u1)
+            l1 = torch.empty(nl, dtype=torch.float64, device="cuda")
+            l2 = torch.empty_like(l1)
+            f.get_solution(u1, l1)
+            g.get_solution(u2, l2)
+            assert torch.equal(u1, u2) and torch.equal(l1, l2), n
+        print(f"  step {n}: identical, iterations {[s['iters'] for s in stg]}", flush=True)
+    bg.close()
+    be.close()
+    for f in ga + ea:
+        f.close()
