@@ -31,6 +31,7 @@ struct BProb {
   const void* splus = nullptr;  // (K_s^+)_bb (m.sofs, m.ldb)
   const void* sbb = nullptr;    // preconditioner blocks
   int f32 = 0;                  // the three are float
+  SymArgs sym;                  // packed lower tiles of K_s^+
   const double* H = nullptr;    // G (G^T G)^{-1}, n_c x N_lambda (n_c > 0)
   const double* Cinv = nullptr;
   int nc = 0;
@@ -67,6 +68,12 @@ struct BDims {
   const int32_t* full_items = nullptr;
   const int32_t* iface_items = nullptr;
   int n_full_items = 0, n_iface_items = 0;
+  // packed tiles: (problem, stored tile) of every tile and of the tiles the recovery
+  // product reads, 2 int32 each; (problem, subdomain, block of 256 rows) of the row sums
+  const int32_t* sym_items = nullptr;
+  const int32_t* sym_kb_items = nullptr;
+  const int32_t* sum_items = nullptr;
+  int n_sym_items = 0, n_sym_kb_items = 0, n_sum_items = 0;
 };
 
 struct BGemv {
@@ -82,7 +89,7 @@ struct BGemv {
   int ybase = BV_NONE;
 };
 
-// launchers (kernels_iface.hip, kernels_fem.hip)
+// launchers (kernels_iface.hip, kernels_fem.hip, kernels_sym.hip)
 void launchb_axpby(const BProb* P, const BDims& d, int len, double a, int x, double b, int y, int z, hipStream_t st);
 void launchb_start(const BProb* P, const BStepVals* V, const BDims& d, hipStream_t st);
 void launchb_sgemv(const BProb* P, const BDims& d, const BGemv& g, int f32, hipStream_t st);
@@ -99,6 +106,10 @@ void launchb_pick_start(const BProb* P, const BStepVals* V, const BDims& d, int 
                         int alt3, int dst3, hipStream_t st);
 void launchb_sub_gather(const BProb* P, const BDims& d, int lam, int r, hipStream_t st);
 void launchb_rhs(const BProb* P, const BStepVals* V, const BDims& d, hipStream_t st);
+// y = K^+ x from the packed tiles (kb = 0, x a torn vector), or the recovery product
+// y = ybase + K^+ [0; gcoef B^T v] (+ R alpha_c) (kb = 1)
+void launchb_sym_gemv(const BProb* P, const BDims& d, int kb, int x, int v, double gcoef, int ybase, int alpha_c,
+                      int y, int f32, hipStream_t st);
 void launchb_elem_matvec(const BProb* P, const BDims& d, int x, int y, hipStream_t st);
 
 }  // namespace feti

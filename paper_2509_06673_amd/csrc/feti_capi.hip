@@ -612,8 +612,14 @@ int torn_end(feti_ctx ctx, const double* lam, double* u) {
     launch_coarse_g(m, ctx->r, nullptr, 1.0, ctx->g, nullptr, st);
     launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, -1.0, nullptr, st);
   }
-  GemvArgs a;
   const Factors fc = factors(ctx);
+  if (!fc.kinv) {
+    // in-place factors: the packed tiles that the interface columns reach
+    launch_sym_gemv_kb(m, ctx->sym, lam, -1.0, ctx->ytmp, ctx->nc > 0 ? ctx->ac : nullptr, u, st);
+    HIPCHK(hipGetLastError());
+    return FETI_OK;
+  }
+  GemvArgs a;
   a.A = fc.kinv; a.a_f32 = fc.f32; a.aofs = m.kofs; a.lda = m.ld; a.which_n = 0;
   a.kb_only = 1; a.ybase = ctx->ytmp;
   a.v = lam; a.gmode = G_SIGNED; a.gcoef = -1.0;
@@ -901,6 +907,30 @@ int solve_refined(feti_ctx ctx, const feti_solve_opts* o, int nref, feti_stats* 
   return rc;
 }
 
+// Stored tiles of the packed K_s^+ of every subdomain, in storage order: subdomain s
+// holds tile rows I < ceil(n_s / 64) and columns J <= I (tile index tbase[s] +
+// I (I + 1) / 2 + J).  kb: the tiles of tile rows I >= tb[s] = (n_s - n_b) / 64 (those
+// the interface columns reach).  Any output may be null.
+void sym_tiles(const MeshHost& mh, std::vector<int32_t>* ts, std::vector<int32_t>* ti, std::vector<int32_t>* tj,
+               std::vector<int32_t>* nt, std::vector<int64_t>* tbase, std::vector<int32_t>* kb,
+               std::vector<int32_t>* tb) {
+  int64_t t = 0;
+  for (int s = 0; s < (int)mh.subs.size(); ++s) {
+    const int T = (mh.subs[s].ns + 63) / 64;
+    const int b0 = (mh.subs[s].ns - mh.subs[s].nb) / 64;
+    if (nt) (*nt)[s] = T;
+    if (tbase) (*tbase)[s] = t;
+    if (tb) (*tb)[s] = b0;
+    for (int I = 0; I < T; ++I)
+      for (int J = 0; J <= I; ++J, ++t) {
+        if (ts) ts->push_back(s);
+        if (ti) ti->push_back(I);
+        if (tj) tj->push_back(J);
+        if (kb && I >= b0) kb->push_back((int32_t)t);
+      }
+  }
+}
+
 // Tile tables (once per mesh) and the packed lower tiles of K_s^+ in the precision of the
 // factors.
 int build_sym(feti_ctx ctx, bool f32) {
@@ -909,30 +939,23 @@ int build_sym(feti_ctx ctx, bool f32) {
   SymArgs& a = ctx->sym;
   if (!a.t_sub) {
     const int nsub = m.nsub;
-    std::vector<int32_t> ts, ti, tj, nt(nsub);
+    std::vector<int32_t> ts, ti, tj, nt(nsub), kb, tbs(nsub);
     std::vector<int64_t> tb(nsub);
-    for (int s = 0; s < nsub; ++s) {
-      const int T = (ctx->mh.subs[s].ns + 63) / 64;
-      nt[s] = T;
-      tb[s] = (int64_t)ts.size();
-      for (int I = 0; I < T; ++I)
-        for (int J = 0; J <= I; ++J) {
-          ts.push_back(s);
-          ti.push_back(I);
-          tj.push_back(J);
-        }
-    }
-    int32_t *d_ts = nullptr, *d_ti = nullptr, *d_tj = nullptr, *d_nt = nullptr;
+    sym_tiles(ctx->mh, &ts, &ti, &tj, &nt, &tb, &kb, &tbs);
+    int32_t *d_ts = nullptr, *d_ti = nullptr, *d_tj = nullptr, *d_nt = nullptr, *d_kb = nullptr, *d_tbs = nullptr;
     int64_t* d_tb = nullptr;
     RC(upload(ctx, &d_ts, ts));
     RC(upload(ctx, &d_ti, ti));
     RC(upload(ctx, &d_tj, tj));
     RC(upload(ctx, &d_nt, nt));
     RC(upload(ctx, &d_tb, tb));
+    RC(upload(ctx, &d_kb, kb));
+    RC(upload(ctx, &d_tbs, tbs));
     RC(dalloc(ctx, &a.part, ts.size() * 128, ctx->allocs));
     HIPCHK(hipStreamSynchronize(st));  // the host tables leave scope
     a.ntile = (int)ts.size();
     a.t_sub = d_ts; a.t_I = d_ti; a.t_J = d_tj; a.nt = d_nt; a.tbase = d_tb;
+    a.kb_tiles = d_kb; a.n_kb_tiles = (int)kb.size(); a.tb = d_tbs;
   }
   if (a.P && a.f32 != (int)f32) {
     auto it = std::find(ctx->mat_allocs.begin(), ctx->mat_allocs.end(), const_cast<void*>(a.P));
@@ -1221,12 +1244,10 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
     launch_copy_block(nsub, m.max_nb, m.kofs, m.ld, m.nI, m.sofs, m.ldb, m.nb, (const double*)ctx->Kinv,
                       ctx->Splus, st);
   }
-  // packed lower tiles of K_s^+ for the local solves, kept beside the dense blocks (an
-  // in-place elimination saves memory and does without them)
-  if (ctx->keep_assembled) {
-    rc = build_sym(ctx, f32);
-    if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
-  }
+  // packed lower tiles of K_s^+ for the local solves (an in-place elimination keeps only
+  // them: its dense blocks are released below)
+  rc = build_sym(ctx, f32);
+  if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
   HIPCHK(hipMemcpyAsync(stat.data(), P.status, nsub * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   {
@@ -1235,12 +1256,21 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
     ctx->t_gj_ms = ms;
   }
   for (void* p : tmp) (void)hipFree(p);
-  if (!ctx->keep_assembled && f32) {
-    // the FP32 factors no longer need the assembled FP64 matrices
-    auto it = std::find(ctx->mat_allocs.begin(), ctx->mat_allocs.end(), (void*)ctx->K);
-    if (it != ctx->mat_allocs.end()) ctx->mat_allocs.erase(it);
-    HIPCHK(hipFree(ctx->K));
+  if (!ctx->keep_assembled) {
+    // an in-place elimination keeps K_s^+ only as packed tiles: the dense blocks (the
+    // assembled matrices, eliminated in place for FP64; their FP32 copy for FP32) go
+    auto release = [&](void* q) -> int {
+      if (!q) return FETI_OK;
+      auto it = std::find(ctx->mat_allocs.begin(), ctx->mat_allocs.end(), q);
+      if (it != ctx->mat_allocs.end()) ctx->mat_allocs.erase(it);
+      HIPCHK(hipFree(q));
+      return FETI_OK;
+    };
+    RC(release(ctx->K));
+    if (f32) RC(release(ctx->Kinv32));
     ctx->K = nullptr;
+    ctx->Kinv = nullptr;
+    ctx->Kinv32 = nullptr;
   }
   for (int s = 0; s < nsub; ++s)
     if (stat[s]) return fail(ctx, FETI_ESINGULAR, "zero or non-finite pivot in subdomain " + std::to_string(s));
@@ -1522,6 +1552,8 @@ int feti_export_local(feti_ctx ctx, int32_t sub, int32_t which, double* out) {
   const SubHost& sh = h.subs[sub];
   if (which == FETI_EXPORT_K && (!ctx->K || (!ctx->keep_assembled && ctx->state >= 3)))
     return fail(ctx, FETI_ESTATE, "the assembled matrices were eliminated in place");
+  if (which == FETI_EXPORT_KPLUS && !(ctx->precision == FETI_FP32_IR ? (void*)ctx->Kinv32 : (void*)ctx->Kinv))
+    return fail(ctx, FETI_ESTATE, "factors eliminated in place are kept as packed tiles only");
   if (which != FETI_EXPORT_K && ctx->precision == FETI_FP32_IR) {
     // FP32 factors: widen the block to FP64 on the way out
     const bool sbb = which == FETI_EXPORT_SBB;
@@ -1706,6 +1738,7 @@ struct feti_batch_s {
   int g_nref = -1, g_cand = -1, g_grid = 0;
   feti_solve_opts g_opts{};  // options whose values the captured launches hold
   bool last_graph = false;   // the last step ran as a graph launch
+  bool dense_kplus = true;   // every problem keeps its dense K^+ (else the recovery reads packed tiles)
 };
 
 namespace {
@@ -1822,6 +1855,7 @@ BProb prob_of(feti_ctx c) {
   a.splus = fc.splus;
   a.sbb = c->precond == FETI_PRECOND_LUMPED ? (const void*)c->Kbb : fc.sbb;
   a.f32 = fc.f32;
+  a.sym = c->sym;
   a.H = c->H;
   a.Cinv = c->Cinv;
   a.nc = c->nc;
@@ -1850,7 +1884,8 @@ int sync_probs(feti_batch b) {
     if (same)
       same = std::memcmp(now[p].v, o.v, sizeof(o.v)) == 0 && now[p].kinv == o.kinv && now[p].splus == o.splus &&
              now[p].sbb == o.sbb && now[p].f32 == o.f32 && now[p].H == o.H && now[p].Cinv == o.Cinv &&
-             now[p].mdiag == o.mdiag && now[p].m.ebuf == o.m.ebuf && now[p].m.emat == o.m.emat;
+             now[p].mdiag == o.mdiag && now[p].m.ebuf == o.m.ebuf && now[p].m.emat == o.m.emat &&
+             now[p].sym.P == o.sym.P && now[p].sym.f32 == o.sym.f32;
   }
   if (same) return FETI_OK;
   b->h_probs = now;
@@ -1869,9 +1904,8 @@ void btorn_begin(feti_batch b, double tol, double utol, int maxit, int f, int cj
   const BDims& d = b->dims;
   hipStream_t st = b->stream;
   const int f32 = b->f32;
-  BGemv g;
-  g.mat = BM_KINV; g.full = 1; g.xbase = f; g.y = BV_YTMP;
-  launchb_sgemv(P, d, g, f32, st);
+  // K^+ f from the packed tiles (every factored context has them)
+  launchb_sym_gemv(P, d, 0, f, BV_NONE, 0.0, BV_NONE, BV_NONE, BV_YTMP, f32, st);
   launchb_jump(P, d, BV_YTMP, 1, BV_D, 0, BV_NONE, st);
   if (cj != BV_NONE) launchb_axpby(P, d, BL_LAMBDA, 1.0, BV_D, -1.0, cj, BV_D, st);
   auto admissible = [&](int v) {
@@ -1920,6 +1954,10 @@ void btorn_end(feti_batch b, int lam, int u) {
   hipStream_t st = b->stream;
   launchb_coarse_g(P, d, BV_R, BV_NONE, 1.0, BV_G, st);
   launchb_coarse_apply(P, d, BV_G, BV_AC, -1.0, st);
+  if (!b->dense_kplus) {
+    launchb_sym_gemv(P, d, 1, BV_NONE, lam, -1.0, BV_YTMP, BV_AC, u, b->f32, st);
+    return;
+  }
   BGemv g;
   g.mat = BM_KINV; g.full = 1; g.kb_only = 1; g.ybase = BV_YTMP; g.v = lam; g.gmode = G_SIGNED; g.gcoef = -1.0;
   g.y = u; g.alpha_c = BV_AC;
@@ -2016,7 +2054,7 @@ int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob) {
   {
     BDims& d = b->dims;
     d.P = nprob;
-    std::vector<int32_t> fi, ii;
+    std::vector<int32_t> fi, ii, yi, ki, si;
     for (int p = 0; p < nprob; ++p) {
       feti_ctx c = ctxs[p];
       const DevMesh& m = c->dm;
@@ -2036,16 +2074,31 @@ int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob) {
       for (int s = 0; s < (int)h.subs.size(); ++s) {
         for (int t = 0; t * 64 < h.subs[s].ns; ++t) { fi.push_back(p); fi.push_back(s); fi.push_back(t); }
         for (int t = 0; t * 64 < h.subs[s].nb; ++t) { ii.push_back(p); ii.push_back(s); ii.push_back(t); }
+        for (int t = 0; t * 256 < h.subs[s].ns; ++t) { si.push_back(p); si.push_back(s); si.push_back(t); }
       }
+      if (!c->sym.P) return bad(FETI_ESTATE, "a context of the batch has no packed factors");
+      std::vector<int32_t> kb;
+      sym_tiles(h, nullptr, nullptr, nullptr, nullptr, nullptr, &kb, nullptr);
+      if ((int)kb.size() != c->sym.n_kb_tiles) return bad(FETI_EINVAL, "packed tile tables out of step");
+      for (int t = 0; t < c->sym.ntile; ++t) { yi.push_back(p); yi.push_back(t); }
+      for (int32_t t : kb) { ki.push_back(p); ki.push_back(t); }
+      if (!factors(c).kinv) b->dense_kplus = false;
     }
-    int32_t *dfi = nullptr, *dii = nullptr;
-    if ((rc = bupload(b, &dfi, fi)) || (rc = bupload(b, &dii, ii)) || (rc = balloc(b, &b->d_probs, nprob)) ||
+    int32_t *dfi = nullptr, *dii = nullptr, *dyi = nullptr, *dki = nullptr, *dsi = nullptr;
+    if ((rc = bupload(b, &dfi, fi)) || (rc = bupload(b, &dii, ii)) || (rc = bupload(b, &dyi, yi)) ||
+        (rc = bupload(b, &dki, ki)) || (rc = bupload(b, &dsi, si)) || (rc = balloc(b, &b->d_probs, nprob)) ||
         (rc = balloc(b, &b->d_vals, nprob)))
       return bad(rc, "");
     d.full_items = dfi;
     d.iface_items = dii;
     d.n_full_items = (int)(fi.size() / 3);
     d.n_iface_items = (int)(ii.size() / 3);
+    d.sym_items = dyi;
+    d.sym_kb_items = dki;
+    d.sum_items = dsi;
+    d.n_sym_items = (int)(yi.size() / 2);
+    d.n_sym_kb_items = (int)(ki.size() / 2);
+    d.n_sum_items = (int)(si.size() / 3);
     if (hipHostMalloc((void**)&b->h_vals, nprob * sizeof(BStepVals), hipHostMallocDefault) != hipSuccess)
       return bad(FETI_ENOMEM, "");
   }

@@ -133,6 +133,11 @@ struct SymArgs {
   const void* P = nullptr;          // ntile x 64 x 64 column-major tiles (double, or float when f32)
   int f32 = 0;
   double* part = nullptr;           // ntile x 2 x 64 partial products
+  // products with x_I = 0 (interface columns only): the stored tiles whose tile row I
+  // reaches the interface block (I >= tb[s] = (n_s - n_b) / 64), and tb per subdomain
+  const int32_t* kb_tiles = nullptr;
+  int n_kb_tiles = 0;
+  const int32_t* tb = nullptr;
 };
 // packed tiles P from the dense row-major blocks K (offsets kofs, leading dims ld)
 template <class T>
@@ -140,5 +145,9 @@ void launch_sym_pack(const SymArgs& a, const T* K, const int64_t* kofs, const in
                      hipStream_t st);
 // y = K_s^+ x_s for every subdomain (torn vectors)
 void launch_sym_gemv(const DevMesh& m, const SymArgs& a, const double* x, double* y, hipStream_t st);
+// y = ybase + K_s^+ [0; gcoef B_s^T v] (+ R_s alpha_c on floating subdomains): the recovery
+// product with the interface columns only, from the stored tiles that reach them
+void launch_sym_gemv_kb(const DevMesh& m, const SymArgs& a, const double* v, double gcoef, const double* ybase,
+                        const double* alpha_c, double* y, hipStream_t st);
 
 }  // namespace feti

@@ -59,8 +59,8 @@ __device__ __forceinline__ void gemv_phase(const PcgArgs& a, const MT* A, const 
   for (int t2 = blockIdx.x; 2 * t2 < a.ntile; t2 += gridDim.x) {
     const int t = 2 * t2 + half;
     const bool valid = t < a.ntile;
-    gemv_tile<MT, SCALED>(m, A, valid ? a.tile_sub[t] : 0, valid ? a.tile_row0[t] : 0, valid, src, src2, beta,
-                          yout, xs2 + half * m.max_nb, red8 + half * 256, ht);
+    gemv_tile<MT, SCALED, GEMV_BATCH, GEMV_PF>(m, A, valid ? a.tile_sub[t] : 0, valid ? a.tile_row0[t] : 0, valid,
+                                               src, src2, beta, yout, xs2 + half * m.max_nb, red8 + half * 256, ht);
   }
 }
 
@@ -92,6 +92,18 @@ __device__ __forceinline__ double gemv_phase_a(const PcgArgs& a, const MT* A, co
     const int64_t b0 = valid ? m.boff[s] : 0;
     double* xs = xs2 + half * m.max_nb;
     double* red4 = red8 + half * 256;
+    const int i = row0 + lane;
+    const int kq = (nbs + 3) / 4;
+    const int kb = wave * kq, ke = min(nbs, kb + kq);
+    MT pre[GEMV_BATCH];
+    const MT* col = nullptr;
+    if (GEMV_PF) {
+      // the first column batch is loaded before the gather (its latency overlaps it)
+      const int64_t ld = valid ? m.ldb[s] : 0;
+      col = valid ? A + m.sofs[s] + (int64_t)kb * ld + i : A;
+#pragma unroll
+      for (int u = 0; u < GEMV_BATCH; ++u) pre[u] = (i < nbs && kb + u < ke) ? col[(int64_t)u * ld] : (MT)0;
+    }
     __syncthreads();  // xs and red4 of the previous tiles are consumed
     if (!have) {
       // first pass of the gather (entries ht and ht + 256) with beta pending
@@ -122,11 +134,12 @@ __device__ __forceinline__ double gemv_phase_a(const PcgArgs& a, const MT* A, co
       gather_x<0>(m, nbs, b0, a.y, a.p, beta, xs, ht);
     }
     __syncthreads();
-    const int i = row0 + lane;
-    const int kq = (nbs + 3) / 4;
-    const int kb = wave * kq, ke = min(nbs, kb + kq);
     double v = 0.0;
-    if (i < nbs) v = tile_cols<MT>(A + m.sofs[s], m.ldb[s], i, kb, ke, xs);
+    if (GEMV_PF) {
+      if (i < nbs) v = tile_cols_pf<MT, GEMV_BATCH>(col, m.ldb[s], kb, ke, xs, pre);
+    } else {
+      if (i < nbs) v = tile_cols<MT>(A + m.sofs[s], m.ldb[s], i, kb, ke, xs);
+    }
     red4[wave * 64 + lane] = v;
     __syncthreads();
     if (wave == 0 && i < nbs)

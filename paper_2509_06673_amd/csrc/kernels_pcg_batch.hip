@@ -17,6 +17,24 @@
 
 namespace feti {
 
+// column loads in flight per lane in the GEMV phases (the batch's interface blocks stream
+// from HBM, so more bytes in flight pay than for one problem's cache-resident blocks)
+#ifndef FETI_BATCH_GEMV_NB
+#define FETI_BATCH_GEMV_NB 8
+#endif
+constexpr int BATCH_GEMV_NB = FETI_BATCH_GEMV_NB;
+// waves per SIMD the register allocation must allow (4: two blocks of PCG_BLOCK threads
+// per compute unit)
+#ifndef FETI_BATCH_MIN_WAVES
+#define FETI_BATCH_MIN_WAVES 4
+#endif
+constexpr int BATCH_MIN_WAVES = FETI_BATCH_MIN_WAVES;
+// 1: the column loads of the GEMV phases run one batch ahead of the products
+#ifndef FETI_BATCH_GEMV_PF
+#define FETI_BATCH_GEMV_PF 0
+#endif
+constexpr int BATCH_GEMV_PF = FETI_BATCH_GEMV_PF;
+
 __device__ inline int iload(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -46,10 +64,11 @@ __device__ void batch_gemv(const BatchArgs& a, int precond_phase, double* xs2, d
     double* red4 = red8 + half * 256;
     const int s = valid ? a.tile_sub[t] : 0, row0 = valid ? a.tile_row0[t] : 0;
     if (!precond_phase)
-      gemv_tile<MT, 0>(pr.m, (const MT*)pr.fm, s, row0, valid, pr.y, pr.p, valid ? ald(a.beta + p) : 0.0, pr.yb,
-                       xs, red4, ht);
+      gemv_tile<MT, 0, BATCH_GEMV_NB, BATCH_GEMV_PF>(pr.m, (const MT*)pr.fm, s, row0, valid, pr.y, pr.p,
+                                                     valid ? ald(a.beta + p) : 0.0, pr.yb, xs, red4, ht);
     else
-      gemv_tile<MT, 1>(pr.m, (const MT*)pr.mm, s, row0, valid, pr.w, nullptr, 0.0, pr.zb, xs, red4, ht);
+      gemv_tile<MT, 1, BATCH_GEMV_NB, BATCH_GEMV_PF>(pr.m, (const MT*)pr.mm, s, row0, valid, pr.w, nullptr, 0.0,
+                                                     pr.zb, xs, red4, ht);
   }
 }
 
@@ -171,7 +190,7 @@ __device__ inline void batch_update(const BatchArgs& a, const ProbArgs& pr, int 
   block_store<NV>(acc, red, pr.part + (int64_t)a.row_chunk[it] * PCG_NPART);
 }
 
-__global__ void __launch_bounds__(PCG_BLOCK) k_pcg_batch(BatchArgs a) {
+__global__ void __launch_bounds__(PCG_BLOCK, BATCH_MIN_WAVES) k_pcg_batch(BatchArgs a) {
   extern __shared__ double lds[];
   __shared__ int s_ok;
   double* xs = lds;                 // 2 x max_nb

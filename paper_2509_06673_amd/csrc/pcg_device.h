@@ -15,6 +15,12 @@ constexpr int PB = PCG_BLOCK;
 #define FETI_GEMV_BATCH 8
 #endif
 constexpr int GEMV_BATCH = FETI_GEMV_BATCH;  // column loads in flight per lane (multiple of 4)
+// 1: the GEMV phases of the single-problem launch load one column batch ahead of the
+// products (and the first batch before the gather)
+#ifndef FETI_GEMV_PF
+#define FETI_GEMV_PF 0
+#endif
+constexpr int GEMV_PF = FETI_GEMV_PF;
 static_assert(GEMV_BATCH % 4 == 0, "GEMV batches are consumed four at a time");
 constexpr long long PCG_SPIN_LIMIT = 1ll << 21;
 
@@ -297,17 +303,18 @@ __device__ inline void gather_x(const DevMesh& m, int nbs, int64_t b0, const dou
 // dimension ld): batches of GEMV_BATCH independent column loads in flight before their
 // FMAs (a lane's column range is a chain of dependent round trips to HBM, so the
 // batch size sets the bytes in flight), the last columns as one batch
-template <class MT>
+template <class MT, int NB = GEMV_BATCH>
 __device__ inline double tile_cols(const MT* As, int64_t ld, int i, int kb, int ke, const double* xs) {
+  static_assert(NB % 4 == 0, "GEMV batches are consumed four at a time");
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   const MT* col = As + (int64_t)kb * ld + i;
   int k = kb;
-  for (; k + GEMV_BATCH <= ke; k += GEMV_BATCH, col += GEMV_BATCH * ld) {
-    MT v[GEMV_BATCH];
+  for (; k + NB <= ke; k += NB, col += NB * ld) {
+    MT v[NB];
 #pragma unroll
-    for (int u = 0; u < GEMV_BATCH; ++u) v[u] = col[(int64_t)u * ld];
+    for (int u = 0; u < NB; ++u) v[u] = col[(int64_t)u * ld];
 #pragma unroll
-    for (int u = 0; u < GEMV_BATCH; u += 4) {
+    for (int u = 0; u < NB; u += 4) {
       acc0 += (double)v[u + 0] * xs[k + u + 0];
       acc1 += (double)v[u + 1] * xs[k + u + 1];
       acc2 += (double)v[u + 2] * xs[k + u + 2];
@@ -315,13 +322,48 @@ __device__ inline double tile_cols(const MT* As, int64_t ld, int i, int kb, int 
     }
   }
   if (k < ke) {
-    // the last (ke - k < GEMV_BATCH) columns: loads together, products in order
-    MT v[GEMV_BATCH];
+    // the last (ke - k < NB) columns: loads together, products in order
+    MT v[NB];
 #pragma unroll
-    for (int u = 0; u < GEMV_BATCH; ++u) v[u] = k + u < ke ? col[(int64_t)u * ld] : (MT)0;
+    for (int u = 0; u < NB; ++u) v[u] = k + u < ke ? col[(int64_t)u * ld] : (MT)0;
 #pragma unroll
-    for (int u = 0; u < GEMV_BATCH; ++u)
+    for (int u = 0; u < NB; ++u)
       if (k + u < ke) acc0 += (double)v[u] * xs[k + u];
+  }
+  return (acc0 + acc1) + (acc2 + acc3);
+}
+
+// The same sum with the loads of the next batch issued before the products of the
+// current one (two batches in flight), and the first batch (v) loaded by the caller
+// before x_b is gathered, so that its latency overlaps the gather.  The products are
+// those of tile_cols in the same order.
+template <class MT, int NB>
+__device__ inline double tile_cols_pf(const MT* col, int64_t ld, int kb, int ke, const double* xs, MT (&v)[NB]) {
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  for (int k = kb; k < ke; k += NB) {
+    const int kn = k + NB;
+    MT w[NB];
+    if (kn < ke) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) w[u] = kn + u < ke ? col[(int64_t)(kn - kb + u) * ld] : (MT)0;
+    }
+    if (kn <= ke) {
+#pragma unroll
+      for (int u = 0; u < NB; u += 4) {
+        acc0 += (double)v[u + 0] * xs[k + u + 0];
+        acc1 += (double)v[u + 1] * xs[k + u + 1];
+        acc2 += (double)v[u + 2] * xs[k + u + 2];
+        acc3 += (double)v[u + 3] * xs[k + u + 3];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+        if (k + u < ke) acc0 += (double)v[u] * xs[k + u];
+    }
+    if (kn < ke) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) v[u] = w[u];
+    }
   }
   return (acc0 + acc1) + (acc2 + acc3);
 }
@@ -329,21 +371,34 @@ __device__ inline double tile_cols(const MT* As, int64_t ld, int i, int kb, int 
 // One 64-row tile of y_b = A_s x_b (interface block of subdomain s) by one half of
 // the block (four wavefronts, threads ht = 0..255): x_b gathered into xs, the
 // wavefronts split the column range and combine in red4.  SCALED as in gather_x.
-// valid = false: the half only takes part in the block's barriers.
-template <class MT, int SCALED>
+// valid = false: the half only takes part in the block's barriers.  PF: the column
+// loads run ahead of the products (tile_cols_pf).
+template <class MT, int SCALED, int NB = GEMV_BATCH, int PF = 0>
 __device__ inline void gemv_tile(const DevMesh& m, const MT* A, int s, int row0, bool valid, const double* src,
                           const double* src2, double beta, double* yout, double* xs, double* red4, int ht) {
   const int wave = ht >> 6, lane = ht & 63;
   const int nbs = valid ? m.nb[s] : 0;
   const int64_t b0 = valid ? m.boff[s] : 0;
-  __syncthreads();  // xs and red4 of the previous tiles are consumed
-  gather_x<SCALED>(m, nbs, b0, src, src2, beta, xs, ht);
-  __syncthreads();
   const int i = row0 + lane;
   const int kq = (nbs + 3) / 4;
   const int kb = wave * kq, ke = min(nbs, kb + kq);
+  MT pre[NB];
+  const MT* col = nullptr;
+  if (PF) {
+    const int64_t ld = valid ? m.ldb[s] : 0;
+    col = valid ? A + m.sofs[s] + (int64_t)kb * ld + i : A;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) pre[u] = (i < nbs && kb + u < ke) ? col[(int64_t)u * ld] : (MT)0;
+  }
+  __syncthreads();  // xs and red4 of the previous tiles are consumed
+  gather_x<SCALED>(m, nbs, b0, src, src2, beta, xs, ht);
+  __syncthreads();
   double v = 0.0;
-  if (i < nbs) v = tile_cols<MT>(A + m.sofs[s], m.ldb[s], i, kb, ke, xs);
+  if (PF) {
+    if (i < nbs) v = tile_cols_pf<MT, NB>(col, m.ldb[s], kb, ke, xs, pre);
+  } else {
+    if (i < nbs) v = tile_cols<MT, NB>(A + m.sofs[s], m.ldb[s], i, kb, ke, xs);
+  }
   red4[wave * 64 + lane] = v;
   __syncthreads();
   if (wave == 0 && i < nbs)
