@@ -1712,7 +1712,7 @@ struct feti_batch_s {
   int32_t *row_prob = nullptr, *row_chunk = nullptr, *flt_prob = nullptr, *flt_f = nullptr;
   int ntile = 0, nrow = 0, nflt = 0;
   double *alpha = nullptr, *beta = nullptr, *rho = nullptr, *part = nullptr;
-  int32_t *done = nullptr, *iters = nullptr, *status = nullptr, *ndone = nullptr;
+  int32_t *done = nullptr, *iters = nullptr, *status = nullptr, *ndone = nullptr, *cnt = nullptr;
   GridBarrier* bar = nullptr;
   int32_t* h_buf = nullptr;  // pinned: iterations and statuses of each launch of a step (2 P per slot)
   int nslot = 0;              // slots of h_buf
@@ -1794,15 +1794,51 @@ int run_batch(feti_batch b, bool corr, bool tune, int slot) {
   a.row_prob = b->row_prob; a.row_chunk = b->row_chunk; a.nrow = b->nrow;
   a.flt_prob = b->flt_prob; a.flt_f = b->flt_f; a.nflt = b->nflt;
   a.alpha = b->alpha; a.beta = b->beta; a.rho = b->rho;
-  a.done = b->done; a.iters = b->iters; a.status = b->status; a.ndone = b->ndone; a.bar = b->bar;
+  a.done = b->done; a.iters = b->iters; a.status = b->status; a.ndone = b->ndone; a.bar = b->bar; a.cnt = b->cnt;
   a.max_nb = b->max_nb;
   const bool timed = !b->tuned && tune;
   const int grid = timed ? b->cand[b->trial % b->cand.size()] : (b->tuned ? b->grid : b->cand[0]);
+  static const bool ptrace = std::getenv("FETI_PCG_TRACE") != nullptr;
+  long long* ts = nullptr;
+  const int nts = 64;
+  if (ptrace) {
+    // diagnostics (host-launched steps only): block 0's clock after every barrier
+    BCHK(hipMalloc(&ts, nts * 12 * sizeof(long long)));
+    launch_zero(nts * 12, reinterpret_cast<double*>(ts), st);
+    a.tstamp = ts;
+    a.tstamp_iters = nts;
+  }
   if (timed) BCHK(hipEventRecord(b->e0, st));
   BCHK(launch_pcg_batch(a, grid, st));
   if (timed) {
     BCHK(hipEventRecord(b->e1, st));
     b->timed_slot = slot;
+  }
+  if (ptrace) {
+    std::vector<long long> h(nts * 12);
+    BCHK(hipMemcpyAsync(h.data(), ts, h.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
+    BCHK(hipStreamSynchronize(st));
+    (void)hipFree(ts);
+    int rate_khz = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
+    constexpr int np = 7;
+    double sum[np] = {0};
+    int cnt = 0;
+    std::string per_it;
+    for (int it = 0; it < nts; ++it) {
+      if (h[it * 12 + np] == 0) break;
+      const long long s0 = it == 0 ? h[0] : h[(it - 1) * 12 + np];
+      for (int k = 0; k < np; ++k) sum[k] += (double)(h[it * 12 + k + 1] - (k > 0 ? h[it * 12 + k] : s0));
+      if (rate_khz > 0) per_it += " " + std::to_string((int)((h[it * 12 + np] - s0) * 1e3 / rate_khz));
+      ++cnt;
+    }
+    if (cnt > 0 && rate_khz > 0) {
+      const double us = 1e3 / rate_khz / cnt;
+      std::fprintf(stderr, "[pcg batch] grid %d, %d iterations, us per phase (A B C D E F G):", grid, cnt);
+      for (int k = 0; k < np; ++k) std::fprintf(stderr, " %.1f", sum[k] * us);
+      std::fprintf(stderr, "\n[pcg batch] us per iteration:%s\n", per_it.c_str());
+    }
   }
   int32_t* rec = b->h_buf + (size_t)slot * 2 * b->P;
   BCHK(hipMemcpyAsync(rec, b->iters, b->P * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -2044,7 +2080,8 @@ int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob) {
       (rc = bupload(b, &b->row_chunk, rcn)) || (rc = bupload(b, &b->flt_prob, fp)) ||
       (rc = bupload(b, &b->flt_f, ff)) || (rc = balloc(b, &b->alpha, nprob)) || (rc = balloc(b, &b->beta, nprob)) ||
       (rc = balloc(b, &b->rho, nprob)) || (rc = balloc(b, &b->done, nprob)) || (rc = balloc(b, &b->iters, nprob)) ||
-      (rc = balloc(b, &b->status, nprob)) || (rc = balloc(b, &b->ndone, 2)) || (rc = balloc(b, &b->bar, 1)))
+      (rc = balloc(b, &b->status, nprob)) || (rc = balloc(b, &b->ndone, 2)) || (rc = balloc(b, &b->bar, 1)) ||
+      (rc = balloc(b, &b->cnt, 3 * nprob)))
     return bad(rc, "");
   b->nslot = 8;
   if (hipHostMalloc((void**)&b->h_buf, (size_t)b->nslot * 2 * nprob * sizeof(int32_t), hipHostMallocDefault) !=
@@ -2242,7 +2279,7 @@ int feti_batch_step(feti_batch b, const feti_load* loads, const feti_solve_opts*
   // A warm step with a fixed grid runs as one graph launch; the graph is captured at the
   // first such step and again when the step's shape (corrections, warm correction start,
   // grid) changes.  The per-step values enter through the pinned staging copy it holds.
-  const bool graph = b->use_graph && b->tuned && !cold;
+  const bool graph = b->use_graph && b->tuned && !cold && !std::getenv("FETI_PCG_TRACE");
   if (graph) {
     const int gc = any_cand ? 1 : 0;
     if (b->gexec && (b->g_nref != nref || b->g_cand != gc || b->g_grid != b->grid ||

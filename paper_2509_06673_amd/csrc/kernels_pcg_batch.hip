@@ -5,12 +5,13 @@
 // The phases of an iteration are those of the single-problem launch
 // (kernels_pcg.hip), over work lists that span every problem: 64-row tiles of
 // the interface blocks, chunks of PCG_BLOCK multiplier rows and the floating
-// subdomains.  Each problem keeps its own scalars.  After each reduction the block
-// with blockIdx = problem mod grid sums that problem's chunk partials (in chunk
-// order) and publishes alpha, the stopping decision or beta before the next
-// barrier, so an iteration has ten barriers: A | B | C | C' | D | D' | E | F | G | G'.
-// A finished problem drops out of the work lists; the launch ends when every
-// problem has finished.
+// subdomains.  Each problem keeps its own scalars: a block that stores a chunk
+// partial of a reduction counts it on the problem's counter, and the block that
+// completes the count sums that problem's chunk partials (a fixed tree) and
+// publishes alpha, the stopping decision or beta before the next barrier.  An
+// iteration has seven barriers: A | B | C (alpha) | D (stopping test) | E | F |
+// G (beta).  A finished problem drops out of the work lists; the launch ends when
+// every problem has finished.
 #include <cstdio>
 
 #include "pcg_device.h"
@@ -42,14 +43,55 @@ __device__ inline void istore(int32_t* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// a problem finishes with a status: published for every block, counted once
+// a problem finishes with a status: published for every block, counted once.  The
+// per-problem state is written by whichever block completes a reduction, so every
+// access to it that another block may repeat is device-coherent.
 __device__ inline void finish(const BatchArgs& a, int p, int status) {
   const ProbArgs& pr = a.probs[p];
-  pr.ist[IS_STATUS] = status;
-  pr.ist[IS_DONE] = 1;
-  a.status[p] = status;
+  istore(pr.ist + IS_STATUS, status);
+  istore(pr.ist + IS_DONE, 1);
+  istore(a.status + p, status);
   istore(a.done + p, 1);
   __hip_atomic_fetch_add(a.ndone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// After this block stored a chunk partial of problem p: counts it, and returns true in
+// the block that completes the count (which then resets the counter).  The partial
+// stores are device-coherent and complete before the count.
+__device__ inline bool last_chunk(int32_t* cnt, int total, int* s_flag) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const bool last = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == total - 1;
+    if (last) __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *s_flag = last ? 1 : 0;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
+// Sums over problem p's chunk partials of the slots [0, NV), in chunk order, into tot
+// (LDS; lane c of the first wavefront sums slot c).
+template <int NV>
+__device__ inline void chunk_totals(const ProbArgs& pr, double* tot) {
+  if (threadIdx.x < NV) {
+    // eight chunk loads in flight at a time, added in chunk order
+    const int n = pr.nrow_items;
+    const double* src = pr.part + threadIdx.x;
+    double s = 0.0;
+    for (int k = 0; k < n; k += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = k + u < n ? ald(src + (int64_t)(k + u) * PCG_NPART) : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k + u < n) s += v[u];
+    }
+    tot[threadIdx.x] = s;
+  }
+  __syncthreads();
 }
 
 template <class MT>
@@ -116,7 +158,7 @@ __device__ void batch_jump(const BatchArgs& a, int scaled, double* red) {
 
 // Phases C and G: vout = vin - G (G^T G)^{-1} g per chunk, partial of (x, vout) with
 // x = x1 + beta x2 (C: p = y + beta p_old against q; G: w against y)
-__device__ void batch_correct_dot(const BatchArgs& a, int second, double* acl, double* red) {
+__device__ void batch_correct_dot(const BatchArgs& a, int second, double* acl, double* red, int* s_flag) {
   for (int it = blockIdx.x; it < a.nrow; it += gridDim.x) {
     const int p = a.row_prob[it];
     if (iload(a.done + p)) continue;
@@ -146,21 +188,34 @@ __device__ void batch_correct_dot(const BatchArgs& a, int second, double* acl, d
     }
     block_sum<1>(acc, red);
     if (threadIdx.x == 0) ast(pr.part + (int64_t)a.row_chunk[it] * PCG_NPART, acc[0]);
+    if (!last_chunk(a.cnt + 3 * p + (second ? 2 : 0), pr.nrow_items, s_flag)) continue;
+    chunk_totals<1>(pr, red);
+    if (threadIdx.x == 0) {
+      if (!second) {
+        // alpha = rho / (p, q)
+        const double pq = red[0];
+        if (!(fabs(pq) > 1e-300) || !isfinite(pq)) finish(a, p, isfinite(pq) ? FETI_EBREAKDOWN : FETI_ENAN);
+        else ast(a.alpha + p, ald(a.rho + p) / pq);
+      } else {
+        // beta = rho_new / rho
+        const double rn = red[0], ro = ald(a.rho + p);
+        if (!(fabs(ro) > 1e-300)) {
+          finish(a, p, FETI_EBREAKDOWN);
+        } else {
+          ast(a.beta + p, rn / ro);
+          ast(a.rho + p, rn);
+        }
+      }
+    }
   }
-}
-
-// sum of problem p's chunk partials, slot c, in chunk order (one thread)
-__device__ inline double chunk_total(const ProbArgs& pr, int c) {
-  double s = 0.0;
-  for (int k = 0; k < pr.nrow_items; ++k) s += ald(pr.part + (int64_t)k * PCG_NPART + c);
-  return s;
 }
 
 // Phase D on one chunk of problem p's multiplier rows: the updates and the chunk's
 // partial sums: per-kind |w|^2 (0..5), the dual energy (6) and, with the update
 // test (NV = 19), per-kind |p|^2 (7..12) and |lambda|^2 (13..18).
 template <int NV>
-__device__ inline void batch_update(const BatchArgs& a, const ProbArgs& pr, int p, int it, double* red) {
+__device__ inline void batch_update(const BatchArgs& a, const ProbArgs& pr, int p, int it, double* red,
+                                    int* s_flag) {
   const double al = ald(a.alpha + p), bt = ald(a.beta + p);
   double acc[NV];
 #pragma unroll
@@ -188,11 +243,38 @@ __device__ inline void batch_update(const BatchArgs& a, const ProbArgs& pr, int 
     }
   }
   block_store<NV>(acc, red, pr.part + (int64_t)a.row_chunk[it] * PCG_NPART);
+  if (!last_chunk(a.cnt + 3 * p + 1, pr.nrow_items, s_flag)) return;
+  // stopping test of problem p
+  chunk_totals<NV>(pr, red);
+  const double* t = red;
+  if (threadIdx.x == 0) {
+    // the tolerances and references are constant during the launch; the counters and
+    // the update ring are read and written device-coherently
+    const double rel = rel_residual_of(t, t[6], pr.sc);
+    const int its = iload(a.iters + p) + 1;
+    istore(a.iters + p, its);
+    const int total = iload(pr.ist + IS_ITERS) + 1;
+    istore(pr.ist + IS_ITERS, total);
+    ast(pr.sc + SC_RES, rel);
+    bool upd = false;
+    if (NV > 7) {
+      double* ring = red + 32;  // LDS, past the totals
+      static_assert(32 + UPD_WIN * 6 <= (PB / 64) * PCG_NPART, "the update ring fits the reduction scratch");
+#pragma unroll
+      for (int k = 0; k < UPD_WIN * 6; ++k) ring[k] = ald(pr.sc + SC_URING + k);
+      upd = update_converged(ring, its, ald(a.alpha + p), t + 7, t + 13, pr.sc[SC_UTOL]);
+#pragma unroll
+      for (int k = 0; k < UPD_WIN * 6; ++k) ast(pr.sc + SC_URING + k, ring[k]);
+    }
+    if (!isfinite(rel)) finish(a, p, FETI_ENAN);
+    else if (rel <= pr.sc[SC_TOL] || upd) finish(a, p, 0);
+    else if (total >= pr.ist[IS_MAXIT]) finish(a, p, FETI_ENOTCONV);
+  }
 }
 
 __global__ void __launch_bounds__(PCG_BLOCK, BATCH_MIN_WAVES) k_pcg_batch(BatchArgs a) {
   extern __shared__ double lds[];
-  __shared__ int s_ok;
+  __shared__ int s_ok, s_flag;
   double* xs = lds;                 // 2 x max_nb
   double* red8 = xs + 2 * a.max_nb; // PB
   double* acl = red8 + PB;          // 2 x PCG_NC_LOCAL
@@ -206,97 +288,70 @@ __global__ void __launch_bounds__(PCG_BLOCK, BATCH_MIN_WAVES) k_pcg_batch(BatchA
       const ProbArgs& pr = a.probs[p];
       ast(a.rho + p, pr.sc[SC_RHO]);
       ast(a.beta + p, 0.0);
-      a.iters[p] = 0;
-      a.status[p] = pr.ist[IS_STATUS];
+      for (int c = 0; c < 3; ++c) istore(a.cnt + 3 * p + c, 0);
+      istore(a.iters + p, 0);
+      istore(a.status + p, pr.ist[IS_STATUS]);
       const int d = pr.ist[IS_DONE] || pr.ist[IS_MAXIT] <= 0;
       istore(a.done + p, d);
       if (d) __hip_atomic_fetch_add(a.ndone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   ok = grid_sync(a.bar, nblk, gen, &s_ok);
-  while (ok) {
+  int it_local = 0, ph = 0;
+  auto stamp = [&]() {
+    if (a.tstamp && blockIdx.x == 0 && threadIdx.x == 0 && it_local < a.tstamp_iters)
+      a.tstamp[it_local * 12 + ph] = (long long)wall_clock64();
+    ++ph;
+  };
+  stamp();
+  for (; ok; ++it_local, ph = 1) {  // stamp 0 of a later iteration is stamp 7 of the one before
     if (iload(a.ndone) >= a.P) break;  // read after a barrier: the same in every block
     // (A) y_b = (K^+)_bb B^T p, p = y + beta p_old
     if (a.f32) batch_gemv<float>(a, 0, xs, red8);
     else batch_gemv<double>(a, 0, xs, red8);
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
+    stamp();
     // (B) q_raw = B y_b, g = G^T q_raw
     batch_jump(a, 0, red);
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
-    // (C) q = P q_raw, partials of (p, q)
-    batch_correct_dot(a, 0, acl, red);
+    stamp();
+    // (C) q = P q_raw, partials of (p, q); alpha = rho / (p, q) by the last chunk's block
+    batch_correct_dot(a, 0, acl, red, &s_flag);
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
-    // (C') alpha = rho / (p, q)
-    if (threadIdx.x == 0)
-      for (int p = blockIdx.x; p < a.P; p += nblk) {
-        if (iload(a.done + p)) continue;
-        const double pq = chunk_total(a.probs[p], 0);
-        if (!(fabs(pq) > 1e-300) || !isfinite(pq)) finish(a, p, isfinite(pq) ? FETI_EBREAKDOWN : FETI_ENAN);
-        else ast(a.alpha + p, ald(a.rho + p) / pq);
-      }
-    if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
+    stamp();
     // (D) lam += alpha p, r -= alpha q_raw, w -= alpha q, p_old = p; partial norms of w
-    // (and of p and lambda for a problem with the update test)
+    // (and of p and lambda for a problem with the update test); the stopping test by
+    // the last chunk's block
     for (int it = blockIdx.x; it < a.nrow; it += nblk) {
       const int p = a.row_prob[it];
       if (iload(a.done + p)) continue;
       const ProbArgs& pr = a.probs[p];
-      if (pr.sc[SC_UTOL] > 0.0) batch_update<19>(a, pr, p, it, red);
-      else batch_update<7>(a, pr, p, it, red);
+      if (pr.sc[SC_UTOL] > 0.0) batch_update<19>(a, pr, p, it, red, &s_flag);
+      else batch_update<7>(a, pr, p, it, red, &s_flag);
     }
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
-    // (D') stopping test
-    if (threadIdx.x == 0)
-      for (int p = blockIdx.x; p < a.P; p += nblk) {
-        if (iload(a.done + p)) continue;
-        const ProbArgs& pr = a.probs[p];
-        double w2[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) w2[k] = chunk_total(pr, k);
-        const double rel = rel_residual_of(w2, chunk_total(pr, 6), pr.sc);
-        const int its = a.iters[p] + 1;
-        a.iters[p] = its;
-        pr.ist[IS_ITERS] += 1;
-        pr.sc[SC_RES] = rel;
-        bool upd = false;
-        if (pr.sc[SC_UTOL] > 0.0) {
-          double p2[6], l2[6];
-#pragma unroll
-          for (int k = 0; k < 6; ++k) {
-            p2[k] = chunk_total(pr, 7 + k);
-            l2[k] = chunk_total(pr, 13 + k);
-          }
-          upd = update_converged(pr.sc + SC_URING, its, ald(a.alpha + p), p2, l2, pr.sc[SC_UTOL]);
-        }
-        if (!isfinite(rel)) finish(a, p, FETI_ENAN);
-        else if (rel <= pr.sc[SC_TOL] || upd) finish(a, p, 0);
-        else if (pr.ist[IS_ITERS] >= pr.ist[IS_MAXIT]) finish(a, p, FETI_ENOTCONV);
-      }
-    if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
+    stamp();
     // (E) z_b = S_bb B^T D w
     if (a.f32) batch_gemv<float>(a, 1, xs, red8);
     else batch_gemv<double>(a, 1, xs, red8);
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
+    stamp();
     // (F) z = D B z_b, g = G^T z
     batch_jump(a, 1, red);
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
-    // (G) y = P z, partials of (w, y)
-    batch_correct_dot(a, 1, acl, red);
+    stamp();
+    // (G) y = P z, partials of (w, y); beta = rho_new / rho by the last chunk's block
+    batch_correct_dot(a, 1, acl, red, &s_flag);
     if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
-    // (G') beta = rho_new / rho
-    if (threadIdx.x == 0)
-      for (int p = blockIdx.x; p < a.P; p += nblk) {
-        if (iload(a.done + p)) continue;
-        const double rn = chunk_total(a.probs[p], 0), ro = ald(a.rho + p);
-        if (!(fabs(ro) > 1e-300)) { finish(a, p, FETI_EBREAKDOWN); continue; }
-        ast(a.beta + p, rn / ro);
-        ast(a.rho + p, rn);
-      }
-    if (!(ok = grid_sync(a.bar, nblk, gen, &s_ok))) break;
+    stamp();
   }
   if (!ok && threadIdx.x == 0)
     for (int p = blockIdx.x; p < a.P; p += nblk) {
       const ProbArgs& pr = a.probs[p];
-      if (!pr.ist[IS_DONE]) { pr.ist[IS_STATUS] = FETI_EHIP; pr.ist[IS_DONE] = 1; a.status[p] = FETI_EHIP; }
+      if (!iload(pr.ist + IS_DONE)) {
+        istore(pr.ist + IS_STATUS, FETI_EHIP);
+        istore(pr.ist + IS_DONE, 1);
+        istore(a.status + p, FETI_EHIP);
+      }
     }
 }
 

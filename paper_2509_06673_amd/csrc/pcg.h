@@ -86,8 +86,11 @@ struct BatchArgs {
   int32_t* iters = nullptr;   // per problem: iterations of this launch
   int32_t* status = nullptr;  // per problem: status at the end of this launch
   int32_t* ndone = nullptr;   // problems finished
+  int32_t* cnt = nullptr;     // per problem: chunk counters of the reductions of phases C, D and G
   GridBarrier* bar = nullptr;
   int max_nb = 0;
+  long long* tstamp = nullptr;  // optional: block 0 records the wall clock after each barrier
+  int tstamp_iters = 0;         // iterations recorded (8 stamps each, 12 slots apart)
 };
 size_t pcg_batch_shmem(int max_nb);
 int pcg_batch_max_grid(int max_nb);
