@@ -52,11 +52,16 @@ class Blocks:
 
 
 class MonolithicSystem:
-    """Assembled system of eq. (linalg-system) for one workload."""
+    """Assembled system of eq. (linalg-system) for one workload.
 
-    def __init__(self, w: Workload):
+    lumped_storage: the fluid-content term of row 4 (-R_P eta^n and -R_P eta^{n-1}) with
+    the mass matrix lumped to its row sums: the implicit counterpart of the decoupled
+    scheme in ``oracle.decoupled`` (row 3 keeps the consistent mass)."""
+
+    def __init__(self, w: Workload, lumped_storage: bool = False):
         t0 = time.perf_counter()
         self.w = w
+        self.lumped_storage = lumped_storage
         self.mesh = m = Mesh(w.ncell, w.order_u, w.layout)
         self.loads = make_loads(w)
         lamP, muP = lame(w.mat_p)
@@ -207,7 +212,13 @@ class MonolithicSystem:
         blk('eta', sidx, 'xiP', sidx, emP['R'], k1)
         blk('eta', sidx, 'eta', sidx, emP['R'], k2)
         blk('eta', sidx, 'p', sidx, emP['R'], -1.0)
-        blk('p', sidx, 'eta', sidx, emP['R'], -1.0)
+        if self.lumped_storage:
+            lumpR = np.zeros_like(emP['R'])
+            idx = np.arange(emP['R'].shape[1])
+            lumpR[:, idx, idx] = emP['R'].sum(axis=2)
+            blk('p', sidx, 'eta', sidx, lumpR, -1.0)
+        else:
+            blk('p', sidx, 'eta', sidx, emP['R'], -1.0)
         blk('p', sidx, 'p', sidx, emP['Af'], -tau)
         # elastic region ----------------------------------------------------
         XE = m.X[self.triE]
@@ -239,7 +250,11 @@ class MonolithicSystem:
         # pieces for the right-hand side
         self._udP, self._sidxP, self._udE = ud, sidx, udE
         self.RP = K[o['eta']:o['eta'] + b.sizes['eta'], o['p']:o['p'] + b.sizes['p']] * -1.0
-        # R_P as (p rows) x (eta cols) is the same matrix (symmetric)
+        # R_P as (p rows) x (eta cols) is the same matrix (symmetric); the storage term of
+        # row 4 (R_P, or its lumped form)
+        self.R4 = self.RP
+        if self.lumped_storage:
+            self.R4 = (K[o['p']:o['p'] + b.sizes['p'], o['eta']:o['eta'] + b.sizes['eta']] * -1.0).T.tocsr()
 
     # ------------------------------------------------------------------
     def rhs(self, t: float, eta_prev: np.ndarray) -> np.ndarray:
@@ -248,7 +263,7 @@ class MonolithicSystem:
         o = b.offsets
         if w.load.kind == RAW:
             f, Z = self._raw_loads(t)
-            f[o['p']:o['p'] + b.sizes['p']] = -(self.RP.T @ eta_prev) - w.tau * Z
+            f[o['p']:o['p'] + b.sizes['p']] = -(self.R4.T @ eta_prev) - w.tau * Z
             return f
         f = np.zeros(self.ndof)
         FuP, ZP = load_vectors(w.order_u, m.X[self.triP], L.fPx, L.fPy, L.z, t)
@@ -258,7 +273,7 @@ class MonolithicSystem:
         Z = np.zeros(b.sizes['p'])
         np.add.at(Z, self._sidxP.ravel(), ZP.ravel())
         # row 4: -R_P eta^{n-1} - tau Z^n   (R_P symmetric, rows = p test nodes)
-        f[o['p']:o['p'] + b.sizes['p']] = -(self.RP.T @ eta_prev) - w.tau * Z
+        f[o['p']:o['p'] + b.sizes['p']] = -(self.R4.T @ eta_prev) - w.tau * Z
         return f
 
     def dirichlet_values(self, t: float) -> np.ndarray:
@@ -409,9 +424,10 @@ class Trajectory:
 
 
 def solve_steps(w: Workload, nsteps: Optional[int] = None, keep: bool = True,
-                eta0: Optional[np.ndarray] = None, init: str = "interp") -> Trajectory:
+                eta0: Optional[np.ndarray] = None, init: str = "interp",
+                lumped_storage: bool = False) -> Trajectory:
     """Run ``nsteps`` backward-Euler steps of eq. (linalg-system) from t=0."""
-    S = MonolithicSystem(w)
+    S = MonolithicSystem(w, lumped_storage=lumped_storage)
     S.factor()
     n = w.nsteps if nsteps is None else nsteps
     eta = S.initial_eta(init) if eta0 is None else eta0
