@@ -327,11 +327,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--variant", default="both", choices=["fp64", "fp64x", "mixed", "both"],
+    ap.add_argument("--variant", default="both", choices=["fp64", "fp64x", "mixed", "decoupled", "both"],
                     help="fp64: FP64 factors, each first solve from the previous step's multipliers; "
                          "fp64x: the same from the extrapolation 2 lambda^n - lambda^(n-1); mixed: "
-                         "FP32 factors on the matrix cores with FP64 refinement; both: fp64 is the "
-                         "headline value and fp64x and mixed are reported beside it")
+                         "FP32 factors on the matrix cores with FP64 refinement; decoupled: the explicit "
+                         "fluid step with the momentum balance alone (FP64); both: fp64 is the "
+                         "headline value and the others are reported beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -363,14 +364,21 @@ def main():
         print(json.dumps(batched_run(args)), flush=True)
         return
 
+    import numpy as np
     import torch
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
     import workloads as W
     w = W.nearly_incompressible_large()
-    variants = ["fp64", "fp64x", "mixed"] if args.variant == "both" else [args.variant]
+    variants = ["fp64", "fp64x", "mixed", "decoupled"] if args.variant == "both" else [args.variant]
     res = {v: run_variant(args, w, v) for v in variants}
     prim = res[variants[0]]
+    if "fp64" in res and "decoupled" in res:
+        # how far the decoupled scheme's fields are from the coupled scheme's after the same
+        # steps (its splitting error; the pressure is a small difference of large terms)
+        a, b = res["decoupled"]["fields"], res["fp64"]["fields"]
+        res["decoupled"]["vs_coupled_rel"] = {
+            k: float(np.abs(a[k] - b[k]).max() / max(np.abs(b[k]).max(), 1e-300)) for k in b}
     out = {
         "metric": "time steps/s and PCG iters at rel. residual 1e-10",
         "value": prim["value"],
@@ -392,7 +400,8 @@ def main():
                                           "pcg_iters_mean", "pcg_iters_first_solve", "refinement_corrections",
                                           "pcg_us_per_iteration", "pcg_iters_all_steps", "kernels", "dtype",
                                           "torn_residual_max", "torn_residual_per_step",
-                                          "replay_matches_timed_run")}
+                                          "replay_matches_timed_run", "sizes") if k in r}
+                        | ({"vs_coupled_rel": r["vs_coupled_rel"]} if "vs_coupled_rel" in r else {})
                      for v, r in res.items()},
     }
     if args.calibrate_copy_mb > 0:
@@ -427,6 +436,8 @@ def run_variant(args, w, variant):
     from paper_2509_06673_amd import _binding as B
     from paper_2509_06673_amd.workload import load, opts, opts_mixed, mesh_args, material
     stream = torch.cuda.current_stream()
+    if variant == "decoupled":
+        w = w.replace(scheme="decoupled")
     f = B.Feti(stream)
     f.setup_mesh(**mesh_args(w))
     sizes = f.get_sizes()
@@ -466,6 +477,12 @@ def run_variant(args, w, variant):
         pcg_ms.append(st["t_ms"][2])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - ta
+    fields = {}
+    for name, kind, nlat in (("ux", B.FIELD_UX, sizes["n_u"]), ("xi_p", B.FIELD_XI_P, sizes["n_p1"]),
+                             ("eta", B.FIELD_ETA, sizes["n_p1"]), ("p", B.FIELD_P, sizes["n_p1"])):
+        out_f = torch.empty(nlat, dtype=torch.float64, device="cuda")
+        f.get_field(kind, out_f)
+        fields[name] = out_f.cpu().numpy()
     # untimed replay of the same (deterministic) trajectory from the checkpoint: the FP64
     # residual of the torn system after every step, and the iteration counts, which must
     # equal those of the timed run
@@ -493,6 +510,7 @@ def run_variant(args, w, variant):
         "dtype": "f32+f64" if mixed else "f64",
         "sizes": {"n_sub": sizes["n_sub"], "n_lambda": sizes["n_lambda"], "n_c": sizes["n_c"],
                   "sum_ns": sizes["sum_ns"], "max_ns": sizes["max_ns"], "max_nb": sizes["max_nb"]},
+        "fields": fields,
         "pcg_iters_mean": float(np.mean(iters)), "pcg_iters_first_solve": iters_first,
         "pcg_iters_all_steps": warm_iters + iters,
         "refinement_corrections": ir_steps,

@@ -91,7 +91,20 @@ typedef struct {
                              increasing from 0 to ncell, or if a subdomain straddles the
                              interface of the layout. */
     const int32_t* cut_y; /* the same for the rows */
+    int32_t scheme;       /* FETI_SCHEME_COUPLED (eq. (linalg-system) at once) or
+                             FETI_SCHEME_DECOUPLED (the explicit fluid step of the Remark
+                             after eq. (linalg-system); see feti_step) */
 } feti_mesh_desc;
+
+/* Time discretisation of a step.  DECOUPLED: the fluid content and the pressure leave the
+ * subdomain unknowns, so a poroelastic subdomain carries (u_P, xi_P) like an elastic one
+ * (u_E, xi_E) and no multiplier glues eta or p.  Each step first updates the fluid content
+ * explicitly with the lumped mass and the previous pressure, m_i (eta^n_i - eta^{n-1}_i) =
+ * tau (Z^n - A_f p^{n-1})_i (at pressure Dirichlet nodes eta^n = (p_D - k1 xi^{n-1}) / k2),
+ * then solves the momentum balance with eta^n known, and sets p^n = k1 xi^n + k2 eta^n
+ * nodally (p_D on Dirichlet nodes).  Explicit, hence stable for tau below the explicit
+ * diffusion limit of the consolidation operator and for alpha^2 < c0 lambda_P. */
+enum { FETI_SCHEME_COUPLED = 0, FETI_SCHEME_DECOUPLED = 1 };
 
 /* Parameters of Table 2 for one region; lame_mode 0: mu = E/(2(1+nu)),
  * 1: mu = E/(1+nu) as printed in Table 3. */
@@ -282,6 +295,8 @@ int feti_torn_residual(feti_ctx ctx, double* rho_host);
  * device vector of feti_state_size() doubles:
  *   [ torn primal solution of the last step (sum n_s; its eta entries are eta^n)
  *   | lambda^n (N_lambda) | lambda^{n-1} (N_lambda) | total correction (N_lambda) ]
+ * followed, for FETI_SCHEME_DECOUPLED, by eta^n, p^n and xi_P^n on the P1 lattice (3 x
+ * (n1)^2; the torn solution then has no eta entries)
  * and four host integers meta = {steps taken, have lambda^n, have lambda^{n-1},
  * have a correction}.  feti_set_state on a context built with the same mesh,
  * materials and time step continues the trajectory bit for bit: steps 1..10 equal
@@ -298,7 +313,9 @@ int feti_set_state(feti_ctx ctx, const double* state_dev, const int64_t* meta_ho
  * the P1 lattice of spacing h, (n1)^2 doubles; sizes [8] and [7] of feti_get_sizes).
  * A node shared by several subdomains takes the value of the lowest-numbered one
  * (the copies agree to the interface tolerance); nodes that carry no unknown of the
- * field (Dirichlet nodes, nodes outside the field's region) are set to 0.
+ * field (Dirichlet nodes, nodes outside the field's region) are set to 0.  With
+ * FETI_SCHEME_DECOUPLED, ETA and P are the explicit step's eta^n and p^n at every node of
+ * the poroelastic region (p^n = p_D on pressure Dirichlet nodes).
  * out_dev: device, caller-owned.  Synchronises the context stream. */
 enum { FETI_FIELD_UX = 0, FETI_FIELD_UY = 1, FETI_FIELD_ETA = 2, FETI_FIELD_XI_P = 3, FETI_FIELD_P = 4,
        FETI_FIELD_XI_E = 5 };
@@ -323,7 +340,8 @@ int feti_interface_load(feti_ctx ctx, const feti_load* load, double* out_dev);
  * finished problem drops out of the launch.  The contexts stay owned by the caller
  * and must outlive the batch. */
 typedef struct feti_batch_s* feti_batch;
-int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob);  /* failure text: feti_last_error(ctxs[0]) */
+int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob);  /* failure text: feti_last_error(ctxs[0]);
+                                                                          contexts of the coupled scheme only */
 int feti_batch_destroy(feti_batch b);
 const char* feti_batch_last_error(feti_batch b);
 

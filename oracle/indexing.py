@@ -132,9 +132,13 @@ def build(w: Workload) -> IndexSpec:
                 for i in range(i0, i1 + 1):
                     node = j * (n + 1) + i
                     if poro:
-                        codes += [8 * node + 2, 8 * node + 3]
-                        if not _sides(i, j, n, w.dirichlet_p):
-                            codes.append(8 * node + 4)
+                        if w.scheme == "decoupled":
+                            # eta and p are not unknowns of the subdomain problems
+                            codes.append(8 * node + 3)
+                        else:
+                            codes += [8 * node + 2, 8 * node + 3]
+                            if not _sides(i, j, n, w.dirichlet_p):
+                                codes.append(8 * node + 4)
                     else:
                         codes.append(8 * node + 5)
             for c in codes:

@@ -35,10 +35,14 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM", 
                 ENAN: "ENAN"}
 
 
+SCHEME_COUPLED, SCHEME_DECOUPLED = 0, 1
+
+
 class MeshDesc(C.Structure):
     _fields_ = [("ncell", C.c_int32), ("order_u", C.c_int32), ("layout", C.c_int32),
                 ("nsub_x", C.c_int32), ("nsub_y", C.c_int32), ("dirichlet_u", C.c_uint32),
-                ("dirichlet_p", C.c_uint32), ("cut_x", C.POINTER(C.c_int32)), ("cut_y", C.POINTER(C.c_int32))]
+                ("dirichlet_p", C.c_uint32), ("cut_x", C.POINTER(C.c_int32)), ("cut_y", C.POINTER(C.c_int32)),
+                ("scheme", C.c_int32)]
 
 
 class Material(C.Structure):
@@ -238,12 +242,12 @@ class Feti:
 
     # -- setup ----------------------------------------------------------------
     def setup_mesh(self, ncell, order_u, layout, nsub_x, nsub_y, dirichlet_u=0xF, dirichlet_p=0xF,
-                   cut_x=None, cut_y=None):
+                   cut_x=None, cut_y=None, scheme=0):
         cx = (C.c_int32 * len(cut_x))(*cut_x) if cut_x is not None else None
         cy = (C.c_int32 * len(cut_y))(*cut_y) if cut_y is not None else None
         d = MeshDesc(ncell, order_u, layout, nsub_x, nsub_y, dirichlet_u, dirichlet_p,
                      C.cast(cx, C.POINTER(C.c_int32)) if cx is not None else None,
-                     C.cast(cy, C.POINTER(C.c_int32)) if cy is not None else None)
+                     C.cast(cy, C.POINTER(C.c_int32)) if cy is not None else None, scheme)
         return self._check(self.lib.feti_setup_mesh(self.ctx, C.byref(d)), "feti_setup_mesh")
 
     def get_sizes(self) -> Dict[str, int]:

@@ -105,6 +105,10 @@ struct feti_ctx_s {
   GridBarrier* bar = nullptr;
   double* ppart = nullptr;
   int pgrid = 0;
+  // decoupled scheme: eta, p and xi_P of the fluid nodes on the P1 lattice, the lumped mass
+  // per fluid node, per-element fluid contributions, and the constants of row 3
+  double *dec_eta = nullptr, *dec_p = nullptr, *dec_xi = nullptr, *dec_mass = nullptr, *dec_ce = nullptr;
+  double dec_k1 = 0.0, dec_k2 = 0.0;
   // captured PCG iteration chunks, keyed by the multiplier buffer they update
   struct Graph {
     hipGraphExec_t exec = nullptr;
@@ -254,6 +258,21 @@ int upload_mesh(feti_ctx ctx) {
   RC(upload(ctx, &m.dwt, h.dwt));
   RC(upload(ctx, &m.row_kind, row_kind));
   RC(upload(ctx, &m.float_sub, h.float_sub));
+  m.decoupled = h.desc.scheme == FETI_SCHEME_DECOUPLED ? 1 : 0;
+  m.n_dec = (int)h.dec_node.size();
+  if (m.decoupled) {
+    RC(upload(ctx, &m.dec_node, h.dec_node));
+    RC(upload(ctx, &m.dec_ptr, h.dec_ptr));
+    RC(upload(ctx, &m.dec_ent, h.dec_ent));
+    RC(upload(ctx, &m.dec_xi, h.dec_xi));
+    RC(upload(ctx, &m.dec_pdir, h.dec_pdir));
+    const size_t n1n = (size_t)h.n1 * h.n1;
+    RC(dalloc(ctx, &ctx->dec_eta, n1n, ctx->allocs));
+    RC(dalloc(ctx, &ctx->dec_p, n1n, ctx->allocs));
+    RC(dalloc(ctx, &ctx->dec_xi, n1n, ctx->allocs));
+    RC(dalloc(ctx, &ctx->dec_mass, std::max(m.n_dec, 1), ctx->allocs));
+    RC(dalloc(ctx, &ctx->dec_ce, (size_t)m.nelem * 3, ctx->allocs));
+  }
   // vectors
   const int64_t nl = h.n_lambda;
   RC(dalloc(ctx, &ctx->f, h.sum_ns, ctx->allocs));
@@ -1314,6 +1333,26 @@ int feti_init_state(feti_ctx ctx, const feti_load* load) {
   HIPCHK(hipMemsetAsync(ctx->lam_prev2, 0, m.n_lambda * sizeof(double), ctx->stream));
   LoadDev L = make_load(ctx, load);
   launch_init_eta(m, ctx->u, L, ctx->stream);
+  if (m.decoupled) {
+    // the fluid state on the lattice, and the lumped mass (from the stored element matrices)
+    const double D = ctx->lamP * ctx->matP.c0 + ctx->matP.alpha * ctx->matP.alpha;
+    if (!(D > 0.0) || ctx->matP.alpha == 0.0)
+      return fail(ctx, FETI_EINVAL, "decoupled scheme needs alpha != 0 (p = k1 xi + k2 eta)");
+    ctx->dec_k1 = ctx->matP.alpha / D;
+    ctx->dec_k2 = ctx->lamP / D;
+    const size_t n1n = (size_t)ctx->mh.n1 * ctx->mh.n1;
+    launch_zero((int64_t)n1n, ctx->dec_eta, ctx->stream);
+    launch_zero((int64_t)n1n, ctx->dec_p, ctx->stream);
+    launch_zero((int64_t)n1n, ctx->dec_xi, ctx->stream);
+    launch_dec_init(m, L, ctx->dec_k1, ctx->dec_k2, ctx->dec_eta, ctx->dec_p, ctx->dec_xi, ctx->stream);
+    double* me = nullptr;
+    HIPCHK(hipMalloc(&me, (size_t)m.nelem * 3 * sizeof(double)));
+    launch_dec_fluid(m, ctx->mpP, L, ctx->dec_p, ctx->dec_ce, me, ctx->stream);
+    launch_dec_mass(m, me, ctx->dec_mass, ctx->stream);
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(me);
+    HIPCHK(e);
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->nstep = 0;
@@ -1331,7 +1370,14 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, fet
   HIPCHK(hipEventRecord(ctx->ev[0], st));
   LoadDev L = make_load(ctx, load);
   int cmode = 0;
-  if (L.kind == FETI_LOAD_MANUFACTURED || L.kind == FETI_LOAD_PATCH) {
+  if (m.decoupled) {
+    // explicit fluid step: eta^n from eta^{n-1}, p^{n-1} (and xi^{n-1} at pressure
+    // Dirichlet nodes); the momentum rows then read eta^n through their prescribed eta
+    // columns (no cached right-hand side: those columns change every step)
+    launch_dec_fluid(m, ctx->mpP, L, ctx->dec_p, ctx->dec_ce, nullptr, st);
+    launch_dec_update(m, L, ctx->dec_k1, ctx->dec_k2, ctx->dec_ce, ctx->dec_mass, ctx->dec_eta, ctx->dec_xi, st);
+    L.eta_dec = ctx->dec_eta;
+  } else if (L.kind == FETI_LOAD_MANUFACTURED || L.kind == FETI_LOAD_PATCH) {
     // these loads do not depend on t: the quadrature of a step repeats that of the last
     // step with the same load and material parameters
     unsigned char key[sizeof(ctx->ekey)];
@@ -1377,6 +1423,12 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, fet
   const double* cand = (o->start == FETI_START_BEST) ? ctx->lam_given : nullptr;
   // (solve_refined advances the multiplier history and synchronises the stream)
   int rc = solve_refined(ctx, o, cold ? std::max(o->ir_cold, o->ir_max) : o->ir_max, stats, cand, &took, true);
+  if (m.decoupled) {
+    // pressure from row 3 (nodal): p^n = k1 xi^n + k2 eta^n
+    launch_dec_pressure(m, L, ctx->dec_k1, ctx->dec_k2, ctx->u, ctx->dec_xi, ctx->dec_p, ctx->dec_eta, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+  }
   if (cand && took) used = FETI_START_GIVEN;
   ctx->have_prev2 = ctx->have_prev;
   ctx->have_prev = true;
@@ -1468,6 +1520,7 @@ int feti_state_size(feti_ctx ctx, int64_t* n_doubles) {
   if (!ctx || !n_doubles) return FETI_EINVAL;
   if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "state_size before assemble");
   *n_doubles = ctx->dm.sum_ns + 3 * ctx->dm.n_lambda;
+  if (ctx->dm.decoupled) *n_doubles += 3 * (int64_t)ctx->mh.n1 * ctx->mh.n1;  // eta, p, xi_P on the lattice
   return FETI_OK;
 }
 
@@ -1484,6 +1537,14 @@ int feti_get_state(feti_ctx ctx, double* state_dev, int64_t* meta) {
   HIPCHK(hipMemcpyAsync(o, ctx->lam_prev2, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
   o += m.n_lambda;
   HIPCHK(hipMemcpyAsync(o, ctx->dlam_prev, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
+  o += m.n_lambda;
+  if (m.decoupled) {
+    const size_t n1n = (size_t)ctx->mh.n1 * ctx->mh.n1;
+    for (const double* src : {(const double*)ctx->dec_eta, (const double*)ctx->dec_p, (const double*)ctx->dec_xi}) {
+      HIPCHK(hipMemcpyAsync(o, src, n1n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      o += n1n;
+    }
+  }
   HIPCHK(hipStreamSynchronize(st));
   meta[0] = ctx->nstep;
   meta[1] = ctx->have_prev ? 1 : 0;
@@ -1508,6 +1569,14 @@ int feti_set_state(feti_ctx ctx, const double* state_dev, const int64_t* meta) {
   HIPCHK(hipMemcpyAsync(ctx->lam_prev2, i, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
   i += m.n_lambda;
   HIPCHK(hipMemcpyAsync(ctx->dlam_prev, i, m.n_lambda * sizeof(double), hipMemcpyDeviceToDevice, st));
+  i += m.n_lambda;
+  if (m.decoupled) {
+    const size_t n1n = (size_t)ctx->mh.n1 * ctx->mh.n1;
+    for (double* dst : {ctx->dec_eta, ctx->dec_p, ctx->dec_xi}) {
+      HIPCHK(hipMemcpyAsync(dst, i, n1n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      i += n1n;
+    }
+  }
   HIPCHK(hipStreamSynchronize(st));
   ctx->nstep = meta[0];
   ctx->have_prev = meta[1] != 0;
@@ -1524,7 +1593,10 @@ int feti_get_field(feti_ctx ctx, int32_t field, double* out_dev) {
   const MeshHost& h = ctx->mh;
   const int64_t nlat = field <= FETI_FIELD_UY ? (int64_t)h.mu * h.mu : (int64_t)h.n1 * h.n1;
   launch_zero(nlat, out_dev, ctx->stream);
-  launch_field_scatter(m, ctx->u, field, out_dev, ctx->stream);
+  if (m.decoupled && (field == FETI_FIELD_ETA || field == FETI_FIELD_P))
+    launch_dec_field(m, field == FETI_FIELD_ETA ? ctx->dec_eta : ctx->dec_p, out_dev, ctx->stream);
+  else
+    launch_field_scatter(m, ctx->u, field, out_dev, ctx->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return FETI_OK;
@@ -2038,6 +2110,7 @@ int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob) {
     if (c->precision != ctxs[0]->precision) return bad(FETI_EINVAL, "batch contexts of different precision");
     if (c->precond == FETI_PRECOND_NONE) return bad(FETI_EINVAL, "batch needs a preconditioner");
     if (c->nc > PCG_NC_LOCAL) return bad(FETI_EINVAL, "coarse space too large for a batch");
+    if (c->dm.decoupled) return bad(FETI_EINVAL, "a batch steps the coupled scheme only");
     b->ctx.push_back(c);
   }
   b->stream = ctxs[0]->stream;

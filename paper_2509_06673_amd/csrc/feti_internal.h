@@ -76,6 +76,12 @@ struct MeshHost {
   std::vector<double> rb;             // sum_nb x 3 (zero rows for non-floating subdomains)
   // rigid modes on all local DOFs (torn, 3 per DOF) for the recovery
   std::vector<double> rfull;
+  // decoupled scheme: the P1 lattice nodes of the poroelastic region (increasing), per node
+  // its (element, vertex) entries e * 3 + v over the poroelastic elements (element order,
+  // CSR), whether it carries pressure Dirichlet data, and the torn index of its first
+  // xi_P copy (lowest subdomain)
+  std::vector<int32_t> dec_node, dec_ptr, dec_ent, dec_xi;
+  std::vector<uint8_t> dec_pdir;
 };
 
 // Builds every host-side table from the mesh description (the numbering that

@@ -67,6 +67,8 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
   if (n < 1 || (d.order_u != 1 && d.order_u != 2) || d.nsub_x < 1 || d.nsub_y < 1 ||
       d.nsub_x > n || d.nsub_y > n || d.layout < 0 || d.layout > 2)
     return "invalid mesh description";
+  if (d.scheme != FETI_SCHEME_COUPLED && d.scheme != FETI_SCHEME_DECOUPLED) return "unknown time scheme";
+  const bool decoupled = d.scheme == FETI_SCHEME_DECOUPLED;
   m = MeshHost();
   m.desc = d;
   m.ratio = d.order_u == 2 ? 2 : 1;
@@ -114,9 +116,10 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
         for (int i = s.i0; i <= s.i1; ++i) {
           const int32_t node = j * m.n1 + i;
           if (s.poro) {
-            s.codes.push_back(8 * node + K_ETA);
+            // decoupled: eta and p are not unknowns of the subdomain problems
+            if (!decoupled) s.codes.push_back(8 * node + K_ETA);
             s.codes.push_back(8 * node + K_XIP);
-            if (!on_sides(i, j, n, d.dirichlet_p)) s.codes.push_back(8 * node + K_P);
+            if (!decoupled && !on_sides(i, j, n, d.dirichlet_p)) s.codes.push_back(8 * node + K_P);
           } else {
             s.codes.push_back(8 * node + K_XIE);
           }
@@ -334,6 +337,47 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
           }
         }
     m.sub_el_off[s.sid + 1] = (int32_t)m.el_sub.size();
+  }
+  // decoupled scheme: the fluid nodes and their element entries
+  if (decoupled) {
+    const int n1n = m.n1 * m.n1;
+    std::vector<int32_t> cntn(n1n, 0), dec_index(n1n, -1);
+    const int64_t nel0 = (int64_t)m.el_sub.size();
+    for (int64_t e = 0; e < nel0; ++e) {
+      if (!m.subs[m.el_sub[e]].poro) continue;
+      for (int v = 0; v < 3; ++v) ++cntn[m.el_code[e * m.edof + 2 * nloc + v] >> 3];
+    }
+    for (int node = 0; node < n1n; ++node)
+      if (cntn[node] > 0) {
+        dec_index[node] = (int32_t)m.dec_node.size();
+        m.dec_node.push_back(node);
+        const int i = node % m.n1, j = node / m.n1;
+        m.dec_pdir.push_back(on_sides(i, j, n, d.dirichlet_p) ? 1 : 0);
+      }
+    const int nd = (int)m.dec_node.size();
+    m.dec_ptr.assign(nd + 1, 0);
+    for (int k = 0; k < nd; ++k) m.dec_ptr[k + 1] = m.dec_ptr[k] + cntn[m.dec_node[k]];
+    m.dec_ent.assign(m.dec_ptr[nd], 0);
+    std::vector<int32_t> fillp(m.dec_ptr.begin(), m.dec_ptr.end() - 1);
+    for (int64_t e = 0; e < nel0; ++e) {
+      if (!m.subs[m.el_sub[e]].poro) continue;
+      for (int v = 0; v < 3; ++v) {
+        const int k = dec_index[m.el_code[e * m.edof + 2 * nloc + v] >> 3];
+        m.dec_ent[fillp[k]++] = (int32_t)(e * 3 + v);
+      }
+    }
+    m.dec_xi.assign(nd, -1);
+    for (const SubHost& s : m.subs) {
+      if (!s.poro) continue;
+      for (int i = 0; i < s.ns; ++i) {
+        const int32_t c = s.codes[i];
+        if (c % 8 != K_XIP) continue;
+        const int k = dec_index[c / 8];
+        if (k >= 0 && m.dec_xi[k] < 0) m.dec_xi[k] = (int32_t)(s.off + i);
+      }
+    }
+    for (int k = 0; k < nd; ++k)
+      if (m.dec_xi[k] < 0) return "a poroelastic node without a xi_P unknown";
   }
   // DOF -> (element, row) adjacency, elements in increasing order
   const int64_t nel = (int64_t)m.el_sub.size();

@@ -55,6 +55,12 @@ struct DevMesh {
   int32_t* row_kind = nullptr;  // DOF kind of each row
   // coarse space
   int32_t* float_sub = nullptr;
+  // decoupled scheme: the fluid nodes of the poroelastic region (P1 lattice indices), per
+  // node its (element, vertex) entries e * 3 + v (CSR), pressure Dirichlet flags and the
+  // torn index of its first xi_P copy
+  int decoupled = 0, n_dec = 0;
+  int32_t *dec_node = nullptr, *dec_ptr = nullptr, *dec_ent = nullptr, *dec_xi = nullptr;
+  uint8_t* dec_pdir = nullptr;
 };
 
 // assembly / right-hand side (kernels_fem.hip)
@@ -71,6 +77,21 @@ void launch_interface_load(const DevMesh& m, const LoadDev& L, double* out, hipS
 // y = K x (torn, element by element, overwriting y)
 // K_e of every element into m.emat (once the materials and tau are known)
 void launch_elem_store(const DevMesh& m, MatParams mpP, MatParams mpE, hipStream_t st);
+// decoupled scheme (the explicit fluid step of the Remark after eq. (linalg-system)):
+// per poroelastic element and vertex the contribution tau Z^n - tau A_f p of the fluid
+// rows (and with me != null the lumped mass row sums); per fluid node the lumped mass;
+// eta^n; the pressure from the momentum solution; the initial state; a field on the
+// lattice
+void launch_dec_fluid(const DevMesh& m, const MatParams& mpP, const LoadDev& L, const double* p_lat, double* ce,
+                      double* me, hipStream_t st);
+void launch_dec_mass(const DevMesh& m, const double* me, double* mass, hipStream_t st);
+void launch_dec_update(const DevMesh& m, const LoadDev& L, double k1, double k2, const double* ce,
+                       const double* mass, double* eta_lat, const double* xi_lat, hipStream_t st);
+void launch_dec_pressure(const DevMesh& m, const LoadDev& L, double k1, double k2, const double* u, double* xi_lat,
+                         double* p_lat, const double* eta_lat, hipStream_t st);
+void launch_dec_init(const DevMesh& m, const LoadDev& L, double k1, double k2, double* eta_lat, double* p_lat,
+                     double* xi_lat, hipStream_t st);
+void launch_dec_field(const DevMesh& m, const double* src_lat, double* out, hipStream_t st);
 void launch_elem_matvec(const DevMesh& m, const double* x, double* y, MatParams mpP, MatParams mpE,
                         hipStream_t st);
 

@@ -53,6 +53,7 @@ __global__ void k_assemble(const int32_t* __restrict__ el_sub, const int32_t* __
 __device__ inline double dirichlet_value(const LoadDev& L, bool poro, int32_t code, int umu,
                                          double uh, int n1, double h) {
   const int kind = code & 7, node = code >> 3;
+  if (kind == 2 && L.eta_dec) return L.eta_dec[node];  // decoupled scheme: eta^n of the step
   if (L.kind == FETI_LOAD_RAW) {
     if (kind <= 1) return L.g_u ? L.g_u[(int64_t)kind * umu * umu + node] : 0.0;
     if (kind == 4) return L.g_p ? L.g_p[node] : 0.0;
@@ -206,7 +207,7 @@ __device__ __forceinline__ void rhs_elem_body(const DevMesh& m, const double* __
   if (poro)
     for (int k = 0; k < 3; ++k) pload[k] = acc[nu + 6 + k];
   const int32_t* ld = m.el_ldof + e * edof;
-  if (poro) {
+  if (poro && ld[nu + 3] >= 0) {  // (the decoupled scheme has no eta unknowns)
     const double* eta = eta_prev + m.soff[s];
     double ev[3];
     for (int b = 0; b < 3; ++b) ev[b] = eta[ld[nu + 3 + b]];
@@ -260,8 +261,10 @@ __global__ void __launch_bounds__(256) k_rhs_prows(DevMesh m, const double* __re
   double acc = cache[(int64_t)m.nelem * edof + e * 3 + k];
   ElemGeom g;
   elem_geom(m.el_cell[e], m.el_type[e], ncell, g);
-  const double* eta = eta_prev + m.soff[s];
-  for (int b = 0; b < 3; ++b) acc -= moment2(g, k, b) * eta[ld[nu + 3 + b]];
+  if (ld[nu + 3] >= 0) {  // (the decoupled scheme has no eta unknowns)
+    const double* eta = eta_prev + m.soff[s];
+    for (int b = 0; b < 3; ++b) acc -= moment2(g, k, b) * eta[ld[nu + 3 + b]];
+  }
   if (ld[r] >= 0) {
     const int umu = order * ncell + 1;
     const double uh = 1.0 / (order * ncell), h = 1.0 / ncell;
@@ -428,6 +431,174 @@ void launch_elem_matvec(const DevMesh& m, const double* x, double* y, MatParams 
   const int64_t nthreads = (int64_t)m.nelem * m.edof;
   hipLaunchKernelGGL(k_elem_matvec, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, m, x);
   hipLaunchKernelGGL(k_gather_elem, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, m, y);
+}
+
+// ---- decoupled scheme: the explicit fluid step ------------------------------------
+// Remark after eq. (linalg-system): the fluid content is advanced by explicit Euler with
+// the lumped mass and the previous pressure, m_i (eta^n_i - eta^{n-1}_i) = tau (Z^n -
+// A_f p^{n-1})_i, before the momentum balance is solved with eta^n known; the pressure
+// then follows nodally from row 3, p = k1 xi + k2 eta.  The element matrices stored at
+// assembly hold the p rows of row 4: -R (eta columns) and -tau A_f (p columns).
+
+// The load part of the fluid rows of element e: -tau (z, phi_k) over the 7-point rule
+// (and the RAW flux terms), accumulated in the order of k_rhs_elem.
+__device__ inline void fluid_load(const DevMesh& m, int64_t e, const LoadDev& L, const ElemGeom& g, double tau,
+                                  double pl[3]) {
+  const int edof = m.edof, order = m.order, nloc = order == 2 ? 6 : 3, nu = 2 * nloc;
+  const int32_t* ec = m.el_code + e * edof;
+  const bool raw = L.kind == FETI_LOAD_RAW;
+  double rz[3] = {0.0, 0.0, 0.0};
+  if (raw && L.z)
+    for (int k = 0; k < 3; ++k) rz[k] = L.z[ec[nu + 3 + k] >> 3];
+  double acc[MAX_EDOF_DEV];
+  for (int r = 0; r < MAX_EDOF_DEV; ++r) acc[r] = 0.0;
+  for (int q = 0; q < 7; ++q) {
+    double l0, l1, l2, w;
+    radon_point(q, l0, l1, l2, w);
+    const double x = l0 * g.x[0] + l1 * g.x[1] + l2 * g.x[2];
+    const double y = l0 * g.y[0] + l1 * g.y[1] + l2 * g.y[2];
+    const double wa = w * g.area;
+    const double lam[3] = {l0, l1, l2};
+    const double z = raw ? rz[0] * l0 + rz[1] * l1 + rz[2] * l2 : source(L, x, y);
+    for (int k = 0; k < 3; ++k) acc[nu + 6 + k] -= tau * wa * z * lam[k];
+  }
+  if (raw) raw_boundary_terms(L, true, ec, order, m.ncell, nloc, nu, tau, acc);
+  for (int k = 0; k < 3; ++k) pl[k] = acc[nu + 6 + k];
+}
+
+// One thread per element (elastic elements return): ce[e][k] = tau Z_k - tau (A_f p)_k,
+// and with me: me[e][k] = sum_b R_e[k][b].
+__global__ void __launch_bounds__(128) k_dec_fluid(DevMesh m, MatParams mpP, LoadDev L,
+                                                   const double* __restrict__ p_lat, double* __restrict__ ce,
+                                                   double* __restrict__ me) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nelem) return;
+  if (!m.sub_poro[m.el_sub[e]]) return;
+  const int edof = m.edof, nloc = m.order == 2 ? 6 : 3, nu = 2 * nloc;
+  ElemGeom g;
+  elem_geom(m.el_cell[e], m.el_type[e], m.ncell, g);
+  double pl[3];
+  fluid_load(m, e, L, g, mpP.tau, pl);
+  const int32_t* ec = m.el_code + e * edof;
+  double pv[3];
+  for (int b = 0; b < 3; ++b) pv[b] = p_lat[ec[nu + b] >> 3];  // vertex nodes from the xi codes
+  const double* Ke = m.emat + e * edof * edof;                  // entry (r, c) at c * edof + r
+  for (int k = 0; k < 3; ++k) {
+    double v = -pl[k];
+    for (int b = 0; b < 3; ++b) v += Ke[(nu + 6 + b) * edof + nu + 6 + k] * pv[b];
+    ce[e * 3 + k] = v;
+    if (me) {
+      double s = 0.0;
+      for (int b = 0; b < 3; ++b) s -= Ke[(nu + 3 + b) * edof + nu + 6 + k];
+      me[e * 3 + k] = s;
+    }
+  }
+}
+
+// one thread per fluid node: the lumped mass, summed over the node's element entries
+__global__ void k_dec_mass(DevMesh m, const double* __restrict__ me, double* __restrict__ mass) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m.n_dec) return;
+  double s = 0.0;
+  for (int q = m.dec_ptr[k]; q < m.dec_ptr[k + 1]; ++q) s += me[m.dec_ent[q]];
+  mass[k] = s;
+}
+
+// one thread per fluid node: eta^n (explicit Euler with the lumped mass; at a pressure
+// Dirichlet node from row 3 with the previous xi)
+__global__ void k_dec_update(DevMesh m, LoadDev L, double k1, double k2, const double* __restrict__ ce,
+                             const double* __restrict__ mass, double* __restrict__ eta_lat,
+                             const double* __restrict__ xi_lat) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m.n_dec) return;
+  const int node = m.dec_node[k];
+  if (m.dec_pdir[k]) {
+    const int umu = m.order * m.ncell + 1, n1 = m.ncell + 1;
+    const double pD = dirichlet_value(L, true, 8 * node + 4, umu, 1.0 / (m.order * m.ncell), n1, 1.0 / m.ncell);
+    eta_lat[node] = (pD - k1 * xi_lat[node]) / k2;
+    return;
+  }
+  double s = 0.0;
+  for (int q = m.dec_ptr[k]; q < m.dec_ptr[k + 1]; ++q) s += ce[m.dec_ent[q]];
+  eta_lat[node] += s / mass[k];
+}
+
+// one thread per fluid node: xi^n from its first torn copy, p^n = k1 xi^n + k2 eta^n
+// (p_D at pressure Dirichlet nodes)
+__global__ void k_dec_pressure(DevMesh m, LoadDev L, double k1, double k2, const double* __restrict__ u,
+                               double* __restrict__ xi_lat, double* __restrict__ p_lat,
+                               const double* __restrict__ eta_lat) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m.n_dec) return;
+  const int node = m.dec_node[k];
+  const double xi = u[m.dec_xi[k]];
+  xi_lat[node] = xi;
+  if (m.dec_pdir[k]) {
+    const int umu = m.order * m.ncell + 1, n1 = m.ncell + 1;
+    p_lat[node] = dirichlet_value(L, true, 8 * node + 4, umu, 1.0 / (m.order * m.ncell), n1, 1.0 / m.ncell);
+  } else {
+    p_lat[node] = k1 * xi + k2 * eta_lat[node];
+  }
+}
+
+// one thread per fluid node: eta^0 (R14), p^0 the interpolant of the initial pressure,
+// xi^0 = (p^0 - k2 eta^0) / k1
+__global__ void k_dec_init(DevMesh m, LoadDev L, double k1, double k2, double* __restrict__ eta_lat,
+                           double* __restrict__ p_lat, double* __restrict__ xi_lat) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m.n_dec) return;
+  const int node = m.dec_node[k];
+  const int n1 = m.ncell + 1;
+  const double h = 1.0 / m.ncell, x = (node % n1) * h, y = (node / n1) * h;
+  double eta, p;
+  if (L.kind == FETI_LOAD_RAW) {
+    eta = L.eta0 ? L.eta0[node] : 0.0;
+    p = 0.0;
+  } else {
+    eta = initial_eta(L, x, y);
+    p = exact_p(L, x, y);
+  }
+  eta_lat[node] = eta;
+  p_lat[node] = p;
+  xi_lat[node] = (p - k2 * eta) / k1;
+}
+
+// out[node] = src[node] at every fluid node
+__global__ void k_dec_field(DevMesh m, const double* __restrict__ src, double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m.n_dec) return;
+  out[m.dec_node[k]] = src[m.dec_node[k]];
+}
+
+void launch_dec_fluid(const DevMesh& m, const MatParams& mpP, const LoadDev& L, const double* p_lat, double* ce,
+                      double* me, hipStream_t st) {
+  hipLaunchKernelGGL(k_dec_fluid, dim3((m.nelem + 127) / 128), dim3(128), 0, st, m, mpP, L, p_lat, ce, me);
+}
+void launch_dec_mass(const DevMesh& m, const double* me, double* mass, hipStream_t st) {
+  if (m.n_dec == 0) return;
+  hipLaunchKernelGGL(k_dec_mass, dim3((m.n_dec + 255) / 256), dim3(256), 0, st, m, me, mass);
+}
+void launch_dec_update(const DevMesh& m, const LoadDev& L, double k1, double k2, const double* ce,
+                       const double* mass, double* eta_lat, const double* xi_lat, hipStream_t st) {
+  if (m.n_dec == 0) return;
+  hipLaunchKernelGGL(k_dec_update, dim3((m.n_dec + 255) / 256), dim3(256), 0, st, m, L, k1, k2, ce, mass, eta_lat,
+                     xi_lat);
+}
+void launch_dec_pressure(const DevMesh& m, const LoadDev& L, double k1, double k2, const double* u, double* xi_lat,
+                         double* p_lat, const double* eta_lat, hipStream_t st) {
+  if (m.n_dec == 0) return;
+  hipLaunchKernelGGL(k_dec_pressure, dim3((m.n_dec + 255) / 256), dim3(256), 0, st, m, L, k1, k2, u, xi_lat, p_lat,
+                     eta_lat);
+}
+void launch_dec_init(const DevMesh& m, const LoadDev& L, double k1, double k2, double* eta_lat, double* p_lat,
+                     double* xi_lat, hipStream_t st) {
+  if (m.n_dec == 0) return;
+  hipLaunchKernelGGL(k_dec_init, dim3((m.n_dec + 255) / 256), dim3(256), 0, st, m, L, k1, k2, eta_lat, p_lat,
+                     xi_lat);
+}
+void launch_dec_field(const DevMesh& m, const double* src_lat, double* out, hipStream_t st) {
+  if (m.n_dec == 0) return;
+  hipLaunchKernelGGL(k_dec_field, dim3((m.n_dec + 255) / 256), dim3(256), 0, st, m, src_lat, out);
 }
 
 // ---- batched launches (problem = blockIdx.y) ----------------------------------

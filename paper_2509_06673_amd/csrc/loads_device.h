@@ -31,6 +31,9 @@ struct LoadDev {
   // u / p Dirichlet data (traction / flux sides)
   const double *f_p, *f_e, *z, *t_side, *zw_side, *g_u, *g_p, *eta0;
   uint32_t dir_u, dir_p;
+  // decoupled scheme: the fluid content eta^n of the step on the P1 lattice (the
+  // prescribed eta columns of the momentum rows read it); null otherwise
+  const double* eta_dec;
 };
 
 // 7-point degree-5 rule of Radon on a triangle (barycentric points, weights summing to 1):

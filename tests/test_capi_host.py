@@ -76,6 +76,42 @@ def test_indexing_bit_exact_against_oracle(w):
     _compare(w)
 
 
+@pytest.mark.parametrize("w", [
+    W.nearly_incompressible_scaled(16, 4).replace(scheme="decoupled"),
+    W.pulsed_core(ncell=16, nsub=4, nsteps=1).replace(scheme="decoupled"),
+    W.patch_case(order_u=1, ncell=8, nsub_x=4, nsub_y=3).replace(scheme="decoupled"),
+], ids=lambda w: w.name + "_decoupled")
+def test_decoupled_indexing_bit_exact_against_oracle(w):
+    """The decoupled scheme leaves eta and p out of the subdomain unknowns: the numbering
+    (and with it every jump row) against the oracle's statement of the same rule."""
+    _compare(w)
+
+
+def test_decoupled_subdomains_balance():
+    """With eta and p out, a poroelastic subdomain carries (u, xi_P) like an elastic one
+    (u, xi_E): the same size for the same cells (the point of the decoupling)."""
+    w = W.nearly_incompressible_scaled(32, 4).replace(scheme="decoupled")
+    f = B.Feti()
+    f.setup_mesh(**mesh_args(w))
+    ix_ = f.export_indexing()
+    ns = np.diff(ix_["sub_offset"])
+    spec = ix.build(w)
+    poro = np.array([s.poro for s in spec.subs])
+    # mirror pairs across x = 1/2 (columns a and 3 - a of a 4 x 4 grid) have the same size
+    for b in range(4):
+        for a in range(2):
+            assert ns[b * 4 + a] == ns[b * 4 + 3 - a] and poro[b * 4 + a] and not poro[b * 4 + 3 - a]
+    f.close()
+
+
+def test_unknown_scheme_is_rejected():
+    f = B.Feti()
+    with pytest.raises(B.FetiError) as e:
+        f.setup_mesh(ncell=8, order_u=2, layout=0, nsub_x=2, nsub_y=1, scheme=7)
+    assert e.value.code == B.EINVAL
+    f.close()
+
+
 def test_uneven_cuts_bit_exact():
     # ncell not divisible by the grid: cuts at floor(a n / nsub)
     w = W.nearly_incompressible_scaled(20, 4).replace(nsub_y=3, ncell=20)

@@ -90,6 +90,9 @@ class Workload:
     # cuts floor(a ncell / nsub)
     cut_x: Optional[Tuple[int, ...]] = None
     cut_y: Optional[Tuple[int, ...]] = None
+    # time discretisation: "coupled" (eq. (linalg-system) at once) or "decoupled" (explicit
+    # fluid step, then the momentum balance alone)
+    scheme: str = "coupled"
 
     def cuts(self) -> Tuple[List[int], List[int]]:
         cx = list(self.cut_x) if self.cut_x is not None else [(a * self.ncell) // self.nsub_x
