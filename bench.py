@@ -458,7 +458,11 @@ def run_variant(args, w, variant):
     meta0 = f.get_state(state0)
     mk = opts_mixed if mixed else opts
     start = B.START_EXTRAPOLATE if variant == "fp64x" else B.START_PREVIOUS
-    o = mk(tol=w.tol, max_it=2000, start=start, check_every=args.check_every)
+    # the decoupled step's first solve meets tol at its start (the right-hand side moves only
+    # through eta), so its correction carries the step: a looser correction tolerance
+    # (1e-2 instead of 1e-3) takes ~74 instead of ~92 iterations at an unchanged torn residual
+    extra = dict(tol_corr=1e-2) if variant == "decoupled" else {}
+    o = mk(tol=w.tol, max_it=2000, start=start, check_every=args.check_every, **extra)
     n = 0
     warm_iters = []
     for _ in range(args.warmup):

@@ -32,6 +32,11 @@ local       the torn per-subdomain matrices and right-hand sides, and the
             plain-definition references the unit tests compare with: the
             interface Schur complement of eq. (reduced-system) and the
             generalised inverse of a floating subdomain.
+dual_primal the dual-primal gluing (primal xi / p and corner DOFs, multipliers on the
+            other u / eta DOFs): partially assembled matrix, interface operator and
+            right-hand side, solution and primal coarse matrix, by sparse direct solves.
+decoupled   the explicit fluid step of the decoupled mass balance (Remark after eq.
+            (linalg-system)) and the momentum balance alone.
 mlp         FP64 forward/backward of the warm-start MLP (BF16 weights, the
             specification's reference) and Adam, for the gradient checks.
 """

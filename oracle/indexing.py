@@ -31,8 +31,14 @@ Numbering
   elimination.
 * Local order: sort by (category, field order, node, component) with field
   order u 0, eta 1, xi 2, p 3 and component 0/1 for ux/uy.
-* Multiplier rows: for each shared code, with S the sorted subdomains having
-  it, one row per consecutive pair (S[k], S[k+1]) with sign +1 on S[k] and -1
+* Dual-primal gluing (Workload.coupling == "primal"): a shared code is primal when
+  its kind is xi_P, p or xi_E, or when its node sits at a corner of the subdomain
+  grid (on a vertical and a horizontal cut line, the outer sides counted); the
+  other shared codes (u and eta on the cut edges) are dual.  Categories then read
+  2 dual interface DOF, 3 primal interface DOF, and no subdomain floats: the
+  primal corners hold every subdomain that has no Dirichlet node.
+* Multiplier rows: for each shared code (each dual code under dual-primal
+  gluing), with S the sorted subdomains having it, one row per consecutive pair (S[k], S[k+1]) with sign +1 on S[k] and -1
   on S[k+1], except that a poroelastic/elastic pair puts +1 on the poroelastic
   side (the sign of H_P in eq. (linalg-system)).  Rows are sorted by
   (kind, node, k).
@@ -92,6 +98,7 @@ class IndexSpec:
     rows: np.ndarray        # (N_lambda, 2, 3): (sub, local index, sign) for the two entries
     row_code: np.ndarray    # (N_lambda,) code of the glued DOF
     mult: np.ndarray        # (N_lambda,) number of subdomains sharing the DOF
+    primal: np.ndarray = None  # dual-primal gluing: the primal codes, in their global order
 
     @property
     def n_lambda(self):
@@ -144,8 +151,25 @@ def build(w: Workload) -> IndexSpec:
             for c in codes:
                 owners.setdefault(c, []).append(sid)
             local_sets.append((sid, poro, i0, i1, j0, j1, codes, not has_dir))
+    dp = w.coupling == "primal"
+    if w.coupling not in ("dual", "primal"):
+        raise ValueError(w.coupling)
+    cxs, cys = set(cx), set(cy)
+
+    def is_primal(c):
+        node, kind = c // 8, c % 8
+        if kind not in U_KINDS:
+            return True
+        if kind == 2:      # eta: P1 lattice
+            i, j = node % (n + 1), node // (n + 1)
+            return i in cxs and j in cys
+        I, J = node % mu, node // mu
+        return I % ratio == 0 and J % ratio == 0 and I // ratio in cxs and J // ratio in cys
+
     for sid, poro, i0, i1, j0, j1, codes, floating in local_sets:
         fixed = set()
+        if dp:
+            floating = False
         if floating:
             A = (ratio * j0) * mu + ratio * i0
             C = (ratio * j1) * mu + ratio * i1
@@ -156,6 +180,8 @@ def build(w: Workload) -> IndexSpec:
             shared = len(owners[c]) > 1
             if c in fixed:
                 cat = 4
+            elif dp:
+                cat = (3 if is_primal(c) else 2) if shared else (0 if kind in U_KINDS else 1)
             elif kind in U_KINDS:
                 cat = 2 if shared else 0
             else:
@@ -169,7 +195,7 @@ def build(w: Workload) -> IndexSpec:
     rows = []
     for c in sorted(owners, key=lambda c: (c % 8, c // 8)):
         S = sorted(owners[c])
-        if len(S) < 2:
+        if len(S) < 2 or (dp and is_primal(c)):
             continue
         for kk in range(len(S) - 1):
             s1, s2 = S[kk], S[kk + 1]
@@ -180,8 +206,14 @@ def build(w: Workload) -> IndexSpec:
                          ((s1, pos[s1][c], sg1), (s2, pos[s2][c], sg2))))
     rows.sort(key=lambda r: r[0])
     R = np.array([r[3] for r in rows], dtype=np.int64).reshape(-1, 2, 3)
+    primal = None
+    if dp:
+        # global primal order: (field order, node, kind), so the U-type corners (u, eta)
+        # come before the P-type fields (xi, p)
+        pc = [c for c in owners if len(owners[c]) > 1 and is_primal(c)]
+        primal = np.array(sorted(pc, key=lambda c: (KIND_FIELD_ORDER[c % 8], c // 8, c % 8)), dtype=np.int64)
     return IndexSpec(subs, R, np.array([r[1] for r in rows], dtype=np.int64),
-                     np.array([r[2] for r in rows], dtype=np.int64))
+                     np.array([r[2] for r in rows], dtype=np.int64), primal)
 
 
 def closed_form_n_lambda(w: Workload) -> int:
@@ -203,6 +235,8 @@ def closed_form_n_lambda(w: Workload) -> int:
         b = max(q for q in range(w.nsub_y) if cy[q] <= j)
         return b * w.nsub_x + a
 
+    dp = w.coupling == "primal"
+    allx, ally = set(cx), set(cy)
     total = 0
     for J in range(r * n + 1):
         for I in range(r * n + 1):
@@ -210,6 +244,8 @@ def closed_form_n_lambda(w: Workload) -> int:
             on_y = (J % r == 0) and (J // r) in cuty
             if not (on_x or on_y):
                 continue
+            if dp and I % r == 0 and J % r == 0 and I // r in allx and J // r in ally:
+                continue           # a grid corner: primal, no multiplier
             # cells whose closure holds lattice node (I, J)
             ilo = (I - 1) // r if I > 0 else 0
             ihi = min(I // r, n - 1)
@@ -223,6 +259,12 @@ def closed_form_n_lambda(w: Workload) -> int:
                 continue
             if not _sides(I, J, r * n, w.dirichlet_u):
                 total += 2 * (len(subs) - 1)
+            if dp:
+                # on a cut edge: eta is dual, xi and p primal
+                if I % r == 0 and J % r == 0:
+                    psubs = {sub_of_cell(ci, cj) for ci, cj in cells if reg_of_cell(ci, cj)}
+                    total += max(len(psubs) - 1, 0)
+                continue
             if I % r == 0 and J % r == 0:
                 i, j = I // r, J // r
                 psubs = {sub_of_cell(ci, cj) for ci, cj in cells if reg_of_cell(ci, cj)}

@@ -35,12 +35,13 @@ def _rel_on(got, ref):
     return np.abs(got[sel] - ref[sel]).max() / (s if s > 0 else 1.0)
 
 
-@pytest.mark.parametrize("w", [
-    W.nearly_incompressible_scaled(32, 4, nsteps=4).replace(scheme="decoupled"),
-    W.nearly_incompressible_scaled(24, 4, nsteps=3).replace(scheme="decoupled", layout=W.YSPLIT,
-                                                             name="ysplit_p2_h24_4x4"),
-], ids=lambda w: w.name + "_decoupled")
-def test_decoupled_steps_match_the_oracle(w):
+@pytest.mark.parametrize("w,tol_corr", [
+    (W.nearly_incompressible_scaled(32, 4, nsteps=4).replace(scheme="decoupled"), 1e-3),
+    (W.nearly_incompressible_scaled(32, 4, nsteps=4).replace(scheme="decoupled"), 1e-2),
+    (W.nearly_incompressible_scaled(24, 4, nsteps=3).replace(scheme="decoupled", layout=W.YSPLIT,
+                                                              name="ysplit_p2_h24_4x4"), 1e-3),
+], ids=["xsplit_corr1e-3", "xsplit_corr1e-2", "ysplit_corr1e-3"])
+def test_decoupled_steps_match_the_oracle(w, tol_corr):
     import torch
     require_gpu()
     nsteps = w.nsteps
@@ -51,7 +52,7 @@ def test_decoupled_steps_match_the_oracle(w):
     codes = idx["code"].astype(np.int64)
     assert not np.isin(codes % 8, (2, 4)).any()  # no eta / p unknowns in the subdomains
     n1 = f.get_sizes()["n_p1"]
-    o = opts(tol=1e-10, max_it=3000)
+    o = opts(tol=1e-10, max_it=3000, tol_corr=tol_corr)
     for n in range(1, nsteps + 1):
         st = f.step(load(w, n * w.tau), o)
         u = torch.empty(len(codes), dtype=torch.float64, device="cuda")

@@ -93,6 +93,10 @@ class Workload:
     # time discretisation: "coupled" (eq. (linalg-system) at once) or "decoupled" (explicit
     # fluid step, then the momentum balance alone)
     scheme: str = "coupled"
+    # gluing of the shared DOFs: "dual" (every shared DOF torn and glued by multipliers) or
+    # "primal" (the shared xi / p DOFs and the shared DOFs at subdomain corners are global
+    # primal unknowns; multipliers glue only the remaining u and eta DOFs)
+    coupling: str = "dual"
 
     def cuts(self) -> Tuple[List[int], List[int]]:
         cx = list(self.cut_x) if self.cut_x is not None else [(a * self.ncell) // self.nsub_x
