@@ -94,7 +94,24 @@ typedef struct {
     int32_t scheme;       /* FETI_SCHEME_COUPLED (eq. (linalg-system) at once) or
                              FETI_SCHEME_DECOUPLED (the explicit fluid step of the Remark
                              after eq. (linalg-system); see feti_step) */
+    int32_t coupling;     /* FETI_COUPLING_DUAL or FETI_COUPLING_PRIMAL (below) */
 } feti_mesh_desc;
+
+/* Gluing of the shared DOFs.  DUAL: every shared DOF is torn and glued by multipliers
+ * (Section 3.1); the interface operator F is symmetric but indefinite, with one negative
+ * eigenvalue per multiplier of xi_P, p or xi_E.  PRIMAL (dual-primal, the FETI-DP
+ * structure that the Introduction cites for three-field Biot): the shared xi_P, p and xi_E
+ * DOFs and every shared DOF at a corner of the subdomain grid (on a vertical and a
+ * horizontal cut line, outer sides included) are global primal unknowns, and multipliers
+ * glue only the other shared DOFs (u and eta on the cut edges).  With K~ the partially
+ * assembled matrix (primal DOFs summed over their owners), F = B K~^{-1} B^T is
+ * symmetric positive definite, no subdomain floats (n_c = 0), and every application of F
+ * solves the primal coarse problem S_PiPi = K~_PiPi - K~_Pir K~_rr^{-1} K~_rPi (dense,
+ * inverted once by feti_factor_subdomains).  The solution is the same (Theorem 3.1's
+ * equivalence).  PRIMAL takes FETI_FP64 factors, the coupled scheme and single contexts
+ * (no batches); FETI_EINVAL from feti_setup_mesh if a subdomain without Dirichlet data has
+ * fewer than two primal displacement nodes. */
+enum { FETI_COUPLING_DUAL = 0, FETI_COUPLING_PRIMAL = 1 };
 
 /* Time discretisation of a step.  DECOUPLED: the fluid content and the pressure leave the
  * subdomain unknowns, so a poroelastic subdomain carries (u_P, xi_P) like an elastic one
@@ -211,7 +228,7 @@ int feti_setup_mesh(feti_ctx ctx, const feti_mesh_desc* mesh);
 
 /* sizes: [0] n_sub, [1] sum n_s, [2] N_lambda, [3] n_c (coarse size),
  * [4] max n_s, [5] max n_b, [6] sum n_b, [7] P1 lattice size, [8] u lattice size,
- * [9] n_floating */
+ * [9] n_floating, [10] number of primal unknowns (dual-primal coupling, else 0) */
 int feti_get_sizes(feti_ctx ctx, int64_t* sizes_host);
 
 /* Bit-exact export of the numbering (host buffers):
@@ -222,6 +239,12 @@ int feti_get_sizes(feti_ctx ctx, int64_t* sizes_host);
 int feti_export_indexing(feti_ctx ctx, int32_t* local_code_host, int32_t* sub_offset_host,
                          int32_t* sub_nb_host, int32_t* brow_sub_host,
                          int32_t* brow_local_host, int8_t* brow_sign_host);
+
+/* Dual-primal coupling (FETI_COUPLING_PRIMAL; host buffers): primal_code[n_primal] the
+ * code of every primal unknown in global order (field order u, eta, xi, p, then node,
+ * then kind: the U-type corners first), sub_npi[n_sub] the number of primal DOFs of each
+ * subdomain, which are the trailing ones of its interface block.  Either may be NULL. */
+int feti_export_primal(feti_ctx ctx, int32_t* primal_code_host, int32_t* sub_npi_host);
 
 /* Element-parallel assembly of every dense local matrix K_s (rows 1-4 or 5-6
  * of eq. (linalg-system) restricted to the subdomain's elements, Dirichlet

@@ -36,13 +36,14 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM", 
 
 
 SCHEME_COUPLED, SCHEME_DECOUPLED = 0, 1
+COUPLING_DUAL, COUPLING_PRIMAL = 0, 1
 
 
 class MeshDesc(C.Structure):
     _fields_ = [("ncell", C.c_int32), ("order_u", C.c_int32), ("layout", C.c_int32),
                 ("nsub_x", C.c_int32), ("nsub_y", C.c_int32), ("dirichlet_u", C.c_uint32),
                 ("dirichlet_p", C.c_uint32), ("cut_x", C.POINTER(C.c_int32)), ("cut_y", C.POINTER(C.c_int32)),
-                ("scheme", C.c_int32)]
+                ("scheme", C.c_int32), ("coupling", C.c_int32)]
 
 
 class Material(C.Structure):
@@ -121,6 +122,7 @@ _SIGS = {
     "feti_export_indexing": [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                              C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                              C.POINTER(C.c_int8)],
+    "feti_export_primal": [C.c_void_p, C.c_void_p, C.c_void_p],
     "feti_assemble": [C.c_void_p, C.POINTER(Material), C.POINTER(Material), C.c_double],
     "feti_factor_subdomains": [C.c_void_p, C.c_int32, C.c_int32],
     "feti_init_state": [C.c_void_p, C.POINTER(Load)],
@@ -242,19 +244,19 @@ class Feti:
 
     # -- setup ----------------------------------------------------------------
     def setup_mesh(self, ncell, order_u, layout, nsub_x, nsub_y, dirichlet_u=0xF, dirichlet_p=0xF,
-                   cut_x=None, cut_y=None, scheme=0):
+                   cut_x=None, cut_y=None, scheme=0, coupling=0):
         cx = (C.c_int32 * len(cut_x))(*cut_x) if cut_x is not None else None
         cy = (C.c_int32 * len(cut_y))(*cut_y) if cut_y is not None else None
         d = MeshDesc(ncell, order_u, layout, nsub_x, nsub_y, dirichlet_u, dirichlet_p,
                      C.cast(cx, C.POINTER(C.c_int32)) if cx is not None else None,
-                     C.cast(cy, C.POINTER(C.c_int32)) if cy is not None else None, scheme)
+                     C.cast(cy, C.POINTER(C.c_int32)) if cy is not None else None, scheme, coupling)
         return self._check(self.lib.feti_setup_mesh(self.ctx, C.byref(d)), "feti_setup_mesh")
 
     def get_sizes(self) -> Dict[str, int]:
-        a = (C.c_int64 * 10)()
+        a = (C.c_int64 * 11)()
         self._check(self.lib.feti_get_sizes(self.ctx, a), "feti_get_sizes")
         keys = ["n_sub", "sum_ns", "n_lambda", "n_c", "max_ns", "max_nb", "sum_nb", "n_p1",
-                "n_u", "n_float"]
+                "n_u", "n_float", "n_primal"]
         return dict(zip(keys, list(a)))
 
     def export_indexing(self):
@@ -273,6 +275,17 @@ class Feti:
                     "feti_export_indexing")
         return dict(code=code, sub_offset=off, sub_nb=nb, brow_sub=bs, brow_local=bl, brow_sign=sg)
 
+
+    def export_primal(self):
+        """Dual-primal coupling: the primal codes in global order and the number of primal
+        (trailing interface) DOFs of every subdomain."""
+        import numpy as np
+        sz = self.get_sizes()
+        code = np.zeros(max(sz["n_primal"], 1), np.int32)
+        npi = np.zeros(sz["n_sub"], np.int32)
+        self._check(self.lib.feti_export_primal(self.ctx, code.ctypes.data_as(C.c_void_p),
+                                                npi.ctypes.data_as(C.c_void_p)), "feti_export_primal")
+        return {"code": code[:sz["n_primal"]], "sub_npi": npi}
     def assemble(self, mat_p: Material, mat_e: Material, tau: float):
         return self._check(self.lib.feti_assemble(self.ctx, C.byref(mat_p), C.byref(mat_e), tau),
                            "feti_assemble")

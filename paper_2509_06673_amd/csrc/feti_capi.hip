@@ -1115,6 +1115,7 @@ int feti_get_sizes(feti_ctx ctx, int64_t* s) {
   s[7] = (int64_t)h.n1 * h.n1;
   s[8] = (int64_t)h.mu * h.mu;
   s[9] = h.n_float;
+  s[10] = h.n_pi;
   return FETI_OK;
 }
 
@@ -1135,6 +1136,20 @@ int feti_export_indexing(feti_ctx ctx, int32_t* code, int32_t* sub_off, int32_t*
       if (brow_sub) brow_sub[2 * j + e] = h.rows[j].sub[e];
       if (brow_local) brow_local[2 * j + e] = h.rows[j].loc[e];
       if (brow_sign) brow_sign[2 * j + e] = h.rows[j].sign[e];
+    }
+  return FETI_OK;
+}
+
+int feti_export_primal(feti_ctx ctx, int32_t* pi_code, int32_t* sub_npi) {
+  if (!ctx) return FETI_EINVAL;
+  if (ctx->state < 1) return fail(ctx, FETI_ESTATE, "no mesh");
+  const MeshHost& h = ctx->mh;
+  if (pi_code && h.n_pi > 0) std::memcpy(pi_code, h.pi_code.data(), h.n_pi * sizeof(int32_t));
+  if (sub_npi)
+    for (size_t s = 0; s < h.subs.size(); ++s) {
+      int c = 0;
+      for (int8_t cat : h.subs[s].cats) c += (h.n_pi > 0 && cat == C_BP) ? 1 : 0;
+      sub_npi[s] = c;
     }
   return FETI_OK;
 }

@@ -82,6 +82,11 @@ struct MeshHost {
   // xi_P copy (lowest subdomain)
   std::vector<int32_t> dec_node, dec_ptr, dec_ent, dec_xi;
   std::vector<uint8_t> dec_pdir;
+  // dual-primal coupling: the primal codes in global order (the first n_pi_u of U type),
+  // per interface DOF its primal index (-1: dual or no coupling), per primal DOF the
+  // interface indices of its owners (4 slots, -1 = none)
+  int n_pi = 0, n_pi_u = 0;
+  std::vector<int32_t> pi_code, bpi, pi_own;
 };
 
 // Builds every host-side table from the mesh description (the numbering that

@@ -68,7 +68,10 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
       d.nsub_x > n || d.nsub_y > n || d.layout < 0 || d.layout > 2)
     return "invalid mesh description";
   if (d.scheme != FETI_SCHEME_COUPLED && d.scheme != FETI_SCHEME_DECOUPLED) return "unknown time scheme";
+  if (d.coupling != FETI_COUPLING_DUAL && d.coupling != FETI_COUPLING_PRIMAL) return "unknown coupling";
   const bool decoupled = d.scheme == FETI_SCHEME_DECOUPLED;
+  const bool dp = d.coupling == FETI_COUPLING_PRIMAL;
+  if (dp && decoupled) return "the decoupled scheme takes the dual coupling only";
   m = MeshHost();
   m.desc = d;
   m.ratio = d.order_u == 2 ? 2 : 1;
@@ -127,9 +130,22 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
       for (int32_t c : s.codes) owners[c].push_back(sid);
     }
   }
+  // dual-primal coupling: a shared code is primal when its kind is xi_P, p or xi_E, or when
+  // its node lies on a vertical and a horizontal cut line (outer sides included)
+  std::vector<uint8_t> xcut(n + 1, 0), ycut(n + 1, 0);
+  for (int a = 0; a <= d.nsub_x; ++a) xcut[cx[a]] = 1;
+  for (int b = 0; b <= d.nsub_y; ++b) ycut[cy[b]] = 1;
+  auto is_primal = [&](int32_t c) -> bool {
+    const int node = c / 8, kind = c % 8;
+    if (kind == K_XIP || kind == K_P || kind == K_XIE) return true;
+    if (kind == K_ETA) return xcut[node % m.n1] && ycut[node / m.n1];
+    const int I = node % m.mu, J = node / m.mu;
+    return I % r == 0 && J % r == 0 && xcut[I / r] && ycut[J / r];
+  };
   // categories and local order
   for (SubHost& s : m.subs) {
-    s.floating = !has_dir[s.sid];
+    // under the dual-primal coupling the primal corners hold every subdomain
+    s.floating = !dp && !has_dir[s.sid];
     int32_t fixA = -1, fixB = -1, fixC = -1;
     if (s.floating) {
       const int32_t A = (r * s.j0) * m.mu + r * s.i0;
@@ -144,6 +160,7 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
       const bool shared = owners[c].size() > 1;
       int cat;
       if (c == fixA || c == fixB || c == fixC) cat = C_FIX;
+      else if (dp) cat = shared ? (is_primal(c) ? C_BP : C_BU) : (kind <= K_ETA ? C_IU : C_IP);
       else if (kind <= K_ETA) cat = shared ? C_BU : C_IU;
       else cat = shared ? C_BP : C_IP;
       keys.push_back({cat, field_order(kind), node, kind == K_UY ? 1 : 0, c});
@@ -161,6 +178,15 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
       if (c == C_FIX) ++s.nfix;
     }
     if (s.floating && s.nfix != 3) return "floating subdomain without its three fixed DOFs";
+    if (dp && !has_dir[s.sid]) {
+      // two distinct primal displacement nodes remove the rigid-body modes
+      std::vector<int32_t> un;
+      for (size_t i = 0; i < s.codes.size(); ++i)
+        if (s.cats[i] == C_BP && s.codes[i] % 8 <= K_UY) un.push_back(s.codes[i] / 8);
+      std::sort(un.begin(), un.end());
+      if (std::unique(un.begin(), un.end()) - un.begin() < 2)
+        return "a subdomain without Dirichlet data has fewer than two primal corners";
+    }
   }
   // offsets
   int64_t off = 0, boff = 0;
@@ -181,7 +207,7 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
   // jump rows sorted by (kind, node, pair index)
   std::vector<int32_t> shared_codes;
   for (auto& kv : owners)
-    if (kv.second.size() > 1) shared_codes.push_back(kv.first);
+    if (kv.second.size() > 1 && !(dp && is_primal(kv.first))) shared_codes.push_back(kv.first);
   std::sort(shared_codes.begin(), shared_codes.end(), [](int32_t x, int32_t y) {
     return std::make_pair(x % 8, x / 8) < std::make_pair(y % 8, y / 8);
   });
@@ -259,6 +285,35 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
       }
       m.bd_row[3 * gb + k] = gs + k;
       m.bd_wt[3 * gb + k] = v;
+    }
+  }
+  // dual-primal coupling: the global primal order (field order, node, kind), so that the
+  // U-type corners (u, eta) precede xi and p; per interface DOF its primal index, per
+  // primal DOF its owners' interface indices (increasing subdomain)
+  m.bpi.assign(m.sum_nb, -1);
+  if (dp) {
+    for (auto& kv : owners)
+      if (kv.second.size() > 1 && is_primal(kv.first)) m.pi_code.push_back(kv.first);
+    std::sort(m.pi_code.begin(), m.pi_code.end(), [](int32_t x, int32_t y) {
+      return std::make_tuple(field_order(x % 8), x / 8, x % 8) < std::make_tuple(field_order(y % 8), y / 8, y % 8);
+    });
+    m.n_pi = (int)m.pi_code.size();
+    m.n_pi_u = 0;
+    for (int32_t c : m.pi_code)
+      if (c % 8 <= K_ETA) ++m.n_pi_u;
+    m.pi_own.assign(4 * (size_t)m.n_pi, -1);
+    for (int k = 0; k < m.n_pi; ++k) {
+      std::vector<int32_t> S = owners[m.pi_code[k]];
+      std::sort(S.begin(), S.end());
+      if (S.size() > 4) return "a node shared by more than four subdomains";
+      for (size_t e = 0; e < S.size(); ++e) {
+        const SubHost& sh = m.subs[S[e]];
+        const int bl = pos[S[e]][m.pi_code[k]] - sh.nI;
+        if (bl < 0) return "primal DOF in the interior";
+        const int64_t gb = sh.boff + bl;
+        m.pi_own[4 * (size_t)k + e] = (int32_t)gb;
+        m.bpi[gb] = k;
+      }
     }
   }
   // coarse space: rigid modes of floating subdomains

@@ -14,7 +14,8 @@ def mesh_args(w) -> Dict:
     return dict(ncell=w.ncell, order_u=w.order_u, layout=_LAYOUT[w.layout], nsub_x=w.nsub_x,
                 nsub_y=w.nsub_y, dirichlet_u=w.dirichlet_u, dirichlet_p=w.dirichlet_p,
                 cut_x=getattr(w, "cut_x", None), cut_y=getattr(w, "cut_y", None),
-                scheme=B.SCHEME_DECOUPLED if getattr(w, "scheme", "coupled") == "decoupled" else B.SCHEME_COUPLED)
+                scheme=B.SCHEME_DECOUPLED if getattr(w, "scheme", "coupled") == "decoupled" else B.SCHEME_COUPLED,
+                coupling=B.COUPLING_PRIMAL if getattr(w, "coupling", "dual") == "primal" else B.COUPLING_DUAL)
 
 
 def material(m) -> B.Material:

@@ -60,6 +60,13 @@ def _compare(w):
     sz = f.get_sizes()
     assert sz["n_lambda"] == spec.n_lambda
     assert sz["n_float"] == sum(s.floating for s in spec.subs)
+    if w.coupling == "primal":
+        pr = f.export_primal()
+        assert np.array_equal(pr["code"].astype(np.int64), spec.primal)
+        assert np.array_equal(pr["sub_npi"], [sum(1 for c in s.cats if c == 3) for s in spec.subs])
+        assert sz["n_primal"] == len(spec.primal)
+    else:
+        assert sz["n_primal"] == 0
     f.close()
 
 
@@ -85,6 +92,29 @@ def test_decoupled_indexing_bit_exact_against_oracle(w):
     """The decoupled scheme leaves eta and p out of the subdomain unknowns: the numbering
     (and with it every jump row) against the oracle's statement of the same rule."""
     _compare(w)
+
+
+@pytest.mark.parametrize("w", [
+    W.plain_fp64_small().replace(coupling="primal"),
+    W.nearly_incompressible_scaled(16, 4).replace(coupling="primal"),
+    W.nearly_incompressible_scaled(24, 4).replace(nsub_y=3, coupling="primal"),
+    W.patch_case(order_u=1, ncell=8, nsub_x=4, nsub_y=3).replace(coupling="primal"),
+    W.pulsed_core(ncell=16, nsub=4, nsteps=1).replace(coupling="primal"),
+    W.nearly_incompressible_scaled(24, 4).replace(coupling="primal", cut_x=(0, 5, 12, 20, 24), layout=W.XSPLIT),
+], ids=lambda w: w.name + "_primal")
+def test_dual_primal_indexing_bit_exact_against_oracle(w):
+    """Dual-primal coupling: local orders (primal DOFs trailing), the jump rows of the dual
+    DOFs and the global primal order against the oracle's statement of the same rule."""
+    _compare(w)
+
+
+def test_dual_primal_coupling_is_rejected_with_the_decoupled_scheme():
+    f = B.Feti()
+    with pytest.raises(B.FetiError) as e:
+        f.setup_mesh(**mesh_args(W.nearly_incompressible_scaled(16, 4).replace(scheme="decoupled",
+                                                                              coupling="primal")))
+    assert e.value.code == B.EINVAL
+    f.close()
 
 
 def test_decoupled_subdomains_balance():
