@@ -395,12 +395,15 @@ int feti_batch_set_capture(feti_batch b, int32_t on);
 /* ---- inspection (unit parity of each stage) ------------------------------- */
 
 /* Dense local matrix K_s, its S_bb snapshot and K_s^+ of subdomain sub, row
- * major into a device buffer of n_s*n_s (K, K^+) or n_b*n_b (S_bb) doubles. */
+ * major into a device buffer of n_s*n_s (K, K^+) or n_b*n_b (S_bb) doubles.  Under the
+ * dual-primal coupling KPLUS gives N_s = [[K_rr^{-1}, -K_rr^{-1} K_rPi], [-K_Pir K_rr^{-1},
+ * -S_s]] (r: every DOF but the primal ones, S_s = K_PiPi - K_Pir K_rr^{-1} K_rPi). */
 int feti_export_local(feti_ctx ctx, int32_t sub, int32_t which, double* out_dev);
 enum { FETI_EXPORT_K = 0, FETI_EXPORT_SBB = 1, FETI_EXPORT_KPLUS = 2 };
 
-/* y = F x (F = sum_s B_s K_s^+ B_s^T) and y = M^{-1} x (Dirichlet
- * preconditioner) on device vectors of N_lambda doubles. */
+/* y = F x (F = sum_s B_s K_s^+ B_s^T; dual-primal coupling: F = B K~^{-1} B^T with its
+ * primal coarse solve) and y = M^{-1} x (Dirichlet preconditioner; dual-primal: the
+ * Schur complements restricted to the dual DOFs) on device vectors of N_lambda doubles. */
 int feti_apply_F(feti_ctx ctx, const double* x_dev, double* y_dev);
 int feti_apply_precond(feti_ctx ctx, const double* x_dev, double* y_dev);
 
@@ -410,8 +413,10 @@ int feti_apply_precond(feti_ctx ctx, const double* x_dev, double* y_dev);
  * (8 MiB, held by every GPU that loads the library until the process ends) instead of
  * the context's buffers, and the call neither allocates nor frees anything.  It is
  * stream-ordered on the context stream and does not synchronise.  The context must be
- * factored and its device current.  FETI_EINVAL when the interface space (sum_s n_b,s)
- * exceeds 2^20 entries or another device is current.  Calls that overlap on one GPU
+ * factored and its device current.  FETI_EINVAL when the interface space (sum_s n_b,s),
+ * plus twice the primal count under the dual-primal coupling (its coarse step keeps the
+ * primal right-hand side and solution there too), exceeds 2^20 entries or another device
+ * is current.  Calls that overlap on one GPU
  * (several streams or host threads) share the array and race; the result is the same
  * as feti_apply_F's, bit for bit. */
 int feti_apply_F_noalloc(feti_ctx ctx, const double* x_dev, double* y_dev);

@@ -109,6 +109,10 @@ struct feti_ctx_s {
   // per fluid node, per-element fluid contributions, and the constants of row 3
   double *dec_eta = nullptr, *dec_p = nullptr, *dec_xi = nullptr, *dec_mass = nullptr, *dec_ce = nullptr;
   double dec_k1 = 0.0, dec_k2 = 0.0;
+  // dual-primal coupling: the inverse of the primal coarse matrix S_PiPi (n_pi x n_pi), the
+  // primal right-hand side and solution, and the local solution of the start
+  bool dp = false;
+  double *Spinv = nullptr, *cpi = nullptr, *upi = nullptr, *ydp = nullptr;
   // captured PCG iteration chunks, keyed by the multiplier buffer they update
   struct Graph {
     hipGraphExec_t exec = nullptr;
@@ -258,6 +262,22 @@ int upload_mesh(feti_ctx ctx) {
   RC(upload(ctx, &m.dwt, h.dwt));
   RC(upload(ctx, &m.row_kind, row_kind));
   RC(upload(ctx, &m.float_sub, h.float_sub));
+  ctx->dp = h.desc.coupling == FETI_COUPLING_PRIMAL;
+  m.nsub_x = h.desc.nsub_x;
+  m.n_pi = h.n_pi;
+  m.max_npi = 0;
+  if (ctx->dp) {
+    std::vector<int32_t> npi(nsub, 0);
+    for (int s = 0; s < nsub; ++s)
+      for (int8_t c : h.subs[s].cats) npi[s] += c == C_BP ? 1 : 0;
+    for (int v : npi) m.max_npi = std::max(m.max_npi, v);
+    RC(upload(ctx, &m.npi, npi));
+    RC(upload(ctx, &m.bpi, h.bpi));
+    RC(upload(ctx, &m.pi_own, h.pi_own));
+    RC(dalloc(ctx, &ctx->cpi, std::max(m.n_pi, 1), ctx->allocs));
+    RC(dalloc(ctx, &ctx->upi, std::max(m.n_pi, 1), ctx->allocs));
+    RC(dalloc(ctx, &ctx->ydp, h.sum_ns, ctx->allocs));
+  }
   m.decoupled = h.desc.scheme == FETI_SCHEME_DECOUPLED ? 1 : 0;
   m.n_dec = (int)h.dec_node.size();
   if (m.decoupled) {
@@ -417,7 +437,11 @@ void op_project(feti_ctx ctx, const double* in, double* out, const int32_t* skip
   launch_coarse_correct(m, ctx->ac, -1.0, in, out, skip, st);
 }
 
-// y_b = (K^+)_bb B^T x per subdomain; y = B y_b; with g: also g = G^T y (same pass)
+// y_b = (K^+)_bb B^T x per subdomain; y = B y_b; with g: also g = G^T y (same pass).
+// Dual-primal coupling (the interface blocks hold N_s = [[K_rr^{-1}, -K_rr^{-1} K_rPi],
+// [-K_Pir K_rr^{-1}, -S_s]] over [dual | primal]): the primal coarse solve of
+// K~ [u_r; u_Pi] = [B^T x; 0] first, u_Pi = S_PiPi^{-1} sum_s L_s^T (N_s [B_s^T x; 0])_Pi,
+// then y = sum_s B_s (N_s [B_s^T x; L_s u_Pi])_dual = B K~^{-1} B^T x.
 void op_F_raw(feti_ctx ctx, const double* x, double* y, double* g, const int32_t* skip) {
   DevMesh& m = ctx->dm;
   GemvArgs a;
@@ -425,6 +449,12 @@ void op_F_raw(feti_ctx ctx, const double* x, double* y, double* g, const int32_t
   a.A = fc.splus; a.a_f32 = fc.f32; a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
   a.v = x; a.gmode = G_SIGNED; a.gcoef = 1.0; a.y = ctx->yb; a.skip = skip;
   launch_sgemv(m, a, ctx->stream);
+  if (ctx->dp && m.n_pi > 0) {
+    launch_pi_gather(m, nullptr, nullptr, ctx->yb, 1.0, ctx->cpi, skip, ctx->stream);
+    launch_coarse_apply(m.n_pi, ctx->Spinv, ctx->cpi, ctx->upi, 1.0, skip, ctx->stream);
+    a.pi_mode = 1; a.pi_v = ctx->upi;
+    launch_sgemv(m, a, ctx->stream);
+  }
   launch_jump(m, ctx->yb, 0, y, 0, g, skip, ctx->stream);
 }
 
@@ -534,7 +564,20 @@ int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
   hipStream_t st = ctx->stream;
   const int64_t nl = m.n_lambda;
   // d = sum_s B_s K_s^+ f_s - c
-  {
+  if (ctx->dp) {
+    // dual-primal: ytmp = N_s [f_r; 0] (kept for the recovery), the primal solution of
+    // K~ u = f~ at lambda = 0, u_Pi = S_PiPi^{-1} sum_s L_s^T (f_Pi + ytmp_Pi), its local
+    // part ydp = N_s [f_r; L_s u_Pi] = ytmp + N_s [0; L_s u_Pi], and d = sum_s B_s ydp
+    SymArgs sa = ctx->sym;
+    sa.pi_mode = 1; sa.pi_v = nullptr;
+    launch_sym_gemv(m, sa, f, ctx->ytmp, st);
+    launch_pi_gather(m, f, ctx->ytmp, nullptr, 0.0, ctx->cpi, nullptr, st);
+    launch_coarse_apply(m.n_pi, ctx->Spinv, ctx->cpi, ctx->upi, 1.0, nullptr, st);
+    sa.pi_v = ctx->upi;
+    launch_sym_gemv_kb(m, sa, nullptr, 0.0, ctx->ytmp, nullptr, ctx->ydp, st);
+    launch_jump(m, ctx->ydp, 1, ctx->d, 0, nullptr, nullptr, st);
+    if (cj) launch_axpby(nl, 1.0, ctx->d, -1.0, cj, ctx->d, st);
+  } else {
     if (ctx->sym.P) {
       launch_sym_gemv(m, ctx->sym, f, ctx->ytmp, st);
     } else {
@@ -624,9 +667,26 @@ int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
 
 // Second half of a torn solve: alpha_c = -(G^T G)^{-1} G^T r and the recovery
 // u = K^+ (f - B^T lam) + R alpha_c, where K^+ f is still in ytmp from torn_begin.
-int torn_end(feti_ctx ctx, const double* lam, double* u) {
+// Dual-primal coupling: u = K~^{-1} (f~ - B^T lam), i.e. u_Pi = S_PiPi^{-1} sum_s L_s^T
+// (f_Pi + ytmp_Pi - (N_s [B_s^T lam; 0])_Pi) and u_s = ytmp + N_s [-B_s^T lam; L_s u_Pi]
+// with u_Pi copied to every owner of a primal DOF.
+int torn_end(feti_ctx ctx, const double* lam, double* u, const double* f) {
   DevMesh& m = ctx->dm;
   hipStream_t st = ctx->stream;
+  if (ctx->dp) {
+    GemvArgs a;
+    a.A = ctx->Splus; a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
+    a.v = lam; a.gmode = G_SIGNED; a.gcoef = 1.0; a.y = ctx->yb;
+    launch_sgemv(m, a, st);
+    launch_pi_gather(m, f, ctx->ytmp, ctx->yb, -1.0, ctx->cpi, nullptr, st);
+    launch_coarse_apply(m.n_pi, ctx->Spinv, ctx->cpi, ctx->upi, 1.0, nullptr, st);
+    SymArgs sa = ctx->sym;
+    sa.pi_mode = 1; sa.pi_v = ctx->upi;
+    launch_sym_gemv_kb(m, sa, lam, -1.0, ctx->ytmp, nullptr, u, st);
+    launch_pi_scatter(m, ctx->upi, u, st);
+    HIPCHK(hipGetLastError());
+    return FETI_OK;
+  }
   if (ctx->nc > 0) {
     launch_coarse_g(m, ctx->r, nullptr, 1.0, ctx->g, nullptr, st);
     launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, -1.0, nullptr, st);
@@ -665,7 +725,7 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
   static const bool use_graph = std::getenv("FETI_NO_GRAPH") == nullptr;
   static const bool use_persist = std::getenv("FETI_NO_PERSIST") == nullptr;
   // (the persistent kernel projects with H = G (G^T G)^{-1}, built when n_c <= PCG_NC_LOCAL)
-  const bool persist = use_persist && !trace && ctx->pcg_mode == FETI_PCG_AUTO && ctx->pgrid > 0 &&
+  const bool persist = use_persist && !trace && !ctx->dp && ctx->pcg_mode == FETI_PCG_AUTO && ctx->pgrid > 0 &&
                        ctx->nc <= PCG_NC_LOCAL && (ctx->nc == 0 || ctx->H != nullptr) &&
                        ctx->precond != FETI_PRECOND_NONE;
   if (persist) {
@@ -772,7 +832,7 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
     }
   }
   HIPCHK(hipEventRecord(ev[2], st));
-  RC(torn_end(ctx, lam, u));
+  RC(torn_end(ctx, lam, u, f));
   HIPCHK(hipEventRecord(ev[3], st));
   HIPCHK(hipMemcpyAsync(ctx->h_rec_ist + slot * IS_COUNT, ctx->ist, IS_COUNT * sizeof(int32_t),
                         hipMemcpyDeviceToHost, st));
@@ -813,6 +873,8 @@ void torn_residual(feti_ctx ctx, const double* f, const double* u, const double*
   launch_elem_matvec(m, u, ctx->ytmp, ctx->mpP, ctx->mpE, st);
   launch_axpby(m.sum_ns, 1.0, f, -1.0, ctx->ytmp, ctx->rf, st);
   launch_sub_gather(m, lam, ctx->rf, st);
+  // dual-primal: a primal row's residual is the sum over its owners (kept in the first)
+  if (ctx->dp) launch_pi_fold(m, ctx->rf, st);
   launch_jump(m, u, 1, ctx->cj, 0, nullptr, nullptr, st);
   launch_axpby(m.n_lambda, -1.0, ctx->cj, 0.0, nullptr, ctx->cj, st);
 }
@@ -1208,6 +1270,7 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   if (precision != FETI_FP64 && precision != FETI_FP32_IR)
     return fail(ctx, FETI_EINVAL, "precision not supported");
   if (precond < 0 || precond > 2) return fail(ctx, FETI_EINVAL, "bad preconditioner");
+  if (ctx->dp && precision != FETI_FP64) return fail(ctx, FETI_EINVAL, "the dual-primal coupling takes FP64 factors");
   ctx->precision = precision;
   ctx->precond = precond;
   drop_graphs(ctx);
@@ -1238,11 +1301,18 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   // host copies of the per-subdomain geometry of the dense blocks
   std::vector<int> n(nsub), nI(nsub), nsw(nsub);
   std::vector<int64_t> aofs(nsub), sofs(nsub);
-  std::vector<int32_t> lda(nsub), ldb(nsub), nbv(nsub), nIv(nsub);
+  std::vector<int32_t> lda(nsub), ldb(nsub), nbv(nsub), nIv(nsub), nfin(nsub);
   int64_t ko = 0, so = 0;
   for (int s = 0; s < nsub; ++s) {
     const SubHost& sh = h.subs[s];
-    n[s] = sh.ns; nI[s] = sh.nI; nsw[s] = sh.ns - sh.nfix;
+    // pivots: every DOF but the fixed ones (dual coupling) or the primal ones (dual-primal
+    // coupling); the final sign change covers the swept block, or (dual-primal) the whole
+    // matrix, which then holds N_s = [[K_rr^{-1}, -K_rr^{-1} K_rPi], [-K_Pir K_rr^{-1}, -S_s]]
+    int npi = 0;
+    if (ctx->dp)
+      for (int8_t c : sh.cats) npi += c == C_BP ? 1 : 0;
+    n[s] = sh.ns; nI[s] = sh.nI; nsw[s] = sh.ns - (ctx->dp ? npi : sh.nfix);
+    nfin[s] = ctx->dp ? sh.ns : nsw[s];
     lda[s] = (int32_t)round8(sh.ns); aofs[s] = ko; ko += (int64_t)sh.ns * lda[s];
     ldb[s] = (int32_t)round8(sh.nb); sofs[s] = so; so += (int64_t)sh.nb * ldb[s];
     nbv[s] = sh.nb; nIv[s] = sh.nI;
@@ -1256,9 +1326,8 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   int rc = build_gj_plan(ctx, P, hflag, nsub, n, nI, nsw, aofs, lda, sofs, ldb, GJ_PANEL, tmp);
   if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
   std::vector<int32_t> stat(nsub, 0);
-  std::vector<int32_t> nswv(nsw.begin(), nsw.end());
   int32_t* d_nsw = nullptr;
-  rc = upload(ctx, &d_nsw, nswv);
+  rc = upload(ctx, &d_nsw, nfin);
   if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
   HIPCHK(hipEventRecord(ctx->ev_gj[0], st));
   if (f32) {
@@ -1308,6 +1377,31 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   }
   for (int s = 0; s < nsub; ++s)
     if (stat[s]) return fail(ctx, FETI_ESINGULAR, "zero or non-finite pivot in subdomain " + std::to_string(s));
+  // dual-primal coupling: the primal coarse matrix S_PiPi = sum_s L_s^T S_s L_s from the
+  // interface blocks (-S_s is their primal block) and its inverse, by the same pivot-free
+  // sweep (the global primal order puts the U-type corners first: quasi-definite)
+  if (ctx->dp && m.n_pi > 0) {
+    const int np = m.n_pi;
+    if (!ctx->Spinv) RC(dalloc(ctx, &ctx->Spinv, (size_t)np * np, ctx->mat_allocs));
+    HIPCHK(hipMemsetAsync(ctx->Spinv, 0, (size_t)np * np * sizeof(double), st));
+    launch_pi_assemble(m, ctx->Splus, ctx->Spinv, st);
+    GJPlan C;
+    std::vector<int32_t> cflag;
+    std::vector<void*> ctmp;
+    rc = build_gj_plan(ctx, C, cflag, 1, {np}, {0}, {np}, {0}, {np}, {-1}, {np}, GJ_PANEL, ctmp);
+    if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
+    for (int s = 0; s < C.nsteps; ++s) launch_gj_step(C, ctx->Spinv, (double*)nullptr, s, false, st);
+    int32_t* d_np = nullptr;
+    std::vector<int32_t> npv{np};
+    rc = upload(ctx, &d_np, npv);
+    if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
+    launch_gj_finalize(C, ctx->Spinv, d_np, st);
+    int32_t cs = 0;
+    HIPCHK(hipMemcpyAsync(&cs, C.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (void* p : ctmp) (void)hipFree(p);
+    if (cs) return fail(ctx, FETI_ESINGULAR, "zero or non-finite pivot in the primal coarse matrix");
+  }
   // coarse matrix G^T G and its inverse
   const int nc = ctx->nc;
   if (nc > 0) {
@@ -1691,7 +1785,11 @@ int feti_apply_F_noalloc(feti_ctx ctx, const double* x, double* y) {
   if (!ctx || !x || !y) return FETI_EINVAL;
   if (ctx->state < 3) return fail(ctx, FETI_ESTATE, "apply_F_noalloc before factor_subdomains");
   DevMesh& m = ctx->dm;
-  if (m.sum_nb > FETI_NOALLOC_SCRATCH) return fail(ctx, FETI_EINVAL, "interface space larger than the static scratch");
+  // scratch: the interface-space products, then (dual-primal coupling) the primal
+  // right-hand side and solution of the coarse step
+  const int64_t npi = ctx->dp ? m.n_pi : 0;
+  if (m.sum_nb + 2 * npi > FETI_NOALLOC_SCRATCH)
+    return fail(ctx, FETI_EINVAL, "interface space larger than the static scratch");
   int dev = -1;
   HIPCHK(hipGetDevice(&dev));
   if (dev != ctx->device) return fail(ctx, FETI_EINVAL, "apply_F_noalloc called with another device current");
@@ -1701,8 +1799,16 @@ int feti_apply_F_noalloc(feti_ctx ctx, const double* x, double* y) {
   const Factors fc = factors(ctx);
   a.A = fc.splus; a.a_f32 = fc.f32; a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
   a.v = x; a.gmode = G_SIGNED; a.gcoef = 1.0; a.y = yb;
-  // every entry of the scratch that the jump reads is written by the GEMV first
+  // every entry of the scratch that a later kernel reads is written before it
   launch_sgemv(m, a, ctx->stream);
+  if (npi > 0) {
+    double* cpi = yb + m.sum_nb;
+    double* upi = cpi + npi;
+    launch_pi_gather(m, nullptr, nullptr, yb, 1.0, cpi, nullptr, ctx->stream);
+    launch_coarse_apply(m.n_pi, ctx->Spinv, cpi, upi, 1.0, nullptr, ctx->stream);
+    a.pi_mode = 1; a.pi_v = upi;
+    launch_sgemv(m, a, ctx->stream);
+  }
   launch_jump(m, yb, 0, y, 0, nullptr, nullptr, ctx->stream);
   HIPCHK(hipGetLastError());
   return FETI_OK;
@@ -2126,6 +2232,7 @@ int feti_batch_create(feti_batch* out, feti_ctx* ctxs, int32_t nprob) {
     if (c->precond == FETI_PRECOND_NONE) return bad(FETI_EINVAL, "batch needs a preconditioner");
     if (c->nc > PCG_NC_LOCAL) return bad(FETI_EINVAL, "coarse space too large for a batch");
     if (c->dm.decoupled) return bad(FETI_EINVAL, "a batch steps the coupled scheme only");
+    if (c->dp) return bad(FETI_EINVAL, "a batch takes the dual coupling only");
     b->ctx.push_back(c);
   }
   b->stream = ctxs[0]->stream;

@@ -61,6 +61,11 @@ struct DevMesh {
   int decoupled = 0, n_dec = 0;
   int32_t *dec_node = nullptr, *dec_ptr = nullptr, *dec_ent = nullptr, *dec_xi = nullptr;
   uint8_t* dec_pdir = nullptr;
+  // dual-primal coupling: n_pi primal unknowns, per interface DOF its primal index (-1:
+  // dual), per primal DOF the interface indices of its owners (4 slots, -1 = none), per
+  // subdomain the number of primal DOFs (the trailing ones of its interface block)
+  int n_pi = 0, max_npi = 0, nsub_x = 1;
+  int32_t *bpi = nullptr, *pi_own = nullptr, *npi = nullptr;
 };
 
 // assembly / right-hand side (kernels_fem.hip)
@@ -141,6 +146,8 @@ struct GemvArgs {
   const int32_t* skip = nullptr;    // optional: do nothing when *skip != 0
   int kb_only = 0;                  // 1: sum only over the interface columns (x_I = 0)
   const double* ybase = nullptr;    // optional: y = ybase + A x (+ R alpha_c)
+  int pi_mode = 0;                  // 1: x at the primal DOFs = pi_v[primal index] (0 if null)
+  const double* pi_v = nullptr;
 };
 
 // Local solves from the packed lower tiles of the symmetric K_s^+ (kernels_sym.hip).
@@ -159,6 +166,9 @@ struct SymArgs {
   const int32_t* kb_tiles = nullptr;
   int n_kb_tiles = 0;
   const int32_t* tb = nullptr;
+  // dual-primal coupling: with pi_mode, x at the primal DOFs is pi_v[primal index] (0 if null)
+  int pi_mode = 0;
+  const double* pi_v = nullptr;
 };
 // packed tiles P from the dense row-major blocks K (offsets kofs, leading dims ld)
 template <class T>
@@ -170,5 +180,17 @@ void launch_sym_gemv(const DevMesh& m, const SymArgs& a, const double* x, double
 // product with the interface columns only, from the stored tiles that reach them
 void launch_sym_gemv_kb(const DevMesh& m, const SymArgs& a, const double* v, double gcoef, const double* ybase,
                         const double* alpha_c, double* y, hipStream_t st);
+
+// dual-primal coupling (kernels_dp.hip)
+// out[k] = sum over the owners o of primal DOF k of t1[torn(o)] + t2[torn(o)] + cy yb[o]
+// (t1, t2 torn vectors, yb interface-space; any may be null)
+void launch_pi_gather(const DevMesh& m, const double* t1, const double* t2, const double* yb, double cy, double* out,
+                      const int32_t* skip, hipStream_t st);
+// u[torn index of every primal interface DOF] = upi[its primal index]
+void launch_pi_scatter(const DevMesh& m, const double* upi, double* u, hipStream_t st);
+// r at the owners of every primal DOF: the first owner receives their sum, the others zero
+void launch_pi_fold(const DevMesh& m, double* r, hipStream_t st);
+// S (n_pi x n_pi, row-major) -= the primal blocks of the compact interface blocks A
+void launch_pi_assemble(const DevMesh& m, const double* A, double* S, hipStream_t st);
 
 }  // namespace feti

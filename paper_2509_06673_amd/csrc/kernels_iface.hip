@@ -171,6 +171,10 @@ __device__ __forceinline__ void sgemv_body(const DevMesh& m, const GemvArgs& a, 
   for (int t = a.kb_only ? first_b + threadIdx.x : threadIdx.x; t < n; t += blockDim.x) {
     double v = a.xbase ? a.xbase[xoff + t] : 0.0;
     if (a.gmode != G_NONE && t >= first_b) v += a.gcoef * gather_b(m, a.v, m.boff[s] + (t - first_b), a.gmode);
+    if (a.pi_mode && t >= first_b) {
+      const int q = m.bpi[m.boff[s] + (t - first_b)];
+      if (q >= 0) v = a.pi_v ? a.pi_v[q] : 0.0;
+    }
     xs[t] = v;
   }
   __syncthreads();

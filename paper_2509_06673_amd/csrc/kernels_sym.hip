@@ -42,14 +42,19 @@ __global__ void __launch_bounds__(256) k_sym_pack(SymArgs a, const T* __restrict
   }
 }
 
-// entry k of x_s: the torn vector (KB = 0), or [0; gcoef B_s^T v] (KB = 1)
+// entry k of x_s: the torn vector (KB = 0), or [0; gcoef B_s^T v] (KB = 1, v may be null);
+// with a.pi_mode the primal DOFs take a.pi_v[primal index] (0 if null) instead
 template <int KB>
-__device__ inline double sym_x(const DevMesh& m, int s, int n, int k, const double* xs, const double* v,
-                               double gcoef) {
+__device__ inline double sym_x(const DevMesh& m, const SymArgs& a, int s, int n, int k, const double* xs,
+                               const double* v, double gcoef) {
   if (k >= n) return 0.0;
-  if (!KB) return xs[k];
   const int first_b = n - m.nb[s];
-  return k >= first_b ? gcoef * gather_b(m, v, m.boff[s] + (k - first_b), G_SIGNED) : 0.0;
+  if (a.pi_mode && k >= first_b) {
+    const int q = m.bpi[m.boff[s] + (k - first_b)];
+    if (q >= 0) return a.pi_v ? a.pi_v[q] : 0.0;
+  }
+  if (!KB) return xs[k];
+  return (k >= first_b && v) ? gcoef * gather_b(m, v, m.boff[s] + (k - first_b), G_SIGNED) : 0.0;
 }
 
 // The row and transposed parts of stored tile t by this wavefront (valid = false: the
@@ -65,8 +70,8 @@ __device__ __forceinline__ void sym_tile_body(const DevMesh& m, const SymArgs& a
   const double* xs = (valid && x) ? x + m.soff[s] : nullptr;
   double* xJ = xv[wave][0];
   double* xI = xv[wave][1];
-  xJ[lane] = valid ? sym_x<KB>(m, s, n, J * SYM_TS + lane, xs, v, gcoef) : 0.0;
-  xI[lane] = valid ? sym_x<KB>(m, s, n, I * SYM_TS + lane, xs, v, gcoef) : 0.0;
+  xJ[lane] = valid ? sym_x<KB>(m, a, s, n, J * SYM_TS + lane, xs, v, gcoef) : 0.0;
+  xI[lane] = valid ? sym_x<KB>(m, a, s, n, I * SYM_TS + lane, xs, v, gcoef) : 0.0;
   const T* tile = P + (int64_t)(valid ? t : 0) * SYM_TE;
   double* Lw = L[wave];
   double u = 0.0;

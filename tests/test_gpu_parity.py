@@ -12,7 +12,7 @@ import pytest
 import workloads as W
 from oracle import indexing as ix, local as lo
 from feti_helpers import (require_gpu, oracle_reference, torn_reference, per_kind_rel_error,
-                          sub_poro_flags)
+                          sub_poro_flags, cached_oracle_lattices)
 
 pytestmark = pytest.mark.gpu
 
@@ -209,9 +209,6 @@ def test_not_converged_is_reported_with_iterate():
     f.close()
 
 
-_FULL_ORACLE = {}
-
-
 @pytest.mark.parametrize("start", [B.START_PREVIOUS, B.START_EXTRAPOLATE], ids=["previous", "extrapolated"])
 def test_full_size_workload_matches_oracle(start):
     """The 64-subdomain h = 1/128 workload, as bench.py runs it (first solves from the
@@ -221,12 +218,10 @@ def test_full_size_workload_matches_oracle(start):
     import torch
     w = W.nearly_incompressible_large()
     nsteps = 25
-    if not _FULL_ORACLE:
-        t0 = time.time()
-        print("[full] oracle ...", flush=True)
-        _FULL_ORACLE["lats"] = oracle_reference(w, nsteps)[1]
-        print(f"[full] oracle done in {time.time() - t0:.1f} s", flush=True)
-    lats = _FULL_ORACLE["lats"]
+    t0 = time.time()
+    print("[full] oracle ...", flush=True)
+    lats = cached_oracle_lattices(w, nsteps)
+    print(f"[full] oracle done in {time.time() - t0:.1f} s", flush=True)
     f = setup(w)
     idx = f.export_indexing()
     codes = idx["code"].astype(np.int64)
