@@ -448,13 +448,16 @@ void op_F_raw(feti_ctx ctx, const double* x, double* y, double* g, const int32_t
   const Factors fc = factors(ctx);
   a.A = fc.splus; a.a_f32 = fc.f32; a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
   a.v = x; a.gmode = G_SIGNED; a.gcoef = 1.0; a.y = ctx->yb; a.skip = skip;
-  launch_sgemv(m, a, ctx->stream);
   if (ctx->dp && m.n_pi > 0) {
+    // primal rows of N_s [B_s^T x; 0] (dual columns only), the coarse solve, then the dual
+    // rows of N_s [B_s^T x; L_s u_Pi]
+    a.rsel = 2; a.csel = 1;
+    launch_sgemv(m, a, ctx->stream);
     launch_pi_gather(m, nullptr, nullptr, ctx->yb, 1.0, ctx->cpi, skip, ctx->stream);
     launch_coarse_apply(m.n_pi, ctx->Spinv, ctx->cpi, ctx->upi, 1.0, skip, ctx->stream);
-    a.pi_mode = 1; a.pi_v = ctx->upi;
-    launch_sgemv(m, a, ctx->stream);
+    a.pi_mode = 1; a.pi_v = ctx->upi; a.rsel = 1; a.csel = 0;
   }
+  launch_sgemv(m, a, ctx->stream);
   launch_jump(m, ctx->yb, 0, y, 0, g, skip, ctx->stream);
 }
 
@@ -476,6 +479,8 @@ void op_M_raw(feti_ctx ctx, const double* x, double* y, double* g, const int32_t
   else { a.A = fc.sbb; a.a_f32 = fc.f32; }
   a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
   a.v = x; a.gmode = G_SCALED; a.gcoef = 1.0; a.y = ctx->zb; a.skip = skip;
+  // dual-primal: the jump reads the dual rows, and x is zero at the primal DOFs
+  if (ctx->dp) { a.rsel = 1; a.csel = 1; }
   launch_sgemv(m, a, ctx->stream);
   launch_jump(m, ctx->zb, 0, y, 1, g, skip, ctx->stream);
 }
@@ -676,7 +681,7 @@ int torn_end(feti_ctx ctx, const double* lam, double* u, const double* f) {
   if (ctx->dp) {
     GemvArgs a;
     a.A = ctx->Splus; a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
-    a.v = lam; a.gmode = G_SIGNED; a.gcoef = 1.0; a.y = ctx->yb;
+    a.v = lam; a.gmode = G_SIGNED; a.gcoef = 1.0; a.y = ctx->yb; a.rsel = 2; a.csel = 1;
     launch_sgemv(m, a, st);
     launch_pi_gather(m, f, ctx->ytmp, ctx->yb, -1.0, ctx->cpi, nullptr, st);
     launch_coarse_apply(m.n_pi, ctx->Spinv, ctx->cpi, ctx->upi, 1.0, nullptr, st);
@@ -1799,16 +1804,18 @@ int feti_apply_F_noalloc(feti_ctx ctx, const double* x, double* y) {
   const Factors fc = factors(ctx);
   a.A = fc.splus; a.a_f32 = fc.f32; a.aofs = m.sofs; a.lda = m.ldb; a.which_n = 1;
   a.v = x; a.gmode = G_SIGNED; a.gcoef = 1.0; a.y = yb;
-  // every entry of the scratch that a later kernel reads is written before it
-  launch_sgemv(m, a, ctx->stream);
+  // every entry of the scratch that a later kernel reads is written before it (the primal
+  // rows by the first product, the dual rows by the second)
   if (npi > 0) {
     double* cpi = yb + m.sum_nb;
     double* upi = cpi + npi;
+    a.rsel = 2; a.csel = 1;
+    launch_sgemv(m, a, ctx->stream);
     launch_pi_gather(m, nullptr, nullptr, yb, 1.0, cpi, nullptr, ctx->stream);
     launch_coarse_apply(m.n_pi, ctx->Spinv, cpi, upi, 1.0, nullptr, ctx->stream);
-    a.pi_mode = 1; a.pi_v = upi;
-    launch_sgemv(m, a, ctx->stream);
+    a.pi_mode = 1; a.pi_v = upi; a.rsel = 1; a.csel = 0;
   }
+  launch_sgemv(m, a, ctx->stream);
   launch_jump(m, yb, 0, y, 0, nullptr, nullptr, ctx->stream);
   HIPCHK(hipGetLastError());
   return FETI_OK;

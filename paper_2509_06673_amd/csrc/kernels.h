@@ -148,6 +148,10 @@ struct GemvArgs {
   const double* ybase = nullptr;    // optional: y = ybase + A x (+ R alpha_c)
   int pi_mode = 0;                  // 1: x at the primal DOFs = pi_v[primal index] (0 if null)
   const double* pi_v = nullptr;
+  // interface blocks under the dual-primal coupling ([dual | primal], primal trailing): rows
+  // 0 all, 1 the dual rows only, 2 the primal rows only (the others are not written);
+  // columns 0 all, 1 the dual columns only (x is taken as zero at the primal DOFs)
+  int rsel = 0, csel = 0;
 };
 
 // Local solves from the packed lower tiles of the symmetric K_s^+ (kernels_sym.hip).

@@ -161,14 +161,22 @@ __device__ __forceinline__ void sgemv_body(const DevMesh& m, const GemvArgs& a, 
   if (s >= m.nsub) return;
   const int ns = m.ns[s], nbs = m.nb[s];
   const int n = FULL ? ns : nbs;
-  const int row0 = bx * 64;
-  if (row0 >= n) return;
+  // row range [rlo, rhi) and column range [k0, chi)
+  int rlo = 0, rhi = n, chi = n;
+  if (!FULL && (a.rsel || a.csel)) {
+    const int nd = nbs - m.npi[s];
+    if (a.rsel == 1) rhi = nd;
+    else if (a.rsel == 2) rlo = nd;
+    if (a.csel == 1) chi = nd;
+  }
+  const int row0 = rlo + bx * 64;
+  if (row0 >= rhi) return;
   extern __shared__ double smem[];
   double* xs = smem;              // n
   double* red = smem + m.max_ns;  // 4 x 64
   const int first_b = n - nbs;
   const int64_t xoff = FULL ? m.soff[s] : m.boff[s];
-  for (int t = a.kb_only ? first_b + threadIdx.x : threadIdx.x; t < n; t += blockDim.x) {
+  for (int t = a.kb_only ? first_b + threadIdx.x : threadIdx.x; t < chi; t += blockDim.x) {
     double v = a.xbase ? a.xbase[xoff + t] : 0.0;
     if (a.gmode != G_NONE && t >= first_b) v += a.gcoef * gather_b(m, a.v, m.boff[s] + (t - first_b), a.gmode);
     if (a.pi_mode && t >= first_b) {
@@ -181,12 +189,12 @@ __device__ __forceinline__ void sgemv_body(const DevMesh& m, const GemvArgs& a, 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = row0 + lane;
   const int k0 = a.kb_only ? first_b : 0;
-  const int kq = (n - k0 + 3) / 4;
-  const int kb = k0 + wave * kq, ke = min(n, kb + kq);
+  const int kq = (chi - k0 + 3) / 4;
+  const int kb = k0 + wave * kq, ke = min(chi, kb + kq);
   const MT* A = static_cast<const MT*>(a.A) + a.aofs[s];
   const int64_t ld = a.lda[s];
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-  if (i < n) {
+  if (i < rhi) {
     // batches of eight independent column loads in flight before their FMAs
     const MT* col = A + (int64_t)kb * ld + i;
     int k = kb;
@@ -215,7 +223,7 @@ __device__ __forceinline__ void sgemv_body(const DevMesh& m, const GemvArgs& a, 
   }
   red[wave * 64 + lane] = (acc0 + acc1) + (acc2 + acc3);
   __syncthreads();
-  if (wave == 0 && i < n) {
+  if (wave == 0 && i < rhi) {
     double yv = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
     if (a.ybase) yv += a.ybase[xoff + i];
     if (a.alpha_c) {
