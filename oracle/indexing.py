@@ -52,8 +52,9 @@ import numpy as np
 
 from workloads import Workload, XSPLIT, YSPLIT, CORE
 
-KIND_FIELD_ORDER = {0: 0, 1: 0, 2: 1, 3: 2, 4: 3, 5: 2}
-U_KINDS = (0, 1, 2)
+KIND_FIELD_ORDER = {0: 0, 1: 0, 2: 1, 3: 2, 4: 3, 5: 2, 6: 0}
+U_KINDS = (0, 1, 2, 6)
+KIND_COMP = {0: 0, 1: 1, 6: 2}      # displacement component of a u kind (uz: kind 6, 3D)
 
 
 def _region_poro(layout, xc, yc):
@@ -90,6 +91,8 @@ class Sub:
     codes: List[int]        # local order
     cats: List[int]
     floating: bool
+    k0: int = 0             # 3D: cell range in z
+    k1: int = 0
 
 
 @dataclass
@@ -106,6 +109,8 @@ class IndexSpec:
 
 
 def build(w: Workload) -> IndexSpec:
+    if w.dim == 3:
+        return build3d(w)
     n = w.ncell
     k = w.order_u
     ratio = 1 if k == 1 else 2
@@ -212,6 +217,101 @@ def build(w: Workload) -> IndexSpec:
         # come before the P-type fields (xi, p)
         pc = [c for c in owners if len(owners[c]) > 1 and is_primal(c)]
         primal = np.array(sorted(pc, key=lambda c: (KIND_FIELD_ORDER[c % 8], c // 8, c % 8)), dtype=np.int64)
+    return IndexSpec(subs, R, np.array([r[1] for r in rows], dtype=np.int64),
+                     np.array([r[2] for r in rows], dtype=np.int64), primal)
+
+
+def build3d(w: Workload) -> IndexSpec:
+    """The numbering on the unit cube (d = 3): subdomain s = (c nsub_y + b) nsub_x + a
+    covers the cells [cx[a], cx[a+1]) x [cy[b], cy[b+1]) x [cz[c], cz[c+1]) at the even cuts;
+    lattices x fastest, then y, then z; displacement kinds ux 0, uy 1, uz 6 (components
+    0, 1, 2), the scalar kinds as in 2D; outer faces (bit 0: x = 0, 1: x = 1, 2: y = 0,
+    3: y = 1, 4: z = 0, 5: z = 1).  Only the dual-primal gluing: the shared xi / p DOFs
+    and the shared DOFs at the corners of the subdomain grid are primal, the other shared
+    DOFs (u and eta on the grid's faces and edges, two or four owners) dual, with the
+    rows, signs, local order and primal order of the 2D rules."""
+    if w.coupling != "primal" or w.layout != XSPLIT or w.scheme != "coupled":
+        raise ValueError("3D takes the x-split layout, the coupled scheme and the dual-primal gluing")
+    n = w.ncell
+    ratio = 1 if w.order_u == 1 else 2
+    mu = ratio * n + 1
+    n1 = n + 1
+    cuts = [[(a * n) // ns for a in range(ns + 1)] for ns in (w.nsub_x, w.nsub_y, w.nsub_z)]
+    cx, cy, cz = cuts
+    if n % 2 or n // 2 not in cx:
+        raise ValueError("a subdomain straddles the interface x = 1/2")
+
+    def face(I, J, K, m, mask):
+        return any((mask >> bit) & 1 and hit for bit, hit in
+                   enumerate((I == 0, I == m - 1, J == 0, J == m - 1, K == 0, K == m - 1)))
+    owners, local_sets = {}, []
+    for c in range(w.nsub_z):
+        for b in range(w.nsub_y):
+            for a in range(w.nsub_x):
+                sid = (c * w.nsub_y + b) * w.nsub_x + a
+                i0, i1, j0, j1, k0, k1 = cx[a], cx[a + 1], cy[b], cy[b + 1], cz[c], cz[c + 1]
+                poro = (i0 + i1) < n            # the cell block lies in x < 1/2
+                codes, has_dir = [], False
+                for K in range(ratio * k0, ratio * k1 + 1):
+                    for J in range(ratio * j0, ratio * j1 + 1):
+                        for I in range(ratio * i0, ratio * i1 + 1):
+                            if face(I, J, K, mu, w.dirichlet_u):
+                                has_dir = True
+                                continue
+                            node = (K * mu + J) * mu + I
+                            codes += [8 * node + 0, 8 * node + 1, 8 * node + 6]
+                for k in range(k0, k1 + 1):
+                    for j in range(j0, j1 + 1):
+                        for i in range(i0, i1 + 1):
+                            node = (k * n1 + j) * n1 + i
+                            if poro:
+                                codes += [8 * node + 2, 8 * node + 3]
+                                if not face(i, j, k, n1, w.dirichlet_p):
+                                    codes.append(8 * node + 4)
+                            else:
+                                codes.append(8 * node + 5)
+                for cd in codes:
+                    owners.setdefault(cd, []).append(sid)
+                local_sets.append((sid, poro, i0, i1, j0, j1, k0, k1, codes, has_dir))
+    sx, sy, sz = set(cx), set(cy), set(cz)
+
+    def is_primal(cd):
+        node, kind = cd // 8, cd % 8
+        if kind not in U_KINDS:
+            return True
+        if kind == 2:
+            i, j, k = node % n1, (node // n1) % n1, node // (n1 * n1)
+            return i in sx and j in sy and k in sz
+        I, J, K = node % mu, (node // mu) % mu, node // (mu * mu)
+        return (I % ratio == 0 and J % ratio == 0 and K % ratio == 0 and I // ratio in sx
+                and J // ratio in sy and K // ratio in sz)
+    subs = []
+    for sid, poro, i0, i1, j0, j1, k0, k1, codes, has_dir in local_sets:
+        keyed = []
+        for cd in codes:
+            node, kind = cd // 8, cd % 8
+            shared = len(owners[cd]) > 1
+            cat = (3 if is_primal(cd) else 2) if shared else (0 if kind in U_KINDS else 1)
+            keyed.append(((cat, KIND_FIELD_ORDER[kind], node, KIND_COMP.get(kind, 0)), cd, cat))
+        keyed.sort()
+        subs.append(Sub(sid, poro, i0, i1, j0, j1, [cd for _, cd, _ in keyed], [ct for _, _, ct in keyed],
+                        False, k0, k1))
+    pos = [dict((cd, i) for i, cd in enumerate(s.codes)) for s in subs]
+    rows = []
+    for cd in sorted(owners, key=lambda q: (q % 8, q // 8)):
+        S = sorted(owners[cd])
+        if len(S) < 2 or is_primal(cd):
+            continue
+        for kk in range(len(S) - 1):
+            s1, s2 = S[kk], S[kk + 1]
+            sg1, sg2 = 1, -1
+            if subs[s1].poro != subs[s2].poro and not subs[s1].poro:
+                sg1, sg2 = -1, 1
+            rows.append(((cd % 8, cd // 8, kk), cd, len(S), ((s1, pos[s1][cd], sg1), (s2, pos[s2][cd], sg2))))
+    rows.sort(key=lambda r: r[0])
+    R = np.array([r[3] for r in rows], dtype=np.int64).reshape(-1, 2, 3)
+    pc = [cd for cd in owners if len(owners[cd]) > 1 and is_primal(cd)]
+    primal = np.array(sorted(pc, key=lambda q: (KIND_FIELD_ORDER[q % 8], q // 8, q % 8)), dtype=np.int64)
     return IndexSpec(subs, R, np.array([r[1] for r in rows], dtype=np.int64),
                      np.array([r[2] for r in rows], dtype=np.int64), primal)
 

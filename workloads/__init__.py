@@ -97,6 +97,10 @@ class Workload:
     # "primal" (the shared xi / p DOFs and the shared DOFs at subdomain corners are global
     # primal unknowns; multipliers glue only the remaining u and eta DOFs)
     coupling: str = "dual"
+    # spatial dimension (2: triangles on the unit square; 3: Kuhn tetrahedra on the unit
+    # cube, with an nsub_x x nsub_y x nsub_z subdomain grid at the even cuts)
+    dim: int = 2
+    nsub_z: int = 1
 
     def cuts(self) -> Tuple[List[int], List[int]]:
         cx = list(self.cut_x) if self.cut_x is not None else [(a * self.ncell) // self.nsub_x
@@ -210,9 +214,14 @@ def raw_shapes(w: Workload) -> Dict[str, Tuple[int, ...]]:
     """Array shapes of the RAW data: displacement lattice of mu = k ncell + 1 points per
     side, P1 lattice of n1 = ncell + 1; lattices row-major with x fastest; the side
     arrays are indexed by side (x = 0, x = 1, y = 0, y = 1) and by the lattice index
-    along the side (y index on x = const, x index on y = const)."""
+    along the side (y index on x = const, x index on y = const).  In 3D the lattices are
+    cubes (x fastest, then y, then z), the displacement data has three components and
+    there are no side data."""
     mu = w.order_u * w.ncell + 1
     n1 = w.ncell + 1
+    if w.dim == 3:
+        return {"f_p": (3, mu ** 3), "f_e": (3, mu ** 3), "z": (n1 ** 3,), "t_side": (0,), "zw_side": (0,),
+                "g_u": (3, mu ** 3), "g_p": (n1 ** 3,), "eta0": (n1 ** 3,)}
     return {"f_p": (2, mu * mu), "f_e": (2, mu * mu), "z": (n1 * n1,), "t_side": (2, 4, 2, mu),
             "zw_side": (4, n1), "g_u": (2, mu * mu), "g_p": (n1 * n1,), "eta0": (n1 * n1,)}
 
@@ -231,6 +240,28 @@ def raw_arrays(w: Workload, t: float) -> Dict[str, np.ndarray]:
         fac = 1.0 if name == "eta0" else 1.0 + 0.5 * math.sin(3.0 * t + 0.7 * i)
         out[name] = fac * base
     return out
+
+
+def cube_case(ncell: int = 4, nsub: Tuple[int, int, int] = (2, 2, 2), order_u: int = 2, nsteps: int = 3,
+              seed: int = 7, nu: float = 0.3) -> Workload:
+    """3D: the unit cube in Kuhn tetrahedra, poroelastic for x < 1/2, elastic for x > 1/2,
+    seeded nodal data (RAW); u Dirichlet on every face, p Dirichlet on the poroelastic
+    parts of x = 0, y = 0 and z = 0 (no flux through the others)."""
+    m = _mat(E=10.0, nu=nu, alpha=1.0, c0=0.5, K=0.2, mu_f=1.0)
+    return Workload(name=f"cube_p{order_u}_h{ncell}_{nsub[0]}x{nsub[1]}x{nsub[2]}_s{seed}", ncell=ncell,
+                    order_u=order_u, layout=XSPLIT, nsub_x=nsub[0], nsub_y=nsub[1], mat_p=m,
+                    mat_e=copy.deepcopy(m), tau=0.05, nsteps=nsteps, load=Load(kind=RAW, raw_seed=seed),
+                    dirichlet_u=0x3F, dirichlet_p=0b010101, coupling="primal", dim=3, nsub_z=nsub[2])
+
+
+def cube_nearly_incompressible(ncell: int = 16, nsub: int = 4, nsteps: int = 25, seed: int = 11) -> Workload:
+    """3D counterpart of the nearly incompressible workload: P2 tetrahedra, h = 1/ncell,
+    nsub^3 subdomains, nu = 0.49999, c0 = 1e-3, K = 1e-6, tau = 1e-3, seeded nodal data."""
+    m = _mat(E=1e4, nu=0.49999, alpha=1.0, c0=1e-3, K=1e-6, mu_f=1.0)
+    return Workload(name=f"cube_p2_h{ncell}_{nsub}x{nsub}x{nsub}", ncell=ncell, order_u=2, layout=XSPLIT,
+                    nsub_x=nsub, nsub_y=nsub, mat_p=m, mat_e=copy.deepcopy(m), tau=1e-3, nsteps=nsteps,
+                    load=Load(kind=RAW, raw_seed=seed), dirichlet_u=0x3F, dirichlet_p=0b010101,
+                    coupling="primal", dim=3, nsub_z=nsub)
 
 
 BATCH_SEED = 20250906
