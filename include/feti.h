@@ -95,7 +95,22 @@ typedef struct {
                              FETI_SCHEME_DECOUPLED (the explicit fluid step of the Remark
                              after eq. (linalg-system); see feti_step) */
     int32_t coupling;     /* FETI_COUPLING_DUAL or FETI_COUPLING_PRIMAL (below) */
+    int32_t dim;          /* 2 (or 0): the unit square in triangles; 3: the unit cube in
+                             tetrahedra (Section 2 allows d = 2, 3), see below */
+    int32_t nsub_z;       /* 3D: subdomains along z */
 } feti_mesh_desc;
+
+/* d = 3: the unit cube, ncell^3 cubes each cut into the six Kuhn tetrahedra around its
+ * main diagonal (vertices v0, v0 + h e_a, v0 + h (e_a + e_b), v0 + h (1, 1, 1) for the
+ * axis permutations (a, b, c)), P_k displacement (k = 1, 2; P2 nodes at the vertices and
+ * edge midpoints) and P1 scalars; poroelastic for x < 1/2 (layout FETI_XSPLIT only);
+ * nsub_x x nsub_y x nsub_z subdomains at the even cuts (cut_x, cut_y NULL; nsub_x even);
+ * lattices x fastest, then y, then z; DOF kinds as in 2D plus uz = 6; outer faces bit 0:
+ * x = 0, 1: x = 1, 2: y = 0, 3: y = 1, 4: z = 0, 5: z = 1.  Takes the dual-primal
+ * coupling, the coupled scheme and loads of kind FETI_LOAD_RAW (nodal body forces,
+ * source, Dirichlet and initial data on the cube lattices: f_p, f_e, g_u of 3 x mu^3
+ * doubles, z, g_p, eta0 of n1^3; no side data, t_side and zw_side NULL); FETI_EINVAL
+ * otherwise. */
 
 /* Gluing of the shared DOFs.  DUAL: every shared DOF is torn and glued by multipliers
  * (Section 3.1); the interface operator F is symmetric but indefinite, with one negative
@@ -341,7 +356,7 @@ int feti_set_state(feti_ctx ctx, const double* state_dev, const int64_t* meta_ho
  * the poroelastic region (p^n = p_D on pressure Dirichlet nodes).
  * out_dev: device, caller-owned.  Synchronises the context stream. */
 enum { FETI_FIELD_UX = 0, FETI_FIELD_UY = 1, FETI_FIELD_ETA = 2, FETI_FIELD_XI_P = 3, FETI_FIELD_P = 4,
-       FETI_FIELD_XI_E = 5 };
+       FETI_FIELD_XI_E = 5, FETI_FIELD_UZ = 6 /* 3D */ };
 int feti_get_field(feti_ctx ctx, int32_t field, double* out_dev);
 
 /* Set the multiplier start of the next step (used with FETI_START_GIVEN and

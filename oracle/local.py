@@ -175,3 +175,72 @@ def generalized_inverse(K: np.ndarray, cats: List[int]) -> np.ndarray:
     Kp = np.zeros_like(K)
     Kp[np.ix_(s, s)] = np.linalg.inv(K[np.ix_(s, s)])
     return Kp
+
+
+def build_local3d(w: Workload) -> LocalSystem:
+    """The 3D torn matrices: K_s of every subdomain of the cube (its tetrahedra's element
+    matrices of ``oracle.fem3d`` in the local order of ``oracle.indexing.build3d``,
+    Dirichlet DOFs removed, K_D the columns of the Dirichlet codes for lifting)."""
+    from .fem3d import Mesh3D, element_matrices as em3
+    spec = ix.build(w)
+    m = Mesh3D(w.ncell, w.order_u)
+    lamP, muP = lame(w.mat_p)
+    lamE, muE = lame(w.mat_e)
+    k1, k2, k3 = kappas(w.mat_p)
+    n = w.ncell
+    nloc = 4 if w.order_u == 1 else 10
+    Ks, KDs, Dcodes, elems = [], [], [], []
+    for s in spec.subs:
+        cells = [(k * n + j) * n + i for k in range(s.k0, s.k1) for j in range(s.j0, s.j1)
+                 for i in range(s.i0, s.i1)]
+        tet = np.array(sorted(6 * c + t for c in cells for t in range(6)))
+        elems.append(tet)
+        em = em3(w.order_u, m.X[tet], muP if s.poro else muE, (w.mat_p.K / w.mat_p.mu_f) if s.poro else 1.0)
+        uc = np.empty((len(tet), 3 * nloc), dtype=np.int64)
+        for c, kind in enumerate((0, 1, 6)):
+            uc[:, c::3] = 8 * m.pu[tet] + kind
+        p1 = m.p1[tet]
+        trip = []
+
+        def add(rc, cc, M, sc=1.0):
+            trip.append((np.broadcast_to(rc[:, :, None], M.shape).ravel(),
+                         np.broadcast_to(cc[:, None, :], M.shape).ravel(), (sc * M).ravel()))
+        if s.poro:
+            xc, ec, pc = 8 * p1 + 3, 8 * p1 + 2, 8 * p1 + 4
+            add(uc, uc, em['A'])
+            add(uc, xc, np.transpose(em['B'], (0, 2, 1)))
+            add(xc, uc, em['B'])
+            add(xc, xc, em['R'], -k3)
+            add(xc, ec, em['R'], k1)
+            add(ec, xc, em['R'], k1)
+            add(ec, ec, em['R'], k2)
+            add(ec, pc, em['R'], -1.0)
+            add(pc, ec, em['R'], -1.0)
+            add(pc, pc, em['Af'], -w.tau)
+        else:
+            xc = 8 * p1 + 5
+            add(uc, uc, em['A'])
+            add(uc, xc, np.transpose(em['B'], (0, 2, 1)))
+            add(xc, uc, em['B'])
+            add(xc, xc, em['R'], -1.0 / lamE)
+        rc = np.concatenate([t[0] for t in trip])
+        cc = np.concatenate([t[1] for t in trip])
+        vv = np.concatenate([t[2] for t in trip])
+        pos = {c: i for i, c in enumerate(s.codes)}
+        allc = np.unique(np.concatenate([rc, cc]))
+        dcodes = np.array([c for c in allc if c not in pos], dtype=np.int64)
+        dpos = {c: i for i, c in enumerate(dcodes)}
+        ns = len(s.codes)
+        K = np.zeros((ns, ns))
+        KD = np.zeros((ns, len(dcodes)))
+        for r_, c_, v_ in zip(rc, cc, vv):
+            if r_ not in pos:
+                continue
+            if c_ in pos:
+                K[pos[r_], pos[c_]] += v_
+            else:
+                KD[pos[r_], dpos[c_]] += v_
+        Ks.append(K)
+        KDs.append(KD)
+        Dcodes.append(dcodes)
+    return LocalSystem(spec, Ks, Dcodes, KDs, elems)

@@ -28,7 +28,7 @@ CORR_ZERO, CORR_PREVIOUS = 0, 1
 PCG_AUTO, PCG_GRAPH = 0, 1
 EXPORT_K, EXPORT_SBB, EXPORT_KPLUS = 0, 1, 2
 KERNEL_LOCAL_SOLVE, KERNEL_IFACE_GEMV, KERNEL_PRECOND_GEMV, KERNEL_ELIMINATION = 0, 1, 2, 3
-FIELD_UX, FIELD_UY, FIELD_ETA, FIELD_XI_P, FIELD_P, FIELD_XI_E = 0, 1, 2, 3, 4, 5
+FIELD_UX, FIELD_UY, FIELD_ETA, FIELD_XI_P, FIELD_P, FIELD_XI_E, FIELD_UZ = 0, 1, 2, 3, 4, 5, 6
 
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM", EHIP: "EHIP",
                 ESINGULAR: "ESINGULAR", ENOTCONV: "ENOTCONV", EBREAKDOWN: "EBREAKDOWN",
@@ -43,7 +43,7 @@ class MeshDesc(C.Structure):
     _fields_ = [("ncell", C.c_int32), ("order_u", C.c_int32), ("layout", C.c_int32),
                 ("nsub_x", C.c_int32), ("nsub_y", C.c_int32), ("dirichlet_u", C.c_uint32),
                 ("dirichlet_p", C.c_uint32), ("cut_x", C.POINTER(C.c_int32)), ("cut_y", C.POINTER(C.c_int32)),
-                ("scheme", C.c_int32), ("coupling", C.c_int32)]
+                ("scheme", C.c_int32), ("coupling", C.c_int32), ("dim", C.c_int32), ("nsub_z", C.c_int32)]
 
 
 class Material(C.Structure):
@@ -244,12 +244,12 @@ class Feti:
 
     # -- setup ----------------------------------------------------------------
     def setup_mesh(self, ncell, order_u, layout, nsub_x, nsub_y, dirichlet_u=0xF, dirichlet_p=0xF,
-                   cut_x=None, cut_y=None, scheme=0, coupling=0):
+                   cut_x=None, cut_y=None, scheme=0, coupling=0, dim=2, nsub_z=1):
         cx = (C.c_int32 * len(cut_x))(*cut_x) if cut_x is not None else None
         cy = (C.c_int32 * len(cut_y))(*cut_y) if cut_y is not None else None
         d = MeshDesc(ncell, order_u, layout, nsub_x, nsub_y, dirichlet_u, dirichlet_p,
                      C.cast(cx, C.POINTER(C.c_int32)) if cx is not None else None,
-                     C.cast(cy, C.POINTER(C.c_int32)) if cy is not None else None, scheme, coupling)
+                     C.cast(cy, C.POINTER(C.c_int32)) if cy is not None else None, scheme, coupling, dim, nsub_z)
         return self._check(self.lib.feti_setup_mesh(self.ctx, C.byref(d)), "feti_setup_mesh")
 
     def get_sizes(self) -> Dict[str, int]:

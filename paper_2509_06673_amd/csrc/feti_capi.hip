@@ -211,7 +211,8 @@ int upload_mesh(feti_ctx ctx) {
     }
   }
   std::vector<int32_t> row_kind(h.n_lambda);
-  for (int64_t j = 0; j < h.n_lambda; ++j) row_kind[j] = h.rows[j].kind;
+  // (3D: the uz rows join the ux kind of the per-kind stopping test, which tracks six kinds)
+  for (int64_t j = 0; j < h.n_lambda; ++j) row_kind[j] = h.rows[j].kind == K_UZ ? K_UX : h.rows[j].kind;
   RC(upload(ctx, &m.ns, ns));
   RC(upload(ctx, &m.nI, nI));
   RC(upload(ctx, &m.nb, nb));
@@ -263,7 +264,9 @@ int upload_mesh(feti_ctx ctx) {
   RC(upload(ctx, &m.row_kind, row_kind));
   RC(upload(ctx, &m.float_sub, h.float_sub));
   ctx->dp = h.desc.coupling == FETI_COUPLING_PRIMAL;
+  static_assert(PI_SLOTS == PI_OWNERS, "the device owner table has the host's slots");
   m.nsub_x = h.desc.nsub_x;
+  m.nsub_y = h.desc.nsub_y;
   m.n_pi = h.n_pi;
   m.max_npi = 0;
   if (ctx->dp) {
@@ -1179,8 +1182,8 @@ int feti_get_sizes(feti_ctx ctx, int64_t* s) {
   s[4] = h.max_ns;
   s[5] = h.max_nb;
   s[6] = h.sum_nb;
-  s[7] = (int64_t)h.n1 * h.n1;
-  s[8] = (int64_t)h.mu * h.mu;
+  s[7] = h.n_p1_lat;
+  s[8] = h.n_u_lat;
   s[9] = h.n_float;
   s[10] = h.n_pi;
   return FETI_OK;
@@ -1257,10 +1260,13 @@ int feti_assemble(feti_ctx ctx, const feti_material* P, const feti_material* E, 
   ctx->mpE.tau = tau;
   RC(upload_mesh(ctx));
   RC(dalloc(ctx, &ctx->dm.emat, (size_t)ctx->dm.nelem * ctx->dm.edof * ctx->dm.edof, ctx->allocs));
-  launch_elem_store(ctx->dm, ctx->mpP, ctx->mpE, ctx->stream);
+  const bool d3 = ctx->mh.dim == 3;
+  if (d3) launch_elem_store3d(ctx->dm, ctx->mpP, ctx->mpE, ctx->stream);
+  else launch_elem_store(ctx->dm, ctx->mpP, ctx->mpE, ctx->stream);
   RC(dalloc(ctx, &ctx->K, ctx->k_total, ctx->mat_allocs));
   HIPCHK(hipMemsetAsync(ctx->K, 0, ctx->k_total * sizeof(double), ctx->stream));
-  launch_assemble(ctx->dm, ctx->K, ctx->mpP, ctx->mpE, ctx->stream);
+  if (d3) launch_assemble3d(ctx->dm, ctx->K, ctx->stream);
+  else launch_assemble(ctx->dm, ctx->K, ctx->mpP, ctx->mpE, ctx->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->state = 2;
@@ -1334,6 +1340,15 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   int32_t* d_nsw = nullptr;
   rc = upload(ctx, &d_nsw, nfin);
   if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
+  // S_bb of a subdomain without interior DOFs (a one-cell slab of a 3D decomposition) is
+  // its K_bb: no interior pivot step takes that snapshot, so every interface block is
+  // copied before the sweep (the snapshots of the other subdomains overwrite theirs)
+  if (f32)
+    launch_copy_block(nsub, m.max_nb, m.kofs, m.ld, m.nI, m.sofs, m.ldb, m.nb, (const float*)ctx->Kinv32,
+                      ctx->Sbb32, st);
+  else
+    launch_copy_block(nsub, m.max_nb, m.kofs, m.ld, m.nI, m.sofs, m.ldb, m.nb, (const double*)ctx->Kinv, ctx->Sbb,
+                      st);
   HIPCHK(hipEventRecord(ctx->ev_gj[0], st));
   if (f32) {
     for (int s = 0; s < P.nsteps; ++s) launch_gj_step(P, ctx->Kinv32, ctx->Sbb32, s, hflag[s] != 0, st);
@@ -1483,6 +1498,9 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, fet
   hipStream_t st = ctx->stream;
   HIPCHK(hipEventRecord(ctx->ev[0], st));
   LoadDev L = make_load(ctx, load);
+  const bool d3 = ctx->mh.dim == 3;
+  if (d3 && (L.kind != FETI_LOAD_RAW || L.t_side || L.zw_side))
+    return fail(ctx, FETI_EINVAL, "3D takes nodal (RAW) loads without side data");
   int cmode = 0;
   if (m.decoupled) {
     // explicit fluid step: eta^n from eta^{n-1}, p^{n-1} (and xi^{n-1} at pressure
@@ -1509,7 +1527,8 @@ int feti_step(feti_ctx ctx, const feti_load* load, const feti_solve_opts* o, fet
       ctx->ecache_valid = true;
     }
   }
-  launch_rhs(m, ctx->u, ctx->f, ctx->mpP, ctx->mpE, L, st, ctx->ecache, cmode);
+  if (d3) launch_rhs3d(m, ctx->u, ctx->f, ctx->mpP, L, st);
+  else launch_rhs(m, ctx->u, ctx->f, ctx->mpP, ctx->mpE, L, st, ctx->ecache, cmode);
   // start vector
   int used = o->start;
   if (o->start == FETI_START_ZERO ||
@@ -1702,10 +1721,12 @@ int feti_set_state(feti_ctx ctx, const double* state_dev, const int64_t* meta) {
 int feti_get_field(feti_ctx ctx, int32_t field, double* out_dev) {
   if (!ctx || !out_dev) return FETI_EINVAL;
   if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "get_field before assemble");
-  if (field < FETI_FIELD_UX || field > FETI_FIELD_XI_E) return fail(ctx, FETI_EINVAL, "unknown field");
-  const DevMesh& m = ctx->dm;
   const MeshHost& h = ctx->mh;
-  const int64_t nlat = field <= FETI_FIELD_UY ? (int64_t)h.mu * h.mu : (int64_t)h.n1 * h.n1;
+  if (field < FETI_FIELD_UX || field > FETI_FIELD_UZ || (field == FETI_FIELD_UZ && h.dim != 3))
+    return fail(ctx, FETI_EINVAL, "unknown field");
+  const DevMesh& m = ctx->dm;
+  const bool ufield = field <= FETI_FIELD_UY || field == FETI_FIELD_UZ;
+  const int64_t nlat = ufield ? h.n_u_lat : h.n_p1_lat;
   launch_zero(nlat, out_dev, ctx->stream);
   if (m.decoupled && (field == FETI_FIELD_ETA || field == FETI_FIELD_P))
     launch_dec_field(m, field == FETI_FIELD_ETA ? ctx->dec_eta : ctx->dec_p, out_dev, ctx->stream);
@@ -1719,6 +1740,7 @@ int feti_get_field(feti_ctx ctx, int32_t field, double* out_dev) {
 int feti_interface_load(feti_ctx ctx, const feti_load* load, double* out_dev) {
   if (!ctx || !load || !out_dev) return FETI_EINVAL;
   if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "interface_load before assemble");
+  if (ctx->mh.dim == 3) return fail(ctx, FETI_EINVAL, "interface_load is 2D only");
   launch_interface_load(ctx->dm, make_load(ctx, load), out_dev, ctx->stream);
   HIPCHK(hipGetLastError());
   return FETI_OK;

@@ -10,7 +10,7 @@
 namespace feti {
 
 // DOF kinds (code = 8 * node + kind)
-enum Kind { K_UX = 0, K_UY = 1, K_ETA = 2, K_XIP = 3, K_P = 4, K_XIE = 5 };
+enum Kind { K_UX = 0, K_UY = 1, K_ETA = 2, K_XIP = 3, K_P = 4, K_XIE = 5, K_UZ = 6 };  // K_UZ: 3D
 
 // Categories of the local order [I_U | I_P | b_U | b_P | fixed]
 enum Cat { C_IU = 0, C_IP = 1, C_BU = 2, C_BP = 3, C_FIX = 4 };
@@ -20,6 +20,7 @@ struct SubHost {
   bool poro = false;
   bool floating = false;
   int i0 = 0, i1 = 0, j0 = 0, j1 = 0;  // cell range [i0, i1) x [j0, j1)
+  int k0 = 0, k1 = 0;                   // 3D: cell range in z
   std::vector<int32_t> codes;          // local order
   std::vector<int8_t> cats;
   int ns = 0, nI = 0, nb = 0, nfix = 0;  // nb includes the fixed DOFs
@@ -37,14 +38,19 @@ struct JumpRow {
   int32_t kind;
 };
 
-// Element DOF table: up to 21 DOFs per element
-constexpr int MAX_EDOF = 21;
+// owners of a primal DOF (a corner of the 3D subdomain grid has eight)
+constexpr int PI_OWNERS = 8;
+
+// Element DOF table: up to 21 DOFs per element in 2D, 42 in 3D (P2 tetrahedra)
+constexpr int MAX_EDOF = 42;
 
 struct MeshHost {
   feti_mesh_desc desc{};
+  int dim = 2;               // 2: triangles on the unit square, 3: tetrahedra on the unit cube
   int ratio = 2;             // displacement lattice refinement (1 for P1, 2 for P2)
   int mu = 0;                // displacement lattice points per side
   int n1 = 0;                // P1 lattice points per side
+  int64_t n_u_lat = 0, n_p1_lat = 0;  // lattice sizes (mu^dim, n1^dim)
   std::vector<SubHost> subs;
   std::vector<JumpRow> rows;
   // per-multiplier block of D = (B B^T)^{-1}: group start and size, row of D
@@ -84,7 +90,7 @@ struct MeshHost {
   std::vector<uint8_t> dec_pdir;
   // dual-primal coupling: the primal codes in global order (the first n_pi_u of U type),
   // per interface DOF its primal index (-1: dual or no coupling), per primal DOF the
-  // interface indices of its owners (4 slots, -1 = none)
+  // interface indices of its owners (PI_OWNERS slots, -1 = none)
   int n_pi = 0, n_pi_u = 0;
   std::vector<int32_t> pi_code, bpi, pi_own;
 };

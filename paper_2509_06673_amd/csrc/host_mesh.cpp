@@ -8,6 +8,7 @@
 // the preconditioner, the element DOF tables for the assembly kernels and the
 // rigid modes of floating subdomains for the coarse space.
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <map>
 #include <numeric>
@@ -36,7 +37,7 @@ bool cell_poro(int layout, int i, int j, int n) {
 
 int field_order(int kind) {
   switch (kind) {
-    case K_UX: case K_UY: return 0;
+    case K_UX: case K_UY: case K_UZ: return 0;
     case K_ETA: return 1;
     case K_XIP: case K_XIE: return 2;
     default: return 3;
@@ -62,96 +63,23 @@ void small_inverse(int n, double* a) {
 
 }  // namespace
 
-std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
-  const int n = d.ncell;
-  if (n < 1 || (d.order_u != 1 && d.order_u != 2) || d.nsub_x < 1 || d.nsub_y < 1 ||
-      d.nsub_x > n || d.nsub_y > n || d.layout < 0 || d.layout > 2)
-    return "invalid mesh description";
-  if (d.scheme != FETI_SCHEME_COUPLED && d.scheme != FETI_SCHEME_DECOUPLED) return "unknown time scheme";
-  if (d.coupling != FETI_COUPLING_DUAL && d.coupling != FETI_COUPLING_PRIMAL) return "unknown coupling";
-  const bool decoupled = d.scheme == FETI_SCHEME_DECOUPLED;
-  const bool dp = d.coupling == FETI_COUPLING_PRIMAL;
-  if (dp && decoupled) return "the decoupled scheme takes the dual coupling only";
-  m = MeshHost();
-  m.desc = d;
-  m.ratio = d.order_u == 2 ? 2 : 1;
-  const int r = m.ratio;
-  const int nu = r * n;  // last displacement lattice index
-  m.mu = nu + 1;
-  m.n1 = n + 1;
-  std::vector<int> cx(d.nsub_x + 1), cy(d.nsub_y + 1);
-  for (int a = 0; a <= d.nsub_x; ++a) cx[a] = d.cut_x ? d.cut_x[a] : (int)((int64_t)a * n / d.nsub_x);
-  for (int b = 0; b <= d.nsub_y; ++b) cy[b] = d.cut_y ? d.cut_y[b] : (int)((int64_t)b * n / d.nsub_y);
-  if (cx[0] != 0 || cx[d.nsub_x] != n || cy[0] != 0 || cy[d.nsub_y] != n) return "cuts must run from 0 to ncell";
-  for (int a = 0; a < d.nsub_x; ++a)
-    if (cx[a + 1] <= cx[a]) return "cuts must increase strictly";
-  for (int b = 0; b < d.nsub_y; ++b)
-    if (cy[b + 1] <= cy[b]) return "cuts must increase strictly";
-  // the pointers are the caller's: the stored description does not keep them
-  m.desc.cut_x = nullptr;
-  m.desc.cut_y = nullptr;
-  const int nsub = d.nsub_x * d.nsub_y;
-  m.subs.resize(nsub);
-  // owners of every DOF code
-  std::unordered_map<int32_t, std::vector<int32_t>> owners;
-  owners.reserve((size_t)nsub * 64);
-  std::vector<bool> has_dir(nsub, false);
-  for (int b = 0; b < d.nsub_y; ++b) {
-    for (int a = 0; a < d.nsub_x; ++a) {
-      const int sid = b * d.nsub_x + a;
-      SubHost& s = m.subs[sid];
-      s.sid = sid;
-      s.i0 = cx[a]; s.i1 = cx[a + 1]; s.j0 = cy[b]; s.j1 = cy[b + 1];
-      if (s.i1 <= s.i0 || s.j1 <= s.j0) return "empty subdomain";
-      const bool p0 = cell_poro(d.layout, s.i0, s.j0, n);
-      for (int j = s.j0; j < s.j1; ++j)
-        for (int i = s.i0; i < s.i1; ++i)
-          if (cell_poro(d.layout, i, j, n) != p0) return "a subdomain straddles the interface";
-      s.poro = p0;
-      for (int J = r * s.j0; J <= r * s.j1; ++J)
-        for (int I = r * s.i0; I <= r * s.i1; ++I) {
-          if (on_sides(I, J, nu, d.dirichlet_u)) { has_dir[sid] = true; continue; }
-          const int32_t node = J * m.mu + I;
-          s.codes.push_back(8 * node + K_UX);
-          s.codes.push_back(8 * node + K_UY);
-        }
-      for (int j = s.j0; j <= s.j1; ++j)
-        for (int i = s.i0; i <= s.i1; ++i) {
-          const int32_t node = j * m.n1 + i;
-          if (s.poro) {
-            // decoupled: eta and p are not unknowns of the subdomain problems
-            if (!decoupled) s.codes.push_back(8 * node + K_ETA);
-            s.codes.push_back(8 * node + K_XIP);
-            if (!decoupled && !on_sides(i, j, n, d.dirichlet_p)) s.codes.push_back(8 * node + K_P);
-          } else {
-            s.codes.push_back(8 * node + K_XIE);
-          }
-        }
-      for (int32_t c : s.codes) owners[c].push_back(sid);
-    }
-  }
-  // dual-primal coupling: a shared code is primal when its kind is xi_P, p or xi_E, or when
-  // its node lies on a vertical and a horizontal cut line (outer sides included)
-  std::vector<uint8_t> xcut(n + 1, 0), ycut(n + 1, 0);
-  for (int a = 0; a <= d.nsub_x; ++a) xcut[cx[a]] = 1;
-  for (int b = 0; b <= d.nsub_y; ++b) ycut[cy[b]] = 1;
-  auto is_primal = [&](int32_t c) -> bool {
-    const int node = c / 8, kind = c % 8;
-    if (kind == K_XIP || kind == K_P || kind == K_XIE) return true;
-    if (kind == K_ETA) return xcut[node % m.n1] && ycut[node / m.n1];
-    const int I = node % m.mu, J = node / m.mu;
-    return I % r == 0 && J % r == 0 && xcut[I / r] && ycut[J / r];
-  };
+// Everything between the subdomains' DOF codes and the element tables, the same in 2D and
+// 3D: categories and local orders, offsets, the positions of the codes, the jump rows
+// with their D = (B B^T)^{-1} weights, the gather maps of the interface space and the
+// primal tables of the dual-primal coupling.
+std::string finish_interface(MeshHost& m, std::unordered_map<int32_t, std::vector<int32_t>>& owners,
+                             const std::vector<bool>& has_dir, bool dp,
+                             const std::function<bool(int32_t)>& is_primal,
+                             const std::function<void(const SubHost&, int32_t&, int32_t&, int32_t&)>& fixed_codes,
+                             const std::function<bool(const std::vector<int32_t>&)>& rigid_ok,
+                             std::vector<std::unordered_map<int32_t, int32_t>>& pos) {
+  const int nsub = (int)m.subs.size();
   // categories and local order
   for (SubHost& s : m.subs) {
     // under the dual-primal coupling the primal corners hold every subdomain
     s.floating = !dp && !has_dir[s.sid];
     int32_t fixA = -1, fixB = -1, fixC = -1;
-    if (s.floating) {
-      const int32_t A = (r * s.j0) * m.mu + r * s.i0;
-      const int32_t C = (r * s.j1) * m.mu + r * s.i1;
-      fixA = 8 * A + K_UX; fixB = 8 * A + K_UY; fixC = 8 * C + K_UX;
-    }
+    if (s.floating) fixed_codes(s, fixA, fixB, fixC);
     struct Key { int cat, fo, node, comp; int32_t code; };
     std::vector<Key> keys;
     keys.reserve(s.codes.size());
@@ -160,10 +88,10 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
       const bool shared = owners[c].size() > 1;
       int cat;
       if (c == fixA || c == fixB || c == fixC) cat = C_FIX;
-      else if (dp) cat = shared ? (is_primal(c) ? C_BP : C_BU) : (kind <= K_ETA ? C_IU : C_IP);
-      else if (kind <= K_ETA) cat = shared ? C_BU : C_IU;
+      else if (dp) cat = shared ? (is_primal(c) ? C_BP : C_BU) : ((kind <= K_ETA || kind == K_UZ) ? C_IU : C_IP);
+      else if (kind <= K_ETA || kind == K_UZ) cat = shared ? C_BU : C_IU;
       else cat = shared ? C_BP : C_IP;
-      keys.push_back({cat, field_order(kind), node, kind == K_UY ? 1 : 0, c});
+      keys.push_back({cat, field_order(kind), node, kind == K_UY ? 1 : (kind == K_UZ ? 2 : 0), c});
     }
     std::sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
       return std::tie(x.cat, x.fo, x.node, x.comp) < std::tie(y.cat, y.fo, y.node, y.comp);
@@ -179,13 +107,16 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
     }
     if (s.floating && s.nfix != 3) return "floating subdomain without its three fixed DOFs";
     if (dp && !has_dir[s.sid]) {
-      // two distinct primal displacement nodes remove the rigid-body modes
+      // primal displacement nodes that remove the rigid-body modes: two distinct ones in
+      // 2D, three not on one line in 3D
       std::vector<int32_t> un;
-      for (size_t i = 0; i < s.codes.size(); ++i)
-        if (s.cats[i] == C_BP && s.codes[i] % 8 <= K_UY) un.push_back(s.codes[i] / 8);
+      for (size_t i = 0; i < s.codes.size(); ++i) {
+        const int k = s.codes[i] % 8;
+        if (s.cats[i] == C_BP && (k == K_UX || k == K_UY || k == K_UZ)) un.push_back(s.codes[i] / 8);
+      }
       std::sort(un.begin(), un.end());
-      if (std::unique(un.begin(), un.end()) - un.begin() < 2)
-        return "a subdomain without Dirichlet data has fewer than two primal corners";
+      un.erase(std::unique(un.begin(), un.end()), un.end());
+      if (!rigid_ok(un)) return "a subdomain without Dirichlet data has too few primal corners";
     }
   }
   // offsets
@@ -199,7 +130,7 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
   m.sum_ns = off;
   m.sum_nb = boff;
   // position of each code in each subdomain
-  std::vector<std::unordered_map<int32_t, int32_t>> pos(nsub);
+  pos.assign(nsub, {});
   for (SubHost& s : m.subs) {
     pos[s.sid].reserve(s.codes.size() * 2);
     for (int i = 0; i < s.ns; ++i) pos[s.sid][s.codes[i]] = i;
@@ -300,21 +231,315 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
     m.n_pi = (int)m.pi_code.size();
     m.n_pi_u = 0;
     for (int32_t c : m.pi_code)
-      if (c % 8 <= K_ETA) ++m.n_pi_u;
-    m.pi_own.assign(4 * (size_t)m.n_pi, -1);
+      if (c % 8 <= K_ETA || c % 8 == K_UZ) ++m.n_pi_u;
+    m.pi_own.assign(PI_OWNERS * (size_t)m.n_pi, -1);
     for (int k = 0; k < m.n_pi; ++k) {
       std::vector<int32_t> S = owners[m.pi_code[k]];
       std::sort(S.begin(), S.end());
-      if (S.size() > 4) return "a node shared by more than four subdomains";
+      if (S.size() > (size_t)PI_OWNERS) return "a primal DOF shared by more than eight subdomains";
       for (size_t e = 0; e < S.size(); ++e) {
         const SubHost& sh = m.subs[S[e]];
         const int bl = pos[S[e]][m.pi_code[k]] - sh.nI;
         if (bl < 0) return "primal DOF in the interior";
         const int64_t gb = sh.boff + bl;
-        m.pi_own[4 * (size_t)k + e] = (int32_t)gb;
+        m.pi_own[PI_OWNERS * (size_t)k + e] = (int32_t)gb;
         m.bpi[gb] = k;
       }
     }
+  }
+  return "";
+}
+
+// DOF -> (element, row) adjacency of the element tables
+void build_adjacency(MeshHost& m) {
+  // DOF -> (element, row) adjacency, elements in increasing order
+  const int64_t nel = (int64_t)m.el_sub.size();
+  std::vector<int32_t> cnt(m.sum_ns + 1, 0);
+  for (int64_t e = 0; e < nel; ++e) {
+    const SubHost& s = m.subs[m.el_sub[e]];
+    for (int a = 0; a < m.edof; ++a) {
+      const int li = m.el_ldof[e * m.edof + a];
+      if (li >= 0) ++cnt[s.off + li + 1];
+    }
+  }
+  m.adj_ptr.assign(m.sum_ns + 1, 0);
+  for (int64_t i = 0; i < m.sum_ns; ++i) m.adj_ptr[i + 1] = m.adj_ptr[i] + cnt[i + 1];
+  m.adj.assign(m.adj_ptr[m.sum_ns], 0);
+  std::vector<int32_t> fill(m.adj_ptr.begin(), m.adj_ptr.end() - 1);
+  for (int64_t e = 0; e < nel; ++e) {
+    const SubHost& s = m.subs[m.el_sub[e]];
+    for (int a = 0; a < m.edof; ++a) {
+      const int li = m.el_ldof[e * m.edof + a];
+      if (li >= 0) m.adj[fill[s.off + li]++] = (int32_t)(e * m.edof + a);
+    }
+  }
+}
+
+// d = 3: the unit cube in Kuhn tetrahedra (see feti.h), dual-primal coupling only.
+std::string build_mesh3d(const feti_mesh_desc& d, MeshHost& m) {
+  const int n = d.ncell;
+  if (n < 2 || (d.order_u != 1 && d.order_u != 2) || d.nsub_x < 1 || d.nsub_y < 1 || d.nsub_z < 1 ||
+      d.nsub_x > n || d.nsub_y > n || d.nsub_z > n)
+    return "invalid mesh description";
+  if (d.layout != FETI_XSPLIT || d.coupling != FETI_COUPLING_PRIMAL || d.scheme != FETI_SCHEME_COUPLED)
+    return "3D takes the x-split layout, the dual-primal coupling and the coupled scheme";
+  if (d.cut_x || d.cut_y) return "3D takes the even cuts";
+  m = MeshHost();
+  m.desc = d;
+  m.dim = 3;
+  m.ratio = d.order_u == 2 ? 2 : 1;
+  const int r = m.ratio;
+  const int nu = r * n;
+  m.mu = nu + 1;
+  m.n1 = n + 1;
+  m.n_u_lat = (int64_t)m.mu * m.mu * m.mu;
+  m.n_p1_lat = (int64_t)m.n1 * m.n1 * m.n1;
+  const int ns3[3] = {d.nsub_x, d.nsub_y, d.nsub_z};
+  std::vector<int> cut[3];
+  std::vector<uint8_t> oncut[3];
+  for (int a = 0; a < 3; ++a) {
+    cut[a].resize(ns3[a] + 1);
+    oncut[a].assign(n + 1, 0);
+    for (int q = 0; q <= ns3[a]; ++q) {
+      cut[a][q] = (int)((int64_t)q * n / ns3[a]);
+      oncut[a][cut[a][q]] = 1;
+    }
+  }
+  if (n % 2 || !oncut[0][n / 2]) return "a subdomain straddles the interface x = 1/2";
+  const int nsub = d.nsub_x * d.nsub_y * d.nsub_z;
+  m.subs.resize(nsub);
+  auto on_faces = [](int I, int J, int K, int nmax, uint32_t mask) {
+    return ((mask & 1u) && I == 0) || ((mask & 2u) && I == nmax) || ((mask & 4u) && J == 0) ||
+           ((mask & 8u) && J == nmax) || ((mask & 16u) && K == 0) || ((mask & 32u) && K == nmax);
+  };
+  const int64_t mu = m.mu, n1 = m.n1;
+  std::unordered_map<int32_t, std::vector<int32_t>> owners;
+  owners.reserve((size_t)nsub * 256);
+  std::vector<bool> has_dir(nsub, false);
+  for (int c = 0; c < d.nsub_z; ++c)
+    for (int b = 0; b < d.nsub_y; ++b)
+      for (int a = 0; a < d.nsub_x; ++a) {
+        const int sid = (c * d.nsub_y + b) * d.nsub_x + a;
+        SubHost& s = m.subs[sid];
+        s.sid = sid;
+        s.i0 = cut[0][a]; s.i1 = cut[0][a + 1];
+        s.j0 = cut[1][b]; s.j1 = cut[1][b + 1];
+        s.k0 = cut[2][c]; s.k1 = cut[2][c + 1];
+        s.poro = 2 * s.i1 <= n;
+        for (int K = r * s.k0; K <= r * s.k1; ++K)
+          for (int J = r * s.j0; J <= r * s.j1; ++J)
+            for (int I = r * s.i0; I <= r * s.i1; ++I) {
+              if (on_faces(I, J, K, nu, d.dirichlet_u)) { has_dir[sid] = true; continue; }
+              const int32_t node = (int32_t)((K * mu + J) * mu + I);
+              s.codes.push_back(8 * node + K_UX);
+              s.codes.push_back(8 * node + K_UY);
+              s.codes.push_back(8 * node + K_UZ);
+            }
+        for (int k = s.k0; k <= s.k1; ++k)
+          for (int j = s.j0; j <= s.j1; ++j)
+            for (int i = s.i0; i <= s.i1; ++i) {
+              const int32_t node = (int32_t)((k * n1 + j) * n1 + i);
+              if (s.poro) {
+                s.codes.push_back(8 * node + K_ETA);
+                s.codes.push_back(8 * node + K_XIP);
+                if (!on_faces(i, j, k, n, d.dirichlet_p)) s.codes.push_back(8 * node + K_P);
+              } else {
+                s.codes.push_back(8 * node + K_XIE);
+              }
+            }
+        for (int32_t cd : s.codes) owners[cd].push_back(sid);
+      }
+  auto is_primal = [&](int32_t cd) -> bool {
+    const int64_t node = cd / 8;
+    const int kind = cd % 8;
+    if (kind == K_XIP || kind == K_P || kind == K_XIE) return true;
+    if (kind == K_ETA) return oncut[0][node % n1] && oncut[1][(node / n1) % n1] && oncut[2][node / (n1 * n1)];
+    const int64_t I = node % mu, J = (node / mu) % mu, K = node / (mu * mu);
+    return I % r == 0 && J % r == 0 && K % r == 0 && oncut[0][I / r] && oncut[1][J / r] && oncut[2][K / r];
+  };
+  auto no_fix = [](const SubHost&, int32_t&, int32_t&, int32_t&) {};
+  auto rigid_ok = [&](const std::vector<int32_t>& un) {
+    // three primal displacement nodes not on one line
+    if (un.size() < 3) return false;
+    auto xyz = [&](int32_t node, double* x) {
+      x[0] = (double)(node % mu); x[1] = (double)((node / mu) % mu); x[2] = (double)(node / (mu * mu));
+    };
+    double p0[3], p1[3], p2[3];
+    xyz(un[0], p0);
+    xyz(un[1], p1);
+    const double u[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+    for (size_t q = 2; q < un.size(); ++q) {
+      xyz(un[q], p2);
+      const double v[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+      const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2], cz = u[0] * v[1] - u[1] * v[0];
+      if (cx * cx + cy * cy + cz * cz > 0.0) return true;
+    }
+    return false;
+  };
+  std::vector<std::unordered_map<int32_t, int32_t>> pos;
+  {
+    const std::string err = finish_interface(m, owners, has_dir, true, is_primal, no_fix, rigid_ok, pos);
+    if (!err.empty()) return err;
+  }
+  // no floating subdomain, no coarse space
+  m.sub_float.assign(nsub, -1);
+  m.rb.assign(3 * m.sum_nb, 0.0);
+  m.rfull.assign(3 * m.sum_ns, 0.0);
+  m.n_float = 0;
+  // element tables: cube (i, j, k) -> cell (k n + j) n + i, six tetrahedra per cube
+  const int nloc = d.order_u == 2 ? 10 : 4;
+  m.edof = 3 * nloc + 12;
+  m.sub_el_off.assign(nsub + 1, 0);
+  const int EP[6] = {0, 0, 0, 1, 1, 2}, EQ[6] = {1, 2, 3, 2, 3, 3};
+  for (SubHost& s : m.subs) {
+    const auto& P = pos[s.sid];
+    for (int k = s.k0; k < s.k1; ++k)
+      for (int j = s.j0; j < s.j1; ++j)
+        for (int i = s.i0; i < s.i1; ++i)
+          for (int t = 0; t < 6; ++t) {
+            const int a = t / 2, rr = t % 2;
+            const int b = a == 0 ? 1 + rr : (a == 1 ? 2 * rr : rr);
+            int V[4][3] = {{i, j, k}, {i, j, k}, {i, j, k}, {i + 1, j + 1, k + 1}};
+            V[1][a] += 1;
+            V[2][a] += 1;
+            V[2][b] += 1;
+            int64_t un[10];
+            for (int v = 0; v < 4; ++v) un[v] = ((int64_t)r * V[v][2] * mu + r * V[v][1]) * mu + r * V[v][0];
+            if (nloc == 10)
+              for (int e = 0; e < 6; ++e) {
+                int U[3];
+                for (int q = 0; q < 3; ++q) U[q] = (r * V[EP[e]][q] + r * V[EQ[e]][q]) / 2;
+                un[4 + e] = ((int64_t)U[2] * mu + U[1]) * mu + U[0];
+              }
+            m.el_sub.push_back(s.sid);
+            m.el_cell.push_back((k * n + j) * n + i);
+            m.el_type.push_back(t);
+            std::vector<int32_t> codes(m.edof, -1);
+            for (int q = 0; q < nloc; ++q) {
+              codes[3 * q] = (int32_t)(8 * un[q] + K_UX);
+              codes[3 * q + 1] = (int32_t)(8 * un[q] + K_UY);
+              codes[3 * q + 2] = (int32_t)(8 * un[q] + K_UZ);
+            }
+            for (int v = 0; v < 4; ++v) {
+              const int32_t node = (int32_t)((V[v][2] * n1 + V[v][1]) * n1 + V[v][0]);
+              if (s.poro) {
+                codes[3 * nloc + v] = 8 * node + K_XIP;
+                codes[3 * nloc + 4 + v] = 8 * node + K_ETA;
+                codes[3 * nloc + 8 + v] = 8 * node + K_P;
+              } else {
+                codes[3 * nloc + v] = 8 * node + K_XIE;
+              }
+            }
+            for (int q = 0; q < m.edof; ++q) {
+              int32_t li = -1;
+              if (codes[q] >= 0) {
+                auto it = P.find(codes[q]);
+                if (it != P.end()) li = it->second;
+              }
+              m.el_ldof.push_back(li);
+              m.el_code.push_back(codes[q]);
+            }
+          }
+    m.sub_el_off[s.sid + 1] = (int32_t)m.el_sub.size();
+  }
+  build_adjacency(m);
+  return "";
+}
+
+std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
+  if (d.dim == 3) return build_mesh3d(d, m);
+  if (d.dim != 0 && d.dim != 2) return "dimension must be 2 or 3";
+  const int n = d.ncell;
+  if (n < 1 || (d.order_u != 1 && d.order_u != 2) || d.nsub_x < 1 || d.nsub_y < 1 ||
+      d.nsub_x > n || d.nsub_y > n || d.layout < 0 || d.layout > 2)
+    return "invalid mesh description";
+  if (d.scheme != FETI_SCHEME_COUPLED && d.scheme != FETI_SCHEME_DECOUPLED) return "unknown time scheme";
+  if (d.coupling != FETI_COUPLING_DUAL && d.coupling != FETI_COUPLING_PRIMAL) return "unknown coupling";
+  const bool decoupled = d.scheme == FETI_SCHEME_DECOUPLED;
+  const bool dp = d.coupling == FETI_COUPLING_PRIMAL;
+  if (dp && decoupled) return "the decoupled scheme takes the dual coupling only";
+  m = MeshHost();
+  m.desc = d;
+  m.ratio = d.order_u == 2 ? 2 : 1;
+  const int r = m.ratio;
+  const int nu = r * n;  // last displacement lattice index
+  m.mu = nu + 1;
+  m.n1 = n + 1;
+  m.n_u_lat = (int64_t)m.mu * m.mu;
+  m.n_p1_lat = (int64_t)m.n1 * m.n1;
+  std::vector<int> cx(d.nsub_x + 1), cy(d.nsub_y + 1);
+  for (int a = 0; a <= d.nsub_x; ++a) cx[a] = d.cut_x ? d.cut_x[a] : (int)((int64_t)a * n / d.nsub_x);
+  for (int b = 0; b <= d.nsub_y; ++b) cy[b] = d.cut_y ? d.cut_y[b] : (int)((int64_t)b * n / d.nsub_y);
+  if (cx[0] != 0 || cx[d.nsub_x] != n || cy[0] != 0 || cy[d.nsub_y] != n) return "cuts must run from 0 to ncell";
+  for (int a = 0; a < d.nsub_x; ++a)
+    if (cx[a + 1] <= cx[a]) return "cuts must increase strictly";
+  for (int b = 0; b < d.nsub_y; ++b)
+    if (cy[b + 1] <= cy[b]) return "cuts must increase strictly";
+  // the pointers are the caller's: the stored description does not keep them
+  m.desc.cut_x = nullptr;
+  m.desc.cut_y = nullptr;
+  const int nsub = d.nsub_x * d.nsub_y;
+  m.subs.resize(nsub);
+  // owners of every DOF code
+  std::unordered_map<int32_t, std::vector<int32_t>> owners;
+  owners.reserve((size_t)nsub * 64);
+  std::vector<bool> has_dir(nsub, false);
+  for (int b = 0; b < d.nsub_y; ++b) {
+    for (int a = 0; a < d.nsub_x; ++a) {
+      const int sid = b * d.nsub_x + a;
+      SubHost& s = m.subs[sid];
+      s.sid = sid;
+      s.i0 = cx[a]; s.i1 = cx[a + 1]; s.j0 = cy[b]; s.j1 = cy[b + 1];
+      if (s.i1 <= s.i0 || s.j1 <= s.j0) return "empty subdomain";
+      const bool p0 = cell_poro(d.layout, s.i0, s.j0, n);
+      for (int j = s.j0; j < s.j1; ++j)
+        for (int i = s.i0; i < s.i1; ++i)
+          if (cell_poro(d.layout, i, j, n) != p0) return "a subdomain straddles the interface";
+      s.poro = p0;
+      for (int J = r * s.j0; J <= r * s.j1; ++J)
+        for (int I = r * s.i0; I <= r * s.i1; ++I) {
+          if (on_sides(I, J, nu, d.dirichlet_u)) { has_dir[sid] = true; continue; }
+          const int32_t node = J * m.mu + I;
+          s.codes.push_back(8 * node + K_UX);
+          s.codes.push_back(8 * node + K_UY);
+        }
+      for (int j = s.j0; j <= s.j1; ++j)
+        for (int i = s.i0; i <= s.i1; ++i) {
+          const int32_t node = j * m.n1 + i;
+          if (s.poro) {
+            // decoupled: eta and p are not unknowns of the subdomain problems
+            if (!decoupled) s.codes.push_back(8 * node + K_ETA);
+            s.codes.push_back(8 * node + K_XIP);
+            if (!decoupled && !on_sides(i, j, n, d.dirichlet_p)) s.codes.push_back(8 * node + K_P);
+          } else {
+            s.codes.push_back(8 * node + K_XIE);
+          }
+        }
+      for (int32_t c : s.codes) owners[c].push_back(sid);
+    }
+  }
+  // dual-primal coupling: a shared code is primal when its kind is xi_P, p or xi_E, or when
+  // its node lies on a vertical and a horizontal cut line (outer sides included)
+  std::vector<uint8_t> xcut(n + 1, 0), ycut(n + 1, 0);
+  for (int a = 0; a <= d.nsub_x; ++a) xcut[cx[a]] = 1;
+  for (int b = 0; b <= d.nsub_y; ++b) ycut[cy[b]] = 1;
+  auto is_primal = [&](int32_t c) -> bool {
+    const int node = c / 8, kind = c % 8;
+    if (kind == K_XIP || kind == K_P || kind == K_XIE) return true;
+    if (kind == K_ETA) return xcut[node % m.n1] && ycut[node / m.n1];
+    const int I = node % m.mu, J = node / m.mu;
+    return I % r == 0 && J % r == 0 && xcut[I / r] && ycut[J / r];
+  };
+  std::vector<std::unordered_map<int32_t, int32_t>> pos;
+  {
+    auto fixed_codes = [&](const SubHost& sh, int32_t& fa, int32_t& fb, int32_t& fc) {
+      const int32_t A = (r * sh.j0) * m.mu + r * sh.i0;
+      const int32_t C = (r * sh.j1) * m.mu + r * sh.i1;
+      fa = 8 * A + K_UX; fb = 8 * A + K_UY; fc = 8 * C + K_UX;
+    };
+    auto rigid_ok = [](const std::vector<int32_t>& un) { return un.size() >= 2; };
+    const std::string err = finish_interface(m, owners, has_dir, dp, is_primal, fixed_codes, rigid_ok, pos);
+    if (!err.empty()) return err;
   }
   // coarse space: rigid modes of floating subdomains
   m.sub_float.assign(nsub, -1);
@@ -434,27 +659,7 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
     for (int k = 0; k < nd; ++k)
       if (m.dec_xi[k] < 0) return "a poroelastic node without a xi_P unknown";
   }
-  // DOF -> (element, row) adjacency, elements in increasing order
-  const int64_t nel = (int64_t)m.el_sub.size();
-  std::vector<int32_t> cnt(m.sum_ns + 1, 0);
-  for (int64_t e = 0; e < nel; ++e) {
-    const SubHost& s = m.subs[m.el_sub[e]];
-    for (int a = 0; a < m.edof; ++a) {
-      const int li = m.el_ldof[e * m.edof + a];
-      if (li >= 0) ++cnt[s.off + li + 1];
-    }
-  }
-  m.adj_ptr.assign(m.sum_ns + 1, 0);
-  for (int64_t i = 0; i < m.sum_ns; ++i) m.adj_ptr[i + 1] = m.adj_ptr[i] + cnt[i + 1];
-  m.adj.assign(m.adj_ptr[m.sum_ns], 0);
-  std::vector<int32_t> fill(m.adj_ptr.begin(), m.adj_ptr.end() - 1);
-  for (int64_t e = 0; e < nel; ++e) {
-    const SubHost& s = m.subs[m.el_sub[e]];
-    for (int a = 0; a < m.edof; ++a) {
-      const int li = m.el_ldof[e * m.edof + a];
-      if (li >= 0) m.adj[fill[s.off + li]++] = (int32_t)(e * m.edof + a);
-    }
-  }
+  build_adjacency(m);
   return "";
 }
 

@@ -10,6 +10,9 @@
 
 namespace feti {
 
+// owners of a primal DOF: up to four in 2D, eight at a corner of the 3D subdomain grid
+constexpr int PI_SLOTS = 8;
+
 // Device copies of the mesh and numbering tables (see MeshHost).
 struct DevMesh {
   int nsub = 0, order = 2, ncell = 0, edof = 0, nelem = 0;
@@ -62,9 +65,9 @@ struct DevMesh {
   int32_t *dec_node = nullptr, *dec_ptr = nullptr, *dec_ent = nullptr, *dec_xi = nullptr;
   uint8_t* dec_pdir = nullptr;
   // dual-primal coupling: n_pi primal unknowns, per interface DOF its primal index (-1:
-  // dual), per primal DOF the interface indices of its owners (4 slots, -1 = none), per
+  // dual), per primal DOF the interface indices of its owners (PI_SLOTS slots, -1 = none), per
   // subdomain the number of primal DOFs (the trailing ones of its interface block)
-  int n_pi = 0, max_npi = 0, nsub_x = 1;
+  int n_pi = 0, max_npi = 0, nsub_x = 1, nsub_y = 1;
   int32_t *bpi = nullptr, *pi_own = nullptr, *npi = nullptr;
 };
 
@@ -77,6 +80,14 @@ void launch_assemble(const DevMesh& m, double* K, MatParams mpP, MatParams mpE, 
 void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams mpP, MatParams mpE,
                 const LoadDev& L, hipStream_t st, double* cache = nullptr, int cmode = 0);
 void launch_init_eta(const DevMesh& m, double* u, const LoadDev& L, hipStream_t st);
+// y_i = sum of the element contributions m.ebuf of torn DOF i, in element order
+void launch_gather_elem(const DevMesh& m, double* y, hipStream_t st);
+// d = 3 (kernels_fem3d.hip): K_e of every tetrahedron into m.emat; K_s += K_e in 48
+// colours; the right-hand side of nodal (RAW) data into f
+void launch_elem_store3d(const DevMesh& m, MatParams mpP, MatParams mpE, hipStream_t st);
+void launch_assemble3d(const DevMesh& m, double* K, hipStream_t st);
+void launch_rhs3d(const DevMesh& m, const double* eta_prev, double* f, MatParams mpP, const LoadDev& L,
+                  hipStream_t st);
 // load sampled at the node of every multiplier row (body force of u rows, source of eta, xi_P, p rows)
 void launch_interface_load(const DevMesh& m, const LoadDev& L, double* out, hipStream_t st);
 // y = K x (torn, element by element, overwriting y)

@@ -21,8 +21,8 @@ __global__ void __launch_bounds__(256) k_pi_gather(DevMesh m, const double* __re
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m.n_pi) return;
   double acc = 0.0;
-  for (int e = 0; e < 4; ++e) {
-    const int gb = m.pi_own[4 * k + e];
+  for (int e = 0; e < PI_SLOTS; ++e) {
+    const int gb = m.pi_own[PI_SLOTS * k + e];
     if (gb < 0) break;
     const int64_t ti = m.b_torn[gb];
     double v = 0.0;
@@ -48,26 +48,26 @@ __global__ void __launch_bounds__(256) k_pi_fold(DevMesh m, double* __restrict__
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m.n_pi) return;
   double acc = 0.0;
-  for (int e = 0; e < 4; ++e) {
-    const int gb = m.pi_own[4 * k + e];
+  for (int e = 0; e < PI_SLOTS; ++e) {
+    const int gb = m.pi_own[PI_SLOTS * k + e];
     if (gb < 0) break;
     acc += r[m.b_torn[gb]];
   }
-  for (int e = 0; e < 4; ++e) {
-    const int gb = m.pi_own[4 * k + e];
+  for (int e = 0; e < PI_SLOTS; ++e) {
+    const int gb = m.pi_own[PI_SLOTS * k + e];
     if (gb < 0) break;
     r[m.b_torn[gb]] = e == 0 ? acc : 0.0;
   }
 }
 
 // S[K][L] -= A_s[a][b] over the primal pairs (a, b) of the subdomains of one colour of the
-// 2 x 2 colouring of the subdomain grid (two subdomains of a colour share no node, so each
-// launch writes every entry at most once; the colours run in a fixed order)
+// 2 x 2 (x 2 in 3D) colouring of the subdomain grid (two subdomains of a colour share no
+// node, so each launch writes every entry at most once; the colours run in a fixed order)
 __global__ void __launch_bounds__(256) k_pi_assemble(DevMesh m, const double* __restrict__ A,
                                                      double* __restrict__ S, int colour) {
   const int s = blockIdx.y;
-  const int sx = s % m.nsub_x, sy = s / m.nsub_x;
-  if ((sx & 1) + 2 * (sy & 1) != colour) return;
+  const int sx = s % m.nsub_x, sy = (s / m.nsub_x) % m.nsub_y, sz = s / (m.nsub_x * m.nsub_y);
+  if ((sx & 1) + 2 * (sy & 1) + 4 * (sz & 1) != colour) return;
   const int np = m.npi[s];
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)np * np) return;
@@ -97,7 +97,8 @@ void launch_pi_fold(const DevMesh& m, double* r, hipStream_t st) {
 void launch_pi_assemble(const DevMesh& m, const double* A, double* S, hipStream_t st) {
   if (m.n_pi == 0 || m.max_npi == 0) return;
   const int64_t cnt = (int64_t)m.max_npi * m.max_npi;
-  for (int c = 0; c < 4; ++c)
+  const int ncol = m.nsub > m.nsub_x * m.nsub_y ? 8 : 4;
+  for (int c = 0; c < ncol; ++c)
     hipLaunchKernelGGL(k_pi_assemble, dim3((unsigned)((cnt + 255) / 256), m.nsub), dim3(256), 0, st, m, A, S, c);
 }
 

@@ -413,6 +413,10 @@ void launch_rhs(const DevMesh& m, const double* eta_prev, double* f, MatParams m
   hipLaunchKernelGGL(k_gather_elem, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, m, f);
 }
 
+void launch_gather_elem(const DevMesh& m, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_elem, dim3((unsigned)((m.sum_ns + 255) / 256)), dim3(256), 0, st, m, y);
+}
+
 void launch_init_eta(const DevMesh& m, double* u, const LoadDev& L, hipStream_t st) {
   const int blk = 256;
   const int grid = (int)((m.sum_ns + blk - 1) / blk);

@@ -3,6 +3,8 @@ from __future__ import annotations
 
 from typing import Dict, List
 
+import numpy as np
+
 from . import _binding as B
 
 _LAYOUT = {"xsplit": B.XSPLIT, "ysplit": B.YSPLIT, "core": B.CORE}
@@ -15,7 +17,8 @@ def mesh_args(w) -> Dict:
                 nsub_y=w.nsub_y, dirichlet_u=w.dirichlet_u, dirichlet_p=w.dirichlet_p,
                 cut_x=getattr(w, "cut_x", None), cut_y=getattr(w, "cut_y", None),
                 scheme=B.SCHEME_DECOUPLED if getattr(w, "scheme", "coupled") == "decoupled" else B.SCHEME_COUPLED,
-                coupling=B.COUPLING_PRIMAL if getattr(w, "coupling", "dual") == "primal" else B.COUPLING_DUAL)
+                coupling=B.COUPLING_PRIMAL if getattr(w, "coupling", "dual") == "primal" else B.COUPLING_DUAL,
+                dim=getattr(w, "dim", 2), nsub_z=getattr(w, "nsub_z", 1))
 
 
 def material(m) -> B.Material:
@@ -44,7 +47,9 @@ def load(w, t: float) -> B.Load:
         import torch
         from workloads import raw_arrays
         arrs = raw_arrays(w, t)
-        L.attach_raw({k: torch.tensor(v.ravel(), dtype=torch.float64, device="cuda") for k, v in arrs.items()})
+        # (empty arrays: data the dimension has no place for, passed as NULL)
+        L.attach_raw({k: torch.tensor(v.ravel(), dtype=torch.float64, device="cuda")
+                      for k, v in arrs.items() if np.asarray(v).size > 0})
     return L
 
 

@@ -3,7 +3,7 @@ from __future__ import annotations
 
 import numpy as np
 
-KIND_NAMES = {0: "ux", 1: "uy", 2: "eta", 3: "xiP", 4: "p", 5: "xiE"}
+KIND_NAMES = {0: "ux", 1: "uy", 2: "eta", 3: "xiP", 4: "p", 5: "xiE", 6: "uz"}
 
 
 def require_gpu():
@@ -42,13 +42,13 @@ def torn_reference(codes, sub_offset, sub_poro, lat):
     nodes = codes // 8
     sub_of = np.repeat(np.arange(len(sub_offset) - 1), np.diff(sub_offset))
     poro = np.asarray(sub_poro)[sub_of]
-    for k in range(6):
+    for k in range(7):
         sel = kinds == k
         if not sel.any():
             continue
-        if k < 2:
-            a = lat[("ux_" if k == 0 else "uy_") + "P"]
-            b = lat[("ux_" if k == 0 else "uy_") + "E"]
+        if k < 2 or k == 6:
+            a = lat[KIND_NAMES[k] + "_P"]
+            b = lat[KIND_NAMES[k] + "_E"]
             out[sel] = np.where(poro[sel], a[nodes[sel]], b[nodes[sel]])
         else:
             out[sel] = lat[KIND_NAMES[k]][nodes[sel]]
@@ -59,7 +59,7 @@ def per_kind_rel_error(codes, got, ref):
     """max |got - ref| / max |ref| for each DOF kind present."""
     kinds = codes % 8
     res = {}
-    for k in range(6):
+    for k in range(7):
         sel = kinds == k
         if not sel.any():
             continue

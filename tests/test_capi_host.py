@@ -108,6 +108,26 @@ def test_dual_primal_indexing_bit_exact_against_oracle(w):
     _compare(w)
 
 
+@pytest.mark.parametrize("w", [
+    W.cube_case(ncell=4),
+    W.cube_case(ncell=4, order_u=1, nsub=(2, 1, 3)),
+    W.cube_case(ncell=8, nsub=(4, 2, 2)),
+    W.cube_nearly_incompressible(),
+], ids=lambda w: w.name)
+def test_3d_indexing_bit_exact_against_oracle(w):
+    """d = 3: local orders, jump rows (up to four owners on the grid edges) and the primal
+    order (up to eight owners at the grid corners) against the oracle's statement."""
+    _compare(w)
+
+
+def test_3d_takes_the_dual_primal_coupling_only():
+    f = B.Feti()
+    with pytest.raises(B.FetiError) as e:
+        f.setup_mesh(**mesh_args(W.cube_case(ncell=4).replace(coupling="dual")))
+    assert e.value.code == B.EINVAL
+    f.close()
+
+
 def test_dual_primal_coupling_is_rejected_with_the_decoupled_scheme():
     f = B.Feti()
     with pytest.raises(B.FetiError) as e:
