@@ -113,6 +113,10 @@ struct feti_ctx_s {
   // primal right-hand side and solution, and the local solution of the start
   bool dp = false;
   double *Spinv = nullptr, *cpi = nullptr, *upi = nullptr, *ydp = nullptr;
+  // deflation of the dual-primal iteration: F W (N_lambda x n_defl, column-major), the
+  // inverse of E = W^T F W, and the coarse vectors of one projection
+  double *FW = nullptr, *Edinv = nullptr, *gdef = nullptr, *adef = nullptr;
+  bool defl = false;
   // captured PCG iteration chunks, keyed by the multiplier buffer they update
   struct Graph {
     hipGraphExec_t exec = nullptr;
@@ -280,6 +284,19 @@ int upload_mesh(feti_ctx ctx) {
     RC(dalloc(ctx, &ctx->cpi, std::max(m.n_pi, 1), ctx->allocs));
     RC(dalloc(ctx, &ctx->upi, std::max(m.n_pi, 1), ctx->allocs));
     RC(dalloc(ctx, &ctx->ydp, h.sum_ns, ctx->allocs));
+    m.n_defl = h.n_defl;
+    if (h.n_defl > 0 && !std::getenv("FETI_NO_DEFLATION")) {
+      RC(upload(ctx, &m.defl_col, h.defl_col));
+      RC(upload(ctx, &m.defl_w, h.defl_w));
+      RC(upload(ctx, &m.defl_ptr, h.defl_ptr));
+      RC(upload(ctx, &m.defl_rows, h.defl_rows));
+      RC(upload(ctx, &m.defl_rw, h.defl_rw));
+      RC(dalloc(ctx, &ctx->gdef, h.n_defl, ctx->allocs));
+      RC(dalloc(ctx, &ctx->adef, h.n_defl, ctx->allocs));
+      ctx->defl = true;
+    } else {
+      m.n_defl = 0;
+    }
   }
   m.decoupled = h.desc.scheme == FETI_SCHEME_DECOUPLED ? 1 : 0;
   m.n_dec = (int)h.dec_node.size();
@@ -492,6 +509,25 @@ void op_M(feti_ctx ctx, const double* x, double* y, const int32_t* skip) {
   op_M_raw(ctx, x, y, nullptr, skip);
 }
 
+// Dual-primal deflation: y = z - W E^{-1} (F W)^T z (a search direction F-orthogonal to W).
+void op_defl_dir(feti_ctx ctx, const double* z, double* y, const int32_t* skip) {
+  DevMesh& m = ctx->dm;
+  launch_defl_fwt(m, ctx->FW, z, ctx->gdef, skip, ctx->stream);
+  launch_coarse_apply(m.n_defl, ctx->Edinv, ctx->gdef, ctx->adef, 1.0, skip, ctx->stream);
+  launch_coarse_correct(m, ctx->adef, -1.0, z, y, skip, ctx->stream);
+}
+
+// Dual-primal deflation of a start: v += W E^{-1} W^T (d - F v), so that W^T (d - F v) = 0.
+void op_defl_start(feti_ctx ctx, double* v) {
+  DevMesh& m = ctx->dm;
+  hipStream_t st = ctx->stream;
+  op_F(ctx, v, ctx->q, nullptr);
+  launch_axpby(m.n_lambda, 1.0, ctx->d, -1.0, ctx->q, ctx->r, st);
+  launch_defl_wt(m, ctx->r, ctx->gdef, nullptr, st);
+  launch_coarse_apply(m.n_defl, ctx->Edinv, ctx->gdef, ctx->adef, 1.0, nullptr, st);
+  launch_coarse_correct(m, ctx->adef, 1.0, v, v, nullptr, st);
+}
+
 // Scratch of feti_apply_F_noalloc: the interface-space products y_b of every subdomain,
 // in a file-scope device array (each GPU that loads the library holds its own copy until
 // the process ends).  Host code refers to it only through the per-device address that
@@ -533,7 +569,12 @@ void pcg_iteration(feti_ctx ctx, double* lam, const int32_t* done) {
                 counter(ctx, PH_CONV), ctx->sc, ctx->ist, st);
   op_M_raw(ctx, ctx->w, ctx->z, coarse ? ctx->g : nullptr, done);
   if (coarse) launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, 1.0, done, st);
-  launch_correct_dot(m, coarse ? ctx->ac : nullptr, ctx->z, ctx->y, ctx->w, ctx->part,
+  if (ctx->defl) {
+    // y = z - W E^{-1} (F W)^T z with (w, y) in the same pass
+    launch_defl_fwt(m, ctx->FW, ctx->z, ctx->gdef, done, st);
+    launch_coarse_apply(m.n_defl, ctx->Edinv, ctx->gdef, ctx->adef, 1.0, done, st);
+  }
+  launch_correct_dot(m, coarse ? ctx->ac : (ctx->defl ? ctx->adef : nullptr), ctx->z, ctx->y, ctx->w, ctx->part,
                      counter(ctx, PH_BETA), ctx->sc, ctx->ist, PH_BETA, st);
   launch_cg_p(m.n_lambda, ctx->sc, ctx->ist, ctx->y, ctx->p, st);
 }
@@ -598,8 +639,10 @@ int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
     launch_jump(m, ctx->ytmp, 1, ctx->d, 0, nullptr, nullptr, st);
     if (cj) launch_axpby(nl, 1.0, ctx->d, -1.0, cj, ctx->d, st);
   }
-  // admissible start: lambda += G (G^T G)^{-1} (e - G^T lambda)
+  // admissible start: lambda += G (G^T G)^{-1} (e - G^T lambda) (dual-primal: the
+  // deflated component of the residual taken exactly)
   auto admissible = [&](double* v) {
+    if (ctx->defl) { op_defl_start(ctx, v); return; }
     if (ctx->nc == 0) return;
     launch_coarse_g(m, v, f, -1.0, ctx->g, nullptr, st);
     launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, 1.0, nullptr, st);
@@ -660,12 +703,13 @@ int torn_begin(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
   op_project(ctx, ctx->d, ctx->tl, nullptr);
   launch_reduce(m, nullptr, nullptr, ctx->tl, ctx->mdiag, ctx->part, counter(ctx, PH_REFNORM), ctx->sc,
                 ctx->ist, PH_REFNORM, st);
-  // r = d - F lambda; w = P r; y = P M^{-1} w; p = y
+  // r = d - F lambda; w = P r; y = P M^{-1} w; p = y (dual-primal: y the deflated direction)
   op_F(ctx, lam, ctx->q, nullptr);
   launch_axpby(nl, 1.0, ctx->d, -1.0, ctx->q, ctx->r, st);
   op_project(ctx, ctx->r, ctx->w, nullptr);
   op_M(ctx, ctx->w, ctx->z, nullptr);
-  op_project(ctx, ctx->z, ctx->y, nullptr);
+  if (ctx->defl) op_defl_dir(ctx, ctx->z, ctx->y, nullptr);
+  else op_project(ctx, ctx->z, ctx->y, nullptr);
   launch_axpby(nl, 1.0, ctx->y, 0.0, nullptr, ctx->p, st);
   launch_reduce(m, ctx->w, ctx->y, ctx->w, ctx->mdiag, ctx->part, counter(ctx, PH_INIT), ctx->sc,
                 ctx->ist, PH_INIT, st);
@@ -1421,6 +1465,34 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
     HIPCHK(hipStreamSynchronize(st));
     for (void* p : ctmp) (void)hipFree(p);
     if (cs) return fail(ctx, FETI_ESINGULAR, "zero or non-finite pivot in the primal coarse matrix");
+  }
+  // deflation of the dual-primal iteration: F W column by column and E = W^T F W, inverted
+  if (ctx->defl) {
+    const int nd = m.n_defl;
+    const int64_t nl = m.n_lambda;
+    if (!ctx->FW) RC(dalloc(ctx, &ctx->FW, (size_t)nl * nd, ctx->mat_allocs));
+    if (!ctx->Edinv) RC(dalloc(ctx, &ctx->Edinv, (size_t)nd * nd, ctx->mat_allocs));
+    for (int c = 0; c < nd; ++c) {
+      launch_defl_column(m, c, ctx->tl, st);
+      op_F(ctx, ctx->tl, ctx->FW + (size_t)c * nl, nullptr);
+    }
+    launch_defl_gram(m, ctx->FW, ctx->Edinv, st);
+    GJPlan C;
+    std::vector<int32_t> cflag;
+    std::vector<void*> ctmp;
+    rc = build_gj_plan(ctx, C, cflag, 1, {nd}, {0}, {nd}, {0}, {nd}, {-1}, {nd}, GJ_PANEL, ctmp);
+    if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
+    for (int s = 0; s < C.nsteps; ++s) launch_gj_step(C, ctx->Edinv, (double*)nullptr, s, false, st);
+    int32_t* d_nd = nullptr;
+    std::vector<int32_t> ndv{nd};
+    rc = upload(ctx, &d_nd, ndv);
+    if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
+    launch_gj_finalize(C, ctx->Edinv, d_nd, st);
+    int32_t cs = 0;
+    HIPCHK(hipMemcpyAsync(&cs, C.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (void* p : ctmp) (void)hipFree(p);
+    if (cs) return fail(ctx, FETI_ESINGULAR, "singular deflation matrix W^T F W");
   }
   // coarse matrix G^T G and its inverse
   const int nc = ctx->nc;

@@ -93,7 +93,16 @@ struct MeshHost {
   // interface indices of its owners (PI_OWNERS slots, -1 = none)
   int n_pi = 0, n_pi_u = 0;
   std::vector<int32_t> pi_code, bpi, pi_own;
+  // dual-primal coupling: the normal-flux vectors that deflate the interface iteration, one
+  // per pair of subdomains sharing a face (an edge in 2D): per multiplier row its column
+  // (-1: none) and weight, and per column its rows (CSR)
+  int n_defl = 0;
+  std::vector<int32_t> defl_col, defl_ptr, defl_rows;
+  std::vector<double> defl_w, defl_rw;
 };
+
+// Builds the deflation vectors of the dual-primal coupling (after the jump rows).
+void build_deflation(MeshHost& m);
 
 // Builds every host-side table from the mesh description (the numbering that
 // the exported indexing documents).  Returns an error string on failure.

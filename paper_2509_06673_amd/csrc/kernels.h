@@ -69,6 +69,12 @@ struct DevMesh {
   // subdomain the number of primal DOFs (the trailing ones of its interface block)
   int n_pi = 0, max_npi = 0, nsub_x = 1, nsub_y = 1;
   int32_t *bpi = nullptr, *pi_own = nullptr, *npi = nullptr;
+  // dual-primal coupling: the n_defl normal-flux vectors W that deflate the iteration; per
+  // multiplier row its column (-1: none) and weight, per column its rows (CSR).  With
+  // defl_col set, the coarse rows (G a)_j of the interface kernels are (W a)_j.
+  int n_defl = 0;
+  int32_t *defl_col = nullptr, *defl_ptr = nullptr, *defl_rows = nullptr;
+  double *defl_w = nullptr, *defl_rw = nullptr;
 };
 
 // assembly / right-hand side (kernels_fem.hip)
@@ -207,5 +213,12 @@ void launch_pi_scatter(const DevMesh& m, const double* upi, double* u, hipStream
 void launch_pi_fold(const DevMesh& m, double* r, hipStream_t st);
 // S (n_pi x n_pi, row-major) -= the primal blocks of the compact interface blocks A
 void launch_pi_assemble(const DevMesh& m, const double* A, double* S, hipStream_t st);
+// deflation (normal-flux vectors W, n_defl columns): out = column c of W (length N_lambda);
+// g = W^T v; g = (F W)^T z with FW column-major (N_lambda x n_defl); E = W^T FW symmetrised
+void launch_defl_column(const DevMesh& m, int c, double* out, hipStream_t st);
+void launch_defl_wt(const DevMesh& m, const double* v, double* g, const int32_t* skip, hipStream_t st);
+void launch_defl_fwt(const DevMesh& m, const double* FW, const double* z, double* g, const int32_t* skip,
+                     hipStream_t st);
+void launch_defl_gram(const DevMesh& m, const double* FW, double* E, hipStream_t st);
 
 }  // namespace feti

@@ -78,6 +78,89 @@ __global__ void __launch_bounds__(256) k_pi_assemble(DevMesh m, const double* __
   S[(int64_t)K * m.n_pi + L] -= A[m.sofs[s] + (int64_t)(base + a) * m.ldb[s] + base + b];
 }
 
+// ---- deflation by the normal-flux vectors ----------------------------------------
+// The interface operator of the dual-primal coupling keeps, as nu -> 1/2, an eigenvalue
+// near zero whose eigenvector is the uniform normal traction on the subdomain faces (the
+// hydrostatic pressure mode).  The iteration is deflated by W = one vector per face, the
+// face integrals of the normal-component basis functions (q^T B u = the integral of the
+// jump of the normal displacement over the face): the start takes the W-component of the
+// residual exactly, and every search direction is made F-orthogonal to W.
+
+__global__ void __launch_bounds__(256) k_defl_column(DevMesh m, int c, double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m.n_lambda) return;
+  out[j] = m.defl_col[j] == c ? m.defl_w[j] : 0.0;
+}
+
+__device__ inline double block_sum256(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// g_c = sum over the rows j of column c of w_j v_j (one block per column, fixed order)
+__global__ void __launch_bounds__(256) k_defl_wt(DevMesh m, const double* __restrict__ v, double* __restrict__ g,
+                                                 const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  double acc = 0.0;
+  for (int k = m.defl_ptr[c] + threadIdx.x; k < m.defl_ptr[c + 1]; k += 256) acc += m.defl_rw[k] * v[m.defl_rows[k]];
+  const double s = block_sum256(acc, red);
+  if (threadIdx.x == 0) g[c] = s;
+}
+
+// g_c = sum_j FW[c][j] z_j (column c of F W, contiguous)
+__global__ void __launch_bounds__(256) k_defl_fwt(DevMesh m, const double* __restrict__ FW, const double* __restrict__ z,
+                                                  double* __restrict__ g, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  const double* col = FW + (int64_t)c * m.n_lambda;
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j < m.n_lambda; j += 256) acc += col[j] * z[j];
+  const double s = block_sum256(acc, red);
+  if (threadIdx.x == 0) g[c] = s;
+}
+
+// E[c][d] = (W^T F W)_{cd} symmetrised: (sum over the rows of c of w_j FW[d][j] + the same
+// with c and d exchanged) / 2 (one block per entry)
+__global__ void __launch_bounds__(256) k_defl_gram(DevMesh m, const double* __restrict__ FW, double* __restrict__ E) {
+  __shared__ double red[256];
+  const int c = blockIdx.x, d = blockIdx.y, n = m.n_defl;
+  double acc = 0.0;
+  for (int k = m.defl_ptr[c] + threadIdx.x; k < m.defl_ptr[c + 1]; k += 256)
+    acc += m.defl_rw[k] * FW[(int64_t)d * m.n_lambda + m.defl_rows[k]];
+  for (int k = m.defl_ptr[d] + threadIdx.x; k < m.defl_ptr[d + 1]; k += 256)
+    acc += m.defl_rw[k] * FW[(int64_t)c * m.n_lambda + m.defl_rows[k]];
+  const double s = block_sum256(acc, red);
+  if (threadIdx.x == 0) E[(int64_t)c * n + d] = 0.5 * s;
+}
+
+void launch_defl_column(const DevMesh& m, int c, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_defl_column, dim3((unsigned)((m.n_lambda + 255) / 256)), dim3(256), 0, st, m, c, out);
+}
+
+void launch_defl_wt(const DevMesh& m, const double* v, double* g, const int32_t* skip, hipStream_t st) {
+  if (m.n_defl == 0) return;
+  hipLaunchKernelGGL(k_defl_wt, dim3(m.n_defl), dim3(256), 0, st, m, v, g, skip);
+}
+
+void launch_defl_fwt(const DevMesh& m, const double* FW, const double* z, double* g, const int32_t* skip,
+                     hipStream_t st) {
+  if (m.n_defl == 0) return;
+  hipLaunchKernelGGL(k_defl_fwt, dim3(m.n_defl), dim3(256), 0, st, m, FW, z, g, skip);
+}
+
+void launch_defl_gram(const DevMesh& m, const double* FW, double* E, hipStream_t st) {
+  if (m.n_defl == 0) return;
+  hipLaunchKernelGGL(k_defl_gram, dim3(m.n_defl, m.n_defl), dim3(256), 0, st, m, FW, E);
+}
+
 void launch_pi_gather(const DevMesh& m, const double* t1, const double* t2, const double* yb, double cy, double* out,
                       const int32_t* skip, hipStream_t st) {
   if (m.n_pi == 0) return;
