@@ -261,6 +261,20 @@ int feti_export_indexing(feti_ctx ctx, int32_t* local_code_host, int32_t* sub_of
  * subdomain, which are the trailing ones of its interface block.  Either may be NULL. */
 int feti_export_primal(feti_ctx ctx, int32_t* primal_code_host, int32_t* sub_npi_host);
 
+/* Dual-primal coupling: the normal-flux vectors that deflate the interface iteration, one
+ * per pair of subdomains sharing a face (an edge in 2D).  Column c holds, on each
+ * multiplier row of that pair whose DOF is the displacement component normal to the
+ * face, the integral over the face of that node's basis function in units of the element
+ * size (h in 2D, the face triangle area h^2 / 2 in 3D), so that q_c^T B u is the integral
+ * of the jump of u . n across the face (sign of the rows).  The start of a solve takes the
+ * residual's component in their span exactly, and every search direction is made
+ * F-orthogonal to them.  A row belongs to at most two columns (a row of a 3D grid edge,
+ * where the jump between two face neighbours is the sum of chained rows):
+ * col_host[2 * N_lambda] and w_host[2 * N_lambda] hold two (column, weight) slots per row
+ * (column -1: unused); n_defl_host receives the number of columns.  Any pointer may be
+ * NULL. */
+int feti_export_deflation(feti_ctx ctx, int32_t* col_host, double* w_host, int32_t* n_defl_host);
+
 /* Element-parallel assembly of every dense local matrix K_s (rows 1-4 or 5-6
  * of eq. (linalg-system) restricted to the subdomain's elements, Dirichlet
  * DOFs removed).  tau is the time step. */

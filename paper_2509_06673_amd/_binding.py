@@ -123,6 +123,7 @@ _SIGS = {
                              C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                              C.POINTER(C.c_int8)],
     "feti_export_primal": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "feti_export_deflation": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "feti_assemble": [C.c_void_p, C.POINTER(Material), C.POINTER(Material), C.c_double],
     "feti_factor_subdomains": [C.c_void_p, C.c_int32, C.c_int32],
     "feti_init_state": [C.c_void_p, C.POINTER(Load)],
@@ -275,6 +276,19 @@ class Feti:
                     "feti_export_indexing")
         return dict(code=code, sub_offset=off, sub_nb=nb, brow_sub=bs, brow_local=bl, brow_sign=sg)
 
+
+    def export_deflation(self):
+        """Dual-primal coupling: per multiplier row two (deflation column, weight) slots (column
+        -1: unused), and the number of columns."""
+        import numpy as np
+        nl = self.get_sizes()["n_lambda"]
+        col = np.zeros(max(2 * nl, 1), np.int32)
+        w = np.zeros(max(2 * nl, 1), np.float64)
+        nd = C.c_int32(0)
+        self._check(self.lib.feti_export_deflation(self.ctx, col.ctypes.data_as(C.c_void_p),
+                                                   w.ctypes.data_as(C.c_void_p), C.byref(nd)),
+                    "feti_export_deflation")
+        return {"col": col[:2 * nl].reshape(nl, 2), "w": w[:2 * nl].reshape(nl, 2), "n_defl": int(nd.value)}
 
     def export_primal(self):
         """Dual-primal coupling: the primal codes in global order and the number of primal

@@ -1268,6 +1268,19 @@ int feti_export_primal(feti_ctx ctx, int32_t* pi_code, int32_t* sub_npi) {
   return FETI_OK;
 }
 
+int feti_export_deflation(feti_ctx ctx, int32_t* col, double* w, int32_t* n_defl) {
+  if (!ctx) return FETI_EINVAL;
+  if (ctx->state < 1) return fail(ctx, FETI_ESTATE, "no mesh");
+  const MeshHost& h = ctx->mh;
+  const bool have = !h.defl_col.empty();
+  for (int64_t j = 0; j < 2 * h.n_lambda; ++j) {
+    if (col) col[j] = have ? h.defl_col[j] : -1;
+    if (w) w[j] = have ? h.defl_w[j] : 0.0;
+  }
+  if (n_defl) *n_defl = h.n_defl;
+  return FETI_OK;
+}
+
 int feti_assemble(feti_ctx ctx, const feti_material* P, const feti_material* E, double tau) {
   if (!ctx || !P || !E) return FETI_EINVAL;
   if (ctx->state < 1) return fail(ctx, FETI_ESTATE, "assemble before setup_mesh");

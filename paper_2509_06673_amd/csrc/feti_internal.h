@@ -94,8 +94,8 @@ struct MeshHost {
   int n_pi = 0, n_pi_u = 0;
   std::vector<int32_t> pi_code, bpi, pi_own;
   // dual-primal coupling: the normal-flux vectors that deflate the interface iteration, one
-  // per pair of subdomains sharing a face (an edge in 2D): per multiplier row its column
-  // (-1: none) and weight, and per column its rows (CSR)
+  // per pair of subdomains sharing a face (an edge in 2D): per multiplier row two (column,
+  // weight) slots (column -1: unused), and per column its rows and weights (CSR)
   int n_defl = 0;
   std::vector<int32_t> defl_col, defl_ptr, defl_rows;
   std::vector<double> defl_w, defl_rw;

@@ -447,19 +447,22 @@ std::string build_mesh3d(const feti_mesh_desc& d, MeshHost& m) {
   return "";
 }
 
-// Normal-flux vectors of the dual-primal coupling.  For a pair of subdomains that share a
-// face (2D: an edge) the vector q has, on every multiplier row of that pair whose DOF is
-// the displacement component normal to the face, the integral over the face of that node's
-// P_k basis function; q^T B u is then the integral of the jump of the normal displacement
-// across the face.  Face integrals per node are summed over the face's element sides (2D:
-// segments, h/6 at the ends and 2h/3 at the midpoint for P2, h/2 at each end for P1) or
-// triangles (3D: each cube face split along the diagonal from its low to its high corner;
-// P2: 0 at the vertices and |t|/3 at the edge midpoints, P1: |t|/3 at the vertices), in
-// units of the element size.
+// Normal-flux vectors of the dual-primal coupling.  For a pair of subdomains A < B that
+// share a face (2D: an edge) the vector q has the entries that make q^T B u the integral
+// over the face of the jump u_A . n - u_B . n (with the sign of the pair's rows) for the
+// finite element u: every non-primal face node whose normal displacement component is a
+// dual DOF contributes the face integral of its basis function, on the row between A and
+// B, or, at a node with four owners (a 3D grid edge, multipliers chained in increasing
+// subdomain order), on each chain row between A and B (the jump u_A - u_B is their sum).
+// Face integrals per node are summed over the face's element sides (2D: segments, h/6 at
+// the ends and 2h/3 at the midpoint for P2, h/2 at each end for P1) or triangles (3D:
+// each cube face split along the diagonal from its low to its high corner; P2: 0 at the
+// vertices and |t|/3 at the edge midpoints, P1: |t|/3 at the vertices), in units of the
+// element size.  A row takes part in at most two vectors.
 void build_deflation(MeshHost& m) {
   m.n_defl = 0;
-  m.defl_col.assign(m.n_lambda, -1);
-  m.defl_w.assign(m.n_lambda, 0.0);
+  m.defl_col.assign(2 * m.n_lambda, -1);
+  m.defl_w.assign(2 * m.n_lambda, 0.0);
   m.defl_ptr.assign(1, 0);
   m.defl_rows.clear();
   m.defl_rw.clear();
@@ -473,14 +476,16 @@ void build_deflation(MeshHost& m) {
     g[1] = d3 ? (sid / nsx) % nsy : sid / nsx;
     g[2] = d3 ? sid / (nsx * nsy) : 0;
   };
+  // first row of every multiplier code (its chain rows follow in pair order)
+  std::unordered_map<int32_t, int64_t> first_row;
+  for (int64_t j = 0; j < m.n_lambda; ++j) first_row.emplace(m.rows[j].code, j);
+  // the face pairs, in the order of their first normal-component row
   std::map<std::pair<int, int>, int> col_of;
   std::vector<std::pair<int, int>> pairs;
   std::vector<int> axis_of;
-  std::vector<std::unordered_map<int64_t, double>> wmap;
   for (int64_t j = 0; j < m.n_lambda; ++j) {
     const JumpRow& jr = m.rows[j];
-    const int kind = jr.kind;
-    const int comp = kind == K_UX ? 0 : kind == K_UY ? 1 : kind == K_UZ ? 2 : -1;
+    const int comp = jr.kind == K_UX ? 0 : jr.kind == K_UY ? 1 : jr.kind == K_UZ ? 2 : -1;
     if (comp < 0) continue;
     int g1[3], g2[3];
     grid(jr.sub[0], g1);
@@ -490,81 +495,88 @@ void build_deflation(MeshHost& m) {
       if (g1[q] != g2[q]) { ++ndiff; axis = q; }
     if (ndiff != 1 || comp != axis) continue;
     const std::pair<int, int> key(std::min(jr.sub[0], jr.sub[1]), std::max(jr.sub[0], jr.sub[1]));
-    auto it = col_of.find(key);
-    int c;
-    if (it == col_of.end()) {
-      c = (int)pairs.size();
-      col_of[key] = c;
+    if (col_of.emplace(key, (int)pairs.size()).second) {
       pairs.push_back(key);
       axis_of.push_back(axis);
-      // the face: the common boundary of the two cell blocks, in displacement-lattice units
-      const SubHost& A = m.subs[key.first];
-      const SubHost& Bs = m.subs[key.second];
-      const int lo[3] = {r * std::max(A.i0, Bs.i0), r * std::max(A.j0, Bs.j0), r * std::max(A.k0, Bs.k0)};
-      const int hi[3] = {r * std::min(A.i1, Bs.i1), r * std::min(A.j1, Bs.j1), r * std::min(A.k1, Bs.k1)};
-      std::unordered_map<int64_t, double> wm;
-      auto node_id = [&](const int* x) { return ((int64_t)x[2] * mu + x[1]) * mu + x[0]; };
-      if (!d3) {
-        const int t = 1 - axis;  // direction along the edge
-        for (int e = lo[t]; e < hi[t]; e += r) {
-          int x0[3] = {lo[0], lo[1], 0}, x1[3] = {lo[0], lo[1], 0};
-          x0[t] = e;
-          x1[t] = e + r;
-          if (r == 2) {
-            int xm[3] = {lo[0], lo[1], 0};
-            xm[t] = e + 1;
-            wm[node_id(x0)] += 1.0 / 6.0;
-            wm[node_id(x1)] += 1.0 / 6.0;
-            wm[node_id(xm)] += 2.0 / 3.0;
-          } else {
-            wm[node_id(x0)] += 0.5;
-            wm[node_id(x1)] += 0.5;
-          }
-        }
-      } else {
-        const int p = axis == 0 ? 1 : 0, q = axis == 2 ? 1 : 2;  // in-plane directions, p < q
-        for (int a = lo[p]; a < hi[p]; a += r)
-          for (int b = lo[q]; b < hi[q]; b += r) {
-            // triangles (0,0)-(1,0)-(1,1) and (0,0)-(0,1)-(1,1) of the square, in (p, q)
-            const int tri[2][3][2] = {{{0, 0}, {1, 0}, {1, 1}}, {{0, 0}, {0, 1}, {1, 1}}};
-            for (int t = 0; t < 2; ++t) {
-              auto put = [&](int up, int uq, double wv) {  // lattice offsets in units of r / 2
-                int x[3] = {lo[0], lo[1], lo[2]};
-                x[p] = a + up;
-                x[q] = b + uq;
-                wm[node_id(x)] += wv;
-              };
-              for (int v = 0; v < 3; ++v) {
-                if (r == 1) put(tri[t][v][0], tri[t][v][1], 1.0 / 3.0);
-                else {
-                  const int w2 = (v + 1) % 3;
-                  put(tri[t][v][0] + tri[t][w2][0], tri[t][v][1] + tri[t][w2][1], 1.0 / 3.0);  // edge midpoint
-                }
-              }
-            }
-          }
-      }
-      wmap.push_back(std::move(wm));
-    } else {
-      c = it->second;
-    }
-    const auto wit = wmap[c].find(jr.code / 8);
-    const double wv = wit == wmap[c].end() ? 0.0 : wit->second;
-    if (wv != 0.0) {
-      m.defl_col[j] = c;
-      m.defl_w[j] = wv;
     }
   }
   m.n_defl = (int)pairs.size();
-  std::vector<std::vector<int32_t>> rows_of(m.n_defl);
-  for (int64_t j = 0; j < m.n_lambda; ++j)
-    if (m.defl_col[j] >= 0) rows_of[m.defl_col[j]].push_back((int32_t)j);
+  std::vector<std::vector<std::pair<int32_t, double>>> entries(m.n_defl);
+  for (int c = 0; c < m.n_defl; ++c) {
+    const int sA = pairs[c].first, sB = pairs[c].second, axis = axis_of[c];
+    const int kind = axis == 0 ? K_UX : axis == 1 ? K_UY : K_UZ;
+    const SubHost& A = m.subs[sA];
+    const SubHost& Bs = m.subs[sB];
+    const int lo[3] = {r * std::max(A.i0, Bs.i0), r * std::max(A.j0, Bs.j0), r * std::max(A.k0, Bs.k0)};
+    const int hi[3] = {r * std::min(A.i1, Bs.i1), r * std::min(A.j1, Bs.j1), r * std::min(A.k1, Bs.k1)};
+    std::map<int64_t, double> wm;  // node -> face integral (ordered: a fixed entry order)
+    auto node_id = [&](const int* x) { return ((int64_t)x[2] * mu + x[1]) * mu + x[0]; };
+    if (!d3) {
+      const int t = 1 - axis;
+      for (int e = lo[t]; e < hi[t]; e += r) {
+        int x0[3] = {lo[0], lo[1], 0}, x1[3] = {lo[0], lo[1], 0};
+        x0[t] = e;
+        x1[t] = e + r;
+        if (r == 2) {
+          int xm[3] = {lo[0], lo[1], 0};
+          xm[t] = e + 1;
+          wm[node_id(x0)] += 1.0 / 6.0;
+          wm[node_id(x1)] += 1.0 / 6.0;
+          wm[node_id(xm)] += 2.0 / 3.0;
+        } else {
+          wm[node_id(x0)] += 0.5;
+          wm[node_id(x1)] += 0.5;
+        }
+      }
+    } else {
+      const int p = axis == 0 ? 1 : 0, q = axis == 2 ? 1 : 2;  // in-plane directions
+      const int tri[2][3][2] = {{{0, 0}, {1, 0}, {1, 1}}, {{0, 0}, {0, 1}, {1, 1}}};
+      for (int a = lo[p]; a < hi[p]; a += r)
+        for (int b = lo[q]; b < hi[q]; b += r)
+          for (int t = 0; t < 2; ++t)
+            for (int v = 0; v < 3; ++v) {
+              int x[3] = {lo[0], lo[1], lo[2]};
+              if (r == 1) {
+                x[p] = a + tri[t][v][0];
+                x[q] = b + tri[t][v][1];
+              } else {  // the midpoint of the triangle's edge (v, v + 1)
+                const int w2 = (v + 1) % 3;
+                x[p] = a + tri[t][v][0] + tri[t][w2][0];
+                x[q] = b + tri[t][v][1] + tri[t][w2][1];
+              }
+              wm[node_id(x)] += 1.0 / 3.0;
+            }
+    }
+    for (const auto& kv : wm) {
+      const int32_t code = (int32_t)(8 * kv.first + kind);
+      const auto it = first_row.find(code);
+      if (it == first_row.end()) continue;  // primal, Dirichlet or not shared
+      const int64_t j0 = it->second;
+      // the chain: owners S[0] < S[1] < ..., row j0 + k between S[k] and S[k + 1]
+      std::vector<int> S{m.rows[j0].sub[0]};
+      for (int64_t j = j0; j < m.n_lambda && m.rows[j].code == code; ++j) S.push_back(m.rows[j].sub[1]);
+      const int ia = (int)(std::find(S.begin(), S.end(), sA) - S.begin());
+      const int ib = (int)(std::find(S.begin(), S.end(), sB) - S.begin());
+      if (ia >= (int)S.size() || ib >= (int)S.size()) continue;
+      // orientation: the sign that the pair's own rows put on A (a P-E pair puts +1 on P)
+      const double sigA = (m.subs[sA].poro != m.subs[sB].poro && !m.subs[sA].poro) ? -1.0 : 1.0;
+      for (int k = ia; k < ib; ++k) {
+        const int64_t jk = j0 + k;
+        const double sgk = m.rows[jk].sign[0];  // sign on S[k]: row = sgk (u_S[k] - u_S[k+1])
+        entries[c].push_back({(int32_t)jk, kv.second * sigA / sgk});
+      }
+    }
+  }
   m.defl_ptr.assign(m.n_defl + 1, 0);
   for (int c = 0; c < m.n_defl; ++c) {
-    m.defl_ptr[c + 1] = m.defl_ptr[c] + (int32_t)rows_of[c].size();
-    for (int32_t j : rows_of[c]) {
-      m.defl_rows.push_back(j);
-      m.defl_rw.push_back(m.defl_w[j]);
+    m.defl_ptr[c + 1] = m.defl_ptr[c] + (int32_t)entries[c].size();
+    for (const auto& e : entries[c]) {
+      m.defl_rows.push_back(e.first);
+      m.defl_rw.push_back(e.second);
+      const int64_t j = e.first;
+      const int slot = m.defl_col[2 * j] < 0 ? 0 : 1;
+      m.defl_col[2 * j + slot] = c;
+      m.defl_w[2 * j + slot] = e.second;
     }
   }
 }

@@ -104,8 +104,12 @@ __device__ inline double jump_row(const DevMesh& m, const double* __restrict__ y
 
 __device__ inline double coarse_G_row(const DevMesh& m, const double* __restrict__ a, int64_t j) {
   if (m.defl_col) {  // dual-primal coupling: the deflation vectors take the place of G
-    const int c = m.defl_col[j];
-    return c >= 0 ? m.defl_w[j] * a[c] : 0.0;
+    double v = 0.0;
+    for (int e = 0; e < 2; ++e) {
+      const int c = m.defl_col[2 * j + e];
+      if (c >= 0) v += m.defl_w[2 * j + e] * a[c];
+    }
+    return v;
   }
   double s = 0.0;
 #pragma unroll

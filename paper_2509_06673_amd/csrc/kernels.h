@@ -70,8 +70,9 @@ struct DevMesh {
   int n_pi = 0, max_npi = 0, nsub_x = 1, nsub_y = 1;
   int32_t *bpi = nullptr, *pi_own = nullptr, *npi = nullptr;
   // dual-primal coupling: the n_defl normal-flux vectors W that deflate the iteration; per
-  // multiplier row its column (-1: none) and weight, per column its rows (CSR).  With
-  // defl_col set, the coarse rows (G a)_j of the interface kernels are (W a)_j.
+  // multiplier row two (column, weight) slots (column -1: unused), per column its rows and
+  // weights (CSR).  With defl_col set, the coarse rows (G a)_j of the interface kernels are
+  // (W a)_j.
   int n_defl = 0;
   int32_t *defl_col = nullptr, *defl_ptr = nullptr, *defl_rows = nullptr;
   double *defl_w = nullptr, *defl_rw = nullptr;

@@ -89,7 +89,10 @@ __global__ void __launch_bounds__(256) k_pi_assemble(DevMesh m, const double* __
 __global__ void __launch_bounds__(256) k_defl_column(DevMesh m, int c, double* __restrict__ out) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m.n_lambda) return;
-  out[j] = m.defl_col[j] == c ? m.defl_w[j] : 0.0;
+  double v = 0.0;
+  for (int e = 0; e < 2; ++e)
+    if (m.defl_col[2 * j + e] == c) v += m.defl_w[2 * j + e];
+  out[j] = v;
 }
 
 __device__ inline double block_sum256(double v, double* red) {

@@ -120,6 +120,106 @@ def test_3d_indexing_bit_exact_against_oracle(w):
     _compare(w)
 
 
+@pytest.mark.parametrize("w", [
+    W.nearly_incompressible_scaled(16, 4).replace(coupling="primal", dirichlet_u=0),
+    W.nearly_incompressible_scaled(12, 4).replace(coupling="primal", order_u=1, nsub_y=3, dirichlet_u=0),
+    W.nearly_incompressible_scaled(24, 4).replace(coupling="primal", cut_x=(0, 5, 12, 20, 24), dirichlet_u=0),
+    W.cube_case(ncell=4).replace(dirichlet_u=0),
+    W.cube_case(ncell=8, nsub=(4, 2, 2)).replace(dirichlet_u=0),
+    W.cube_case(ncell=6, nsub=(2, 3, 2)).replace(dirichlet_u=0),
+], ids=lambda w: w.name + ("_primal" if w.dim == 2 else ""))
+def test_deflation_vectors_integrate_the_normal_jump(w):
+    """q_c^T B u is the integral over face c of the jump of u . n (sign of the pair's rows),
+    for displacements that are a different quadratic polynomial in every subdomain (linear
+    for P1), reproduced exactly by the nodal values: checked against the analytic face
+    integrals.  Without displacement Dirichlet data every face node is a dual unknown but
+    the primal grid corners; those carry no multiplier (their jump vanishes in the
+    dual-primal coupling), so their share of the integral is taken off (2D: h/6 at each end
+    of an edge for P2, h/2 for P1; 3D P2: the corners are triangle vertices, whose P2 basis
+    functions integrate to zero over the face)."""
+    f = B.Feti()
+    f.setup_mesh(**mesh_args(w))
+    dfl = f.export_deflation()
+    spec = ix.build(w)
+    d3 = w.dim == 3
+    n, r = w.ncell, (2 if w.order_u == 2 else 1)
+    mu = r * n + 1
+    rng = np.random.default_rng(5)
+    quad = w.order_u == 2
+    coef = rng.standard_normal((len(spec.subs), 3, 10))
+
+    def u_of(s, c, x):
+        a = coef[s, c]
+        v = a[0] + a[1] * x[0] + a[2] * x[1] + a[3] * x[2]
+        if quad:
+            v = v + a[4] * x[0] ** 2 + a[5] * x[1] ** 2 + a[6] * x[2] ** 2 + a[7] * x[0] * x[1] + \
+                a[8] * x[0] * x[2] + a[9] * x[1] * x[2]
+        return v
+    comp_of = {0: 0, 1: 1, 6: 2}
+    rows = spec.rows
+    jump = np.zeros(spec.n_lambda)
+    for j, (row, code) in enumerate(zip(rows, spec.row_code)):
+        node, kind = int(code) // 8, int(code) % 8
+        if kind not in comp_of:
+            continue
+        x = np.array([node % mu, (node // mu) % mu if d3 else node // mu, node // (mu * mu) if d3 else 0]) / float(r * n)
+        jump[j] = sum(sg * u_of(s, comp_of[kind], x) for s, _, sg in row)
+    cols, wts, nd = dfl["col"], dfl["w"], dfl["n_defl"]
+    assert nd > 0 and cols.max() == nd - 1
+    unit = (1.0 / n) if not d3 else 0.5 / n ** 2
+    got = np.zeros(nd)
+    for slot in range(2):
+        sel = cols[:, slot] >= 0
+        np.add.at(got, cols[sel, slot], wts[sel, slot] * jump[sel] * unit)
+    g, gw = np.polynomial.legendre.leggauss(4)
+    seen = set()
+    nsx, nsy = w.nsub_x, w.nsub_y
+
+    def grid(sid):
+        return (sid % nsx, (sid // nsx) % nsy, sid // (nsx * nsy)) if d3 else (sid % nsx, sid // nsx, 0)
+
+    def own_pair(j):
+        # a row of the face pair itself: the two subdomains differ along the row's component axis only
+        (a, _, _), (b, _, _) = rows[j]
+        axis = comp_of[int(spec.row_code[j]) % 8]
+        diff = [q for q in range(3) if grid(a)[q] != grid(b)[q]]
+        return diff == [axis]
+    for c in range(nd):
+        js = np.nonzero((cols == c).any(axis=1))[0]
+        direct = [j for j in js if own_pair(j)]
+        (s1, _, g1), (s2, _, g2) = rows[direct[0]]
+        seen.add((min(s1, s2), max(s1, s2)))
+        axis = comp_of[int(spec.row_code[direct[0]]) % 8]
+        A, Bs = spec.subs[s1], spec.subs[s2]
+        lo = [max(A.i0, Bs.i0), max(A.j0, Bs.j0), max(A.k0, Bs.k0)]
+        hi = [min(A.i1, Bs.i1), min(A.j1, Bs.j1), min(A.k1, Bs.k1)]
+        inpl = [q for q in range(3 if d3 else 2) if q != axis]
+        grids = [((hi[q] - lo[q]) / n * 0.5 * (g + 1) + lo[q] / n, (hi[q] - lo[q]) / n * 0.5 * gw) for q in inpl]
+        pts = np.meshgrid(*[gq for gq, _ in grids], indexing="ij")
+        wq = np.ones_like(pts[0])
+        for k, (_, gwk) in enumerate(grids):
+            shape = [1] * len(grids)
+            shape[k] = -1
+            wq = wq * gwk.reshape(shape)
+        x = [None, None, None]
+        x[axis] = np.full(pts[0].shape, lo[axis] / n)
+        for k, q in enumerate(inpl):
+            x[q] = pts[k]
+        if not d3:
+            x[2] = np.zeros(pts[0].shape)
+        exp = np.sum(wq * (g1 * u_of(s1, axis, x) + g2 * u_of(s2, axis, x)))
+        if not d3:
+            t = inpl[0]
+            for end in (lo[t], hi[t]):
+                xe = [0.0, 0.0, 0.0]
+                xe[axis] = lo[axis] / n
+                xe[t] = end / n
+                exp -= (1.0 / (6 * n) if quad else 0.5 / n) * (g1 * u_of(s1, axis, xe) + g2 * u_of(s2, axis, xe))
+        assert abs(got[c] - exp) <= 1e-12 * max(1.0, abs(exp)), (c, got[c], exp)
+    assert len(seen) == nd
+    f.close()
+
+
 def test_3d_takes_the_dual_primal_coupling_only():
     f = B.Feti()
     with pytest.raises(B.FetiError) as e:
