@@ -115,7 +115,7 @@ struct feti_ctx_s {
   double *Spinv = nullptr, *cpi = nullptr, *upi = nullptr, *ydp = nullptr;
   // deflation of the dual-primal iteration: F W (N_lambda x n_defl, column-major), the
   // inverse of E = W^T F W, and the coarse vectors of one projection
-  double *FW = nullptr, *Edinv = nullptr, *gdef = nullptr, *adef = nullptr;
+  double *FW = nullptr, *Edinv = nullptr, *gdef = nullptr, *adef = nullptr, *dpart = nullptr;
   bool defl = false;
   // captured PCG iteration chunks, keyed by the multiplier buffer they update
   struct Graph {
@@ -293,6 +293,7 @@ int upload_mesh(feti_ctx ctx) {
       RC(upload(ctx, &m.defl_rw, h.defl_rw));
       RC(dalloc(ctx, &ctx->gdef, h.n_defl, ctx->allocs));
       RC(dalloc(ctx, &ctx->adef, h.n_defl, ctx->allocs));
+      RC(dalloc(ctx, &ctx->dpart, (size_t)h.n_defl * DEFL_CHUNKS, ctx->allocs));
       ctx->defl = true;
     } else {
       m.n_defl = 0;
@@ -512,7 +513,7 @@ void op_M(feti_ctx ctx, const double* x, double* y, const int32_t* skip) {
 // Dual-primal deflation: y = z - W E^{-1} (F W)^T z (a search direction F-orthogonal to W).
 void op_defl_dir(feti_ctx ctx, const double* z, double* y, const int32_t* skip) {
   DevMesh& m = ctx->dm;
-  launch_defl_fwt(m, ctx->FW, z, ctx->gdef, skip, ctx->stream);
+  launch_defl_fwt(m, ctx->FW, z, ctx->gdef, ctx->dpart, skip, ctx->stream);
   launch_coarse_apply(m.n_defl, ctx->Edinv, ctx->gdef, ctx->adef, 1.0, skip, ctx->stream);
   launch_coarse_correct(m, ctx->adef, -1.0, z, y, skip, ctx->stream);
 }
@@ -571,7 +572,7 @@ void pcg_iteration(feti_ctx ctx, double* lam, const int32_t* done) {
   if (coarse) launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, 1.0, done, st);
   if (ctx->defl) {
     // y = z - W E^{-1} (F W)^T z with (w, y) in the same pass
-    launch_defl_fwt(m, ctx->FW, ctx->z, ctx->gdef, done, st);
+    launch_defl_fwt(m, ctx->FW, ctx->z, ctx->gdef, ctx->dpart, done, st);
     launch_coarse_apply(m.n_defl, ctx->Edinv, ctx->gdef, ctx->adef, 1.0, done, st);
   }
   launch_correct_dot(m, coarse ? ctx->ac : (ctx->defl ? ctx->adef : nullptr), ctx->z, ctx->y, ctx->w, ctx->part,

@@ -218,8 +218,10 @@ void launch_pi_assemble(const DevMesh& m, const double* A, double* S, hipStream_
 // g = W^T v; g = (F W)^T z with FW column-major (N_lambda x n_defl); E = W^T FW symmetrised
 void launch_defl_column(const DevMesh& m, int c, double* out, hipStream_t st);
 void launch_defl_wt(const DevMesh& m, const double* v, double* g, const int32_t* skip, hipStream_t st);
-void launch_defl_fwt(const DevMesh& m, const double* FW, const double* z, double* g, const int32_t* skip,
-                     hipStream_t st);
+// (part: n_defl x DEFL_CHUNKS partial sums of the chunked reduction)
+constexpr int DEFL_CHUNKS = 16;
+void launch_defl_fwt(const DevMesh& m, const double* FW, const double* z, double* g, double* part,
+                     const int32_t* skip, hipStream_t st);
 void launch_defl_gram(const DevMesh& m, const double* FW, double* E, hipStream_t st);
 
 }  // namespace feti

@@ -117,17 +117,30 @@ __global__ void __launch_bounds__(256) k_defl_wt(DevMesh m, const double* __rest
   if (threadIdx.x == 0) g[c] = s;
 }
 
-// g_c = sum_j FW[c][j] z_j (column c of F W, contiguous)
+// g_c = sum_j FW[c][j] z_j (column c of F W, contiguous): block (c, k) sums the rows of
+// chunk k into part[c][k]; k_defl_sum adds the DEFL_CHUNKS partials of a column in order
 __global__ void __launch_bounds__(256) k_defl_fwt(DevMesh m, const double* __restrict__ FW, const double* __restrict__ z,
-                                                  double* __restrict__ g, const int32_t* __restrict__ skip) {
+                                                  double* __restrict__ part, const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ double red[256];
-  const int c = blockIdx.x;
+  const int c = blockIdx.x, k = blockIdx.y;
+  const int64_t len = (m.n_lambda + DEFL_CHUNKS - 1) / DEFL_CHUNKS;
+  const int64_t j0 = k * len, j1 = min(m.n_lambda, j0 + len);
   const double* col = FW + (int64_t)c * m.n_lambda;
   double acc = 0.0;
-  for (int64_t j = threadIdx.x; j < m.n_lambda; j += 256) acc += col[j] * z[j];
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) acc += col[j] * z[j];
   const double s = block_sum256(acc, red);
-  if (threadIdx.x == 0) g[c] = s;
+  if (threadIdx.x == 0) part[c * DEFL_CHUNKS + k] = s;
+}
+
+__global__ void __launch_bounds__(256) k_defl_sum(int n, const double* __restrict__ part, double* __restrict__ g,
+                                                  const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < DEFL_CHUNKS; ++k) s += part[c * DEFL_CHUNKS + k];
+  g[c] = s;
 }
 
 // E[c][d] = (W^T F W)_{cd} symmetrised: (sum over the rows of c of w_j FW[d][j] + the same
@@ -153,10 +166,11 @@ void launch_defl_wt(const DevMesh& m, const double* v, double* g, const int32_t*
   hipLaunchKernelGGL(k_defl_wt, dim3(m.n_defl), dim3(256), 0, st, m, v, g, skip);
 }
 
-void launch_defl_fwt(const DevMesh& m, const double* FW, const double* z, double* g, const int32_t* skip,
-                     hipStream_t st) {
+void launch_defl_fwt(const DevMesh& m, const double* FW, const double* z, double* g, double* part,
+                     const int32_t* skip, hipStream_t st) {
   if (m.n_defl == 0) return;
-  hipLaunchKernelGGL(k_defl_fwt, dim3(m.n_defl), dim3(256), 0, st, m, FW, z, g, skip);
+  hipLaunchKernelGGL(k_defl_fwt, dim3(m.n_defl, DEFL_CHUNKS), dim3(256), 0, st, m, FW, z, part, skip);
+  hipLaunchKernelGGL(k_defl_sum, dim3((m.n_defl + 255) / 256), dim3(256), 0, st, m.n_defl, part, g, skip);
 }
 
 void launch_defl_gram(const DevMesh& m, const double* FW, double* E, hipStream_t st) {
