@@ -592,7 +592,6 @@ std::string build_mesh(const feti_mesh_desc& d, MeshHost& m) {
   if (d.coupling != FETI_COUPLING_DUAL && d.coupling != FETI_COUPLING_PRIMAL) return "unknown coupling";
   const bool decoupled = d.scheme == FETI_SCHEME_DECOUPLED;
   const bool dp = d.coupling == FETI_COUPLING_PRIMAL;
-  if (dp && decoupled) return "the decoupled scheme takes the dual coupling only";
   m = MeshHost();
   m.desc = d;
   m.ratio = d.order_u == 2 ? 2 : 1;

@@ -101,6 +101,7 @@ def test_decoupled_indexing_bit_exact_against_oracle(w):
     W.patch_case(order_u=1, ncell=8, nsub_x=4, nsub_y=3).replace(coupling="primal"),
     W.pulsed_core(ncell=16, nsub=4, nsteps=1).replace(coupling="primal"),
     W.nearly_incompressible_scaled(24, 4).replace(coupling="primal", cut_x=(0, 5, 12, 20, 24), layout=W.XSPLIT),
+    W.nearly_incompressible_scaled(16, 4).replace(coupling="primal", scheme="decoupled", name="xsplit_h16_decoupled"),
 ], ids=lambda w: w.name + "_primal")
 def test_dual_primal_indexing_bit_exact_against_oracle(w):
     """Dual-primal coupling: local orders (primal DOFs trailing), the jump rows of the dual
@@ -224,15 +225,6 @@ def test_3d_takes_the_dual_primal_coupling_only():
     f = B.Feti()
     with pytest.raises(B.FetiError) as e:
         f.setup_mesh(**mesh_args(W.cube_case(ncell=4).replace(coupling="dual")))
-    assert e.value.code == B.EINVAL
-    f.close()
-
-
-def test_dual_primal_coupling_is_rejected_with_the_decoupled_scheme():
-    f = B.Feti()
-    with pytest.raises(B.FetiError) as e:
-        f.setup_mesh(**mesh_args(W.nearly_incompressible_scaled(16, 4).replace(scheme="decoupled",
-                                                                              coupling="primal")))
     assert e.value.code == B.EINVAL
     f.close()
 

@@ -40,7 +40,10 @@ def _rel_on(got, ref):
     (W.nearly_incompressible_scaled(32, 4, nsteps=4).replace(scheme="decoupled"), 1e-2),
     (W.nearly_incompressible_scaled(24, 4, nsteps=3).replace(scheme="decoupled", layout=W.YSPLIT,
                                                               name="ysplit_p2_h24_4x4"), 1e-3),
-], ids=["xsplit_corr1e-3", "xsplit_corr1e-2", "ysplit_corr1e-3"])
+    (W.nearly_incompressible_scaled(32, 4, nsteps=4).replace(scheme="decoupled", coupling="primal"), 1e-3),
+    (W.nearly_incompressible_scaled(24, 4, nsteps=3).replace(scheme="decoupled", layout=W.YSPLIT, coupling="primal",
+                                                              name="ysplit_p2_h24_4x4"), 1e-3),
+], ids=["xsplit_corr1e-3", "xsplit_corr1e-2", "ysplit_corr1e-3", "xsplit_dual_primal", "ysplit_dual_primal"])
 def test_decoupled_steps_match_the_oracle(w, tol_corr):
     import torch
     require_gpu()
