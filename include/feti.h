@@ -123,9 +123,12 @@ typedef struct {
  * symmetric positive definite, no subdomain floats (n_c = 0), and every application of F
  * solves the primal coarse problem S_PiPi = K~_PiPi - K~_Pir K~_rr^{-1} K~_rPi (dense,
  * inverted once by feti_factor_subdomains).  The solution is the same (Theorem 3.1's
- * equivalence).  PRIMAL takes FETI_FP64 factors, the coupled scheme and single contexts
- * (no batches); FETI_EINVAL from feti_setup_mesh if a subdomain without Dirichlet data has
- * fewer than two primal displacement nodes. */
+ * equivalence).  With more than one subdomain the iteration is deflated by one
+ * normal-flux vector per face-sharing subdomain pair (feti_export_deflation).  PRIMAL
+ * takes FETI_FP64 factors and single contexts (no batches), and both schemes in 2D (under
+ * FETI_SCHEME_DECOUPLED the subdomains carry (u, xi) only, so xi and the grid corners are
+ * primal and multipliers glue u); FETI_EINVAL from feti_setup_mesh if a subdomain without
+ * Dirichlet data has fewer than two primal displacement nodes. */
 enum { FETI_COUPLING_DUAL = 0, FETI_COUPLING_PRIMAL = 1 };
 
 /* Time discretisation of a step.  DECOUPLED: the fluid content and the pressure leave the
@@ -302,6 +305,16 @@ int feti_set_keep_assembled(feti_ctx ctx, int32_t keep);
  * Algorithms 1 and 2 with the same stopping tests.  May be called at any time. */
 enum { FETI_PCG_AUTO = 0, FETI_PCG_GRAPH = 1 };
 int feti_set_pcg_mode(feti_ctx ctx, int32_t mode);
+
+/* Diagnostic environment variables (read once per process; none changes a result beyond
+ * rounding order):
+ *   FETI_TRACE       per-solve iteration counts and residuals on stderr; takes the
+ *                    host-driven kernel chain instead of the persistent launch;
+ *   FETI_PCG_TRACE   per-phase clock stamps of the persistent launch on stderr (this
+ *                    allocates a small device buffer per solve);
+ *   FETI_NO_PERSIST  never the persistent launch (as FETI_PCG_GRAPH);
+ *   FETI_NO_GRAPH    launch the kernel chain directly instead of replaying its graph;
+ *   FETI_PCG_GRID    blocks of the persistent launch (clamped to what is co-resident). */
 
 /* ---- time stepping ----------------------------------------------------------- */
 

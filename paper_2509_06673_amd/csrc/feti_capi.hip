@@ -285,7 +285,7 @@ int upload_mesh(feti_ctx ctx) {
     RC(dalloc(ctx, &ctx->upi, std::max(m.n_pi, 1), ctx->allocs));
     RC(dalloc(ctx, &ctx->ydp, h.sum_ns, ctx->allocs));
     m.n_defl = h.n_defl;
-    if (h.n_defl > 0 && !std::getenv("FETI_NO_DEFLATION")) {
+    if (h.n_defl > 0) {
       RC(upload(ctx, &m.defl_col, h.defl_col));
       RC(upload(ctx, &m.defl_w, h.defl_w));
       RC(upload(ctx, &m.defl_ptr, h.defl_ptr));
