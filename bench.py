@@ -40,8 +40,8 @@ MEASURED_TRAFFIC = {"sources": ["paper_2509_06673_amd/csrc/kernels_pcg.hip",
                                 "paper_2509_06673_amd/csrc/pcg_device.h",
                                 "paper_2509_06673_amd/csrc/pcg.h",
                                 "paper_2509_06673_amd/csrc/iface_device.h"],
-                    "sha256_16": "06e9db539a9e987e",
-                    "bytes_per_iteration": (41883506.2 * 1.99982 + 592441.9) * 1024 / 555}
+                    "sha256_16": "789718cb3bef211a",
+                    "bytes_per_iteration": (74395967.6 * 1.99971 + 1055130.5) * 1024 / 986}
 
 
 def source_hash(paths):
