@@ -1333,6 +1333,35 @@ int feti_assemble(feti_ctx ctx, const feti_material* P, const feti_material* E, 
   return FETI_OK;
 }
 
+// In-place inverse of one dense symmetric n x n matrix A (device, row major) by the
+// pivot-free sweep of the elimination; the plan's temporaries and the uploaded size are
+// freed on every path.  FETI_ESINGULAR (with what) on a zero or non-finite pivot.
+int invert_dense(feti_ctx ctx, double* A, int n, const char* what) {
+  hipStream_t st = ctx->stream;
+  GJPlan C;
+  std::vector<int32_t> cflag;
+  std::vector<void*> tmp;
+  auto done = [&](int rc) {
+    for (void* p : tmp) (void)hipFree(p);
+    return rc;
+  };
+  int rc = build_gj_plan(ctx, C, cflag, 1, {n}, {0}, {n}, {0}, {n}, {-1}, {n}, GJ_PANEL, tmp);
+  if (rc) return done(rc);
+  for (int s = 0; s < C.nsteps; ++s) launch_gj_step(C, A, (double*)nullptr, s, false, st);
+  int32_t* d_n = nullptr;
+  if (hipMalloc(&d_n, sizeof(int32_t)) != hipSuccess) return done(fail(ctx, FETI_ENOMEM, "device allocation failed"));
+  tmp.push_back(d_n);
+  if (hipMemcpyAsync(d_n, &n, sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess)
+    return done(fail(ctx, FETI_EHIP, "copy of the matrix size failed"));
+  launch_gj_finalize(C, A, d_n, st);
+  int32_t cs = 0;
+  if (hipMemcpyAsync(&cs, C.status, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return done(fail(ctx, FETI_EHIP, std::string("inversion of the ") + what + " failed"));
+  if (cs) return done(fail(ctx, FETI_ESINGULAR, std::string("zero or non-finite pivot in the ") + what));
+  return done(FETI_OK);
+}
+
 int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   if (!ctx) return FETI_EINVAL;
   if (ctx->state < 2) return fail(ctx, FETI_ESTATE, "factor before assemble");
@@ -1395,9 +1424,17 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
   int rc = build_gj_plan(ctx, P, hflag, nsub, n, nI, nsw, aofs, lda, sofs, ldb, GJ_PANEL, tmp);
   if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
   std::vector<int32_t> stat(nsub, 0);
+  // the swept counts of the finalisation: a temporary like the plan's tables
   int32_t* d_nsw = nullptr;
-  rc = upload(ctx, &d_nsw, nfin);
-  if (rc) { for (void* p : tmp) (void)hipFree(p); return rc; }
+  if (hipMalloc(&d_nsw, nfin.size() * sizeof(int32_t)) != hipSuccess) {
+    for (void* p : tmp) (void)hipFree(p);
+    return fail(ctx, FETI_ENOMEM, "device allocation failed");
+  }
+  tmp.push_back(d_nsw);
+  if (hipMemcpyAsync(d_nsw, nfin.data(), nfin.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess) {
+    for (void* p : tmp) (void)hipFree(p);
+    return fail(ctx, FETI_EHIP, "copy of the swept counts failed");
+  }
   // S_bb of a subdomain without interior DOFs (a one-cell slab of a 3D decomposition) is
   // its K_bb: no interior pivot step takes that snapshot, so every interface block is
   // copied before the sweep (the snapshots of the other subdomains overwrite theirs)
@@ -1463,22 +1500,7 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
     if (!ctx->Spinv) RC(dalloc(ctx, &ctx->Spinv, (size_t)np * np, ctx->mat_allocs));
     HIPCHK(hipMemsetAsync(ctx->Spinv, 0, (size_t)np * np * sizeof(double), st));
     launch_pi_assemble(m, ctx->Splus, ctx->Spinv, st);
-    GJPlan C;
-    std::vector<int32_t> cflag;
-    std::vector<void*> ctmp;
-    rc = build_gj_plan(ctx, C, cflag, 1, {np}, {0}, {np}, {0}, {np}, {-1}, {np}, GJ_PANEL, ctmp);
-    if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
-    for (int s = 0; s < C.nsteps; ++s) launch_gj_step(C, ctx->Spinv, (double*)nullptr, s, false, st);
-    int32_t* d_np = nullptr;
-    std::vector<int32_t> npv{np};
-    rc = upload(ctx, &d_np, npv);
-    if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
-    launch_gj_finalize(C, ctx->Spinv, d_np, st);
-    int32_t cs = 0;
-    HIPCHK(hipMemcpyAsync(&cs, C.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (void* p : ctmp) (void)hipFree(p);
-    if (cs) return fail(ctx, FETI_ESINGULAR, "zero or non-finite pivot in the primal coarse matrix");
+    RC(invert_dense(ctx, ctx->Spinv, np, "primal coarse matrix"));
   }
   // deflation of the dual-primal iteration: F W column by column and E = W^T F W, inverted
   if (ctx->defl) {
@@ -1491,44 +1513,14 @@ int feti_factor_subdomains(feti_ctx ctx, int32_t precision, int32_t precond) {
       op_F(ctx, ctx->tl, ctx->FW + (size_t)c * nl, nullptr);
     }
     launch_defl_gram(m, ctx->FW, ctx->Edinv, st);
-    GJPlan C;
-    std::vector<int32_t> cflag;
-    std::vector<void*> ctmp;
-    rc = build_gj_plan(ctx, C, cflag, 1, {nd}, {0}, {nd}, {0}, {nd}, {-1}, {nd}, GJ_PANEL, ctmp);
-    if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
-    for (int s = 0; s < C.nsteps; ++s) launch_gj_step(C, ctx->Edinv, (double*)nullptr, s, false, st);
-    int32_t* d_nd = nullptr;
-    std::vector<int32_t> ndv{nd};
-    rc = upload(ctx, &d_nd, ndv);
-    if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
-    launch_gj_finalize(C, ctx->Edinv, d_nd, st);
-    int32_t cs = 0;
-    HIPCHK(hipMemcpyAsync(&cs, C.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (void* p : ctmp) (void)hipFree(p);
-    if (cs) return fail(ctx, FETI_ESINGULAR, "singular deflation matrix W^T F W");
+    RC(invert_dense(ctx, ctx->Edinv, nd, "deflation matrix W^T F W"));
   }
   // coarse matrix G^T G and its inverse
   const int nc = ctx->nc;
   if (nc > 0) {
     if (!ctx->Cinv) RC(dalloc(ctx, &ctx->Cinv, (size_t)nc * nc, ctx->mat_allocs));
     launch_gtg(m, ctx->Cinv, nc, st);
-    GJPlan C;
-    std::vector<int32_t> cflag;
-    std::vector<void*> ctmp;
-    rc = build_gj_plan(ctx, C, cflag, 1, {nc}, {0}, {nc}, {0}, {nc}, {-1}, {nc}, GJ_PANEL, ctmp);
-    if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
-    for (int s = 0; s < C.nsteps; ++s) launch_gj_step(C, ctx->Cinv, (double*)nullptr, s, false, st);
-    int32_t* d_nc = nullptr;
-    std::vector<int32_t> ncv{nc};
-    rc = upload(ctx, &d_nc, ncv);
-    if (rc) { for (void* p : ctmp) (void)hipFree(p); return rc; }
-    launch_gj_finalize(C, ctx->Cinv, d_nc, st);
-    int32_t cs = 0;
-    HIPCHK(hipMemcpyAsync(&cs, C.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (void* p : ctmp) (void)hipFree(p);
-    if (cs) return fail(ctx, FETI_ESINGULAR, "singular coarse matrix G^T G");
+    RC(invert_dense(ctx, ctx->Cinv, nc, "coarse matrix G^T G"));
     if (nc <= PCG_NC_LOCAL) {
       if (!ctx->H) RC(dalloc(ctx, &ctx->H, (size_t)nc * m.n_lambda, ctx->mat_allocs));
       launch_build_h(m, ctx->Cinv, nc, ctx->H, st);

@@ -175,3 +175,32 @@ def test_dual_primal_is_rejected_where_unsupported():
         f.factor_subdomains(B.FP32_IR, B.PRECOND_DIRICHLET)
     assert e.value.code == B.EINVAL
     f.close()
+
+
+@pytest.mark.parametrize("coupling", ["dual", "primal"])
+def test_refactorisation_reproduces_the_steps_bit_for_bit(coupling):
+    """A second feti_factor_subdomains on the same context (the dense coarse inverses of
+    G^T G, S_PiPi and W^T F W rebuilt in place) gives the same steps bit for bit as one
+    factorisation."""
+    require_gpu()
+    import torch
+    w = W.nearly_incompressible_scaled(16, 4).replace(coupling=coupling)
+    o = opts(tol=w.tol, max_it=2000)
+    out = []
+    for nfact in (1, 2):
+        f = B.Feti()
+        f.setup_mesh(**mesh_args(w))
+        f.assemble(material(w.mat_p), material(w.mat_e), w.tau)
+        for _ in range(nfact):
+            f.factor_subdomains(B.FP64, B.PRECOND_DIRICHLET)
+        f.init_state(load(w, 0.0))
+        sz = f.get_sizes()
+        for n in range(1, 4):
+            st = f.step(load(w, n * w.tau), o)
+            assert st["status"] == 0
+        u = torch.empty(sz["sum_ns"], dtype=torch.float64, device="cuda")
+        lam = torch.empty(sz["n_lambda"], dtype=torch.float64, device="cuda")
+        f.get_solution(u=u, lam=lam)
+        out.append((u.cpu().numpy(), lam.cpu().numpy()))
+        f.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
