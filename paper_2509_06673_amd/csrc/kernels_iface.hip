@@ -338,7 +338,19 @@ __device__ __forceinline__ void coarse_apply_body(int nc, const double* __restri
   if (row >= nc) return;
   const double* Cr = C + (int64_t)row * nc;
   double s = 0.0;
-  for (int k = lane; k < nc; k += 64) s += Cr[k] * g[k];
+  // eight row entries per lane in flight, summed in the order of the plain loop
+  int k = lane;
+  for (; k + 7 * 64 < nc; k += 8 * 64) {
+    double c[8], x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      c[u] = Cr[k + u * 64];
+      x[u] = g[k + u * 64];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += c[u] * x[u];
+  }
+  for (; k < nc; k += 64) s += Cr[k] * g[k];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) a[row] = scale * s;
 }
