@@ -513,8 +513,7 @@ void op_M(feti_ctx ctx, const double* x, double* y, const int32_t* skip) {
 // Dual-primal deflation: y = z - W E^{-1} (F W)^T z (a search direction F-orthogonal to W).
 void op_defl_dir(feti_ctx ctx, const double* z, double* y, const int32_t* skip) {
   DevMesh& m = ctx->dm;
-  launch_defl_fwt(m, ctx->FW, z, ctx->gdef, ctx->dpart, skip, ctx->stream);
-  launch_coarse_apply(m.n_defl, ctx->Edinv, ctx->gdef, ctx->adef, 1.0, skip, ctx->stream);
+  launch_defl_fwt_apply(m, ctx->FW, z, ctx->Edinv, ctx->adef, ctx->dpart, skip, ctx->stream);
   launch_coarse_correct(m, ctx->adef, -1.0, z, y, skip, ctx->stream);
 }
 
@@ -572,8 +571,7 @@ void pcg_iteration(feti_ctx ctx, double* lam, const int32_t* done) {
   if (coarse) launch_coarse_apply(ctx->nc, ctx->Cinv, ctx->g, ctx->ac, 1.0, done, st);
   if (ctx->defl) {
     // y = z - W E^{-1} (F W)^T z with (w, y) in the same pass
-    launch_defl_fwt(m, ctx->FW, ctx->z, ctx->gdef, ctx->dpart, done, st);
-    launch_coarse_apply(m.n_defl, ctx->Edinv, ctx->gdef, ctx->adef, 1.0, done, st);
+    launch_defl_fwt_apply(m, ctx->FW, ctx->z, ctx->Edinv, ctx->adef, ctx->dpart, done, st);
   }
   launch_correct_dot(m, coarse ? ctx->ac : (ctx->defl ? ctx->adef : nullptr), ctx->z, ctx->y, ctx->w, ctx->part,
                      counter(ctx, PH_BETA), ctx->sc, ctx->ist, PH_BETA, st);

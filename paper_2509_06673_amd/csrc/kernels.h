@@ -220,8 +220,9 @@ void launch_defl_column(const DevMesh& m, int c, double* out, hipStream_t st);
 void launch_defl_wt(const DevMesh& m, const double* v, double* g, const int32_t* skip, hipStream_t st);
 // (part: n_defl x DEFL_CHUNKS partial sums of the chunked reduction)
 constexpr int DEFL_CHUNKS = 16;
-void launch_defl_fwt(const DevMesh& m, const double* FW, const double* z, double* g, double* part,
-                     const int32_t* skip, hipStream_t st);
+// a = E^{-1} (F W)^T z (the partials of (F W)^T z in part, n_defl x DEFL_CHUNKS)
+void launch_defl_fwt_apply(const DevMesh& m, const double* FW, const double* z, const double* Einv, double* a,
+                           double* part, const int32_t* skip, hipStream_t st);
 void launch_defl_gram(const DevMesh& m, const double* FW, double* E, hipStream_t st);
 
 }  // namespace feti

@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(256) k_defl_wt(DevMesh m, const double* __rest
 }
 
 // g_c = sum_j FW[c][j] z_j (column c of F W, contiguous): block (c, k) sums the rows of
-// chunk k into part[c][k]; k_defl_sum adds the DEFL_CHUNKS partials of a column in order
+// chunk k into part[c][k]; k_defl_apply adds the DEFL_CHUNKS partials of a column in order
 __global__ void __launch_bounds__(256) k_defl_fwt(DevMesh m, const double* __restrict__ FW, const double* __restrict__ z,
                                                   double* __restrict__ part, const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
@@ -133,14 +133,25 @@ __global__ void __launch_bounds__(256) k_defl_fwt(DevMesh m, const double* __res
   if (threadIdx.x == 0) part[c * DEFL_CHUNKS + k] = s;
 }
 
-__global__ void __launch_bounds__(256) k_defl_sum(int n, const double* __restrict__ part, double* __restrict__ g,
-                                                  const int32_t* __restrict__ skip) {
+// a = E^{-1} g with g_d = the DEFL_CHUNKS partials of column d summed in order: one
+// wavefront per row of the dense E^{-1}, each lane forming the g_d it multiplies (the
+// order of both sums is that of a separate chunk sum followed by the dense coarse apply)
+__global__ void __launch_bounds__(256) k_defl_apply(int n, const double* __restrict__ part,
+                                                    const double* __restrict__ Einv, double* __restrict__ a,
+                                                    const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double* Er = Einv + (int64_t)row * n;
   double s = 0.0;
-  for (int k = 0; k < DEFL_CHUNKS; ++k) s += part[c * DEFL_CHUNKS + k];
-  g[c] = s;
+  for (int d = lane; d < n; d += 64) {
+    double g = 0.0;
+    for (int k = 0; k < DEFL_CHUNKS; ++k) g += part[d * DEFL_CHUNKS + k];
+    s += Er[d] * g;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) a[row] = s;
 }
 
 // E[c][d] = (W^T F W)_{cd} symmetrised: (sum over the rows of c of w_j FW[d][j] + the same
@@ -166,11 +177,11 @@ void launch_defl_wt(const DevMesh& m, const double* v, double* g, const int32_t*
   hipLaunchKernelGGL(k_defl_wt, dim3(m.n_defl), dim3(256), 0, st, m, v, g, skip);
 }
 
-void launch_defl_fwt(const DevMesh& m, const double* FW, const double* z, double* g, double* part,
-                     const int32_t* skip, hipStream_t st) {
+void launch_defl_fwt_apply(const DevMesh& m, const double* FW, const double* z, const double* Einv, double* a,
+                           double* part, const int32_t* skip, hipStream_t st) {
   if (m.n_defl == 0) return;
   hipLaunchKernelGGL(k_defl_fwt, dim3(m.n_defl, DEFL_CHUNKS), dim3(256), 0, st, m, FW, z, part, skip);
-  hipLaunchKernelGGL(k_defl_sum, dim3((m.n_defl + 255) / 256), dim3(256), 0, st, m.n_defl, part, g, skip);
+  hipLaunchKernelGGL(k_defl_apply, dim3((m.n_defl + 3) / 4), dim3(256), 0, st, m.n_defl, part, Einv, a, skip);
 }
 
 void launch_defl_gram(const DevMesh& m, const double* FW, double* E, hipStream_t st) {
