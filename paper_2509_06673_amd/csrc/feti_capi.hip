@@ -122,7 +122,9 @@ struct feti_ctx_s {
     hipGraphExec_t exec = nullptr;
     const double* lam = nullptr;
     int chunk = 0;
-  } graphs[2];
+  } graphs[12];
+  int graph_next = 0;            // round-robin replacement among the captured chunks
+  int prev_iters[NREC] = {};     // iterations of the last solve in each record slot
 };
 
 namespace {
@@ -771,7 +773,7 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
   RC(torn_begin(ctx, o, tol, utol, f, cj, lam, cand, pick_flag));
   HIPCHK(hipEventRecord(ev[1], st));
   const int32_t* done = ctx->ist + IS_DONE;
-  const int chunk = std::max(1, o->check_every);
+  const int base_chunk = std::max(1, o->check_every);
   static const bool trace = std::getenv("FETI_TRACE") != nullptr;
   static const bool use_graph = std::getenv("FETI_NO_GRAPH") == nullptr;
   static const bool use_persist = std::getenv("FETI_NO_PERSIST") == nullptr;
@@ -859,13 +861,35 @@ int solve_torn(feti_ctx ctx, const feti_solve_opts* o, double tol, double utol, 
       }
     }
     if (ctx->h_ist[IS_DONE] || ctx->h_ist[IS_ITERS] >= o->max_it) break;
+    // The iterations of a chunk that follow convergence are launched and return at once
+    // (a few microseconds per kernel), so a chunk is sized from the iteration count of the
+    // last solve in the same record slot: the largest power of two within what that count
+    // leaves (at most check_every), or check_every once this solve has run past it.  The
+    // arithmetic is that of any chunking.
+    int chunk = base_chunk;
+    {
+      const int left = ctx->prev_iters[slot] - ctx->h_ist[IS_ITERS];
+      if (left > 0) {
+        const int cap = std::min(left, base_chunk);
+        chunk = 1;
+        while (2 * chunk <= cap) chunk *= 2;
+        if (cap == base_chunk) chunk = base_chunk;
+      }
+    }
     // one chunk of iterations, replayed from a captured graph
     feti_ctx_s::Graph* gr = nullptr;
     if (use_graph) {
       for (auto& g : ctx->graphs)
         if (g.exec && g.lam == lam && g.chunk == chunk) gr = &g;
       if (!gr) {
-        gr = ctx->graphs[0].exec == nullptr ? &ctx->graphs[0] : &ctx->graphs[1];
+        gr = nullptr;
+        for (auto& g : ctx->graphs)
+          if (!gr && g.exec == nullptr) gr = &g;
+        if (!gr) {
+          constexpr int NG = (int)(sizeof(ctx->graphs) / sizeof(ctx->graphs[0]));
+          gr = &ctx->graphs[ctx->graph_next];
+          ctx->graph_next = (ctx->graph_next + 1) % NG;
+        }
         if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
         *gr = feti_ctx_s::Graph();
         hipGraph_t graph = nullptr;
@@ -898,6 +922,7 @@ int finish_solve(feti_ctx ctx, int slot, feti_stats* stats, int* iters_out, doub
   const int32_t* hi = ctx->h_rec_ist + slot * IS_COUNT;
   const double* hs = ctx->h_rec_sc + slot * SC_COUNT;
   const int status = hi[IS_STATUS];
+  ctx->prev_iters[slot] = hi[IS_ITERS];
   if (iters_out) *iters_out += hi[IS_ITERS];
   if (res0) *res0 = hs[SC_RES0];
   if (res) *res = hs[SC_RES];
